@@ -1,0 +1,143 @@
+"""Pins for the whole oracle solve (no GPU).
+
+Closed forms (flat Fresnel stack, homogeneous stack), invariants (flux
+conservation, index-matched interface invisibility, mirror symmetry,
+independence of the least-squares definition), a structural cross-check
+(dense least squares on the full rectangular system) and Wood-anomaly
+robustness.  "Resolved" sizes raise N, P, M_w above the literal workload so
+that the discretisation error is below the tolerances used here.
+"""
+import numpy as np
+import pytest
+
+import workloads
+import oracle
+from oracle import fresnel, fills
+
+RES = dict(N=160, P=140, M_w=100)
+
+
+def _order0(r):
+    return list(r.orders).index(0)
+
+
+def test_fresnel_single_interface_textbook():
+    # one flat interface at y = 0: r = (q1 - q2)/(q1 + q2), t = 2 q1/(q1 + q2)
+    k, th, yU, yD = [10.0, 14.0], -0.9, 1.5, -2.5
+    aU, aD, q = fresnel.flat_stack_amplitudes(k, [0.0], th, yU, yD)
+    r = (q[0] - q[1]) / (q[0] + q[1])
+    t = 2 * q[0] / (q[0] + q[1])
+    assert abs(aU - r * np.exp(1j * q[0] * yU)) < 1e-14
+    assert abs(aD - t * np.exp(-1j * q[1] * yD)) < 1e-14
+
+
+def test_flat_stack_matches_fresnel():
+    s = workloads.config1_flat(**RES)
+    r = oracle.solve_stack(s)
+    aU, aD, _ = fresnel.flat_stack_amplitudes(s.k, [0.0, -2.0], s.thetas[0], s.y_U, s.y_D)
+    i0 = _order0(r)
+    assert abs(r.aU[i0] - aU) < 1e-12
+    assert abs(r.aD[i0] - aD) < 1e-12
+    assert np.max(np.abs(np.delete(r.aU, i0))) < 1e-11
+    assert np.max(np.abs(np.delete(r.aD, i0))) < 1e-11
+    assert abs(r.flux_err) < 1e-12
+
+
+def test_flat_stack_literal_sizes():
+    # at the literal workload sizes the flat twin is still within 1e-8
+    s = workloads.config1_flat()
+    r = oracle.solve_stack(s)
+    aU, aD, _ = fresnel.flat_stack_amplitudes(s.k, [0.0, -2.0], s.thetas[0], s.y_U, s.y_D)
+    i0 = _order0(r)
+    assert abs(r.aU[i0] - aU) < 1e-8 and abs(r.aD[i0] - aD) < 1e-8
+
+
+def test_homogeneous_stack_is_transparent():
+    # all k equal: no scattering; u_inc lives only in the top layer, so the
+    # transmitted zeroth order is the plane wave referenced at y_D
+    s = workloads.homogeneous(**RES)
+    r = oracle.solve_stack(s)
+    i0 = _order0(r)
+    k, th = s.k[0], s.thetas[0]
+    assert np.max(np.abs(r.aU)) < 1e-11
+    assert abs(r.aD[i0] - np.exp(1j * k * np.sin(th) * s.y_D)) < 1e-11
+    assert np.max(np.abs(np.delete(r.aD, i0))) < 1e-11
+
+
+def test_flux_conservation_curved():
+    r = oracle.solve_stack(workloads.config1(**RES))
+    assert abs(r.flux_err) < 1e-11
+
+
+def test_index_matched_interface_is_invisible():
+    base = workloads.config1(**RES)
+    three = workloads.config1(**RES)
+    mid = workloads.Interface("fourier", -1.0, n_nodes=RES["N"], cos_coef=np.array([0.1, 0.05]),
+                              sin_coef=np.array([-0.15, 0.0]))
+    three.interfaces = [three.interfaces[0], mid, three.interfaces[1]]
+    three.k = np.array([10.0, 13.0, 13.0, 16.0])
+    three.y_D = base.y_D
+    r2 = oracle.solve_stack(base)
+    r3 = oracle.solve_stack(three)
+    assert np.max(np.abs(r2.aU - r3.aU)) < 1e-10
+    assert np.max(np.abs(r2.aD - r3.aD)) < 1e-10
+
+
+def test_mirror_symmetry_of_efficiencies():
+    # y = 0.3 cos x is symmetric about x = 0: mirroring kappa0 -> -kappa0
+    # (theta -> -pi - theta) maps order n to -n
+    s = workloads.config1(**RES)
+    for c in s.interfaces:
+        c.cos_coef, c.sin_coef = np.array([0.3]), np.array([0.0])
+    th = -0.7
+    ra = oracle.solve_stack(s, theta=th)
+    rb = oracle.solve_stack(s, theta=-np.pi - th)
+    ea = {int(n): abs(a) ** 2 * kk.real for n, a, kk in zip(ra.orders, ra.aU, ra.kU) if kk.real > 0}
+    eb = {int(n): abs(a) ** 2 * kk.real for n, a, kk in zip(rb.orders, rb.aU, rb.kU) if kk.real > 0}
+    for n, e in ea.items():
+        assert abs(e - eb[-n]) < 1e-10
+
+
+def test_bragg_amplitudes_independent_of_ls_definition():
+    # the Remark after eq. (78): the Schur complements pick *a* quasi-periodic
+    # Green's function; the Bragg amplitudes do not depend on which one.
+    s = workloads.config1(**RES)
+    rt = oracle.solve_stack(s)
+    for mu in (1e-15, 1e-13, 1e-12):
+        r = oracle.solve_stack(s, mu_rel=mu)
+        assert np.max(np.abs(rt.aU - r.aU)) < 1e-11
+        assert np.max(np.abs(rt.aD - r.aD)) < 1e-11
+    # a rank-truncated pivoted-QR basic solution agrees to the discretisation
+    # error at the literal sizes (it loses accuracy when P is generous, since
+    # its coefficients are not small-norm)
+    s = workloads.config1()
+    rt = oracle.solve_stack(s)
+    rc = oracle.solve_stack(s, ls="cpqr")
+    assert np.max(np.abs(rt.aU - rc.aU)) < 2e-6
+    assert np.max(np.abs(rt.aD - rc.aD)) < 2e-6
+
+
+def test_schur_path_matches_full_rectangular_system():
+    s = workloads.config1(**RES)
+    r1 = oracle.solve_stack(s)
+    r2 = oracle.solve.solve_full_system(s)
+    assert np.max(np.abs(r1.aU - r2.aU)) < 1e-10
+    assert np.max(np.abs(r1.aD - r2.aD)) < 1e-10
+
+
+def test_wood_anomaly_top_layer_is_robust():
+    # top-layer Wood anomaly: kappa_1 = k_1 exactly (grazing first order)
+    s = workloads.config1(**RES)
+    th = -np.arccos(1 - 2 * np.pi / (s.d * s.k[0]))
+    r = oracle.solve_stack(s, theta=th)
+    kap = fills.rb_orders(s.k[0], th, s.d, s.K)[1]
+    assert np.min(np.abs(np.abs(kap) - s.k[0])) < 1e-12
+    assert abs(r.flux_err) < 1e-10
+
+
+def test_rb_window_contains_all_propagating_orders():
+    s = workloads.config2()
+    for th in (-0.05, -np.pi / 6, -np.pi / 2, -3.0):
+        n, kap = fills.rb_orders(s.k[0], th, s.d, s.K)
+        kmax = max(s.k[0], s.k[-1])
+        assert kap[0] < -kmax and kap[-1] > kmax

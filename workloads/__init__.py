@@ -1,0 +1,13 @@
+"""Seeded synthetic multilayer stacks.
+
+This module only draws random numbers and packs them into plain stack
+descriptions (interface shapes, layer wavenumbers, discretisation sizes,
+incident angles).  It holds none of the solver's arithmetic, so the CPU
+oracle and the GPU path can both read the same inputs without sharing any
+method code.
+"""
+from .stacks import (Interface, Stack, config1, config1_flat, config2,
+                     config3, homogeneous, small_stack)
+
+__all__ = ["Interface", "Stack", "config1", "config1_flat", "config2",
+           "config3", "homogeneous", "small_stack"]

@@ -1,0 +1,198 @@
+"""Seeded synthetic stack generators (inputs only).
+
+Geometry conventions shared by every consumer (they are part of the input
+description, not of the method):
+
+* period ``d``; the unit cell is ``-d/2 <= x < d/2``;
+* interfaces are listed top (Gamma_1) to bottom (Gamma_I);
+* a ``fourier`` interface is the graph
+  ``y = y0 + sum_m cos_coef[m-1] cos(2 pi m x/d) + sin_coef[m-1] sin(2 pi m x/d)``;
+* a ``polygon`` interface is the periodic broken line through the vertices
+  ``(vx[c], vy[c])``, ``vx[0] = -d/2``, ``vx[-1] = d/2``, ``vy[0] = vy[-1]``,
+  one straight segment per consecutive vertex pair, ``seg_nodes[c]`` nodes on
+  segment ``c``, Kress grading exponent ``q``;
+* ``k`` has I+1 real layer wavenumbers, top layer first;
+* ``y_U`` / ``y_D`` are the heights of the upper / lower radiation lines.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+
+@dataclass
+class Interface:
+    kind: str                      # "fourier" or "polygon"
+    y0: float
+    n_nodes: int = 0               # fourier: N_i
+    cos_coef: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    sin_coef: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    vx: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    vy: np.ndarray = field(default_factory=lambda: np.zeros(0))
+    seg_nodes: np.ndarray = field(default_factory=lambda: np.zeros(0, dtype=np.int32))
+    q: float = 6.0
+
+    @property
+    def N(self) -> int:
+        if self.kind == "fourier":
+            return int(self.n_nodes)
+        return int(np.sum(self.seg_nodes))
+
+
+@dataclass
+class Stack:
+    name: str
+    d: float
+    k: np.ndarray                  # (I+1,)
+    interfaces: List[Interface]
+    y_U: float
+    y_D: float
+    P: int
+    R: float
+    M_w: int
+    M_ud: int
+    K: int
+    thetas: np.ndarray             # incident angles in (-pi, 0)
+    ls_mu: float = 1e-14           # Tikhonov weight relative to ||Q||_F
+
+    @property
+    def I(self) -> int:
+        return len(self.interfaces)
+
+    @property
+    def n_den(self) -> int:
+        return 2 * sum(s.N for s in self.interfaces)
+
+    @property
+    def n_tot(self) -> int:
+        return self.n_den + (self.I + 1) * self.P + 2 * (2 * self.K + 1)
+
+
+def _scaled_fourier(rng: np.random.Generator, d: float, n_modes: int, peak: float):
+    """Draw cos/sin coefficients ~ N(0,1) (cos first, then sin) and scale the
+    profile so that its peak |value| on a 4096-point grid equals ``peak``."""
+    a = rng.standard_normal(n_modes)
+    b = rng.standard_normal(n_modes)
+    x = -d / 2 + d * np.arange(4096) / 4096
+    m = np.arange(1, n_modes + 1)[:, None]
+    f = (a[:, None] * np.cos(2 * np.pi * m * x / d) + b[:, None] * np.sin(2 * np.pi * m * x / d)).sum(0)
+    s = peak / np.max(np.abs(f))
+    return a * s, b * s
+
+
+def config1(N: int = 120, P: int = 60, M_w: int = 60, M_ud: int = 60, K: int = 25,
+            amplitude: float = 0.3, k=(10.0, 13.0, 16.0)) -> Stack:
+    """Three layers, two interfaces y = 0.3 sin x and y = -2 + 0.3 sin x, d = 2 pi."""
+    d = 2 * np.pi
+    ifs = [Interface("fourier", y0, n_nodes=N, cos_coef=np.zeros(1),
+                     sin_coef=np.array([amplitude])) for y0 in (0.0, -2.0)]
+    return Stack("config1", d, np.array(k, dtype=float), ifs, y_U=2.0, y_D=-4.0,
+                 P=P, R=d, M_w=M_w, M_ud=M_ud, K=K, thetas=np.array([-np.pi / 6]))
+
+
+def config1_flat(**kw) -> Stack:
+    """Flat twin of config1 (amplitude 0): a 1-D layered problem."""
+    s = config1(amplitude=0.0, **kw)
+    s.name = "config1_flat"
+    return s
+
+
+def homogeneous(kval: float = 10.0, **kw) -> Stack:
+    """config1 geometry with every layer at the same wavenumber."""
+    s = config1(k=(kval, kval, kval), **kw)
+    s.name = "homogeneous"
+    return s
+
+
+def config2(seed: int = 2, I: int = 50, N: int = 100, P: int = 50, M_w: int = 50,
+            M_ud: int = 60, K: int = 25, wood_layer: Optional[int] = 26,
+            theta: float = -np.pi / 6) -> Stack:
+    """I random smooth interfaces (Fourier modes 1..5, peak 0.3, spacing 1.5),
+    k_j = 10 n_j with n_j ~ U[1,2]; layer ``wood_layer`` (1-based) is retuned
+    so that kappa_m = k_j exactly for some order m (a Wood anomaly).
+
+    Draw order: for each interface top to bottom, 5 cos then 5 sin N(0,1)
+    coefficients; then I+1 uniforms for n_j."""
+    d = 2 * np.pi
+    rng = np.random.default_rng(seed)
+    ifs = []
+    for i in range(I):
+        a, b = _scaled_fourier(rng, d, 5, 0.3)
+        ifs.append(Interface("fourier", -1.5 * i, n_nodes=N, cos_coef=a, sin_coef=b))
+    n = rng.uniform(1.0, 2.0, I + 1)
+    k = 10.0 * n
+    if wood_layer is not None and 1 <= wood_layer <= I + 1:
+        kappa0 = k[0] * math.cos(theta)
+        g = 2 * np.pi / d
+        j = wood_layer - 1
+        m = round((k[j] - kappa0) / g)
+        kw = kappa0 + m * g
+        if kw > 20.0:
+            kw -= g
+        if kw < 10.0:
+            kw += g
+        k[j] = kw
+    return Stack("config2", d, k, ifs, y_U=1.5, y_D=-1.5 * (I - 1) - 1.5, P=P, R=d,
+                 M_w=M_w, M_ud=M_ud, K=K, thetas=np.array([theta]))
+
+
+def small_stack(seed: int = 0, I: int = 3, N: int = 64, P: int = 40, M_w: int = 40,
+                M_ud: int = 40, K: int = 8, d: float = 1.0, omega: float = 8.0,
+                spacing: float = 0.5, peak: float = 0.08, theta: float = -np.pi / 5,
+                n_modes: int = 3) -> Stack:
+    """Small random smooth stack (paper-like scale: d = 1) for quick tests."""
+    rng = np.random.default_rng(seed)
+    ifs = []
+    for i in range(I):
+        a, b = _scaled_fourier(rng, d, n_modes, peak)
+        ifs.append(Interface("fourier", -spacing * i, n_nodes=N, cos_coef=a, sin_coef=b))
+    n = rng.uniform(1.0, 1.5, I + 1)
+    n[0] = 1.0
+    return Stack("small", d, omega * n, ifs, y_U=spacing, y_D=-spacing * I,
+                 P=P, R=1.5 * d, M_w=M_w, M_ud=M_ud, K=K, thetas=np.array([theta]))
+
+
+def _polygon(kind: str, y0: float, d: float, h: float, nseg: int):
+    """Vertices of one period of a cornered profile of height ``h`` about y0."""
+    if kind == "triangle":          # valley at x = +-d/2, peak at 0: 2 segments
+        vx = np.array([-d / 2, 0.0, d / 2])
+        vy = np.array([y0 - h, y0 + h, y0 - h])
+    elif kind == "trapezoid":       # flat, up, top, down, flat: 5 segments
+        vx = np.array([-d / 2, -d / 4, -d / 8, d / 8, d / 4, d / 2])
+        vy = np.array([y0 - h, y0 - h, y0 + h, y0 + h, y0 - h, y0 - h])
+    else:                           # triangle on a flat: 4 segments
+        vx = np.array([-d / 2, -d / 6, 0.0, d / 6, d / 2])
+        vy = np.array([y0 - h, y0 - h, y0 + h, y0 - h, y0 - h])
+    return vx, vy
+
+
+def config3(seed: int = 3, I: int = 1000, n_angles: int = 100, N_smooth: int = 120,
+            N_corner: int = 250, P: int = 60, M_w: int = 60, M_ud: int = 60,
+            K: int = 25) -> Stack:
+    """I interfaces, a seeded 70/30 mix of smooth random-Fourier (N_smooth nodes)
+    and cornered (N_corner nodes over 2-5 graded segments) profiles, spacing 1.5,
+    k_j = 10 n_j with n_j ~ U[1,2], and ``n_angles`` angles uniform in (-pi/2, 0)."""
+    d = 2 * np.pi
+    rng = np.random.default_rng(seed)
+    corner = rng.permutation(I) < int(round(0.3 * I))
+    ifs = []
+    kinds = ("triangle", "trapezoid", "tri_on_flat")
+    for i in range(I):
+        y0 = -1.5 * i
+        a, b = _scaled_fourier(rng, d, 5, 0.3)
+        kind = kinds[int(rng.integers(0, 3))]
+        if not corner[i]:
+            ifs.append(Interface("fourier", y0, n_nodes=N_smooth, cos_coef=a, sin_coef=b))
+            continue
+        vx, vy = _polygon(kind, y0, d, 0.3, 0)
+        seglen = np.hypot(np.diff(vx), np.diff(vy))
+        nodes = np.maximum(8, np.round(N_corner * seglen / seglen.sum()).astype(np.int32))
+        nodes[np.argmax(nodes)] += N_corner - int(nodes.sum())
+        ifs.append(Interface("polygon", y0, vx=vx, vy=vy, seg_nodes=nodes.astype(np.int32), q=6.0))
+    n = rng.uniform(1.0, 2.0, I + 1)
+    thetas = -(np.pi / 2) * (np.arange(n_angles) + 0.5) / n_angles
+    return Stack("config3", d, 10.0 * n, ifs, y_U=1.5, y_D=-1.5 * (I - 1) - 1.5, P=P, R=d,
+                 M_w=M_w, M_ud=M_ud, K=K, thetas=thetas)
