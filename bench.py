@@ -1,0 +1,170 @@
+#!/usr/bin/env python3
+"""Throughput of the multilayer quasi-periodic Helmholtz solve on one MI355X.
+
+One step = one pass of the whole hot path for one incident angle: the
+alpha-independent fills (Nystrom self/neighbour blocks with the Alpert
+correction, proxy, wall and radiation blocks), alpha assembly, the per-layer
+Tikhonov least-squares Schur eliminations, the Schur-complement GEMMs, the
+block-tridiagonal LU sweep, the backward sweep and the Bragg/flux extraction.
+Inputs (interface geometry, wavenumbers) are resident on the device before
+timing starts; the Bragg amplitudes are copied back each step.
+
+Default workload: 50 random smooth interfaces (Fourier modes 1..5, peak 0.3,
+spacing 1.5, d = 2 pi), k_j = 10 n_j with n_j ~ U[1,2] and one interior layer
+at a Wood anomaly, theta = -pi/6, discretised finely enough for a flux error
+<= 1e-9 (N = 260 nodes per interface, P = 120 proxies, M_w = 80, M_ud = 60,
+K = 25).
+"""
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "multilayer solves/s (unknowns/s) at flux err ≤1e-9; adjoint grads/s; % FP64 peak"
+HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6
+
+WORKLOADS = {
+    # name: (generator name, kwargs, description)
+    "config2_resolved": ("config2", dict(N=260, P=120, M_w=80),
+                         "I=50 random Fourier interfaces, N=260, P=120, M_w=80, M_ud=60, K=25"),
+    "config2": ("config2", dict(), "I=50 random Fourier interfaces, N=100, P=50, M_w=50, M_ud=60, K=25"),
+    "config1_resolved": ("config1", dict(N=160, P=140, M_w=100),
+                         "I=2 sine interfaces, N=160, P=140, M_w=100, M_ud=60, K=25"),
+    "config1": ("config1", dict(), "I=2 sine interfaces, N=120, P=60, M_w=60, M_ud=60, K=25"),
+}
+
+
+def make_desc(name, I=None):
+    import workloads
+    gen, kw, _ = WORKLOADS[name]
+    kw = dict(kw)
+    if I is not None:
+        kw["I"] = I
+    return getattr(workloads, gen)(**kw)
+
+
+def flops_lu(n):
+    return 8.0 * n ** 3 / 3.0
+
+
+def cpu_baseline(name, sample_I):
+    """Time the oracle on the first `sample_I` interfaces of the workload (one
+    thread, separate process) and scale linearly in the number of layers."""
+    code = (
+        "import os,sys,time;sys.path.insert(0,%r);"
+        "import bench,oracle;d=bench.make_desc(%r,I=%d);"
+        "t=time.perf_counter();r=oracle.solve_stack(d);print(time.perf_counter()-t)"
+    ) % (ROOT, name, sample_I)
+    env = dict(os.environ, OPENBLAS_NUM_THREADS="1", OMP_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=600)
+    if out.returncode != 0:
+        raise RuntimeError(out.stderr)
+    return float(out.stdout.strip().splitlines()[-1])
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="config2_resolved", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-layers", type=int, default=6)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import paper_1410_5003_amd as mlh
+
+    desc = make_desc(args.workload)
+    ctx = mlh.Context(0)
+    st = mlh.Stack(ctx, desc)
+    info = st.info()
+    thetas = np.asarray(desc.thetas, dtype=float)
+    print("workload %s: I=%d n_tot=%d device MB %.1f" % (args.workload, desc.I, info["n_tot"],
+                                                        info["device_bytes"] / 2 ** 20), file=sys.stderr, flush=True)
+    out = None
+    for _ in range(args.warmup):
+        st.refill()
+        out = st.solve(thetas)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st.refill()
+        out = st.solve(thetas)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    solves_per_s = len(thetas) / (ms * 1e-3)
+    print("step %.3f ms  flux err %.2e" % (ms, out.flux_err[0]), file=sys.stderr, flush=True)
+
+    # per-kernel device times (HIP events on the library's stream)
+    profs = [st.profile_step(thetas[0]) for _ in range(3)]
+    prof = {k: float(np.mean([p[k] for p in profs])) for k in profs[0]}
+    print("profile " + json.dumps({k: round(v, 4) for k, v in prof.items()}), file=sys.stderr, flush=True)
+    n = 2 * desc.interfaces[0].n_nodes
+    groups = {
+        "lu_kernel": prof["lu_ms"], "lu_solve_kernel": prof["lu_solve_ms"],
+        "zgemm_kernel(sweep)": prof["sweep_gemm_ms"], "zgemm_kernel(schur)": prof["schur_ms"],
+        "ls_qr_kernel": prof["ls_qr_ms"], "ls_apply_kernel": prof["ls_apply_ms"],
+        "fill_kernel": prof["fill_pairs_ms"], "self_kernel": prof["fill_self_ms"],
+        "alpert_kernel": prof["fill_alpert_ms"], "backsub_kernel": prof["backsub_ms"],
+    }
+    dom = max(groups, key=groups.get)
+    I, P = desc.I, desc.P
+    if dom == "lu_kernel":
+        per_launch_ms = prof["lu_ms"] / max(1, prof["n_lu"])
+        achieved = flops_lu(n) / (per_launch_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s"}
+    elif dom == "lu_solve_kernel":
+        per_launch_ms = prof["lu_solve_ms"] / max(1, prof["n_lu_solve"])
+        achieved = 8.0 * n * n * (n + 1) / (per_launch_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s"}
+    elif dom == "zgemm_kernel(sweep)":
+        per_launch_ms = prof["sweep_gemm_ms"] / max(1, prof["n_sweep_gemm"])
+        achieved = 8.0 * n * (n + 1) * n / (per_launch_ms * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s"}
+    elif dom == "zgemm_kernel(schur)":
+        per_launch_ms = prof["schur_ms"]
+        fl = 8.0 * P * (I * (2 * n * n) + (I - 1) * 2 * n * n)
+        achieved = fl / (per_launch_ms * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s"}
+    else:
+        per_launch_ms = groups[dom]
+        achieved = 0.0
+        roof = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = dom
+    roof["avg_launch_ms"] = per_launch_ms
+
+    line = {
+        "metric": METRIC, "value": solves_per_s, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64 (complex128)", "data": "synthetic (seeded stacks)",
+        "config": {"workload": args.workload, "description": WORKLOADS[args.workload][2],
+                   "interfaces": desc.I, "unknowns": info["n_tot"], "angles_per_step": len(thetas)},
+        "unknowns_per_s": solves_per_s * info["n_tot"], "flux_err": float(out.flux_err[0]),
+        "phase_ms": {k: round(v, 4) for k, v in prof.items() if k.endswith("_ms")},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        ts = cpu_baseline(args.workload, args.cpu_sample_layers)
+        t_full = ts * desc.I / args.cpu_sample_layers
+        line["cpu_baseline"] = {"value": 1.0 / t_full, "unit": "solves/s", "cores": 1, "kind": "oracle",
+                                "sample": "first %d of %d interfaces of the same stack, one angle, %.2f s, "
+                                          "scaled linearly in the number of layers" % (args.cpu_sample_layers,
+                                                                                       desc.I, ts)}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

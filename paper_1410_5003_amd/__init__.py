@@ -1,0 +1,192 @@
+"""MI355X-native robust periodic multilayer Helmholtz solver.
+
+Python front end of libmlh.so (include/mlh.h): a hand-written gfx950 HIP
+implementation of the Cho & Barnett periodizing integral-equation scheme
+(arXiv:1410.5003) -- dense complex float64 Nystrom/proxy/wall/radiation fills,
+per-layer least-squares Schur eliminations and the block-tridiagonal LU sweep.
+PyTorch only supplies the HIP stream the library enqueues its work on.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+
+from ._lib import (ABI_VERSION, MLH_IFACE_FOURIER, MLH_IFACE_POLYGON, PIECES, MlhError, check,
+                   dptr, iptr, lib, mlh_interface, mlh_profile, mlh_stack_desc)
+
+__all__ = ["Context", "Stack", "SolveOutput", "MlhError", "lib"]
+
+
+def _current_stream_handle():
+    try:
+        import torch
+    except ImportError:  # no torch: the null stream
+        return None
+    if not torch.cuda.is_available():
+        raise MlhError(4, "no HIP device visible")
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Context:
+    """A device plus the HIP stream work is enqueued on (torch's current stream
+    by default)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self._h = C.c_void_p()
+        if stream is None:
+            stream = _current_stream_handle()
+        check(lib().mlh_ctx_create(device, stream, C.byref(self._h)))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            lib().mlh_ctx_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def hankel(self, x) -> np.ndarray:
+        """(H0(x), (i pi x/2) H1(x) - 1) from the device routine, shape (n, 2) complex."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        out = np.zeros(4 * x.size)
+        check(lib().mlh_debug_hankel(self._h, x.size, dptr(x), dptr(out)))
+        return out.view(np.complex128).reshape(-1, 2)
+
+    def zgemm(self, alpha: complex, A: np.ndarray, B: np.ndarray, Cm: np.ndarray) -> np.ndarray:
+        """C + alpha A B computed by the library's FP64-MFMA kernel."""
+        m, k = A.shape
+        k2, n = B.shape
+        assert k == k2 and Cm.shape == (m, n)
+        a = np.asfortranarray(A, dtype=np.complex128)
+        b = np.asfortranarray(B, dtype=np.complex128)
+        c = np.asfortranarray(Cm, dtype=np.complex128).copy(order="F")
+        al = np.array([alpha.real, alpha.imag])
+        check(lib().mlh_debug_zgemm(self._h, m, n, k, dptr(al), dptr(a), dptr(b), dptr(c)))
+        return c
+
+
+@dataclass
+class SolveOutput:
+    aU: np.ndarray       # (n_angles, 2K+1) complex
+    aD: np.ndarray
+    orders: np.ndarray   # (n_angles, 2K+1) int
+    flux_err: np.ndarray  # (n_angles,)
+
+
+class Stack:
+    """A prepared multilayer structure on the device.
+
+    ``desc`` is any object with the attributes of ``workloads.Stack``:
+    d, k, interfaces (kind, y0, n_nodes, cos_coef, sin_coef, vx, vy,
+    seg_nodes, q), y_U, y_D, P, R, M_w, M_ud, K and optionally ls_mu."""
+
+    def __init__(self, ctx: Context, desc):
+        self.ctx = ctx
+        self._keep = []
+        ifs = (mlh_interface * len(desc.interfaces))()
+        for i, f in enumerate(desc.interfaces):
+            e = ifs[i]
+            e.y0 = float(f.y0)
+            if f.kind == "fourier":
+                ca = np.ascontiguousarray(f.cos_coef, dtype=np.float64)
+                sa = np.ascontiguousarray(f.sin_coef, dtype=np.float64)
+                assert ca.size == sa.size
+                self._keep += [ca, sa]
+                e.kind = MLH_IFACE_FOURIER
+                e.n_modes = ca.size
+                e.cos_coef = dptr(ca)
+                e.sin_coef = dptr(sa)
+                e.n_nodes = int(f.n_nodes)
+            else:
+                vx = np.ascontiguousarray(f.vx, dtype=np.float64)
+                vy = np.ascontiguousarray(f.vy, dtype=np.float64)
+                sn = np.ascontiguousarray(f.seg_nodes, dtype=np.int32)
+                self._keep += [vx, vy, sn]
+                e.kind = MLH_IFACE_POLYGON
+                e.n_vert = vx.size
+                e.vx, e.vy, e.seg_nodes = dptr(vx), dptr(vy), iptr(sn)
+                e.q = float(f.q)
+        k = np.ascontiguousarray(desc.k, dtype=np.float64)
+        self._keep += [ifs, k]
+        d = mlh_stack_desc()
+        d.abi_version = ABI_VERSION
+        d.I = len(desc.interfaces)
+        d.iface = C.cast(ifs, C.POINTER(mlh_interface))
+        d.k = dptr(k)
+        d.d, d.y_U, d.y_D = float(desc.d), float(desc.y_U), float(desc.y_D)
+        d.P, d.R = int(desc.P), float(desc.R)
+        d.M_w, d.M_ud, d.K = int(desc.M_w), int(desc.M_ud), int(desc.K)
+        d.ls_mu = float(getattr(desc, "ls_mu", 0.0))
+        self.K = int(desc.K)
+        self._h = C.c_void_p()
+        check(lib().mlh_stack_create(ctx.handle, C.byref(d), C.byref(self._h)))
+        self._keep = []
+
+    def close(self):
+        if self._h:
+            lib().mlh_stack_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def refill(self):
+        check(lib().mlh_stack_refill(self._h))
+
+    def info(self):
+        a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+        check(lib().mlh_stack_info(self._h, C.byref(a), C.byref(b), C.byref(c)))
+        return {"n_den": a.value, "n_tot": b.value, "device_bytes": c.value}
+
+    def solve(self, thetas) -> SolveOutput:
+        th = np.ascontiguousarray(np.atleast_1d(thetas), dtype=np.float64)
+        na, nK = th.size, 2 * self.K + 1
+        aU = np.zeros((na, nK), dtype=np.complex128)
+        aD = np.zeros((na, nK), dtype=np.complex128)
+        orders = np.zeros((na, nK), dtype=np.int32)
+        flux = np.zeros(na)
+        check(lib().mlh_solve(self._h, na, dptr(th), dptr(aU), dptr(aD),
+                              iptr(orders), dptr(flux)))
+        return SolveOutput(aU, aD, orders, flux)
+
+    def profile_step(self, theta: float) -> dict:
+        """Per-kernel device times (ms) of one refill + one-angle solve."""
+        p = mlh_profile()
+        check(lib().mlh_profile_step(self._h, float(theta), C.byref(p)))
+        return {name: getattr(p, name) for name, _ in p._fields_}
+
+    def solve_partial(self, theta: float, stop_phase: int):
+        """Inspection: run one angle up to a phase (1 assembly, 2 least squares,
+        3 Schur, 4 sweep) and keep its workspace for ``work``."""
+        check(lib().mlh_debug_solve_partial(self._h, float(theta), int(stop_phase)))
+
+    WORK = {"Dg": 0, "Up": 1, "Dn": 2, "S": 3, "RHS": 4, "UG": 5, "eta": 6}
+
+    def work(self, name: str, index: int) -> np.ndarray:
+        which = self.WORK[name]
+        r, c = C.c_int32(), C.c_int32()
+        check(lib().mlh_debug_get_work(self._h, which, index, None, C.byref(r), C.byref(c)))
+        out = np.zeros((c.value, r.value), dtype=np.complex128)
+        check(lib().mlh_debug_get_work(self._h, which, index, dptr(out), C.byref(r), C.byref(c)))
+        return out.T
+
+    def piece(self, name: str, index: int = 0, piece: int = 0) -> np.ndarray:
+        which = PIECES[name]
+        r, c = C.c_int32(), C.c_int32()
+        check(lib().mlh_debug_get_piece(self._h, which, index, piece, None, C.byref(r), C.byref(c)))
+        out = np.zeros((c.value, r.value), dtype=np.complex128)  # column-major storage
+        check(lib().mlh_debug_get_piece(self._h, which, index, piece, dptr(out),
+                                        C.byref(r), C.byref(c)))
+        return out.T

@@ -1,0 +1,179 @@
+// Internal declarations shared by the host orchestration and the kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "hankel.hpp"
+
+namespace mlh {
+
+// ---------------------------------------------------------------------------
+// fill jobs: one (target set) x (source set) block, up to three shifted pieces
+// ---------------------------------------------------------------------------
+enum FillKind : int { kFillLayerPotential = 0, kFillProxy = 1 };
+
+struct FillJob {
+  const double* tx;
+  const double* ty;
+  const double* tnx;   // null: constant normal (cnx, cny)
+  const double* tny;
+  const double* sx;
+  const double* sy;
+  const double* snx;
+  const double* sny;
+  const double* sw;    // source weights (layer potentials only)
+  double cnx, cny;
+  double dy0;          // (target base height) - (source base height)
+  double k;
+  double scale;
+  double tshift[3];
+  double sshift[3];
+  cplx* out[3];
+  int Mt, Ns, ld, kind, npieces;
+  int tile_begin, tiles_m;
+};
+
+constexpr int kFillTileM = 64;
+constexpr int kFillTileN = 4;
+
+// self block of one interface: difference kernels at ka (above) and kb (below)
+struct SelfJob {
+  const double* x;
+  const double* y;
+  const double* nx;
+  const double* ny;
+  const double* w;
+  double ka, kb, d;
+  cplx* out[3];   // pieces l = -1, 0, 1 (n x n, ld = n)
+  int N;
+  int tile_begin, tiles_m;
+};
+
+// Alpert correction of one interface: aux invariants per (target, aux)
+struct AlpertJob {
+  const double* r2;
+  const double* nd;
+  const double* npd;
+  const double* nn;
+  const double* cw;   // aux weight u_k h |Z'|
+  const double* t;    // aux position in node-index units
+  double ka, kb;
+  cplx* out[3];
+  int N;
+  int block_begin;
+};
+
+constexpr int kAlpertAux = 30;     // 2 x 15 auxiliary nodes per target
+constexpr int kAlpertStencil = 16; // Lagrange interpolation stencil
+
+// ---------------------------------------------------------------------------
+// alpha assembly: dst = sum_p coef[p] * src[p] elementwise (up to 3 pieces),
+// rows x cols sub-block with its own leading dimensions
+// ---------------------------------------------------------------------------
+struct AsmJob {
+  const cplx* src[3];
+  cplx* dst;
+  cplx coef[3];
+  int npieces;
+  int rows, cols, lds, ldd;
+  int64_t elem_begin;
+};
+
+// batched complex GEMM  C += alpha (A B + A2 B2)  (column-major); the second
+// product (k2 may be 0) lets one descriptor own its output tile, so no two
+// workgroups of a launch ever update the same C entry
+struct GemmDesc {
+  const cplx* A;
+  const cplx* B;
+  const cplx* A2;
+  const cplx* B2;
+  cplx* C;
+  cplx alpha;
+  int m, n, k, lda, ldb, k2, lda2, ldb2, ldc;
+  int tile_begin, tiles_m;
+};
+
+// least-squares problem of one layer and one angle
+struct LsDesc {
+  cplx* S;       // (m + c) x c stacked matrix, column-major, ld = m + c
+  cplx* tau;     // c
+  cplx* RHS;     // (m + c) x ncol, ld = m + c; top c rows receive X
+  double mu_rel;
+  int m, c, ncol;
+  int col_block_begin;
+};
+
+// block-tridiagonal sweep helpers
+struct LuDesc {
+  cplx* A;
+  int* piv;
+  int n, lda;
+  int* info;
+};
+
+struct LuSolveDesc {
+  const cplx* LU;
+  const int* piv;
+  const cplx* B1;   // first n1 RHS columns (ld ldb1)
+  const cplx* B2;   // next n2 RHS columns (ld ldb2)
+  cplx* X;          // n x (n1 + n2), ld n
+  int n, lda, n1, ldb1, n2, ldb2;
+  int col_begin;
+};
+
+// host-side launchers (kernels_*.hip)
+void launch_fill(const FillJob* d_jobs, int njobs, int total_tiles, hipStream_t st);
+void launch_self(const SelfJob* d_jobs, int njobs, int total_tiles, int a_excl, hipStream_t st);
+void launch_alpert(const AlpertJob* d_jobs, int njobs, int total_blocks, int a_excl, hipStream_t st);
+void launch_assemble(const AsmJob* d_jobs, int njobs, int64_t total_elems, hipStream_t st);
+void launch_gemm(const GemmDesc* d_desc, int ndesc, int total_tiles, hipStream_t st);
+void launch_ls_qr(const LsDesc* d_desc, int ndesc, hipStream_t st);
+void launch_ls_apply(const LsDesc* d_desc, int ndesc, int total_col_blocks, int max_rows, hipStream_t st);
+void launch_lu(const LuDesc* d_desc, int ndesc, hipStream_t st);
+void launch_lu_solve(const LuSolveDesc* d_desc, int ndesc, int total_cols, int max_n, hipStream_t st);
+void launch_hankel_eval(const double* x, double* out, int n, hipStream_t st);
+
+}  // namespace mlh
+
+namespace mlh {
+
+// per-angle radiation rows, right-hand side and Bragg/flux extraction
+struct AngleDesc {
+  double theta;
+  cplx* S0;       // layer-1 stacked LS matrix (W_U goes at rows 2 M_w.., cols P..)
+  cplx* SI;       // layer-(I+1) stacked LS matrix (W_D)
+  int ldS0, ldSI;
+  cplx* F0;       // right-hand side of interface 1 (n_1 entries)
+  const cplx* X0; // layer-1 least-squares solution, ld ldX0 (rows P.. are a^U rows)
+  const cplx* XI; // layer-(I+1) least-squares solution
+  int ldX0, ldXI;
+  const cplx* eta0;
+  const cplx* etaI;
+  cplx* aU;
+  cplx* aD;
+  int* orders;
+  double* flux;
+};
+
+struct StackConsts {
+  const double* x1;     // Gamma_1 nodes (x, y relative to y0_1, normals)
+  const double* y1;
+  const double* nx1;
+  const double* ny1;
+  const double* xud;    // U / D node abscissae
+  double y0_1;
+  double d, k1, kI1;
+  int N1, NI, Mw, Mud, P, K;
+};
+
+struct BacksubDesc {
+  const cplx* UG;  // n_i x (n_{i+1} + 1), ld n_i ; last column = G_i
+  cplx* eta;       // n_i
+  int n, nnext;
+};
+
+void launch_rb_setup(const AngleDesc* d_ang, int nang, StackConsts sc, hipStream_t st);
+void launch_backsub(const BacksubDesc* d_desc, int I, int nbatch, hipStream_t st);
+void launch_bragg(const AngleDesc* d_ang, int nang, StackConsts sc, hipStream_t st);
+
+}  // namespace mlh

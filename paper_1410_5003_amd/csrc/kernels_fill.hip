@@ -1,0 +1,234 @@
+// Fill kernels: every alpha-independent matrix piece of the discretised
+// coupled system (Sec. 2.5; pieces as in the sweep precomputation of Sec. 3.4).
+//
+//  fill_kernel    plain Nystrom / proxy blocks: one thread per (target, source)
+//                 pair, 64 consecutive targets per wave so that the
+//                 column-major stores are coalesced.
+//  self_kernel    self blocks A_ii (eq. (37)): difference kernels of layers i
+//                 and i+1 over the three copies, zero inside the Alpert window
+//                 |J - m| < a of the extended index J = j + l N, jump terms
+//                 -I / +I on the diagonal.
+//  alpert_kernel  the auxiliary-node correction inside the window (Sec. 2.5
+//                 and the Remark on the quasi-periodic wrap): one wavefront per
+//                 target row owns every corrected column of that row, so the
+//                 read-modify-write needs no atomics.
+#include "internal.hpp"
+
+namespace mlh {
+
+template <class T>
+__device__ inline int find_job(const T* jobs, int njobs, int key) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].tile_begin <= key)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ inline void store(cplx* p, cplx v) { *reinterpret_cast<double2*>(p) = make_double2(v.re, v.im); }
+
+__global__ __launch_bounds__(256) void fill_kernel(const FillJob* __restrict__ jobs, int njobs) {
+  const int tile = blockIdx.x;
+  const FillJob& J = jobs[find_job(jobs, njobs, tile)];
+  const int lt = tile - J.tile_begin;
+  const int tm = lt % J.tiles_m, tn = lt / J.tiles_m;
+  const int m = tm * kFillTileM + (threadIdx.x & (kFillTileM - 1));
+  const int j = tn * kFillTileN + threadIdx.x / kFillTileM;
+  if (m >= J.Mt || j >= J.Ns) return;
+  const double tx = J.tx[m];
+  const double ty = J.ty[m] + J.dy0;
+  const double tnx = J.tnx ? J.tnx[m] : J.cnx;
+  const double tny = J.tny ? J.tny[m] : J.cny;
+  const double sx = J.sx[j], sy = J.sy[j], snx = J.snx[j], sny = J.sny[j];
+  const double dy = ty - sy;
+  const double nn = tnx * snx + tny * sny;
+  const int ld = J.ld;
+  for (int p = 0; p < J.npieces; ++p) {
+    const double dx = (tx - sx) + (J.tshift[p] - J.sshift[p]);
+    const double r2 = dx * dx + dy * dy;
+    const double nd = tnx * dx + tny * dy;
+    const double npd = snx * dx + sny * dy;
+    const Kern4 K = lp_kernels(J.k, r2, nd, npd, nn);
+    cplx* o = J.out[p];
+    if (J.kind == kFillLayerPotential) {
+      const double w = J.sw[j] * J.scale;
+      store(o + (size_t)j * ld + m, {K.D.re * w, K.D.im * w});
+      store(o + (size_t)(J.Ns + j) * ld + m, {K.S.re * w, K.S.im * w});
+      store(o + (size_t)j * ld + J.Mt + m, {K.T.re * w, K.T.im * w});
+      store(o + (size_t)(J.Ns + j) * ld + J.Mt + m, {K.Ds.re * w, K.Ds.im * w});
+    } else {
+      // phi = dG/dn_p + i k G ; dphi/dn = T + i k D*   (eq. (15))
+      const double k = J.k, s = J.scale;
+      const cplx phi = {K.D.re - k * K.S.im, K.D.im + k * K.S.re};
+      const cplx dphi = {K.T.re - k * K.Ds.im, K.T.im + k * K.Ds.re};
+      store(o + (size_t)j * ld + m, {phi.re * s, phi.im * s});
+      store(o + (size_t)j * ld + J.Mt + m, {dphi.re * s, dphi.im * s});
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void self_kernel(const SelfJob* __restrict__ jobs, int njobs, int a) {
+  const int tile = blockIdx.x;
+  const SelfJob& J = jobs[find_job(jobs, njobs, tile)];
+  const int lt = tile - J.tile_begin;
+  const int tm = lt % J.tiles_m, tn = lt / J.tiles_m;
+  const int N = J.N;
+  const int m = tm * kFillTileM + (threadIdx.x & (kFillTileM - 1));
+  const int j = tn * kFillTileN + threadIdx.x / kFillTileM;
+  if (m >= N || j >= N) return;
+  const double tnx = J.nx[m], tny = J.ny[m];
+  const double snx = J.nx[j], sny = J.ny[j];
+  const double dy = J.y[m] - J.y[j];
+  const double dx0 = J.x[m] - J.x[j];
+  const double nn = tnx * snx + tny * sny;
+  const double w = J.w[j];
+  const int ld = 2 * N;
+  for (int l = -1; l <= 1; ++l) {
+    const int off = j + l * N - m;
+    cplx D = {0, 0}, S = {0, 0}, T = {0, 0}, Ds = {0, 0};
+    if (off >= a || off <= -a) {
+      const double dx = dx0 - l * J.d;
+      const double r2 = dx * dx + dy * dy;
+      const Kern4 K = lp_kernels_diff(J.ka, J.kb, r2, tnx * dx + tny * dy, snx * dx + sny * dy, nn);
+      D = {K.D.re * w, K.D.im * w};
+      S = {K.S.re * w, K.S.im * w};
+      T = {K.T.re * w, K.T.im * w};
+      Ds = {K.Ds.re * w, K.Ds.im * w};
+    }
+    if (l == 0 && j == m) {  // jump relations: -tau / +sigma
+      D.re -= 1.0;
+      Ds.re += 1.0;
+    }
+    cplx* o = J.out[l + 1];
+    store(o + (size_t)j * ld + m, D);
+    store(o + (size_t)(N + j) * ld + m, S);
+    store(o + (size_t)j * ld + N + m, T);
+    store(o + (size_t)(N + j) * ld + N + m, Ds);
+  }
+}
+
+__global__ __launch_bounds__(64) void alpert_kernel(const AlpertJob* __restrict__ jobs, int njobs, int a) {
+  const int blk = blockIdx.x;
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].block_begin <= blk)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const AlpertJob& J = jobs[lo];
+  const int m = blk - J.block_begin;
+  const int N = J.N;
+  __shared__ cplx kv[kAlpertAux][4];
+  __shared__ double tpos[kAlpertAux];
+  const int lane = threadIdx.x;
+  if (lane < kAlpertAux) {
+    const size_t q = (size_t)m * kAlpertAux + lane;
+    const Kern4 K = lp_kernels_diff(J.ka, J.kb, J.r2[q], J.nd[q], J.npd[q], J.nn[q]);
+    const double c = J.cw[q];
+    kv[lane][0] = {K.D.re * c, K.D.im * c};
+    kv[lane][1] = {K.S.re * c, K.S.im * c};
+    kv[lane][2] = {K.T.re * c, K.T.im * c};
+    kv[lane][3] = {K.Ds.re * c, K.Ds.im * c};
+    tpos[lane] = J.t[q];
+  }
+  __syncthreads();
+  const int half = a + 8;
+  if (lane > 2 * half) return;
+  const int Jx = m - half + lane;  // extended column index
+  cplx acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+  bool any = false;
+  for (int q = 0; q < kAlpertAux; ++q) {
+    const double t = tpos[q];
+    const int j0 = (int)floor(t) - (kAlpertStencil / 2 - 1);
+    const int r = Jx - j0;
+    if (r < 0 || r >= kAlpertStencil) continue;
+    double L = 1.0;
+    for (int s = 0; s < kAlpertStencil; ++s) {
+      if (s == r) continue;
+      L *= (t - (double)(j0 + s)) / (double)(r - s);
+    }
+    any = true;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      acc[e].re += L * kv[q][e].re;
+      acc[e].im += L * kv[q][e].im;
+    }
+  }
+  if (!any) return;
+  const int l = (Jx >= 0) ? Jx / N : -((-Jx + N - 1) / N);
+  const int col = Jx - l * N;
+  cplx* o = J.out[l + 1];
+  const int ld = 2 * N;
+  const size_t idx[4] = {(size_t)col * ld + m, (size_t)(N + col) * ld + m, (size_t)col * ld + N + m,
+                         (size_t)(N + col) * ld + N + m};
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    double2 v = *reinterpret_cast<double2*>(o + idx[e]);
+    v.x += acc[e].re;
+    v.y += acc[e].im;
+    *reinterpret_cast<double2*>(o + idx[e]) = v;
+  }
+}
+
+__global__ __launch_bounds__(256) void assemble_kernel(const AsmJob* __restrict__ jobs, int njobs,
+                                                      int64_t total) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].elem_begin <= e)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const AsmJob& J = jobs[lo];
+  const int64_t le = e - J.elem_begin;
+  const int r = (int)(le % J.rows), c = (int)(le / J.rows);
+  double re = 0.0, im = 0.0;
+  for (int p = 0; p < J.npieces; ++p) {
+    const double2 v = *reinterpret_cast<const double2*>(J.src[p] + (size_t)c * J.lds + r);
+    re += J.coef[p].re * v.x - J.coef[p].im * v.y;
+    im += J.coef[p].re * v.y + J.coef[p].im * v.x;
+  }
+  *reinterpret_cast<double2*>(J.dst + (size_t)c * J.ldd + r) = make_double2(re, im);
+}
+
+__global__ void hankel_eval_kernel(const double* x, double* out, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  cplx h0, g;
+  hankel_pieces(x[i], h0, g);
+  out[4 * i + 0] = h0.re;
+  out[4 * i + 1] = h0.im;
+  out[4 * i + 2] = g.re;
+  out[4 * i + 3] = g.im;
+}
+
+void launch_fill(const FillJob* d_jobs, int njobs, int total_tiles, hipStream_t st) {
+  if (total_tiles > 0) hipLaunchKernelGGL(fill_kernel, dim3(total_tiles), dim3(256), 0, st, d_jobs, njobs);
+}
+void launch_self(const SelfJob* d_jobs, int njobs, int total_tiles, int a_excl, hipStream_t st) {
+  if (total_tiles > 0)
+    hipLaunchKernelGGL(self_kernel, dim3(total_tiles), dim3(256), 0, st, d_jobs, njobs, a_excl);
+}
+void launch_alpert(const AlpertJob* d_jobs, int njobs, int total_blocks, int a_excl, hipStream_t st) {
+  if (total_blocks > 0)
+    hipLaunchKernelGGL(alpert_kernel, dim3(total_blocks), dim3(64), 0, st, d_jobs, njobs, a_excl);
+}
+void launch_assemble(const AsmJob* d_jobs, int njobs, int64_t total_elems, hipStream_t st) {
+  if (total_elems > 0)
+    hipLaunchKernelGGL(assemble_kernel, dim3((unsigned)((total_elems + 255) / 256)), dim3(256), 0, st, d_jobs,
+                       njobs, total_elems);
+}
+void launch_hankel_eval(const double* x, double* out, int n, hipStream_t st) {
+  if (n > 0) hipLaunchKernelGGL(hankel_eval_kernel, dim3((n + 255) / 256), dim3(256), 0, st, x, out, n);
+}
+
+}  // namespace mlh

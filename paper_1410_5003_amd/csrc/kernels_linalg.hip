@@ -1,0 +1,563 @@
+// Dense complex float64 linear algebra of the solve phase (Sec. 3):
+//
+//  zgemm_kernel     batched C += alpha A B on the FP64 matrix cores
+//                   (v_mfma_f64_16x16x4f64, four real products per complex
+//                   product); Schur updates eq. (74)-(78) and the sweep update.
+//                   Operand layout of the 16x16x4 f64 instruction: lane l holds
+//                   A[l%16][l/16] and B[l/16][l%16]; accumulator register r of
+//                   lane l holds D[l/16 + 4r][l%16].
+//  ls_qr_kernel     Householder QR of the Tikhonov-stacked [Q; mu I] of one
+//                   layer (Sec. 3.2: backward-stable least squares, the
+//                   pseudo-inverse is never formed).
+//  ls_apply_kernel  Q^H and R^{-1} applied to the stacked right-hand side
+//                   [C; 0], one wavefront per column: X = Q^+ C.
+//  lu_kernel        LU with partial pivoting of one diagonal block of the
+//                   block-tridiagonal sweep (Sec. 3.3).
+//  lu_solve_kernel  forward/back substitution for [A'_{i,i+1} | f~_i].
+//  backsub_kernel   backward sweep eta_i = g_i - U_i eta_{i+1}.
+//  rb_setup_kernel  Rayleigh-Bloch rows W_U, W_D (eq. (59)) and the
+//                   incident-field right-hand side f (Sec. 2.2).
+//  bragg_kernel     a^U = -[X_1 eta_1]_a, a^D = -[X_{I+1} eta_I]_a (Sec. 3.3)
+//                   and the flux error eq. (86).
+#include "internal.hpp"
+
+namespace mlh {
+
+typedef double dvec4 __attribute__((ext_vector_type(4)));
+
+template <class T>
+__device__ inline int find_tile(const T* d, int n, int key) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (d[mid].tile_begin <= key)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ inline double2 ld2(const cplx* p) { return *reinterpret_cast<const double2*>(p); }
+__device__ inline void st2(cplx* p, double re, double im) {
+  *reinterpret_cast<double2*>(p) = make_double2(re, im);
+}
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// batched complex GEMM: 32 x 32 output tile per workgroup, 4 wavefronts each
+// owning a 16 x 16 sub-tile; k staged through LDS in slabs of 16.
+// ---------------------------------------------------------------------------
+constexpr int kGT = 32;
+constexpr int kGK = 16;
+
+__global__ __launch_bounds__(256) void zgemm_kernel(const GemmDesc* __restrict__ descs, int ndesc) {
+  const GemmDesc& G = descs[find_tile(descs, ndesc, (int)blockIdx.x)];
+  const int lt = blockIdx.x - G.tile_begin;
+  const int row0 = (lt % G.tiles_m) * kGT, col0 = (lt / G.tiles_m) * kGT;
+  __shared__ double Ar[kGK][kGT + 1], Ai[kGK][kGT + 1];
+  __shared__ double Br[kGK][kGT + 1], Bi[kGK][kGT + 1];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wm = (wave & 1) * 16, wn = (wave >> 1) * 16;
+  dvec4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+  const int m = G.m, n = G.n, K1 = G.k, K = G.k + G.k2;
+  for (int k0 = 0; k0 < K; k0 += kGK) {
+    for (int e = tid; e < kGT * kGK; e += 256) {
+      const int r = e % kGT, kk = e / kGT;
+      const int gr = row0 + r, gk = k0 + kk;
+      double2 v = make_double2(0.0, 0.0);
+      if (gr < m && gk < K)
+        v = gk < K1 ? ld2(G.A + (size_t)gk * G.lda + gr) : ld2(G.A2 + (size_t)(gk - K1) * G.lda2 + gr);
+      Ar[kk][r] = v.x;
+      Ai[kk][r] = v.y;
+    }
+    for (int e = tid; e < kGT * kGK; e += 256) {
+      const int kk = e % kGK, c = e / kGK;
+      const int gc = col0 + c, gk = k0 + kk;
+      double2 v = make_double2(0.0, 0.0);
+      if (gc < n && gk < K)
+        v = gk < K1 ? ld2(G.B + (size_t)gc * G.ldb + gk) : ld2(G.B2 + (size_t)gc * G.ldb2 + (gk - K1));
+      Br[kk][c] = v.x;
+      Bi[kk][c] = v.y;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < kGK; kk += 4) {
+      const int ka = kk + (lane >> 4);
+      const double ar = Ar[ka][wm + (lane & 15)], ai = Ai[ka][wm + (lane & 15)];
+      const double br = Br[ka][wn + (lane & 15)], bi = Bi[ka][wn + (lane & 15)];
+      cr = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, cr, 0, 0, 0);
+      cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, bi, cr, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, ci, 0, 0, 0);
+      ci = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, ci, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  const int col = col0 + wn + (lane & 15);
+  if (col >= n) return;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = row0 + wm + (lane >> 4) + 4 * r;
+    if (row < m) {
+      cplx* p = G.C + (size_t)col * G.ldc + row;
+      const double2 c = ld2(p);
+      const double xr = cr[r], xi = ci[r];
+      st2(p, c.x + G.alpha.re * xr - G.alpha.im * xi, c.y + G.alpha.re * xi + G.alpha.im * xr);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// least squares of one layer: Householder QR of S = [Q; mu I]
+// ---------------------------------------------------------------------------
+__device__ inline double block_sum(double v, double* red) {
+  const int tid = threadIdx.x;
+  v = wave_sum(v);
+  __syncthreads();
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+  return s;
+}
+
+__global__ __launch_bounds__(256) void ls_qr_kernel(const LsDesc* __restrict__ descs) {
+  const LsDesc& L = descs[blockIdx.x];
+  const int m = L.m, c = L.c, M = m + c;
+  cplx* S = L.S;
+  __shared__ double red[8];
+  __shared__ double sh[6];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  double acc = 0.0;
+  for (int e = tid; e < m * c; e += 256) {
+    const double2 v = ld2(S + (size_t)(e / m) * M + (e % m));
+    acc += v.x * v.x + v.y * v.y;
+  }
+  const double mu = L.mu_rel * sqrt(block_sum(acc, red));
+  for (int e = tid; e < c * c; e += 256) {
+    const int r = e % c, col = e / c;
+    st2(S + (size_t)col * M + m + r, r == col ? mu : 0.0, 0.0);
+  }
+  __syncthreads();
+  for (int kc = 0; kc < c; ++kc) {
+    cplx* col = S + (size_t)kc * M;
+    acc = 0.0;
+    for (int r = kc + 1 + tid; r < M; r += 256) {
+      const double2 v = ld2(col + r);
+      acc += v.x * v.x + v.y * v.y;
+    }
+    const double xn2 = block_sum(acc, red);
+    if (tid == 0) {
+      const double2 al = ld2(col + kc);
+      double tr = 0.0, ti = 0.0, sr = 1.0, si = 0.0, beta = al.x;
+      if (!(xn2 == 0.0 && al.y == 0.0)) {
+        beta = -copysign(sqrt(al.x * al.x + al.y * al.y + xn2), al.x);
+        tr = (beta - al.x) / beta;
+        ti = -al.y / beta;
+        // scale = 1 / (alpha - beta)
+        const double dr = al.x - beta, di = al.y;
+        const double den = dr * dr + di * di;
+        sr = dr / den;
+        si = -di / den;
+      }
+      sh[0] = tr;
+      sh[1] = ti;
+      sh[2] = sr;
+      sh[3] = si;
+      sh[4] = beta;
+      st2(L.tau + kc, tr, ti);
+    }
+    __syncthreads();
+    const double sr = sh[2], si = sh[3];
+    for (int r = kc + 1 + tid; r < M; r += 256) {
+      const double2 v = ld2(col + r);
+      st2(col + r, v.x * sr - v.y * si, v.x * si + v.y * sr);
+    }
+    if (tid == 0) st2(col + kc, sh[4], 0.0);
+    __syncthreads();
+    // trailing columns: S[kc:, j] -= conj(tau) v (v^H S[kc:, j])
+    const double ctr = sh[0], cti = -sh[1];
+    for (int j = kc + 1 + wave; j < c; j += 4) {
+      cplx* cj = S + (size_t)j * M;
+      double wr = 0.0, wi = 0.0;
+      for (int r = kc + lane; r < M; r += 64) {
+        const double2 b = ld2(cj + r);
+        double vr = 1.0, vi = 0.0;
+        if (r > kc) {
+          const double2 v = ld2(col + r);
+          vr = v.x;
+          vi = v.y;
+        }
+        // conj(v) * b
+        wr += vr * b.x + vi * b.y;
+        wi += vr * b.y - vi * b.x;
+      }
+      wr = wave_sum(wr);
+      wi = wave_sum(wi);
+      const double tr2 = ctr * wr - cti * wi, ti2 = ctr * wi + cti * wr;
+      for (int r = kc + lane; r < M; r += 64) {
+        double vr = 1.0, vi = 0.0;
+        if (r > kc) {
+          const double2 v = ld2(col + r);
+          vr = v.x;
+          vi = v.y;
+        }
+        const double2 b = ld2(cj + r);
+        st2(cj + r, b.x - (vr * tr2 - vi * ti2), b.y - (vr * ti2 + vi * tr2));
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// one wavefront per right-hand-side column; 4 columns per workgroup share the
+// reflector staged in LDS
+__global__ __launch_bounds__(256) void ls_apply_kernel(const LsDesc* __restrict__ descs, int ndesc) {
+  int lo = 0, hi = ndesc - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (descs[mid].col_block_begin <= (int)blockIdx.x)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const LsDesc& L = descs[lo];
+  const int m = L.m, c = L.c, M = m + c;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int colidx = ((int)blockIdx.x - L.col_block_begin) * 4 + wave;
+  const bool active = colidx < L.ncol;
+  extern __shared__ double2 smem[];
+  double2* v = smem;
+  double2* b = smem + M + (size_t)wave * M;
+  cplx* gcol = L.RHS + (size_t)(active ? colidx : 0) * M;
+  for (int r = lane; r < M; r += 64) b[r] = active ? ld2(gcol + r) : make_double2(0.0, 0.0);
+  for (int kc = 0; kc < c; ++kc) {
+    __syncthreads();
+    const cplx* sc = L.S + (size_t)kc * M;
+    for (int r = kc + tid; r < M; r += 256) v[r] = (r == kc) ? make_double2(1.0, 0.0) : ld2(sc + r);
+    __syncthreads();
+    double wr = 0.0, wi = 0.0;
+    for (int r = kc + lane; r < M; r += 64) {
+      const double2 vv = v[r], bb = b[r];
+      wr += vv.x * bb.x + vv.y * bb.y;
+      wi += vv.x * bb.y - vv.y * bb.x;
+    }
+    wr = wave_sum(wr);
+    wi = wave_sum(wi);
+    const double2 t = ld2(L.tau + kc);
+    // conj(tau) * w
+    const double tr = t.x * wr + t.y * wi, ti = t.x * wi - t.y * wr;
+    for (int r = kc + lane; r < M; r += 64) {
+      const double2 vv = v[r];
+      double2 bb = b[r];
+      bb.x -= vv.x * tr - vv.y * ti;
+      bb.y -= vv.x * ti + vv.y * tr;
+      b[r] = bb;
+    }
+  }
+  __syncthreads();
+  // R X = (Q^H B)[0:c]
+  for (int kc = c - 1; kc >= 0; --kc) {
+    const double rkk = ld2(L.S + (size_t)kc * M + kc).x;
+    const double2 bk = b[kc];
+    const double xr = bk.x / rkk, xi = bk.y / rkk;
+    const cplx* rc = L.S + (size_t)kc * M;
+    for (int r = lane; r < kc; r += 64) {
+      const double2 rv = ld2(rc + r);
+      double2 bb = b[r];
+      bb.x -= rv.x * xr - rv.y * xi;
+      bb.y -= rv.x * xi + rv.y * xr;
+      b[r] = bb;
+    }
+    __syncthreads();
+    if (lane == 0) b[kc] = make_double2(xr, xi);
+    __syncthreads();
+  }
+  if (active)
+    for (int r = lane; r < c; r += 64) st2(gcol + r, b[r].x, b[r].y);
+}
+
+// ---------------------------------------------------------------------------
+// LU with partial pivoting, one workgroup per matrix
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void lu_kernel(const LuDesc* __restrict__ descs) {
+  const LuDesc& D = descs[blockIdx.x];
+  const int n = D.n, lda = D.lda;
+  cplx* A = D.A;
+  __shared__ double bval[16];
+  __shared__ int bidx[16];
+  __shared__ int sp;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int k = 0; k < n; ++k) {
+    double best = -1.0;
+    int bi = k;
+    for (int r = k + tid; r < n; r += 1024) {
+      const double2 v = ld2(A + (size_t)k * lda + r);
+      const double a = v.x * v.x + v.y * v.y;
+      if (a > best) {
+        best = a;
+        bi = r;
+      }
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+      const double ob = __shfl_xor(best, o, 64);
+      const int oi = __shfl_xor(bi, o, 64);
+      if (ob > best || (ob == best && oi < bi)) {
+        best = ob;
+        bi = oi;
+      }
+    }
+    if (lane == 0) {
+      bval[wave] = best;
+      bidx[wave] = bi;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double b = bval[0];
+      int i = bidx[0];
+      for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
+        if (bval[w] > b || (bval[w] == b && bidx[w] < i)) {
+          b = bval[w];
+          i = bidx[w];
+        }
+      sp = i;
+      D.piv[k] = i;
+      if (b <= 0.0 && D.info[0] == 0) D.info[0] = k + 1;
+    }
+    __syncthreads();
+    const int p = sp;
+    if (p != k)
+      for (int c = tid; c < n; c += 1024) {
+        const double2 x = ld2(A + (size_t)c * lda + k), y = ld2(A + (size_t)c * lda + p);
+        st2(A + (size_t)c * lda + k, y.x, y.y);
+        st2(A + (size_t)c * lda + p, x.x, x.y);
+      }
+    __syncthreads();
+    const double2 pv = ld2(A + (size_t)k * lda + k);
+    const double den = pv.x * pv.x + pv.y * pv.y;
+    if (den > 0.0) {
+      const double ir = pv.x / den, ii = -pv.y / den;
+      for (int r = k + 1 + tid; r < n; r += 1024) {
+        const double2 v = ld2(A + (size_t)k * lda + r);
+        st2(A + (size_t)k * lda + r, v.x * ir - v.y * ii, v.x * ii + v.y * ir);
+      }
+    }
+    __syncthreads();
+    const int nt = n - k - 1;
+    const int tot = nt * nt;
+    for (int e = tid; e < tot; e += 1024) {
+      const int r = k + 1 + e % nt, c = k + 1 + e / nt;
+      const double2 l = ld2(A + (size_t)k * lda + r), u = ld2(A + (size_t)c * lda + k);
+      const double2 a = ld2(A + (size_t)c * lda + r);
+      st2(A + (size_t)c * lda + r, a.x - (l.x * u.x - l.y * u.y), a.y - (l.x * u.y + l.y * u.x));
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(64) void lu_solve_kernel(const LuSolveDesc* __restrict__ descs, int ndesc) {
+  int lo = 0, hi = ndesc - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (descs[mid].col_begin <= (int)blockIdx.x)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const LuSolveDesc& D = descs[lo];
+  const int col = blockIdx.x - D.col_begin;
+  const int n = D.n, lda = D.lda, lane = threadIdx.x;
+  extern __shared__ double2 bsh[];
+  const cplx* src = col < D.n1 ? D.B1 + (size_t)col * D.ldb1 : D.B2 + (size_t)(col - D.n1) * D.ldb2;
+  for (int r = lane; r < n; r += 64) bsh[r] = ld2(src + r);
+  __syncthreads();
+  if (lane == 0)
+    for (int k = 0; k < n; ++k) {
+      const int p = D.piv[k];
+      if (p != k) {
+        const double2 t = bsh[k];
+        bsh[k] = bsh[p];
+        bsh[p] = t;
+      }
+    }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    const double2 xk = bsh[k];
+    const cplx* lc = D.LU + (size_t)k * lda;
+    for (int r = k + 1 + lane; r < n; r += 64) {
+      const double2 l = ld2(lc + r);
+      double2 b = bsh[r];
+      b.x -= l.x * xk.x - l.y * xk.y;
+      b.y -= l.x * xk.y + l.y * xk.x;
+      bsh[r] = b;
+    }
+    __syncthreads();
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    const cplx* uc = D.LU + (size_t)k * lda;
+    const double2 u = ld2(uc + k);
+    const double2 bk = bsh[k];
+    const double den = u.x * u.x + u.y * u.y;
+    const double xr = (bk.x * u.x + bk.y * u.y) / den, xi = (bk.y * u.x - bk.x * u.y) / den;
+    for (int r = lane; r < k; r += 64) {
+      const double2 a = ld2(uc + r);
+      double2 b = bsh[r];
+      b.x -= a.x * xr - a.y * xi;
+      b.y -= a.x * xi + a.y * xr;
+      bsh[r] = b;
+    }
+    __syncthreads();
+    if (lane == 0) bsh[k] = make_double2(xr, xi);
+    __syncthreads();
+  }
+  cplx* dst = D.X + (size_t)col * n;
+  for (int r = lane; r < n; r += 64) st2(dst + r, bsh[r].x, bsh[r].y);
+}
+
+// ---------------------------------------------------------------------------
+// backward sweep, one workgroup per batch entry: eta_i = g_i - U_i eta_{i+1}
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void backsub_kernel(const BacksubDesc* __restrict__ descs, int I) {
+  const BacksubDesc* D = descs + (size_t)blockIdx.x * I;
+  const int tid = threadIdx.x;
+  {
+    const BacksubDesc& L = D[I - 1];
+    for (int r = tid; r < L.n; r += 256) {
+      const double2 g = ld2(L.UG + (size_t)L.nnext * L.n + r);
+      st2(L.eta + r, g.x, g.y);
+    }
+  }
+  __syncthreads();
+  for (int i = I - 2; i >= 0; --i) {
+    const BacksubDesc& L = D[i];
+    const cplx* en = D[i + 1].eta;
+    for (int r = tid; r < L.n; r += 256) {
+      double2 acc = ld2(L.UG + (size_t)L.nnext * L.n + r);
+      for (int j = 0; j < L.nnext; ++j) {
+        const double2 u = ld2(L.UG + (size_t)j * L.n + r);
+        const double2 e = ld2(en + j);
+        acc.x -= u.x * e.x - u.y * e.y;
+        acc.y -= u.x * e.y + u.y * e.x;
+      }
+      st2(L.eta + r, acc.x, acc.y);
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Rayleigh-Bloch orders, W blocks and the incident right-hand side
+// ---------------------------------------------------------------------------
+__device__ inline int rb_n0(double kappa0, double d) { return (int)floor(-kappa0 * d / (2.0 * kPi) + 0.5); }
+
+__device__ inline cplx vert_wavenumber(double k, double kappa) {
+  const double q = k * k - kappa * kappa;
+  if (fabs(q) <= 1e-14 * k * k) return {0.0, 0.0};
+  if (q > 0) return {sqrt(q), 0.0};
+  return {0.0, sqrt(-q)};
+}
+
+__global__ __launch_bounds__(256) void rb_setup_kernel(const AngleDesc* __restrict__ ang, StackConsts sc) {
+  const AngleDesc& A = ang[blockIdx.x];
+  const int nK = 2 * sc.K + 1;
+  const double kappa0 = sc.k1 * cos(A.theta);
+  const int n0 = rb_n0(kappa0, sc.d);
+  const int tid = threadIdx.x;
+  const int r0 = 2 * sc.Mw;
+  for (int e = tid; e < sc.Mud * nK; e += 256) {
+    const int mrow = e % sc.Mud, q = e / sc.Mud;
+    const double kap = kappa0 + 2.0 * kPi * (double)(n0 - sc.K + q) / sc.d;
+    double s, c;
+    sincos(kap * sc.xud[mrow], &s, &c);
+    const cplx ku = vert_wavenumber(sc.k1, kap), kd = vert_wavenumber(sc.kI1, kap);
+    cplx* wu = A.S0 + (size_t)(sc.P + q) * A.ldS0 + r0;
+    cplx* wd = A.SI + (size_t)(sc.P + q) * A.ldSI + r0;
+    st2(wu + mrow, -c, -s);
+    st2(wd + mrow, -c, -s);
+    // -i k^U e  and  +i k^D e
+    const cplx iku = {-ku.im, ku.re}, ikd = {-kd.im, kd.re};
+    st2(wu + sc.Mud + mrow, -(iku.re * c - iku.im * s), -(iku.re * s + iku.im * c));
+    st2(wd + sc.Mud + mrow, (ikd.re * c - ikd.im * s), (ikd.re * s + ikd.im * c));
+  }
+  const double kx = sc.k1 * cos(A.theta), ky = sc.k1 * sin(A.theta);
+  for (int j = tid; j < sc.N1; j += 256) {
+    double s, c;
+    sincos(kx * sc.x1[j] + ky * (sc.y0_1 + sc.y1[j]), &s, &c);
+    const double dn = kx * sc.nx1[j] + ky * sc.ny1[j];
+    st2(A.F0 + j, -c, -s);
+    // -(i dn) e
+    st2(A.F0 + sc.N1 + j, dn * s, -dn * c);
+  }
+}
+
+__global__ __launch_bounds__(64) void bragg_kernel(const AngleDesc* __restrict__ ang, StackConsts sc) {
+  const AngleDesc& A = ang[blockIdx.x];
+  const int nK = 2 * sc.K + 1;
+  const int lane = threadIdx.x;
+  const double kappa0 = sc.k1 * cos(A.theta);
+  const int n0 = rb_n0(kappa0, sc.d);
+  double fl = 0.0;
+  const int n1 = 2 * sc.N1, nI = 2 * sc.NI;
+  for (int q = lane; q < nK; q += 64) {
+    double ur = 0.0, ui = 0.0, dr = 0.0, di = 0.0;
+    for (int j = 0; j < n1; ++j) {
+      const double2 x = ld2(A.X0 + (size_t)j * A.ldX0 + sc.P + q), e = ld2(A.eta0 + j);
+      ur -= x.x * e.x - x.y * e.y;
+      ui -= x.x * e.y + x.y * e.x;
+    }
+    for (int j = 0; j < nI; ++j) {
+      const double2 x = ld2(A.XI + (size_t)j * A.ldXI + sc.P + q), e = ld2(A.etaI + j);
+      dr -= x.x * e.x - x.y * e.y;
+      di -= x.x * e.y + x.y * e.x;
+    }
+    st2(A.aU + q, ur, ui);
+    st2(A.aD + q, dr, di);
+    A.orders[q] = n0 - sc.K + q;
+    const double kap = kappa0 + 2.0 * kPi * (double)(n0 - sc.K + q) / sc.d;
+    const cplx ku = vert_wavenumber(sc.k1, kap), kd = vert_wavenumber(sc.kI1, kap);
+    if (ku.im == 0.0 && ku.re > 0.0) fl += ku.re * (ur * ur + ui * ui);
+    if (kd.im == 0.0 && kd.re > 0.0) fl += kd.re * (dr * dr + di * di);
+  }
+  fl = wave_sum(fl);
+  if (lane == 0) {
+    const double inc = sc.k1 * fabs(sin(A.theta));
+    A.flux[0] = (fl - inc) / inc;
+  }
+}
+
+void launch_gemm(const GemmDesc* d_desc, int ndesc, int total_tiles, hipStream_t st) {
+  if (total_tiles > 0) hipLaunchKernelGGL(zgemm_kernel, dim3(total_tiles), dim3(256), 0, st, d_desc, ndesc);
+}
+void launch_ls_qr(const LsDesc* d_desc, int ndesc, hipStream_t st) {
+  if (ndesc > 0) hipLaunchKernelGGL(ls_qr_kernel, dim3(ndesc), dim3(256), 0, st, d_desc);
+}
+void launch_ls_apply(const LsDesc* d_desc, int ndesc, int total_col_blocks, int max_rows, hipStream_t st) {
+  if (total_col_blocks > 0)
+    hipLaunchKernelGGL(ls_apply_kernel, dim3(total_col_blocks), dim3(256), (size_t)5 * max_rows * sizeof(double2),
+                       st, d_desc, ndesc);
+}
+void launch_lu(const LuDesc* d_desc, int ndesc, hipStream_t st) {
+  if (ndesc > 0) hipLaunchKernelGGL(lu_kernel, dim3(ndesc), dim3(1024), 0, st, d_desc);
+}
+void launch_lu_solve(const LuSolveDesc* d_desc, int ndesc, int total_cols, int max_n, hipStream_t st) {
+  if (total_cols > 0)
+    hipLaunchKernelGGL(lu_solve_kernel, dim3(total_cols), dim3(64), (size_t)max_n * sizeof(double2), st, d_desc,
+                       ndesc);
+}
+void launch_rb_setup(const AngleDesc* d_ang, int nang, StackConsts sc, hipStream_t st) {
+  if (nang > 0) hipLaunchKernelGGL(rb_setup_kernel, dim3(nang), dim3(256), 0, st, d_ang, sc);
+}
+void launch_backsub(const BacksubDesc* d_desc, int I, int nbatch, hipStream_t st) {
+  if (nbatch > 0) hipLaunchKernelGGL(backsub_kernel, dim3(nbatch), dim3(256), 0, st, d_desc, I);
+}
+void launch_bragg(const AngleDesc* d_ang, int nang, StackConsts sc, hipStream_t st) {
+  if (nang > 0) hipLaunchKernelGGL(bragg_kernel, dim3(nang), dim3(64), 0, st, d_ang, sc);
+}
+
+}  // namespace mlh

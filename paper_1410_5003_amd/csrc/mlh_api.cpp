@@ -1,0 +1,1500 @@
+// Host side of the C ABI declared in include/mlh.h: argument validation,
+// quadrature geometry (Sec. 2.5), device memory layout, and the launch
+// sequence of the fill, least-squares, Schur and sweep phases (Sec. 2-3).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mlh.h"
+#include "alpert_rule.inc"
+#include "internal.hpp"
+
+using namespace mlh;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static mlh_status fail(mlh_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return fail(e_ == hipErrorOutOfMemory ? MLH_E_NOMEM : MLH_E_DEVICE,                  \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                      \
+  } while (0)
+
+#define MLH_TRY(expr)                 \
+  do {                                \
+    mlh_status s_ = (expr);           \
+    if (s_ != MLH_OK) return s_;      \
+  } while (0)
+
+extern "C" const char* mlh_last_error(void) { return g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+struct mlh_ctx_s {
+  int device;
+  hipStream_t stream;
+};
+
+extern "C" mlh_status mlh_ctx_create(int32_t device, void* hip_stream, mlh_ctx* out) {
+  if (!out) return fail(MLH_E_INVALID_ARG, "mlh_ctx_create: out is NULL");
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(MLH_E_INVALID_ARG, "mlh_ctx_create: no such device");
+  HIP_TRY(hipSetDevice(device));
+  *out = new mlh_ctx_s{device, (hipStream_t)hip_stream};
+  return MLH_OK;
+}
+
+extern "C" mlh_status mlh_ctx_destroy(mlh_ctx ctx) {
+  delete ctx;
+  return MLH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// host geometry of one smooth interface
+// ---------------------------------------------------------------------------
+namespace {
+
+struct FourierProfile {
+  std::vector<double> ca, sa, om;
+
+  double f(double x) const {
+    double s = 0.0;
+    for (size_t m = 0; m < om.size(); ++m) s += ca[m] * std::cos(om[m] * x) + sa[m] * std::sin(om[m] * x);
+    return s;
+  }
+  double fp(double x) const {
+    double s = 0.0;
+    for (size_t m = 0; m < om.size(); ++m) s += om[m] * (-ca[m] * std::sin(om[m] * x) + sa[m] * std::cos(om[m] * x));
+    return s;
+  }
+  // f(x + h) - f(x) from product formulas
+  double diff(double x, double h) const {
+    double s = 0.0;
+    for (size_t m = 0; m < om.size(); ++m) {
+      const double sh = std::sin(0.5 * om[m] * h), mid = om[m] * (x + 0.5 * h);
+      s += -2.0 * ca[m] * std::sin(mid) * sh + 2.0 * sa[m] * std::cos(mid) * sh;
+    }
+    return s;
+  }
+  // f(x + h) - f(x) - h f'(x), mode by mode
+  double rem(double x, double h) const {
+    double s = 0.0;
+    for (size_t m = 0; m < om.size(); ++m) {
+      const double u = om[m] * h;
+      const double su = std::sin(0.5 * u);
+      const double cm1 = -2.0 * su * su;
+      double smu;
+      if (std::fabs(u) < 0.5) {  // sin u - u by its Taylor series
+        const double u2 = u * u;
+        double term = -u * u2 / 6.0, acc = 0.0;
+        for (int k = 0; k < 12; ++k) {
+          acc += term;
+          term *= -u2 / ((2.0 * k + 4.0) * (2.0 * k + 5.0));
+        }
+        smu = acc;
+      } else {
+        smu = std::sin(u) - u;
+      }
+      const double c = std::cos(om[m] * x), s_ = std::sin(om[m] * x);
+      s += ca[m] * (c * cm1 - s_ * smu) + sa[m] * (s_ * cm1 + c * smu);
+    }
+    return s;
+  }
+};
+
+struct HostCurve {
+  int N = 0;
+  double y0 = 0.0;
+  FourierProfile prof;
+  std::vector<double> x, y, nx, ny, w;                   // y relative to y0
+  std::vector<double> ar2, and_, anpd, ann, acw, at;     // Alpert aux invariants, N x 30
+};
+
+void build_fourier_curve(const mlh_interface& in, double d, HostCurve& c) {
+  c.N = in.n_nodes;
+  c.y0 = in.y0;
+  c.prof.ca.assign(in.cos_coef, in.cos_coef + in.n_modes);
+  c.prof.sa.assign(in.sin_coef, in.sin_coef + in.n_modes);
+  c.prof.om.resize(in.n_modes);
+  for (int m = 0; m < in.n_modes; ++m) c.prof.om[m] = 2.0 * kPi * (m + 1) / d;
+  const int N = c.N;
+  const double hx = d / N;
+  c.x.resize(N);
+  c.y.resize(N);
+  c.nx.resize(N);
+  c.ny.resize(N);
+  c.w.resize(N);
+  for (int j = 0; j < N; ++j) {
+    const double x = -0.5 * d + hx * (j + 0.5);
+    const double fp = c.prof.fp(x);
+    const double nu = std::sqrt(1.0 + fp * fp);
+    c.x[j] = x;
+    c.y[j] = c.prof.f(x);
+    c.nx[j] = fp / nu;
+    c.ny[j] = -1.0 / nu;
+    c.w[j] = hx * nu;
+  }
+  // auxiliary nodes s_m +- chi_k h of the Alpert correction, with separations
+  // formed without cancellation
+  const size_t na = (size_t)N * kAlpertAux;
+  c.ar2.resize(na);
+  c.and_.resize(na);
+  c.anpd.resize(na);
+  c.ann.resize(na);
+  c.acw.resize(na);
+  c.at.resize(na);
+  for (int m = 0; m < N; ++m) {
+    const double xm = c.x[m];
+    const double fm = c.prof.fp(xm);
+    const double num = std::sqrt(1.0 + fm * fm);
+    for (int q = 0; q < kAlpertAux; ++q) {
+      const int kq = q % kAlpertJ;
+      const double sg = q < kAlpertJ ? 1.0 : -1.0;
+      const double chi = kAlpertChi[kq];
+      const double dx = sg * chi * hx;
+      const double xs = xm + dx;
+      const double fs = c.prof.fp(xs);
+      const double nus = std::sqrt(1.0 + fs * fs);
+      const double df = c.prof.diff(xm, dx);
+      const size_t i = (size_t)m * kAlpertAux + q;
+      c.ar2[i] = dx * dx + df * df;
+      c.and_[i] = c.prof.rem(xm, dx) / num;
+      c.anpd[i] = -c.prof.rem(xs, -dx) / nus;
+      c.ann[i] = (fm * fs + 1.0) / (num * nus);
+      c.acw[i] = kAlpertW[kq] * hx * nus;
+      c.at[i] = m + sg * chi;
+    }
+  }
+}
+
+// simple bump allocator over one device arena
+struct Arena {
+  char* base = nullptr;
+  size_t off = 0, cap = 0;
+  size_t reserve(size_t bytes) {
+    const size_t o = (off + 255) & ~size_t(255);
+    off = o + bytes;
+    return o;
+  }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// stack
+// ---------------------------------------------------------------------------
+struct mlh_stack_s {
+  mlh_ctx ctx = nullptr;
+  int I = 0, P = 0, Mw = 0, Mud = 0, K = 0, nK = 0;
+  double d = 0, yU = 0, yD = 0, R = 0, mu = 1e-14;
+  std::vector<double> k;
+  std::vector<HostCurve> curves;
+  std::vector<int> N, n;
+  std::vector<double> centre;  // proxy circle centre heights per layer
+
+  char* dmem = nullptr;
+  size_t dbytes = 0;
+  // device geometry
+  std::vector<double*> gx, gy, gnx, gny, gw;
+  std::vector<double*> ar2, and_, anpd, ann, acw, at;
+  std::vector<double*> wall_x, wall_y;  // per layer, y relative to centre
+  double* ud_x = nullptr;
+  double* ud_y = nullptr;  // zeros
+  std::vector<double*> px, py, pnx, pny;  // per layer, y relative to centre
+  // pieces
+  std::vector<cplx*> A_self, A_up, A_dn, B_own, B_below, C_own, C_above, Q;
+  cplx* Z_U = nullptr;
+  cplx* Z_D = nullptr;
+  cplx* V_U = nullptr;
+  cplx* V_D = nullptr;
+  // fill job tables on the device
+  FillJob* d_fill = nullptr;
+  int n_fill = 0, fill_tiles = 0;
+  SelfJob* d_self = nullptr;
+  int n_self = 0, self_tiles = 0;
+  AlpertJob* d_alp = nullptr;
+  int n_alp = 0, alp_blocks = 0;
+
+  // workspace views of the first angle of the last inspection solve
+  std::vector<cplx*> dbg_Dg, dbg_Up, dbg_Dn, dbg_S, dbg_RHS, dbg_UG, dbg_eta;
+
+  // solve workspace (reused across calls with the same batch size)
+  char* wmem = nullptr;
+  size_t wbytes = 0;
+};
+
+static size_t cbytes(size_t n) { return n * sizeof(cplx); }
+
+static mlh_status validate(const mlh_stack_desc* D) {
+  if (!D) return fail(MLH_E_INVALID_ARG, "desc is NULL");
+  if (D->abi_version != MLH_ABI_VERSION) return fail(MLH_E_INVALID_ARG, "abi_version mismatch");
+  if (D->I < 1) return fail(MLH_E_INVALID_ARG, "I must be >= 1");
+  if (!D->iface || !D->k) return fail(MLH_E_INVALID_ARG, "iface or k is NULL");
+  if (!(D->d > 0) || !std::isfinite(D->d)) return fail(MLH_E_INVALID_ARG, "period d must be positive");
+  for (int i = 0; i <= D->I; ++i)
+    if (!(D->k[i] > 0) || !std::isfinite(D->k[i])) return fail(MLH_E_INVALID_ARG, "wavenumbers must be positive");
+  if (D->P < 1 || !(D->R > 0)) return fail(MLH_E_INVALID_ARG, "need P >= 1 and R > 0");
+  if (D->M_w < 1 || D->K < 0) return fail(MLH_E_INVALID_ARG, "need M_w >= 1 and K >= 0");
+  if (D->M_ud < 2 * D->K + 1) return fail(MLH_E_INVALID_ARG, "M_ud must be >= 2K+1 (aliasing of Rayleigh-Bloch orders)");
+  if (D->ls_mu < 0 || !std::isfinite(D->ls_mu)) return fail(MLH_E_INVALID_ARG, "ls_mu must be >= 0");
+  const int nmin = 2 * (kAlpertA + 8) + 1;
+  for (int i = 0; i < D->I; ++i) {
+    const mlh_interface& f = D->iface[i];
+    if (f.kind == MLH_IFACE_POLYGON)
+      return fail(MLH_E_UNSUPPORTED, "cornered (polygon) interfaces are not supported by this build");
+    if (f.kind != MLH_IFACE_FOURIER) return fail(MLH_E_INVALID_ARG, "unknown interface kind");
+    if (f.n_modes < 0 || (f.n_modes > 0 && (!f.cos_coef || !f.sin_coef)))
+      return fail(MLH_E_INVALID_ARG, "Fourier coefficients missing");
+    if (f.n_nodes < nmin)
+      return fail(MLH_E_INVALID_ARG, "each interface needs at least " + std::to_string(nmin) + " nodes");
+    if (!std::isfinite(f.y0)) return fail(MLH_E_INVALID_ARG, "non-finite y0");
+  }
+  return MLH_OK;
+}
+
+// interfaces must be ordered and separated, radiation lines clear, proxy
+// circles must enclose their layer cell
+static mlh_status check_geometry(mlh_stack_s* s) {
+  const int G = 512;
+  std::vector<double> lo(s->I), hi(s->I);
+  std::vector<std::vector<double>> prof(s->I, std::vector<double>(G + 1));
+  for (int i = 0; i < s->I; ++i) {
+    lo[i] = 1e300;
+    hi[i] = -1e300;
+    for (int g = 0; g <= G; ++g) {
+      const double x = -0.5 * s->d + s->d * g / G;
+      const double y = s->curves[i].y0 + s->curves[i].prof.f(x);
+      prof[i][g] = y;
+      lo[i] = std::min(lo[i], y);
+      hi[i] = std::max(hi[i], y);
+    }
+  }
+  for (int i = 0; i + 1 < s->I; ++i)
+    for (int g = 0; g <= G; ++g)
+      if (!(prof[i + 1][g] < prof[i][g]))
+        return fail(MLH_E_GEOMETRY, "interfaces " + std::to_string(i + 1) + " and " + std::to_string(i + 2) + " cross");
+  if (!(s->yU > hi[0])) return fail(MLH_E_GEOMETRY, "y_U must lie above the first interface");
+  if (!(s->yD < lo[s->I - 1])) return fail(MLH_E_GEOMETRY, "y_D must lie below the last interface");
+  for (int j = 0; j <= s->I; ++j) {
+    const double top = j == 0 ? s->yU : hi[j - 1];
+    const double bot = j == s->I ? s->yD : lo[j];
+    const double c = s->centre[j];
+    const double r = std::hypot(0.5 * s->d, std::max(top - c, c - bot));
+    if (!(s->R > r))
+      return fail(MLH_E_GEOMETRY, "proxy circle of layer " + std::to_string(j + 1) + " does not enclose its cell");
+  }
+  return MLH_OK;
+}
+
+static void build_fill_tables(mlh_stack_s* s, std::vector<FillJob>& fj, std::vector<SelfJob>& sj,
+                              std::vector<AlpertJob>& aj) {
+  const int I = s->I;
+  const double d = s->d;
+  int tiles = 0;
+  auto add = [&](FillJob J) {
+    J.tiles_m = (J.Mt + kFillTileM - 1) / kFillTileM;
+    J.tile_begin = tiles;
+    tiles += J.tiles_m * ((J.Ns + kFillTileN - 1) / kFillTileN);
+    fj.push_back(J);
+  };
+  auto curve_src = [&](FillJob& J, int i) {
+    J.sx = s->gx[i];
+    J.sy = s->gy[i];
+    J.snx = s->gnx[i];
+    J.sny = s->gny[i];
+    J.sw = s->gw[i];
+    J.Ns = s->N[i];
+  };
+  auto curve_tgt = [&](FillJob& J, int i) {
+    J.tx = s->gx[i];
+    J.ty = s->gy[i];
+    J.tnx = s->gnx[i];
+    J.tny = s->gny[i];
+    J.Mt = s->N[i];
+  };
+  auto proxy_src = [&](FillJob& J, int layer) {
+    J.sx = s->px[layer];
+    J.sy = s->py[layer];
+    J.snx = s->pnx[layer];
+    J.sny = s->pny[layer];
+    J.sw = nullptr;
+    J.Ns = s->P;
+  };
+  auto three = [&](FillJob& J, cplx* base, size_t piece_elems) {
+    J.npieces = 3;
+    for (int l = 0; l < 3; ++l) {
+      J.tshift[l] = 0.0;
+      J.sshift[l] = (l - 1) * d;
+      J.out[l] = base + l * piece_elems;
+    }
+  };
+  // neighbour blocks A_{i,i+1} = -[...]^{k_{i+1}}, A_{i+1,i} = +[...]^{k_{i+1}}
+  for (int i = 0; i + 1 < I; ++i) {
+    FillJob J{};
+    curve_tgt(J, i);
+    curve_src(J, i + 1);
+    J.kind = kFillLayerPotential;
+    J.k = s->k[i + 1];
+    J.scale = -1.0;
+    J.dy0 = s->curves[i].y0 - s->curves[i + 1].y0;
+    J.ld = s->n[i];
+    three(J, s->A_up[i], (size_t)s->n[i] * s->n[i + 1]);
+    add(J);
+    FillJob K{};
+    curve_tgt(K, i + 1);
+    curve_src(K, i);
+    K.kind = kFillLayerPotential;
+    K.k = s->k[i + 1];
+    K.scale = 1.0;
+    K.dy0 = s->curves[i + 1].y0 - s->curves[i].y0;
+    K.ld = s->n[i + 1];
+    three(K, s->A_dn[i], (size_t)s->n[i + 1] * s->n[i]);
+    add(K);
+  }
+  // proxy blocks B_{i,i} (layer above) and B_{i,i+1} (layer below, negated)
+  for (int i = 0; i < I; ++i) {
+    for (int side = 0; side < 2; ++side) {
+      const int layer = i + side;
+      FillJob J{};
+      curve_tgt(J, i);
+      proxy_src(J, layer);
+      J.kind = kFillProxy;
+      J.k = s->k[layer];
+      J.scale = side ? -1.0 : 1.0;
+      J.dy0 = s->curves[i].y0 - s->centre[layer];
+      J.ld = s->n[i];
+      J.npieces = 1;
+      J.out[0] = side ? s->B_below[i] : s->B_own[i];
+      add(J);
+    }
+  }
+  // wall blocks: C (targets x + 2d and x - d) and Q (x + d and x), normal (1, 0)
+  for (int j = 0; j <= I; ++j) {
+    for (int side = 0; side < 2; ++side) {
+      const int src = side == 0 ? j : j - 1;  // C_own: Gamma_j ; C_above: Gamma_{j-1}
+      if (src < 0 || src >= I) continue;
+      FillJob J{};
+      J.tx = s->wall_x[j];
+      J.ty = s->wall_y[j];
+      J.tnx = nullptr;
+      J.tny = nullptr;
+      J.cnx = 1.0;
+      J.cny = 0.0;
+      J.Mt = s->Mw;
+      curve_src(J, src);
+      J.kind = kFillLayerPotential;
+      J.k = s->k[j];
+      J.scale = 1.0;
+      J.dy0 = s->centre[j] - s->curves[src].y0;
+      J.ld = 2 * s->Mw;
+      J.npieces = 2;
+      const size_t pe = (size_t)2 * s->Mw * s->n[src];
+      cplx* base = side == 0 ? s->C_own[j] : s->C_above[j];
+      J.tshift[0] = 2 * d;
+      J.tshift[1] = -d;
+      J.sshift[0] = J.sshift[1] = 0.0;
+      J.out[0] = base;
+      J.out[1] = base + pe;
+      add(J);
+    }
+    FillJob J{};
+    J.tx = s->wall_x[j];
+    J.ty = s->wall_y[j];
+    J.cnx = 1.0;
+    J.cny = 0.0;
+    J.Mt = s->Mw;
+    proxy_src(J, j);
+    J.kind = kFillProxy;
+    J.k = s->k[j];
+    J.scale = 1.0;
+    J.dy0 = 0.0;
+    J.ld = 2 * s->Mw;
+    J.npieces = 2;
+    J.tshift[0] = d;
+    J.tshift[1] = 0.0;
+    J.sshift[0] = J.sshift[1] = 0.0;
+    J.out[0] = s->Q[j];
+    J.out[1] = s->Q[j] + (size_t)2 * s->Mw * s->P;
+    add(J);
+  }
+  // radiation lines: Z_U / Z_D (3 copies) and V_U / V_D, normal (0, 1)
+  for (int side = 0; side < 2; ++side) {
+    const int ci = side == 0 ? 0 : I - 1;
+    const int layer = side == 0 ? 0 : I;
+    const double yline = side == 0 ? s->yU : s->yD;
+    FillJob J{};
+    J.tx = s->ud_x;
+    J.ty = s->ud_y;
+    J.cnx = 0.0;
+    J.cny = 1.0;
+    J.Mt = s->Mud;
+    curve_src(J, ci);
+    J.kind = kFillLayerPotential;
+    J.k = s->k[layer];
+    J.scale = 1.0;
+    J.dy0 = yline - s->curves[ci].y0;
+    J.ld = 2 * s->Mud;
+    three(J, side == 0 ? s->Z_U : s->Z_D, (size_t)2 * s->Mud * s->n[ci]);
+    add(J);
+    FillJob V{};
+    V.tx = s->ud_x;
+    V.ty = s->ud_y;
+    V.cnx = 0.0;
+    V.cny = 1.0;
+    V.Mt = s->Mud;
+    proxy_src(V, layer);
+    V.kind = kFillProxy;
+    V.k = s->k[layer];
+    V.scale = 1.0;
+    V.dy0 = yline - s->centre[layer];
+    V.ld = 2 * s->Mud;
+    V.npieces = 1;
+    V.out[0] = side == 0 ? s->V_U : s->V_D;
+    add(V);
+  }
+  s->fill_tiles = tiles;
+  // self blocks and Alpert corrections
+  int st = 0, ab = 0;
+  for (int i = 0; i < I; ++i) {
+    SelfJob S{};
+    S.x = s->gx[i];
+    S.y = s->gy[i];
+    S.nx = s->gnx[i];
+    S.ny = s->gny[i];
+    S.w = s->gw[i];
+    S.ka = s->k[i];
+    S.kb = s->k[i + 1];
+    S.d = d;
+    S.N = s->N[i];
+    const size_t pe = (size_t)s->n[i] * s->n[i];
+    for (int l = 0; l < 3; ++l) S.out[l] = s->A_self[i] + l * pe;
+    S.tiles_m = (S.N + kFillTileM - 1) / kFillTileM;
+    S.tile_begin = st;
+    st += S.tiles_m * ((S.N + kFillTileN - 1) / kFillTileN);
+    sj.push_back(S);
+    AlpertJob A{};
+    A.r2 = s->ar2[i];
+    A.nd = s->and_[i];
+    A.npd = s->anpd[i];
+    A.nn = s->ann[i];
+    A.cw = s->acw[i];
+    A.t = s->at[i];
+    A.ka = s->k[i];
+    A.kb = s->k[i + 1];
+    for (int l = 0; l < 3; ++l) A.out[l] = S.out[l];
+    A.N = s->N[i];
+    A.block_begin = ab;
+    ab += A.N;
+    aj.push_back(A);
+  }
+  s->self_tiles = st;
+  s->alp_blocks = ab;
+}
+
+static mlh_status run_fills(mlh_stack_s* s) {
+  hipStream_t st = s->ctx->stream;
+  launch_self(s->d_self, s->n_self, s->self_tiles, kAlpertA, st);
+  HIP_TRY(hipGetLastError());
+  launch_alpert(s->d_alp, s->n_alp, s->alp_blocks, kAlpertA, st);
+  HIP_TRY(hipGetLastError());
+  launch_fill(s->d_fill, s->n_fill, s->fill_tiles, st);
+  HIP_TRY(hipGetLastError());
+  return MLH_OK;
+}
+
+extern "C" mlh_status mlh_stack_create(mlh_ctx ctx, const mlh_stack_desc* D, mlh_stack* out) {
+  if (!ctx || !out) return fail(MLH_E_INVALID_ARG, "mlh_stack_create: NULL argument");
+  MLH_TRY(validate(D));
+  mlh_stack_s* s = new mlh_stack_s();
+  s->ctx = ctx;
+  s->I = D->I;
+  s->P = D->P;
+  s->Mw = D->M_w;
+  s->Mud = D->M_ud;
+  s->K = D->K;
+  s->nK = 2 * D->K + 1;
+  s->d = D->d;
+  s->yU = D->y_U;
+  s->yD = D->y_D;
+  s->R = D->R;
+  s->mu = D->ls_mu > 0 ? D->ls_mu : 1e-14;
+  s->k.assign(D->k, D->k + D->I + 1);
+  const int I = s->I;
+  s->curves.resize(I);
+  s->N.resize(I);
+  s->n.resize(I);
+  for (int i = 0; i < I; ++i) {
+    build_fourier_curve(D->iface[i], s->d, s->curves[i]);
+    s->N[i] = s->curves[i].N;
+    s->n[i] = 2 * s->N[i];
+  }
+  // proxy circle centres: middle of each layer's nominal extent
+  s->centre.resize(I + 1);
+  for (int j = 0; j <= I; ++j) {
+    const double top = j == 0 ? s->yU : s->curves[j - 1].y0;
+    const double bot = j == I ? s->yD : s->curves[j].y0;
+    s->centre[j] = 0.5 * (top + bot);
+  }
+  mlh_status gs = check_geometry(s);
+  if (gs != MLH_OK) {
+    delete s;
+    return gs;
+  }
+  // ---- device layout
+  Arena ar;
+  std::vector<size_t> o_geo(I), o_aux(I), o_wall(I + 1), o_prox(I + 1);
+  for (int i = 0; i < I; ++i) o_geo[i] = ar.reserve(sizeof(double) * 5 * s->N[i]);
+  for (int i = 0; i < I; ++i) o_aux[i] = ar.reserve(sizeof(double) * 6 * (size_t)s->N[i] * kAlpertAux);
+  for (int j = 0; j <= I; ++j) o_wall[j] = ar.reserve(sizeof(double) * 2 * s->Mw);
+  const size_t o_ud = ar.reserve(sizeof(double) * 2 * s->Mud);
+  for (int j = 0; j <= I; ++j) o_prox[j] = ar.reserve(sizeof(double) * 4 * s->P);
+  std::vector<size_t> o_as(I), o_au(I), o_ad(I), o_bo(I), o_bb(I), o_co(I + 1), o_ca(I + 1), o_q(I + 1);
+  for (int i = 0; i < I; ++i) o_as[i] = ar.reserve(cbytes((size_t)3 * s->n[i] * s->n[i]));
+  for (int i = 0; i + 1 < I; ++i) {
+    o_au[i] = ar.reserve(cbytes((size_t)3 * s->n[i] * s->n[i + 1]));
+    o_ad[i] = ar.reserve(cbytes((size_t)3 * s->n[i + 1] * s->n[i]));
+  }
+  for (int i = 0; i < I; ++i) {
+    o_bo[i] = ar.reserve(cbytes((size_t)s->n[i] * s->P));
+    o_bb[i] = ar.reserve(cbytes((size_t)s->n[i] * s->P));
+  }
+  for (int j = 0; j <= I; ++j) {
+    if (j < I) o_co[j] = ar.reserve(cbytes((size_t)2 * 2 * s->Mw * s->n[j]));
+    if (j > 0) o_ca[j] = ar.reserve(cbytes((size_t)2 * 2 * s->Mw * s->n[j - 1]));
+    o_q[j] = ar.reserve(cbytes((size_t)2 * 2 * s->Mw * s->P));
+  }
+  const size_t o_zu = ar.reserve(cbytes((size_t)3 * 2 * s->Mud * s->n[0]));
+  const size_t o_zd = ar.reserve(cbytes((size_t)3 * 2 * s->Mud * s->n[I - 1]));
+  const size_t o_vu = ar.reserve(cbytes((size_t)2 * s->Mud * s->P));
+  const size_t o_vd = ar.reserve(cbytes((size_t)2 * s->Mud * s->P));
+  // job tables are sized after the pointers are known
+  std::vector<FillJob> fj;
+  std::vector<SelfJob> sj;
+  std::vector<AlpertJob> aj;
+  const size_t o_fill = ar.reserve(sizeof(FillJob) * (size_t)(2 * I + 2 * I + 3 * (I + 1) + 4 + 8));
+  const size_t o_self = ar.reserve(sizeof(SelfJob) * I);
+  const size_t o_alp = ar.reserve(sizeof(AlpertJob) * I);
+  s->dbytes = ar.off;
+  hipError_t e = hipSetDevice(ctx->device);
+  if (e == hipSuccess) e = hipMalloc((void**)&s->dmem, s->dbytes);
+  if (e != hipSuccess) {
+    delete s;
+    return fail(e == hipErrorOutOfMemory ? MLH_E_NOMEM : MLH_E_DEVICE, "stack allocation failed");
+  }
+  char* b = s->dmem;
+  auto dp = [&](size_t o) { return reinterpret_cast<double*>(b + o); };
+  auto cp = [&](size_t o) { return reinterpret_cast<cplx*>(b + o); };
+  s->gx.resize(I);
+  s->gy.resize(I);
+  s->gnx.resize(I);
+  s->gny.resize(I);
+  s->gw.resize(I);
+  s->ar2.resize(I);
+  s->and_.resize(I);
+  s->anpd.resize(I);
+  s->ann.resize(I);
+  s->acw.resize(I);
+  s->at.resize(I);
+  std::vector<double> hbuf;
+  hipStream_t st = ctx->stream;
+  for (int i = 0; i < I; ++i) {
+    const int N = s->N[i];
+    double* g = dp(o_geo[i]);
+    s->gx[i] = g;
+    s->gy[i] = g + N;
+    s->gnx[i] = g + 2 * N;
+    s->gny[i] = g + 3 * N;
+    s->gw[i] = g + 4 * N;
+    const HostCurve& c = s->curves[i];
+    hbuf.clear();
+    for (auto* v : {&c.x, &c.y, &c.nx, &c.ny, &c.w}) hbuf.insert(hbuf.end(), v->begin(), v->end());
+    HIP_TRY(hipMemcpy(g, hbuf.data(), hbuf.size() * sizeof(double), hipMemcpyHostToDevice));
+    const size_t na = (size_t)N * kAlpertAux;
+    double* a = dp(o_aux[i]);
+    s->ar2[i] = a;
+    s->and_[i] = a + na;
+    s->anpd[i] = a + 2 * na;
+    s->ann[i] = a + 3 * na;
+    s->acw[i] = a + 4 * na;
+    s->at[i] = a + 5 * na;
+    hbuf.clear();
+    for (auto* v : {&c.ar2, &c.and_, &c.anpd, &c.ann, &c.acw, &c.at}) hbuf.insert(hbuf.end(), v->begin(), v->end());
+    HIP_TRY(hipMemcpy(a, hbuf.data(), hbuf.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
+  // walls: M_w Gauss-Legendre nodes on x = -d/2 between the layer's boundaries
+  std::vector<double> gl_t(s->Mw), gl_w(s->Mw);
+  {
+    const int M = s->Mw;
+    for (int i = 0; i < M; ++i) {  // Newton on P_M from the Chebyshev guess
+      double t = std::cos(kPi * (i + 0.75) / (M + 0.5));
+      for (int it = 0; it < 100; ++it) {
+        double p0 = 1.0, p1 = t;
+        for (int k = 2; k <= M; ++k) {
+          const double p2 = ((2.0 * k - 1.0) * t * p1 - (k - 1.0) * p0) / k;
+          p0 = p1;
+          p1 = p2;
+        }
+        if (M == 1) {
+          p1 = t;
+          p0 = 1.0;
+        }
+        const double dp = M * (t * p1 - p0) / (t * t - 1.0);
+        const double dt = p1 / dp;
+        t -= dt;
+        if (std::fabs(dt) < 1e-16) break;
+      }
+      gl_t[M - 1 - i] = t;
+    }
+  }
+  s->wall_x.resize(I + 1);
+  s->wall_y.resize(I + 1);
+  for (int j = 0; j <= I; ++j) {
+    const double top = j == 0 ? s->yU : s->curves[j - 1].y0 + s->curves[j - 1].prof.f(-0.5 * s->d);
+    const double bot = j == I ? s->yD : s->curves[j].y0 + s->curves[j].prof.f(-0.5 * s->d);
+    hbuf.assign(2 * s->Mw, -0.5 * s->d);
+    for (int m = 0; m < s->Mw; ++m) hbuf[s->Mw + m] = bot + (top - bot) * 0.5 * (gl_t[m] + 1.0) - s->centre[j];
+    double* w = dp(o_wall[j]);
+    s->wall_x[j] = w;
+    s->wall_y[j] = w + s->Mw;
+    HIP_TRY(hipMemcpy(w, hbuf.data(), hbuf.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
+  hbuf.assign(2 * s->Mud, 0.0);
+  for (int m = 0; m < s->Mud; ++m) hbuf[m] = -0.5 * s->d + s->d * (m + 0.5) / s->Mud;
+  s->ud_x = dp(o_ud);
+  s->ud_y = s->ud_x + s->Mud;
+  HIP_TRY(hipMemcpy(s->ud_x, hbuf.data(), hbuf.size() * sizeof(double), hipMemcpyHostToDevice));
+  s->px.resize(I + 1);
+  s->py.resize(I + 1);
+  s->pnx.resize(I + 1);
+  s->pny.resize(I + 1);
+  for (int j = 0; j <= I; ++j) {
+    hbuf.assign(4 * s->P, 0.0);
+    for (int p = 0; p < s->P; ++p) {
+      const double th = 2.0 * kPi * (p + 1) / s->P;
+      hbuf[p] = s->R * std::cos(th);
+      hbuf[s->P + p] = s->R * std::sin(th);
+      hbuf[2 * s->P + p] = std::cos(th);
+      hbuf[3 * s->P + p] = std::sin(th);
+    }
+    double* q = dp(o_prox[j]);
+    s->px[j] = q;
+    s->py[j] = q + s->P;
+    s->pnx[j] = q + 2 * s->P;
+    s->pny[j] = q + 3 * s->P;
+    HIP_TRY(hipMemcpy(q, hbuf.data(), hbuf.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
+  s->A_self.resize(I);
+  s->A_up.assign(I, nullptr);
+  s->A_dn.assign(I, nullptr);
+  s->B_own.resize(I);
+  s->B_below.resize(I);
+  s->C_own.assign(I + 1, nullptr);
+  s->C_above.assign(I + 1, nullptr);
+  s->Q.resize(I + 1);
+  for (int i = 0; i < I; ++i) {
+    s->A_self[i] = cp(o_as[i]);
+    if (i + 1 < I) {
+      s->A_up[i] = cp(o_au[i]);
+      s->A_dn[i] = cp(o_ad[i]);
+    }
+    s->B_own[i] = cp(o_bo[i]);
+    s->B_below[i] = cp(o_bb[i]);
+  }
+  for (int j = 0; j <= I; ++j) {
+    if (j < I) s->C_own[j] = cp(o_co[j]);
+    if (j > 0) s->C_above[j] = cp(o_ca[j]);
+    s->Q[j] = cp(o_q[j]);
+  }
+  s->Z_U = cp(o_zu);
+  s->Z_D = cp(o_zd);
+  s->V_U = cp(o_vu);
+  s->V_D = cp(o_vd);
+  build_fill_tables(s, fj, sj, aj);
+  s->d_fill = reinterpret_cast<FillJob*>(b + o_fill);
+  s->d_self = reinterpret_cast<SelfJob*>(b + o_self);
+  s->d_alp = reinterpret_cast<AlpertJob*>(b + o_alp);
+  s->n_fill = (int)fj.size();
+  s->n_self = (int)sj.size();
+  s->n_alp = (int)aj.size();
+  HIP_TRY(hipMemcpy(s->d_fill, fj.data(), sizeof(FillJob) * fj.size(), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(s->d_self, sj.data(), sizeof(SelfJob) * sj.size(), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(s->d_alp, aj.data(), sizeof(AlpertJob) * aj.size(), hipMemcpyHostToDevice));
+  mlh_status fs = run_fills(s);
+  if (fs == MLH_OK) {
+    hipError_t e2 = hipStreamSynchronize(st);
+    if (e2 != hipSuccess) fs = fail(MLH_E_DEVICE, std::string("fill: ") + hipGetErrorString(e2));
+  }
+  if (fs != MLH_OK) {
+    hipFree(s->dmem);
+    delete s;
+    return fs;
+  }
+  *out = s;
+  return MLH_OK;
+}
+
+extern "C" mlh_status mlh_stack_refill(mlh_stack s) {
+  if (!s) return fail(MLH_E_INVALID_ARG, "NULL stack");
+  HIP_TRY(hipSetDevice(s->ctx->device));
+  MLH_TRY(run_fills(s));
+  HIP_TRY(hipStreamSynchronize(s->ctx->stream));
+  return MLH_OK;
+}
+
+extern "C" mlh_status mlh_stack_destroy(mlh_stack s) {
+  if (!s) return MLH_OK;
+  hipSetDevice(s->ctx->device);
+  if (s->dmem) hipFree(s->dmem);
+  if (s->wmem) hipFree(s->wmem);
+  delete s;
+  return MLH_OK;
+}
+
+extern "C" mlh_status mlh_stack_info(mlh_stack s, int64_t* n_den, int64_t* n_tot, int64_t* device_bytes) {
+  if (!s) return fail(MLH_E_INVALID_ARG, "NULL stack");
+  int64_t nd = 0;
+  for (int v : s->n) nd += v;
+  if (n_den) *n_den = nd;
+  if (n_tot) *n_tot = nd + (int64_t)(s->I + 1) * s->P + 2 * s->nK;
+  if (device_bytes) *device_bytes = (int64_t)(s->dbytes + s->wbytes);
+  return MLH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// solve
+// ---------------------------------------------------------------------------
+namespace {
+
+inline cplx cx(double re, double im) { return cplx{re, im}; }
+inline cplx cpow_alpha(double phase, int p) { return cplx{std::cos(p * phase), std::sin(p * phase)}; }
+
+}  // namespace
+
+static void layer_dims(const mlh_stack_s* s, int j, int& m, int& c, int& ncol) {
+  const int I = s->I;
+  const bool end = (j == 0 || j == I);
+  m = 2 * s->Mw + (end ? 2 * s->Mud : 0);
+  c = s->P + (end ? s->nK : 0);
+  if (j == 0)
+    ncol = s->n[0];
+  else if (j == I)
+    ncol = s->n[I - 1];
+  else
+    ncol = s->n[j - 1] + s->n[j];
+}
+
+// HIP-event timer for the profiling entry point
+namespace {
+struct EvTimer {
+  hipStream_t st;
+  std::vector<hipEvent_t> ev;
+  std::vector<double*> dst;
+  std::vector<int> pairs;  // index of start event per interval
+  void begin(double* acc) {
+    hipEvent_t e;
+    hipEventCreate(&e);
+    hipEventRecord(e, st);
+    pairs.push_back((int)ev.size());
+    ev.push_back(e);
+    dst.push_back(acc);
+  }
+  void end() {
+    hipEvent_t e;
+    hipEventCreate(&e);
+    hipEventRecord(e, st);
+    ev.push_back(e);
+  }
+  void collect() {
+    hipStreamSynchronize(st);
+    for (size_t i = 0; i < pairs.size(); ++i) {
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, ev[pairs[i]], ev[pairs[i] + 1]);
+      *dst[i] += ms;
+    }
+    for (auto e : ev) hipEventDestroy(e);
+    ev.clear();
+    dst.clear();
+    pairs.clear();
+  }
+};
+}  // namespace
+
+static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta, double* aU, double* aD,
+                             int32_t* orders, double* flux_err, int stop_phase, mlh_profile* prof = nullptr) {
+  if (!s) return fail(MLH_E_INVALID_ARG, "NULL stack");
+  if (n_angles < 1 || !theta || !aU || !aD) return fail(MLH_E_INVALID_ARG, "mlh_solve: bad arguments");
+  for (int a = 0; a < n_angles; ++a)
+    if (!(theta[a] > -kPi && theta[a] < 0.0)) return fail(MLH_E_INVALID_ARG, "incident angle must lie in (-pi, 0)");
+  HIP_TRY(hipSetDevice(s->ctx->device));
+  hipStream_t st = s->ctx->stream;
+  const int I = s->I, P = s->P, nK = s->nK;
+  const std::vector<int>& n = s->n;
+  // ---- workspace size for one angle
+  size_t per = 0;
+  Arena ar;
+  auto plan = [&](Arena& A, std::vector<size_t>* offs) {
+    auto R = [&](size_t bytes) {
+      const size_t o = A.reserve(bytes);
+      if (offs) offs->push_back(o);
+    };
+    for (int i = 0; i < I; ++i) R(cbytes((size_t)n[i] * (n[i] + 1)));                    // Dg
+    for (int i = 0; i + 1 < I; ++i) R(cbytes((size_t)n[i] * n[i + 1]));                  // Up
+    for (int i = 0; i + 1 < I; ++i) R(cbytes((size_t)n[i + 1] * n[i]));                  // Dn
+    for (int i = 0; i < I; ++i) R(cbytes((size_t)n[i] * ((i + 1 < I ? n[i + 1] : 0) + 1)));  // UG
+    for (int j = 0; j <= I; ++j) {
+      int m, c, nc;
+      layer_dims(s, j, m, c, nc);
+      R(cbytes((size_t)(m + c) * c));   // S
+      R(cbytes((size_t)c));             // tau
+      R(cbytes((size_t)(m + c) * nc));  // RHS / X
+    }
+    for (int i = 0; i < I; ++i) R(sizeof(int) * n[i]);  // pivots
+    for (int i = 0; i < I; ++i) R(cbytes(n[i]));        // eta
+    R(cbytes(2 * nK));                                  // aU, aD
+    R(sizeof(double) * 2);                              // flux
+    R(sizeof(int) * nK);                                // orders
+  };
+  plan(ar, nullptr);
+  per = (ar.off + 255) & ~size_t(255);
+  // descriptor space (generous upper bound per angle)
+  const size_t desc_per = sizeof(AsmJob) * (size_t)(10 * (I + 2)) + sizeof(GemmDesc) * (size_t)(6 * I + 4) +
+                          sizeof(LsDesc) * (size_t)(2 * (I + 1)) + sizeof(LuDesc) * I + sizeof(LuSolveDesc) * I +
+                          sizeof(BacksubDesc) * I + sizeof(AngleDesc) + 4096;
+  size_t freeb = 0, totb = 0;
+  HIP_TRY(hipMemGetInfo(&freeb, &totb));
+  int B = n_angles;
+  const size_t budget = (size_t)(0.8 * (double)(freeb + s->wbytes));
+  while (B > 1 && (size_t)B * (per + desc_per) > budget) B = (B + 1) / 2;
+  const size_t need = (size_t)B * (per + desc_per) + 4096;
+  if (need > s->wbytes) {
+    if (s->wmem) HIP_TRY(hipFree(s->wmem));
+    s->wmem = nullptr;
+    s->wbytes = 0;
+    HIP_TRY(hipMalloc((void**)&s->wmem, need));
+    s->wbytes = need;
+  }
+  std::vector<double> h_flux(n_angles);
+  for (int a0 = 0; a0 < n_angles; a0 += B) {
+    const int nb = std::min(B, n_angles - a0);
+    // ---- carve the workspace
+    std::vector<std::vector<size_t>> offs(nb);
+    std::vector<char*> wb(nb);
+    for (int b = 0; b < nb; ++b) {
+      Arena A;
+      plan(A, &offs[b]);
+      wb[b] = s->wmem + (size_t)b * per;
+    }
+    char* dbase = s->wmem + (size_t)B * per;
+    struct View {
+      std::vector<cplx*> Dg, Up, Dn, UG, S, tau, RHS, eta;
+      std::vector<int*> piv;
+      cplx *aU, *aD;
+      double* flux;
+      int* orders;
+    };
+    std::vector<View> V(nb);
+    for (int b = 0; b < nb; ++b) {
+      size_t k = 0;
+      auto C = [&]() { return reinterpret_cast<cplx*>(wb[b] + offs[b][k++]); };
+      View& v = V[b];
+      for (int i = 0; i < I; ++i) v.Dg.push_back(C());
+      for (int i = 0; i + 1 < I; ++i) v.Up.push_back(C());
+      for (int i = 0; i + 1 < I; ++i) v.Dn.push_back(C());
+      for (int i = 0; i < I; ++i) v.UG.push_back(C());
+      for (int j = 0; j <= I; ++j) {
+        v.S.push_back(C());
+        v.tau.push_back(C());
+        v.RHS.push_back(C());
+      }
+      for (int i = 0; i < I; ++i) v.piv.push_back(reinterpret_cast<int*>(wb[b] + offs[b][k++]));
+      for (int i = 0; i < I; ++i) v.eta.push_back(C());
+      v.aU = C();
+      v.aD = v.aU + nK;
+      v.flux = reinterpret_cast<double*>(wb[b] + offs[b][k++]);
+      v.orders = reinterpret_cast<int*>(wb[b] + offs[b][k++]);
+    }
+    // ---- descriptors
+    std::vector<AsmJob> asmj;
+    int64_t elems = 0;
+    auto asm_add = [&](cplx* dst, int ldd, int rows, int cols, int np, const cplx* const* src, int lds,
+                       const cplx* coef) {
+      AsmJob J{};
+      J.dst = dst;
+      J.ldd = ldd;
+      J.rows = rows;
+      J.cols = cols;
+      J.npieces = np;
+      J.lds = lds;
+      for (int p = 0; p < np; ++p) {
+        J.src[p] = src[p];
+        J.coef[p] = coef[p];
+      }
+      if (rows <= 0 || cols <= 0) return;
+      J.elem_begin = elems;
+      elems += (int64_t)rows * cols;
+      asmj.push_back(J);
+    };
+    std::vector<GemmDesc> gs;  // Schur GEMMs
+    int gtiles = 0;
+    auto gemm_add2 = [&](std::vector<GemmDesc>& vec, int& tiles, const cplx* A, int lda, const cplx* Bm, int ldb,
+                         cplx* Cm, int ldc, int m, int nn, int k, const cplx* A2, int lda2, const cplx* B2, int ldb2,
+                         int k2) {
+      GemmDesc G{};
+      G.A = A;
+      G.B = Bm;
+      G.A2 = A2;
+      G.B2 = B2;
+      G.lda2 = lda2;
+      G.ldb2 = ldb2;
+      G.k2 = k2;
+      G.C = Cm;
+      G.alpha = cx(-1.0, 0.0);
+      G.m = m;
+      G.n = nn;
+      G.k = k;
+      G.lda = lda;
+      G.ldb = ldb;
+      G.ldc = ldc;
+      G.tiles_m = (m + 31) / 32;
+      G.tile_begin = tiles;
+      tiles += G.tiles_m * ((nn + 31) / 32);
+      vec.push_back(G);
+    };
+    auto gemm_add = [&](std::vector<GemmDesc>& vec, int& tiles, const cplx* A, int lda, const cplx* Bm, int ldb,
+                        cplx* Cm, int ldc, int m, int nn, int k) {
+      gemm_add2(vec, tiles, A, lda, Bm, ldb, Cm, ldc, m, nn, k, nullptr, lda, nullptr, ldb, 0);
+    };
+    std::vector<LsDesc> ls;
+    int colblocks = 0, maxrows = 0;
+    std::vector<AngleDesc> angs(nb);
+    for (int b = 0; b < nb; ++b) {
+      View& v = V[b];
+      const double th = theta[a0 + b];
+      const double ph = s->d * s->k[0] * std::cos(th);  // alpha = e^{i ph}
+      const cplx a_m1 = cpow_alpha(ph, -1), a_p1 = cpow_alpha(ph, 1), a_m2 = cpow_alpha(ph, -2);
+      const cplx one = cx(1, 0), mone = cx(-1, 0);
+      const cplx c3[3] = {a_m1, one, a_p1};
+      const cplx cC[2] = {a_m2, cx(-a_p1.re, -a_p1.im)};
+      const cplx cQ[2] = {a_m1, mone};
+      for (int i = 0; i < I; ++i) {
+        const size_t pe = (size_t)n[i] * n[i];
+        const cplx* src[3] = {s->A_self[i], s->A_self[i] + pe, s->A_self[i] + 2 * pe};
+        asm_add(v.Dg[i], n[i], n[i], n[i], 3, src, n[i], c3);
+        if (i > 0) asm_add(v.Dg[i] + pe, n[i], n[i], 1, 0, src, n[i], c3);  // f~_i = 0
+        if (i + 1 < I) {
+          const size_t pu = (size_t)n[i] * n[i + 1];
+          const cplx* su[3] = {s->A_up[i], s->A_up[i] + pu, s->A_up[i] + 2 * pu};
+          asm_add(v.Up[i], n[i], n[i], n[i + 1], 3, su, n[i], c3);
+          const cplx* sd[3] = {s->A_dn[i], s->A_dn[i] + pu, s->A_dn[i] + 2 * pu};
+          asm_add(v.Dn[i], n[i + 1], n[i + 1], n[i], 3, sd, n[i + 1], c3);
+        }
+      }
+      for (int j = 0; j <= I; ++j) {
+        int m, c, nc;
+        layer_dims(s, j, m, c, nc);
+        const int M = m + c;
+        maxrows = std::max(maxrows, M);
+        const int mw2 = 2 * s->Mw, mud2 = 2 * s->Mud;
+        const size_t qe = (size_t)mw2 * P;
+        const cplx* sq[2] = {s->Q[j], s->Q[j] + qe};
+        asm_add(v.S[j], M, mw2, P, 2, sq, mw2, cQ);
+        if (j == 0 || j == I) {
+          const cplx* vv[1] = {j == 0 ? s->V_U : s->V_D};
+          asm_add(v.S[j] + mw2, M, mud2, P, 1, vv, mud2, &one);
+          asm_add(v.S[j] + (size_t)P * M, M, mw2, nK, 0, vv, mud2, &one);  // zero block
+          // RHS: [C; Z; 0]
+          const int ci = j == 0 ? 0 : I - 1;
+          const size_t ce = (size_t)mw2 * n[ci];
+          const cplx* cs = j == 0 ? s->C_own[0] : s->C_above[I];
+          const cplx* sc[2] = {cs, cs + ce};
+          asm_add(v.RHS[j], M, mw2, n[ci], 2, sc, mw2, cC);
+          const size_t ze = (size_t)mud2 * n[ci];
+          const cplx* zb = j == 0 ? s->Z_U : s->Z_D;
+          const cplx* sz[3] = {zb, zb + ze, zb + 2 * ze};
+          asm_add(v.RHS[j] + mw2, M, mud2, n[ci], 3, sz, mud2, c3);
+          asm_add(v.RHS[j] + m, M, c, n[ci], 0, sz, mud2, c3);
+        } else {
+          const size_t ea = (size_t)mw2 * n[j - 1], eo = (size_t)mw2 * n[j];
+          const cplx* sa[2] = {s->C_above[j], s->C_above[j] + ea};
+          const cplx* so[2] = {s->C_own[j], s->C_own[j] + eo};
+          asm_add(v.RHS[j], M, mw2, n[j - 1], 2, sa, mw2, cC);
+          asm_add(v.RHS[j] + (size_t)n[j - 1] * M, M, mw2, n[j], 2, so, mw2, cC);
+          asm_add(v.RHS[j] + m, M, c, nc, 0, sa, mw2, cC);
+        }
+        LsDesc L{};
+        L.S = v.S[j];
+        L.tau = v.tau[j];
+        L.RHS = v.RHS[j];
+        L.mu_rel = s->mu;
+        L.m = m;
+        L.c = c;
+        L.ncol = nc;
+        L.col_block_begin = colblocks;
+        colblocks += (nc + 3) / 4;
+        ls.push_back(L);
+      }
+      // Schur complements eq. (74)-(78)
+      for (int i = 0; i < I; ++i) {
+        int m0, c0, nc0, m1, c1, nc1;
+        layer_dims(s, i, m0, c0, nc0);
+        layer_dims(s, i + 1, m1, c1, nc1);
+        const int Ma = m0 + c0, Mb = m1 + c1;
+        const cplx* Xa = (i == 0) ? v.RHS[0] : v.RHS[i] + (size_t)n[i - 1] * Ma;
+        const cplx* Xb = v.RHS[i + 1];  // columns acting on eta_i come first
+        gemm_add2(gs, gtiles, s->B_own[i], n[i], Xa, Ma, v.Dg[i], n[i], n[i], n[i], P, s->B_below[i], n[i], Xb,
+                  Mb, P);
+        if (i + 1 < I) {
+          gemm_add(gs, gtiles, s->B_below[i], n[i], v.RHS[i + 1] + (size_t)n[i] * Mb, Mb, v.Up[i], n[i], n[i],
+                   n[i + 1], P);
+          gemm_add(gs, gtiles, s->B_own[i + 1], n[i + 1], v.RHS[i + 1], Mb, v.Dn[i], n[i + 1], n[i + 1], n[i], P);
+        }
+      }
+      AngleDesc& A = angs[b];
+      A.theta = th;
+      int m0, c0, nc0, mI, cI, ncI;
+      layer_dims(s, 0, m0, c0, nc0);
+      layer_dims(s, I, mI, cI, ncI);
+      A.S0 = v.S[0];
+      A.ldS0 = m0 + c0;
+      A.SI = v.S[I];
+      A.ldSI = mI + cI;
+      A.F0 = v.Dg[0] + (size_t)n[0] * n[0];
+      A.X0 = v.RHS[0];
+      A.ldX0 = m0 + c0;
+      A.XI = v.RHS[I];
+      A.ldXI = mI + cI;
+      A.eta0 = v.eta[0];
+      A.etaI = v.eta[I - 1];
+      A.aU = v.aU;
+      A.aD = v.aD;
+      A.orders = v.orders;
+      A.flux = v.flux;
+    }
+    // sweep descriptors per step
+    std::vector<std::vector<GemmDesc>> sg(I);
+    std::vector<int> sg_tiles(I, 0);
+    std::vector<std::vector<LuDesc>> lu(I);
+    std::vector<std::vector<LuSolveDesc>> lus(I);
+    std::vector<int> lus_cols(I, 0);
+    std::vector<BacksubDesc> bs;
+    int maxn = 0;
+    for (int i = 0; i < I; ++i) maxn = std::max(maxn, n[i]);
+    for (int b = 0; b < nb; ++b) {
+      View& v = V[b];
+      for (int i = 0; i < I; ++i) {
+        const int nn = (i + 1 < I) ? n[i + 1] : 0;
+        if (i > 0) gemm_add(sg[i], sg_tiles[i], v.Dn[i - 1], n[i], v.UG[i - 1], n[i - 1], v.Dg[i], n[i], n[i], n[i] + 1, n[i - 1]);
+        LuDesc L{};
+        L.A = v.Dg[i];
+        L.piv = v.piv[i];
+        L.n = n[i];
+        L.lda = n[i];
+        L.info = nullptr;
+        lu[i].push_back(L);
+        LuSolveDesc S{};
+        S.LU = v.Dg[i];
+        S.piv = v.piv[i];
+        S.n = n[i];
+        S.lda = n[i];
+        if (nn > 0) {
+          S.B1 = v.Up[i];
+          S.ldb1 = n[i];
+          S.n1 = nn;
+          S.B2 = v.Dg[i] + (size_t)n[i] * n[i];
+          S.ldb2 = n[i];
+          S.n2 = 1;
+        } else {
+          S.B1 = v.Dg[i] + (size_t)n[i] * n[i];
+          S.ldb1 = n[i];
+          S.n1 = 1;
+          S.B2 = nullptr;
+          S.ldb2 = n[i];
+          S.n2 = 0;
+        }
+        S.X = v.UG[i];
+        S.col_begin = lus_cols[i];
+        lus_cols[i] += S.n1 + S.n2;
+        lus[i].push_back(S);
+        BacksubDesc Bd{};
+        Bd.UG = v.UG[i];
+        Bd.eta = v.eta[i];
+        Bd.n = n[i];
+        Bd.nnext = nn;
+        bs.push_back(Bd);
+      }
+    }
+    // ---- upload descriptors
+    size_t doff = 0;
+    std::vector<char> hdesc;
+    auto push = [&](const void* p, size_t bytes) {
+      const size_t o = (doff + 255) & ~size_t(255);
+      hdesc.resize(o + bytes);
+      if (bytes && p) std::memcpy(hdesc.data() + o, p, bytes);
+      doff = o + bytes;
+      return o;
+    };
+    const size_t oi = push(nullptr, sizeof(int) * 4);
+    std::memset(hdesc.data() + oi, 0, sizeof(int) * 4);
+    int* d_info = reinterpret_cast<int*>(dbase + oi);
+    for (int i = 0; i < I; ++i)
+      for (auto& L : lu[i]) L.info = d_info;
+    const size_t o_asm = push(asmj.data(), sizeof(AsmJob) * asmj.size());
+    const size_t o_gs = push(gs.data(), sizeof(GemmDesc) * gs.size());
+    const size_t o_ls = push(ls.data(), sizeof(LsDesc) * ls.size());
+    const size_t o_ang = push(angs.data(), sizeof(AngleDesc) * angs.size());
+    std::vector<size_t> o_sg(I), o_lu(I), o_lus(I);
+    for (int i = 0; i < I; ++i) {
+      o_sg[i] = push(sg[i].data(), sizeof(GemmDesc) * sg[i].size());
+      o_lu[i] = push(lu[i].data(), sizeof(LuDesc) * lu[i].size());
+      o_lus[i] = push(lus[i].data(), sizeof(LuSolveDesc) * lus[i].size());
+    }
+    const size_t o_bs = push(bs.data(), sizeof(BacksubDesc) * bs.size());
+    if (doff > (size_t)B * desc_per) return fail(MLH_E_DEVICE, "descriptor space exhausted");
+    HIP_TRY(hipMemcpyAsync(dbase, hdesc.data(), doff, hipMemcpyHostToDevice, st));
+    StackConsts sc{};
+    sc.x1 = s->gx[0];
+    sc.y1 = s->gy[0];
+    sc.nx1 = s->gnx[0];
+    sc.ny1 = s->gny[0];
+    sc.xud = s->ud_x;
+    sc.y0_1 = s->curves[0].y0;
+    sc.d = s->d;
+    sc.k1 = s->k[0];
+    sc.kI1 = s->k[I];
+    sc.N1 = s->N[0];
+    sc.NI = s->N[I - 1];
+    sc.Mw = s->Mw;
+    sc.Mud = s->Mud;
+    sc.P = P;
+    sc.K = s->K;
+    // ---- launch sequence
+    EvTimer T{st};
+    double dummy = 0.0;
+    auto tb = [&](double* acc) {
+      if (prof) T.begin(acc ? acc : &dummy);
+    };
+    auto te = [&]() {
+      if (prof) T.end();
+    };
+    tb(prof ? &prof->assemble_ms : nullptr);
+    launch_assemble(reinterpret_cast<AsmJob*>(dbase + o_asm), (int)asmj.size(), elems, st);
+    te();
+    const AngleDesc* d_ang = reinterpret_cast<AngleDesc*>(dbase + o_ang);
+    tb(prof ? &prof->rb_setup_ms : nullptr);
+    launch_rb_setup(d_ang, nb, sc, st);
+    te();
+    const LsDesc* d_ls = reinterpret_cast<LsDesc*>(dbase + o_ls);
+    if (stop_phase == 0 || stop_phase >= 2) {
+      tb(prof ? &prof->ls_qr_ms : nullptr);
+      launch_ls_qr(d_ls, (int)ls.size(), st);
+      te();
+      tb(prof ? &prof->ls_apply_ms : nullptr);
+      launch_ls_apply(d_ls, (int)ls.size(), colblocks, maxrows, st);
+      te();
+    }
+    if (stop_phase == 0 || stop_phase >= 3) {
+      tb(prof ? &prof->schur_ms : nullptr);
+      launch_gemm(reinterpret_cast<GemmDesc*>(dbase + o_gs), (int)gs.size(), gtiles, st);
+      te();
+    }
+    if (stop_phase == 0 || stop_phase >= 4) {
+      for (int i = 0; i < I; ++i) {
+        if (i > 0) {
+          tb(prof ? &prof->sweep_gemm_ms : nullptr);
+          launch_gemm(reinterpret_cast<GemmDesc*>(dbase + o_sg[i]), (int)sg[i].size(), sg_tiles[i], st);
+          te();
+          if (prof) prof->n_sweep_gemm++;
+        }
+        tb(prof ? &prof->lu_ms : nullptr);
+        launch_lu(reinterpret_cast<LuDesc*>(dbase + o_lu[i]), (int)lu[i].size(), st);
+        te();
+        tb(prof ? &prof->lu_solve_ms : nullptr);
+        launch_lu_solve(reinterpret_cast<LuSolveDesc*>(dbase + o_lus[i]), (int)lus[i].size(), lus_cols[i], maxn,
+                        st);
+        te();
+        if (prof) {
+          prof->n_lu++;
+          prof->n_lu_solve++;
+        }
+      }
+      tb(prof ? &prof->backsub_ms : nullptr);
+      launch_backsub(reinterpret_cast<BacksubDesc*>(dbase + o_bs), I, nb, st);
+      te();
+      tb(prof ? &prof->bragg_ms : nullptr);
+      launch_bragg(d_ang, nb, sc, st);
+      te();
+    }
+    HIP_TRY(hipGetLastError());
+    if (prof) T.collect();
+    if (stop_phase != 0) {
+      // keep the first angle's workspace views for inspection
+      s->dbg_Dg = V[0].Dg;
+      s->dbg_Up = V[0].Up;
+      s->dbg_Dn = V[0].Dn;
+      s->dbg_S = V[0].S;
+      s->dbg_RHS = V[0].RHS;
+      s->dbg_UG = V[0].UG;
+      s->dbg_eta = V[0].eta;
+      HIP_TRY(hipStreamSynchronize(st));
+      return MLH_OK;
+    }
+    // ---- results
+    for (int b = 0; b < nb; ++b) {
+      const int a = a0 + b;
+      HIP_TRY(hipMemcpyAsync(aU + (size_t)2 * nK * a, V[b].aU, cbytes(nK), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipMemcpyAsync(aD + (size_t)2 * nK * a, V[b].aD, cbytes(nK), hipMemcpyDeviceToHost, st));
+      if (orders) HIP_TRY(hipMemcpyAsync(orders + (size_t)nK * a, V[b].orders, sizeof(int) * nK, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipMemcpyAsync(&h_flux[a], V[b].flux, sizeof(double), hipMemcpyDeviceToHost, st));
+    }
+    int info[4] = {0, 0, 0, 0};
+    HIP_TRY(hipMemcpyAsync(info, d_info, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (info[0] != 0) return fail(MLH_E_SINGULAR, "exact zero pivot in the block-tridiagonal sweep");
+  }
+  if (flux_err)
+    for (int a = 0; a < n_angles; ++a) flux_err[a] = h_flux[a];
+  return MLH_OK;
+}
+
+extern "C" mlh_status mlh_solve(mlh_stack s, int32_t n_angles, const double* theta, double* aU, double* aD,
+                                int32_t* orders, double* flux_err) {
+  return solve_impl(s, n_angles, theta, aU, aD, orders, flux_err, 0);
+}
+
+// ---------------------------------------------------------------------------
+// inspection entry points
+// ---------------------------------------------------------------------------
+extern "C" mlh_status mlh_debug_get_piece(mlh_stack s, int32_t which, int32_t index, int32_t piece, double* out,
+                                          int32_t* rows, int32_t* cols) {
+  if (!s) return fail(MLH_E_INVALID_ARG, "NULL stack");
+  const int I = s->I;
+  int r = 0, c = 0, np = 1;
+  const cplx* base = nullptr;
+  auto need = [&](bool ok) { return ok; };
+  switch (which) {
+    case 0:
+      if (!need(index >= 0 && index < I)) break;
+      r = c = s->n[index];
+      np = 3;
+      base = s->A_self[index];
+      break;
+    case 1:
+    case 2:
+      if (!need(index >= 0 && index + 1 < I)) break;
+      r = which == 1 ? s->n[index] : s->n[index + 1];
+      c = which == 1 ? s->n[index + 1] : s->n[index];
+      np = 3;
+      base = which == 1 ? s->A_up[index] : s->A_dn[index];
+      break;
+    case 3:
+    case 4:
+      if (!need(index >= 0 && index < I)) break;
+      r = s->n[index];
+      c = s->P;
+      base = which == 3 ? s->B_own[index] : s->B_below[index];
+      break;
+    case 5:
+      if (!need(index >= 0 && index < I)) break;
+      r = 2 * s->Mw;
+      c = s->n[index];
+      np = 2;
+      base = s->C_own[index];
+      break;
+    case 6:
+      if (!need(index >= 1 && index <= I)) break;
+      r = 2 * s->Mw;
+      c = s->n[index - 1];
+      np = 2;
+      base = s->C_above[index];
+      break;
+    case 7:
+      if (!need(index >= 0 && index <= I)) break;
+      r = 2 * s->Mw;
+      c = s->P;
+      np = 2;
+      base = s->Q[index];
+      break;
+    case 8:
+    case 9:
+      r = 2 * s->Mud;
+      c = which == 8 ? s->n[0] : s->n[I - 1];
+      np = 3;
+      base = which == 8 ? s->Z_U : s->Z_D;
+      break;
+    case 10:
+    case 11:
+      r = 2 * s->Mud;
+      c = s->P;
+      base = which == 10 ? s->V_U : s->V_D;
+      break;
+    default:
+      break;
+  }
+  if (!base || piece < 0 || piece >= np) return fail(MLH_E_INVALID_ARG, "mlh_debug_get_piece: no such piece");
+  if (rows) *rows = r;
+  if (cols) *cols = c;
+  if (out) {
+    HIP_TRY(hipSetDevice(s->ctx->device));
+    HIP_TRY(hipStreamSynchronize(s->ctx->stream));
+    HIP_TRY(hipMemcpy(out, base + (size_t)piece * r * c, cbytes((size_t)r * c), hipMemcpyDeviceToHost));
+  }
+  return MLH_OK;
+}
+
+extern "C" mlh_status mlh_debug_hankel(mlh_ctx ctx, int32_t n, const double* x, double* out) {
+  if (!ctx || n < 0 || (n > 0 && (!x || !out))) return fail(MLH_E_INVALID_ARG, "mlh_debug_hankel: bad arguments");
+  for (int i = 0; i < n; ++i)
+    if (!(x[i] > 0)) return fail(MLH_E_INVALID_ARG, "mlh_debug_hankel: arguments must be positive");
+  if (n == 0) return MLH_OK;
+  HIP_TRY(hipSetDevice(ctx->device));
+  double* d = nullptr;
+  HIP_TRY(hipMalloc((void**)&d, sizeof(double) * 5 * n));
+  hipMemcpy(d, x, sizeof(double) * n, hipMemcpyHostToDevice);
+  launch_hankel_eval(d, d + n, n, ctx->stream);
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e == hipSuccess) e = hipMemcpy(out, d + n, sizeof(double) * 4 * n, hipMemcpyDeviceToHost);
+  hipFree(d);
+  if (e != hipSuccess) return fail(MLH_E_DEVICE, hipGetErrorString(e));
+  return MLH_OK;
+}
+
+extern "C" mlh_status mlh_debug_zgemm(mlh_ctx ctx, int32_t m, int32_t n, int32_t k, const double* alpha,
+                                      const double* A, const double* Bm, double* C) {
+  if (!ctx || m < 1 || n < 1 || k < 1 || !alpha || !A || !Bm || !C)
+    return fail(MLH_E_INVALID_ARG, "mlh_debug_zgemm: bad arguments");
+  HIP_TRY(hipSetDevice(ctx->device));
+  const size_t na = (size_t)m * k, nb = (size_t)k * n, nc = (size_t)m * n;
+  char* d = nullptr;
+  const size_t bytes = cbytes(na + nb + nc) + sizeof(GemmDesc) + 256;
+  HIP_TRY(hipMalloc((void**)&d, bytes));
+  cplx* dA = reinterpret_cast<cplx*>(d);
+  cplx* dB = dA + na;
+  cplx* dC = dB + nb;
+  GemmDesc* dg = reinterpret_cast<GemmDesc*>(d + ((cbytes(na + nb + nc) + 255) & ~size_t(255)));
+  GemmDesc G{};
+  G.A = dA;
+  G.B = dB;
+  G.C = dC;
+  G.alpha = cx(alpha[0], alpha[1]);
+  G.k2 = 0;
+  G.m = m;
+  G.n = n;
+  G.k = k;
+  G.lda = m;
+  G.ldb = k;
+  G.ldc = m;
+  G.tiles_m = (m + 31) / 32;
+  G.tile_begin = 0;
+  const int tiles = G.tiles_m * ((n + 31) / 32);
+  hipError_t e = hipMemcpy(dA, A, cbytes(na), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(dB, Bm, cbytes(nb), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(dC, C, cbytes(nc), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(dg, &G, sizeof(G), hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    launch_gemm(dg, 1, tiles, ctx->stream);
+    e = hipStreamSynchronize(ctx->stream);
+  }
+  if (e == hipSuccess) e = hipMemcpy(C, dC, cbytes(nc), hipMemcpyDeviceToHost);
+  hipFree(d);
+  if (e != hipSuccess) return fail(MLH_E_DEVICE, hipGetErrorString(e));
+  return MLH_OK;
+}
+
+extern "C" mlh_status mlh_debug_solve_partial(mlh_stack s, double theta, int32_t stop_phase) {
+  if (stop_phase < 1 || stop_phase > 4) return fail(MLH_E_INVALID_ARG, "stop_phase must be 1..4");
+  double aU[2 * 512], aD[2 * 512], fl[1];
+  int ord[512];
+  if (!s || 2 * s->K + 1 > 512) return fail(MLH_E_INVALID_ARG, "bad stack");
+  return solve_impl(s, 1, &theta, aU, aD, ord, fl, stop_phase);
+}
+
+extern "C" mlh_status mlh_debug_get_work(mlh_stack s, int32_t which, int32_t index, double* out, int32_t* rows,
+                                         int32_t* cols) {
+  if (!s || s->dbg_Dg.empty()) return fail(MLH_E_INVALID_ARG, "no inspection solve has run");
+  const int I = s->I;
+  int r = 0, c = 0;
+  const cplx* p = nullptr;
+  if (which == 0 && index >= 0 && index < I) {
+    r = s->n[index];
+    c = s->n[index] + 1;
+    p = s->dbg_Dg[index];
+  } else if ((which == 1 || which == 2) && index >= 0 && index + 1 < I) {
+    r = which == 1 ? s->n[index] : s->n[index + 1];
+    c = which == 1 ? s->n[index + 1] : s->n[index];
+    p = which == 1 ? s->dbg_Up[index] : s->dbg_Dn[index];
+  } else if ((which == 3 || which == 4) && index >= 0 && index <= I) {
+    int m, cc, nc;
+    layer_dims(s, index, m, cc, nc);
+    r = m + cc;
+    c = which == 3 ? cc : nc;
+    p = which == 3 ? s->dbg_S[index] : s->dbg_RHS[index];
+  } else if (which == 5 && index >= 0 && index < I) {
+    r = s->n[index];
+    c = (index + 1 < I ? s->n[index + 1] : 0) + 1;
+    p = s->dbg_UG[index];
+  } else if (which == 6 && index >= 0 && index < I) {
+    r = s->n[index];
+    c = 1;
+    p = s->dbg_eta[index];
+  }
+  if (!p) return fail(MLH_E_INVALID_ARG, "mlh_debug_get_work: no such block");
+  if (rows) *rows = r;
+  if (cols) *cols = c;
+  if (out) {
+    HIP_TRY(hipSetDevice(s->ctx->device));
+    HIP_TRY(hipMemcpy(out, p, cbytes((size_t)r * c), hipMemcpyDeviceToHost));
+  }
+  return MLH_OK;
+}
+
+extern "C" mlh_status mlh_profile_step(mlh_stack s, double theta, mlh_profile* out) {
+  if (!s || !out) return fail(MLH_E_INVALID_ARG, "mlh_profile_step: NULL argument");
+  std::memset(out, 0, sizeof(*out));
+  HIP_TRY(hipSetDevice(s->ctx->device));
+  hipStream_t st = s->ctx->stream;
+  EvTimer T{st};
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  HIP_TRY(hipEventRecord(e0, st));
+  T.begin(&out->fill_self_ms);
+  launch_self(s->d_self, s->n_self, s->self_tiles, kAlpertA, st);
+  T.end();
+  T.begin(&out->fill_alpert_ms);
+  launch_alpert(s->d_alp, s->n_alp, s->alp_blocks, kAlpertA, st);
+  T.end();
+  T.begin(&out->fill_pairs_ms);
+  launch_fill(s->d_fill, s->n_fill, s->fill_tiles, st);
+  T.end();
+  HIP_TRY(hipGetLastError());
+  T.collect();
+  const int nK = 2 * s->K + 1;
+  std::vector<double> aU(2 * nK), aD(2 * nK);
+  std::vector<int> ord(nK);
+  double fl = 0;
+  mlh_status r = solve_impl(s, 1, &theta, aU.data(), aD.data(), ord.data(), &fl, 0, out);
+  HIP_TRY(hipEventRecord(e1, st));
+  HIP_TRY(hipEventSynchronize(e1));
+  float ms = 0;
+  hipEventElapsedTime(&ms, e0, e1);
+  out->total_ms = ms;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  return r;
+}

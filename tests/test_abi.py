@@ -1,0 +1,46 @@
+"""The C-ABI library loads and exports every symbol include/mlh.h declares
+(CPU only: no compute call is made)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mlh.h")
+LIB = os.path.join(ROOT, "paper_1410_5003_amd", "libmlh.so")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mlh_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("mlh_ctx_create", "mlh_stack_create", "mlh_solve", "mlh_stack_destroy",
+                     "mlh_last_error", "mlh_stack_info", "mlh_stack_refill"):
+        assert required in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libmlh.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libmlh.so not built")
+def test_binding_signatures_cover_the_header():
+    from paper_1410_5003_amd import _lib
+    assert set(_lib.SIGNATURES) == set(declared_functions())
+
+
+def test_no_oracle_import_in_product():
+    pkg = os.path.join(ROOT, "paper_1410_5003_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".cpp", ".hip", ".hpp", ".h")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in txt and "from oracle" not in txt, f
