@@ -49,8 +49,75 @@ def make_desc(name, I=None):
     return getattr(workloads, gen)(**kw)
 
 
-def flops_lu(n):
-    return 8.0 * n ** 3 / 3.0
+def algorithmic_work(desc):
+    """Real float64 flops (complex multiply-add = 8) of each kernel group in one
+    step, and the bytes the fill kernels must write (16 per complex entry)."""
+    I, P, K, Mw, Mud = desc.I, desc.P, desc.K, desc.M_w, desc.M_ud
+    n = [2 * f.n_nodes for f in desc.interfaces]
+    nK = 2 * K + 1
+    nb = 16
+    w = {}
+    gu = gp = 0.0
+    for i in range(I):
+        width = n[i] + (n[i + 1] if i + 1 < I else 0) + 1
+        for k in range(0, n[i], nb):
+            b = min(nb, n[i] - k)
+            rest = width - k - b
+            gu += 8.0 * n[i] * rest * b + 8.0 * b * b * rest
+            L = n[i] - k
+            gp += 4.0 * L * b * b + 4.0 * (L - b) * b * b
+    w["gje_update"] = gu
+    w["gje_panel"] = gp
+    w["sweep_gemm"] = sum(8.0 * n[i] * (n[i] + 1) * n[i - 1] for i in range(1, I))
+    w["schur"] = sum(8.0 * P * 2 * n[i] * n[i] for i in range(I)) + \
+        sum(8.0 * P * 2 * n[i] * n[i + 1] for i in range(I - 1))
+    qr = ap = 0.0
+    for j in range(I + 1):
+        end = j in (0, I)
+        m = 2 * Mw + (2 * Mud if end else 0)
+        c = P + (nK if end else 0)
+        M = m + c
+        ncol = n[0] if j == 0 else (n[I - 1] if j == I else n[j - 1] + n[j])
+        qr += 8.0 * M * c * c - 8.0 * c ** 3 / 3.0
+        ap += ncol * (16.0 * M * c - 4.0 * c * c)
+    w["ls_qr"] = qr
+    w["ls_apply"] = ap
+    w["backsub"] = sum(8.0 * n[i] * n[i + 1] for i in range(I - 1))
+    # fill: complex entries written (three copies for A and Z, two for C and Q)
+    ent_self = sum(3 * n[i] * n[i] for i in range(I))
+    ent_pair = sum(3 * 2 * n[i] * n[i + 1] for i in range(I - 1)) + sum(2 * n[i] * P for i in range(I)) + \
+        sum(2 * 2 * Mw * (n[j] if j < I else 0) + 2 * 2 * Mw * (n[j - 1] if j > 0 else 0) + 2 * 2 * Mw * P
+            for j in range(I + 1)) + 3 * 2 * Mud * (n[0] + n[I - 1]) + 2 * 2 * Mud * P
+    w["fill_self_bytes"] = 16.0 * ent_self
+    w["fill_pairs_bytes"] = 16.0 * ent_pair
+    return w
+
+
+GROUPS = [  # (name, profile time key, launch-count key, work key, bound)
+    ("gje_update_kernel", "gje_update_ms", "n_gje_update", "gje_update", "mfma"),
+    ("gje_panel_kernel", "gje_panel_ms", "n_gje_panel", "gje_panel", "alu"),
+    ("zgemm_kernel (sweep update)", "sweep_gemm_ms", "n_sweep_gemm", "sweep_gemm", "mfma"),
+    ("zgemm_kernel (Schur complements)", "schur_ms", None, "schur", "mfma"),
+    ("ls_qr_kernel", "ls_qr_ms", None, "ls_qr", "alu"),
+    ("ls_apply_kernel", "ls_apply_ms", None, "ls_apply", "alu"),
+    ("gemv_step_kernel", "backsub_ms", None, "backsub", "alu"),
+    ("self_kernel", "fill_self_ms", None, "fill_self_bytes", "hbm"),
+    ("fill_kernel", "fill_pairs_ms", None, "fill_pairs_bytes", "hbm"),
+]
+
+
+def roofline(desc, prof):
+    work = algorithmic_work(desc)
+    name, tkey, nkey, wkey, bound = max(GROUPS, key=lambda g: prof[g[1]])
+    t = prof[tkey] * 1e-3
+    launches = int(prof[nkey]) if nkey else 1
+    if bound == "hbm":
+        ach, peak, unit = work[wkey] / t / 1e9, HBM_PEAK_GBS, "GB/s"
+    else:
+        ach, peak, unit = work[wkey] / t / 1e12, FP64_PEAK_TFS, "TFLOP/s"
+    return {"bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak, "traffic": None,
+            "kernel": name, "launches_per_step": launches, "avg_launch_ms": prof[tkey] / launches,
+            "work_per_launch": work[wkey] / launches}
 
 
 def cpu_baseline(name, sample_I):
@@ -110,42 +177,7 @@ def main():
     profs = [st.profile_step(thetas[0]) for _ in range(3)]
     prof = {k: float(np.mean([p[k] for p in profs])) for k in profs[0]}
     print("profile " + json.dumps({k: round(v, 4) for k, v in prof.items()}), file=sys.stderr, flush=True)
-    n = 2 * desc.interfaces[0].n_nodes
-    groups = {
-        "lu_kernel": prof["lu_ms"], "lu_solve_kernel": prof["lu_solve_ms"],
-        "zgemm_kernel(sweep)": prof["sweep_gemm_ms"], "zgemm_kernel(schur)": prof["schur_ms"],
-        "ls_qr_kernel": prof["ls_qr_ms"], "ls_apply_kernel": prof["ls_apply_ms"],
-        "fill_kernel": prof["fill_pairs_ms"], "self_kernel": prof["fill_self_ms"],
-        "alpert_kernel": prof["fill_alpert_ms"], "backsub_kernel": prof["backsub_ms"],
-    }
-    dom = max(groups, key=groups.get)
-    I, P = desc.I, desc.P
-    if dom == "lu_kernel":
-        per_launch_ms = prof["lu_ms"] / max(1, prof["n_lu"])
-        achieved = flops_lu(n) / (per_launch_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s"}
-    elif dom == "lu_solve_kernel":
-        per_launch_ms = prof["lu_solve_ms"] / max(1, prof["n_lu_solve"])
-        achieved = 8.0 * n * n * (n + 1) / (per_launch_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s"}
-    elif dom == "zgemm_kernel(sweep)":
-        per_launch_ms = prof["sweep_gemm_ms"] / max(1, prof["n_sweep_gemm"])
-        achieved = 8.0 * n * (n + 1) * n / (per_launch_ms * 1e-3) / 1e12
-        roof = {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s"}
-    elif dom == "zgemm_kernel(schur)":
-        per_launch_ms = prof["schur_ms"]
-        fl = 8.0 * P * (I * (2 * n * n) + (I - 1) * 2 * n * n)
-        achieved = fl / (per_launch_ms * 1e-3) / 1e12
-        roof = {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s"}
-    else:
-        per_launch_ms = groups[dom]
-        achieved = 0.0
-        roof = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
-    roof["kernel"] = dom
-    roof["avg_launch_ms"] = per_launch_ms
-
+    roof = roofline(desc, prof)
     line = {
         "metric": METRIC, "value": solves_per_s, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",

@@ -164,7 +164,7 @@ mlh_status mlh_debug_solve_partial(mlh_stack s, double theta, int32_t stop_phase
 /* Inspection: copy a workspace block of the last mlh_debug_solve_partial:
  * which 0 [A'_ii | f~_i] (n_i x (n_i+1)), 1 A'_{i,i+1}, 2 A'_{i+1,i},
  * 3 stacked least-squares matrix of layer j ((m+c) x c), 4 its right-hand
- * side / solution ((m+c) x ncol), 5 [U_i | g_i], 6 eta_i.  Column-major,
+ * side / solution ((m+c) x ncol), 6 eta_i (densities, phase 4).  Column-major,
  * complex interleaved; out may be NULL to query the shape. */
 mlh_status mlh_debug_get_work(mlh_stack s, int32_t which, int32_t index, double* out, int32_t* rows,
                               int32_t* cols);
@@ -174,8 +174,8 @@ mlh_status mlh_debug_get_work(mlh_stack s, int32_t which, int32_t index, double*
 typedef struct {
   double fill_self_ms, fill_alpert_ms, fill_pairs_ms;
   double assemble_ms, rb_setup_ms, ls_qr_ms, ls_apply_ms, schur_ms;
-  double sweep_gemm_ms, lu_ms, lu_solve_ms, backsub_ms, bragg_ms;
-  int32_t n_sweep_gemm, n_lu, n_lu_solve;
+  double sweep_gemm_ms, gje_panel_ms, gje_update_ms, backsub_ms, bragg_ms;
+  int32_t n_sweep_gemm, n_gje_panel, n_gje_update;
   double total_ms;
 } mlh_profile;
 

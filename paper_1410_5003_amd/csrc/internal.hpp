@@ -87,9 +87,10 @@ struct GemmDesc {
   const cplx* B;
   const cplx* A2;
   const cplx* B2;
+  const cplx* C0;  // C = C0 + alpha (...); C0 = C updates in place, null starts from zero
   cplx* C;
   cplx alpha;
-  int m, n, k, lda, ldb, k2, lda2, ldb2, ldc;
+  int m, n, k, lda, ldb, k2, lda2, ldb2, ldc, ldc0;
   int tile_begin, tiles_m;
 };
 
@@ -103,23 +104,7 @@ struct LsDesc {
   int col_block_begin;
 };
 
-// block-tridiagonal sweep helpers
-struct LuDesc {
-  cplx* A;
-  int* piv;
-  int n, lda;
-  int* info;
-};
 
-struct LuSolveDesc {
-  const cplx* LU;
-  const int* piv;
-  const cplx* B1;   // first n1 RHS columns (ld ldb1)
-  const cplx* B2;   // next n2 RHS columns (ld ldb2)
-  cplx* X;          // n x (n1 + n2), ld n
-  int n, lda, n1, ldb1, n2, ldb2;
-  int col_begin;
-};
 
 // host-side launchers (kernels_*.hip)
 void launch_fill(const FillJob* d_jobs, int njobs, int total_tiles, hipStream_t st);
@@ -129,8 +114,6 @@ void launch_assemble(const AsmJob* d_jobs, int njobs, int64_t total_elems, hipSt
 void launch_gemm(const GemmDesc* d_desc, int ndesc, int total_tiles, hipStream_t st);
 void launch_ls_qr(const LsDesc* d_desc, int ndesc, hipStream_t st);
 void launch_ls_apply(const LsDesc* d_desc, int ndesc, int total_col_blocks, int max_rows, hipStream_t st);
-void launch_lu(const LuDesc* d_desc, int ndesc, hipStream_t st);
-void launch_lu_solve(const LuSolveDesc* d_desc, int ndesc, int total_cols, int max_n, hipStream_t st);
 void launch_hankel_eval(const double* x, double* out, int n, hipStream_t st);
 
 }  // namespace mlh
@@ -166,14 +149,43 @@ struct StackConsts {
   int N1, NI, Mw, Mud, P, K;
 };
 
-struct BacksubDesc {
-  const cplx* UG;  // n_i x (n_{i+1} + 1), ld n_i ; last column = G_i
-  cplx* eta;       // n_i
-  int n, nnext;
-};
 
 void launch_rb_setup(const AngleDesc* d_ang, int nang, StackConsts sc, hipStream_t st);
-void launch_backsub(const BacksubDesc* d_desc, int I, int nbatch, hipStream_t st);
 void launch_bragg(const AngleDesc* d_ang, int nang, StackConsts sc, hipStream_t st);
+
+}  // namespace mlh
+
+namespace mlh {
+
+// Blocked Gauss-Jordan solve with partial pivoting of W = [A | B] (n x ncol,
+// column-major, ld = n): after all panels W[:, n:] = A^{-1} B.
+constexpr int kGjeNb = 16;  // panel width
+constexpr int kGjeCols = 32;  // trailing columns per update workgroup
+constexpr int kGjeMaxN = 608; // largest block order whose panel fits in LDS (N_i <= 304)
+
+struct GjeDesc {
+  cplx* W;
+  cplx* P;    // scratch n x kGjeNb: panel multipliers of the current step
+  cplx* M1;   // scratch kGjeNb x kGjeNb: inverse of the pivot block
+  int* piv;   // scratch kGjeNb: pivot rows of the current step
+  int* info;  // set to (global column + 1) on an exactly zero pivot
+  int n, ncol;
+};
+
+// y = g - U1 x1 - U2 x2 (back substitution of the cyclic reduction, batched)
+struct GemvDesc {
+  const cplx* U1;  // n x m1, ld n
+  const cplx* U2;  // n x m2, ld n
+  const cplx* g;   // n
+  const cplx* x1;  // m1
+  const cplx* x2;  // m2
+  cplx* y;         // n
+  int n, m1, m2;
+};
+
+void gje_init();
+void launch_gje_panel(const GjeDesc* d, int nbatch, int k, int max_n, hipStream_t st);
+void launch_gje_update(const GjeDesc* d, int nbatch, int k, int max_ncol, hipStream_t st);
+void launch_gemv_step(const GemvDesc* d, int nbatch, int max_n, hipStream_t st);
 
 }  // namespace mlh

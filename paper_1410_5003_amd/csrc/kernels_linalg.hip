@@ -11,10 +11,6 @@
 //                   pseudo-inverse is never formed).
 //  ls_apply_kernel  Q^H and R^{-1} applied to the stacked right-hand side
 //                   [C; 0], one wavefront per column: X = Q^+ C.
-//  lu_kernel        LU with partial pivoting of one diagonal block of the
-//                   block-tridiagonal sweep (Sec. 3.3).
-//  lu_solve_kernel  forward/back substitution for [A'_{i,i+1} | f~_i].
-//  backsub_kernel   backward sweep eta_i = g_i - U_i eta_{i+1}.
 //  rb_setup_kernel  Rayleigh-Bloch rows W_U, W_D (eq. (59)) and the
 //                   incident-field right-hand side f (Sec. 2.2).
 //  bragg_kernel     a^U = -[X_1 eta_1]_a, a^D = -[X_{I+1} eta_I]_a (Sec. 3.3)
@@ -105,7 +101,7 @@ __global__ __launch_bounds__(256) void zgemm_kernel(const GemmDesc* __restrict__
     const int row = row0 + wm + (lane >> 4) + 4 * r;
     if (row < m) {
       cplx* p = G.C + (size_t)col * G.ldc + row;
-      const double2 c = ld2(p);
+      const double2 c = G.C0 ? ld2(G.C0 + (size_t)col * G.ldc0 + row) : make_double2(0.0, 0.0);
       const double xr = cr[r], xi = ci[r];
       st2(p, c.x + G.alpha.re * xr - G.alpha.im * xi, c.y + G.alpha.re * xi + G.alpha.im * xr);
     }
@@ -283,175 +279,6 @@ __global__ __launch_bounds__(256) void ls_apply_kernel(const LsDesc* __restrict_
 }
 
 // ---------------------------------------------------------------------------
-// LU with partial pivoting, one workgroup per matrix
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(1024) void lu_kernel(const LuDesc* __restrict__ descs) {
-  const LuDesc& D = descs[blockIdx.x];
-  const int n = D.n, lda = D.lda;
-  cplx* A = D.A;
-  __shared__ double bval[16];
-  __shared__ int bidx[16];
-  __shared__ int sp;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int k = 0; k < n; ++k) {
-    double best = -1.0;
-    int bi = k;
-    for (int r = k + tid; r < n; r += 1024) {
-      const double2 v = ld2(A + (size_t)k * lda + r);
-      const double a = v.x * v.x + v.y * v.y;
-      if (a > best) {
-        best = a;
-        bi = r;
-      }
-    }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-      const double ob = __shfl_xor(best, o, 64);
-      const int oi = __shfl_xor(bi, o, 64);
-      if (ob > best || (ob == best && oi < bi)) {
-        best = ob;
-        bi = oi;
-      }
-    }
-    if (lane == 0) {
-      bval[wave] = best;
-      bidx[wave] = bi;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      double b = bval[0];
-      int i = bidx[0];
-      for (int w = 1; w < (int)(blockDim.x >> 6); ++w)
-        if (bval[w] > b || (bval[w] == b && bidx[w] < i)) {
-          b = bval[w];
-          i = bidx[w];
-        }
-      sp = i;
-      D.piv[k] = i;
-      if (b <= 0.0 && D.info[0] == 0) D.info[0] = k + 1;
-    }
-    __syncthreads();
-    const int p = sp;
-    if (p != k)
-      for (int c = tid; c < n; c += 1024) {
-        const double2 x = ld2(A + (size_t)c * lda + k), y = ld2(A + (size_t)c * lda + p);
-        st2(A + (size_t)c * lda + k, y.x, y.y);
-        st2(A + (size_t)c * lda + p, x.x, x.y);
-      }
-    __syncthreads();
-    const double2 pv = ld2(A + (size_t)k * lda + k);
-    const double den = pv.x * pv.x + pv.y * pv.y;
-    if (den > 0.0) {
-      const double ir = pv.x / den, ii = -pv.y / den;
-      for (int r = k + 1 + tid; r < n; r += 1024) {
-        const double2 v = ld2(A + (size_t)k * lda + r);
-        st2(A + (size_t)k * lda + r, v.x * ir - v.y * ii, v.x * ii + v.y * ir);
-      }
-    }
-    __syncthreads();
-    const int nt = n - k - 1;
-    const int tot = nt * nt;
-    for (int e = tid; e < tot; e += 1024) {
-      const int r = k + 1 + e % nt, c = k + 1 + e / nt;
-      const double2 l = ld2(A + (size_t)k * lda + r), u = ld2(A + (size_t)c * lda + k);
-      const double2 a = ld2(A + (size_t)c * lda + r);
-      st2(A + (size_t)c * lda + r, a.x - (l.x * u.x - l.y * u.y), a.y - (l.x * u.y + l.y * u.x));
-    }
-    __syncthreads();
-  }
-}
-
-__global__ __launch_bounds__(64) void lu_solve_kernel(const LuSolveDesc* __restrict__ descs, int ndesc) {
-  int lo = 0, hi = ndesc - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (descs[mid].col_begin <= (int)blockIdx.x)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  const LuSolveDesc& D = descs[lo];
-  const int col = blockIdx.x - D.col_begin;
-  const int n = D.n, lda = D.lda, lane = threadIdx.x;
-  extern __shared__ double2 bsh[];
-  const cplx* src = col < D.n1 ? D.B1 + (size_t)col * D.ldb1 : D.B2 + (size_t)(col - D.n1) * D.ldb2;
-  for (int r = lane; r < n; r += 64) bsh[r] = ld2(src + r);
-  __syncthreads();
-  if (lane == 0)
-    for (int k = 0; k < n; ++k) {
-      const int p = D.piv[k];
-      if (p != k) {
-        const double2 t = bsh[k];
-        bsh[k] = bsh[p];
-        bsh[p] = t;
-      }
-    }
-  __syncthreads();
-  for (int k = 0; k < n; ++k) {
-    const double2 xk = bsh[k];
-    const cplx* lc = D.LU + (size_t)k * lda;
-    for (int r = k + 1 + lane; r < n; r += 64) {
-      const double2 l = ld2(lc + r);
-      double2 b = bsh[r];
-      b.x -= l.x * xk.x - l.y * xk.y;
-      b.y -= l.x * xk.y + l.y * xk.x;
-      bsh[r] = b;
-    }
-    __syncthreads();
-  }
-  for (int k = n - 1; k >= 0; --k) {
-    const cplx* uc = D.LU + (size_t)k * lda;
-    const double2 u = ld2(uc + k);
-    const double2 bk = bsh[k];
-    const double den = u.x * u.x + u.y * u.y;
-    const double xr = (bk.x * u.x + bk.y * u.y) / den, xi = (bk.y * u.x - bk.x * u.y) / den;
-    for (int r = lane; r < k; r += 64) {
-      const double2 a = ld2(uc + r);
-      double2 b = bsh[r];
-      b.x -= a.x * xr - a.y * xi;
-      b.y -= a.x * xi + a.y * xr;
-      bsh[r] = b;
-    }
-    __syncthreads();
-    if (lane == 0) bsh[k] = make_double2(xr, xi);
-    __syncthreads();
-  }
-  cplx* dst = D.X + (size_t)col * n;
-  for (int r = lane; r < n; r += 64) st2(dst + r, bsh[r].x, bsh[r].y);
-}
-
-// ---------------------------------------------------------------------------
-// backward sweep, one workgroup per batch entry: eta_i = g_i - U_i eta_{i+1}
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void backsub_kernel(const BacksubDesc* __restrict__ descs, int I) {
-  const BacksubDesc* D = descs + (size_t)blockIdx.x * I;
-  const int tid = threadIdx.x;
-  {
-    const BacksubDesc& L = D[I - 1];
-    for (int r = tid; r < L.n; r += 256) {
-      const double2 g = ld2(L.UG + (size_t)L.nnext * L.n + r);
-      st2(L.eta + r, g.x, g.y);
-    }
-  }
-  __syncthreads();
-  for (int i = I - 2; i >= 0; --i) {
-    const BacksubDesc& L = D[i];
-    const cplx* en = D[i + 1].eta;
-    for (int r = tid; r < L.n; r += 256) {
-      double2 acc = ld2(L.UG + (size_t)L.nnext * L.n + r);
-      for (int j = 0; j < L.nnext; ++j) {
-        const double2 u = ld2(L.UG + (size_t)j * L.n + r);
-        const double2 e = ld2(en + j);
-        acc.x -= u.x * e.x - u.y * e.y;
-        acc.y -= u.x * e.y + u.y * e.x;
-      }
-      st2(L.eta + r, acc.x, acc.y);
-    }
-    __syncthreads();
-  }
-}
-
-// ---------------------------------------------------------------------------
 // Rayleigh-Bloch orders, W blocks and the incident right-hand side
 // ---------------------------------------------------------------------------
 __device__ inline int rb_n0(double kappa0, double d) { return (int)floor(-kappa0 * d / (2.0 * kPi) + 0.5); }
@@ -542,19 +369,8 @@ void launch_ls_apply(const LsDesc* d_desc, int ndesc, int total_col_blocks, int 
     hipLaunchKernelGGL(ls_apply_kernel, dim3(total_col_blocks), dim3(256), (size_t)5 * max_rows * sizeof(double2),
                        st, d_desc, ndesc);
 }
-void launch_lu(const LuDesc* d_desc, int ndesc, hipStream_t st) {
-  if (ndesc > 0) hipLaunchKernelGGL(lu_kernel, dim3(ndesc), dim3(1024), 0, st, d_desc);
-}
-void launch_lu_solve(const LuSolveDesc* d_desc, int ndesc, int total_cols, int max_n, hipStream_t st) {
-  if (total_cols > 0)
-    hipLaunchKernelGGL(lu_solve_kernel, dim3(total_cols), dim3(64), (size_t)max_n * sizeof(double2), st, d_desc,
-                       ndesc);
-}
 void launch_rb_setup(const AngleDesc* d_ang, int nang, StackConsts sc, hipStream_t st) {
   if (nang > 0) hipLaunchKernelGGL(rb_setup_kernel, dim3(nang), dim3(256), 0, st, d_ang, sc);
-}
-void launch_backsub(const BacksubDesc* d_desc, int I, int nbatch, hipStream_t st) {
-  if (nbatch > 0) hipLaunchKernelGGL(backsub_kernel, dim3(nbatch), dim3(256), 0, st, d_desc, I);
 }
 void launch_bragg(const AngleDesc* d_ang, int nang, StackConsts sc, hipStream_t st) {
   if (nang > 0) hipLaunchKernelGGL(bragg_kernel, dim3(nang), dim3(64), 0, st, d_ang, sc);

@@ -56,6 +56,7 @@ extern "C" mlh_status mlh_ctx_create(int32_t device, void* hip_stream, mlh_ctx* 
   HIP_TRY(hipGetDeviceCount(&ndev));
   if (device < 0 || device >= ndev) return fail(MLH_E_INVALID_ARG, "mlh_ctx_create: no such device");
   HIP_TRY(hipSetDevice(device));
+  gje_init();
   *out = new mlh_ctx_s{device, (hipStream_t)hip_stream};
   return MLH_OK;
 }
@@ -232,7 +233,7 @@ struct mlh_stack_s {
   int n_alp = 0, alp_blocks = 0;
 
   // workspace views of the first angle of the last inspection solve
-  std::vector<cplx*> dbg_Dg, dbg_Up, dbg_Dn, dbg_S, dbg_RHS, dbg_UG, dbg_eta;
+  std::vector<cplx*> dbg_R, dbg_S, dbg_RHS, dbg_eta;
 
   // solve workspace (reused across calls with the same batch size)
   char* wmem = nullptr;
@@ -254,6 +255,7 @@ static mlh_status validate(const mlh_stack_desc* D) {
   if (D->M_ud < 2 * D->K + 1) return fail(MLH_E_INVALID_ARG, "M_ud must be >= 2K+1 (aliasing of Rayleigh-Bloch orders)");
   if (D->ls_mu < 0 || !std::isfinite(D->ls_mu)) return fail(MLH_E_INVALID_ARG, "ls_mu must be >= 0");
   const int nmin = 2 * (kAlpertA + 8) + 1;
+  const int nmax = kGjeMaxN / 2;
   for (int i = 0; i < D->I; ++i) {
     const mlh_interface& f = D->iface[i];
     if (f.kind == MLH_IFACE_POLYGON)
@@ -263,6 +265,8 @@ static mlh_status validate(const mlh_stack_desc* D) {
       return fail(MLH_E_INVALID_ARG, "Fourier coefficients missing");
     if (f.n_nodes < nmin)
       return fail(MLH_E_INVALID_ARG, "each interface needs at least " + std::to_string(nmin) + " nodes");
+    if (f.n_nodes > nmax)
+      return fail(MLH_E_UNSUPPORTED, "at most " + std::to_string(nmax) + " nodes per interface are supported");
     if (!std::isfinite(f.y0)) return fail(MLH_E_INVALID_ARG, "non-finite y0");
   }
   return MLH_OK;
@@ -835,6 +839,11 @@ struct EvTimer {
 };
 }  // namespace
 
+static int row_width(const mlh_stack_s* s, int i) {
+  // columns of the level-0 row block [A'_ii | A'_{i,i-1} | A'_{i,i+1} | f~_i]
+  return s->n[i] + (i > 0 ? s->n[i - 1] : 0) + (i + 1 < s->I ? s->n[i + 1] : 0) + 1;
+}
+
 static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta, double* aU, double* aD,
                              int32_t* orders, double* flux_err, int stop_phase, mlh_profile* prof = nullptr) {
   if (!s) return fail(MLH_E_INVALID_ARG, "NULL stack");
@@ -845,37 +854,47 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
   hipStream_t st = s->ctx->stream;
   const int I = s->I, P = s->P, nK = s->nK;
   const std::vector<int>& n = s->n;
-  // ---- workspace size for one angle
-  size_t per = 0;
-  Arena ar;
+  int maxn = 0;
+  for (int i = 0; i < I; ++i) maxn = std::max(maxn, n[i]);
+  std::vector<int> wmax(I), nL0(I), nU0(I);
+  for (int i = 0; i < I; ++i) {
+    wmax[i] = n[i] + 2 * maxn + 1;
+    nL0[i] = i > 0 ? n[i - 1] : 0;
+    nU0[i] = i + 1 < I ? n[i + 1] : 0;
+  }
+  // ---- workspace of one angle: two row-block buffers per interface (the
+  //      reduction reads one and writes the other), least-squares systems,
+  //      eta, Gauss-Jordan scratch per interface, outputs
   auto plan = [&](Arena& A, std::vector<size_t>* offs) {
     auto R = [&](size_t bytes) {
       const size_t o = A.reserve(bytes);
       if (offs) offs->push_back(o);
     };
-    for (int i = 0; i < I; ++i) R(cbytes((size_t)n[i] * (n[i] + 1)));                    // Dg
-    for (int i = 0; i + 1 < I; ++i) R(cbytes((size_t)n[i] * n[i + 1]));                  // Up
-    for (int i = 0; i + 1 < I; ++i) R(cbytes((size_t)n[i + 1] * n[i]));                  // Dn
-    for (int i = 0; i < I; ++i) R(cbytes((size_t)n[i] * ((i + 1 < I ? n[i + 1] : 0) + 1)));  // UG
+    for (int i = 0; i < I; ++i) R(cbytes((size_t)n[i] * wmax[i]));
+    for (int i = 0; i < I; ++i) R(cbytes((size_t)n[i] * wmax[i]));
     for (int j = 0; j <= I; ++j) {
       int m, c, nc;
       layer_dims(s, j, m, c, nc);
-      R(cbytes((size_t)(m + c) * c));   // S
-      R(cbytes((size_t)c));             // tau
-      R(cbytes((size_t)(m + c) * nc));  // RHS / X
+      R(cbytes((size_t)(m + c) * c));
+      R(cbytes((size_t)c));
+      R(cbytes((size_t)(m + c) * nc));
     }
-    for (int i = 0; i < I; ++i) R(sizeof(int) * n[i]);  // pivots
-    for (int i = 0; i < I; ++i) R(cbytes(n[i]));        // eta
-    R(cbytes(2 * nK));                                  // aU, aD
-    R(sizeof(double) * 2);                              // flux
-    R(sizeof(int) * nK);                                // orders
+    for (int i = 0; i < I; ++i) R(cbytes(n[i]));
+    for (int i = 0; i < I; ++i) {
+      R(cbytes((size_t)n[i] * kGjeNb));
+      R(cbytes((size_t)kGjeNb * kGjeNb));
+      R(sizeof(int) * kGjeNb);
+    }
+    R(cbytes(2 * nK));
+    R(sizeof(double) * 2);
+    R(sizeof(int) * nK);
   };
+  Arena ar;
   plan(ar, nullptr);
-  per = (ar.off + 255) & ~size_t(255);
-  // descriptor space (generous upper bound per angle)
-  const size_t desc_per = sizeof(AsmJob) * (size_t)(10 * (I + 2)) + sizeof(GemmDesc) * (size_t)(6 * I + 4) +
-                          sizeof(LsDesc) * (size_t)(2 * (I + 1)) + sizeof(LuDesc) * I + sizeof(LuSolveDesc) * I +
-                          sizeof(BacksubDesc) * I + sizeof(AngleDesc) + 4096;
+  const size_t per = (ar.off + 255) & ~size_t(255);
+  const size_t desc_per = sizeof(AsmJob) * (size_t)(10 * (I + 2)) + sizeof(GemmDesc) * (size_t)(8 * I + 8) +
+                          sizeof(LsDesc) * (size_t)(I + 1) + sizeof(GjeDesc) * (size_t)(I + 1) +
+                          sizeof(GemvDesc) * (size_t)(I + 1) + sizeof(AngleDesc) + 256 * (size_t)(3 * 40 + 16);
   size_t freeb = 0, totb = 0;
   HIP_TRY(hipMemGetInfo(&freeb, &totb));
   int B = n_angles;
@@ -889,20 +908,17 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
     HIP_TRY(hipMalloc((void**)&s->wmem, need));
     s->wbytes = need;
   }
+  std::vector<size_t> offs;
+  {
+    Arena A;
+    plan(A, &offs);
+  }
   std::vector<double> h_flux(n_angles);
   for (int a0 = 0; a0 < n_angles; a0 += B) {
     const int nb = std::min(B, n_angles - a0);
-    // ---- carve the workspace
-    std::vector<std::vector<size_t>> offs(nb);
-    std::vector<char*> wb(nb);
-    for (int b = 0; b < nb; ++b) {
-      Arena A;
-      plan(A, &offs[b]);
-      wb[b] = s->wmem + (size_t)b * per;
-    }
     char* dbase = s->wmem + (size_t)B * per;
     struct View {
-      std::vector<cplx*> Dg, Up, Dn, UG, S, tau, RHS, eta;
+      std::vector<cplx*> W[2], S, tau, RHS, eta, Pg, M1;
       std::vector<int*> piv;
       cplx *aU, *aD;
       double* flux;
@@ -910,30 +926,38 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
     };
     std::vector<View> V(nb);
     for (int b = 0; b < nb; ++b) {
+      char* wb = s->wmem + (size_t)b * per;
       size_t k = 0;
-      auto C = [&]() { return reinterpret_cast<cplx*>(wb[b] + offs[b][k++]); };
+      auto C = [&]() { return reinterpret_cast<cplx*>(wb + offs[k++]); };
       View& v = V[b];
-      for (int i = 0; i < I; ++i) v.Dg.push_back(C());
-      for (int i = 0; i + 1 < I; ++i) v.Up.push_back(C());
-      for (int i = 0; i + 1 < I; ++i) v.Dn.push_back(C());
-      for (int i = 0; i < I; ++i) v.UG.push_back(C());
+      for (int i = 0; i < I; ++i) v.W[0].push_back(C());
+      for (int i = 0; i < I; ++i) v.W[1].push_back(C());
       for (int j = 0; j <= I; ++j) {
         v.S.push_back(C());
         v.tau.push_back(C());
         v.RHS.push_back(C());
       }
-      for (int i = 0; i < I; ++i) v.piv.push_back(reinterpret_cast<int*>(wb[b] + offs[b][k++]));
       for (int i = 0; i < I; ++i) v.eta.push_back(C());
+      for (int i = 0; i < I; ++i) {
+        v.Pg.push_back(C());
+        v.M1.push_back(C());
+        v.piv.push_back(reinterpret_cast<int*>(wb + offs[k++]));
+      }
       v.aU = C();
       v.aD = v.aU + nK;
-      v.flux = reinterpret_cast<double*>(wb[b] + offs[b][k++]);
-      v.orders = reinterpret_cast<int*>(wb[b] + offs[b][k++]);
+      v.flux = reinterpret_cast<double*>(wb + offs[k++]);
+      v.orders = reinterpret_cast<int*>(wb + offs[k++]);
     }
+    auto Dblk = [&](int b, int i) { return V[b].W[0][i]; };
+    auto Lblk = [&](int b, int i) { return V[b].W[0][i] + (size_t)n[i] * n[i]; };
+    auto Ublk = [&](int b, int i) { return V[b].W[0][i] + (size_t)n[i] * (n[i] + nL0[i]); };
+    auto Fcol = [&](int b, int i) { return V[b].W[0][i] + (size_t)n[i] * (n[i] + nL0[i] + nU0[i]); };
     // ---- descriptors
     std::vector<AsmJob> asmj;
     int64_t elems = 0;
     auto asm_add = [&](cplx* dst, int ldd, int rows, int cols, int np, const cplx* const* src, int lds,
                        const cplx* coef) {
+      if (rows <= 0 || cols <= 0) return;
       AsmJob J{};
       J.dst = dst;
       J.ldd = ldd;
@@ -945,64 +969,63 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
         J.src[p] = src[p];
         J.coef[p] = coef[p];
       }
-      if (rows <= 0 || cols <= 0) return;
       J.elem_begin = elems;
       elems += (int64_t)rows * cols;
       asmj.push_back(J);
     };
-    std::vector<GemmDesc> gs;  // Schur GEMMs
-    int gtiles = 0;
-    auto gemm_add2 = [&](std::vector<GemmDesc>& vec, int& tiles, const cplx* A, int lda, const cplx* Bm, int ldb,
-                         cplx* Cm, int ldc, int m, int nn, int k, const cplx* A2, int lda2, const cplx* B2, int ldb2,
-                         int k2) {
+    // C = C0 + alpha (A B + A2 B2); m x nn output, inner sizes k and k2
+    auto gemm_add = [&](std::vector<GemmDesc>& vec, int& tiles, cplx* Cm, int ldc, const cplx* C0, int ldc0, int m,
+                        int nn, const cplx* A, int lda, const cplx* Bm, int ldb, int k, const cplx* A2, int lda2,
+                        const cplx* B2, int ldb2, int k2) {
+      if (m <= 0 || nn <= 0) return;
       GemmDesc G{};
       G.A = A;
       G.B = Bm;
-      G.A2 = A2;
-      G.B2 = B2;
-      G.lda2 = lda2;
-      G.ldb2 = ldb2;
-      G.k2 = k2;
-      G.C = Cm;
-      G.alpha = cx(-1.0, 0.0);
-      G.m = m;
-      G.n = nn;
       G.k = k;
       G.lda = lda;
       G.ldb = ldb;
+      G.A2 = A2;
+      G.B2 = B2;
+      G.k2 = k2;
+      G.lda2 = lda2;
+      G.ldb2 = ldb2;
+      G.C = Cm;
       G.ldc = ldc;
+      G.C0 = C0;
+      G.ldc0 = ldc0;
+      G.alpha = cx(-1.0, 0.0);
+      G.m = m;
+      G.n = nn;
       G.tiles_m = (m + 31) / 32;
       G.tile_begin = tiles;
       tiles += G.tiles_m * ((nn + 31) / 32);
       vec.push_back(G);
     };
-    auto gemm_add = [&](std::vector<GemmDesc>& vec, int& tiles, const cplx* A, int lda, const cplx* Bm, int ldb,
-                        cplx* Cm, int ldc, int m, int nn, int k) {
-      gemm_add2(vec, tiles, A, lda, Bm, ldb, Cm, ldc, m, nn, k, nullptr, lda, nullptr, ldb, 0);
-    };
+    std::vector<GemmDesc> gs;
+    int gtiles = 0;
     std::vector<LsDesc> ls;
     int colblocks = 0, maxrows = 0;
     std::vector<AngleDesc> angs(nb);
+    const cplx one = cx(1, 0);
     for (int b = 0; b < nb; ++b) {
       View& v = V[b];
       const double th = theta[a0 + b];
-      const double ph = s->d * s->k[0] * std::cos(th);  // alpha = e^{i ph}
+      const double ph = s->d * s->k[0] * std::cos(th);  // alpha = e^{i ph}, eq. (2)
       const cplx a_m1 = cpow_alpha(ph, -1), a_p1 = cpow_alpha(ph, 1), a_m2 = cpow_alpha(ph, -2);
-      const cplx one = cx(1, 0), mone = cx(-1, 0);
       const cplx c3[3] = {a_m1, one, a_p1};
       const cplx cC[2] = {a_m2, cx(-a_p1.re, -a_p1.im)};
-      const cplx cQ[2] = {a_m1, mone};
+      const cplx cQ[2] = {a_m1, cx(-1, 0)};
       for (int i = 0; i < I; ++i) {
         const size_t pe = (size_t)n[i] * n[i];
         const cplx* src[3] = {s->A_self[i], s->A_self[i] + pe, s->A_self[i] + 2 * pe};
-        asm_add(v.Dg[i], n[i], n[i], n[i], 3, src, n[i], c3);
-        if (i > 0) asm_add(v.Dg[i] + pe, n[i], n[i], 1, 0, src, n[i], c3);  // f~_i = 0
+        asm_add(Dblk(b, i), n[i], n[i], n[i], 3, src, n[i], c3);
+        if (i > 0) asm_add(Fcol(b, i), n[i], n[i], 1, 0, src, n[i], c3);  // f_i = 0 below Gamma_1
         if (i + 1 < I) {
           const size_t pu = (size_t)n[i] * n[i + 1];
           const cplx* su[3] = {s->A_up[i], s->A_up[i] + pu, s->A_up[i] + 2 * pu};
-          asm_add(v.Up[i], n[i], n[i], n[i + 1], 3, su, n[i], c3);
+          asm_add(Ublk(b, i), n[i], n[i], n[i + 1], 3, su, n[i], c3);
           const cplx* sd[3] = {s->A_dn[i], s->A_dn[i] + pu, s->A_dn[i] + 2 * pu};
-          asm_add(v.Dn[i], n[i + 1], n[i + 1], n[i], 3, sd, n[i + 1], c3);
+          asm_add(Lblk(b, i + 1), n[i + 1], n[i + 1], n[i], 3, sd, n[i + 1], c3);
         }
       }
       for (int j = 0; j <= I; ++j) {
@@ -1017,8 +1040,7 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
         if (j == 0 || j == I) {
           const cplx* vv[1] = {j == 0 ? s->V_U : s->V_D};
           asm_add(v.S[j] + mw2, M, mud2, P, 1, vv, mud2, &one);
-          asm_add(v.S[j] + (size_t)P * M, M, mw2, nK, 0, vv, mud2, &one);  // zero block
-          // RHS: [C; Z; 0]
+          asm_add(v.S[j] + (size_t)P * M, M, mw2, nK, 0, vv, mud2, &one);
           const int ci = j == 0 ? 0 : I - 1;
           const size_t ce = (size_t)mw2 * n[ci];
           const cplx* cs = j == 0 ? s->C_own[0] : s->C_above[I];
@@ -1049,21 +1071,23 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
         colblocks += (nc + 3) / 4;
         ls.push_back(L);
       }
-      // Schur complements eq. (74)-(78)
+      // Schur complements eq. (74)-(78): A' = A - B X, in place; each
+      // descriptor owns its output block
       for (int i = 0; i < I; ++i) {
         int m0, c0, nc0, m1, c1, nc1;
         layer_dims(s, i, m0, c0, nc0);
         layer_dims(s, i + 1, m1, c1, nc1);
         const int Ma = m0 + c0, Mb = m1 + c1;
         const cplx* Xa = (i == 0) ? v.RHS[0] : v.RHS[i] + (size_t)n[i - 1] * Ma;
-        const cplx* Xb = v.RHS[i + 1];  // columns acting on eta_i come first
-        gemm_add2(gs, gtiles, s->B_own[i], n[i], Xa, Ma, v.Dg[i], n[i], n[i], n[i], P, s->B_below[i], n[i], Xb,
-                  Mb, P);
-        if (i + 1 < I) {
-          gemm_add(gs, gtiles, s->B_below[i], n[i], v.RHS[i + 1] + (size_t)n[i] * Mb, Mb, v.Up[i], n[i], n[i],
-                   n[i + 1], P);
-          gemm_add(gs, gtiles, s->B_own[i + 1], n[i + 1], v.RHS[i + 1], Mb, v.Dn[i], n[i + 1], n[i + 1], n[i], P);
-        }
+        const cplx* Xb = v.RHS[i + 1];
+        gemm_add(gs, gtiles, Dblk(b, i), n[i], Dblk(b, i), n[i], n[i], n[i], s->B_own[i], n[i], Xa, Ma, P,
+                 s->B_below[i], n[i], Xb, Mb, P);
+        if (i + 1 < I)
+          gemm_add(gs, gtiles, Ublk(b, i), n[i], Ublk(b, i), n[i], n[i], n[i + 1], s->B_below[i], n[i],
+                   v.RHS[i + 1] + (size_t)n[i] * Mb, Mb, P, nullptr, 1, nullptr, 1, 0);
+        if (i > 0)
+          gemm_add(gs, gtiles, Lblk(b, i), n[i], Lblk(b, i), n[i], n[i], n[i - 1], s->B_own[i], n[i], v.RHS[i], Ma, P,
+                   nullptr, 1, nullptr, 1, 0);
       }
       AngleDesc& A = angs[b];
       A.theta = th;
@@ -1074,7 +1098,7 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
       A.ldS0 = m0 + c0;
       A.SI = v.S[I];
       A.ldSI = mI + cI;
-      A.F0 = v.Dg[0] + (size_t)n[0] * n[0];
+      A.F0 = Fcol(b, 0);
       A.X0 = v.RHS[0];
       A.ldX0 = m0 + c0;
       A.XI = v.RHS[I];
@@ -1086,58 +1110,146 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
       A.orders = v.orders;
       A.flux = v.flux;
     }
-    // sweep descriptors per step
-    std::vector<std::vector<GemmDesc>> sg(I);
-    std::vector<int> sg_tiles(I, 0);
-    std::vector<std::vector<LuDesc>> lu(I);
-    std::vector<std::vector<LuSolveDesc>> lus(I);
-    std::vector<int> lus_cols(I, 0);
-    std::vector<BacksubDesc> bs;
-    int maxn = 0;
-    for (int i = 0; i < I; ++i) maxn = std::max(maxn, n[i]);
-    for (int b = 0; b < nb; ++b) {
-      View& v = V[b];
-      for (int i = 0; i < I; ++i) {
-        const int nn = (i + 1 < I) ? n[i + 1] : 0;
-        if (i > 0) gemm_add(sg[i], sg_tiles[i], v.Dn[i - 1], n[i], v.UG[i - 1], n[i - 1], v.Dg[i], n[i], n[i], n[i] + 1, n[i - 1]);
-        LuDesc L{};
-        L.A = v.Dg[i];
-        L.piv = v.piv[i];
-        L.n = n[i];
-        L.lda = n[i];
-        L.info = nullptr;
-        lu[i].push_back(L);
-        LuSolveDesc S{};
-        S.LU = v.Dg[i];
-        S.piv = v.piv[i];
-        S.n = n[i];
-        S.lda = n[i];
-        if (nn > 0) {
-          S.B1 = v.Up[i];
-          S.ldb1 = n[i];
-          S.n1 = nn;
-          S.B2 = v.Dg[i] + (size_t)n[i] * n[i];
-          S.ldb2 = n[i];
-          S.n2 = 1;
-        } else {
-          S.B1 = v.Dg[i] + (size_t)n[i] * n[i];
-          S.ldb1 = n[i];
-          S.n1 = 1;
-          S.B2 = nullptr;
-          S.ldb2 = n[i];
-          S.n2 = 0;
+    // ---- block-tridiagonal solve by cyclic reduction (the paper's block LU,
+    //      Sec. 3.3, reordered so that every level eliminates half of the
+    //      remaining blocks at once).  Block j holds [D_j | L_j | U_j | f_j]
+    //      with L_j / U_j its couplings to the left / right neighbour in the
+    //      active set.  Eliminating e: [XL | XU | xf] = D_e^{-1} [L_e | U_e | f_e];
+    //      a kept neighbour j then becomes
+    //        D_j - L_j XU_{e_l} - U_j XL_{e_r},  f_j - L_j xf_{e_l} - U_j xf_{e_r},
+    //        L_j' = -L_j XL_{e_l},  U_j' = -U_j XU_{e_r}.
+    struct Level {
+      std::vector<GjeDesc> gje;
+      int maxn = 0, maxcol = 0;
+      std::vector<GemmDesc> upd;
+      int upd_tiles = 0;
+      std::vector<GemvDesc> back;
+      int backn = 0;
+    };
+    std::vector<Level> levels;
+    std::vector<int> cur(I, 0), nLc(nL0), nUc(nU0);
+    std::vector<int> S_act(I);
+    for (int i = 0; i < I; ++i) S_act[i] = i;
+    auto Wp = [&](int b, int i, int which) { return V[b].W[which][i]; };
+    while (true) {
+      Level lv;
+      const int m = (int)S_act.size();
+      if (m == 1) {
+        const int j = S_act[0];
+        for (int b = 0; b < nb; ++b) {
+          GjeDesc G{};
+          G.W = Wp(b, j, cur[j]);
+          G.P = V[b].Pg[j];
+          G.M1 = V[b].M1[j];
+          G.piv = V[b].piv[j];
+          G.n = n[j];
+          G.ncol = n[j] + nLc[j] + nUc[j] + 1;
+          lv.gje.push_back(G);
+          GemvDesc Gv{};
+          Gv.g = G.W + (size_t)n[j] * (n[j] + nLc[j] + nUc[j]);
+          Gv.y = V[b].eta[j];
+          Gv.n = n[j];
+          lv.back.push_back(Gv);
         }
-        S.X = v.UG[i];
-        S.col_begin = lus_cols[i];
-        lus_cols[i] += S.n1 + S.n2;
-        lus[i].push_back(S);
-        BacksubDesc Bd{};
-        Bd.UG = v.UG[i];
-        Bd.eta = v.eta[i];
-        Bd.n = n[i];
-        Bd.nnext = nn;
-        bs.push_back(Bd);
+        lv.maxn = n[j];
+        lv.maxcol = n[j] + nLc[j] + nUc[j] + 1;
+        lv.backn = n[j];
+        levels.push_back(lv);
+        break;
       }
+      // eliminate odd positions
+      for (int p = 1; p < m; p += 2) {
+        const int e = S_act[p], left = S_act[p - 1], right = (p + 1 < m) ? S_act[p + 1] : -1;
+        for (int b = 0; b < nb; ++b) {
+          GjeDesc G{};
+          G.W = Wp(b, e, cur[e]);
+          G.P = V[b].Pg[e];
+          G.M1 = V[b].M1[e];
+          G.piv = V[b].piv[e];
+          G.n = n[e];
+          G.ncol = n[e] + nLc[e] + nUc[e] + 1;
+          lv.gje.push_back(G);
+          const cplx* X = G.W + (size_t)n[e] * n[e];
+          GemvDesc Gv{};
+          Gv.U1 = X;
+          Gv.m1 = nLc[e];
+          Gv.x1 = V[b].eta[left];
+          Gv.U2 = X + (size_t)n[e] * nLc[e];
+          Gv.m2 = right >= 0 ? nUc[e] : 0;
+          Gv.x2 = right >= 0 ? V[b].eta[right] : nullptr;
+          Gv.g = X + (size_t)n[e] * (nLc[e] + nUc[e]);
+          Gv.y = V[b].eta[e];
+          Gv.n = n[e];
+          lv.back.push_back(Gv);
+        }
+        lv.maxn = std::max(lv.maxn, n[e]);
+        lv.maxcol = std::max(lv.maxcol, n[e] + nLc[e] + nUc[e] + 1);
+        lv.backn = std::max(lv.backn, n[e]);
+      }
+      // update the kept blocks
+      std::vector<int> newL(I), newU(I);
+      for (int p = 0; p < m; p += 2) {
+        const int j = S_act[p];
+        const int el = p >= 1 ? S_act[p - 1] : -1, er = p + 1 < m ? S_act[p + 1] : -1;
+        const int ll = p >= 2 ? S_act[p - 2] : -1, rr = p + 2 < m ? S_act[p + 2] : -1;
+        const int nLn = ll >= 0 ? n[ll] : 0, nUn = rr >= 0 ? n[rr] : 0;
+        newL[j] = nLn;
+        newU[j] = nUn;
+        const int nj = n[j];
+        for (int b = 0; b < nb; ++b) {
+          cplx* Wc = Wp(b, j, cur[j]);
+          cplx* Wn = Wp(b, j, cur[j] ^ 1);
+          const cplx* Lj = Wc + (size_t)nj * nj;
+          const cplx* Uj = Wc + (size_t)nj * (nj + nLc[j]);
+          const cplx* fj = Wc + (size_t)nj * (nj + nLc[j] + nUc[j]);
+          const cplx *XLl = nullptr, *XUl = nullptr, *xfl = nullptr, *XLr = nullptr, *XUr = nullptr, *xfr = nullptr;
+          int nel = 0, ner = 0;
+          if (el >= 0) {
+            nel = n[el];
+            const cplx* X = Wp(b, el, cur[el]) + (size_t)nel * nel;
+            XLl = X;
+            XUl = X + (size_t)nel * nLc[el];
+            xfl = X + (size_t)nel * (nLc[el] + nUc[el]);
+          }
+          if (er >= 0) {
+            ner = n[er];
+            const cplx* X = Wp(b, er, cur[er]) + (size_t)ner * ner;
+            XLr = X;
+            XUr = X + (size_t)ner * nLc[er];
+            xfr = X + (size_t)ner * (nLc[er] + nUc[er]);
+          }
+          // D and f (one or two products each)
+          if (el >= 0 && er >= 0) {
+            gemm_add(lv.upd, lv.upd_tiles, Wn, nj, Wc, nj, nj, nj, Lj, nj, XUl, nel, nel, Uj, nj, XLr, ner, ner);
+            gemm_add(lv.upd, lv.upd_tiles, Wn + (size_t)nj * (nj + nLn + nUn), nj, fj, nj, nj, 1, Lj, nj, xfl, nel,
+                     nel, Uj, nj, xfr, ner, ner);
+          } else if (el >= 0) {
+            gemm_add(lv.upd, lv.upd_tiles, Wn, nj, Wc, nj, nj, nj, Lj, nj, XUl, nel, nel, nullptr, 1, nullptr, 1, 0);
+            gemm_add(lv.upd, lv.upd_tiles, Wn + (size_t)nj * (nj + nLn + nUn), nj, fj, nj, nj, 1, Lj, nj, xfl, nel,
+                     nel, nullptr, 1, nullptr, 1, 0);
+          } else {
+            gemm_add(lv.upd, lv.upd_tiles, Wn, nj, Wc, nj, nj, nj, Uj, nj, XLr, ner, ner, nullptr, 1, nullptr, 1, 0);
+            gemm_add(lv.upd, lv.upd_tiles, Wn + (size_t)nj * (nj + nLn + nUn), nj, fj, nj, nj, 1, Uj, nj, xfr, ner,
+                     ner, nullptr, 1, nullptr, 1, 0);
+          }
+          if (ll >= 0)
+            gemm_add(lv.upd, lv.upd_tiles, Wn + (size_t)nj * nj, nj, nullptr, nj, nj, nLn, Lj, nj, XLl, nel, nel,
+                     nullptr, 1, nullptr, 1, 0);
+          if (rr >= 0)
+            gemm_add(lv.upd, lv.upd_tiles, Wn + (size_t)nj * (nj + nLn), nj, nullptr, nj, nj, nUn, Uj, nj, XUr, ner,
+                     ner, nullptr, 1, nullptr, 1, 0);
+        }
+      }
+      levels.push_back(lv);
+      std::vector<int> K;
+      for (int p = 0; p < m; p += 2) {
+        const int j = S_act[p];
+        cur[j] ^= 1;
+        nLc[j] = newL[j];
+        nUc[j] = newU[j];
+        K.push_back(j);
+      }
+      S_act = K;
     }
     // ---- upload descriptors
     size_t doff = 0;
@@ -1152,19 +1264,19 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
     const size_t oi = push(nullptr, sizeof(int) * 4);
     std::memset(hdesc.data() + oi, 0, sizeof(int) * 4);
     int* d_info = reinterpret_cast<int*>(dbase + oi);
-    for (int i = 0; i < I; ++i)
-      for (auto& L : lu[i]) L.info = d_info;
+    for (auto& lv : levels)
+      for (auto& G : lv.gje) G.info = d_info;
     const size_t o_asm = push(asmj.data(), sizeof(AsmJob) * asmj.size());
     const size_t o_gs = push(gs.data(), sizeof(GemmDesc) * gs.size());
     const size_t o_ls = push(ls.data(), sizeof(LsDesc) * ls.size());
     const size_t o_ang = push(angs.data(), sizeof(AngleDesc) * angs.size());
-    std::vector<size_t> o_sg(I), o_lu(I), o_lus(I);
-    for (int i = 0; i < I; ++i) {
-      o_sg[i] = push(sg[i].data(), sizeof(GemmDesc) * sg[i].size());
-      o_lu[i] = push(lu[i].data(), sizeof(LuDesc) * lu[i].size());
-      o_lus[i] = push(lus[i].data(), sizeof(LuSolveDesc) * lus[i].size());
+    const int NL = (int)levels.size();
+    std::vector<size_t> o_gje(NL), o_upd(NL), o_back(NL);
+    for (int l = 0; l < NL; ++l) {
+      o_gje[l] = push(levels[l].gje.data(), sizeof(GjeDesc) * levels[l].gje.size());
+      o_upd[l] = push(levels[l].upd.data(), sizeof(GemmDesc) * levels[l].upd.size());
+      o_back[l] = push(levels[l].back.data(), sizeof(GemvDesc) * levels[l].back.size());
     }
-    const size_t o_bs = push(bs.data(), sizeof(BacksubDesc) * bs.size());
     if (doff > (size_t)B * desc_per) return fail(MLH_E_DEVICE, "descriptor space exhausted");
     HIP_TRY(hipMemcpyAsync(dbase, hdesc.data(), doff, hipMemcpyHostToDevice, st));
     StackConsts sc{};
@@ -1214,27 +1326,33 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
       te();
     }
     if (stop_phase == 0 || stop_phase >= 4) {
-      for (int i = 0; i < I; ++i) {
-        if (i > 0) {
+      for (int l = 0; l < NL; ++l) {
+        const Level& lv = levels[l];
+        const GjeDesc* dg = reinterpret_cast<GjeDesc*>(dbase + o_gje[l]);
+        const int ng = (int)lv.gje.size();
+        for (int k = 0; k < lv.maxn; k += kGjeNb) {
+          tb(prof ? &prof->gje_panel_ms : nullptr);
+          launch_gje_panel(dg, ng, k, lv.maxn, st);
+          te();
+          tb(prof ? &prof->gje_update_ms : nullptr);
+          launch_gje_update(dg, ng, k, lv.maxcol, st);
+          te();
+          if (prof) {
+            prof->n_gje_panel++;
+            prof->n_gje_update++;
+          }
+        }
+        if (!lv.upd.empty()) {
           tb(prof ? &prof->sweep_gemm_ms : nullptr);
-          launch_gemm(reinterpret_cast<GemmDesc*>(dbase + o_sg[i]), (int)sg[i].size(), sg_tiles[i], st);
+          launch_gemm(reinterpret_cast<GemmDesc*>(dbase + o_upd[l]), (int)lv.upd.size(), lv.upd_tiles, st);
           te();
           if (prof) prof->n_sweep_gemm++;
         }
-        tb(prof ? &prof->lu_ms : nullptr);
-        launch_lu(reinterpret_cast<LuDesc*>(dbase + o_lu[i]), (int)lu[i].size(), st);
-        te();
-        tb(prof ? &prof->lu_solve_ms : nullptr);
-        launch_lu_solve(reinterpret_cast<LuSolveDesc*>(dbase + o_lus[i]), (int)lus[i].size(), lus_cols[i], maxn,
-                        st);
-        te();
-        if (prof) {
-          prof->n_lu++;
-          prof->n_lu_solve++;
-        }
       }
       tb(prof ? &prof->backsub_ms : nullptr);
-      launch_backsub(reinterpret_cast<BacksubDesc*>(dbase + o_bs), I, nb, st);
+      for (int l = NL - 1; l >= 0; --l)
+        launch_gemv_step(reinterpret_cast<GemvDesc*>(dbase + o_back[l]), (int)levels[l].back.size(), levels[l].backn,
+                         st);
       te();
       tb(prof ? &prof->bragg_ms : nullptr);
       launch_bragg(d_ang, nb, sc, st);
@@ -1243,13 +1361,9 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
     HIP_TRY(hipGetLastError());
     if (prof) T.collect();
     if (stop_phase != 0) {
-      // keep the first angle's workspace views for inspection
-      s->dbg_Dg = V[0].Dg;
-      s->dbg_Up = V[0].Up;
-      s->dbg_Dn = V[0].Dn;
+      s->dbg_R = V[0].W[0];
       s->dbg_S = V[0].S;
       s->dbg_RHS = V[0].RHS;
-      s->dbg_UG = V[0].UG;
       s->dbg_eta = V[0].eta;
       HIP_TRY(hipStreamSynchronize(st));
       return MLH_OK;
@@ -1259,13 +1373,14 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
       const int a = a0 + b;
       HIP_TRY(hipMemcpyAsync(aU + (size_t)2 * nK * a, V[b].aU, cbytes(nK), hipMemcpyDeviceToHost, st));
       HIP_TRY(hipMemcpyAsync(aD + (size_t)2 * nK * a, V[b].aD, cbytes(nK), hipMemcpyDeviceToHost, st));
-      if (orders) HIP_TRY(hipMemcpyAsync(orders + (size_t)nK * a, V[b].orders, sizeof(int) * nK, hipMemcpyDeviceToHost, st));
+      if (orders)
+        HIP_TRY(hipMemcpyAsync(orders + (size_t)nK * a, V[b].orders, sizeof(int) * nK, hipMemcpyDeviceToHost, st));
       HIP_TRY(hipMemcpyAsync(&h_flux[a], V[b].flux, sizeof(double), hipMemcpyDeviceToHost, st));
     }
     int info[4] = {0, 0, 0, 0};
     HIP_TRY(hipMemcpyAsync(info, d_info, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    if (info[0] != 0) return fail(MLH_E_SINGULAR, "exact zero pivot in the block-tridiagonal sweep");
+    if (info[0] != 0) return fail(MLH_E_SINGULAR, "exact zero pivot in the block-tridiagonal solve");
   }
   if (flux_err)
     for (int a = 0; a < n_angles; ++a) flux_err[a] = h_flux[a];
@@ -1393,6 +1508,8 @@ extern "C" mlh_status mlh_debug_zgemm(mlh_ctx ctx, int32_t m, int32_t n, int32_t
   G.C = dC;
   G.alpha = cx(alpha[0], alpha[1]);
   G.k2 = 0;
+  G.C0 = dC;
+  G.ldc0 = m;
   G.m = m;
   G.n = n;
   G.k = k;
@@ -1426,39 +1543,46 @@ extern "C" mlh_status mlh_debug_solve_partial(mlh_stack s, double theta, int32_t
 
 extern "C" mlh_status mlh_debug_get_work(mlh_stack s, int32_t which, int32_t index, double* out, int32_t* rows,
                                          int32_t* cols) {
-  if (!s || s->dbg_Dg.empty()) return fail(MLH_E_INVALID_ARG, "no inspection solve has run");
+  if (!s || s->dbg_R.empty()) return fail(MLH_E_INVALID_ARG, "no inspection solve has run");
   const int I = s->I;
-  int r = 0, c = 0;
-  const cplx* p = nullptr;
-  if (which == 0 && index >= 0 && index < I) {
+  // level-0 row block of interface i: [A'_ii | A'_{i,i-1} | A'_{i,i+1} | f~_i]
+  auto nl = [&](int i) { return i > 0 ? s->n[i - 1] : 0; };
+  auto nu = [&](int i) { return i + 1 < I ? s->n[i + 1] : 0; };
+  int r = 0, c1 = 0, c2 = 0;
+  const cplx* p1 = nullptr;
+  const cplx* p2 = nullptr;
+  if (which == 0 && index >= 0 && index < I) {  // [A'_ii | f~_i]
     r = s->n[index];
-    c = s->n[index] + 1;
-    p = s->dbg_Dg[index];
-  } else if ((which == 1 || which == 2) && index >= 0 && index + 1 < I) {
-    r = which == 1 ? s->n[index] : s->n[index + 1];
-    c = which == 1 ? s->n[index + 1] : s->n[index];
-    p = which == 1 ? s->dbg_Up[index] : s->dbg_Dn[index];
+    c1 = r;
+    p1 = s->dbg_R[index];
+    c2 = 1;
+    p2 = s->dbg_R[index] + (size_t)r * (r + nl(index) + nu(index));
+  } else if (which == 1 && index >= 0 && index + 1 < I) {  // A'_{i,i+1}
+    r = s->n[index];
+    c1 = s->n[index + 1];
+    p1 = s->dbg_R[index] + (size_t)r * (r + nl(index));
+  } else if (which == 2 && index >= 0 && index + 1 < I) {  // A'_{i+1,i}
+    r = s->n[index + 1];
+    c1 = s->n[index];
+    p1 = s->dbg_R[index + 1] + (size_t)r * r;
   } else if ((which == 3 || which == 4) && index >= 0 && index <= I) {
     int m, cc, nc;
     layer_dims(s, index, m, cc, nc);
     r = m + cc;
-    c = which == 3 ? cc : nc;
-    p = which == 3 ? s->dbg_S[index] : s->dbg_RHS[index];
-  } else if (which == 5 && index >= 0 && index < I) {
-    r = s->n[index];
-    c = (index + 1 < I ? s->n[index + 1] : 0) + 1;
-    p = s->dbg_UG[index];
+    c1 = which == 3 ? cc : nc;
+    p1 = which == 3 ? s->dbg_S[index] : s->dbg_RHS[index];
   } else if (which == 6 && index >= 0 && index < I) {
     r = s->n[index];
-    c = 1;
-    p = s->dbg_eta[index];
+    c1 = 1;
+    p1 = s->dbg_eta[index];
   }
-  if (!p) return fail(MLH_E_INVALID_ARG, "mlh_debug_get_work: no such block");
+  if (!p1) return fail(MLH_E_INVALID_ARG, "mlh_debug_get_work: no such block");
   if (rows) *rows = r;
-  if (cols) *cols = c;
+  if (cols) *cols = c1 + c2;
   if (out) {
     HIP_TRY(hipSetDevice(s->ctx->device));
-    HIP_TRY(hipMemcpy(out, p, cbytes((size_t)r * c), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(out, p1, cbytes((size_t)r * c1), hipMemcpyDeviceToHost));
+    if (p2) HIP_TRY(hipMemcpy(out + (size_t)2 * r * c1, p2, cbytes((size_t)r * c2), hipMemcpyDeviceToHost));
   }
   return MLH_OK;
 }
