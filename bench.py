@@ -80,8 +80,8 @@ def algorithmic_work(desc):
         ncol = n[0] if j == 0 else (n[I - 1] if j == I else n[j - 1] + n[j])
         qr += 8.0 * M * c * c - 8.0 * c ** 3 / 3.0
         ap += ncol * (16.0 * M * c - 4.0 * c * c)
-    w["ls_qr"] = qr
-    w["ls_apply"] = ap
+    w["ls_panel"] = qr
+    w["ls_update"] = ap
     w["backsub"] = sum(8.0 * n[i] * n[i + 1] for i in range(I - 1))
     # fill: complex entries written (three copies for A and Z, two for C and Q)
     ent_self = sum(3 * n[i] * n[i] for i in range(I))
@@ -98,8 +98,8 @@ GROUPS = [  # (name, profile time key, launch-count key, work key, bound)
     ("gje_panel_kernel", "gje_panel_ms", "n_gje_panel", "gje_panel", "alu"),
     ("zgemm_kernel (sweep update)", "sweep_gemm_ms", "n_sweep_gemm", "sweep_gemm", "mfma"),
     ("zgemm_kernel (Schur complements)", "schur_ms", None, "schur", "mfma"),
-    ("ls_qr_kernel", "ls_qr_ms", None, "ls_qr", "alu"),
-    ("ls_apply_kernel", "ls_apply_ms", None, "ls_apply", "alu"),
+    ("hq_panel_kernel", "ls_panel_ms", None, "ls_panel", "alu"),
+    ("hq_update_kernel", "ls_update_ms", None, "ls_update", "alu"),
     ("gemv_step_kernel", "backsub_ms", None, "backsub", "alu"),
     ("self_kernel", "fill_self_ms", None, "fill_self_bytes", "hbm"),
     ("fill_kernel", "fill_pairs_ms", None, "fill_pairs_bytes", "hbm"),

@@ -94,15 +94,6 @@ struct GemmDesc {
   int tile_begin, tiles_m;
 };
 
-// least-squares problem of one layer and one angle
-struct LsDesc {
-  cplx* S;       // (m + c) x c stacked matrix, column-major, ld = m + c
-  cplx* tau;     // c
-  cplx* RHS;     // (m + c) x ncol, ld = m + c; top c rows receive X
-  double mu_rel;
-  int m, c, ncol;
-  int col_block_begin;
-};
 
 
 
@@ -112,8 +103,6 @@ void launch_self(const SelfJob* d_jobs, int njobs, int total_tiles, int a_excl, 
 void launch_alpert(const AlpertJob* d_jobs, int njobs, int total_blocks, int a_excl, hipStream_t st);
 void launch_assemble(const AsmJob* d_jobs, int njobs, int64_t total_elems, hipStream_t st);
 void launch_gemm(const GemmDesc* d_desc, int ndesc, int total_tiles, hipStream_t st);
-void launch_ls_qr(const LsDesc* d_desc, int ndesc, hipStream_t st);
-void launch_ls_apply(const LsDesc* d_desc, int ndesc, int total_col_blocks, int max_rows, hipStream_t st);
 void launch_hankel_eval(const double* x, double* out, int n, hipStream_t st);
 
 }  // namespace mlh
@@ -167,7 +156,7 @@ struct GjeDesc {
   cplx* W;
   cplx* P;    // scratch n x kGjeNb: panel multipliers of the current step
   cplx* M1;   // scratch kGjeNb x kGjeNb: inverse of the pivot block
-  int* piv;   // scratch kGjeNb: pivot rows of the current step
+  int* piv;   // scratch 1 + 4 kGjeNb ints: the current step's row interchanges
   int* info;  // set to (global column + 1) on an exactly zero pivot
   int n, ncol;
 };
@@ -187,5 +176,30 @@ void gje_init();
 void launch_gje_panel(const GjeDesc* d, int nbatch, int k, int max_n, hipStream_t st);
 void launch_gje_update(const GjeDesc* d, int nbatch, int k, int max_ncol, hipStream_t st);
 void launch_gemv_step(const GemvDesc* d, int nbatch, int max_n, hipStream_t st);
+
+}  // namespace mlh
+
+namespace mlh {
+
+// Blocked Householder least squares of one layer (Sec. 3.2): the augmented
+// matrix A = [S | RHS] (M x (c + ncol), ld M, M = m + c) with S = [Q; mu I]
+// is reduced panel by panel (WY form), then R X = (Q^H RHS)[0:c] is solved
+// by back substitution; X overwrites the top c rows of RHS.
+constexpr int kHqNb = 16;
+constexpr int kHqCols = 32;
+constexpr int kHqMaxRows = 512;  // M  (LDS holds an M x 16 panel)
+constexpr int kHqMaxC = 256;     // c  (LDS holds a c x 32 back-substitution tile)
+
+struct HqDesc {
+  cplx* A;
+  cplx* T;    // scratch 16 x 16: block reflector factor of the current panel
+  double mu_rel;
+  int m, c, ncol;
+};
+
+void launch_hq_prep(const HqDesc* d, int n, hipStream_t st);
+void launch_hq_panel(const HqDesc* d, int n, int k, hipStream_t st);
+void launch_hq_update(const HqDesc* d, int n, int k, int max_cols, hipStream_t st);
+void launch_hq_backsub(const HqDesc* d, int n, int max_ncol, hipStream_t st);
 
 }  // namespace mlh

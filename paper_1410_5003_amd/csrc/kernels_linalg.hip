@@ -6,11 +6,6 @@
 //                   Operand layout of the 16x16x4 f64 instruction: lane l holds
 //                   A[l%16][l/16] and B[l/16][l%16]; accumulator register r of
 //                   lane l holds D[l/16 + 4r][l%16].
-//  ls_qr_kernel     Householder QR of the Tikhonov-stacked [Q; mu I] of one
-//                   layer (Sec. 3.2: backward-stable least squares, the
-//                   pseudo-inverse is never formed).
-//  ls_apply_kernel  Q^H and R^{-1} applied to the stacked right-hand side
-//                   [C; 0], one wavefront per column: X = Q^+ C.
 //  rb_setup_kernel  Rayleigh-Bloch rows W_U, W_D (eq. (59)) and the
 //                   incident-field right-hand side f (Sec. 2.2).
 //  bragg_kernel     a^U = -[X_1 eta_1]_a, a^D = -[X_{I+1} eta_I]_a (Sec. 3.3)
@@ -111,172 +106,6 @@ __global__ __launch_bounds__(256) void zgemm_kernel(const GemmDesc* __restrict__
 // ---------------------------------------------------------------------------
 // least squares of one layer: Householder QR of S = [Q; mu I]
 // ---------------------------------------------------------------------------
-__device__ inline double block_sum(double v, double* red) {
-  const int tid = threadIdx.x;
-  v = wave_sum(v);
-  __syncthreads();
-  if ((tid & 63) == 0) red[tid >> 6] = v;
-  __syncthreads();
-  double s = 0.0;
-  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
-  return s;
-}
-
-__global__ __launch_bounds__(256) void ls_qr_kernel(const LsDesc* __restrict__ descs) {
-  const LsDesc& L = descs[blockIdx.x];
-  const int m = L.m, c = L.c, M = m + c;
-  cplx* S = L.S;
-  __shared__ double red[8];
-  __shared__ double sh[6];
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  double acc = 0.0;
-  for (int e = tid; e < m * c; e += 256) {
-    const double2 v = ld2(S + (size_t)(e / m) * M + (e % m));
-    acc += v.x * v.x + v.y * v.y;
-  }
-  const double mu = L.mu_rel * sqrt(block_sum(acc, red));
-  for (int e = tid; e < c * c; e += 256) {
-    const int r = e % c, col = e / c;
-    st2(S + (size_t)col * M + m + r, r == col ? mu : 0.0, 0.0);
-  }
-  __syncthreads();
-  for (int kc = 0; kc < c; ++kc) {
-    cplx* col = S + (size_t)kc * M;
-    acc = 0.0;
-    for (int r = kc + 1 + tid; r < M; r += 256) {
-      const double2 v = ld2(col + r);
-      acc += v.x * v.x + v.y * v.y;
-    }
-    const double xn2 = block_sum(acc, red);
-    if (tid == 0) {
-      const double2 al = ld2(col + kc);
-      double tr = 0.0, ti = 0.0, sr = 1.0, si = 0.0, beta = al.x;
-      if (!(xn2 == 0.0 && al.y == 0.0)) {
-        beta = -copysign(sqrt(al.x * al.x + al.y * al.y + xn2), al.x);
-        tr = (beta - al.x) / beta;
-        ti = -al.y / beta;
-        // scale = 1 / (alpha - beta)
-        const double dr = al.x - beta, di = al.y;
-        const double den = dr * dr + di * di;
-        sr = dr / den;
-        si = -di / den;
-      }
-      sh[0] = tr;
-      sh[1] = ti;
-      sh[2] = sr;
-      sh[3] = si;
-      sh[4] = beta;
-      st2(L.tau + kc, tr, ti);
-    }
-    __syncthreads();
-    const double sr = sh[2], si = sh[3];
-    for (int r = kc + 1 + tid; r < M; r += 256) {
-      const double2 v = ld2(col + r);
-      st2(col + r, v.x * sr - v.y * si, v.x * si + v.y * sr);
-    }
-    if (tid == 0) st2(col + kc, sh[4], 0.0);
-    __syncthreads();
-    // trailing columns: S[kc:, j] -= conj(tau) v (v^H S[kc:, j])
-    const double ctr = sh[0], cti = -sh[1];
-    for (int j = kc + 1 + wave; j < c; j += 4) {
-      cplx* cj = S + (size_t)j * M;
-      double wr = 0.0, wi = 0.0;
-      for (int r = kc + lane; r < M; r += 64) {
-        const double2 b = ld2(cj + r);
-        double vr = 1.0, vi = 0.0;
-        if (r > kc) {
-          const double2 v = ld2(col + r);
-          vr = v.x;
-          vi = v.y;
-        }
-        // conj(v) * b
-        wr += vr * b.x + vi * b.y;
-        wi += vr * b.y - vi * b.x;
-      }
-      wr = wave_sum(wr);
-      wi = wave_sum(wi);
-      const double tr2 = ctr * wr - cti * wi, ti2 = ctr * wi + cti * wr;
-      for (int r = kc + lane; r < M; r += 64) {
-        double vr = 1.0, vi = 0.0;
-        if (r > kc) {
-          const double2 v = ld2(col + r);
-          vr = v.x;
-          vi = v.y;
-        }
-        const double2 b = ld2(cj + r);
-        st2(cj + r, b.x - (vr * tr2 - vi * ti2), b.y - (vr * ti2 + vi * tr2));
-      }
-    }
-    __syncthreads();
-  }
-}
-
-// one wavefront per right-hand-side column; 4 columns per workgroup share the
-// reflector staged in LDS
-__global__ __launch_bounds__(256) void ls_apply_kernel(const LsDesc* __restrict__ descs, int ndesc) {
-  int lo = 0, hi = ndesc - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (descs[mid].col_block_begin <= (int)blockIdx.x)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  const LsDesc& L = descs[lo];
-  const int m = L.m, c = L.c, M = m + c;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int colidx = ((int)blockIdx.x - L.col_block_begin) * 4 + wave;
-  const bool active = colidx < L.ncol;
-  extern __shared__ double2 smem[];
-  double2* v = smem;
-  double2* b = smem + M + (size_t)wave * M;
-  cplx* gcol = L.RHS + (size_t)(active ? colidx : 0) * M;
-  for (int r = lane; r < M; r += 64) b[r] = active ? ld2(gcol + r) : make_double2(0.0, 0.0);
-  for (int kc = 0; kc < c; ++kc) {
-    __syncthreads();
-    const cplx* sc = L.S + (size_t)kc * M;
-    for (int r = kc + tid; r < M; r += 256) v[r] = (r == kc) ? make_double2(1.0, 0.0) : ld2(sc + r);
-    __syncthreads();
-    double wr = 0.0, wi = 0.0;
-    for (int r = kc + lane; r < M; r += 64) {
-      const double2 vv = v[r], bb = b[r];
-      wr += vv.x * bb.x + vv.y * bb.y;
-      wi += vv.x * bb.y - vv.y * bb.x;
-    }
-    wr = wave_sum(wr);
-    wi = wave_sum(wi);
-    const double2 t = ld2(L.tau + kc);
-    // conj(tau) * w
-    const double tr = t.x * wr + t.y * wi, ti = t.x * wi - t.y * wr;
-    for (int r = kc + lane; r < M; r += 64) {
-      const double2 vv = v[r];
-      double2 bb = b[r];
-      bb.x -= vv.x * tr - vv.y * ti;
-      bb.y -= vv.x * ti + vv.y * tr;
-      b[r] = bb;
-    }
-  }
-  __syncthreads();
-  // R X = (Q^H B)[0:c]
-  for (int kc = c - 1; kc >= 0; --kc) {
-    const double rkk = ld2(L.S + (size_t)kc * M + kc).x;
-    const double2 bk = b[kc];
-    const double xr = bk.x / rkk, xi = bk.y / rkk;
-    const cplx* rc = L.S + (size_t)kc * M;
-    for (int r = lane; r < kc; r += 64) {
-      const double2 rv = ld2(rc + r);
-      double2 bb = b[r];
-      bb.x -= rv.x * xr - rv.y * xi;
-      bb.y -= rv.x * xi + rv.y * xr;
-      b[r] = bb;
-    }
-    __syncthreads();
-    if (lane == 0) b[kc] = make_double2(xr, xi);
-    __syncthreads();
-  }
-  if (active)
-    for (int r = lane; r < c; r += 64) st2(gcol + r, b[r].x, b[r].y);
-}
 
 // ---------------------------------------------------------------------------
 // Rayleigh-Bloch orders, W blocks and the incident right-hand side
@@ -360,14 +189,6 @@ __global__ __launch_bounds__(64) void bragg_kernel(const AngleDesc* __restrict__
 
 void launch_gemm(const GemmDesc* d_desc, int ndesc, int total_tiles, hipStream_t st) {
   if (total_tiles > 0) hipLaunchKernelGGL(zgemm_kernel, dim3(total_tiles), dim3(256), 0, st, d_desc, ndesc);
-}
-void launch_ls_qr(const LsDesc* d_desc, int ndesc, hipStream_t st) {
-  if (ndesc > 0) hipLaunchKernelGGL(ls_qr_kernel, dim3(ndesc), dim3(256), 0, st, d_desc);
-}
-void launch_ls_apply(const LsDesc* d_desc, int ndesc, int total_col_blocks, int max_rows, hipStream_t st) {
-  if (total_col_blocks > 0)
-    hipLaunchKernelGGL(ls_apply_kernel, dim3(total_col_blocks), dim3(256), (size_t)5 * max_rows * sizeof(double2),
-                       st, d_desc, ndesc);
 }
 void launch_rb_setup(const AngleDesc* d_ang, int nang, StackConsts sc, hipStream_t st) {
   if (nang > 0) hipLaunchKernelGGL(rb_setup_kernel, dim3(nang), dim3(256), 0, st, d_ang, sc);

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -235,6 +236,14 @@ struct mlh_stack_s {
   // workspace views of the first angle of the last inspection solve
   std::vector<cplx*> dbg_R, dbg_S, dbg_RHS, dbg_eta;
 
+  // captured launch sequence of the solve (replayed while the batch shape and
+  // the workspace stay the same; only the descriptor contents change)
+  hipGraphExec_t gexec = nullptr;
+  hipStream_t cap_stream = nullptr;
+  int g_nb = -1, g_B = -1;
+  size_t g_doff = 0;
+  char* g_wmem = nullptr;
+
   // solve workspace (reused across calls with the same batch size)
   char* wmem = nullptr;
   size_t wbytes = 0;
@@ -254,6 +263,9 @@ static mlh_status validate(const mlh_stack_desc* D) {
   if (D->M_w < 1 || D->K < 0) return fail(MLH_E_INVALID_ARG, "need M_w >= 1 and K >= 0");
   if (D->M_ud < 2 * D->K + 1) return fail(MLH_E_INVALID_ARG, "M_ud must be >= 2K+1 (aliasing of Rayleigh-Bloch orders)");
   if (D->ls_mu < 0 || !std::isfinite(D->ls_mu)) return fail(MLH_E_INVALID_ARG, "ls_mu must be >= 0");
+  if (2 * D->M_w + 2 * D->M_ud + D->P + 2 * D->K + 1 > kHqMaxRows || D->P + 2 * D->K + 1 > kHqMaxC)
+    return fail(MLH_E_UNSUPPORTED, "least-squares blocks too large: need 2 M_w + 2 M_ud + P + 2K + 1 <= 512 "
+                                   "and P + 2K + 1 <= 256");
   const int nmin = 2 * (kAlpertA + 8) + 1;
   const int nmax = kGjeMaxN / 2;
   for (int i = 0; i < D->I; ++i) {
@@ -765,6 +777,8 @@ extern "C" mlh_status mlh_stack_destroy(mlh_stack s) {
   if (!s) return MLH_OK;
   hipSetDevice(s->ctx->device);
   if (s->dmem) hipFree(s->dmem);
+  if (s->gexec) hipGraphExecDestroy(s->gexec);
+  if (s->cap_stream) hipStreamDestroy(s->cap_stream);
   if (s->wmem) hipFree(s->wmem);
   delete s;
   return MLH_OK;
@@ -875,15 +889,14 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
     for (int j = 0; j <= I; ++j) {
       int m, c, nc;
       layer_dims(s, j, m, c, nc);
-      R(cbytes((size_t)(m + c) * c));
-      R(cbytes((size_t)c));
-      R(cbytes((size_t)(m + c) * nc));
+      R(cbytes((size_t)(m + c) * (c + nc)));  // [S | RHS]
+      R(cbytes((size_t)kHqNb * kHqNb));
     }
     for (int i = 0; i < I; ++i) R(cbytes(n[i]));
     for (int i = 0; i < I; ++i) {
       R(cbytes((size_t)n[i] * kGjeNb));
       R(cbytes((size_t)kGjeNb * kGjeNb));
-      R(sizeof(int) * kGjeNb);
+      R(sizeof(int) * (1 + 4 * kGjeNb));
     }
     R(cbytes(2 * nK));
     R(sizeof(double) * 2);
@@ -893,7 +906,7 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
   plan(ar, nullptr);
   const size_t per = (ar.off + 255) & ~size_t(255);
   const size_t desc_per = sizeof(AsmJob) * (size_t)(10 * (I + 2)) + sizeof(GemmDesc) * (size_t)(8 * I + 8) +
-                          sizeof(LsDesc) * (size_t)(I + 1) + sizeof(GjeDesc) * (size_t)(I + 1) +
+                          sizeof(HqDesc) * (size_t)(I + 1) + sizeof(GjeDesc) * (size_t)(I + 1) +
                           sizeof(GemvDesc) * (size_t)(I + 1) + sizeof(AngleDesc) + 256 * (size_t)(3 * 40 + 16);
   size_t freeb = 0, totb = 0;
   HIP_TRY(hipMemGetInfo(&freeb, &totb));
@@ -902,6 +915,10 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
   while (B > 1 && (size_t)B * (per + desc_per) > budget) B = (B + 1) / 2;
   const size_t need = (size_t)B * (per + desc_per) + 4096;
   if (need > s->wbytes) {
+    if (s->gexec) {
+      hipGraphExecDestroy(s->gexec);
+      s->gexec = nullptr;
+    }
     if (s->wmem) HIP_TRY(hipFree(s->wmem));
     s->wmem = nullptr;
     s->wbytes = 0;
@@ -918,7 +935,7 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
     const int nb = std::min(B, n_angles - a0);
     char* dbase = s->wmem + (size_t)B * per;
     struct View {
-      std::vector<cplx*> W[2], S, tau, RHS, eta, Pg, M1;
+      std::vector<cplx*> W[2], S, Th, RHS, eta, Pg, M1;
       std::vector<int*> piv;
       cplx *aU, *aD;
       double* flux;
@@ -933,9 +950,12 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
       for (int i = 0; i < I; ++i) v.W[0].push_back(C());
       for (int i = 0; i < I; ++i) v.W[1].push_back(C());
       for (int j = 0; j <= I; ++j) {
-        v.S.push_back(C());
-        v.tau.push_back(C());
-        v.RHS.push_back(C());
+        int m, c, nc;
+        layer_dims(s, j, m, c, nc);
+        cplx* aug = C();
+        v.S.push_back(aug);
+        v.RHS.push_back(aug + (size_t)(m + c) * c);
+        v.Th.push_back(C());
       }
       for (int i = 0; i < I; ++i) v.eta.push_back(C());
       for (int i = 0; i < I; ++i) {
@@ -1003,8 +1023,8 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
     };
     std::vector<GemmDesc> gs;
     int gtiles = 0;
-    std::vector<LsDesc> ls;
-    int colblocks = 0, maxrows = 0;
+    std::vector<HqDesc> hq;
+    int maxc = 0, maxcols = 0, maxncol = 0;
     std::vector<AngleDesc> angs(nb);
     const cplx one = cx(1, 0);
     for (int b = 0; b < nb; ++b) {
@@ -1032,7 +1052,6 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
         int m, c, nc;
         layer_dims(s, j, m, c, nc);
         const int M = m + c;
-        maxrows = std::max(maxrows, M);
         const int mw2 = 2 * s->Mw, mud2 = 2 * s->Mud;
         const size_t qe = (size_t)mw2 * P;
         const cplx* sq[2] = {s->Q[j], s->Q[j] + qe};
@@ -1059,17 +1078,17 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
           asm_add(v.RHS[j] + (size_t)n[j - 1] * M, M, mw2, n[j], 2, so, mw2, cC);
           asm_add(v.RHS[j] + m, M, c, nc, 0, sa, mw2, cC);
         }
-        LsDesc L{};
-        L.S = v.S[j];
-        L.tau = v.tau[j];
-        L.RHS = v.RHS[j];
-        L.mu_rel = s->mu;
-        L.m = m;
-        L.c = c;
-        L.ncol = nc;
-        L.col_block_begin = colblocks;
-        colblocks += (nc + 3) / 4;
-        ls.push_back(L);
+        HqDesc H{};
+        H.A = v.S[j];
+        H.T = v.Th[j];
+        H.mu_rel = s->mu;
+        H.m = m;
+        H.c = c;
+        H.ncol = nc;
+        hq.push_back(H);
+        maxc = std::max(maxc, c);
+        maxcols = std::max(maxcols, c + nc);
+        maxncol = std::max(maxncol, nc);
       }
       // Schur complements eq. (74)-(78): A' = A - B X, in place; each
       // descriptor owns its output block
@@ -1268,7 +1287,7 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
       for (auto& G : lv.gje) G.info = d_info;
     const size_t o_asm = push(asmj.data(), sizeof(AsmJob) * asmj.size());
     const size_t o_gs = push(gs.data(), sizeof(GemmDesc) * gs.size());
-    const size_t o_ls = push(ls.data(), sizeof(LsDesc) * ls.size());
+    const size_t o_hq = push(hq.data(), sizeof(HqDesc) * hq.size());
     const size_t o_ang = push(angs.data(), sizeof(AngleDesc) * angs.size());
     const int NL = (int)levels.size();
     std::vector<size_t> o_gje(NL), o_upd(NL), o_back(NL);
@@ -1295,70 +1314,116 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
     sc.Mud = s->Mud;
     sc.P = P;
     sc.K = s->K;
-    // ---- launch sequence
-    EvTimer T{st};
-    double dummy = 0.0;
-    auto tb = [&](double* acc) {
-      if (prof) T.begin(acc ? acc : &dummy);
-    };
-    auto te = [&]() {
-      if (prof) T.end();
-    };
-    tb(prof ? &prof->assemble_ms : nullptr);
-    launch_assemble(reinterpret_cast<AsmJob*>(dbase + o_asm), (int)asmj.size(), elems, st);
-    te();
-    const AngleDesc* d_ang = reinterpret_cast<AngleDesc*>(dbase + o_ang);
-    tb(prof ? &prof->rb_setup_ms : nullptr);
-    launch_rb_setup(d_ang, nb, sc, st);
-    te();
-    const LsDesc* d_ls = reinterpret_cast<LsDesc*>(dbase + o_ls);
-    if (stop_phase == 0 || stop_phase >= 2) {
-      tb(prof ? &prof->ls_qr_ms : nullptr);
-      launch_ls_qr(d_ls, (int)ls.size(), st);
+    // ---- launch sequence (captured into a graph and replayed when possible)
+    auto launch_all = [&](hipStream_t ls, EvTimer& T) -> mlh_status {
+      double dummy = 0.0;
+      auto tb = [&](double* acc) {
+        if (prof) T.begin(acc ? acc : &dummy);
+      };
+      auto te = [&]() {
+        if (prof) T.end();
+      };
+      tb(prof ? &prof->assemble_ms : nullptr);
+      launch_assemble(reinterpret_cast<AsmJob*>(dbase + o_asm), (int)asmj.size(), elems, ls);
       te();
-      tb(prof ? &prof->ls_apply_ms : nullptr);
-      launch_ls_apply(d_ls, (int)ls.size(), colblocks, maxrows, st);
+      const AngleDesc* d_ang = reinterpret_cast<AngleDesc*>(dbase + o_ang);
+      tb(prof ? &prof->rb_setup_ms : nullptr);
+      launch_rb_setup(d_ang, nb, sc, ls);
       te();
-    }
-    if (stop_phase == 0 || stop_phase >= 3) {
-      tb(prof ? &prof->schur_ms : nullptr);
-      launch_gemm(reinterpret_cast<GemmDesc*>(dbase + o_gs), (int)gs.size(), gtiles, st);
-      te();
-    }
-    if (stop_phase == 0 || stop_phase >= 4) {
-      for (int l = 0; l < NL; ++l) {
-        const Level& lv = levels[l];
-        const GjeDesc* dg = reinterpret_cast<GjeDesc*>(dbase + o_gje[l]);
-        const int ng = (int)lv.gje.size();
-        for (int k = 0; k < lv.maxn; k += kGjeNb) {
-          tb(prof ? &prof->gje_panel_ms : nullptr);
-          launch_gje_panel(dg, ng, k, lv.maxn, st);
+      const HqDesc* d_hq = reinterpret_cast<HqDesc*>(dbase + o_hq);
+      const int nhq = (int)hq.size();
+      if (stop_phase == 0 || stop_phase >= 2) {
+        tb(prof ? &prof->ls_panel_ms : nullptr);
+        launch_hq_prep(d_hq, nhq, ls);
+        te();
+        for (int k = 0; k < maxc; k += kHqNb) {
+          tb(prof ? &prof->ls_panel_ms : nullptr);
+          launch_hq_panel(d_hq, nhq, k, ls);
           te();
-          tb(prof ? &prof->gje_update_ms : nullptr);
-          launch_gje_update(dg, ng, k, lv.maxcol, st);
+          tb(prof ? &prof->ls_update_ms : nullptr);
+          launch_hq_update(d_hq, nhq, k, maxcols, ls);
           te();
-          if (prof) {
-            prof->n_gje_panel++;
-            prof->n_gje_update++;
+        }
+        tb(prof ? &prof->ls_backsub_ms : nullptr);
+        launch_hq_backsub(d_hq, nhq, maxncol, ls);
+        te();
+      }
+      if (stop_phase == 0 || stop_phase >= 3) {
+        tb(prof ? &prof->schur_ms : nullptr);
+        launch_gemm(reinterpret_cast<GemmDesc*>(dbase + o_gs), (int)gs.size(), gtiles, ls);
+        te();
+      }
+      if (stop_phase == 0 || stop_phase >= 4) {
+        for (int l = 0; l < NL; ++l) {
+          const Level& lv = levels[l];
+          const GjeDesc* dg = reinterpret_cast<GjeDesc*>(dbase + o_gje[l]);
+          const int ng = (int)lv.gje.size();
+          for (int k = 0; k < lv.maxn; k += kGjeNb) {
+            tb(prof ? &prof->gje_panel_ms : nullptr);
+            launch_gje_panel(dg, ng, k, lv.maxn, ls);
+            te();
+            tb(prof ? &prof->gje_update_ms : nullptr);
+            launch_gje_update(dg, ng, k, lv.maxcol, ls);
+            te();
+            if (prof) {
+              prof->n_gje_panel++;
+              prof->n_gje_update++;
+            }
+          }
+          if (!lv.upd.empty()) {
+            tb(prof ? &prof->sweep_gemm_ms : nullptr);
+            launch_gemm(reinterpret_cast<GemmDesc*>(dbase + o_upd[l]), (int)lv.upd.size(), lv.upd_tiles, ls);
+            te();
+            if (prof) prof->n_sweep_gemm++;
           }
         }
-        if (!lv.upd.empty()) {
-          tb(prof ? &prof->sweep_gemm_ms : nullptr);
-          launch_gemm(reinterpret_cast<GemmDesc*>(dbase + o_upd[l]), (int)lv.upd.size(), lv.upd_tiles, st);
-          te();
-          if (prof) prof->n_sweep_gemm++;
-        }
+        tb(prof ? &prof->backsub_ms : nullptr);
+        for (int l = NL - 1; l >= 0; --l)
+          launch_gemv_step(reinterpret_cast<GemvDesc*>(dbase + o_back[l]), (int)levels[l].back.size(), levels[l].backn,
+                           ls);
+        te();
+        tb(prof ? &prof->bragg_ms : nullptr);
+        launch_bragg(d_ang, nb, sc, ls);
+        te();
       }
-      tb(prof ? &prof->backsub_ms : nullptr);
-      for (int l = NL - 1; l >= 0; --l)
-        launch_gemv_step(reinterpret_cast<GemvDesc*>(dbase + o_back[l]), (int)levels[l].back.size(), levels[l].backn,
-                         st);
-      te();
-      tb(prof ? &prof->bragg_ms : nullptr);
-      launch_bragg(d_ang, nb, sc, st);
-      te();
+      HIP_TRY(hipGetLastError());
+
+      return MLH_OK;
+    };
+    EvTimer T{st};
+    static const bool no_graph = std::getenv("MLH_NO_GRAPH") != nullptr;
+    if (prof || stop_phase != 0 || no_graph) {
+      MLH_TRY(launch_all(st, T));
+    } else {
+      if (!(s->gexec && s->g_nb == nb && s->g_B == B && s->g_doff == doff && s->g_wmem == s->wmem)) {
+        if (s->gexec) {
+          hipGraphExecDestroy(s->gexec);
+          s->gexec = nullptr;
+        }
+        if (!s->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+        // the capture stream waits for the descriptor upload
+        hipEvent_t up;
+        HIP_TRY(hipEventCreateWithFlags(&up, hipEventDisableTiming));
+        HIP_TRY(hipEventRecord(up, st));
+        HIP_TRY(hipStreamWaitEvent(s->cap_stream, up, 0));
+        HIP_TRY(hipStreamSynchronize(s->cap_stream));
+        hipEventDestroy(up);
+        hipGraph_t g = nullptr;
+        HIP_TRY(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
+        mlh_status ls_ = launch_all(s->cap_stream, T);
+        hipError_t ce = hipStreamEndCapture(s->cap_stream, &g);
+        if (ls_ != MLH_OK) return ls_;
+        if (ce != hipSuccess) return fail(MLH_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
+        hipError_t ie = hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (ie != hipSuccess) return fail(MLH_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(ie));
+        s->g_nb = nb;
+        s->g_B = B;
+        s->g_doff = doff;
+        s->g_wmem = s->wmem;
+      }
+      HIP_TRY(hipGraphLaunch(s->gexec, st));
     }
-    HIP_TRY(hipGetLastError());
     if (prof) T.collect();
     if (stop_phase != 0) {
       s->dbg_R = V[0].W[0];
