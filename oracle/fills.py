@@ -16,14 +16,16 @@ extended three-copy index J = j + l N, and Alpert's auxiliary-node correction
 inside it, with 16-point Lagrange interpolation of the density from the
 nodes; stencil nodes that fall in the neighbouring copies carry alpha^{+-1}
 (Sec. 2.5 and its Remark on the quasi-periodic wrap).  The jump terms give
--I on the (tau, tau) block and +I on the (sigma, sigma) block.
+-I on the (tau, tau) block and +I on the (sigma, sigma) block.  Cornered
+interfaces apply the correction per graded segment (see
+_self_pieces_polygon).
 """
 from __future__ import annotations
 
 import numpy as np
 
 from . import special
-from .geometry import Curve, Geometry, proxies
+from .geometry import Curve, Geometry, kress_w, kress_wc, proxies
 
 STENCIL = 16
 
@@ -121,7 +123,74 @@ def self_pieces(c: Curve, ka: float, kb: float, rule) -> np.ndarray:
 
 
 def _self_pieces_polygon(c: Curve, ka, kb, rule):
-    raise NotImplementedError("cornered self blocks are not part of the oracle yet")
+    """Pieces of A_ii for a cornered interface (Sec. 2.5).
+
+    Every segment carries its own Kress-graded trapezoid rule in the segment
+    parameter s in [0, 2 pi).  Interactions between different segments, and
+    all interactions with the neighbouring copies l = +-1, are plain Nystrom
+    entries.  Within one segment the rule is treated as periodic in s with no
+    Bloch phase (the graded Jacobian vanishes to high order at both segment
+    ends, so the integrand continues smoothly across s = 0 ~ 2 pi): entries
+    with cyclic segment-local index distance < a are replaced by Alpert's
+    auxiliary nodes s_m +- chi_k h.  What is interpolated to the auxiliary
+    nodes is the product of the density and the graded Jacobian |Z'(w(s))|
+    w'(s), which is smooth and periodic in s, whereas the density alone is not
+    continuous across the segment ends; the auxiliary weight is then u_k and
+    the interpolation weights multiply the node weights w_j."""
+    N, d = c.N, c.d
+    chi, u, a = rule
+    out = np.zeros((3, 2 * N, 2 * N), dtype=complex)
+    seg = c.seg_of
+    loc = np.arange(N) - c.seg_start[seg]            # segment-local index
+    nseg = c.seg_n[seg]
+    for li, l in enumerate((-1, 0, 1)):
+        r2, nd, npd, nn = _pair_geom(c.x, c.y, c.nx, c.ny, c.x + l * d, c.y, c.nx, c.ny)
+        mask = np.ones((N, N), dtype=bool)
+        if l == 0:
+            same = seg[:, None] == seg[None, :]
+            dist = np.mod(loc[None, :] - loc[:, None], nseg[:, None])
+            cyc = np.minimum(dist, nseg[:, None] - dist)
+            mask = ~(same & (cyc < a))
+        r2 = np.where(mask, r2, 1.0)                 # dummy separation inside the window
+        S, D, Ds, T = special.kernels_diff(ka, kb, r2, nd, npd, nn)
+        out[li] += _lp_block(S, D, Ds, T, c.w[None, :]) * np.tile(mask, (2, 2))
+    # Alpert correction on each straight segment: the separation from node m
+    # to the point at parameter s is (w(s_m) - w(s))/(2 pi) times the chord,
+    # orthogonal to the (constant) normal
+    for sg in range(len(c.seg_n)):
+        n = int(c.seg_n[sg])
+        s0 = int(c.seg_start[sg])
+        L = np.hypot(c.vx[sg + 1] - c.vx[sg], c.vy[sg + 1] - c.vy[sg])
+        h = 2 * np.pi / n
+        m = np.arange(n)
+        sm = h * (m + 0.5)
+        wm, _ = kress_w(sm, c.q)
+        wcm = kress_wc(sm, c.q)
+        for sgn in (1.0, -1.0):
+            t = m[:, None] + sgn * chi[None, :]                  # local index units
+            sa = np.mod(h * (t + 0.5), 2 * np.pi)
+            wa, _ = kress_w(sa, c.q)
+            wca = kress_wc(sa, c.q)
+            # near the far corner both w round to 2 pi: use the complements
+            far = (sm[:, None] >= np.pi) & (sa >= np.pi)
+            dw = np.where(far, wca - wcm[:, None], wm[:, None] - wa) / (2 * np.pi) * L
+            zero = np.zeros_like(dw)
+            S, D, Ds, T = special.kernels_diff(ka, kb, dw * dw, zero, zero, zero + 1.0)
+            j0 = np.floor(t).astype(int) - (STENCIL // 2 - 1)
+            for q in range(STENCIL):
+                Jq = j0 + q
+                Lq = np.ones_like(t)
+                for r in range(STENCIL):
+                    if r != q:
+                        Lq = Lq * (t - (j0 + r)) / (q - r)
+                cols = s0 + np.mod(Jq, n)
+                coef = u[None, :] * Lq * c.w[cols]
+                rows = np.broadcast_to(s0 + m[:, None], t.shape)
+                for blk_r, blk_c, K in ((0, 0, D), (0, N, S), (N, 0, T), (N, N, Ds)):
+                    np.add.at(out, (1, blk_r + rows, blk_c + cols), K * coef)
+    out[1, :N, :N] -= np.eye(N)
+    out[1, N:, N:] += np.eye(N)
+    return out
 
 
 def pair_pieces(ct: Curve, cs: Curve, k: float) -> np.ndarray:

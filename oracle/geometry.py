@@ -124,6 +124,19 @@ def kress_w(s, q):
     return w, wp
 
 
+def kress_wc(s, q):
+    """2 pi - w(s), formed as 2 pi v(2 pi - s)^q/(v^q + v(2 pi - s)^q) so that it
+    keeps full relative accuracy near s = 2 pi, where w(s) rounds to 2 pi."""
+    s = np.asarray(s, dtype=float)
+
+    def v(t):
+        return (1.0 / q - 0.5) * ((np.pi - t) / np.pi) ** 3 + (t - np.pi) / (q * np.pi) + 0.5
+
+    A = v(s) ** q
+    B = v(2 * np.pi - s) ** q
+    return 2 * np.pi * B / (A + B)
+
+
 def make_curve(iface, d: float) -> Curve:
     if iface.kind == "fourier":
         N = int(iface.n_nodes)
@@ -146,16 +159,29 @@ def make_curve(iface, d: float) -> Curve:
         n = segn[c_]
         s = 2 * np.pi * (np.arange(n) + 0.5) / n
         wv, wpv = kress_w(s, iface.q)
+        wc = kress_wc(s, iface.q)
         dx, dy = vx[c_ + 1] - vx[c_], vy[c_ + 1] - vy[c_]
         L = np.hypot(dx, dy)
-        xs.append(vx[c_] + wv / (2 * np.pi) * dx)
-        ys.append(vy[c_] + wv / (2 * np.pi) * dy)
+        # each node is placed from its nearer corner, so that its (tiny)
+        # distance to that corner is not lost to rounding
+        first = s < np.pi
+        xs.append(np.where(first, vx[c_] + wv / (2 * np.pi) * dx, vx[c_ + 1] - wc / (2 * np.pi) * dx))
+        ys.append(np.where(first, vy[c_] + wv / (2 * np.pi) * dy, vy[c_ + 1] - wc / (2 * np.pi) * dy))
         nxs.append(np.full(n, dy / L))
         nys.append(np.full(n, -dx / L))
         ws.append(L / n * wpv)
         seg_of.append(np.full(n, c_))
     starts = np.concatenate([[0], np.cumsum(segn)[:-1]])
-    return Curve("polygon", int(segn.sum()), d, float(iface.y0), np.concatenate(xs), np.concatenate(ys),
+    X, Y = np.concatenate(xs), np.concatenate(ys)
+    # graded nodes of adjacent segments (also across x = +-d/2) must stay
+    # distinct in float64; with a very strong grading they round onto the corner
+    for l in (-1, 0, 1):
+        r2 = (X[:, None] - X[None, :] - l * d) ** 2 + (Y[:, None] - Y[None, :]) ** 2
+        if l == 0:
+            np.fill_diagonal(r2, 1.0)
+        if np.any(r2 == 0.0):
+            raise ValueError("graded nodes coincide in float64: lower q or the segment node counts")
+    return Curve("polygon", int(segn.sum()), d, float(iface.y0), X, Y,
                  np.concatenate(nxs), np.concatenate(nys), np.concatenate(ws),
                  seg_start=starts, seg_n=segn, seg_of=np.concatenate(seg_of), vx=vx, vy=vy, q=iface.q)
 

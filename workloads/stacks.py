@@ -189,10 +189,33 @@ def config3(seed: int = 3, I: int = 1000, n_angles: int = 100, N_smooth: int = 1
             continue
         vx, vy = _polygon(kind, y0, d, 0.3, 0)
         seglen = np.hypot(np.diff(vx), np.diff(vy))
-        nodes = np.maximum(8, np.round(N_corner * seglen / seglen.sum()).astype(np.int32))
+        nodes = np.maximum(40, np.round(N_corner * seglen / seglen.sum()).astype(np.int32))
         nodes[np.argmax(nodes)] += N_corner - int(nodes.sum())
         ifs.append(Interface("polygon", y0, vx=vx, vy=vy, seg_nodes=nodes.astype(np.int32), q=6.0))
     n = rng.uniform(1.0, 2.0, I + 1)
     thetas = -(np.pi / 2) * (np.arange(n_angles) + 0.5) / n_angles
     return Stack("config3", d, 10.0 * n, ifs, y_U=1.5, y_D=-1.5 * (I - 1) - 1.5, P=P, R=d,
                  M_w=M_w, M_ud=M_ud, K=K, thetas=thetas)
+
+
+def small_polygon_stack(flat: bool = False, nper: int = 60, q: float = 6.0, k=(8.0, 10.0, 11.0),
+                        P: int = 60, M_w: int = 40, M_ud: int = 40, K: int = 8,
+                        height: float = 0.08, theta: float = -np.pi / 5) -> Stack:
+    """Two cornered interfaces at d = 1: a triangle (2 segments, peak at x = 0)
+    over a triangle-on-a-flat (4 segments), ``nper`` graded nodes per segment.
+    ``flat=True`` puts every vertex at the interface's mean height, which gives
+    a planar stack carried on graded segments."""
+    d = 1.0
+    ifs = []
+    h = 0.0 if flat else height
+    for i, y0 in enumerate((0.0, -0.5)):
+        if i == 0:
+            vx = np.array([-d / 2, 0.0, d / 2])
+            vy = np.array([y0 - h, y0 + h, y0 - h])
+        else:
+            vx = np.array([-d / 2, -d / 6, 0.0, d / 6, d / 2])
+            vy = np.array([y0 - h, y0 - h, y0 + h, y0 - h, y0 - h])
+        ns = np.full(len(vx) - 1, nper, dtype=np.int32)
+        ifs.append(Interface("polygon", y0, vx=vx, vy=vy, seg_nodes=ns, q=q))
+    return Stack("small_polygon", d, np.array(k, dtype=float), ifs, y_U=0.5, y_D=-1.0, P=P, R=1.5 * d,
+                 M_w=M_w, M_ud=M_ud, K=K, thetas=np.array([theta]))
