@@ -53,7 +53,7 @@ enum {
   MLH_E_NOMEM = 3,       /* device allocation failed                         */
   MLH_E_DEVICE = 4,      /* a HIP call failed                                */
   MLH_E_SINGULAR = 5,    /* exact zero pivot in the block LU                 */
-  MLH_E_UNSUPPORTED = 7  /* interface kind not supported                     */
+  MLH_E_UNSUPPORTED = 7  /* sizes beyond this library's limits              */
 };
 
 typedef struct mlh_ctx_s* mlh_ctx;
@@ -66,8 +66,16 @@ enum { MLH_IFACE_FOURIER = 0, MLH_IFACE_POLYGON = 1 };
  *          + sin_coef[m-1] sin(2 pi m x/d), discretised by the periodic
  *          trapezoid rule with n_nodes nodes s_j = 2 pi (j - 1/2)/n_nodes.
  * POLYGON: the periodic broken line through (vx[c], vy[c]), c = 0..n_vert-1,
- *          vx[0] = -d/2, vx[n_vert-1] = d/2, vy[0] = vy[n_vert-1]; segment c
- *          carries seg_nodes[c] Kress-graded nodes (grading exponent q). */
+ *          vx[0] = -d/2, vx[n_vert-1] = d/2, vy[0] = vy[n_vert-1], vx
+ *          strictly increasing (a graph); vy and y0 are absolute heights, y0
+ *          being the nominal height that places the proxy circles.  Segment c
+ *          carries seg_nodes[c] >= 37 nodes of the Kress-graded trapezoid rule
+ *          s_j = 2 pi (j - 1/2)/n on Z(w(s)) with grading exponent q >= 2
+ *          (Sec. 2.5).  The singular self interaction is corrected per segment
+ *          (Alpert's rule, periodic in s, no Bloch phase); segments interact
+ *          through plain Nystrom entries.  A grading so strong that two nodes
+ *          coincide in float64 is rejected (MLH_E_INVALID_ARG).
+ * Both kinds: at most 304 nodes per interface (MLH_E_UNSUPPORTED beyond). */
 typedef struct {
   int32_t kind;
   double y0;

@@ -43,6 +43,8 @@ struct SelfJob {
   const double* nx;
   const double* ny;
   const double* w;
+  const int* seg_lo;   // cornered interface: first node of each node's segment
+  const int* seg_len;  //   and that segment's node count (null: smooth)
   double ka, kb, d;
   cplx* out[3];   // pieces l = -1, 0, 1 (n x n, ld = n)
   int N;
@@ -55,8 +57,11 @@ struct AlpertJob {
   const double* nd;
   const double* npd;
   const double* nn;
-  const double* cw;   // aux weight u_k h |Z'|
-  const double* t;    // aux position in node-index units
+  const double* cw;   // smooth: aux weight u_k h |Z'|; cornered: u_k
+  const double* t;    // aux position in node-index units (segment-local if cornered)
+  const int* seg_lo;  // cornered interface: segment of each node (null: smooth)
+  const int* seg_len;
+  const double* colw; // cornered interface: node weights w_j (interpolation of density x Jacobian)
   double ka, kb;
   cplx* out[3];
   int N;

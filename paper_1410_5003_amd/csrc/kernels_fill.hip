@@ -11,7 +11,12 @@
 //  alpert_kernel  the auxiliary-node correction inside the window (Sec. 2.5
 //                 and the Remark on the quasi-periodic wrap): one wavefront per
 //                 target row owns every corrected column of that row, so the
-//                 read-modify-write needs no atomics.
+//                 read-modify-write needs no atomics.  On a cornered interface
+//                 the window, the stencil and the correction stay inside the
+//                 target's graded segment (cyclic in the segment parameter, no
+//                 Bloch phase), and the interpolated quantity is the density
+//                 times the graded Jacobian, so the stencil weights multiply
+//                 the node weights w_j.
 #include "internal.hpp"
 
 namespace mlh {
@@ -87,10 +92,22 @@ __global__ __launch_bounds__(256) void self_kernel(const SelfJob* __restrict__ j
   const double nn = tnx * snx + tny * sny;
   const double w = J.w[j];
   const int ld = 2 * N;
+  // Alpert window: smooth curves exclude |J - m| < a over the extended index
+  // J = j + l N; a cornered curve excludes, in copy l = 0 only, the nodes of
+  // the target's own segment within cyclic segment-local distance a
+  bool same_seg = false;
+  int cyc = 0;
+  if (J.seg_lo) {
+    same_seg = J.seg_lo[j] == J.seg_lo[m];
+    const int len = J.seg_len[m];
+    const int dd = j >= m ? j - m : m - j;
+    cyc = dd < len - dd ? dd : len - dd;
+  }
   for (int l = -1; l <= 1; ++l) {
     const int off = j + l * N - m;
     cplx D = {0, 0}, S = {0, 0}, T = {0, 0}, Ds = {0, 0};
-    if (off >= a || off <= -a) {
+    const bool plain = J.seg_lo ? !(l == 0 && same_seg && cyc < a) : (off >= a || off <= -a);
+    if (plain) {
       const double dx = dx0 - l * J.d;
       const double r2 = dx * dx + dy * dy;
       const Kern4 K = lp_kernels_diff(J.ka, J.kb, r2, tnx * dx + tny * dy, snx * dx + sny * dy, nn);
@@ -124,6 +141,11 @@ __global__ __launch_bounds__(64) void alpert_kernel(const AlpertJob* __restrict_
   const AlpertJob& J = jobs[lo];
   const int m = blk - J.block_begin;
   const int N = J.N;
+  // cornered interface: work in the target's segment, cyclically, piece l = 0
+  const bool seg = J.seg_lo != nullptr;
+  const int s_lo = seg ? J.seg_lo[m] : 0;
+  const int s_len = seg ? J.seg_len[m] : N;
+  const int m_idx = seg ? m - s_lo : m;
   __shared__ cplx kv[kAlpertAux][4];
   __shared__ double tpos[kAlpertAux];
   const int lane = threadIdx.x;
@@ -140,7 +162,7 @@ __global__ __launch_bounds__(64) void alpert_kernel(const AlpertJob* __restrict_
   __syncthreads();
   const int half = a + 8;
   if (lane > 2 * half) return;
-  const int Jx = m - half + lane;  // extended column index
+  const int Jx = m_idx - half + lane;  // extended (or segment-local) column index
   cplx acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
   bool any = false;
   for (int q = 0; q < kAlpertAux; ++q) {
@@ -161,8 +183,20 @@ __global__ __launch_bounds__(64) void alpert_kernel(const AlpertJob* __restrict_
     }
   }
   if (!any) return;
-  const int l = (Jx >= 0) ? Jx / N : -((-Jx + N - 1) / N);
-  const int col = Jx - l * N;
+  int l, col;
+  if (seg) {  // 2 half + 1 <= s_len, so no two lanes share a column
+    l = 0;
+    col = s_lo + (Jx >= 0 ? Jx % s_len : (s_len - 1) - ((-Jx - 1) % s_len));
+    const double wc = J.colw[col];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      acc[e].re *= wc;
+      acc[e].im *= wc;
+    }
+  } else {
+    l = (Jx >= 0) ? Jx / N : -((-Jx + N - 1) / N);
+    col = Jx - l * N;
+  }
   cplx* o = J.out[l + 1];
   const int ld = 2 * N;
   const size_t idx[4] = {(size_t)col * ld + m, (size_t)(N + col) * ld + m, (size_t)col * ld + N + m,

@@ -122,11 +122,117 @@ struct FourierProfile {
 
 struct HostCurve {
   int N = 0;
+  bool cornered = false;
   double y0 = 0.0;
   FourierProfile prof;
+  std::vector<double> vx, vy;                            // cornered: vertices (absolute y)
   std::vector<double> x, y, nx, ny, w;                   // y relative to y0
+  std::vector<int> seg_lo, seg_len;                      // cornered: segment of each node
   std::vector<double> ar2, and_, anpd, ann, acw, at;     // Alpert aux invariants, N x 30
+
+  // absolute height of the interface at abscissa x in the unit cell
+  double height(double xx) const {
+    if (!cornered) return y0 + prof.f(xx);
+    size_t c = 0;
+    while (c + 2 < vx.size() && xx > vx[c + 1]) ++c;
+    const double t = (xx - vx[c]) / (vx[c + 1] - vx[c]);
+    return vy[c] + t * (vy[c + 1] - vy[c]);
+  }
 };
+
+// Kress grading (Sec. 2.5): w(s) = 2 pi v(s)^q/(v(s)^q + v(2 pi - s)^q).
+// Returns w, its complement 2 pi - w (formed from v(2 pi - s)^q so that it
+// keeps its relative accuracy near s = 2 pi) and w'.
+struct Kress {
+  double w, wc, wp;
+};
+Kress kress(double s, double q) {
+  auto v = [q](double t) {
+    const double u = (kPi - t) / kPi;
+    return (1.0 / q - 0.5) * u * u * u + (t - kPi) / (q * kPi) + 0.5;
+  };
+  auto vp = [q](double t) {
+    const double u = (kPi - t) / kPi;
+    return -(3.0 / kPi) * (1.0 / q - 0.5) * u * u + 1.0 / (q * kPi);
+  };
+  const double va = v(s), vb = v(2.0 * kPi - s);
+  const double A = std::pow(va, q), B = std::pow(vb, q);
+  const double Ap = q * std::pow(va, q - 1.0) * vp(s);
+  const double Bp = -q * std::pow(vb, q - 1.0) * vp(2.0 * kPi - s);
+  const double den = A + B;
+  return {2.0 * kPi * A / den, 2.0 * kPi * B / den, 2.0 * kPi * (Ap * B - A * Bp) / (den * den)};
+}
+
+// Cornered interface: straight segments between consecutive vertices, each
+// with its own Kress-graded trapezoid rule s_j = 2 pi (j - 1/2)/n (midpoints).
+// A node is placed from its nearer corner so that its distance to that corner
+// survives rounding.  The Alpert correction runs per segment, periodic in s
+// with no phase; on a straight segment the separation of two of its points is
+// (w(s_m) - w(s))/(2 pi) times the chord, orthogonal to the normal.
+void build_polygon_curve(const mlh_interface& in, HostCurve& c) {
+  c.cornered = true;
+  c.y0 = in.y0;
+  c.vx.assign(in.vx, in.vx + in.n_vert);
+  c.vy.assign(in.vy, in.vy + in.n_vert);
+  const int nseg = in.n_vert - 1;
+  int N = 0;
+  for (int g = 0; g < nseg; ++g) N += in.seg_nodes[g];
+  c.N = N;
+  c.x.resize(N);
+  c.y.resize(N);
+  c.nx.resize(N);
+  c.ny.resize(N);
+  c.w.resize(N);
+  c.seg_lo.resize(N);
+  c.seg_len.resize(N);
+  const size_t na = (size_t)N * kAlpertAux;
+  c.ar2.assign(na, 0.0);
+  c.and_.assign(na, 0.0);
+  c.anpd.assign(na, 0.0);
+  c.ann.assign(na, 1.0);
+  c.acw.resize(na);
+  c.at.resize(na);
+  const double q = in.q;
+  int lo = 0;
+  for (int g = 0; g < nseg; ++g) {
+    const int n = in.seg_nodes[g];
+    const double dx = c.vx[g + 1] - c.vx[g], dy = c.vy[g + 1] - c.vy[g];
+    const double L = std::hypot(dx, dy);
+    const double h = 2.0 * kPi / n;
+    for (int j = 0; j < n; ++j) {
+      const double sj = h * (j + 0.5);
+      const Kress K = kress(sj, q);
+      const int i = lo + j;
+      if (sj < kPi) {
+        c.x[i] = c.vx[g] + K.w / (2.0 * kPi) * dx;
+        c.y[i] = (c.vy[g] - c.y0) + K.w / (2.0 * kPi) * dy;
+      } else {
+        c.x[i] = c.vx[g + 1] - K.wc / (2.0 * kPi) * dx;
+        c.y[i] = (c.vy[g + 1] - c.y0) - K.wc / (2.0 * kPi) * dy;
+      }
+      c.nx[i] = dy / L;
+      c.ny[i] = -dx / L;
+      c.w[i] = L / n * K.wp;
+      c.seg_lo[i] = lo;
+      c.seg_len[i] = n;
+      for (int qa = 0; qa < kAlpertAux; ++qa) {
+        const int kq = qa % kAlpertJ;
+        const double sg = qa < kAlpertJ ? 1.0 : -1.0;
+        const double t = j + sg * kAlpertChi[kq];  // segment-local index units
+        double sa = std::fmod(h * (t + 0.5), 2.0 * kPi);
+        if (sa < 0) sa += 2.0 * kPi;
+        const Kress Ka = kress(sa, q);
+        const double dw = (sj >= kPi && sa >= kPi) ? Ka.wc - K.wc : K.w - Ka.w;
+        const double sep = dw / (2.0 * kPi) * L;
+        const size_t o = (size_t)i * kAlpertAux + qa;
+        c.ar2[o] = sep * sep;
+        c.acw[o] = kAlpertW[kq];
+        c.at[o] = t;
+      }
+    }
+    lo += n;
+  }
+}
 
 void build_fourier_curve(const mlh_interface& in, double d, HostCurve& c) {
   c.N = in.n_nodes;
@@ -215,6 +321,7 @@ struct mlh_stack_s {
   // device geometry
   std::vector<double*> gx, gy, gnx, gny, gw;
   std::vector<double*> ar2, and_, anpd, ann, acw, at;
+  std::vector<int*> seg_lo, seg_len;  // cornered interfaces only (else null)
   std::vector<double*> wall_x, wall_y;  // per layer, y relative to centre
   double* ud_x = nullptr;
   double* ud_y = nullptr;  // zeros
@@ -270,16 +377,35 @@ static mlh_status validate(const mlh_stack_desc* D) {
   const int nmax = kGjeMaxN / 2;
   for (int i = 0; i < D->I; ++i) {
     const mlh_interface& f = D->iface[i];
-    if (f.kind == MLH_IFACE_POLYGON)
-      return fail(MLH_E_UNSUPPORTED, "cornered (polygon) interfaces are not supported by this build");
-    if (f.kind != MLH_IFACE_FOURIER) return fail(MLH_E_INVALID_ARG, "unknown interface kind");
-    if (f.n_modes < 0 || (f.n_modes > 0 && (!f.cos_coef || !f.sin_coef)))
-      return fail(MLH_E_INVALID_ARG, "Fourier coefficients missing");
-    if (f.n_nodes < nmin)
-      return fail(MLH_E_INVALID_ARG, "each interface needs at least " + std::to_string(nmin) + " nodes");
-    if (f.n_nodes > nmax)
-      return fail(MLH_E_UNSUPPORTED, "at most " + std::to_string(nmax) + " nodes per interface are supported");
     if (!std::isfinite(f.y0)) return fail(MLH_E_INVALID_ARG, "non-finite y0");
+    int ntot = 0;
+    if (f.kind == MLH_IFACE_FOURIER) {
+      if (f.n_modes < 0 || (f.n_modes > 0 && (!f.cos_coef || !f.sin_coef)))
+        return fail(MLH_E_INVALID_ARG, "Fourier coefficients missing");
+      if (f.n_nodes < nmin)
+        return fail(MLH_E_INVALID_ARG, "each interface needs at least " + std::to_string(nmin) + " nodes");
+      ntot = f.n_nodes;
+    } else if (f.kind == MLH_IFACE_POLYGON) {
+      if (f.n_vert < 2 || !f.vx || !f.vy || !f.seg_nodes)
+        return fail(MLH_E_INVALID_ARG, "polygon interface needs n_vert >= 2, vx, vy and seg_nodes");
+      if (!(f.q >= 2.0) || !std::isfinite(f.q)) return fail(MLH_E_INVALID_ARG, "grading exponent q must be >= 2");
+      const double tol = 1e-12 * D->d;
+      if (std::fabs(f.vx[0] + 0.5 * D->d) > tol || std::fabs(f.vx[f.n_vert - 1] - 0.5 * D->d) > tol)
+        return fail(MLH_E_INVALID_ARG, "polygon must run from x = -d/2 to x = d/2");
+      if (!(std::fabs(f.vy[0] - f.vy[f.n_vert - 1]) <= tol))
+        return fail(MLH_E_INVALID_ARG, "polygon must be periodic: vy[0] == vy[n_vert-1]");
+      for (int c = 0; c + 1 < f.n_vert; ++c) {
+        if (!std::isfinite(f.vy[c]) || !(f.vx[c + 1] > f.vx[c]))
+          return fail(MLH_E_INVALID_ARG, "polygon vertices must have finite, strictly increasing x");
+        if (f.seg_nodes[c] < nmin)
+          return fail(MLH_E_INVALID_ARG, "each polygon segment needs at least " + std::to_string(nmin) + " nodes");
+        ntot += f.seg_nodes[c];
+      }
+    } else {
+      return fail(MLH_E_INVALID_ARG, "unknown interface kind");
+    }
+    if (ntot > nmax)
+      return fail(MLH_E_UNSUPPORTED, "at most " + std::to_string(nmax) + " nodes per interface are supported");
   }
   return MLH_OK;
 }
@@ -295,10 +421,14 @@ static mlh_status check_geometry(mlh_stack_s* s) {
     hi[i] = -1e300;
     for (int g = 0; g <= G; ++g) {
       const double x = -0.5 * s->d + s->d * g / G;
-      const double y = s->curves[i].y0 + s->curves[i].prof.f(x);
+      const double y = s->curves[i].height(x);
       prof[i][g] = y;
       lo[i] = std::min(lo[i], y);
       hi[i] = std::max(hi[i], y);
+    }
+    for (double vy : s->curves[i].vy) {  // corners between grid points
+      lo[i] = std::min(lo[i], vy);
+      hi[i] = std::max(hi[i], vy);
     }
   }
   for (int i = 0; i + 1 < s->I; ++i)
@@ -494,6 +624,8 @@ static void build_fill_tables(mlh_stack_s* s, std::vector<FillJob>& fj, std::vec
     S.nx = s->gnx[i];
     S.ny = s->gny[i];
     S.w = s->gw[i];
+    S.seg_lo = s->seg_lo[i];
+    S.seg_len = s->seg_len[i];
     S.ka = s->k[i];
     S.kb = s->k[i + 1];
     S.d = d;
@@ -511,6 +643,9 @@ static void build_fill_tables(mlh_stack_s* s, std::vector<FillJob>& fj, std::vec
     A.nn = s->ann[i];
     A.cw = s->acw[i];
     A.t = s->at[i];
+    A.seg_lo = s->seg_lo[i];
+    A.seg_len = s->seg_len[i];
+    A.colw = s->seg_lo[i] ? s->gw[i] : nullptr;
     A.ka = s->k[i];
     A.kb = s->k[i + 1];
     for (int l = 0; l < 3; ++l) A.out[l] = S.out[l];
@@ -556,9 +691,28 @@ extern "C" mlh_status mlh_stack_create(mlh_ctx ctx, const mlh_stack_desc* D, mlh
   s->N.resize(I);
   s->n.resize(I);
   for (int i = 0; i < I; ++i) {
-    build_fourier_curve(D->iface[i], s->d, s->curves[i]);
+    if (D->iface[i].kind == MLH_IFACE_POLYGON)
+      build_polygon_curve(D->iface[i], s->curves[i]);
+    else
+      build_fourier_curve(D->iface[i], s->d, s->curves[i]);
     s->N[i] = s->curves[i].N;
     s->n[i] = 2 * s->N[i];
+    // strongly graded nodes of adjacent segments (also across x = +-d/2)
+    // must stay distinct in float64
+    const HostCurve& c = s->curves[i];
+    if (c.cornered) {
+      for (int a = 0; a < c.N; ++a)
+        for (int b = 0; b < c.N; ++b)
+          for (int l = -1; l <= 1; ++l) {
+            if (l == 0 && a == b) continue;
+            const double ddx = c.x[a] - c.x[b] - l * s->d, ddy = c.y[a] - c.y[b];
+            if (ddx * ddx + ddy * ddy == 0.0) {
+              delete s;
+              return fail(MLH_E_INVALID_ARG, "graded nodes of interface " + std::to_string(i + 1) +
+                                                 " coincide in float64: lower q or the segment node counts");
+            }
+          }
+    }
   }
   // proxy circle centres: middle of each layer's nominal extent
   s->centre.resize(I + 1);
@@ -577,6 +731,9 @@ extern "C" mlh_status mlh_stack_create(mlh_ctx ctx, const mlh_stack_desc* D, mlh
   std::vector<size_t> o_geo(I), o_aux(I), o_wall(I + 1), o_prox(I + 1);
   for (int i = 0; i < I; ++i) o_geo[i] = ar.reserve(sizeof(double) * 5 * s->N[i]);
   for (int i = 0; i < I; ++i) o_aux[i] = ar.reserve(sizeof(double) * 6 * (size_t)s->N[i] * kAlpertAux);
+  std::vector<size_t> o_seg(I, 0);
+  for (int i = 0; i < I; ++i)
+    if (s->curves[i].cornered) o_seg[i] = ar.reserve(sizeof(int) * 2 * s->N[i]);
   for (int j = 0; j <= I; ++j) o_wall[j] = ar.reserve(sizeof(double) * 2 * s->Mw);
   const size_t o_ud = ar.reserve(sizeof(double) * 2 * s->Mud);
   for (int j = 0; j <= I; ++j) o_prox[j] = ar.reserve(sizeof(double) * 4 * s->P);
@@ -627,6 +784,8 @@ extern "C" mlh_status mlh_stack_create(mlh_ctx ctx, const mlh_stack_desc* D, mlh
   s->ann.resize(I);
   s->acw.resize(I);
   s->at.resize(I);
+  s->seg_lo.assign(I, nullptr);
+  s->seg_len.assign(I, nullptr);
   std::vector<double> hbuf;
   hipStream_t st = ctx->stream;
   for (int i = 0; i < I; ++i) {
@@ -652,6 +811,14 @@ extern "C" mlh_status mlh_stack_create(mlh_ctx ctx, const mlh_stack_desc* D, mlh
     hbuf.clear();
     for (auto* v : {&c.ar2, &c.and_, &c.anpd, &c.ann, &c.acw, &c.at}) hbuf.insert(hbuf.end(), v->begin(), v->end());
     HIP_TRY(hipMemcpy(a, hbuf.data(), hbuf.size() * sizeof(double), hipMemcpyHostToDevice));
+    if (c.cornered) {
+      int* sg = reinterpret_cast<int*>(b + o_seg[i]);
+      s->seg_lo[i] = sg;
+      s->seg_len[i] = sg + N;
+      std::vector<int> ib(c.seg_lo);
+      ib.insert(ib.end(), c.seg_len.begin(), c.seg_len.end());
+      HIP_TRY(hipMemcpy(sg, ib.data(), ib.size() * sizeof(int), hipMemcpyHostToDevice));
+    }
   }
   // walls: M_w Gauss-Legendre nodes on x = -d/2 between the layer's boundaries
   std::vector<double> gl_t(s->Mw), gl_w(s->Mw);
@@ -681,8 +848,8 @@ extern "C" mlh_status mlh_stack_create(mlh_ctx ctx, const mlh_stack_desc* D, mlh
   s->wall_x.resize(I + 1);
   s->wall_y.resize(I + 1);
   for (int j = 0; j <= I; ++j) {
-    const double top = j == 0 ? s->yU : s->curves[j - 1].y0 + s->curves[j - 1].prof.f(-0.5 * s->d);
-    const double bot = j == I ? s->yD : s->curves[j].y0 + s->curves[j].prof.f(-0.5 * s->d);
+    const double top = j == 0 ? s->yU : s->curves[j - 1].height(-0.5 * s->d);
+    const double bot = j == I ? s->yD : s->curves[j].height(-0.5 * s->d);
     hbuf.assign(2 * s->Mw, -0.5 * s->d);
     for (int m = 0; m < s->Mw; ++m) hbuf[s->Mw + m] = bot + (top - bot) * 0.5 * (gl_t[m] + 1.0) - s->centre[j];
     double* w = dp(o_wall[j]);

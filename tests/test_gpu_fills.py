@@ -66,3 +66,17 @@ def test_fill_pieces_small_ragged(ctx):
 
 def test_fill_pieces_config2_head(ctx):
     _compare_all(ctx, workloads.config2(I=4))
+
+
+def test_fill_pieces_cornered(ctx):
+    # graded segments: per-segment Alpert window, plain entries across corners
+    _compare_all(ctx, workloads.small_polygon_stack(nper=40))
+
+
+def test_fill_pieces_mixed_uneven(ctx):
+    _compare_all(ctx, workloads.small_mixed_stack(min_seg=40))
+
+
+def test_fill_pieces_config3_head(ctx):
+    # 120-node smooth and 250-node cornered interfaces at d = 2 pi
+    _compare_all(ctx, workloads.config3(I=4, n_angles=1))

@@ -219,3 +219,34 @@ def small_polygon_stack(flat: bool = False, nper: int = 60, q: float = 6.0, k=(8
         ifs.append(Interface("polygon", y0, vx=vx, vy=vy, seg_nodes=ns, q=q))
     return Stack("small_polygon", d, np.array(k, dtype=float), ifs, y_U=0.5, y_D=-1.0, P=P, R=1.5 * d,
                  M_w=M_w, M_ud=M_ud, K=K, thetas=np.array([theta]))
+
+
+def small_mixed_stack(seed: int = 7, I: int = 4, N_smooth: int = 72, seg_scale: int = 60,
+                      P: int = 60, M_w: int = 40, M_ud: int = 40, K: int = 8, d: float = 1.0,
+                      omega: float = 8.0, spacing: float = 0.5, peak: float = 0.08,
+                      q: float = 6.0, theta: float = -np.pi / 5, min_seg: int = 40) -> Stack:
+    """Paper-scale (d = 1) stack alternating smooth random-Fourier interfaces
+    (N_smooth nodes) and cornered ones (triangle, trapezoid, triangle on a
+    flat; about ``seg_scale`` graded nodes per unit of d along each segment,
+    at least ``min_seg`` per segment): uneven node counts across the interfaces.
+
+    Draw order: per interface, 3 cos then 3 sin N(0,1) coefficients, one
+    shape index; then I+1 uniforms for the layer indices."""
+    rng = np.random.default_rng(seed)
+    kinds = ("triangle", "trapezoid", "tri_on_flat")
+    ifs = []
+    for i in range(I):
+        y0 = -spacing * i
+        a, b = _scaled_fourier(rng, d, 3, peak)
+        kind = kinds[int(rng.integers(0, 3))]
+        if i % 2 == 0:
+            ifs.append(Interface("fourier", y0, n_nodes=N_smooth, cos_coef=a, sin_coef=b))
+            continue
+        vx, vy = _polygon(kind, y0, d, peak, 0)
+        seglen = np.hypot(np.diff(vx), np.diff(vy))
+        nodes = np.maximum(min_seg, np.round(seg_scale * seglen / d).astype(np.int32))
+        ifs.append(Interface("polygon", y0, vx=vx, vy=vy, seg_nodes=nodes.astype(np.int32), q=q))
+    n = rng.uniform(1.0, 1.5, I + 1)
+    n[0] = 1.0
+    return Stack("small_mixed", d, omega * n, ifs, y_U=spacing, y_D=-spacing * I,
+                 P=P, R=1.5 * d, M_w=M_w, M_ud=M_ud, K=K, thetas=np.array([theta]))
