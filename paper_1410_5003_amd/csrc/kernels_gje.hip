@@ -8,11 +8,12 @@
 //
 // Panel step k (columns k..k+NB-1), for every matrix of the batch:
 //   gje_panel_kernel   one workgroup: LU with partial pivoting of the tall
-//                      panel rows k..n-1 held in registers; writes the NB pivot rows, the
-//                      inverse M1 of the NB x NB pivot block, and the
-//                      multipliers P of rows >= k (L21 U11, the pivoted
-//                      original panel values; zero on the pivot rows).  Rows
-//                      above k use their current panel values, read from W;
+//                      panel rows k..n-1 held in registers; writes the row
+//                      interchanges, applies them to the panel columns of W
+//                      and writes the inverse M1 of the NB x NB pivot block.
+//                      The multipliers of the update are the panel values
+//                      themselves (original values for rows >= k, current
+//                      values above k), read from W;
 //   gje_update_kernel  one workgroup per 32 trailing columns: applies the row
 //                      swaps, Z = M1 Y(pivot rows), Y(other rows) -= P Z on the
 //                      FP64 matrix cores, Y(pivot rows) = Z.
@@ -33,11 +34,131 @@ __device__ inline double2 cinv2(double2 a) {
 }
 
 // Panel kernel: the (n - k) x NB tall panel lives in registers, thread t owning
-// local rows t and t + 512 (n <= 608).
+// local rows t and t + 512 (n <= 608).  Rows are not moved while the panel is
+// factored: a row that wins the pivot search for column c is marked done and
+// broadcast through LDS, so each column costs one workgroup barrier.  Every
+// wave reduces its candidates to one 64-bit key (high word of |a|^2, then the
+// complemented row index, so that ties go to the lowest row) with DPP moves,
+// and its winning lane stages its row in LDS next to the key.
 constexpr int kPanelThreads = 512;
 constexpr int kUpdThreads = 1024;
 constexpr int kUpdWaves = kUpdThreads / 64;
 constexpr int kPanelSlots = (kGjeMaxN + kPanelThreads - 1) / kPanelThreads;
+constexpr int kPanelWaves = kPanelThreads / 64;
+
+template <int CTRL, int ROWS>
+__device__ inline uint64_t key_max_dpp(uint64_t x) {
+  const int lo = (int)(uint32_t)x, hi = (int)(uint32_t)(x >> 32);
+  const uint32_t lo2 = (uint32_t)__builtin_amdgcn_update_dpp(0, lo, CTRL, ROWS, 0xf, true);
+  const uint32_t hi2 = (uint32_t)__builtin_amdgcn_update_dpp(0, hi, CTRL, ROWS, 0xf, true);
+  const uint64_t y = ((uint64_t)hi2 << 32) | lo2;
+  return y > x ? y : x;
+}
+
+// maximum of x over the wavefront, returned in every lane
+__device__ inline uint64_t wave_key_max(uint64_t x) {
+  x = key_max_dpp<0x111, 0xf>(x);  // row_shr:1
+  x = key_max_dpp<0x112, 0xf>(x);  // row_shr:2
+  x = key_max_dpp<0x114, 0xf>(x);  // row_shr:4
+  x = key_max_dpp<0x118, 0xf>(x);  // row_shr:8  -> lane 15 of each row: row maximum
+  x = key_max_dpp<0x142, 0xa>(x);  // row_bcast:15 into rows 1, 3
+  x = key_max_dpp<0x143, 0xc>(x);  // row_bcast:31 into rows 2, 3 -> lane 63: wave maximum
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, 63);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), 63);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ inline uint64_t pivot_key(double2 v, int lr) {
+  const double m2 = v.x * v.x + v.y * v.y;
+  const uint64_t hi = (uint64_t)(__double_as_longlong(m2)) >> 32;  // monotone for m2 >= 0
+  return (hi << 32) | (uint64_t)(0xffffffffu - (uint32_t)lr);
+}
+
+// state of one panel factorisation shared by the per-column steps
+struct PanelState {
+  double2 a[kPanelSlots][kGjeNb];
+  int pidx[kPanelSlots];  // pivot order of the row, -1 while still eligible
+  int singular;
+};
+
+struct PanelShared {
+  uint64_t key[2][kPanelWaves];
+  double2 row[2][kPanelWaves][kGjeNb];
+  int spiv[kGjeNb];
+};
+
+// one column of the panel LU; C is a template parameter so that every
+// register index is static
+template <int C>
+__device__ __forceinline__ void panel_column(PanelState& st, PanelShared& sh, int nb, int k, int tid) {
+  if (C >= nb) return;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int buf = C & 1;
+  uint64_t best = 0;
+#pragma unroll
+  for (int sl = 0; sl < kPanelSlots; ++sl) {
+    const uint64_t key = st.pidx[sl] < 0 ? pivot_key(st.a[sl][C], tid + sl * kPanelThreads) : 0;
+    best = key > best ? key : best;
+  }
+  const uint64_t wbest = wave_key_max(best);
+  if (lane == 0) sh.key[buf][wave] = wbest;
+  if (wbest != 0 && best == wbest) {  // this lane holds the wave's candidate row
+    const int sl = (int)(0xffffffffu - (uint32_t)wbest) / kPanelThreads;
+#pragma unroll
+    for (int s2 = 0; s2 < kPanelSlots; ++s2)
+      if (s2 == sl)
+#pragma unroll
+        for (int j = 0; j < kGjeNb; ++j) sh.row[buf][wave][j] = st.a[s2][j];
+  }
+  __syncthreads();
+  uint64_t kb = sh.key[buf][0];
+  int wb = 0;
+#pragma unroll
+  for (int w = 1; w < kPanelWaves; ++w) {
+    const uint64_t kw = sh.key[buf][w];
+    if (kw > kb) {
+      kb = kw;
+      wb = w;
+    }
+  }
+  const int p = (int)(0xffffffffu - (uint32_t)kb);
+  if ((kb >> 32) == 0 && st.singular == 0) st.singular = k + C + 1;
+  if (tid == 0) sh.spiv[C] = p;
+  const double2 ucc = sh.row[buf][wb][C];
+  const bool ok = (ucc.x != 0.0 || ucc.y != 0.0);
+  const double2 ip = ok ? cinv2(ucc) : make_double2(0.0, 0.0);
+  double2 prow[kGjeNb];
+#pragma unroll
+  for (int j = C + 1; j < kGjeNb; ++j) prow[j] = sh.row[buf][wb][j];
+#pragma unroll
+  for (int sl = 0; sl < kPanelSlots; ++sl) {
+    const int lr = tid + sl * kPanelThreads;
+    if (lr == p) {
+      st.pidx[sl] = C;
+    } else if (st.pidx[sl] < 0) {
+      const double2 l = cmul2(st.a[sl][C], ip);
+      st.a[sl][C] = l;
+#pragma unroll
+      for (int j = C + 1; j < kGjeNb; ++j) {
+        const double2 t = cmul2(l, prow[j]);
+        st.a[sl][j].x -= t.x;
+        st.a[sl][j].y -= t.y;
+      }
+    }
+  }
+}
+
+template <int C>
+struct PanelColumns {
+  static __device__ __forceinline__ void run(PanelState& st, PanelShared& sh, int nb, int k, int tid) {
+    panel_column<C>(st, sh, nb, k, tid);
+    PanelColumns<C + 1>::run(st, sh, nb, k, tid);
+  }
+};
+template <>
+struct PanelColumns<kGjeNb> {
+  static __device__ __forceinline__ void run(PanelState&, PanelShared&, int, int, int) {}
+};
 
 __global__ __launch_bounds__(kPanelThreads) void gje_panel_kernel(const GjeDesc* __restrict__ descs, int k) {
   const GjeDesc& D = descs[blockIdx.x];
@@ -45,199 +166,120 @@ __global__ __launch_bounds__(kPanelThreads) void gje_panel_kernel(const GjeDesc*
   if (k >= n) return;
   const int nb = min(kGjeNb, n - k);
   const int L = n - k;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x;
   cplx* W = D.W;
-  __shared__ double bval[kPanelThreads / 64];
-  __shared__ int bidx[kPanelThreads / 64];
-  __shared__ double2 rowc[kGjeNb], rowp[kGjeNb];
-  __shared__ int spiv[kGjeNb];
+  __shared__ PanelShared sh;
   __shared__ double2 lu11[kGjeNb][kGjeNb + 1];
-  double2 a[kPanelSlots][kGjeNb];
+  __shared__ int sdst[2 * kGjeNb], ssrc[2 * kGjeNb], snaff;
+  __shared__ double2 stage[2 * kGjeNb][kGjeNb];
+  PanelState st;
+  st.singular = 0;
 #pragma unroll
   for (int sl = 0; sl < kPanelSlots; ++sl) {
     const int lr = tid + sl * kPanelThreads;
+    st.pidx[sl] = lr < L ? -1 : kGjeNb;
 #pragma unroll
     for (int j = 0; j < kGjeNb; ++j)
-      a[sl][j] = (lr < L && j < nb) ? gld(W + (size_t)(k + j) * n + k + lr) : make_double2(0.0, 0.0);
+      st.a[sl][j] = (lr < L && j < nb) ? gld(W + (size_t)(k + j) * n + k + lr) : make_double2(0.0, 0.0);
   }
-  int singular = 0;
-  for (int c = 0; c < nb; ++c) {
-    double best = -1.0;
-    int bi = c;
-#pragma unroll
-    for (int sl = 0; sl < kPanelSlots; ++sl) {
-      const int lr = tid + sl * kPanelThreads;
-      double2 v = make_double2(0.0, 0.0);
-#pragma unroll
-      for (int j = 0; j < kGjeNb; ++j)
-        if (j == c) v = a[sl][j];
-      const double m2 = v.x * v.x + v.y * v.y;
-      if (lr >= c && lr < L && m2 > best) {
-        best = m2;
-        bi = lr;
-      }
-    }
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) {
-      const double ob = __shfl_xor(best, o, 64);
-      const int oi = __shfl_xor(bi, o, 64);
-      if (ob > best || (ob == best && oi < bi)) {
-        best = ob;
-        bi = oi;
-      }
-    }
-    if (lane == 0) {
-      bval[wave] = best;
-      bidx[wave] = bi;
-    }
-    __syncthreads();
-    double b = bval[0];
-    int p = bidx[0];
-#pragma unroll
-    for (int w = 1; w < kPanelThreads / 64; ++w)
-      if (bval[w] > b || (bval[w] == b && bidx[w] < p)) {
-        b = bval[w];
-        p = bidx[w];
-      }
-    if (tid == 0) spiv[c] = k + p;
-    if (b <= 0.0 && singular == 0) singular = k + c + 1;
-    // exchange rows c and p through LDS
-    const int owner_p = p % kPanelThreads, slot_p = p / kPanelThreads;
-    if (tid == c) {
-#pragma unroll
-      for (int j = 0; j < kGjeNb; ++j) rowc[j] = a[0][j];
-    }
-    if (tid == owner_p) {
-#pragma unroll
-      for (int sl = 0; sl < kPanelSlots; ++sl)
-        if (sl == slot_p)
-#pragma unroll
-          for (int j = 0; j < kGjeNb; ++j) rowp[j] = a[sl][j];
-    }
-    __syncthreads();
-    if (tid == owner_p) {
-#pragma unroll
-      for (int sl = 0; sl < kPanelSlots; ++sl)
-        if (sl == slot_p)
-#pragma unroll
-          for (int j = 0; j < kGjeNb; ++j) a[sl][j] = rowc[j];
-    }
-    if (tid == c) {
-#pragma unroll
-      for (int j = 0; j < kGjeNb; ++j) a[0][j] = rowp[j];
-    }
-    // eliminate below the pivot with the new pivot row (= old row p, in LDS)
-    const double2 ucc = rowp[c];
-    const bool ok = (ucc.x != 0.0 || ucc.y != 0.0);
-    const double2 ip = ok ? cinv2(ucc) : make_double2(0.0, 0.0);
-#pragma unroll
-    for (int sl = 0; sl < kPanelSlots; ++sl) {
-      const int lr = tid + sl * kPanelThreads;
-      if (lr > c && lr < L) {
-        double2 l = make_double2(0.0, 0.0);
-#pragma unroll
-        for (int j = 0; j < kGjeNb; ++j)
-          if (j == c) l = cmul2(a[sl][j], ip);
-#pragma unroll
-        for (int j = 0; j < kGjeNb; ++j) {
-          if (j == c) a[sl][j] = l;
-          if (j > c) {
-            const double2 t = cmul2(l, rowp[j]);
-            a[sl][j].x -= t.x;
-            a[sl][j].y -= t.y;
-          }
-        }
-      }
-    }
-  }
+  PanelColumns<0>::run(st, sh, nb, k, tid);
+  const int singular = st.singular;
+  int* spiv = sh.spiv;
+  double2 (&a)[kPanelSlots][kGjeNb] = st.a;
+  int (&pidx)[kPanelSlots] = st.pidx;
   if (tid == 0 && singular != 0) atomicCAS(D.info, 0, singular);
-  // compose the NB row interchanges into (destination, source) pairs for the
-  // update kernel: piv[0] = count, piv[1..] destinations, piv[1+2NB..] sources
+  // the factored pivot block: row of pivot c holds L11 (j < c) and U11 (j >= c)
+#pragma unroll
+  for (int sl = 0; sl < kPanelSlots; ++sl)
+    if (pidx[sl] >= 0 && pidx[sl] < kGjeNb)
+#pragma unroll
+      for (int j = 0; j < kGjeNb; ++j) lu11[pidx[sl]][j] = a[sl][j];
+  if (tid >= nb && tid < kGjeNb)
+#pragma unroll
+    for (int j = 0; j < kGjeNb; ++j) lu11[tid][j] = make_double2(0.0, 0.0);
+  // the row permutation of this step as (destination, source) pairs of
+  // global rows: pivot q (local row spiv[q], never moved in registers) goes
+  // to position q; rows of positions 0..nb-1 that were not chosen fill the
+  // positions the chosen rows vacated below the block.  piv[0] = count,
+  // piv[1..] destinations, piv[1+2NB..] sources.
+  __syncthreads();
   if (tid == 0) {
-    int rows[2 * kGjeNb], from[2 * kGjeNb], na = 0;
+    int na = 0;
+    bool chosen[kGjeNb];
+    for (int q = 0; q < kGjeNb; ++q) chosen[q] = false;
+    for (int q = 0; q < nb; ++q)
+      if (spiv[q] < nb) chosen[spiv[q]] = true;
+    int nxt = 0;  // next pivot row from below the block, in pivot order
     for (int q = 0; q < nb; ++q) {
-      const int r1 = k + q, r2 = spiv[q];
-      if (r1 == r2) continue;
-      int i1 = -1, i2 = -1;
-      for (int t = 0; t < na; ++t) {
-        if (rows[t] == r1) i1 = t;
-        if (rows[t] == r2) i2 = t;
+      if (spiv[q] != q) {
+        sdst[na] = k + q;
+        ssrc[na] = k + spiv[q];
+        ++na;
       }
-      if (i1 < 0) {
-        rows[na] = r1;
-        from[na] = r1;
-        i1 = na++;
+      if (!chosen[q]) {  // row at position q was displaced: send it below
+        while (spiv[nxt] < nb) ++nxt;
+        sdst[na] = k + spiv[nxt];
+        ssrc[na] = k + q;
+        ++na;
+        ++nxt;
       }
-      if (i2 < 0) {
-        rows[na] = r2;
-        from[na] = r2;
-        i2 = na++;
-      }
-      const int t = from[i1];
-      from[i1] = from[i2];
-      from[i2] = t;
     }
     D.piv[0] = na;
+    snaff = na;
     for (int t = 0; t < na; ++t) {
-      D.piv[1 + t] = rows[t];
-      D.piv[1 + 2 * kGjeNb + t] = from[t];
+      D.piv[1 + t] = sdst[t];
+      D.piv[1 + 2 * kGjeNb + t] = ssrc[t];
     }
-  }
-  // the pivot block L11\U11 sits in rows 0..nb-1 (threads 0..nb-1, slot 0)
-  if (tid < kGjeNb) {
-#pragma unroll
-    for (int j = 0; j < kGjeNb; ++j) lu11[tid][j] = (tid < nb) ? a[0][j] : make_double2(0.0, 0.0);
   }
   __syncthreads();
-  // multipliers of the rows below the pivot block: P = L21 U11
-#pragma unroll
-  for (int sl = 0; sl < kPanelSlots; ++sl) {
-    const int lr = tid + sl * kPanelThreads;
-    if (lr < L) {
-#pragma unroll
-      for (int j = 0; j < kGjeNb; ++j) {
-        double2 v = make_double2(0.0, 0.0);
-        if (lr >= nb && j < nb) {
-#pragma unroll
-          for (int q = 0; q <= j; ++q) {
-            const double2 t = cmul2(a[sl][q], lu11[q][j]);
-            v.x += t.x;
-            v.y += t.y;
-          }
-        }
-        gst(D.P + (size_t)j * n + k + lr, v);
-      }
-    }
+  // apply the interchanges to the panel columns of W, which still hold the
+  // values the panel started from: the update kernel reads its multipliers
+  // (original values of the rows below the pivot block) from there
+  const int naff = snaff;
+  for (int e = tid; e < naff * kGjeNb; e += kPanelThreads) {
+    const int t = e % naff, j = e / naff;
+    stage[t][j] = j < nb ? gld(W + (size_t)(k + j) * n + ssrc[t]) : make_double2(0.0, 0.0);
   }
-  // M1 = (L11 U11)^{-1}, one thread per column, the column in registers
-  // (fully unrolled so that only the 16 x 16 factors are read from LDS)
+  __syncthreads();
+  for (int e = tid; e < naff * kGjeNb; e += kPanelThreads) {
+    const int t = e % naff, j = e / naff;
+    if (j < nb) gst(W + (size_t)(k + j) * n + sdst[t], stage[t][j]);
+  }
+  // M1 = (L11 U11)^{-1}, one thread per column; each row of the factors is
+  // fetched from LDS in one batch before it is used
   if (tid < kGjeNb) {
     double2 x[kGjeNb];
 #pragma unroll
     for (int r = 0; r < kGjeNb; ++r) x[r] = make_double2(r == tid ? 1.0 : 0.0, 0.0);
 #pragma unroll
-    for (int r = 1; r < kGjeNb; ++r)
+    for (int r = 1; r < kGjeNb; ++r) {
+      double2 lr_[kGjeNb];
+#pragma unroll
+      for (int q = 0; q < r; ++q) lr_[q] = lu11[r][q];
 #pragma unroll
       for (int q = 0; q < r; ++q) {
-        const double2 t = cmul2(lu11[r][q], x[q]);
+        const double2 t = cmul2(lr_[q], x[q]);
         x[r].x -= t.x;
         x[r].y -= t.y;
       }
+    }
 #pragma unroll
     for (int r = kGjeNb - 1; r >= 0; --r) {
+      double2 ur[kGjeNb];
+#pragma unroll
+      for (int q = r; q < kGjeNb; ++q) ur[q] = lu11[r][q];
 #pragma unroll
       for (int q = r + 1; q < kGjeNb; ++q) {
-        const double2 t = cmul2(lu11[r][q], x[q]);
+        const double2 t = cmul2(ur[q], x[q]);
         x[r].x -= t.x;
         x[r].y -= t.y;
       }
-      const double2 d = lu11[r][r];
+      const double2 d = ur[r];
       x[r] = (r < nb && (d.x != 0.0 || d.y != 0.0)) ? cmul2(x[r], cinv2(d)) : make_double2(0.0, 0.0);
     }
 #pragma unroll
     for (int r = 0; r < kGjeNb; ++r) gst(D.M1 + (size_t)tid * kGjeNb + r, (tid < nb) ? x[r] : make_double2(0.0, 0.0));
   }
-
 }
 
 __global__ __launch_bounds__(kUpdThreads) void gje_update_kernel(const GjeDesc* __restrict__ descs, int k) {
@@ -303,12 +345,11 @@ __global__ __launch_bounds__(kUpdThreads) void gje_update_kernel(const GjeDesc* 
       dvec4 accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
 #pragma unroll
       for (int kk = 0; kk < kGjeNb; kk += 4) {
+        // multipliers: the panel columns of W (rows below k: current values;
+        // rows below the pivot block: their original values, already
+        // interchanged by the panel kernel; pivot rows are masked below)
         const int row = r0 + (lane & 15), kq = kk + (lane >> 4);
-        double2 a = make_double2(0.0, 0.0);
-        if (row < k)
-          a = kq < nb ? gld(W + (size_t)(k + kq) * n + row) : make_double2(0.0, 0.0);
-        else if (row < n)
-          a = gld(D.P + (size_t)kq * n + row);
+        const double2 a = (row < n && kq < nb) ? gld(W + (size_t)(k + kq) * n + row) : make_double2(0.0, 0.0);
         const double br = zr[kq][cb * 16 + (lane & 15)], bi = zi[kq][cb * 16 + (lane & 15)];
         accr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, br, accr, 0, 0, 0);
         accr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, bi, accr, 0, 0, 0);
