@@ -117,6 +117,7 @@ namespace mlh {
 // per-angle radiation rows, right-hand side and Bragg/flux extraction
 struct AngleDesc {
   double theta;
+  int owner;      // first angle of its system: writes the shared W rows
   cplx* S0;       // layer-1 stacked LS matrix (W_U goes at rows 2 M_w.., cols P..)
   cplx* SI;       // layer-(I+1) stacked LS matrix (W_D)
   int ldS0, ldSI;
@@ -153,13 +154,16 @@ namespace mlh {
 
 // Blocked Gauss-Jordan solve with partial pivoting of W = [A | B] (n x ncol,
 // column-major, ld = n): after all panels W[:, n:] = A^{-1} B.
+// two incident angles share a system when their kappa_0 d/(2 pi) agree modulo
+// 1 to this tolerance (alpha = exp(i kappa_0 d) then agrees to about 1e-11)
+constexpr double kAlphaTol = 1e-12;
+
 constexpr int kGjeNb = 16;  // panel width
 constexpr int kGjeCols = 32;  // trailing columns per update workgroup
 constexpr int kGjeMaxN = 608; // largest block order whose panel fits in LDS (N_i <= 304)
 
 struct GjeDesc {
   cplx* W;
-  cplx* P;    // scratch n x kGjeNb: panel multipliers of the current step
   cplx* M1;   // scratch kGjeNb x kGjeNb: inverse of the pivot block
   int* piv;   // scratch 1 + 4 kGjeNb ints: the current step's row interchanges
   int* info;  // set to (global column + 1) on an exactly zero pivot
@@ -167,20 +171,22 @@ struct GjeDesc {
 };
 
 // y = g - U1 x1 - U2 x2 (back substitution of the cyclic reduction, batched)
+// Y = G - U1 X1 - U2 X2 with r right-hand-side columns (ld n for G and Y,
+// m1 for X1, m2 for X2)
 struct GemvDesc {
   const cplx* U1;  // n x m1, ld n
   const cplx* U2;  // n x m2, ld n
-  const cplx* g;   // n
-  const cplx* x1;  // m1
-  const cplx* x2;  // m2
-  cplx* y;         // n
-  int n, m1, m2;
+  const cplx* g;   // n x r
+  const cplx* x1;  // m1 x r
+  const cplx* x2;  // m2 x r
+  cplx* y;         // n x r
+  int n, m1, m2, r;
 };
 
 void gje_init();
 void launch_gje_panel(const GjeDesc* d, int nbatch, int k, int max_n, hipStream_t st);
 void launch_gje_update(const GjeDesc* d, int nbatch, int k, int max_ncol, hipStream_t st);
-void launch_gemv_step(const GemvDesc* d, int nbatch, int max_n, hipStream_t st);
+void launch_gemv_step(const GemvDesc* d, int nbatch, int max_n, int max_r, hipStream_t st);
 
 }  // namespace mlh
 

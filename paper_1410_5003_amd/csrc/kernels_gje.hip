@@ -379,21 +379,26 @@ __global__ __launch_bounds__(kUpdThreads) void gje_update_kernel(const GjeDesc* 
   }
 }
 
-// y = g - U1 x1 - U2 x2, one workgroup per 64 rows, four wavefronts split the columns
+// y = g - U1 x1 - U2 x2 for right-hand-side column blockIdx.z, one workgroup
+// per 64 rows, four wavefronts split the columns of U1, U2
 __global__ __launch_bounds__(256) void gemv_step_kernel(const GemvDesc* __restrict__ descs) {
   const GemvDesc& D = descs[blockIdx.y];
+  const int rc = blockIdx.z;
+  if (rc >= D.r) return;
   const int row = blockIdx.x * 64 + (threadIdx.x & 63);
   const int wave = threadIdx.x >> 6;
+  const cplx* x1 = D.x1 + (size_t)rc * D.m1;
+  const cplx* x2 = D.x2 + (size_t)rc * D.m2;
   __shared__ double2 part[4][64];
   double2 acc = make_double2(0.0, 0.0);
   if (row < D.n) {
     for (int j = wave; j < D.m1; j += 4) {
-      const double2 u = gld(D.U1 + (size_t)j * D.n + row), x = gld(D.x1 + j);
+      const double2 u = gld(D.U1 + (size_t)j * D.n + row), x = gld(x1 + j);
       acc.x += u.x * x.x - u.y * x.y;
       acc.y += u.x * x.y + u.y * x.x;
     }
     for (int j = wave; j < D.m2; j += 4) {
-      const double2 u = gld(D.U2 + (size_t)j * D.n + row), x = gld(D.x2 + j);
+      const double2 u = gld(D.U2 + (size_t)j * D.n + row), x = gld(x2 + j);
       acc.x += u.x * x.x - u.y * x.y;
       acc.y += u.x * x.y + u.y * x.x;
     }
@@ -401,12 +406,12 @@ __global__ __launch_bounds__(256) void gemv_step_kernel(const GemvDesc* __restri
   part[wave][threadIdx.x & 63] = acc;
   __syncthreads();
   if (wave == 0 && row < D.n) {
-    double2 s = gld(D.g + row);
+    double2 s = gld(D.g + (size_t)rc * D.n + row);
     for (int w = 0; w < 4; ++w) {
       s.x -= part[w][threadIdx.x].x;
       s.y -= part[w][threadIdx.x].y;
     }
-    gst(D.y + row, s);
+    gst(D.y + (size_t)rc * D.n + row, s);
   }
 }
 
@@ -422,8 +427,9 @@ void launch_gje_update(const GjeDesc* d, int nbatch, int k, int max_ncol, hipStr
   if (nbatch > 0 && max_ncol > k)
     hipLaunchKernelGGL(gje_update_kernel, dim3(tiles, nbatch), dim3(kUpdThreads), 0, st, d, k);
 }
-void launch_gemv_step(const GemvDesc* d, int nbatch, int max_n, hipStream_t st) {
-  if (nbatch > 0 && max_n > 0) hipLaunchKernelGGL(gemv_step_kernel, dim3((max_n + 63) / 64, nbatch), dim3(256), 0, st, d);
+void launch_gemv_step(const GemvDesc* d, int nbatch, int max_n, int max_r, hipStream_t st) {
+  if (nbatch > 0 && max_n > 0 && max_r > 0)
+    hipLaunchKernelGGL(gemv_step_kernel, dim3((max_n + 63) / 64, nbatch, max_r), dim3(256), 0, st, d);
 }
 
 }  // namespace mlh

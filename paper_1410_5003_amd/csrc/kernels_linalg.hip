@@ -126,7 +126,7 @@ __global__ __launch_bounds__(256) void rb_setup_kernel(const AngleDesc* __restri
   const int n0 = rb_n0(kappa0, sc.d);
   const int tid = threadIdx.x;
   const int r0 = 2 * sc.Mw;
-  for (int e = tid; e < sc.Mud * nK; e += 256) {
+  for (int e = tid; A.owner && e < sc.Mud * nK; e += 256) {  // W rows: once per system
     const int mrow = e % sc.Mud, q = e / sc.Mud;
     const double kap = kappa0 + 2.0 * kPi * (double)(n0 - sc.K + q) / sc.d;
     double s, c;

@@ -347,9 +347,7 @@ struct mlh_stack_s {
   // the workspace stay the same; only the descriptor contents change)
   hipGraphExec_t gexec = nullptr;
   hipStream_t cap_stream = nullptr;
-  int g_nb = -1, g_B = -1;
-  size_t g_doff = 0;
-  char* g_wmem = nullptr;
+  std::vector<int64_t> g_sig;
 
   // solve workspace (reused across calls with the same batch size)
   char* wmem = nullptr;
@@ -1037,15 +1035,41 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
   const std::vector<int>& n = s->n;
   int maxn = 0;
   for (int i = 0; i < I; ++i) maxn = std::max(maxn, n[i]);
+  // ---- angles whose Bloch phases alpha agree (kappa_0 on one grid of spacing
+  //      2 pi/d, Sec. 3.4) share every matrix of the solve: they form one
+  //      system, with one right-hand side column per angle
+  std::vector<std::vector<int>> groups;
+  {
+    std::vector<double> tfrac;
+    for (int a = 0; a < n_angles; ++a) {
+      const double t = s->d * s->k[0] * std::cos(theta[a]) / (2.0 * kPi);
+      const double f = t - std::floor(t);
+      int g = -1;
+      for (size_t q = 0; q < groups.size() && g < 0; ++q) {
+        const double dd = std::fabs(f - tfrac[q]);
+        if (std::min(dd, 1.0 - dd) < kAlphaTol) g = (int)q;
+      }
+      if (g < 0) {
+        groups.emplace_back();
+        tfrac.push_back(f);
+        g = (int)groups.size() - 1;
+      }
+      groups[g].push_back(a);
+    }
+  }
+  const int n_sys = (int)groups.size();
+  int rmax = 1;
+  for (const auto& g : groups) rmax = std::max(rmax, (int)g.size());
   std::vector<int> wmax(I), nL0(I), nU0(I);
   for (int i = 0; i < I; ++i) {
-    wmax[i] = n[i] + 2 * maxn + 1;
+    wmax[i] = n[i] + 2 * maxn + rmax;
     nL0[i] = i > 0 ? n[i - 1] : 0;
     nU0[i] = i + 1 < I ? n[i + 1] : 0;
   }
-  // ---- workspace of one angle: two row-block buffers per interface (the
+  // ---- workspace of one system: two row-block buffers per interface (the
   //      reduction reads one and writes the other), least-squares systems,
-  //      eta, Gauss-Jordan scratch per interface, outputs
+  //      eta (one column per angle), Gauss-Jordan scratch per interface,
+  //      outputs per angle
   auto plan = [&](Arena& A, std::vector<size_t>* offs) {
     auto R = [&](size_t bytes) {
       const size_t o = A.reserve(bytes);
@@ -1059,25 +1083,25 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
       R(cbytes((size_t)(m + c) * (c + nc)));  // [S | RHS]
       R(cbytes((size_t)kHqNb * kHqNb));
     }
-    for (int i = 0; i < I; ++i) R(cbytes(n[i]));
+    for (int i = 0; i < I; ++i) R(cbytes((size_t)n[i] * rmax));
     for (int i = 0; i < I; ++i) {
-      R(cbytes((size_t)n[i] * kGjeNb));
       R(cbytes((size_t)kGjeNb * kGjeNb));
       R(sizeof(int) * (1 + 4 * kGjeNb));
     }
-    R(cbytes(2 * nK));
-    R(sizeof(double) * 2);
-    R(sizeof(int) * nK);
+    R(cbytes((size_t)2 * nK * rmax));
+    R(sizeof(double) * rmax);
+    R(sizeof(int) * nK * rmax);
   };
   Arena ar;
   plan(ar, nullptr);
   const size_t per = (ar.off + 255) & ~size_t(255);
   const size_t desc_per = sizeof(AsmJob) * (size_t)(10 * (I + 2)) + sizeof(GemmDesc) * (size_t)(8 * I + 8) +
                           sizeof(HqDesc) * (size_t)(I + 1) + sizeof(GjeDesc) * (size_t)(I + 1) +
-                          sizeof(GemvDesc) * (size_t)(I + 1) + sizeof(AngleDesc) + 256 * (size_t)(3 * 40 + 16);
+                          sizeof(GemvDesc) * (size_t)(I + 1) + sizeof(AngleDesc) * (size_t)rmax +
+                          256 * (size_t)(3 * 40 + 16);
   size_t freeb = 0, totb = 0;
   HIP_TRY(hipMemGetInfo(&freeb, &totb));
-  int B = n_angles;
+  int B = n_sys;
   const size_t budget = (size_t)(0.8 * (double)(freeb + s->wbytes));
   while (B > 1 && (size_t)B * (per + desc_per) > budget) B = (B + 1) / 2;
   const size_t need = (size_t)B * (per + desc_per) + 4096;
@@ -1098,13 +1122,19 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
     plan(A, &offs);
   }
   std::vector<double> h_flux(n_angles);
-  for (int a0 = 0; a0 < n_angles; a0 += B) {
-    const int nb = std::min(B, n_angles - a0);
+  for (int s0 = 0; s0 < n_sys; s0 += B) {
+    const int nb = std::min(B, n_sys - s0);
+    int nang = 0, rchunk = 1;
+    for (int b = 0; b < nb; ++b) {
+      nang += (int)groups[s0 + b].size();
+      rchunk = std::max(rchunk, (int)groups[s0 + b].size());
+    }
+    auto R_of = [&](int b) { return (int)groups[s0 + b].size(); };
     char* dbase = s->wmem + (size_t)B * per;
     struct View {
-      std::vector<cplx*> W[2], S, Th, RHS, eta, Pg, M1;
+      std::vector<cplx*> W[2], S, Th, RHS, eta, M1;
       std::vector<int*> piv;
-      cplx *aU, *aD;
+      cplx* out;  // per angle: a^U (nK) then a^D (nK)
       double* flux;
       int* orders;
     };
@@ -1126,12 +1156,10 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
       }
       for (int i = 0; i < I; ++i) v.eta.push_back(C());
       for (int i = 0; i < I; ++i) {
-        v.Pg.push_back(C());
         v.M1.push_back(C());
         v.piv.push_back(reinterpret_cast<int*>(wb + offs[k++]));
       }
-      v.aU = C();
-      v.aD = v.aU + nK;
+      v.out = C();
       v.flux = reinterpret_cast<double*>(wb + offs[k++]);
       v.orders = reinterpret_cast<int*>(wb + offs[k++]);
     }
@@ -1192,11 +1220,12 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
     int gtiles = 0;
     std::vector<HqDesc> hq;
     int maxc = 0, maxcols = 0, maxncol = 0;
-    std::vector<AngleDesc> angs(nb);
+    std::vector<AngleDesc> angs;
     const cplx one = cx(1, 0);
     for (int b = 0; b < nb; ++b) {
       View& v = V[b];
-      const double th = theta[a0 + b];
+      const int rb = R_of(b);
+      const double th = theta[groups[s0 + b][0]];
       const double ph = s->d * s->k[0] * std::cos(th);  // alpha = e^{i ph}, eq. (2)
       const cplx a_m1 = cpow_alpha(ph, -1), a_p1 = cpow_alpha(ph, 1), a_m2 = cpow_alpha(ph, -2);
       const cplx c3[3] = {a_m1, one, a_p1};
@@ -1206,7 +1235,7 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
         const size_t pe = (size_t)n[i] * n[i];
         const cplx* src[3] = {s->A_self[i], s->A_self[i] + pe, s->A_self[i] + 2 * pe};
         asm_add(Dblk(b, i), n[i], n[i], n[i], 3, src, n[i], c3);
-        if (i > 0) asm_add(Fcol(b, i), n[i], n[i], 1, 0, src, n[i], c3);  // f_i = 0 below Gamma_1
+        if (i > 0) asm_add(Fcol(b, i), n[i], n[i], rb, 0, src, n[i], c3);  // f_i = 0 below Gamma_1
         if (i + 1 < I) {
           const size_t pu = (size_t)n[i] * n[i + 1];
           const cplx* su[3] = {s->A_up[i], s->A_up[i] + pu, s->A_up[i] + 2 * pu};
@@ -1275,26 +1304,30 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
           gemm_add(gs, gtiles, Lblk(b, i), n[i], Lblk(b, i), n[i], n[i], n[i - 1], s->B_own[i], n[i], v.RHS[i], Ma, P,
                    nullptr, 1, nullptr, 1, 0);
       }
-      AngleDesc& A = angs[b];
-      A.theta = th;
       int m0, c0, nc0, mI, cI, ncI;
       layer_dims(s, 0, m0, c0, nc0);
       layer_dims(s, I, mI, cI, ncI);
-      A.S0 = v.S[0];
-      A.ldS0 = m0 + c0;
-      A.SI = v.S[I];
-      A.ldSI = mI + cI;
-      A.F0 = Fcol(b, 0);
-      A.X0 = v.RHS[0];
-      A.ldX0 = m0 + c0;
-      A.XI = v.RHS[I];
-      A.ldXI = mI + cI;
-      A.eta0 = v.eta[0];
-      A.etaI = v.eta[I - 1];
-      A.aU = v.aU;
-      A.aD = v.aD;
-      A.orders = v.orders;
-      A.flux = v.flux;
+      for (int q = 0; q < rb; ++q) {  // one descriptor per angle of the system
+        AngleDesc A{};
+        A.theta = theta[groups[s0 + b][q]];
+        A.owner = q == 0;
+        A.S0 = v.S[0];
+        A.ldS0 = m0 + c0;
+        A.SI = v.S[I];
+        A.ldSI = mI + cI;
+        A.F0 = Fcol(b, 0) + (size_t)q * n[0];
+        A.X0 = v.RHS[0];
+        A.ldX0 = m0 + c0;
+        A.XI = v.RHS[I];
+        A.ldXI = mI + cI;
+        A.eta0 = v.eta[0] + (size_t)q * n[0];
+        A.etaI = v.eta[I - 1] + (size_t)q * n[I - 1];
+        A.aU = v.out + (size_t)2 * nK * q;
+        A.aD = A.aU + nK;
+        A.orders = v.orders + (size_t)nK * q;
+        A.flux = v.flux + q;
+        angs.push_back(A);
+      }
     }
     // ---- block-tridiagonal solve by cyclic reduction (the paper's block LU,
     //      Sec. 3.3, reordered so that every level eliminates half of the
@@ -1325,20 +1358,20 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
         for (int b = 0; b < nb; ++b) {
           GjeDesc G{};
           G.W = Wp(b, j, cur[j]);
-          G.P = V[b].Pg[j];
           G.M1 = V[b].M1[j];
           G.piv = V[b].piv[j];
           G.n = n[j];
-          G.ncol = n[j] + nLc[j] + nUc[j] + 1;
+          G.ncol = n[j] + nLc[j] + nUc[j] + R_of(b);
           lv.gje.push_back(G);
+          lv.maxcol = std::max(lv.maxcol, G.ncol);
           GemvDesc Gv{};
           Gv.g = G.W + (size_t)n[j] * (n[j] + nLc[j] + nUc[j]);
           Gv.y = V[b].eta[j];
           Gv.n = n[j];
+          Gv.r = R_of(b);
           lv.back.push_back(Gv);
         }
         lv.maxn = n[j];
-        lv.maxcol = n[j] + nLc[j] + nUc[j] + 1;
         lv.backn = n[j];
         levels.push_back(lv);
         break;
@@ -1349,12 +1382,12 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
         for (int b = 0; b < nb; ++b) {
           GjeDesc G{};
           G.W = Wp(b, e, cur[e]);
-          G.P = V[b].Pg[e];
           G.M1 = V[b].M1[e];
           G.piv = V[b].piv[e];
           G.n = n[e];
-          G.ncol = n[e] + nLc[e] + nUc[e] + 1;
+          G.ncol = n[e] + nLc[e] + nUc[e] + R_of(b);
           lv.gje.push_back(G);
+          lv.maxcol = std::max(lv.maxcol, G.ncol);
           const cplx* X = G.W + (size_t)n[e] * n[e];
           GemvDesc Gv{};
           Gv.U1 = X;
@@ -1366,10 +1399,10 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
           Gv.g = X + (size_t)n[e] * (nLc[e] + nUc[e]);
           Gv.y = V[b].eta[e];
           Gv.n = n[e];
+          Gv.r = R_of(b);
           lv.back.push_back(Gv);
         }
         lv.maxn = std::max(lv.maxn, n[e]);
-        lv.maxcol = std::max(lv.maxcol, n[e] + nLc[e] + nUc[e] + 1);
         lv.backn = std::max(lv.backn, n[e]);
       }
       // update the kept blocks
@@ -1407,15 +1440,15 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
           // D and f (one or two products each)
           if (el >= 0 && er >= 0) {
             gemm_add(lv.upd, lv.upd_tiles, Wn, nj, Wc, nj, nj, nj, Lj, nj, XUl, nel, nel, Uj, nj, XLr, ner, ner);
-            gemm_add(lv.upd, lv.upd_tiles, Wn + (size_t)nj * (nj + nLn + nUn), nj, fj, nj, nj, 1, Lj, nj, xfl, nel,
+            gemm_add(lv.upd, lv.upd_tiles, Wn + (size_t)nj * (nj + nLn + nUn), nj, fj, nj, nj, R_of(b), Lj, nj, xfl, nel,
                      nel, Uj, nj, xfr, ner, ner);
           } else if (el >= 0) {
             gemm_add(lv.upd, lv.upd_tiles, Wn, nj, Wc, nj, nj, nj, Lj, nj, XUl, nel, nel, nullptr, 1, nullptr, 1, 0);
-            gemm_add(lv.upd, lv.upd_tiles, Wn + (size_t)nj * (nj + nLn + nUn), nj, fj, nj, nj, 1, Lj, nj, xfl, nel,
+            gemm_add(lv.upd, lv.upd_tiles, Wn + (size_t)nj * (nj + nLn + nUn), nj, fj, nj, nj, R_of(b), Lj, nj, xfl, nel,
                      nel, nullptr, 1, nullptr, 1, 0);
           } else {
             gemm_add(lv.upd, lv.upd_tiles, Wn, nj, Wc, nj, nj, nj, Uj, nj, XLr, ner, ner, nullptr, 1, nullptr, 1, 0);
-            gemm_add(lv.upd, lv.upd_tiles, Wn + (size_t)nj * (nj + nLn + nUn), nj, fj, nj, nj, 1, Uj, nj, xfr, ner,
+            gemm_add(lv.upd, lv.upd_tiles, Wn + (size_t)nj * (nj + nLn + nUn), nj, fj, nj, nj, R_of(b), Uj, nj, xfr, ner,
                      ner, nullptr, 1, nullptr, 1, 0);
           }
           if (ll >= 0)
@@ -1495,7 +1528,7 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
       te();
       const AngleDesc* d_ang = reinterpret_cast<AngleDesc*>(dbase + o_ang);
       tb(prof ? &prof->rb_setup_ms : nullptr);
-      launch_rb_setup(d_ang, nb, sc, ls);
+      launch_rb_setup(d_ang, nang, sc, ls);
       te();
       const HqDesc* d_hq = reinterpret_cast<HqDesc*>(dbase + o_hq);
       const int nhq = (int)hq.size();
@@ -1547,10 +1580,10 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
         tb(prof ? &prof->backsub_ms : nullptr);
         for (int l = NL - 1; l >= 0; --l)
           launch_gemv_step(reinterpret_cast<GemvDesc*>(dbase + o_back[l]), (int)levels[l].back.size(), levels[l].backn,
-                           ls);
+                           rchunk, ls);
         te();
         tb(prof ? &prof->bragg_ms : nullptr);
-        launch_bragg(d_ang, nb, sc, ls);
+        launch_bragg(d_ang, nang, sc, ls);
         te();
       }
       HIP_TRY(hipGetLastError());
@@ -1562,7 +1595,20 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
     if (prof || stop_phase != 0 || no_graph) {
       MLH_TRY(launch_all(st, T));
     } else {
-      if (!(s->gexec && s->g_nb == nb && s->g_B == B && s->g_doff == doff && s->g_wmem == s->wmem)) {
+      // every launch shape of the sequence: a cached graph is replayed only
+      // when all of them, and the workspace, are unchanged
+      std::vector<int64_t> sig = {nb, B, nang, rchunk, (int64_t)doff, (int64_t)(intptr_t)s->wmem, (int64_t)elems,
+                                  gtiles, maxc, maxcols, maxncol, (int64_t)hq.size(), (int64_t)gs.size()};
+      for (const Level& lv : levels) {
+        sig.push_back(lv.maxn);
+        sig.push_back(lv.maxcol);
+        sig.push_back((int64_t)lv.gje.size());
+        sig.push_back(lv.upd_tiles);
+        sig.push_back((int64_t)lv.upd.size());
+        sig.push_back(lv.backn);
+        sig.push_back((int64_t)lv.back.size());
+      }
+      if (!(s->gexec && s->g_sig == sig)) {
         if (s->gexec) {
           hipGraphExecDestroy(s->gexec);
           s->gexec = nullptr;
@@ -1584,10 +1630,7 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
         hipError_t ie = hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0);
         hipGraphDestroy(g);
         if (ie != hipSuccess) return fail(MLH_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(ie));
-        s->g_nb = nb;
-        s->g_B = B;
-        s->g_doff = doff;
-        s->g_wmem = s->wmem;
+        s->g_sig = sig;
       }
       HIP_TRY(hipGraphLaunch(s->gexec, st));
     }
@@ -1601,14 +1644,17 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
       return MLH_OK;
     }
     // ---- results
-    for (int b = 0; b < nb; ++b) {
-      const int a = a0 + b;
-      HIP_TRY(hipMemcpyAsync(aU + (size_t)2 * nK * a, V[b].aU, cbytes(nK), hipMemcpyDeviceToHost, st));
-      HIP_TRY(hipMemcpyAsync(aD + (size_t)2 * nK * a, V[b].aD, cbytes(nK), hipMemcpyDeviceToHost, st));
-      if (orders)
-        HIP_TRY(hipMemcpyAsync(orders + (size_t)nK * a, V[b].orders, sizeof(int) * nK, hipMemcpyDeviceToHost, st));
-      HIP_TRY(hipMemcpyAsync(&h_flux[a], V[b].flux, sizeof(double), hipMemcpyDeviceToHost, st));
-    }
+    for (int b = 0; b < nb; ++b)
+      for (int q = 0; q < R_of(b); ++q) {
+        const int a = groups[s0 + b][q];
+        const cplx* o = V[b].out + (size_t)2 * nK * q;
+        HIP_TRY(hipMemcpyAsync(aU + (size_t)2 * nK * a, o, cbytes(nK), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(aD + (size_t)2 * nK * a, o + nK, cbytes(nK), hipMemcpyDeviceToHost, st));
+        if (orders)
+          HIP_TRY(hipMemcpyAsync(orders + (size_t)nK * a, V[b].orders + (size_t)nK * q, sizeof(int) * nK,
+                                 hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(&h_flux[a], V[b].flux + q, sizeof(double), hipMemcpyDeviceToHost, st));
+      }
     int info[4] = {0, 0, 0, 0};
     HIP_TRY(hipMemcpyAsync(info, d_info, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));

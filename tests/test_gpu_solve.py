@@ -205,3 +205,28 @@ def test_config3_head_literal(ctx):
     err = rel_amp_err(g.aU[0], g.aD[0], o.aU, o.aD)
     print("config3 literal head rel err %.2e (flux %.1e, LS spread %.1e)" % (err, o.flux_err, spread))
     assert err < tol
+
+
+def test_shared_alpha_angles_solved_as_one_system(ctx):
+    # angles whose kappa_0 = k_1 cos(theta) differ by multiples of 2 pi/d share
+    # alpha and hence every matrix (Sec. 3.4); they are solved as one system
+    # with several right-hand sides.  Each angle must still match its own
+    # oracle solve and the GPU's solve of that angle alone.
+    import paper_1410_5003_amd as mlh
+    s = workloads.config1(N=160, P=140, M_w=100)
+    g = 2 * np.pi / s.d
+    kap = [0.3 - 7 * g, 0.65 - g, 0.3, 0.3 + 3 * g, 0.65 + 4 * g, 0.3 - 2 * g, 0.3 + 8 * g]
+    th = -np.arccos(np.array(kap) / s.k[0])
+    st = mlh.Stack(ctx, s)
+    out = st.solve(th)
+    for a, t in enumerate(th):
+        o = oracle.solve_stack(s, theta=t)
+        assert np.array_equal(out.orders[a], o.orders)
+        err = rel_amp_err(out.aU[a], out.aD[a], o.aU, o.aD)
+        one = st.solve([t])
+        err1 = rel_amp_err(out.aU[a], out.aD[a], one.aU[0], one.aD[0])
+        print("kappa0 %+.3f rel err vs oracle %.2e vs single-angle GPU %.2e flux %.1e" %
+              (kap[a], err, err1, out.flux_err[a]))
+        assert err < TOL and err1 < 1e-11
+        assert abs(out.flux_err[a]) < 1e-9
+    st.close()
