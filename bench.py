@@ -29,31 +29,67 @@ METRIC = "multilayer solves/s (unknowns/s) at flux err ≤1e-9; adjoint grads/s;
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6
 
+RES3 = dict(N_smooth=260, N_corner=300, P=140, M_w=100)
 WORKLOADS = {
-    # name: (generator name, kwargs, description)
+    # name: (generator name, kwargs, description, angles of one step)
+    #   angles: "first" = the generator's single angle, "all" = its angle list,
+    #   "kgrid" = a kappa_0 grid holding 20 distinct alpha, 5 angles each
     "config2_resolved": ("config2", dict(N=260, P=120, M_w=80),
-                         "I=50 random Fourier interfaces, N=260, P=120, M_w=80, M_ud=60, K=25"),
-    "config2": ("config2", dict(), "I=50 random Fourier interfaces, N=100, P=50, M_w=50, M_ud=60, K=25"),
+                         "I=50 random Fourier interfaces, N=260, P=120, M_w=80, M_ud=60, K=25", "first"),
+    "config2": ("config2", dict(), "I=50 random Fourier interfaces, N=100, P=50, M_w=50, M_ud=60, K=25", "first"),
     "config1_resolved": ("config1", dict(N=160, P=140, M_w=100),
-                         "I=2 sine interfaces, N=160, P=140, M_w=100, M_ud=60, K=25"),
-    "config1": ("config1", dict(), "I=2 sine interfaces, N=120, P=60, M_w=60, M_ud=60, K=25"),
+                         "I=2 sine interfaces, N=160, P=140, M_w=100, M_ud=60, K=25", "first"),
+    "config1": ("config1", dict(), "I=2 sine interfaces, N=120, P=60, M_w=60, M_ud=60, K=25", "first"),
+    "config3_resolved": ("config3", RES3,
+                         "I=1000, 70% random Fourier (N=260) / 30% cornered (N=300, Kress q=6), P=140, M_w=100, "
+                         "M_ud=60, K=25; sweep of 100 angles uniform in (-pi/2, 0)", "all"),
+    "config3_kgrid_resolved": ("config3", RES3,
+                               "I=1000 stack of config3_resolved; sweep of 100 angles on a kappa_0 grid of "
+                               "spacing 2 pi/(20 d) (20 distinct alpha, 5 angles each)", "kgrid"),
+    "config3": ("config3", dict(),
+                "I=1000, 70% random Fourier (N=120) / 30% cornered (N=250), P=60, M_w=60, M_ud=60, K=25; "
+                "sweep of 100 angles uniform in (-pi/2, 0)", "all"),
 }
 
 
 def make_desc(name, I=None):
     import workloads
-    gen, kw, _ = WORKLOADS[name]
+    gen, kw, _, _ = WORKLOADS[name]
     kw = dict(kw)
     if I is not None:
         kw["I"] = I
     return getattr(workloads, gen)(**kw)
 
 
+def step_thetas(name, desc):
+    import numpy as np
+    import workloads
+    mode = WORKLOADS[name][3]
+    if mode == "first":
+        return np.asarray(desc.thetas[:1], dtype=float)
+    if mode == "all":
+        return np.asarray(desc.thetas, dtype=float)
+    return workloads.kappa_grid_thetas(desc, n_angles=100, n_alpha=20)
+
+
+def distinct_alpha(desc, thetas, tol=1e-12):
+    """Number of distinct Bloch phases among the angles (same rule as the library)."""
+    import math
+    fr = []
+    for t in thetas:
+        x = desc.d * desc.k[0] * math.cos(t) / (2 * math.pi)
+        f = x - math.floor(x)
+        if not any(min(abs(f - g), 1 - abs(f - g)) < tol for g in fr):
+            fr.append(f)
+    return len(fr)
+
+
 def algorithmic_work(desc):
-    """Real float64 flops (complex multiply-add = 8) of each kernel group in one
-    step, and the bytes the fill kernels must write (16 per complex entry)."""
+    """Real float64 flops (complex multiply-add = 8) of each kernel group for
+    one Bloch phase, and the bytes the fill kernels must write (16 per
+    complex entry)."""
     I, P, K, Mw, Mud = desc.I, desc.P, desc.K, desc.M_w, desc.M_ud
-    n = [2 * f.n_nodes for f in desc.interfaces]
+    n = [2 * f.N for f in desc.interfaces]
     nK = 2 * K + 1
     nb = 16
     w = {}
@@ -106,8 +142,8 @@ GROUPS = [  # (name, profile time key, launch-count key, work key, bound)
 ]
 
 
-def roofline(desc, prof):
-    work = algorithmic_work(desc)
+def roofline(desc, prof, n_sys=1):
+    work = {k: (v if k.startswith("fill") else v * n_sys) for k, v in algorithmic_work(desc).items()}
     name, tkey, nkey, wkey, bound = max(GROUPS, key=lambda g: prof[g[1]])
     t = prof[tkey] * 1e-3
     launches = int(prof[nkey]) if nkey else 1
@@ -121,8 +157,9 @@ def roofline(desc, prof):
 
 
 def cpu_baseline(name, sample_I):
-    """Time the oracle on the first `sample_I` interfaces of the workload (one
-    thread, separate process) and scale linearly in the number of layers."""
+    """Time the oracle on the first `sample_I` interfaces of the workload, one
+    angle (one thread, separate process); the caller scales linearly in the
+    number of layers and angles."""
     code = (
         "import os,sys,time;sys.path.insert(0,%r);"
         "import bench,oracle;d=bench.make_desc(%r,I=%d);"
@@ -138,11 +175,13 @@ def cpu_baseline(name, sample_I):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="config2_resolved", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-layers", type=int, default=6)
+    ap.add_argument("--plain-sample", type=int, default=4,
+                    help="sweeps: angles timed one by one (refill + one-angle solve each)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
@@ -152,42 +191,72 @@ def main():
     import paper_1410_5003_amd as mlh
 
     desc = make_desc(args.workload)
+    thetas = step_thetas(args.workload, desc)
+    sweep = len(thetas) > 1
+    steps = args.steps if args.steps is not None else (1 if sweep else 20)
+    warmup = args.warmup if args.warmup is not None else (1 if sweep else 3)
     ctx = mlh.Context(0)
     st = mlh.Stack(ctx, desc)
     info = st.info()
-    thetas = np.asarray(desc.thetas, dtype=float)
-    print("workload %s: I=%d n_tot=%d device MB %.1f" % (args.workload, desc.I, info["n_tot"],
-                                                        info["device_bytes"] / 2 ** 20), file=sys.stderr, flush=True)
+    n_sys = distinct_alpha(desc, thetas)
+    print("workload %s: I=%d n_tot=%d device MB %.1f angles %d distinct alpha %d" %
+          (args.workload, desc.I, info["n_tot"], info["device_bytes"] / 2 ** 20, len(thetas), n_sys),
+          file=sys.stderr, flush=True)
     out = None
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         st.refill()
         out = st.solve(thetas)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         st.refill()
         out = st.solve(thetas)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    ms = (t1 - t0) * 1e3 / args.steps
+    ms = (t1 - t0) * 1e3 / steps
     solves_per_s = len(thetas) / (ms * 1e-3)
-    print("step %.3f ms  flux err %.2e" % (ms, out.flux_err[0]), file=sys.stderr, flush=True)
+    flux = np.abs(out.flux_err)
+    print("step %.3f ms  flux err max %.2e median %.2e" % (ms, flux.max(), np.median(flux)),
+          file=sys.stderr, flush=True)
 
     # per-kernel device times (HIP events on the library's stream)
-    profs = [st.profile_step(thetas[0]) for _ in range(3)]
-    prof = {k: float(np.mean([p[k] for p in profs])) for k in profs[0]}
+    if sweep:
+        prof = st.profile_solve(thetas)
+    else:
+        profs = [st.profile_step(thetas[0]) for _ in range(3)]
+        prof = {k: float(np.mean([p[k] for p in profs])) for k in profs[0]}
     print("profile " + json.dumps({k: round(v, 4) for k, v in prof.items()}), file=sys.stderr, flush=True)
-    roof = roofline(desc, prof)
+    roof = roofline(desc, prof, n_sys)
     line = {
-        "metric": METRIC, "value": solves_per_s, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "metric": METRIC, "value": solves_per_s, "unit": "solves/s", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64 (complex128)", "data": "synthetic (seeded stacks)",
         "config": {"workload": args.workload, "description": WORKLOADS[args.workload][2],
-                   "interfaces": desc.I, "unknowns": info["n_tot"], "angles_per_step": len(thetas)},
+                   "interfaces": desc.I, "unknowns": info["n_tot"], "angles_per_step": len(thetas),
+                   "distinct_alpha": n_sys},
         "unknowns_per_s": solves_per_s * info["n_tot"], "flux_err": float(out.flux_err[0]),
+        "flux_err_max": float(flux.max()),
         "phase_ms": {k: round(v, 4) for k, v in prof.items() if k.endswith("_ms")},
         "roofline": roof,
     }
+    if sweep:
+        # the same angles solved one at a time, each with its own refill
+        npl = min(args.plain_sample, len(thetas))
+        idx = np.linspace(0, len(thetas) - 1, npl).round().astype(int)
+        st.refill()
+        st.solve(thetas[idx[:1]])
+        torch.cuda.synchronize()
+        tp0 = time.perf_counter()
+        for a in idx:
+            st.refill()
+            st.solve(thetas[a:a + 1])
+        torch.cuda.synchronize()
+        plain = (time.perf_counter() - tp0) / npl
+        batched = ms * 1e-3 / len(thetas)
+        line["sweep"] = {"plain_s_per_angle": plain, "batched_s_per_angle": batched,
+                         "speedup_vs_plain": plain / batched, "plain_sample_angles": int(npl)}
+        print("sweep: plain %.3f s/angle, batched %.3f s/angle, speed-up %.2fx" % (plain, batched, plain / batched),
+              file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         ts = cpu_baseline(args.workload, args.cpu_sample_layers)
         t_full = ts * desc.I / args.cpu_sample_layers

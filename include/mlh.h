@@ -191,6 +191,11 @@ typedef struct {
  * around each kernel launch and return the per-kernel times. */
 mlh_status mlh_profile_step(mlh_stack s, double theta, mlh_profile* out);
 
+/* The same for mlh_stack_refill + mlh_solve of n_angles angles (theta: host
+ * array); times are summed over the batches the solve runs in.  The
+ * instrumented run is not graph-captured. */
+mlh_status mlh_profile_solve(mlh_stack s, int32_t n_angles, const double* theta, mlh_profile* out);
+
 const char* mlh_last_error(void);
 
 #ifdef __cplusplus

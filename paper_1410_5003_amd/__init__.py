@@ -167,6 +167,13 @@ class Stack:
         check(lib().mlh_profile_step(self._h, float(theta), C.byref(p)))
         return {name: getattr(p, name) for name, _ in p._fields_}
 
+    def profile_solve(self, thetas) -> dict:
+        """Per-kernel device times (ms) of one refill + a solve of all ``thetas``."""
+        th = np.ascontiguousarray(np.atleast_1d(thetas), dtype=np.float64)
+        p = mlh_profile()
+        check(lib().mlh_profile_solve(self._h, th.size, dptr(th), C.byref(p)))
+        return {name: getattr(p, name) for name, _ in p._fields_}
+
     def solve_partial(self, theta: float, stop_phase: int):
         """Inspection: run one angle up to a phase (1 assembly, 2 least squares,
         3 Schur, 4 sweep) and keep its workspace for ``work``."""

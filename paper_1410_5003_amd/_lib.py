@@ -78,6 +78,7 @@ SIGNATURES = {
     "mlh_debug_get_work": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double),
                                        C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "mlh_profile_step": (C.c_int32, [C.c_void_p, C.c_double, C.c_void_p]),
+    "mlh_profile_solve": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.c_void_p]),
     "mlh_last_error": (C.c_char_p, []),
 }
 

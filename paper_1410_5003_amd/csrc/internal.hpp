@@ -33,6 +33,9 @@ struct FillJob {
   int tile_begin, tiles_m;
 };
 
+// largest grid of one launch (workgroups); bigger launches are split
+constexpr int kMaxLaunchBlocks = 1 << 22;
+
 constexpr int kFillTileM = 64;
 constexpr int kFillTileN = 4;
 

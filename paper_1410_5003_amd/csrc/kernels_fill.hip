@@ -17,6 +17,8 @@
 //                 Bloch phase), and the interpolated quantity is the density
 //                 times the graded Jacobian, so the stencil weights multiply
 //                 the node weights w_j.
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace mlh {
@@ -36,8 +38,8 @@ __device__ inline int find_job(const T* jobs, int njobs, int key) {
 
 __device__ inline void store(cplx* p, cplx v) { *reinterpret_cast<double2*>(p) = make_double2(v.re, v.im); }
 
-__global__ __launch_bounds__(256) void fill_kernel(const FillJob* __restrict__ jobs, int njobs) {
-  const int tile = blockIdx.x;
+__global__ __launch_bounds__(256) void fill_kernel(const FillJob* __restrict__ jobs, int njobs, int tile0) {
+  const int tile = tile0 + (int)blockIdx.x;
   const FillJob& J = jobs[find_job(jobs, njobs, tile)];
   const int lt = tile - J.tile_begin;
   const int tm = lt % J.tiles_m, tn = lt / J.tiles_m;
@@ -76,8 +78,8 @@ __global__ __launch_bounds__(256) void fill_kernel(const FillJob* __restrict__ j
   }
 }
 
-__global__ __launch_bounds__(256) void self_kernel(const SelfJob* __restrict__ jobs, int njobs, int a) {
-  const int tile = blockIdx.x;
+__global__ __launch_bounds__(256) void self_kernel(const SelfJob* __restrict__ jobs, int njobs, int a, int tile0) {
+  const int tile = tile0 + (int)blockIdx.x;
   const SelfJob& J = jobs[find_job(jobs, njobs, tile)];
   const int lt = tile - J.tile_begin;
   const int tm = lt % J.tiles_m, tn = lt / J.tiles_m;
@@ -128,8 +130,8 @@ __global__ __launch_bounds__(256) void self_kernel(const SelfJob* __restrict__ j
   }
 }
 
-__global__ __launch_bounds__(64) void alpert_kernel(const AlpertJob* __restrict__ jobs, int njobs, int a) {
-  const int blk = blockIdx.x;
+__global__ __launch_bounds__(64) void alpert_kernel(const AlpertJob* __restrict__ jobs, int njobs, int a, int blk0) {
+  const int blk = blk0 + (int)blockIdx.x;
   int lo = 0, hi = njobs - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -210,28 +212,31 @@ __global__ __launch_bounds__(64) void alpert_kernel(const AlpertJob* __restrict_
   }
 }
 
+// grid-stride over all elements of all jobs (the total can exceed what one
+// launch addresses with a thread per element)
 __global__ __launch_bounds__(256) void assemble_kernel(const AsmJob* __restrict__ jobs, int njobs,
                                                       int64_t total) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= total) return;
-  int lo = 0, hi = njobs - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (jobs[mid].elem_begin <= e)
-      lo = mid;
-    else
-      hi = mid - 1;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
+    int lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (jobs[mid].elem_begin <= e)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const AsmJob& J = jobs[lo];
+    const int64_t le = e - J.elem_begin;
+    const int r = (int)(le % J.rows), c = (int)(le / J.rows);
+    double re = 0.0, im = 0.0;
+    for (int p = 0; p < J.npieces; ++p) {
+      const double2 v = *reinterpret_cast<const double2*>(J.src[p] + (size_t)c * J.lds + r);
+      re += J.coef[p].re * v.x - J.coef[p].im * v.y;
+      im += J.coef[p].re * v.y + J.coef[p].im * v.x;
+    }
+    *reinterpret_cast<double2*>(J.dst + (size_t)c * J.ldd + r) = make_double2(re, im);
   }
-  const AsmJob& J = jobs[lo];
-  const int64_t le = e - J.elem_begin;
-  const int r = (int)(le % J.rows), c = (int)(le / J.rows);
-  double re = 0.0, im = 0.0;
-  for (int p = 0; p < J.npieces; ++p) {
-    const double2 v = *reinterpret_cast<const double2*>(J.src[p] + (size_t)c * J.lds + r);
-    re += J.coef[p].re * v.x - J.coef[p].im * v.y;
-    im += J.coef[p].re * v.y + J.coef[p].im * v.x;
-  }
-  *reinterpret_cast<double2*>(J.dst + (size_t)c * J.ldd + r) = make_double2(re, im);
 }
 
 __global__ void hankel_eval_kernel(const double* x, double* out, int n) {
@@ -245,21 +250,27 @@ __global__ void hankel_eval_kernel(const double* x, double* out, int n) {
   out[4 * i + 3] = g.im;
 }
 
+// launches larger than kMaxLaunchBlocks workgroups are split, each part
+// passing its first tile index
 void launch_fill(const FillJob* d_jobs, int njobs, int total_tiles, hipStream_t st) {
-  if (total_tiles > 0) hipLaunchKernelGGL(fill_kernel, dim3(total_tiles), dim3(256), 0, st, d_jobs, njobs);
+  for (int t0 = 0; t0 < total_tiles; t0 += kMaxLaunchBlocks)
+    hipLaunchKernelGGL(fill_kernel, dim3(std::min(kMaxLaunchBlocks, total_tiles - t0)), dim3(256), 0, st, d_jobs,
+                       njobs, t0);
 }
 void launch_self(const SelfJob* d_jobs, int njobs, int total_tiles, int a_excl, hipStream_t st) {
-  if (total_tiles > 0)
-    hipLaunchKernelGGL(self_kernel, dim3(total_tiles), dim3(256), 0, st, d_jobs, njobs, a_excl);
+  for (int t0 = 0; t0 < total_tiles; t0 += kMaxLaunchBlocks)
+    hipLaunchKernelGGL(self_kernel, dim3(std::min(kMaxLaunchBlocks, total_tiles - t0)), dim3(256), 0, st, d_jobs,
+                       njobs, a_excl, t0);
 }
 void launch_alpert(const AlpertJob* d_jobs, int njobs, int total_blocks, int a_excl, hipStream_t st) {
-  if (total_blocks > 0)
-    hipLaunchKernelGGL(alpert_kernel, dim3(total_blocks), dim3(64), 0, st, d_jobs, njobs, a_excl);
+  for (int b0 = 0; b0 < total_blocks; b0 += kMaxLaunchBlocks)
+    hipLaunchKernelGGL(alpert_kernel, dim3(std::min(kMaxLaunchBlocks, total_blocks - b0)), dim3(64), 0, st, d_jobs,
+                       njobs, a_excl, b0);
 }
 void launch_assemble(const AsmJob* d_jobs, int njobs, int64_t total_elems, hipStream_t st) {
+  const int64_t blocks = std::min<int64_t>((total_elems + 255) / 256, int64_t(1) << 20);
   if (total_elems > 0)
-    hipLaunchKernelGGL(assemble_kernel, dim3((unsigned)((total_elems + 255) / 256)), dim3(256), 0, st, d_jobs,
-                       njobs, total_elems);
+    hipLaunchKernelGGL(assemble_kernel, dim3((unsigned)blocks), dim3(256), 0, st, d_jobs, njobs, total_elems);
 }
 void launch_hankel_eval(const double* x, double* out, int n, hipStream_t st) {
   if (n > 0) hipLaunchKernelGGL(hankel_eval_kernel, dim3((n + 255) / 256), dim3(256), 0, st, x, out, n);

@@ -10,6 +10,8 @@
 //                   incident-field right-hand side f (Sec. 2.2).
 //  bragg_kernel     a^U = -[X_1 eta_1]_a, a^D = -[X_{I+1} eta_I]_a (Sec. 3.3)
 //                   and the flux error eq. (86).
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace mlh {
@@ -47,9 +49,10 @@ __device__ inline double wave_sum(double v) {
 constexpr int kGT = 32;
 constexpr int kGK = 16;
 
-__global__ __launch_bounds__(256) void zgemm_kernel(const GemmDesc* __restrict__ descs, int ndesc) {
-  const GemmDesc& G = descs[find_tile(descs, ndesc, (int)blockIdx.x)];
-  const int lt = blockIdx.x - G.tile_begin;
+__global__ __launch_bounds__(256) void zgemm_kernel(const GemmDesc* __restrict__ descs, int ndesc, int tile0) {
+  const int tile = tile0 + (int)blockIdx.x;
+  const GemmDesc& G = descs[find_tile(descs, ndesc, tile)];
+  const int lt = tile - G.tile_begin;
   const int row0 = (lt % G.tiles_m) * kGT, col0 = (lt / G.tiles_m) * kGT;
   __shared__ double Ar[kGK][kGT + 1], Ai[kGK][kGT + 1];
   __shared__ double Br[kGK][kGT + 1], Bi[kGK][kGT + 1];
@@ -188,7 +191,9 @@ __global__ __launch_bounds__(64) void bragg_kernel(const AngleDesc* __restrict__
 }
 
 void launch_gemm(const GemmDesc* d_desc, int ndesc, int total_tiles, hipStream_t st) {
-  if (total_tiles > 0) hipLaunchKernelGGL(zgemm_kernel, dim3(total_tiles), dim3(256), 0, st, d_desc, ndesc);
+  for (int t0 = 0; t0 < total_tiles; t0 += kMaxLaunchBlocks)
+    hipLaunchKernelGGL(zgemm_kernel, dim3(std::min(kMaxLaunchBlocks, total_tiles - t0)), dim3(256), 0, st, d_desc,
+                       ndesc, t0);
 }
 void launch_rb_setup(const AngleDesc* d_ang, int nang, StackConsts sc, hipStream_t st) {
   if (nang > 0) hipLaunchKernelGGL(rb_setup_kernel, dim3(nang), dim3(256), 0, st, d_ang, sc);

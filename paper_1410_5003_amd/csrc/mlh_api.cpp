@@ -1104,6 +1104,8 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
   int B = n_sys;
   const size_t budget = (size_t)(0.8 * (double)(freeb + s->wbytes));
   while (B > 1 && (size_t)B * (per + desc_per) > budget) B = (B + 1) / 2;
+  // batched launches put one matrix per grid row: at most 65535 of them
+  while (B > 1 && (size_t)B * (I + 1) > 65535) B = (B + 1) / 2;
   const size_t need = (size_t)B * (per + desc_per) + 4096;
   if (need > s->wbytes) {
     if (s->gexec) {
@@ -1866,7 +1868,11 @@ extern "C" mlh_status mlh_debug_get_work(mlh_stack s, int32_t which, int32_t ind
 }
 
 extern "C" mlh_status mlh_profile_step(mlh_stack s, double theta, mlh_profile* out) {
-  if (!s || !out) return fail(MLH_E_INVALID_ARG, "mlh_profile_step: NULL argument");
+  return mlh_profile_solve(s, 1, &theta, out);
+}
+
+extern "C" mlh_status mlh_profile_solve(mlh_stack s, int32_t n_angles, const double* theta, mlh_profile* out) {
+  if (!s || !out || !theta || n_angles < 1) return fail(MLH_E_INVALID_ARG, "mlh_profile_solve: bad arguments");
   std::memset(out, 0, sizeof(*out));
   HIP_TRY(hipSetDevice(s->ctx->device));
   hipStream_t st = s->ctx->stream;
@@ -1887,10 +1893,10 @@ extern "C" mlh_status mlh_profile_step(mlh_stack s, double theta, mlh_profile* o
   HIP_TRY(hipGetLastError());
   T.collect();
   const int nK = 2 * s->K + 1;
-  std::vector<double> aU(2 * nK), aD(2 * nK);
-  std::vector<int> ord(nK);
-  double fl = 0;
-  mlh_status r = solve_impl(s, 1, &theta, aU.data(), aD.data(), ord.data(), &fl, 0, out);
+  std::vector<double> aU((size_t)2 * nK * n_angles), aD((size_t)2 * nK * n_angles);
+  std::vector<int> ord((size_t)nK * n_angles);
+  std::vector<double> fl(n_angles);
+  mlh_status r = solve_impl(s, n_angles, theta, aU.data(), aD.data(), ord.data(), fl.data(), 0, out);
   HIP_TRY(hipEventRecord(e1, st));
   HIP_TRY(hipEventSynchronize(e1));
   float ms = 0;

@@ -250,3 +250,29 @@ def small_mixed_stack(seed: int = 7, I: int = 4, N_smooth: int = 72, seg_scale: 
     n[0] = 1.0
     return Stack("small_mixed", d, omega * n, ifs, y_U=spacing, y_D=-spacing * I,
                  P=P, R=1.5 * d, M_w=M_w, M_ud=M_ud, K=K, thetas=np.array([theta]))
+
+
+def kappa_grid_thetas(stack: Stack, n_angles: int = 100, n_alpha: int = 20, span: float = 0.6) -> np.ndarray:
+    """Incident angles whose kappa_0 = k_1 cos(theta) lie on a uniform grid of
+    spacing 2 pi/(n_alpha d) centred on 0: the grid holds exactly n_alpha
+    distinct Bloch phases alpha, each shared by every n_alpha-th angle.  The
+    grid must fit in (-span k_1, span k_1).  Its offset (a multiple of
+    spacing/64) keeps every order kappa_0 + 2 pi n/d furthest from the
+    grazing points +-k_1 and +-k_{I+1}."""
+    d = stack.d
+    g = 2 * np.pi / (n_alpha * d)
+    if (n_angles - 1) * g > 2 * span * stack.k[0]:
+        raise ValueError("grid does not fit inside (-span k_1, span k_1)")
+    base = -0.5 * (n_angles - 1) * g + g * np.arange(n_angles)
+    period = 2 * np.pi / d
+    best, off_best = -1.0, 0.0
+    for t in range(64):
+        off = g * t / 64
+        worst = np.inf
+        for kk in (stack.k[0], stack.k[-1]):
+            for sgn in (1.0, -1.0):
+                r = np.mod(base + off - sgn * kk, period)
+                worst = min(worst, float(np.min(np.minimum(r, period - r))))
+        if worst > best:
+            best, off_best = worst, off
+    return -np.arccos((base + off_best) / stack.k[0])
