@@ -93,17 +93,21 @@ def algorithmic_work(desc):
     nK = 2 * K + 1
     nb = 16
     w = {}
-    gu = gp = 0.0
+    # block Thomas sweep in Gauss-Jordan form: interface i applies the inverse
+    # of its diagonal block to [A'_{i,i+1} | f_i] (n_{i+1} + 1 columns)
+    gu = gp = gr = 0.0
     for i in range(I):
-        width = n[i] + (n[i + 1] if i + 1 < I else 0) + 1
+        rhs = (n[i + 1] if i + 1 < I else 0) + 1
         for k in range(0, n[i], nb):
             b = min(nb, n[i] - k)
-            rest = width - k - b
+            rest = n[i] - k - b
             gu += 8.0 * n[i] * rest * b + 8.0 * b * b * rest
             L = n[i] - k
             gp += 4.0 * L * b * b + 4.0 * (L - b) * b * b
+            gr += 8.0 * n[i] * rhs * b + 8.0 * b * b * rhs
     w["gje_update"] = gu
     w["gje_panel"] = gp
+    w["gje_rhs"] = gr
     w["sweep_gemm"] = sum(8.0 * n[i] * (n[i] + 1) * n[i - 1] for i in range(1, I))
     w["schur"] = sum(8.0 * P * 2 * n[i] * n[i] for i in range(I)) + \
         sum(8.0 * P * 2 * n[i] * n[i + 1] for i in range(I - 1))
@@ -131,6 +135,7 @@ def algorithmic_work(desc):
 
 GROUPS = [  # (name, profile time key, launch-count key, work key, bound)
     ("gje_update_kernel", "gje_update_ms", "n_gje_update", "gje_update", "mfma"),
+    ("gje_rhs_kernel", "gje_rhs_ms", None, "gje_rhs", "mfma"),
     ("gje_panel_kernel", "gje_panel_ms", "n_gje_panel", "gje_panel", "alu"),
     ("zgemm_kernel (sweep update)", "sweep_gemm_ms", "n_sweep_gemm", "sweep_gemm", "mfma"),
     ("zgemm_kernel (Schur complements)", "schur_ms", None, "schur", "mfma"),

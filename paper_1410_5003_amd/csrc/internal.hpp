@@ -165,10 +165,14 @@ constexpr int kGjeNb = 16;  // panel width
 constexpr int kGjeCols = 32;  // trailing columns per update workgroup
 constexpr int kGjeMaxN = 608; // largest block order whose panel fits in LDS (N_i <= 304)
 
+constexpr int kRhsCols = 16;       // right-hand-side columns per gje_rhs_kernel workgroup
+constexpr int kGjePivStride = 68;  // ints per step: count, 2 NB destinations, 2 NB sources
+
+// one matrix W = [D | right-hand sides] (n x ncol, ld n) reduced to [. | D^{-1} rhs]
 struct GjeDesc {
   cplx* W;
-  cplx* M1;   // scratch kGjeNb x kGjeNb: inverse of the pivot block
-  int* piv;   // scratch 1 + 4 kGjeNb ints: the current step's row interchanges
+  cplx* M1;   // scratch ceil(n/NB) x NB x NB: inverse of each step's pivot block
+  int* piv;   // scratch ceil(n/NB) x kGjePivStride: each step's row interchanges
   int* info;  // set to (global column + 1) on an exactly zero pivot
   int n, ncol;
 };
@@ -188,7 +192,8 @@ struct GemvDesc {
 
 void gje_init();
 void launch_gje_panel(const GjeDesc* d, int nbatch, int k, int max_n, hipStream_t st);
-void launch_gje_update(const GjeDesc* d, int nbatch, int k, int max_ncol, hipStream_t st);
+void launch_gje_update(const GjeDesc* d, int nbatch, int k, int max_n, hipStream_t st);
+void launch_gje_rhs(const GjeDesc* d, int nbatch, int max_rhs, hipStream_t st);
 void launch_gemv_step(const GemvDesc* d, int nbatch, int max_n, int max_r, hipStream_t st);
 
 }  // namespace mlh

@@ -14,9 +14,16 @@
 //                      The multipliers of the update are the panel values
 //                      themselves (original values for rows >= k, current
 //                      values above k), read from W;
-//   gje_update_kernel  one workgroup per 32 trailing columns: applies the row
-//                      swaps, Z = M1 Y(pivot rows), Y(other rows) -= P Z on the
-//                      FP64 matrix cores, Y(pivot rows) = Z.
+//   gje_update_kernel  one workgroup per 32 trailing columns of the diagonal
+//                      block: applies the row swaps, Z = M1 Y(pivot rows),
+//                      Y(other rows) -= P Z on the FP64 matrix cores,
+//                      Y(pivot rows) = Z.
+//   gje_rhs_kernel     after the last step: one workgroup per 16 right-hand-
+//                      side columns keeps its (n x 16) tile in LDS and applies
+//                      every step's interchanges and update to it, reading the
+//                      multipliers P (the panel columns of W, unchanged after
+//                      their step) and M1 of each step.  The right-hand sides
+//                      thus cross HBM once instead of once per step.
 #include "internal.hpp"
 
 namespace mlh {
@@ -224,11 +231,12 @@ __global__ __launch_bounds__(kPanelThreads) void gje_panel_kernel(const GjeDesc*
         ++nxt;
       }
     }
-    D.piv[0] = na;
+    int* piv = D.piv + (size_t)(k / kGjeNb) * kGjePivStride;
+    piv[0] = na;
     snaff = na;
     for (int t = 0; t < na; ++t) {
-      D.piv[1 + t] = sdst[t];
-      D.piv[1 + 2 * kGjeNb + t] = ssrc[t];
+      piv[1 + t] = sdst[t];
+      piv[1 + 2 * kGjeNb + t] = ssrc[t];
     }
   }
   __syncthreads();
@@ -277,8 +285,9 @@ __global__ __launch_bounds__(kPanelThreads) void gje_panel_kernel(const GjeDesc*
       const double2 d = ur[r];
       x[r] = (r < nb && (d.x != 0.0 || d.y != 0.0)) ? cmul2(x[r], cinv2(d)) : make_double2(0.0, 0.0);
     }
+    cplx* M1 = D.M1 + (size_t)(k / kGjeNb) * kGjeNb * kGjeNb;
 #pragma unroll
-    for (int r = 0; r < kGjeNb; ++r) gst(D.M1 + (size_t)tid * kGjeNb + r, (tid < nb) ? x[r] : make_double2(0.0, 0.0));
+    for (int r = 0; r < kGjeNb; ++r) gst(M1 + (size_t)tid * kGjeNb + r, (tid < nb) ? x[r] : make_double2(0.0, 0.0));
   }
 }
 
@@ -288,8 +297,10 @@ __global__ __launch_bounds__(kUpdThreads) void gje_update_kernel(const GjeDesc* 
   if (k >= n) return;
   const int nb = min(kGjeNb, n - k);
   const int c0 = k + nb + blockIdx.x * kGjeCols;
-  if (c0 >= D.ncol) return;
-  const int nc = min(kGjeCols, D.ncol - c0);
+  if (c0 >= n) return;  // right-hand-side columns: gje_rhs_kernel, after all steps
+  const int nc = min(kGjeCols, n - c0);
+  const int* piv = D.piv + (size_t)(k / kGjeNb) * kGjePivStride;
+  const cplx* M1 = D.M1 + (size_t)(k / kGjeNb) * kGjeNb * kGjeNb;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   cplx* W = D.W;
   __shared__ double zr[kGjeNb][kGjeCols + 1], zi[kGjeNb][kGjeCols + 1];
@@ -299,12 +310,12 @@ __global__ __launch_bounds__(kUpdThreads) void gje_update_kernel(const GjeDesc* 
   //    pairs composed by the panel kernel: stage the sources, then write back
   __shared__ int sdst[2 * kGjeNb], ssrc[2 * kGjeNb];
   __shared__ double2 stage[2 * kGjeNb][kGjeCols];
-  const int naff = D.piv[0];
+  const int naff = piv[0];
   if (tid < naff) {
-    sdst[tid] = D.piv[1 + tid];
-    ssrc[tid] = D.piv[1 + 2 * kGjeNb + tid];
+    sdst[tid] = piv[1 + tid];
+    ssrc[tid] = piv[1 + 2 * kGjeNb + tid];
   }
-  for (int e = tid; e < kGjeNb * kGjeNb; e += kUpdThreads) m1[e % kGjeNb][e / kGjeNb] = gld(D.M1 + e);
+  for (int e = tid; e < kGjeNb * kGjeNb; e += kUpdThreads) m1[e % kGjeNb][e / kGjeNb] = gld(M1 + e);
   __syncthreads();
   for (int e = tid; e < naff * nc; e += kUpdThreads) {
     const int t = e % naff, c = e / naff;
@@ -415,6 +426,117 @@ __global__ __launch_bounds__(256) void gemv_step_kernel(const GemvDesc* __restri
   }
 }
 
+// Right-hand-side kernel: 8 wavefronts, wave w owns the 16-row blocks
+// w, w + 8, ... of the LDS tile.  Per step each wave loads the multipliers of
+// its blocks and M1 into registers first (their latency overlaps the row
+// interchanges), forms Z = M1 Y(pivot rows) itself on the matrix cores (the
+// accumulator layout of Z is exactly the B-operand layout of the update
+// product), then updates its blocks in LDS.
+constexpr int kRhsWaves = 8;
+constexpr int kRhsBlocks = (kGjeMaxN / 16 + kRhsWaves - 1) / kRhsWaves;  // row blocks per wave
+
+__global__ __launch_bounds__(kRhsWaves * 64) void gje_rhs_kernel(const GjeDesc* __restrict__ descs) {
+  const GjeDesc& D = descs[blockIdx.y];
+  const int n = D.n;
+  const int c0 = n + blockIdx.x * kRhsCols;
+  if (c0 >= D.ncol) return;
+  const int nc = min(kRhsCols, D.ncol - c0);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int lr = lane & 15, lq = lane >> 4;
+  cplx* W = D.W;
+  __shared__ double2 Y[kGjeMaxN][kRhsCols];
+  for (int e = tid; e < n * kRhsCols; e += kRhsWaves * 64) {
+    const int r = e % n, c = e / n;
+    Y[r][c] = c < nc ? gld(W + (size_t)(c0 + c) * n + r) : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  const int nsteps = (n + kGjeNb - 1) / kGjeNb;
+  for (int sidx = 0; sidx < nsteps; ++sidx) {
+    const int k = sidx * kGjeNb;
+    const int nb = min(kGjeNb, n - k);
+    const int* piv = D.piv + (size_t)sidx * kGjePivStride;
+    const cplx* M1 = D.M1 + (size_t)sidx * kGjeNb * kGjeNb;
+    // 0. operands of this step into registers: multipliers of my row blocks
+    //    (lane: row r0 + lr, column kk + lq) and M1 (lane: row lr, column kk + lq)
+    double2 pa[kRhsBlocks][4], ma[4];
+#pragma unroll
+    for (int j = 0; j < kRhsBlocks; ++j) {
+      const int row = (wave + j * kRhsWaves) * 16 + lr;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int kq = 4 * kk + lq;
+        pa[j][kk] = (row < n && kq < nb) ? gld(W + (size_t)(k + kq) * n + row) : make_double2(0.0, 0.0);
+      }
+    }
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) ma[kk] = gld(M1 + (size_t)(4 * kk + lq) * kGjeNb + lr);
+    // 1. this step's row interchanges (at most 2 NB pairs x 16 columns)
+    const int naff = piv[0];
+    const int e0 = tid;
+    const int cA = e0 % kRhsCols;
+    const int dA = e0 < naff * kRhsCols ? piv[1 + e0 / kRhsCols] : -1;
+    double2 vA = make_double2(0.0, 0.0);
+    if (dA >= 0) vA = Y[piv[1 + 2 * kGjeNb + e0 / kRhsCols]][cA];
+    __syncthreads();
+    if (dA >= 0) Y[dA][cA] = vA;
+    __syncthreads();
+    // 2. Z = M1 Y(pivot rows), rows of Y beyond nb read as zero
+    dvec4 zr = {0, 0, 0, 0}, zi = {0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int q = 4 * kk + lq;
+      const double2 b = q < nb ? Y[k + q][lr] : make_double2(0.0, 0.0);
+      const double2 a = ma[kk];
+      zr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, zr, 0, 0, 0);
+      zr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, zr, 0, 0, 0);
+      zi = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, zi, 0, 0, 0);
+      zi = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, zi, 0, 0, 0);
+    }
+    __syncthreads();  // every wave has read the pivot rows
+    // 3. Y(other rows) -= P Z; the pivot block (k is a multiple of 16, and
+    //    nb < 16 only in the last block) receives Z.  Register q of Z holds
+    //    row 4 q + lq, column lr: the B operand of step kk = q.
+#pragma unroll
+    for (int j = 0; j < kRhsBlocks; ++j) {
+      const int r0 = (wave + j * kRhsWaves) * 16;
+      if (r0 >= n) break;
+      if (r0 == k) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int rr = lq + 4 * q;
+          if (r0 + rr < n) Y[r0 + rr][lr] = make_double2(zr[q], zi[q]);
+        }
+        continue;
+      }
+      dvec4 accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const double2 a = pa[j][kk];
+        const double br = zr[kk], bi = zi[kk];
+        accr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, br, accr, 0, 0, 0);
+        accr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, bi, accr, 0, 0, 0);
+        acci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, bi, acci, 0, 0, 0);
+        acci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, br, acci, 0, 0, 0);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = r0 + lq + 4 * q;
+        if (row < n) {
+          double2 y = Y[row][lr];
+          y.x -= accr[q];
+          y.y -= acci[q];
+          Y[row][lr] = y;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < n * kRhsCols; e += kRhsWaves * 64) {
+    const int r = e % n, c = e / n;
+    if (c < nc) gst(W + (size_t)(c0 + c) * n + r, Y[r][c]);
+  }
+}
+
 void gje_init() {}
 
 void launch_gje_panel(const GjeDesc* d, int nbatch, int k, int max_n, hipStream_t st) {
@@ -422,10 +544,16 @@ void launch_gje_panel(const GjeDesc* d, int nbatch, int k, int max_n, hipStream_
   (void)lds;
   if (nbatch > 0 && max_n > k) hipLaunchKernelGGL(gje_panel_kernel, dim3(nbatch), dim3(kPanelThreads), 0, st, d, k);
 }
-void launch_gje_update(const GjeDesc* d, int nbatch, int k, int max_ncol, hipStream_t st) {
-  const int tiles = (max_ncol - k - 1) / kGjeCols + 1;
-  if (nbatch > 0 && max_ncol > k)
+void launch_gje_update(const GjeDesc* d, int nbatch, int k, int max_n, hipStream_t st) {
+  if (nbatch > 0 && max_n > k + kGjeNb) {
+    const int tiles = (max_n - k - kGjeNb - 1) / kGjeCols + 1;
     hipLaunchKernelGGL(gje_update_kernel, dim3(tiles, nbatch), dim3(kUpdThreads), 0, st, d, k);
+  }
+}
+void launch_gje_rhs(const GjeDesc* d, int nbatch, int max_rhs, hipStream_t st) {
+  if (nbatch > 0 && max_rhs > 0)
+    hipLaunchKernelGGL(gje_rhs_kernel, dim3((max_rhs + kRhsCols - 1) / kRhsCols, nbatch), dim3(kRhsWaves * 64), 0,
+                       st, d);
 }
 void launch_gemv_step(const GemvDesc* d, int nbatch, int max_n, int max_r, hipStream_t st) {
   if (nbatch > 0 && max_n > 0 && max_r > 0)

@@ -1085,8 +1085,9 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
     }
     for (int i = 0; i < I; ++i) R(cbytes((size_t)n[i] * rmax));
     for (int i = 0; i < I; ++i) {
-      R(cbytes((size_t)kGjeNb * kGjeNb));
-      R(sizeof(int) * (1 + 4 * kGjeNb));
+      const size_t steps = (size_t)(n[i] + kGjeNb - 1) / kGjeNb;
+      R(cbytes(steps * kGjeNb * kGjeNb));
+      R(sizeof(int) * steps * kGjePivStride);
     }
     R(cbytes((size_t)2 * nK * rmax));
     R(sizeof(double) * rmax);
@@ -1341,7 +1342,7 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
     //        L_j' = -L_j XL_{e_l},  U_j' = -U_j XU_{e_r}.
     struct Level {
       std::vector<GjeDesc> gje;
-      int maxn = 0, maxcol = 0;
+      int maxn = 0, maxcol = 0, maxrhs = 0;
       std::vector<GemmDesc> upd;
       int upd_tiles = 0;
       std::vector<GemvDesc> back;
@@ -1366,6 +1367,7 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
           G.ncol = n[j] + nLc[j] + nUc[j] + R_of(b);
           lv.gje.push_back(G);
           lv.maxcol = std::max(lv.maxcol, G.ncol);
+          lv.maxrhs = std::max(lv.maxrhs, G.ncol - G.n);
           GemvDesc Gv{};
           Gv.g = G.W + (size_t)n[j] * (n[j] + nLc[j] + nUc[j]);
           Gv.y = V[b].eta[j];
@@ -1390,6 +1392,7 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
           G.ncol = n[e] + nLc[e] + nUc[e] + R_of(b);
           lv.gje.push_back(G);
           lv.maxcol = std::max(lv.maxcol, G.ncol);
+          lv.maxrhs = std::max(lv.maxrhs, G.ncol - G.n);
           const cplx* X = G.W + (size_t)n[e] * n[e];
           GemvDesc Gv{};
           Gv.U1 = X;
@@ -1565,13 +1568,16 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
             launch_gje_panel(dg, ng, k, lv.maxn, ls);
             te();
             tb(prof ? &prof->gje_update_ms : nullptr);
-            launch_gje_update(dg, ng, k, lv.maxcol, ls);
+            launch_gje_update(dg, ng, k, lv.maxn, ls);
             te();
             if (prof) {
               prof->n_gje_panel++;
               prof->n_gje_update++;
             }
           }
+          tb(prof ? &prof->gje_rhs_ms : nullptr);
+          launch_gje_rhs(dg, ng, lv.maxrhs, ls);
+          te();
           if (!lv.upd.empty()) {
             tb(prof ? &prof->sweep_gemm_ms : nullptr);
             launch_gemm(reinterpret_cast<GemmDesc*>(dbase + o_upd[l]), (int)lv.upd.size(), lv.upd_tiles, ls);
@@ -1604,6 +1610,7 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
       for (const Level& lv : levels) {
         sig.push_back(lv.maxn);
         sig.push_back(lv.maxcol);
+        sig.push_back(lv.maxrhs);
         sig.push_back((int64_t)lv.gje.size());
         sig.push_back(lv.upd_tiles);
         sig.push_back((int64_t)lv.upd.size());
