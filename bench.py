@@ -121,7 +121,8 @@ def algorithmic_work(desc):
         qr += 8.0 * M * c * c - 8.0 * c ** 3 / 3.0
         ap += ncol * (16.0 * M * c - 4.0 * c * c)
     w["ls_panel"] = qr
-    w["ls_update"] = ap
+    w["ls_update"] = qr
+    w["ls_rhs"] = ap
     w["backsub"] = sum(8.0 * n[i] * n[i + 1] for i in range(I - 1))
     # fill: complex entries written (three copies for A and Z, two for C and Q)
     ent_self = sum(3 * n[i] * n[i] for i in range(I))
@@ -141,6 +142,7 @@ GROUPS = [  # (name, profile time key, launch-count key, work key, bound)
     ("zgemm_kernel (Schur complements)", "schur_ms", None, "schur", "mfma"),
     ("hq_panel_kernel", "ls_panel_ms", None, "ls_panel", "alu"),
     ("hq_update_kernel", "ls_update_ms", None, "ls_update", "alu"),
+    ("hq_rhs_kernel", "ls_rhs_ms", None, "ls_rhs", "mfma"),
     ("gemv_step_kernel", "backsub_ms", None, "backsub", "alu"),
     ("self_kernel", "fill_self_ms", None, "fill_self_bytes", "hbm"),
     ("fill_kernel", "fill_pairs_ms", None, "fill_pairs_bytes", "hbm"),

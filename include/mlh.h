@@ -181,7 +181,7 @@ mlh_status mlh_debug_get_work(mlh_stack s, int32_t which, int32_t index, double*
  * measured with HIP events on the context's stream around every launch. */
 typedef struct {
   double fill_self_ms, fill_alpert_ms, fill_pairs_ms;
-  double assemble_ms, rb_setup_ms, ls_panel_ms, ls_update_ms, ls_backsub_ms, schur_ms;
+  double assemble_ms, rb_setup_ms, ls_panel_ms, ls_update_ms, ls_rhs_ms, schur_ms;
   double sweep_gemm_ms, gje_panel_ms, gje_update_ms, gje_rhs_ms, backsub_ms, bragg_ms;
   int32_t n_sweep_gemm, n_gje_panel, n_gje_update;
   double total_ms;

@@ -48,7 +48,7 @@ class mlh_stack_desc(C.Structure):
 class mlh_profile(C.Structure):
     _fields_ = [(n, C.c_double) for n in (
         "fill_self_ms", "fill_alpert_ms", "fill_pairs_ms", "assemble_ms", "rb_setup_ms", "ls_panel_ms",
-        "ls_update_ms", "ls_backsub_ms", "schur_ms", "sweep_gemm_ms", "gje_panel_ms", "gje_update_ms", "gje_rhs_ms", "backsub_ms",
+        "ls_update_ms", "ls_rhs_ms", "schur_ms", "sweep_gemm_ms", "gje_panel_ms", "gje_update_ms", "gje_rhs_ms", "backsub_ms",
         "bragg_ms")] + \
         [("n_sweep_gemm", C.c_int32), ("n_gje_panel", C.c_int32), ("n_gje_update", C.c_int32),
          ("total_ms", C.c_double)]

@@ -207,11 +207,11 @@ namespace mlh {
 constexpr int kHqNb = 16;
 constexpr int kHqCols = 32;
 constexpr int kHqMaxRows = 512;  // M  (LDS holds an M x 16 panel)
-constexpr int kHqMaxC = 256;     // c  (LDS holds a c x 32 back-substitution tile)
+constexpr int kHqMaxC = 256;     // c  (proxy plus Bragg unknowns of one layer)
 
 struct HqDesc {
   cplx* A;
-  cplx* T;    // scratch 16 x 16: block reflector factor of the current panel
+  cplx* T;    // scratch ceil(c/16) x 16 x 16: block reflector factor T of each panel
   double mu_rel;
   int m, c, ncol;
 };
@@ -219,6 +219,6 @@ struct HqDesc {
 void launch_hq_prep(const HqDesc* d, int n, hipStream_t st);
 void launch_hq_panel(const HqDesc* d, int n, int k, hipStream_t st);
 void launch_hq_update(const HqDesc* d, int n, int k, int max_cols, hipStream_t st);
-void launch_hq_backsub(const HqDesc* d, int n, int max_ncol, hipStream_t st);
+void launch_hq_rhs(const HqDesc* d, int n, int max_ncol, hipStream_t st);
 
 }  // namespace mlh

@@ -8,11 +8,15 @@
 //   hq_panel_kernel    Householder QR of a 16-column panel in LDS, and the
 //                      triangular factor T of its block reflector
 //                      H = I - V T V^H (compact WY form);
-//   hq_update_kernel   every later column Y <- H^H Y = Y - V T^H (V^H Y),
-//                      the solve's right-hand sides included, 32 columns per
-//                      workgroup, one wavefront per column;
-//   hq_backsub_kernel  R X = (Q^H C)[0:c] by back substitution, 32 columns
-//                      per workgroup with the tile in LDS.
+//   hq_update_kernel   the later columns of S: Y <- H^H Y = Y - V T^H (V^H Y),
+//                      32 columns per workgroup, one wavefront per column;
+//   hq_rhs_kernel      after the last panel, one workgroup per 16 right-hand
+//                      sides: the (M x 16) tile stays in LDS while every block
+//                      reflector is applied to it and R X = (Q^H C)[0:c] is
+//                      solved by 16-row blocks (substitution inside each
+//                      diagonal block, products on the FP64 matrix cores
+//                      elsewhere).  The right-hand sides cross HBM once
+//                      instead of once per panel.
 #include "internal.hpp"
 
 namespace mlh {
@@ -161,7 +165,8 @@ __global__ __launch_bounds__(256) void hq_panel_kernel(const HqDesc* __restrict_
     }
   }
   __syncthreads();
-  for (int e = tid; e < kHqNb * kHqNb; e += 256) hst(D.T + e, T[e % kHqNb][e / kHqNb]);
+  const int pidx = k / kHqNb;
+  for (int e = tid; e < kHqNb * kHqNb; e += 256) hst(D.T + (size_t)pidx * kHqNb * kHqNb + e, T[e % kHqNb][e / kHqNb]);
   for (int e = tid; e < L * nb; e += 256) {
     const int r = e % L, j = e / L;
     hst(A + (size_t)(k + j) * M + k + r, pan[r][j]);
@@ -176,7 +181,7 @@ __global__ __launch_bounds__(256) void hq_update_kernel(const HqDesc* __restrict
   if (k >= c) return;
   const int nb = min(kHqNb, c - k);
   const int L = M - k;
-  const int total = c + D.ncol;
+  const int total = c;  // right-hand sides: hq_rhs_kernel
   const int c0 = k + nb + blockIdx.x * kHqCols;
   if (c0 >= total) return;
   const int nc = min(kHqCols, total - c0);
@@ -195,7 +200,8 @@ __global__ __launch_bounds__(256) void hq_update_kernel(const HqDesc* __restrict
     }
     V[r][j] = v;
   }
-  for (int e = tid; e < kHqNb * kHqNb; e += 256) T[e % kHqNb][e / kHqNb] = hld(D.T + e);
+  const cplx* Tk = D.T + (size_t)(k / kHqNb) * kHqNb * kHqNb;  // this panel's T
+  for (int e = tid; e < kHqNb * kHqNb; e += 256) T[e % kHqNb][e / kHqNb] = hld(Tk + e);
   __syncthreads();
   __shared__ double2 wsh[4][kHqNb], ush[4][kHqNb];
   for (int cc = wave; cc < nc; cc += 4) {
@@ -250,46 +256,169 @@ __global__ __launch_bounds__(256) void hq_update_kernel(const HqDesc* __restrict
   }
 }
 
-__global__ __launch_bounds__(256) void hq_backsub_kernel(const HqDesc* __restrict__ descs) {
+typedef double hvec4 __attribute__((ext_vector_type(4)));
+
+// V of panel k as an MFMA operand value: column i, row r (global); unit
+// diagonal and zeros above it, Householder vectors below
+__device__ inline double2 hq_v(const cplx* A, int M, int k, int nb, int r, int i) {
+  if (i >= nb || r < k + i) return make_double2(0.0, 0.0);
+  if (r == k + i) return make_double2(1.0, 0.0);
+  return hld(A + (size_t)(k + i) * M + r);
+}
+
+constexpr int kHqRhsCols = 16;
+constexpr int kHqRhsWaves = 4;
+
+__global__ __launch_bounds__(kHqRhsWaves * 64) void hq_rhs_kernel(const HqDesc* __restrict__ descs) {
   const HqDesc& D = descs[blockIdx.y];
   const int c = D.c, M = D.m + c;
-  const int col0 = blockIdx.x * kHqCols;
+  const int col0 = blockIdx.x * kHqRhsCols;
   if (col0 >= D.ncol) return;
-  const int nc = min(kHqCols, D.ncol - col0);
-  const int tid = threadIdx.x;
-  __shared__ double2 z[kHqMaxC][kHqCols + 1];
-  __shared__ double2 xk[kHqCols];
-  cplx* A = D.A;
-  cplx* B = A + (size_t)c * M;  // right-hand sides start after the c columns of S
-  for (int e = tid; e < c * kHqCols; e += 256) {
-    const int r = e % c, j = e / c;
-    z[r][j] = j < nc ? hld(B + (size_t)(col0 + j) * M + r) : make_double2(0.0, 0.0);
+  const int nc = min(kHqRhsCols, D.ncol - col0);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int lr = lane & 15, lq = lane >> 4;
+  const cplx* A = D.A;
+  cplx* B = D.A + (size_t)c * M;  // right-hand sides start after the c columns of S
+  __shared__ double2 Y[kHqMaxRows][kHqRhsCols];
+  __shared__ double red[kHqRhsWaves][2][4][64];
+  for (int e = tid; e < M * kHqRhsCols; e += kHqRhsWaves * 64) {
+    const int r = e % M, j = e / M;
+    Y[r][j] = j < nc ? hld(B + (size_t)(col0 + j) * M + r) : make_double2(0.0, 0.0);
   }
   __syncthreads();
-  const int j = tid % kHqCols, rg = tid / kHqCols;  // 8 row groups
-  for (int kc = c - 1; kc >= 0; --kc) {
-    const cplx* rc = A + (size_t)kc * M;
-    if (tid < kHqCols) {
-      const double rkk = hld(rc + kc).x;
-      const double2 b = z[kc][tid];
-      const double2 x = make_double2(b.x / rkk, b.y / rkk);
-      xk[tid] = x;
-      z[kc][tid] = x;
+  const int npan = (c + kHqNb - 1) / kHqNb;
+  for (int p = 0; p < npan; ++p) {
+    const int k = p * kHqNb;
+    const int nb = min(kHqNb, c - k);
+    const cplx* Tp = D.T + (size_t)p * kHqNb * kHqNb;
+    // 1. partial w = V^H Y over this wave's 4-row steps of rows k..M-1
+    hvec4 wr = {0, 0, 0, 0}, wi = {0, 0, 0, 0};
+    for (int r0 = k + 4 * wave; r0 < M; r0 += 4 * kHqRhsWaves) {
+      const int r = r0 + lq;
+      const double2 v = r < M ? hq_v(A, M, k, nb, r, lr) : make_double2(0.0, 0.0);  // A[i=lr][k=r]
+      const double2 y = r < M ? Y[r][lr] : make_double2(0.0, 0.0);                  // B[k=r][col=lr]
+      // w = conj(V)^T Y
+      wr = __builtin_amdgcn_mfma_f64_16x16x4f64(v.x, y.x, wr, 0, 0, 0);
+      wr = __builtin_amdgcn_mfma_f64_16x16x4f64(v.y, y.y, wr, 0, 0, 0);
+      wi = __builtin_amdgcn_mfma_f64_16x16x4f64(v.x, y.y, wi, 0, 0, 0);
+      wi = __builtin_amdgcn_mfma_f64_16x16x4f64(-v.y, y.x, wi, 0, 0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      red[wave][0][q][lane] = wr[q];
+      red[wave][1][q][lane] = wi[q];
     }
     __syncthreads();
-    const double2 x = xk[j];
-    for (int r = rg; r < kc; r += 8) {
-      const double2 a = hld(rc + r);
-      double2 b = z[r][j];
-      b.x -= a.x * x.x - a.y * x.y;
-      b.y -= a.x * x.y + a.y * x.x;
-      z[r][j] = b;
+    // 2. full w in every wave (register q: row 4q + lq, column lr), then
+    //    u = T^H w on the matrix cores (the result is again in that layout)
+    double w_r[4], w_i[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double a = 0.0, b = 0.0;
+#pragma unroll
+      for (int w = 0; w < kHqRhsWaves; ++w) {
+        a += red[w][0][q][lane];
+        b += red[w][1][q][lane];
+      }
+      w_r[q] = a;
+      w_i[q] = b;
+    }
+    hvec4 ur = {0, 0, 0, 0}, ui = {0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int q = 4 * kk + lq;
+      const double2 t = hld(Tp + (size_t)lr * kHqNb + q);  // T[q][i = lr]; A = conj(T)^T
+      ur = __builtin_amdgcn_mfma_f64_16x16x4f64(t.x, w_r[kk], ur, 0, 0, 0);
+      ur = __builtin_amdgcn_mfma_f64_16x16x4f64(t.y, w_i[kk], ur, 0, 0, 0);
+      ui = __builtin_amdgcn_mfma_f64_16x16x4f64(t.x, w_i[kk], ui, 0, 0, 0);
+      ui = __builtin_amdgcn_mfma_f64_16x16x4f64(-t.y, w_r[kk], ui, 0, 0, 0);
+    }
+    // 3. Y(rows k..M-1) -= V u, 16-row blocks (k is a multiple of 16)
+    for (int r0 = k + 16 * wave; r0 < M; r0 += 16 * kHqRhsWaves) {
+      hvec4 ar = {0, 0, 0, 0}, ai = {0, 0, 0, 0};
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int i = 4 * kk + lq, r = r0 + lr;
+        const double2 v = r < M ? hq_v(A, M, k, nb, r, i) : make_double2(0.0, 0.0);
+        ar = __builtin_amdgcn_mfma_f64_16x16x4f64(v.x, ur[kk], ar, 0, 0, 0);
+        ar = __builtin_amdgcn_mfma_f64_16x16x4f64(-v.y, ui[kk], ar, 0, 0, 0);
+        ai = __builtin_amdgcn_mfma_f64_16x16x4f64(v.x, ui[kk], ai, 0, 0, 0);
+        ai = __builtin_amdgcn_mfma_f64_16x16x4f64(v.y, ur[kk], ai, 0, 0, 0);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = r0 + lq + 4 * q;
+        if (r < M) {
+          double2 y = Y[r][lr];
+          y.x -= ar[q];
+          y.y -= ai[q];
+          Y[r][lr] = y;
+        }
+      }
     }
     __syncthreads();
   }
-  for (int e = tid; e < c * kHqCols; e += 256) {
-    const int r = e % c, jj = e / c;
-    if (jj < nc) hst(B + (size_t)(col0 + jj) * M + r, z[r][jj]);
+  // 4. R X = Y(0:c) by 16-row blocks from the bottom: substitution inside
+  //    the diagonal block (one thread per column; R's diagonal spans the
+  //    Tikhonov scale, so no explicit block inverse), then
+  //    Y(rows above) -= R(rows above, block) X_b on the matrix cores
+  __shared__ double2 Rb[kHqNb][kHqNb + 1];
+  for (int b = npan - 1; b >= 0; --b) {
+    const int j0 = b * kHqNb;
+    const int nbb = min(kHqNb, c - j0);
+    {
+      const int r = tid % kHqNb, q = tid / kHqNb;
+      if (q < kHqNb) Rb[r][q] = (r < nbb && q < nbb && r <= q) ? hld(A + (size_t)(j0 + q) * M + j0 + r)
+                                                                : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    if (tid < kHqRhsCols) {
+      for (int r = nbb - 1; r >= 0; --r) {
+        double2 acc = Y[j0 + r][tid];
+        for (int q = r + 1; q < nbb; ++q) {
+          const double2 a = Rb[r][q], x = Y[j0 + q][tid];
+          acc.x -= a.x * x.x - a.y * x.y;
+          acc.y -= a.x * x.y + a.y * x.x;
+        }
+        const double2 d = Rb[r][r];
+        const double dd = d.x * d.x + d.y * d.y;
+        Y[j0 + r][tid] = make_double2((acc.x * d.x + acc.y * d.y) / dd, (acc.y * d.x - acc.x * d.y) / dd);
+      }
+    }
+    __syncthreads();
+    double xr[4], xi[4];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int q = 4 * kk + lq;
+      const double2 x = q < nbb ? Y[j0 + q][lr] : make_double2(0.0, 0.0);
+      xr[kk] = x.x;
+      xi[kk] = x.y;
+    }
+    for (int r0 = 16 * wave; r0 < j0; r0 += 16 * kHqRhsWaves) {
+      hvec4 ar = {0, 0, 0, 0}, ai = {0, 0, 0, 0};
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int q = 4 * kk + lq;
+        const double2 a = q < nbb ? hld(A + (size_t)(j0 + q) * M + r0 + lr) : make_double2(0.0, 0.0);
+        ar = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, xr[kk], ar, 0, 0, 0);
+        ar = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, xi[kk], ar, 0, 0, 0);
+        ai = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, xi[kk], ai, 0, 0, 0);
+        ai = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, xr[kk], ai, 0, 0, 0);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = r0 + lq + 4 * q;
+        double2 y = Y[r][lr];
+        y.x -= ar[q];
+        y.y -= ai[q];
+        Y[r][lr] = y;
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < c * kHqRhsCols; e += kHqRhsWaves * 64) {
+    const int r = e % c, j = e / c;
+    if (j < nc) hst(B + (size_t)(col0 + j) * M + r, Y[r][j]);
   }
 }
 
@@ -303,9 +432,10 @@ void launch_hq_update(const HqDesc* d, int n, int k, int max_cols, hipStream_t s
   const int tiles = (max_cols - k - 1) / kHqCols + 1;
   if (n > 0 && tiles > 0) hipLaunchKernelGGL(hq_update_kernel, dim3(tiles, n), dim3(256), 0, st, d, k);
 }
-void launch_hq_backsub(const HqDesc* d, int n, int max_ncol, hipStream_t st) {
-  const int tiles = (max_ncol + kHqCols - 1) / kHqCols;
-  if (n > 0 && tiles > 0) hipLaunchKernelGGL(hq_backsub_kernel, dim3(tiles, n), dim3(256), 0, st, d);
+void launch_hq_rhs(const HqDesc* d, int n, int max_ncol, hipStream_t st) {
+  const int tiles = (max_ncol + kHqRhsCols - 1) / kHqRhsCols;
+  if (n > 0 && tiles > 0)
+    hipLaunchKernelGGL(hq_rhs_kernel, dim3(tiles, n), dim3(kHqRhsWaves * 64), 0, st, d);
 }
 
 }  // namespace mlh

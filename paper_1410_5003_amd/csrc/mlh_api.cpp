@@ -1081,7 +1081,7 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
       int m, c, nc;
       layer_dims(s, j, m, c, nc);
       R(cbytes((size_t)(m + c) * (c + nc)));  // [S | RHS]
-      R(cbytes((size_t)kHqNb * kHqNb));
+      R(cbytes((size_t)((c + kHqNb - 1) / kHqNb) * kHqNb * kHqNb));
     }
     for (int i = 0; i < I; ++i) R(cbytes((size_t)n[i] * rmax));
     for (int i = 0; i < I; ++i) {
@@ -1546,11 +1546,11 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
           launch_hq_panel(d_hq, nhq, k, ls);
           te();
           tb(prof ? &prof->ls_update_ms : nullptr);
-          launch_hq_update(d_hq, nhq, k, maxcols, ls);
+          launch_hq_update(d_hq, nhq, k, maxc, ls);
           te();
         }
-        tb(prof ? &prof->ls_backsub_ms : nullptr);
-        launch_hq_backsub(d_hq, nhq, maxncol, ls);
+        tb(prof ? &prof->ls_rhs_ms : nullptr);
+        launch_hq_rhs(d_hq, nhq, maxncol, ls);
         te();
       }
       if (stop_phase == 0 || stop_phase >= 3) {
