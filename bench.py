@@ -29,7 +29,7 @@ METRIC = "multilayer solves/s (unknowns/s) at flux err ≤1e-9; adjoint grads/s;
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFS = 78.6
 
-RES3 = dict(N_smooth=260, N_corner=300, P=140, M_w=100)
+RES3 = dict(N_smooth=260, N_corner=500, P=140, M_w=100)
 WORKLOADS = {
     # name: (generator name, kwargs, description, angles of one step)
     #   angles: "first" = the generator's single angle, "all" = its angle list,
@@ -41,7 +41,7 @@ WORKLOADS = {
                          "I=2 sine interfaces, N=160, P=140, M_w=100, M_ud=60, K=25", "first"),
     "config1": ("config1", dict(), "I=2 sine interfaces, N=120, P=60, M_w=60, M_ud=60, K=25", "first"),
     "config3_resolved": ("config3", RES3,
-                         "I=1000, 70% random Fourier (N=260) / 30% cornered (N=300, Kress q=6), P=140, M_w=100, "
+                         "I=1000, 70% random Fourier (N=260) / 30% cornered (N=500, Kress q=6), P=140, M_w=100, "
                          "M_ud=60, K=25; sweep of 100 angles uniform in (-pi/2, 0)", "all"),
     "config3_kgrid_resolved": ("config3", RES3,
                                "I=1000 stack of config3_resolved; sweep of 100 angles on a kappa_0 grid of "

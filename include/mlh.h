@@ -75,7 +75,7 @@ enum { MLH_IFACE_FOURIER = 0, MLH_IFACE_POLYGON = 1 };
  *          (Alpert's rule, periodic in s, no Bloch phase); segments interact
  *          through plain Nystrom entries.  A grading so strong that two nodes
  *          coincide in float64 is rejected (MLH_E_INVALID_ARG).
- * Both kinds: at most 304 nodes per interface (MLH_E_UNSUPPORTED beyond). */
+ * Both kinds: at most 512 nodes per interface (MLH_E_UNSUPPORTED beyond). */
 typedef struct {
   int32_t kind;
   double y0;

@@ -163,9 +163,8 @@ constexpr double kAlphaTol = 1e-12;
 
 constexpr int kGjeNb = 16;  // panel width
 constexpr int kGjeCols = 32;  // trailing columns per update workgroup
-constexpr int kGjeMaxN = 608; // largest block order whose panel fits in LDS (N_i <= 304)
+constexpr int kGjeMaxN = 1024; // largest block order: the panel kernel holds 2 rows per thread (N_i <= 512)
 
-constexpr int kRhsCols = 16;       // right-hand-side columns per gje_rhs_kernel workgroup
 constexpr int kGjePivStride = 68;  // ints per step: count, 2 NB destinations, 2 NB sources
 
 // one matrix W = [D | right-hand sides] (n x ncol, ld n) reduced to [. | D^{-1} rhs]
@@ -193,7 +192,7 @@ struct GemvDesc {
 void gje_init();
 void launch_gje_panel(const GjeDesc* d, int nbatch, int k, int max_n, hipStream_t st);
 void launch_gje_update(const GjeDesc* d, int nbatch, int k, int max_n, hipStream_t st);
-void launch_gje_rhs(const GjeDesc* d, int nbatch, int max_rhs, hipStream_t st);
+void launch_gje_rhs(const GjeDesc* d, int nbatch, int max_rhs, int max_n, hipStream_t st);
 void launch_gemv_step(const GemvDesc* d, int nbatch, int max_n, int max_r, hipStream_t st);
 
 }  // namespace mlh

@@ -18,8 +18,8 @@
 //                      block: applies the row swaps, Z = M1 Y(pivot rows),
 //                      Y(other rows) -= P Z on the FP64 matrix cores,
 //                      Y(pivot rows) = Z.
-//   gje_rhs_kernel     after the last step: one workgroup per 16 right-hand-
-//                      side columns keeps its (n x 16) tile in LDS and applies
+//   gje_rhs_kernel     after the last step: one workgroup per 16 (8 for
+//                      n > 608) right-hand-side columns keeps its tile in LDS and applies
 //                      every step's interchanges and update to it, reading the
 //                      multipliers P (the panel columns of W, unchanged after
 //                      their step) and M1 of each step.  The right-hand sides
@@ -433,19 +433,25 @@ __global__ __launch_bounds__(256) void gemv_step_kernel(const GemvDesc* __restri
 // accumulator layout of Z is exactly the B-operand layout of the update
 // product), then updates its blocks in LDS.
 constexpr int kRhsWaves = 8;
-constexpr int kRhsBlocks = (kGjeMaxN / 16 + kRhsWaves - 1) / kRhsWaves;  // row blocks per wave
+constexpr int kRhsMaxN16 = 608;  // largest order whose 16-column tile fits in LDS
 
+// TC right-hand-side columns per workgroup (16, or 8 for orders up to
+// kGjeMaxN, whose 16-column tile would not fit in LDS: then lanes of columns
+// 8..15 carry zeros through the 16-wide matrix-core products)
+template <int TC, int MAXN>
 __global__ __launch_bounds__(kRhsWaves * 64) void gje_rhs_kernel(const GjeDesc* __restrict__ descs) {
+  constexpr int NBLK = (MAXN / 16 + kRhsWaves - 1) / kRhsWaves;  // row blocks per wave
   const GjeDesc& D = descs[blockIdx.y];
   const int n = D.n;
-  const int c0 = n + blockIdx.x * kRhsCols;
+  const int c0 = n + blockIdx.x * TC;
   if (c0 >= D.ncol) return;
-  const int nc = min(kRhsCols, D.ncol - c0);
+  const int nc = min(TC, D.ncol - c0);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int lr = lane & 15, lq = lane >> 4;
+  const bool cl = lr < TC;
   cplx* W = D.W;
-  __shared__ double2 Y[kGjeMaxN][kRhsCols];
-  for (int e = tid; e < n * kRhsCols; e += kRhsWaves * 64) {
+  __shared__ double2 Y[MAXN][TC];
+  for (int e = tid; e < n * TC; e += kRhsWaves * 64) {
     const int r = e % n, c = e / n;
     Y[r][c] = c < nc ? gld(W + (size_t)(c0 + c) * n + r) : make_double2(0.0, 0.0);
   }
@@ -458,9 +464,9 @@ __global__ __launch_bounds__(kRhsWaves * 64) void gje_rhs_kernel(const GjeDesc* 
     const cplx* M1 = D.M1 + (size_t)sidx * kGjeNb * kGjeNb;
     // 0. operands of this step into registers: multipliers of my row blocks
     //    (lane: row r0 + lr, column kk + lq) and M1 (lane: row lr, column kk + lq)
-    double2 pa[kRhsBlocks][4], ma[4];
+    double2 pa[NBLK][4], ma[4];
 #pragma unroll
-    for (int j = 0; j < kRhsBlocks; ++j) {
+    for (int j = 0; j < NBLK; ++j) {
       const int row = (wave + j * kRhsWaves) * 16 + lr;
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
@@ -470,13 +476,13 @@ __global__ __launch_bounds__(kRhsWaves * 64) void gje_rhs_kernel(const GjeDesc* 
     }
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) ma[kk] = gld(M1 + (size_t)(4 * kk + lq) * kGjeNb + lr);
-    // 1. this step's row interchanges (at most 2 NB pairs x 16 columns)
+    // 1. this step's row interchanges (at most 2 NB pairs x TC columns)
     const int naff = piv[0];
     const int e0 = tid;
-    const int cA = e0 % kRhsCols;
-    const int dA = e0 < naff * kRhsCols ? piv[1 + e0 / kRhsCols] : -1;
+    const int cA = e0 % TC;
+    const int dA = e0 < naff * TC ? piv[1 + e0 / TC] : -1;
     double2 vA = make_double2(0.0, 0.0);
-    if (dA >= 0) vA = Y[piv[1 + 2 * kGjeNb + e0 / kRhsCols]][cA];
+    if (dA >= 0) vA = Y[piv[1 + 2 * kGjeNb + e0 / TC]][cA];
     __syncthreads();
     if (dA >= 0) Y[dA][cA] = vA;
     __syncthreads();
@@ -485,7 +491,7 @@ __global__ __launch_bounds__(kRhsWaves * 64) void gje_rhs_kernel(const GjeDesc* 
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
       const int q = 4 * kk + lq;
-      const double2 b = q < nb ? Y[k + q][lr] : make_double2(0.0, 0.0);
+      const double2 b = (q < nb && cl) ? Y[k + q][lr] : make_double2(0.0, 0.0);
       const double2 a = ma[kk];
       zr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, zr, 0, 0, 0);
       zr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, zr, 0, 0, 0);
@@ -497,14 +503,14 @@ __global__ __launch_bounds__(kRhsWaves * 64) void gje_rhs_kernel(const GjeDesc* 
     //    nb < 16 only in the last block) receives Z.  Register q of Z holds
     //    row 4 q + lq, column lr: the B operand of step kk = q.
 #pragma unroll
-    for (int j = 0; j < kRhsBlocks; ++j) {
+    for (int j = 0; j < NBLK; ++j) {
       const int r0 = (wave + j * kRhsWaves) * 16;
       if (r0 >= n) break;
       if (r0 == k) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int rr = lq + 4 * q;
-          if (r0 + rr < n) Y[r0 + rr][lr] = make_double2(zr[q], zi[q]);
+          if (cl && r0 + rr < n) Y[r0 + rr][lr] = make_double2(zr[q], zi[q]);
         }
         continue;
       }
@@ -521,7 +527,7 @@ __global__ __launch_bounds__(kRhsWaves * 64) void gje_rhs_kernel(const GjeDesc* 
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int row = r0 + lq + 4 * q;
-        if (row < n) {
+        if (cl && row < n) {
           double2 y = Y[row][lr];
           y.x -= accr[q];
           y.y -= acci[q];
@@ -531,7 +537,7 @@ __global__ __launch_bounds__(kRhsWaves * 64) void gje_rhs_kernel(const GjeDesc* 
     }
     __syncthreads();
   }
-  for (int e = tid; e < n * kRhsCols; e += kRhsWaves * 64) {
+  for (int e = tid; e < n * TC; e += kRhsWaves * 64) {
     const int r = e % n, c = e / n;
     if (c < nc) gst(W + (size_t)(c0 + c) * n + r, Y[r][c]);
   }
@@ -550,10 +556,14 @@ void launch_gje_update(const GjeDesc* d, int nbatch, int k, int max_n, hipStream
     hipLaunchKernelGGL(gje_update_kernel, dim3(tiles, nbatch), dim3(kUpdThreads), 0, st, d, k);
   }
 }
-void launch_gje_rhs(const GjeDesc* d, int nbatch, int max_rhs, hipStream_t st) {
-  if (nbatch > 0 && max_rhs > 0)
-    hipLaunchKernelGGL(gje_rhs_kernel, dim3((max_rhs + kRhsCols - 1) / kRhsCols, nbatch), dim3(kRhsWaves * 64), 0,
+void launch_gje_rhs(const GjeDesc* d, int nbatch, int max_rhs, int max_n, hipStream_t st) {
+  if (nbatch <= 0 || max_rhs <= 0) return;
+  if (max_n <= kRhsMaxN16)
+    hipLaunchKernelGGL((gje_rhs_kernel<16, kRhsMaxN16>), dim3((max_rhs + 15) / 16, nbatch), dim3(kRhsWaves * 64), 0,
                        st, d);
+  else
+    hipLaunchKernelGGL((gje_rhs_kernel<8, kGjeMaxN>), dim3((max_rhs + 7) / 8, nbatch), dim3(kRhsWaves * 64), 0, st,
+                       d);
 }
 void launch_gemv_step(const GemvDesc* d, int nbatch, int max_n, int max_r, hipStream_t st) {
   if (nbatch > 0 && max_n > 0 && max_r > 0)

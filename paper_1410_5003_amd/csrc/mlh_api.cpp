@@ -1576,7 +1576,7 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
             }
           }
           tb(prof ? &prof->gje_rhs_ms : nullptr);
-          launch_gje_rhs(dg, ng, lv.maxrhs, ls);
+          launch_gje_rhs(dg, ng, lv.maxrhs, lv.maxn, ls);
           te();
           if (!lv.upd.empty()) {
             tb(prof ? &prof->sweep_gemm_ms : nullptr);

@@ -127,7 +127,7 @@ def test_errors_are_reported(ctx):
     with pytest.raises(mlh.MlhError) as e:
         mlh.Stack(ctx, bad)
     assert e.value.status == 1
-    bad = workloads.config1(N=400)            # more nodes than one block holds
+    bad = workloads.config1(N=600)            # more nodes than one block holds
     with pytest.raises(mlh.MlhError) as e:
         mlh.Stack(ctx, bad)
     assert e.value.status == 7
@@ -172,7 +172,7 @@ def test_mixed_smooth_and_cornered_resolved(ctx):
     _check(ctx, workloads.small_mixed_stack(min_seg=72))
 
 
-RES3 = dict(N_smooth=260, N_corner=300, P=140, M_w=100)
+RES3 = dict(N_smooth=260, N_corner=500, P=140, M_w=100)
 
 
 def test_config3_head_resolved_twin(ctx):
