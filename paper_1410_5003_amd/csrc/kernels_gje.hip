@@ -24,6 +24,8 @@
 //                      multipliers P (the panel columns of W, unchanged after
 //                      their step) and M1 of each step.  The right-hand sides
 //                      thus cross HBM once instead of once per step.
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace mlh {
@@ -40,8 +42,10 @@ __device__ inline double2 cinv2(double2 a) {
   return make_double2(a.x / d, -a.y / d);
 }
 
-// Panel kernel: the (n - k) x NB tall panel lives in registers, thread t owning
-// local rows t and t + 512 (n <= 608).  Rows are not moved while the panel is
+// Panel kernel: the n x NB panel columns live in registers, thread t owning
+// rows t and t + 512.  The kernel first applies the previous step's
+// transformation to them (the update kernel does the other columns), then
+// factors rows k..n-1.  Rows are not moved while the panel is
 // factored: a row that wins the pivot search for column c is marked done and
 // broadcast through LDS, so each column costs one workgroup barrier.  Every
 // wave reduces its candidates to one 64-bit key (high word of |a|^2, then the
@@ -172,28 +176,104 @@ __global__ __launch_bounds__(kPanelThreads) void gje_panel_kernel(const GjeDesc*
   const int n = D.n;
   if (k >= n) return;
   const int nb = min(kGjeNb, n - k);
-  const int L = n - k;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   cplx* W = D.W;
   __shared__ PanelShared sh;
   __shared__ double2 lu11[kGjeNb][kGjeNb + 1];
   __shared__ int sdst[2 * kGjeNb], ssrc[2 * kGjeNb], snaff;
   __shared__ double2 stage[2 * kGjeNb][kGjeNb];
+  __shared__ double2 zs[kGjeNb][kGjeNb];
+  if (k > 0) {
+    // the previous step's transformation on these 16 columns, in W (the
+    // update kernel does the columns after them): its row interchanges,
+    // Z = M1 Y(its pivot rows) and Y(other rows) -= P Z on the matrix cores
+    const int kp = k - kGjeNb;
+    const int lr = lane & 15, lq = lane >> 4;
+    const int* pivp = D.piv + (size_t)(kp / kGjeNb) * kGjePivStride;
+    const cplx* M1p = D.M1 + (size_t)(kp / kGjeNb) * kGjeNb * kGjeNb;
+    if (tid == 0) snaff = pivp[0];
+    if (tid < 2 * kGjeNb) {
+      sdst[tid] = pivp[1 + tid];
+      ssrc[tid] = pivp[1 + 2 * kGjeNb + tid];
+    }
+    __syncthreads();
+    const int nap = snaff;
+    for (int e = tid; e < nap * kGjeNb; e += kPanelThreads) {
+      const int t = e % nap, j = e / nap;
+      stage[t][j] = j < nb ? gld(W + (size_t)(k + j) * n + ssrc[t]) : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    for (int e = tid; e < nap * kGjeNb; e += kPanelThreads) {
+      const int t = e % nap, j = e / nap;
+      if (j < nb) gst(W + (size_t)(k + j) * n + sdst[t], stage[t][j]);
+    }
+    __syncthreads();
+    if (wave == 0) {  // Z = M1 Y1: lane holds M1[lr][q] and Y1[q][lr], q = 4 kk + lq
+      dvec4 zr = {0, 0, 0, 0}, zi = {0, 0, 0, 0};
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int q = 4 * kk + lq;
+        const double2 m = gld(M1p + (size_t)q * kGjeNb + lr);
+        const double2 y = lr < nb ? gld(W + (size_t)(k + lr) * n + kp + q) : make_double2(0.0, 0.0);
+        zr = __builtin_amdgcn_mfma_f64_16x16x4f64(m.x, y.x, zr, 0, 0, 0);
+        zr = __builtin_amdgcn_mfma_f64_16x16x4f64(-m.y, y.y, zr, 0, 0, 0);
+        zi = __builtin_amdgcn_mfma_f64_16x16x4f64(m.x, y.y, zi, 0, 0, 0);
+        zi = __builtin_amdgcn_mfma_f64_16x16x4f64(m.y, y.x, zi, 0, 0, 0);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) zs[lq + 4 * q][lr] = make_double2(zr[q], zi[q]);
+    }
+    __syncthreads();
+    const int nrb = (n + 15) / 16;
+    for (int rb = wave; rb < nrb; rb += kPanelWaves) {
+      const int r0 = rb * 16;
+      if (r0 == kp) {  // the previous pivot rows receive Z
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (lr < nb) gst(W + (size_t)(k + lr) * n + kp + lq + 4 * q, zs[lq + 4 * q][lr]);
+        continue;
+      }
+      dvec4 accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int row = r0 + lr, q = 4 * kk + lq;
+        const double2 a = row < n ? gld(W + (size_t)(kp + q) * n + row) : make_double2(0.0, 0.0);
+        const double2 b = zs[q][lr];
+        accr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, accr, 0, 0, 0);
+        accr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, accr, 0, 0, 0);
+        acci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, acci, 0, 0, 0);
+        acci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, acci, 0, 0, 0);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = r0 + lq + 4 * q;
+        if (row < n && lr < nb) {
+          cplx* p = W + (size_t)(k + lr) * n + row;
+          double2 v = gld(p);
+          v.x -= accr[q];
+          v.y -= acci[q];
+          gst(p, v);
+        }
+      }
+    }
+    __syncthreads();
+  }
   PanelState st;
   st.singular = 0;
+  // every row of the panel columns: thread t holds rows t and t + 512
 #pragma unroll
   for (int sl = 0; sl < kPanelSlots; ++sl) {
-    const int lr = tid + sl * kPanelThreads;
-    st.pidx[sl] = lr < L ? -1 : kGjeNb;
+    const int r = tid + sl * kPanelThreads;
+    st.pidx[sl] = (r >= k && r < n) ? -1 : kGjeNb;
 #pragma unroll
     for (int j = 0; j < kGjeNb; ++j)
-      st.a[sl][j] = (lr < L && j < nb) ? gld(W + (size_t)(k + j) * n + k + lr) : make_double2(0.0, 0.0);
+      st.a[sl][j] = (r < n && j < nb) ? gld(W + (size_t)(k + j) * n + r) : make_double2(0.0, 0.0);
   }
+  double2 (&a)[kPanelSlots][kGjeNb] = st.a;
+  int (&pidx)[kPanelSlots] = st.pidx;
   PanelColumns<0>::run(st, sh, nb, k, tid);
   const int singular = st.singular;
   int* spiv = sh.spiv;
-  double2 (&a)[kPanelSlots][kGjeNb] = st.a;
-  int (&pidx)[kPanelSlots] = st.pidx;
   if (tid == 0 && singular != 0) atomicCAS(D.info, 0, singular);
   // the factored pivot block: row of pivot c holds L11 (j < c) and U11 (j >= c)
 #pragma unroll
@@ -205,8 +285,8 @@ __global__ __launch_bounds__(kPanelThreads) void gje_panel_kernel(const GjeDesc*
 #pragma unroll
     for (int j = 0; j < kGjeNb; ++j) lu11[tid][j] = make_double2(0.0, 0.0);
   // the row permutation of this step as (destination, source) pairs of
-  // global rows: pivot q (local row spiv[q], never moved in registers) goes
-  // to position q; rows of positions 0..nb-1 that were not chosen fill the
+  // global rows: pivot q (row spiv[q], never moved in registers) goes to
+  // position k + q; rows of positions k..k+nb-1 that were not chosen fill the
   // positions the chosen rows vacated below the block.  piv[0] = count,
   // piv[1..] destinations, piv[1+2NB..] sources.
   __syncthreads();
@@ -215,17 +295,17 @@ __global__ __launch_bounds__(kPanelThreads) void gje_panel_kernel(const GjeDesc*
     bool chosen[kGjeNb];
     for (int q = 0; q < kGjeNb; ++q) chosen[q] = false;
     for (int q = 0; q < nb; ++q)
-      if (spiv[q] < nb) chosen[spiv[q]] = true;
+      if (spiv[q] - k < nb) chosen[spiv[q] - k] = true;
     int nxt = 0;  // next pivot row from below the block, in pivot order
     for (int q = 0; q < nb; ++q) {
-      if (spiv[q] != q) {
+      if (spiv[q] != k + q) {
         sdst[na] = k + q;
-        ssrc[na] = k + spiv[q];
+        ssrc[na] = spiv[q];
         ++na;
       }
       if (!chosen[q]) {  // row at position q was displaced: send it below
-        while (spiv[nxt] < nb) ++nxt;
-        sdst[na] = k + spiv[nxt];
+        while (spiv[nxt] - k < nb) ++nxt;
+        sdst[na] = spiv[nxt];
         ssrc[na] = k + q;
         ++na;
         ++nxt;
@@ -240,9 +320,9 @@ __global__ __launch_bounds__(kPanelThreads) void gje_panel_kernel(const GjeDesc*
     }
   }
   __syncthreads();
-  // apply the interchanges to the panel columns of W, which still hold the
-  // values the panel started from: the update kernel reads its multipliers
-  // (original values of the rows below the pivot block) from there
+  // apply the interchanges to the panel columns of W, which hold the values
+  // the panel started from: the update kernels read their multipliers
+  // (those values, for the rows off the pivot block) from there
   const int naff = snaff;
   for (int e = tid; e < naff * kGjeNb; e += kPanelThreads) {
     const int t = e % naff, j = e / naff;
@@ -253,52 +333,63 @@ __global__ __launch_bounds__(kPanelThreads) void gje_panel_kernel(const GjeDesc*
     const int t = e % naff, j = e / naff;
     if (j < nb) gst(W + (size_t)(k + j) * n + sdst[t], stage[t][j]);
   }
-  // M1 = (L11 U11)^{-1}, one thread per column; each row of the factors is
-  // fetched from LDS in one batch before it is used
-  if (tid < kGjeNb) {
-    double2 x[kGjeNb];
+  // M1 = (L11 U11)^{-1} in wave 0: lane (lq, lr) holds rows lq + 4 q of
+  // column lr; X = L11^{-1} by row operations, then M1 = U11^{-1} X
+  if (wave == 0) {
+    const int lr = lane & 15, lq = lane >> 4;
+    double2 x[4];
 #pragma unroll
-    for (int r = 0; r < kGjeNb; ++r) x[r] = make_double2(r == tid ? 1.0 : 0.0, 0.0);
+    for (int q = 0; q < 4; ++q) x[q] = make_double2(lq + 4 * q == lr ? 1.0 : 0.0, 0.0);
 #pragma unroll
-    for (int r = 1; r < kGjeNb; ++r) {
-      double2 lr_[kGjeNb];
+    for (int r = 0; r < kGjeNb - 1; ++r) {
+      const double2 xr = make_double2(__shfl(x[r / 4].x, (r % 4) * 16 + lr, 64), __shfl(x[r / 4].y, (r % 4) * 16 + lr, 64));
 #pragma unroll
-      for (int q = 0; q < r; ++q) lr_[q] = lu11[r][q];
-#pragma unroll
-      for (int q = 0; q < r; ++q) {
-        const double2 t = cmul2(lr_[q], x[q]);
-        x[r].x -= t.x;
-        x[r].y -= t.y;
+      for (int q = 0; q < 4; ++q) {
+        const int i = lq + 4 * q;
+        if (i > r) {
+          const double2 l = lu11[i][r];
+          x[q].x -= l.x * xr.x - l.y * xr.y;
+          x[q].y -= l.x * xr.y + l.y * xr.x;
+        }
       }
     }
 #pragma unroll
     for (int r = kGjeNb - 1; r >= 0; --r) {
-      double2 ur[kGjeNb];
+      const double2 d = lu11[r][r];
+      const bool ok = r < nb && (d.x != 0.0 || d.y != 0.0);
+      double2 xr = make_double2(__shfl(x[r / 4].x, (r % 4) * 16 + lr, 64), __shfl(x[r / 4].y, (r % 4) * 16 + lr, 64));
+      xr = ok ? cmul2(xr, cinv2(d)) : make_double2(0.0, 0.0);
 #pragma unroll
-      for (int q = r; q < kGjeNb; ++q) ur[q] = lu11[r][q];
-#pragma unroll
-      for (int q = r + 1; q < kGjeNb; ++q) {
-        const double2 t = cmul2(ur[q], x[q]);
-        x[r].x -= t.x;
-        x[r].y -= t.y;
+      for (int q = 0; q < 4; ++q) {
+        const int i = lq + 4 * q;
+        if (i == r) {
+          x[q] = xr;
+        } else if (i < r) {
+          const double2 u = lu11[i][r];
+          x[q].x -= u.x * xr.x - u.y * xr.y;
+          x[q].y -= u.x * xr.y + u.y * xr.x;
+        }
       }
-      const double2 d = ur[r];
-      x[r] = (r < nb && (d.x != 0.0 || d.y != 0.0)) ? cmul2(x[r], cinv2(d)) : make_double2(0.0, 0.0);
     }
     cplx* M1 = D.M1 + (size_t)(k / kGjeNb) * kGjeNb * kGjeNb;
 #pragma unroll
-    for (int r = 0; r < kGjeNb; ++r) gst(M1 + (size_t)tid * kGjeNb + r, (tid < nb) ? x[r] : make_double2(0.0, 0.0));
+    for (int q = 0; q < 4; ++q)
+      gst(M1 + (size_t)lr * kGjeNb + lq + 4 * q, lr < nb ? x[q] : make_double2(0.0, 0.0));
   }
 }
 
-__global__ __launch_bounds__(kUpdThreads) void gje_update_kernel(const GjeDesc* __restrict__ descs, int k) {
+// columns [k + nb + lo, min(n, k + nb + hi)) of the diagonal block; the
+// right-hand-side columns are left to gje_rhs_kernel, after all steps
+__global__ __launch_bounds__(kUpdThreads) void gje_update_kernel(const GjeDesc* __restrict__ descs, int k, int lo,
+                                                                 int hi) {
   const GjeDesc& D = descs[blockIdx.y];
   const int n = D.n;
   if (k >= n) return;
   const int nb = min(kGjeNb, n - k);
-  const int c0 = k + nb + blockIdx.x * kGjeCols;
-  if (c0 >= n) return;  // right-hand-side columns: gje_rhs_kernel, after all steps
-  const int nc = min(kGjeCols, n - c0);
+  const int cend = min(n, k + nb + hi);
+  const int c0 = k + nb + lo + blockIdx.x * kGjeCols;
+  if (c0 >= cend) return;
+  const int nc = min(kGjeCols, cend - c0);
   const int* piv = D.piv + (size_t)(k / kGjeNb) * kGjePivStride;
   const cplx* M1 = D.M1 + (size_t)(k / kGjeNb) * kGjeNb * kGjeNb;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -550,10 +641,11 @@ void launch_gje_panel(const GjeDesc* d, int nbatch, int k, int max_n, hipStream_
   (void)lds;
   if (nbatch > 0 && max_n > k) hipLaunchKernelGGL(gje_panel_kernel, dim3(nbatch), dim3(kPanelThreads), 0, st, d, k);
 }
-void launch_gje_update(const GjeDesc* d, int nbatch, int k, int max_n, hipStream_t st) {
-  if (nbatch > 0 && max_n > k + kGjeNb) {
-    const int tiles = (max_n - k - kGjeNb - 1) / kGjeCols + 1;
-    hipLaunchKernelGGL(gje_update_kernel, dim3(tiles, nbatch), dim3(kUpdThreads), 0, st, d, k);
+void launch_gje_update(const GjeDesc* d, int nbatch, int k, int max_n, int lo, int hi, hipStream_t st) {
+  const int width = std::min(max_n - k - kGjeNb, hi) - lo;
+  if (nbatch > 0 && width > 0) {
+    const int tiles = (width - 1) / kGjeCols + 1;
+    hipLaunchKernelGGL(gje_update_kernel, dim3(tiles, nbatch), dim3(kUpdThreads), 0, st, d, k, lo, hi);
   }
 }
 void launch_gje_rhs(const GjeDesc* d, int nbatch, int max_rhs, int max_n, hipStream_t st) {

@@ -347,6 +347,9 @@ struct mlh_stack_s {
   // the workspace stay the same; only the descriptor contents change)
   hipGraphExec_t gexec = nullptr;
   hipStream_t cap_stream = nullptr;
+  // second stream of the Gauss-Jordan look-ahead and its dependency events
+  hipStream_t aux_stream = nullptr;
+  std::vector<hipEvent_t> evpool;
   std::vector<int64_t> g_sig;
 
   // solve workspace (reused across calls with the same batch size)
@@ -944,6 +947,8 @@ extern "C" mlh_status mlh_stack_destroy(mlh_stack s) {
   if (s->dmem) hipFree(s->dmem);
   if (s->gexec) hipGraphExecDestroy(s->gexec);
   if (s->cap_stream) hipStreamDestroy(s->cap_stream);
+  if (s->aux_stream) hipStreamDestroy(s->aux_stream);
+  for (hipEvent_t e : s->evpool) hipEventDestroy(e);
   if (s->wmem) hipFree(s->wmem);
   delete s;
   return MLH_OK;
@@ -1520,7 +1525,18 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
     sc.P = P;
     sc.K = s->K;
     // ---- launch sequence (captured into a graph and replayed when possible)
+    if (!s->aux_stream) HIP_TRY(hipStreamCreateWithFlags(&s->aux_stream, hipStreamNonBlocking));
+    size_t ev_used = 0;
+    auto ev_next = [&]() -> hipEvent_t {
+      if (ev_used == s->evpool.size()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+        s->evpool.push_back(e);
+      }
+      return s->evpool[ev_used++];
+    };
     auto launch_all = [&](hipStream_t ls, EvTimer& T) -> mlh_status {
+      ev_used = 0;
       double dummy = 0.0;
       auto tb = [&](double* acc) {
         if (prof) T.begin(acc ? acc : &dummy);
@@ -1563,17 +1579,37 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
           const Level& lv = levels[l];
           const GjeDesc* dg = reinterpret_cast<GjeDesc*>(dbase + o_gje[l]);
           const int ng = (int)lv.gje.size();
-          for (int k = 0; k < lv.maxn; k += kGjeNb) {
-            tb(prof ? &prof->gje_panel_ms : nullptr);
-            launch_gje_panel(dg, ng, k, lv.maxn, ls);
-            te();
-            tb(prof ? &prof->gje_update_ms : nullptr);
-            launch_gje_update(dg, ng, k, lv.maxn, ls);
-            te();
-            if (prof) {
+          // Step s: the panel kernel applies step s - 1 to its own 16 columns
+          // and factors them; the update kernel applies step s to the
+          // columns from k + 32 on.  Panel s needs the update of step s - 2
+          // only, so it runs while the update of step s - 1 is in flight on
+          // the second stream.
+          if (prof) {  // one stream, every launch timed on its own
+            for (int k = 0; k < lv.maxn; k += kGjeNb) {
+              tb(&prof->gje_panel_ms);
+              launch_gje_panel(dg, ng, k, lv.maxn, ls);
+              te();
+              tb(&prof->gje_update_ms);
+              launch_gje_update(dg, ng, k, lv.maxn, kGjeNb, 1 << 30, ls);
+              te();
               prof->n_gje_panel++;
               prof->n_gje_update++;
             }
+          } else {
+            hipEvent_t rest1 = nullptr, rest2 = nullptr;  // updates of steps s - 1, s - 2
+            for (int k = 0; k < lv.maxn; k += kGjeNb) {
+              if (rest2) HIP_TRY(hipStreamWaitEvent(ls, rest2, 0));
+              launch_gje_panel(dg, ng, k, lv.maxn, ls);
+              hipEvent_t ep = ev_next();
+              HIP_TRY(hipEventRecord(ep, ls));
+              HIP_TRY(hipStreamWaitEvent(s->aux_stream, ep, 0));
+              launch_gje_update(dg, ng, k, lv.maxn, kGjeNb, 1 << 30, s->aux_stream);
+              hipEvent_t er = ev_next();
+              HIP_TRY(hipEventRecord(er, s->aux_stream));
+              rest2 = rest1;
+              rest1 = er;
+            }
+            if (rest1) HIP_TRY(hipStreamWaitEvent(ls, rest1, 0));
           }
           tb(prof ? &prof->gje_rhs_ms : nullptr);
           launch_gje_rhs(dg, ng, lv.maxrhs, lv.maxn, ls);
