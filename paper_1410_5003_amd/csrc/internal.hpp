@@ -84,8 +84,9 @@ struct AsmJob {
   cplx coef[3];
   int npieces;
   int rows, cols, lds, ldd;
-  int64_t elem_begin;
+  int tile_begin;  // first kAsmTile-element tile of this job in the launch
 };
+constexpr int kAsmTile = 2048;  // elements per assembly workgroup (8 per thread)
 
 // batched complex GEMM  C += alpha (A B + A2 B2)  (column-major); the second
 // product (k2 may be 0) lets one descriptor own its output tile, so no two
@@ -109,7 +110,7 @@ struct GemmDesc {
 void launch_fill(const FillJob* d_jobs, int njobs, int total_tiles, hipStream_t st);
 void launch_self(const SelfJob* d_jobs, int njobs, int total_tiles, int a_excl, hipStream_t st);
 void launch_alpert(const AlpertJob* d_jobs, int njobs, int total_blocks, int a_excl, hipStream_t st);
-void launch_assemble(const AsmJob* d_jobs, int njobs, int64_t total_elems, hipStream_t st);
+void launch_assemble(const AsmJob* d_jobs, int njobs, int total_tiles, hipStream_t st);
 void launch_gemm(const GemmDesc* d_desc, int ndesc, int total_tiles, hipStream_t st);
 void launch_hankel_eval(const double* x, double* out, int n, hipStream_t st);
 

@@ -212,25 +212,22 @@ __global__ __launch_bounds__(64) void alpert_kernel(const AlpertJob* __restrict_
   }
 }
 
-// grid-stride over all elements of all jobs (the total can exceed what one
-// launch addresses with a thread per element)
-__global__ __launch_bounds__(256) void assemble_kernel(const AsmJob* __restrict__ jobs, int njobs,
-                                                      int64_t total) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += stride) {
-    int lo = 0, hi = njobs - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (jobs[mid].elem_begin <= e)
-        lo = mid;
-      else
-        hi = mid - 1;
-    }
-    const AsmJob& J = jobs[lo];
-    const int64_t le = e - J.elem_begin;
+// one workgroup per kAsmTile elements of one job (jobs own whole tiles), so
+// the job is found once per workgroup; 8 elements per thread, consecutive
+// threads on consecutive rows
+__global__ __launch_bounds__(256) void assemble_kernel(const AsmJob* __restrict__ jobs, int njobs, int tile0) {
+  const int tile = tile0 + (int)blockIdx.x;
+  const AsmJob& J = jobs[find_job(jobs, njobs, tile)];
+  const int64_t total = (int64_t)J.rows * J.cols;
+  const int64_t base = (int64_t)(tile - J.tile_begin) * kAsmTile;
+  const int np = J.npieces;
+#pragma unroll
+  for (int u = 0; u < kAsmTile / 256; ++u) {
+    const int64_t le = base + u * 256 + threadIdx.x;
+    if (le >= total) break;
     const int r = (int)(le % J.rows), c = (int)(le / J.rows);
     double re = 0.0, im = 0.0;
-    for (int p = 0; p < J.npieces; ++p) {
+    for (int p = 0; p < np; ++p) {
       const double2 v = *reinterpret_cast<const double2*>(J.src[p] + (size_t)c * J.lds + r);
       re += J.coef[p].re * v.x - J.coef[p].im * v.y;
       im += J.coef[p].re * v.y + J.coef[p].im * v.x;
@@ -267,10 +264,10 @@ void launch_alpert(const AlpertJob* d_jobs, int njobs, int total_blocks, int a_e
     hipLaunchKernelGGL(alpert_kernel, dim3(std::min(kMaxLaunchBlocks, total_blocks - b0)), dim3(64), 0, st, d_jobs,
                        njobs, a_excl, b0);
 }
-void launch_assemble(const AsmJob* d_jobs, int njobs, int64_t total_elems, hipStream_t st) {
-  const int64_t blocks = std::min<int64_t>((total_elems + 255) / 256, int64_t(1) << 20);
-  if (total_elems > 0)
-    hipLaunchKernelGGL(assemble_kernel, dim3((unsigned)blocks), dim3(256), 0, st, d_jobs, njobs, total_elems);
+void launch_assemble(const AsmJob* d_jobs, int njobs, int total_tiles, hipStream_t st) {
+  for (int t0 = 0; t0 < total_tiles; t0 += kMaxLaunchBlocks)
+    hipLaunchKernelGGL(assemble_kernel, dim3(std::min(kMaxLaunchBlocks, total_tiles - t0)), dim3(256), 0, st, d_jobs,
+                       njobs, t0);
 }
 void launch_hankel_eval(const double* x, double* out, int n, hipStream_t st) {
   if (n > 0) hipLaunchKernelGGL(hankel_eval_kernel, dim3((n + 255) / 256), dim3(256), 0, st, x, out, n);

@@ -293,15 +293,22 @@ __global__ __launch_bounds__(kHqRhsWaves * 64) void hq_rhs_kernel(const HqDesc* 
     const cplx* Tp = D.T + (size_t)p * kHqNb * kHqNb;
     // 1. partial w = V^H Y over this wave's 4-row steps of rows k..M-1
     hvec4 wr = {0, 0, 0, 0}, wi = {0, 0, 0, 0};
-    for (int r0 = k + 4 * wave; r0 < M; r0 += 4 * kHqRhsWaves) {
-      const int r = r0 + lq;
-      const double2 v = r < M ? hq_v(A, M, k, nb, r, lr) : make_double2(0.0, 0.0);  // A[i=lr][k=r]
-      const double2 y = r < M ? Y[r][lr] : make_double2(0.0, 0.0);                  // B[k=r][col=lr]
-      // w = conj(V)^T Y
-      wr = __builtin_amdgcn_mfma_f64_16x16x4f64(v.x, y.x, wr, 0, 0, 0);
-      wr = __builtin_amdgcn_mfma_f64_16x16x4f64(v.y, y.y, wr, 0, 0, 0);
-      wi = __builtin_amdgcn_mfma_f64_16x16x4f64(v.x, y.y, wi, 0, 0, 0);
-      wi = __builtin_amdgcn_mfma_f64_16x16x4f64(-v.y, y.x, wi, 0, 0, 0);
+    // four 4-row steps per batch, all loads issued before the products
+    for (int r0 = k + 4 * wave; r0 < M; r0 += 16 * kHqRhsWaves) {
+      double2 v[4], y[4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int r = r0 + 4 * kHqRhsWaves * b + lq;
+        v[b] = r < M ? hq_v(A, M, k, nb, r, lr) : make_double2(0.0, 0.0);  // A[i=lr][k=r]
+        y[b] = r < M ? Y[r][lr] : make_double2(0.0, 0.0);                  // B[k=r][col=lr]
+      }
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {  // w = conj(V)^T Y
+        wr = __builtin_amdgcn_mfma_f64_16x16x4f64(v[b].x, y[b].x, wr, 0, 0, 0);
+        wr = __builtin_amdgcn_mfma_f64_16x16x4f64(v[b].y, y[b].y, wr, 0, 0, 0);
+        wi = __builtin_amdgcn_mfma_f64_16x16x4f64(v[b].x, y[b].y, wi, 0, 0, 0);
+        wi = __builtin_amdgcn_mfma_f64_16x16x4f64(-v[b].y, y[b].x, wi, 0, 0, 0);
+      }
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -336,14 +343,18 @@ __global__ __launch_bounds__(kHqRhsWaves * 64) void hq_rhs_kernel(const HqDesc* 
     // 3. Y(rows k..M-1) -= V u, 16-row blocks (k is a multiple of 16)
     for (int r0 = k + 16 * wave; r0 < M; r0 += 16 * kHqRhsWaves) {
       hvec4 ar = {0, 0, 0, 0}, ai = {0, 0, 0, 0};
+      double2 v[4];
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
         const int i = 4 * kk + lq, r = r0 + lr;
-        const double2 v = r < M ? hq_v(A, M, k, nb, r, i) : make_double2(0.0, 0.0);
-        ar = __builtin_amdgcn_mfma_f64_16x16x4f64(v.x, ur[kk], ar, 0, 0, 0);
-        ar = __builtin_amdgcn_mfma_f64_16x16x4f64(-v.y, ui[kk], ar, 0, 0, 0);
-        ai = __builtin_amdgcn_mfma_f64_16x16x4f64(v.x, ui[kk], ai, 0, 0, 0);
-        ai = __builtin_amdgcn_mfma_f64_16x16x4f64(v.y, ur[kk], ai, 0, 0, 0);
+        v[kk] = r < M ? hq_v(A, M, k, nb, r, i) : make_double2(0.0, 0.0);
+      }
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        ar = __builtin_amdgcn_mfma_f64_16x16x4f64(v[kk].x, ur[kk], ar, 0, 0, 0);
+        ar = __builtin_amdgcn_mfma_f64_16x16x4f64(-v[kk].y, ui[kk], ar, 0, 0, 0);
+        ai = __builtin_amdgcn_mfma_f64_16x16x4f64(v[kk].x, ui[kk], ai, 0, 0, 0);
+        ai = __builtin_amdgcn_mfma_f64_16x16x4f64(v[kk].y, ur[kk], ai, 0, 0, 0);
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {

@@ -155,38 +155,59 @@ __global__ __launch_bounds__(256) void rb_setup_kernel(const AngleDesc* __restri
   }
 }
 
-__global__ __launch_bounds__(64) void bragg_kernel(const AngleDesc* __restrict__ ang, StackConsts sc) {
+// one workgroup per angle: lane q of every wave takes order q, the 8 waves
+// split the density index and their partial sums meet in LDS
+__global__ __launch_bounds__(512) void bragg_kernel(const AngleDesc* __restrict__ ang, StackConsts sc) {
   const AngleDesc& A = ang[blockIdx.x];
   const int nK = 2 * sc.K + 1;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const double kappa0 = sc.k1 * cos(A.theta);
   const int n0 = rb_n0(kappa0, sc.d);
-  double fl = 0.0;
   const int n1 = 2 * sc.N1, nI = 2 * sc.NI;
-  for (int q = lane; q < nK; q += 64) {
+  __shared__ double2 pu[8][64], pd[8][64];
+  double fl = 0.0;
+  for (int q0 = 0; q0 < nK; q0 += 64) {
+    const int q = q0 + lane;
     double ur = 0.0, ui = 0.0, dr = 0.0, di = 0.0;
-    for (int j = 0; j < n1; ++j) {
-      const double2 x = ld2(A.X0 + (size_t)j * A.ldX0 + sc.P + q), e = ld2(A.eta0 + j);
-      ur -= x.x * e.x - x.y * e.y;
-      ui -= x.x * e.y + x.y * e.x;
+    if (q < nK) {
+      for (int j = wave; j < n1; j += 8) {
+        const double2 x = ld2(A.X0 + (size_t)j * A.ldX0 + sc.P + q), e = ld2(A.eta0 + j);
+        ur -= x.x * e.x - x.y * e.y;
+        ui -= x.x * e.y + x.y * e.x;
+      }
+      for (int j = wave; j < nI; j += 8) {
+        const double2 x = ld2(A.XI + (size_t)j * A.ldXI + sc.P + q), e = ld2(A.etaI + j);
+        dr -= x.x * e.x - x.y * e.y;
+        di -= x.x * e.y + x.y * e.x;
+      }
     }
-    for (int j = 0; j < nI; ++j) {
-      const double2 x = ld2(A.XI + (size_t)j * A.ldXI + sc.P + q), e = ld2(A.etaI + j);
-      dr -= x.x * e.x - x.y * e.y;
-      di -= x.x * e.y + x.y * e.x;
+    pu[wave][lane] = make_double2(ur, ui);
+    pd[wave][lane] = make_double2(dr, di);
+    __syncthreads();
+    if (wave == 0 && q < nK) {
+      ur = ui = dr = di = 0.0;
+      for (int w = 0; w < 8; ++w) {
+        ur += pu[w][lane].x;
+        ui += pu[w][lane].y;
+        dr += pd[w][lane].x;
+        di += pd[w][lane].y;
+      }
+      st2(A.aU + q, ur, ui);
+      st2(A.aD + q, dr, di);
+      A.orders[q] = n0 - sc.K + q;
+      const double kap = kappa0 + 2.0 * kPi * (double)(n0 - sc.K + q) / sc.d;
+      const cplx ku = vert_wavenumber(sc.k1, kap), kd = vert_wavenumber(sc.kI1, kap);
+      if (ku.im == 0.0 && ku.re > 0.0) fl += ku.re * (ur * ur + ui * ui);
+      if (kd.im == 0.0 && kd.re > 0.0) fl += kd.re * (dr * dr + di * di);
     }
-    st2(A.aU + q, ur, ui);
-    st2(A.aD + q, dr, di);
-    A.orders[q] = n0 - sc.K + q;
-    const double kap = kappa0 + 2.0 * kPi * (double)(n0 - sc.K + q) / sc.d;
-    const cplx ku = vert_wavenumber(sc.k1, kap), kd = vert_wavenumber(sc.kI1, kap);
-    if (ku.im == 0.0 && ku.re > 0.0) fl += ku.re * (ur * ur + ui * ui);
-    if (kd.im == 0.0 && kd.re > 0.0) fl += kd.re * (dr * dr + di * di);
+    __syncthreads();
   }
-  fl = wave_sum(fl);
-  if (lane == 0) {
-    const double inc = sc.k1 * fabs(sin(A.theta));
-    A.flux[0] = (fl - inc) / inc;
+  if (wave == 0) {
+    fl = wave_sum(fl);
+    if (lane == 0) {
+      const double inc = sc.k1 * fabs(sin(A.theta));
+      A.flux[0] = (fl - inc) / inc;
+    }
   }
 }
 
@@ -199,7 +220,7 @@ void launch_rb_setup(const AngleDesc* d_ang, int nang, StackConsts sc, hipStream
   if (nang > 0) hipLaunchKernelGGL(rb_setup_kernel, dim3(nang), dim3(256), 0, st, d_ang, sc);
 }
 void launch_bragg(const AngleDesc* d_ang, int nang, StackConsts sc, hipStream_t st) {
-  if (nang > 0) hipLaunchKernelGGL(bragg_kernel, dim3(nang), dim3(64), 0, st, d_ang, sc);
+  if (nang > 0) hipLaunchKernelGGL(bragg_kernel, dim3(nang), dim3(512), 0, st, d_ang, sc);
 }
 
 }  // namespace mlh

@@ -1192,8 +1192,8 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
         J.src[p] = src[p];
         J.coef[p] = coef[p];
       }
-      J.elem_begin = elems;
-      elems += (int64_t)rows * cols;
+      J.tile_begin = (int)elems;
+      elems += ((int64_t)rows * cols + kAsmTile - 1) / kAsmTile;
       asmj.push_back(J);
     };
     // C = C0 + alpha (A B + A2 B2); m x nn output, inner sizes k and k2
@@ -1545,7 +1545,7 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
         if (prof) T.end();
       };
       tb(prof ? &prof->assemble_ms : nullptr);
-      launch_assemble(reinterpret_cast<AsmJob*>(dbase + o_asm), (int)asmj.size(), elems, ls);
+      launch_assemble(reinterpret_cast<AsmJob*>(dbase + o_asm), (int)asmj.size(), (int)elems, ls);
       te();
       const AngleDesc* d_ang = reinterpret_cast<AngleDesc*>(dbase + o_ang);
       tb(prof ? &prof->rb_setup_ms : nullptr);
