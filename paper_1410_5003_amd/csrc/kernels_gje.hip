@@ -529,26 +529,31 @@ constexpr int kRhsMaxN16 = 608;  // largest order whose 16-column tile fits in L
 // TC right-hand-side columns per workgroup (16, or 8 for orders up to
 // kGjeMaxN, whose 16-column tile would not fit in LDS: then lanes of columns
 // 8..15 carry zeros through the 16-wide matrix-core products)
+// Steps [s0, s1) are replayed (clipped to each matrix's step count); the
+// grid may be smaller than the number of tiles, workgroups then loop over
+// tiles, so that a launch can run beside the panel chain on part of the chip.
 template <int TC, int MAXN>
-__global__ __launch_bounds__(kRhsWaves * 64) void gje_rhs_kernel(const GjeDesc* __restrict__ descs) {
+__global__ __launch_bounds__(kRhsWaves * 64) void gje_rhs_kernel(const GjeDesc* __restrict__ descs, int nbatch,
+                                                                 int tiles_per, int s0, int s1) {
   constexpr int NBLK = (MAXN / 16 + kRhsWaves - 1) / kRhsWaves;  // row blocks per wave
-  const GjeDesc& D = descs[blockIdx.y];
-  const int n = D.n;
-  const int c0 = n + blockIdx.x * TC;
-  if (c0 >= D.ncol) return;
-  const int nc = min(TC, D.ncol - c0);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int lr = lane & 15, lq = lane >> 4;
   const bool cl = lr < TC;
-  cplx* W = D.W;
   __shared__ double2 Y[MAXN][TC];
+  for (int tile = blockIdx.x; tile < nbatch * tiles_per; tile += gridDim.x) {
+  const GjeDesc& D = descs[tile / tiles_per];
+  const int n = D.n;
+  const int c0 = n + (tile % tiles_per) * TC;
+  if (c0 >= D.ncol) continue;
+  const int nc = min(TC, D.ncol - c0);
+  cplx* W = D.W;
   for (int e = tid; e < n * TC; e += kRhsWaves * 64) {
     const int r = e % n, c = e / n;
     Y[r][c] = c < nc ? gld(W + (size_t)(c0 + c) * n + r) : make_double2(0.0, 0.0);
   }
   __syncthreads();
-  const int nsteps = (n + kGjeNb - 1) / kGjeNb;
-  for (int sidx = 0; sidx < nsteps; ++sidx) {
+  const int nsteps = min(s1, (n + kGjeNb - 1) / kGjeNb);
+  for (int sidx = s0; sidx < nsteps; ++sidx) {
     const int k = sidx * kGjeNb;
     const int nb = min(kGjeNb, n - k);
     const int* piv = D.piv + (size_t)sidx * kGjePivStride;
@@ -632,6 +637,8 @@ __global__ __launch_bounds__(kRhsWaves * 64) void gje_rhs_kernel(const GjeDesc* 
     const int r = e % n, c = e / n;
     if (c < nc) gst(W + (size_t)(c0 + c) * n + r, Y[r][c]);
   }
+  __syncthreads();  // before the next tile refills the LDS tile
+  }
 }
 
 void gje_init() {}
@@ -648,14 +655,19 @@ void launch_gje_update(const GjeDesc* d, int nbatch, int k, int max_n, int lo, i
     hipLaunchKernelGGL(gje_update_kernel, dim3(tiles, nbatch), dim3(kUpdThreads), 0, st, d, k, lo, hi);
   }
 }
-void launch_gje_rhs(const GjeDesc* d, int nbatch, int max_rhs, int max_n, hipStream_t st) {
-  if (nbatch <= 0 || max_rhs <= 0) return;
-  if (max_n <= kRhsMaxN16)
-    hipLaunchKernelGGL((gje_rhs_kernel<16, kRhsMaxN16>), dim3((max_rhs + 15) / 16, nbatch), dim3(kRhsWaves * 64), 0,
-                       st, d);
+void launch_gje_rhs(const GjeDesc* d, int nbatch, int max_rhs, int max_n, int s0, int s1, int max_blocks,
+                    hipStream_t st) {
+  if (nbatch <= 0 || max_rhs <= 0 || s1 <= s0) return;
+  const bool wide = max_n <= kRhsMaxN16;
+  const int tiles_per = wide ? (max_rhs + 15) / 16 : (max_rhs + 7) / 8;
+  const int total = nbatch * tiles_per;
+  const int grid = max_blocks > 0 ? std::min(total, max_blocks) : total;
+  if (wide)
+    hipLaunchKernelGGL((gje_rhs_kernel<16, kRhsMaxN16>), dim3(grid), dim3(kRhsWaves * 64), 0, st, d, nbatch,
+                       tiles_per, s0, s1);
   else
-    hipLaunchKernelGGL((gje_rhs_kernel<8, kGjeMaxN>), dim3((max_rhs + 7) / 8, nbatch), dim3(kRhsWaves * 64), 0, st,
-                       d);
+    hipLaunchKernelGGL((gje_rhs_kernel<8, kGjeMaxN>), dim3(grid), dim3(kRhsWaves * 64), 0, st, d, nbatch, tiles_per,
+                       s0, s1);
 }
 void launch_gemv_step(const GemvDesc* d, int nbatch, int max_n, int max_r, hipStream_t st) {
   if (nbatch > 0 && max_n > 0 && max_r > 0)

@@ -35,6 +35,7 @@ __global__ __launch_bounds__(256) void hq_prep_kernel(const HqDesc* __restrict__
   const int m = D.m, c = D.c, M = m + c;
   __shared__ double red[4];
   double acc = 0.0;
+#pragma unroll 8
   for (int e = threadIdx.x; e < m * c; e += 256) {
     const double2 x = hld(D.A + (size_t)(e / m) * M + (e % m));
     acc += x.x * x.x + x.y * x.y;
@@ -49,20 +50,43 @@ __global__ __launch_bounds__(256) void hq_prep_kernel(const HqDesc* __restrict__
   }
 }
 
-// panel rows k..M-1 of columns k..k+15 in LDS (stride 17 against bank conflicts)
+// sum of v over the 16 lanes of each DPP row (lanes 16 m .. 16 m + 15); the
+// total lands in the row's last lane
+template <int CTRL>
+__device__ inline double dpp_shr_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffff), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)((unsigned long long)b >> 32), CTRL, 0xf, 0xf, true);
+  return __longlong_as_double(((long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+__device__ inline double row16_sum(double v) {
+  v += dpp_shr_d<0x111>(v);  // row_shr:1
+  v += dpp_shr_d<0x112>(v);  // row_shr:2
+  v += dpp_shr_d<0x114>(v);  // row_shr:4
+  v += dpp_shr_d<0x118>(v);  // row_shr:8
+  return v;
+}
+
+// Panel rows k..M-1 of columns k..k+15 in LDS (stride 17 against bank
+// conflicts).  Thread (j, q) = (tid / 16, tid % 16) owns column j of the rows
+// congruent to q modulo 16 below the current reflector, so each column step
+// is one pass (the norm of column i and the raw products of column i with
+// the later columns), sums over the 16 lanes of a DPP row, one barrier, and
+// one update pass.  The scaling of column i into its Householder vector is
+// deferred to the next pass, which does not read that column.
 __global__ __launch_bounds__(256) void hq_panel_kernel(const HqDesc* __restrict__ descs, int k) {
   const HqDesc& D = descs[blockIdx.x];
   const int c = D.c, M = D.m + c;
   if (k >= c) return;
   const int nb = min(kHqNb, c - k);
   const int L = M - k;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int jc = tid >> 4, q16 = tid & 15;
   __shared__ double2 pan[kHqMaxRows][kHqNb + 1];
-  __shared__ double red[4];
-  __shared__ double2 sh_scale;
-  __shared__ double2 tau[kHqNb];
+  __shared__ double2 red[2][kHqNb];
+  __shared__ double2 tau[kHqNb], scl[kHqNb];
   __shared__ double2 gram[kHqNb][kHqNb + 1];
-  __shared__ double2 wcol[kHqNb];
+  __shared__ double2 T[kHqNb][kHqNb + 1];
   cplx* A = D.A;
   for (int e = tid; e < L * kHqNb; e += 256) {
     const int r = e % L, j = e / L;
@@ -70,98 +94,129 @@ __global__ __launch_bounds__(256) void hq_panel_kernel(const HqDesc* __restrict_
   }
   __syncthreads();
   for (int i = 0; i < nb; ++i) {
-    double acc = 0.0;
-    for (int r = i + 1 + tid; r < L; r += 256) {
-      const double2 x = pan[r][i];
-      acc += x.x * x.x + x.y * x.y;
-    }
-    acc = hwave_sum(acc);
-    if (lane == 0) red[wave] = acc;
-    __syncthreads();
-    if (tid == 0) {
-      const double xn2 = red[0] + red[1] + red[2] + red[3];
-      const double2 al = pan[i][i];
-      double tr = 0.0, ti = 0.0, sr = 1.0, si = 0.0, beta = al.x;
-      if (!(xn2 == 0.0 && al.y == 0.0)) {
-        beta = -copysign(sqrt(al.x * al.x + al.y * al.y + xn2), al.x);
-        tr = (beta - al.x) / beta;
-        ti = -al.y / beta;
-        const double dr = al.x - beta, di = al.y;
-        const double den = dr * dr + di * di;
-        sr = dr / den;
-        si = -di / den;
-      }
-      tau[i] = make_double2(tr, ti);
-      sh_scale = make_double2(sr, si);
-      pan[i][i] = make_double2(beta, 0.0);
-    }
-    __syncthreads();
-    const double2 sc = sh_scale;
-    for (int r = i + 1 + tid; r < L; r += 256) {
-      const double2 x = pan[r][i];
-      pan[r][i] = make_double2(x.x * sc.x - x.y * sc.y, x.x * sc.y + x.y * sc.x);
-    }
-    __syncthreads();
-    // H_i^H on the panel's later columns: one wavefront per column
-    const double2 t = tau[i];
-    for (int jj = i + 1 + wave; jj < nb; jj += 4) {
-      double wr = 0.0, wi = 0.0;
-      for (int r = i + lane; r < L; r += 64) {
-        const double2 v = r == i ? make_double2(1.0, 0.0) : pan[r][i];
-        const double2 b = pan[r][jj];
-        wr += v.x * b.x + v.y * b.y;
-        wi += v.x * b.y - v.y * b.x;
-      }
-      wr = hwave_sum(wr);
-      wi = hwave_sum(wi);
-      const double tr2 = t.x * wr + t.y * wi, ti2 = t.x * wi - t.y * wr;  // conj(tau) w
-      for (int r = i + lane; r < L; r += 64) {
-        const double2 v = r == i ? make_double2(1.0, 0.0) : pan[r][i];
-        double2 b = pan[r][jj];
-        b.x -= v.x * tr2 - v.y * ti2;
-        b.y -= v.x * ti2 + v.y * tr2;
-        pan[r][jj] = b;
+    const int buf = i & 1;
+    // deferred: column i - 1 becomes its Householder vector
+    if (i > 0 && jc == i - 1) {
+      const double2 sc = scl[i - 1];
+      for (int r = i + q16; r < L; r += 16) {
+        const double2 x = pan[r][i - 1];
+        pan[r][i - 1] = make_double2(x.x * sc.x - x.y * sc.y, x.x * sc.y + x.y * sc.x);
       }
     }
-    __syncthreads();
-  }
-  // Gram matrix G = V^H V (V unit lower trapezoidal) for the T factor
-  for (int e = wave; e < nb * nb; e += 4) {
-    const int a = e % nb, b = e / nb;
-    if (a >= b) continue;  // need G[a][b] for a < b
-    double gr = 0.0, gi = 0.0;
-    for (int r = b + lane; r < L; r += 64) {
-      const double2 va = r == a ? make_double2(1.0, 0.0) : pan[r][a];
-      const double2 vb = r == b ? make_double2(1.0, 0.0) : pan[r][b];
-      gr += va.x * vb.x + va.y * vb.y;
-      gi += va.x * vb.y - va.y * vb.x;
-    }
-    gr = hwave_sum(gr);
-    gi = hwave_sum(gi);
-    if (lane == 0) gram[a][b] = make_double2(gr, gi);
-  }
-  __syncthreads();
-  // T: T[i][i] = tau_i ; T[0:i, i] = -tau_i T[0:i, 0:i] G[0:i, i]
-  __shared__ double2 T[kHqNb][kHqNb + 1];
-  for (int e = tid; e < kHqNb * kHqNb; e += 256) T[e % kHqNb][e / kHqNb] = make_double2(0.0, 0.0);
-  __syncthreads();
-  if (tid == 0) {
-    for (int i = 0; i < nb; ++i) {
-      for (int a = 0; a < i; ++a) {
-        double2 s = make_double2(0.0, 0.0);
-        for (int q = a; q < i; ++q) {
-          const double2 x = T[a][q], g = gram[q][i];
-          s.x += x.x * g.x - x.y * g.y;
-          s.y += x.x * g.y + x.y * g.x;
+    // pass 1: |x|^2 below the diagonal of column i; raw products of column i
+    // with the later columns (rows below i)
+    double ar = 0.0, ai = 0.0;
+    if (jc >= i) {
+#pragma unroll 4
+      for (int r = i + 1 + q16; r < L; r += 16) {
+        const double2 x = pan[r][i];
+        if (jc == i) {
+          ar += x.x * x.x + x.y * x.y;
+        } else {
+          const double2 y = pan[r][jc];
+          ar += x.x * y.x + x.y * y.y;  // conj(x) y
+          ai += x.x * y.y - x.y * y.x;
         }
-        wcol[a] = s;
       }
+    }
+    ar = row16_sum(ar);
+    ai = row16_sum(ai);
+    if (q16 == 15) red[buf][jc] = make_double2(ar, ai);
+    __syncthreads();
+    // the reflector of column i, formed identically in every thread
+    const double xn2 = red[buf][i].x;
+    const double2 al = pan[i][i];
+    double tr = 0.0, ti = 0.0, sr = 1.0, si = 0.0, beta = al.x;
+    if (!(xn2 == 0.0 && al.y == 0.0)) {
+      beta = -copysign(sqrt(al.x * al.x + al.y * al.y + xn2), al.x);
+      tr = (beta - al.x) / beta;
+      ti = -al.y / beta;
+      const double dr = al.x - beta, di = al.y;
+      const double den = dr * dr + di * di;
+      sr = dr / den;
+      si = -di / den;
+    }
+    // pass 2: H_i^H on the later columns: w = y_i + conj(s) raw, u = conj(tau) w,
+    // y_i -= u, y_r -= s x_r u
+    if (jc > i && jc < kHqNb) {
+      const double2 raw = red[buf][jc], yi = pan[i][jc];
+      const double wr = yi.x + sr * raw.x + si * raw.y, wi = yi.y + sr * raw.y - si * raw.x;
+      const double ur = tr * wr + ti * wi, ui = tr * wi - ti * wr;
+      const double vr = sr * ur - si * ui, vi = sr * ui + si * ur;  // s u
+      if (q16 == 0) pan[i][jc] = make_double2(yi.x - ur, yi.y - ui);
+#pragma unroll 4
+      for (int r = i + 1 + q16; r < L; r += 16) {
+        const double2 x = pan[r][i];
+        double2 y = pan[r][jc];
+        y.x -= x.x * vr - x.y * vi;
+        y.y -= x.x * vi + x.y * vr;
+        pan[r][jc] = y;
+      }
+    }
+    if (tid == 0) {
+      tau[i] = make_double2(tr, ti);
+      scl[i] = make_double2(sr, si);
+    }
+    __syncthreads();
+    if (tid == 0) pan[i][i] = make_double2(beta, 0.0);  // column i is not read again until scaled
+  }
+  if (jc == nb - 1) {  // the last column's scaling
+    const double2 sc = scl[nb - 1];
+    for (int r = nb + q16; r < L; r += 16) {
+      const double2 x = pan[r][nb - 1];
+      pan[r][nb - 1] = make_double2(x.x * sc.x - x.y * sc.y, x.x * sc.y + x.y * sc.x);
+    }
+  }
+  __syncthreads();
+  // Gram matrix G = V^H V (V unit lower trapezoidal): thread (b, q) sums
+  // conj(v_a) v_b over its rows for every a < b
+  {
+    double2 g[kHqNb];
+#pragma unroll
+    for (int a = 0; a < kHqNb; ++a) g[a] = make_double2(0.0, 0.0);
+    if (jc < nb) {
+#pragma unroll 4
+      for (int r = jc + q16; r < L; r += 16) {
+        const double2 vb = r == jc ? make_double2(1.0, 0.0) : pan[r][jc];
+#pragma unroll
+        for (int a = 0; a < kHqNb; ++a) {
+          if (a < jc) {
+            const double2 va = r == a ? make_double2(1.0, 0.0) : pan[r][a];  // r >= jc > a
+            g[a].x += va.x * vb.x + va.y * vb.y;
+            g[a].y += va.x * vb.y - va.y * vb.x;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < kHqNb; ++a) {
+      const double gr = row16_sum(g[a].x), gi = row16_sum(g[a].y);
+      if (q16 == 15 && a < jc && jc < nb) gram[a][jc] = make_double2(gr, gi);
+    }
+  }
+  __syncthreads();
+  // T: T[i][i] = tau_i ; T[0:i, i] = -tau_i T[0:i, 0:i] G[0:i, i]  (wave 0,
+  // lane a computes row a)
+  if (wave == 0) {
+    for (int e = lane; e < kHqNb * kHqNb; e += 64) T[e % kHqNb][e / kHqNb] = make_double2(0.0, 0.0);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int i = 0; i < nb; ++i) {
       const double2 ti = tau[i];
-      for (int a = 0; a < i; ++a) {
-        const double2 s = wcol[a];
-        T[a][i] = make_double2(-(ti.x * s.x - ti.y * s.y), -(ti.x * s.y + ti.y * s.x));
+      if (lane < i) {
+        double2 sacc = make_double2(0.0, 0.0);
+        for (int q = lane; q < i; ++q) {
+          const double2 x = T[lane][q], gg = gram[q][i];
+          sacc.x += x.x * gg.x - x.y * gg.y;
+          sacc.y += x.x * gg.y + x.y * gg.x;
+        }
+        T[lane][i] = make_double2(-(ti.x * sacc.x - ti.y * sacc.y), -(ti.x * sacc.y + ti.y * sacc.x));
       }
-      T[i][i] = ti;
+      if (lane == i) T[i][i] = ti;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
   }
   __syncthreads();

@@ -1584,6 +1584,7 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
           // columns from k + 32 on.  Panel s needs the update of step s - 2
           // only, so it runs while the update of step s - 1 is in flight on
           // the second stream.
+          const int nsteps = (lv.maxn + kGjeNb - 1) / kGjeNb;
           if (prof) {  // one stream, every launch timed on its own
             for (int k = 0; k < lv.maxn; k += kGjeNb) {
               tb(&prof->gje_panel_ms);
@@ -1595,9 +1596,13 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
               prof->n_gje_panel++;
               prof->n_gje_update++;
             }
+            tb(&prof->gje_rhs_ms);
+            launch_gje_rhs(dg, ng, lv.maxrhs, lv.maxn, 0, nsteps, 0, ls);
+            te();
           } else {
             hipEvent_t rest1 = nullptr, rest2 = nullptr;  // updates of steps s - 1, s - 2
-            for (int k = 0; k < lv.maxn; k += kGjeNb) {
+            for (int st_i = 0; st_i < nsteps; ++st_i) {
+              const int k = st_i * kGjeNb;
               if (rest2) HIP_TRY(hipStreamWaitEvent(ls, rest2, 0));
               launch_gje_panel(dg, ng, k, lv.maxn, ls);
               hipEvent_t ep = ev_next();
@@ -1610,10 +1615,8 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
               rest1 = er;
             }
             if (rest1) HIP_TRY(hipStreamWaitEvent(ls, rest1, 0));
+            launch_gje_rhs(dg, ng, lv.maxrhs, lv.maxn, 0, nsteps, 0, ls);
           }
-          tb(prof ? &prof->gje_rhs_ms : nullptr);
-          launch_gje_rhs(dg, ng, lv.maxrhs, lv.maxn, ls);
-          te();
           if (!lv.upd.empty()) {
             tb(prof ? &prof->sweep_gemm_ms : nullptr);
             launch_gemm(reinterpret_cast<GemmDesc*>(dbase + o_upd[l]), (int)lv.upd.size(), lv.upd_tiles, ls);
