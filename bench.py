@@ -286,7 +286,7 @@ def main():
         "phase_ms": {k: round(v, 4) for k, v in prof.items() if k.endswith("_ms")},
         "roofline": roof,
     }
-    if sweep:
+    if sweep and args.plain_sample > 0:
         # the same angles solved one at a time, each with its own refill
         npl = min(args.plain_sample, len(thetas))
         idx = np.linspace(0, len(thetas) - 1, npl).round().astype(int)

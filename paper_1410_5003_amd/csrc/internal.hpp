@@ -167,6 +167,7 @@ constexpr int kGjeCols = 32;  // trailing columns per update workgroup
 constexpr int kGjeMaxN = 1024; // largest block order: the panel kernel holds 2 rows per thread (N_i <= 512)
 
 constexpr int kGjePivStride = 68;  // ints per step: count, 2 NB destinations, 2 NB sources
+constexpr int kRhsMaxN16 = 608;    // largest order whose 16-column right-hand-side tile fits in LDS
 
 // one matrix W = [D | right-hand sides] (n x ncol, ld n) reduced to [. | D^{-1} rhs]
 struct GjeDesc {

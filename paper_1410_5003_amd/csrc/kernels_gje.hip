@@ -524,7 +524,6 @@ __global__ __launch_bounds__(256) void gemv_step_kernel(const GemvDesc* __restri
 // accumulator layout of Z is exactly the B-operand layout of the update
 // product), then updates its blocks in LDS.
 constexpr int kRhsWaves = 8;
-constexpr int kRhsMaxN16 = 608;  // largest order whose 16-column tile fits in LDS
 
 // TC right-hand-side columns per workgroup (16, or 8 for orders up to
 // kGjeMaxN, whose 16-column tile would not fit in LDS: then lanes of columns
@@ -536,6 +535,7 @@ template <int TC, int MAXN>
 __global__ __launch_bounds__(kRhsWaves * 64) void gje_rhs_kernel(const GjeDesc* __restrict__ descs, int nbatch,
                                                                  int tiles_per, int s0, int s1) {
   constexpr int NBLK = (MAXN / 16 + kRhsWaves - 1) / kRhsWaves;  // row blocks per wave
+  constexpr int PF = NBLK <= 5 ? NBLK : 4;  // blocks whose multipliers are prefetched (register budget)
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int lr = lane & 15, lq = lane >> 4;
   const bool cl = lr < TC;
@@ -560,9 +560,9 @@ __global__ __launch_bounds__(kRhsWaves * 64) void gje_rhs_kernel(const GjeDesc* 
     const cplx* M1 = D.M1 + (size_t)sidx * kGjeNb * kGjeNb;
     // 0. operands of this step into registers: multipliers of my row blocks
     //    (lane: row r0 + lr, column kk + lq) and M1 (lane: row lr, column kk + lq)
-    double2 pa[NBLK][4], ma[4];
+    double2 pa[PF][4], ma[4];
 #pragma unroll
-    for (int j = 0; j < NBLK; ++j) {
+    for (int j = 0; j < PF; ++j) {
       const int row = (wave + j * kRhsWaves) * 16 + lr;
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
@@ -610,10 +610,19 @@ __global__ __launch_bounds__(kRhsWaves * 64) void gje_rhs_kernel(const GjeDesc* 
         }
         continue;
       }
+      double2 pb[4];
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int row = r0 + lr, kq = 4 * kk + lq;
+        if (j < PF)
+          pb[kk] = pa[j < PF ? j : 0][kk];
+        else
+          pb[kk] = (row < n && kq < nb) ? gld(W + (size_t)(k + kq) * n + row) : make_double2(0.0, 0.0);
+      }
       dvec4 accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
-        const double2 a = pa[j][kk];
+        const double2 a = pb[kk];
         const double br = zr[kk], bi = zi[kk];
         accr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, br, accr, 0, 0, 0);
         accr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, bi, accr, 0, 0, 0);

@@ -1346,8 +1346,9 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
     //        D_j - L_j XU_{e_l} - U_j XL_{e_r},  f_j - L_j xf_{e_l} - U_j xf_{e_r},
     //        L_j' = -L_j XL_{e_l},  U_j' = -U_j XU_{e_r}.
     struct Level {
-      std::vector<GjeDesc> gje;
+      std::vector<GjeDesc> gje;  // orders <= kRhsMaxN16 first (size classes of the right-hand-side kernel)
       int maxn = 0, maxcol = 0, maxrhs = 0;
+      int nsmall = 0, rhs_small = 0, rhs_large = 0;
       std::vector<GemmDesc> upd;
       int upd_tiles = 0;
       std::vector<GemvDesc> back;
@@ -1358,6 +1359,17 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
     std::vector<int> S_act(I);
     for (int i = 0; i < I; ++i) S_act[i] = i;
     auto Wp = [&](int b, int i, int which) { return V[b].W[which][i]; };
+    auto size_classes = [](Level& lv) {
+      std::stable_partition(lv.gje.begin(), lv.gje.end(), [](const GjeDesc& G) { return G.n <= kRhsMaxN16; });
+      for (const GjeDesc& G : lv.gje) {
+        if (G.n <= kRhsMaxN16) {
+          ++lv.nsmall;
+          lv.rhs_small = std::max(lv.rhs_small, G.ncol - G.n);
+        } else {
+          lv.rhs_large = std::max(lv.rhs_large, G.ncol - G.n);
+        }
+      }
+    };
     while (true) {
       Level lv;
       const int m = (int)S_act.size();
@@ -1382,6 +1394,7 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
         }
         lv.maxn = n[j];
         lv.backn = n[j];
+        size_classes(lv);
         levels.push_back(lv);
         break;
       }
@@ -1469,6 +1482,7 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
                      ner, nullptr, 1, nullptr, 1, 0);
         }
       }
+      size_classes(lv);
       levels.push_back(lv);
       std::vector<int> K;
       for (int p = 0; p < m; p += 2) {
@@ -1597,7 +1611,8 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
               prof->n_gje_update++;
             }
             tb(&prof->gje_rhs_ms);
-            launch_gje_rhs(dg, ng, lv.maxrhs, lv.maxn, 0, nsteps, 0, ls);
+            launch_gje_rhs(dg, lv.nsmall, lv.rhs_small, kRhsMaxN16, 0, nsteps, 0, ls);
+            launch_gje_rhs(dg + lv.nsmall, ng - lv.nsmall, lv.rhs_large, lv.maxn, 0, nsteps, 0, ls);
             te();
           } else {
             hipEvent_t rest1 = nullptr, rest2 = nullptr;  // updates of steps s - 1, s - 2
@@ -1615,7 +1630,8 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
               rest1 = er;
             }
             if (rest1) HIP_TRY(hipStreamWaitEvent(ls, rest1, 0));
-            launch_gje_rhs(dg, ng, lv.maxrhs, lv.maxn, 0, nsteps, 0, ls);
+            launch_gje_rhs(dg, lv.nsmall, lv.rhs_small, kRhsMaxN16, 0, nsteps, 0, ls);
+            launch_gje_rhs(dg + lv.nsmall, ng - lv.nsmall, lv.rhs_large, lv.maxn, 0, nsteps, 0, ls);
           }
           if (!lv.upd.empty()) {
             tb(prof ? &prof->sweep_gemm_ms : nullptr);
@@ -1650,6 +1666,7 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
         sig.push_back(lv.maxn);
         sig.push_back(lv.maxcol);
         sig.push_back(lv.maxrhs);
+        sig.push_back(lv.nsmall);
         sig.push_back((int64_t)lv.gje.size());
         sig.push_back(lv.upd_tiles);
         sig.push_back((int64_t)lv.upd.size());
