@@ -163,7 +163,6 @@ namespace mlh {
 constexpr double kAlphaTol = 1e-12;
 
 constexpr int kGjeNb = 16;  // panel width
-constexpr int kGjeCols = 32;  // trailing columns per update workgroup
 constexpr int kGjeMaxN = 1024; // largest block order: the panel kernel holds 2 rows per thread (N_i <= 512)
 
 constexpr int kGjePivStride = 68;  // ints per step: count, 2 NB destinations, 2 NB sources

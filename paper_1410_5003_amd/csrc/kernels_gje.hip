@@ -42,20 +42,27 @@ __device__ inline double2 cinv2(double2 a) {
   return make_double2(a.x / d, -a.y / d);
 }
 
-// Panel kernel: the n x NB panel columns live in registers, thread t owning
-// rows t and t + 512.  The kernel first applies the previous step's
-// transformation to them (the update kernel does the other columns), then
-// factors rows k..n-1.  Rows are not moved while the panel is
-// factored: a row that wins the pivot search for column c is marked done and
-// broadcast through LDS, so each column costs one workgroup barrier.  Every
-// wave reduces its candidates to one 64-bit key (high word of |a|^2, then the
-// complemented row index, so that ties go to the lowest row) with DPP moves,
-// and its winning lane stages its row in LDS next to the key.
-constexpr int kPanelThreads = 512;
-constexpr int kUpdThreads = 1024;
-constexpr int kUpdWaves = kUpdThreads / 64;
-constexpr int kPanelSlots = (kGjeMaxN + kPanelThreads - 1) / kPanelThreads;
-constexpr int kPanelWaves = kPanelThreads / 64;
+// Panel kernel.  Thread t of the workgroup owns rows k + t + s NT (s < SLOTS)
+// of the 16 panel columns, in registers.  It runs in three parts.
+//  1. (k > 0) The previous step's transformation on these columns, rows >= k:
+//     the old values, the previous interchanges and M1 arrive in one round of
+//     loads and the pivot rows Y1 (and the rows the interchanges bring in) in
+//     a second; Z = M1 Y1 goes to LDS; Y -= P Z runs on the matrix cores 16
+//     rows at a time, each result block handed to the rows' owners through a
+//     per-wave LDS tile.  The values reached are this step's start values;
+//     they go back to W, where the update kernels read their multipliers.
+//  2. LU with partial pivoting of rows k..n-1.  Rows are not moved: a row
+//     that wins the pivot search for column c is marked and its values are
+//     staged in LDS, so each column costs one workgroup barrier.  Every wave
+//     reduces its candidates to one 64-bit key (high word of |a|^2, then the
+//     complemented row offset, so that ties go to the lowest row) with DPP
+//     moves; the candidate lanes form the reciprocal of their pivot while the
+//     reduction runs, and the winning lane stages it with its row.
+//  3. The tail, split over waves: wave 0 composes this step's interchanges
+//     with ballots and applies them to the panel columns of W; wave 1 forms
+//     M1 = (L11 U11)^-1; the other waves apply the previous step to the rows
+//     above k (Z on its pivot rows, V - P Z above them).
+constexpr int kPanelMaxWaves = 10;
 
 template <int CTRL, int ROWS>
 __device__ inline uint64_t key_max_dpp(uint64_t x) {
@@ -79,116 +86,182 @@ __device__ inline uint64_t wave_key_max(uint64_t x) {
   return ((uint64_t)hi << 32) | lo;
 }
 
-__device__ inline uint64_t pivot_key(double2 v, int lr) {
+__device__ inline uint64_t pivot_key(double2 v, int rel) {
   const double m2 = v.x * v.x + v.y * v.y;
   const uint64_t hi = (uint64_t)(__double_as_longlong(m2)) >> 32;  // monotone for m2 >= 0
-  return (hi << 32) | (uint64_t)(0xffffffffu - (uint32_t)lr);
+  return (hi << 32) | (uint64_t)(0xffffffffu - (uint32_t)rel);
 }
 
-// state of one panel factorisation shared by the per-column steps
-struct PanelState {
-  double2 a[kPanelSlots][kGjeNb];
-  int pidx[kPanelSlots];  // pivot order of the row, -1 while still eligible
+// 1/v, zero for v = 0
+__device__ inline double2 crecip(double2 v) {
+  const double d = v.x * v.x + v.y * v.y;
+  const double r = d != 0.0 ? 1.0 / d : 0.0;
+  return make_double2(v.x * r, -v.y * r);
+}
+
+// value of lane S of each group of four lanes (DPP quad permutation)
+__device__ inline double quad_bcast(double v, int S) {
+  const long long b = __double_as_longlong(v);
+  int lo = (int)(uint32_t)b, hi = (int)(uint32_t)(b >> 32);
+  switch (S) {
+    case 0:
+      lo = __builtin_amdgcn_mov_dpp(lo, 0x00, 0xf, 0xf, false);
+      hi = __builtin_amdgcn_mov_dpp(hi, 0x00, 0xf, 0xf, false);
+      break;
+    case 1:
+      lo = __builtin_amdgcn_mov_dpp(lo, 0x55, 0xf, 0xf, false);
+      hi = __builtin_amdgcn_mov_dpp(hi, 0x55, 0xf, 0xf, false);
+      break;
+    case 2:
+      lo = __builtin_amdgcn_mov_dpp(lo, 0xaa, 0xf, 0xf, false);
+      hi = __builtin_amdgcn_mov_dpp(hi, 0xaa, 0xf, 0xf, false);
+      break;
+    default:
+      lo = __builtin_amdgcn_mov_dpp(lo, 0xff, 0xf, 0xf, false);
+      hi = __builtin_amdgcn_mov_dpp(hi, 0xff, 0xf, 0xf, false);
+      break;
+  }
+  return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+// orders LDS traffic between the lanes of one wavefront
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// rows of one thread and the LU state shared by the per-column steps
+template <int SLOTS>
+struct PanelRows {
+  double2 a[SLOTS][kGjeNb];
+  int pidx[SLOTS];  // pivot order of the row, -1 while still eligible, kGjeNb for no row
   int singular;
 };
 
-struct PanelShared {
-  uint64_t key[2][kPanelWaves];
-  double2 row[2][kPanelWaves][kGjeNb];
-  int spiv[kGjeNb];
+struct PanelShared {  // per-column exchange, double-buffered over columns
+  uint64_t key[2][kPanelMaxWaves];
+  double2 row[2][kPanelMaxWaves][kGjeNb];
+  double2 ip[2][kPanelMaxWaves];
+  int spiv[kGjeNb];       // global row of each pivot
+  double2 ipiv[kGjeNb];   // reciprocal of each pivot
 };
 
 // one column of the panel LU; C is a template parameter so that every
 // register index is static
-template <int C>
-__device__ __forceinline__ void panel_column(PanelState& st, PanelShared& sh, int nb, int k, int tid) {
+template <int NT, int SLOTS, int C>
+__device__ __forceinline__ void panel_column(PanelRows<SLOTS>& st, PanelShared& sh, int nb, int k, int tid) {
   if (C >= nb) return;
+  constexpr int NW = NT / 64;
   const int lane = tid & 63, wave = tid >> 6;
   const int buf = C & 1;
   uint64_t best = 0;
+  double2 cand = make_double2(0.0, 0.0);
 #pragma unroll
-  for (int sl = 0; sl < kPanelSlots; ++sl) {
-    const uint64_t key = st.pidx[sl] < 0 ? pivot_key(st.a[sl][C], tid + sl * kPanelThreads) : 0;
-    best = key > best ? key : best;
+  for (int sl = 0; sl < SLOTS; ++sl) {
+    const uint64_t key = st.pidx[sl] < 0 ? pivot_key(st.a[sl][C], tid + sl * NT) : 0;
+    if (key > best) {
+      best = key;
+      cand = st.a[sl][C];
+    }
   }
+  const double2 cip = crecip(cand);  // overlaps the reduction
   const uint64_t wbest = wave_key_max(best);
   if (lane == 0) sh.key[buf][wave] = wbest;
   if (wbest != 0 && best == wbest) {  // this lane holds the wave's candidate row
-    const int sl = (int)(0xffffffffu - (uint32_t)wbest) / kPanelThreads;
+    const int rel = (int)(0xffffffffu - (uint32_t)wbest);
 #pragma unroll
-    for (int s2 = 0; s2 < kPanelSlots; ++s2)
-      if (s2 == sl)
+    for (int sl = 0; sl < SLOTS; ++sl)
+      if (rel == tid + sl * NT)
 #pragma unroll
-        for (int j = 0; j < kGjeNb; ++j) sh.row[buf][wave][j] = st.a[s2][j];
+        for (int j = 0; j < kGjeNb; ++j) sh.row[buf][wave][j] = st.a[sl][j];
+    sh.ip[buf][wave] = cip;
   }
   __syncthreads();
-  uint64_t kb = sh.key[buf][0];
-  int wb = 0;
+  uint64_t kv[NW];
 #pragma unroll
-  for (int w = 1; w < kPanelWaves; ++w) {
-    const uint64_t kw = sh.key[buf][w];
-    if (kw > kb) {
-      kb = kw;
-      wb = w;
-    }
-  }
-  const int p = (int)(0xffffffffu - (uint32_t)kb);
+  for (int w = 0; w < NW; ++w) kv[w] = sh.key[buf][w];
+#pragma unroll
+  for (int s = 1; s < NW; s *= 2)
+#pragma unroll
+    for (int w = 0; w + s < NW; w += 2 * s) kv[w] = kv[w + s] > kv[w] ? kv[w + s] : kv[w];
+  const uint64_t kb = kv[0];
+  const int rel = (int)(0xffffffffu - (uint32_t)kb);  // pivot row - k
+  const int wb = (rel % NT) >> 6;                      // the wave that staged it
   if ((kb >> 32) == 0 && st.singular == 0) st.singular = k + C + 1;
-  if (tid == 0) sh.spiv[C] = p;
-  const double2 ucc = sh.row[buf][wb][C];
-  const bool ok = (ucc.x != 0.0 || ucc.y != 0.0);
-  const double2 ip = ok ? cinv2(ucc) : make_double2(0.0, 0.0);
+  const double2 ip = sh.ip[buf][wb];
   double2 prow[kGjeNb];
 #pragma unroll
   for (int j = C + 1; j < kGjeNb; ++j) prow[j] = sh.row[buf][wb][j];
+  if (tid == 0) {
+    sh.spiv[C] = k + rel;
+    sh.ipiv[C] = ip;
+  }
 #pragma unroll
-  for (int sl = 0; sl < kPanelSlots; ++sl) {
-    const int lr = tid + sl * kPanelThreads;
-    if (lr == p) {
+  for (int sl = 0; sl < SLOTS; ++sl) {
+    if (tid + sl * NT == rel) {
       st.pidx[sl] = C;
     } else if (st.pidx[sl] < 0) {
-      const double2 l = cmul2(st.a[sl][C], ip);
+      const double2 v = st.a[sl][C];
+      const double2 l = make_double2(v.x * ip.x - v.y * ip.y, v.x * ip.y + v.y * ip.x);
       st.a[sl][C] = l;
 #pragma unroll
       for (int j = C + 1; j < kGjeNb; ++j) {
-        const double2 t = cmul2(l, prow[j]);
-        st.a[sl][j].x -= t.x;
-        st.a[sl][j].y -= t.y;
+        double2 y = st.a[sl][j];
+        y.x = __builtin_fma(-l.x, prow[j].x, __builtin_fma(l.y, prow[j].y, y.x));
+        y.y = __builtin_fma(-l.x, prow[j].y, __builtin_fma(-l.y, prow[j].x, y.y));
+        st.a[sl][j] = y;
       }
     }
   }
 }
 
-template <int C>
+template <int NT, int SLOTS, int C>
 struct PanelColumns {
-  static __device__ __forceinline__ void run(PanelState& st, PanelShared& sh, int nb, int k, int tid) {
-    panel_column<C>(st, sh, nb, k, tid);
-    PanelColumns<C + 1>::run(st, sh, nb, k, tid);
+  static __device__ __forceinline__ void run(PanelRows<SLOTS>& st, PanelShared& sh, int nb, int k, int tid) {
+    panel_column<NT, SLOTS, C>(st, sh, nb, k, tid);
+    PanelColumns<NT, SLOTS, C + 1>::run(st, sh, nb, k, tid);
   }
 };
-template <>
-struct PanelColumns<kGjeNb> {
-  static __device__ __forceinline__ void run(PanelState&, PanelShared&, int, int, int) {}
+template <int NT, int SLOTS>
+struct PanelColumns<NT, SLOTS, kGjeNb> {
+  static __device__ __forceinline__ void run(PanelRows<SLOTS>&, PanelShared&, int, int, int) {}
 };
 
-__global__ __launch_bounds__(kPanelThreads) void gje_panel_kernel(const GjeDesc* __restrict__ descs, int k) {
+template <int NT, int SLOTS>
+__global__ __launch_bounds__(NT) void gje_panel_kernel(const GjeDesc* __restrict__ descs, int k) {
+  static_assert(NT % 64 == 0 && NT / 64 <= kPanelMaxWaves && NT >= 256, "panel workgroup shape");
+  constexpr int NW = NT / 64;
   const GjeDesc& D = descs[blockIdx.x];
   const int n = D.n;
   if (k >= n) return;
   const int nb = min(kGjeNb, n - k);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int lr = lane & 15, lq = lane >> 4;
   cplx* W = D.W;
   __shared__ PanelShared sh;
-  __shared__ double2 lu11[kGjeNb][kGjeNb + 1];
   __shared__ int sdst[2 * kGjeNb], ssrc[2 * kGjeNb], snaff;
-  __shared__ double2 stage[2 * kGjeNb][kGjeNb];
+  __shared__ double2 m1[kGjeNb][kGjeNb];
+  __shared__ double2 ys[kGjeNb][kGjeNb];
   __shared__ double2 zs[kGjeNb][kGjeNb];
+  __shared__ double2 tile[NW][kGjeNb][kGjeNb + 1];
+  __shared__ double2 lu11[kGjeNb][kGjeNb + 1];
+  __shared__ int pdst[2 * kGjeNb], psrc[2 * kGjeNb], below[kGjeNb];
+
+  PanelRows<SLOTS> st;
+  st.singular = 0;
+#pragma unroll
+  for (int sl = 0; sl < SLOTS; ++sl) {
+    const int r = k + tid + sl * NT;
+    st.pidx[sl] = r < n ? -1 : kGjeNb;
+#pragma unroll
+    for (int j = 0; j < kGjeNb; ++j)
+      st.a[sl][j] = (r < n && j < nb) ? gld(W + (size_t)(k + j) * n + r) : make_double2(0.0, 0.0);
+  }
+  const int kp = k - kGjeNb;
   if (k > 0) {
-    // the previous step's transformation on these 16 columns, in W (the
-    // update kernel does the columns after them): its row interchanges,
-    // Z = M1 Y(its pivot rows) and Y(other rows) -= P Z on the matrix cores
-    const int kp = k - kGjeNb;
-    const int lr = lane & 15, lq = lane >> 4;
+    // round 1: the previous step's interchanges and M1 (the old values of
+    // our rows are in flight above)
     const int* pivp = D.piv + (size_t)(kp / kGjeNb) * kGjePivStride;
     const cplx* M1p = D.M1 + (size_t)(kp / kGjeNb) * kGjeNb * kGjeNb;
     if (tid == 0) snaff = pivp[0];
@@ -196,235 +269,416 @@ __global__ __launch_bounds__(kPanelThreads) void gje_panel_kernel(const GjeDesc*
       sdst[tid] = pivp[1 + tid];
       ssrc[tid] = pivp[1 + 2 * kGjeNb + tid];
     }
+    if (tid < kGjeNb * kGjeNb) m1[tid % kGjeNb][tid / kGjeNb] = gld(M1p + tid);  // column-major M1
     __syncthreads();
-    const int nap = snaff;
-    for (int e = tid; e < nap * kGjeNb; e += kPanelThreads) {
-      const int t = e % nap, j = e / nap;
-      stage[t][j] = j < nb ? gld(W + (size_t)(k + j) * n + ssrc[t]) : make_double2(0.0, 0.0);
+    // round 2: Y1 = the previous pivot rows after the interchanges, and the
+    // rows the interchanges bring into our rows (all from rows kp..k-1)
+    const int naff = snaff;
+    if (tid < kGjeNb * kGjeNb) {
+      const int i = tid % kGjeNb, c = tid / kGjeNb;
+      int src = kp + i;
+      for (int t = 0; t < naff; ++t)
+        if (sdst[t] == kp + i) src = ssrc[t];
+      ys[i][c] = c < nb ? gld(W + (size_t)(k + c) * n + src) : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int sl = 0; sl < SLOTS; ++sl) {
+      const int r = k + tid + sl * NT;
+      int src = -1;
+      for (int t = 0; t < naff; ++t)
+        if (sdst[t] == r) src = ssrc[t];
+      if (src >= 0)
+#pragma unroll
+        for (int j = 0; j < kGjeNb; ++j)
+          st.a[sl][j] = j < nb ? gld(W + (size_t)(k + j) * n + src) : make_double2(0.0, 0.0);
     }
     __syncthreads();
-    for (int e = tid; e < nap * kGjeNb; e += kPanelThreads) {
-      const int t = e % nap, j = e / nap;
-      if (j < nb) gst(W + (size_t)(k + j) * n + sdst[t], stage[t][j]);
+    if (tid < kGjeNb * kGjeNb) {  // Z = M1 Y1
+      const int i = tid % kGjeNb, c = tid / kGjeNb;
+      double sr = 0.0, si = 0.0;
+#pragma unroll
+      for (int q = 0; q < kGjeNb; ++q) {
+        const double2 x = m1[i][q], y = ys[q][c];
+        sr += x.x * y.x - x.y * y.y;
+        si += x.x * y.y + x.y * y.x;
+      }
+      zs[i][c] = make_double2(sr, si);
     }
     __syncthreads();
-    if (wave == 0) {  // Z = M1 Y1: lane holds M1[lr][q] and Y1[q][lr], q = 4 kk + lq
-      dvec4 zr = {0, 0, 0, 0}, zi = {0, 0, 0, 0};
+    // Y -= P Z for our rows, 16 at a time: lane (lq, lr) holds P[r0 + lr][4 kk + lq]
+    // and receives (P Z)[r0 + lq + 4 q][lr]
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const int q = 4 * kk + lq;
-        const double2 m = gld(M1p + (size_t)q * kGjeNb + lr);
-        const double2 y = lr < nb ? gld(W + (size_t)(k + lr) * n + kp + q) : make_double2(0.0, 0.0);
-        zr = __builtin_amdgcn_mfma_f64_16x16x4f64(m.x, y.x, zr, 0, 0, 0);
-        zr = __builtin_amdgcn_mfma_f64_16x16x4f64(-m.y, y.y, zr, 0, 0, 0);
-        zi = __builtin_amdgcn_mfma_f64_16x16x4f64(m.x, y.y, zi, 0, 0, 0);
-        zi = __builtin_amdgcn_mfma_f64_16x16x4f64(m.y, y.x, zi, 0, 0, 0);
-      }
+    for (int sl = 0; sl < SLOTS; ++sl) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) zs[lq + 4 * q][lr] = make_double2(zr[q], zi[q]);
-    }
-    __syncthreads();
-    const int nrb = (n + 15) / 16;
-    for (int rb = wave; rb < nrb; rb += kPanelWaves) {
-      const int r0 = rb * 16;
-      if (r0 == kp) {  // the previous pivot rows receive Z
+      for (int i = 0; i < 4; ++i) {
+        const int r0 = k + sl * NT + wave * 64 + i * 16;
+        if (r0 >= n) break;
+        dvec4 accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if (lr < nb) gst(W + (size_t)(k + lr) * n + kp + lq + 4 * q, zs[lq + 4 * q][lr]);
-        continue;
-      }
-      dvec4 accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const int row = r0 + lr, q = 4 * kk + lq;
-        const double2 a = row < n ? gld(W + (size_t)(kp + q) * n + row) : make_double2(0.0, 0.0);
-        const double2 b = zs[q][lr];
-        accr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, accr, 0, 0, 0);
-        accr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, accr, 0, 0, 0);
-        acci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, acci, 0, 0, 0);
-        acci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, acci, 0, 0, 0);
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int row = r0 + lq + 4 * q;
-        if (row < n && lr < nb) {
-          cplx* p = W + (size_t)(k + lr) * n + row;
-          double2 v = gld(p);
-          v.x -= accr[q];
-          v.y -= acci[q];
-          gst(p, v);
+        for (int kk = 0; kk < 4; ++kk) {
+          const int row = r0 + lr, kq = 4 * kk + lq;
+          const double2 pa = row < n ? gld(W + (size_t)(kp + kq) * n + row) : make_double2(0.0, 0.0);
+          const double2 b = zs[kq][lr];
+          accr = __builtin_amdgcn_mfma_f64_16x16x4f64(pa.x, b.x, accr, 0, 0, 0);
+          accr = __builtin_amdgcn_mfma_f64_16x16x4f64(-pa.y, b.y, accr, 0, 0, 0);
+          acci = __builtin_amdgcn_mfma_f64_16x16x4f64(pa.x, b.y, acci, 0, 0, 0);
+          acci = __builtin_amdgcn_mfma_f64_16x16x4f64(pa.y, b.x, acci, 0, 0, 0);
         }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) tile[wave][lq + 4 * q][lr] = make_double2(accr[q], acci[q]);
+        wave_lds_sync();
+        if (lq == i) {
+#pragma unroll
+          for (int j = 0; j < kGjeNb; ++j) {
+            const double2 t = tile[wave][lr][j];
+            st.a[sl][j].x -= t.x;
+            st.a[sl][j].y -= t.y;
+          }
+        }
+        wave_lds_sync();
       }
     }
-    __syncthreads();
-  }
-  PanelState st;
-  st.singular = 0;
-  // every row of the panel columns: thread t holds rows t and t + 512
+    // this step's start values back to W
 #pragma unroll
-  for (int sl = 0; sl < kPanelSlots; ++sl) {
-    const int r = tid + sl * kPanelThreads;
-    st.pidx[sl] = (r >= k && r < n) ? -1 : kGjeNb;
+    for (int sl = 0; sl < SLOTS; ++sl) {
+      const int r = k + tid + sl * NT;
+      if (r < n)
 #pragma unroll
-    for (int j = 0; j < kGjeNb; ++j)
-      st.a[sl][j] = (r < n && j < nb) ? gld(W + (size_t)(k + j) * n + r) : make_double2(0.0, 0.0);
+        for (int j = 0; j < kGjeNb; ++j)
+          if (j < nb) gst(W + (size_t)(k + j) * n + r, st.a[sl][j]);
+    }
   }
-  double2 (&a)[kPanelSlots][kGjeNb] = st.a;
-  int (&pidx)[kPanelSlots] = st.pidx;
-  PanelColumns<0>::run(st, sh, nb, k, tid);
-  const int singular = st.singular;
-  int* spiv = sh.spiv;
-  if (tid == 0 && singular != 0) atomicCAS(D.info, 0, singular);
+  PanelColumns<NT, SLOTS, 0>::run(st, sh, nb, k, tid);
+  if (tid == 0 && st.singular != 0) atomicCAS(D.info, 0, st.singular);
   // the factored pivot block: row of pivot c holds L11 (j < c) and U11 (j >= c)
 #pragma unroll
-  for (int sl = 0; sl < kPanelSlots; ++sl)
-    if (pidx[sl] >= 0 && pidx[sl] < kGjeNb)
+  for (int sl = 0; sl < SLOTS; ++sl)
+    if (st.pidx[sl] >= 0 && st.pidx[sl] < kGjeNb)
 #pragma unroll
-      for (int j = 0; j < kGjeNb; ++j) lu11[pidx[sl]][j] = a[sl][j];
-  if (tid >= nb && tid < kGjeNb)
+      for (int j = 0; j < kGjeNb; ++j) lu11[st.pidx[sl]][j] = st.a[sl][j];
+  if (tid >= nb && tid < kGjeNb) {
 #pragma unroll
     for (int j = 0; j < kGjeNb; ++j) lu11[tid][j] = make_double2(0.0, 0.0);
-  // the row permutation of this step as (destination, source) pairs of
-  // global rows: pivot q (row spiv[q], never moved in registers) goes to
-  // position k + q; rows of positions k..k+nb-1 that were not chosen fill the
-  // positions the chosen rows vacated below the block.  piv[0] = count,
-  // piv[1..] destinations, piv[1+2NB..] sources.
-  __syncthreads();
-  if (tid == 0) {
-    int na = 0;
-    bool chosen[kGjeNb];
-    for (int q = 0; q < kGjeNb; ++q) chosen[q] = false;
-    for (int q = 0; q < nb; ++q)
-      if (spiv[q] - k < nb) chosen[spiv[q] - k] = true;
-    int nxt = 0;  // next pivot row from below the block, in pivot order
-    for (int q = 0; q < nb; ++q) {
-      if (spiv[q] != k + q) {
-        sdst[na] = k + q;
-        ssrc[na] = spiv[q];
-        ++na;
-      }
-      if (!chosen[q]) {  // row at position q was displaced: send it below
-        while (spiv[nxt] - k < nb) ++nxt;
-        sdst[na] = spiv[nxt];
-        ssrc[na] = k + q;
-        ++na;
-        ++nxt;
-      }
-    }
-    int* piv = D.piv + (size_t)(k / kGjeNb) * kGjePivStride;
-    piv[0] = na;
-    snaff = na;
-    for (int t = 0; t < na; ++t) {
-      piv[1 + t] = sdst[t];
-      piv[1 + 2 * kGjeNb + t] = ssrc[t];
-    }
+    sh.ipiv[tid] = make_double2(0.0, 0.0);
   }
   __syncthreads();
-  // apply the interchanges to the panel columns of W, which hold the values
-  // the panel started from: the update kernels read their multipliers
-  // (those values, for the rows off the pivot block) from there
-  const int naff = snaff;
-  for (int e = tid; e < naff * kGjeNb; e += kPanelThreads) {
-    const int t = e % naff, j = e / naff;
-    stage[t][j] = j < nb ? gld(W + (size_t)(k + j) * n + ssrc[t]) : make_double2(0.0, 0.0);
-  }
-  __syncthreads();
-  for (int e = tid; e < naff * kGjeNb; e += kPanelThreads) {
-    const int t = e % naff, j = e / naff;
-    if (j < nb) gst(W + (size_t)(k + j) * n + sdst[t], stage[t][j]);
-  }
-  // M1 = (L11 U11)^{-1} in wave 0: lane (lq, lr) holds rows lq + 4 q of
-  // column lr; X = L11^{-1} by row operations, then M1 = U11^{-1} X
   if (wave == 0) {
-    const int lr = lane & 15, lq = lane >> 4;
+    // this step's row permutation as (destination, source) pairs of global
+    // rows: pivot q (row spiv[q], never moved in registers) goes to k + q;
+    // rows of positions k..k+nb-1 that were not chosen fill, in order, the
+    // rows that the pivots from below the block vacated, in pivot order.
+    // piv[0] = count, piv[1..] destinations, piv[1+2NB..] sources.
+    const int q = lane;
+    const int p = q < nb ? sh.spiv[q] : -1;
+    bool chosen = false;
+    for (int t = 0; t < nb; ++t) chosen |= (sh.spiv[t] == k + q);
+    const bool isA = q < nb && p != k + q;
+    const bool isB = q < nb && p >= k + nb;
+    const bool isU = q < nb && !chosen;
+    const uint64_t bA = __ballot(isA), bB = __ballot(isB), bU = __ballot(isU);
+    const uint64_t lt = (1ull << lane) - 1ull;
+    const int nA = __popcll(bA);
+    if (isB) below[__popcll(bB & lt)] = p;
+    wave_lds_sync();
+    int* piv = D.piv + (size_t)(k / kGjeNb) * kGjePivStride;
+    if (isA) {
+      const int t = __popcll(bA & lt);
+      pdst[t] = k + q;
+      psrc[t] = p;
+      piv[1 + t] = k + q;
+      piv[1 + 2 * kGjeNb + t] = p;
+    }
+    if (isU) {
+      const int u = __popcll(bU & lt), t = nA + u;
+      pdst[t] = below[u];
+      psrc[t] = k + q;
+      piv[1 + t] = below[u];
+      piv[1 + 2 * kGjeNb + t] = k + q;
+    }
+    const int na = nA + __popcll(bU);
+    if (lane == 0) piv[0] = na;
+    wave_lds_sync();
+    // apply it to the panel columns of W (this step's start values): every
+    // source is read before any destination is written
+    double2 v[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int e = lane + 64 * m;
+      v[m] = e < na * nb ? gld(W + (size_t)(k + e / na) * n + psrc[e % na]) : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int e = lane + 64 * m;
+      if (e < na * nb) gst(W + (size_t)(k + e / na) * n + pdst[e % na], v[m]);
+    }
+  } else if (wave == 1) {
+    // M1 = (L11 U11)^{-1}: lane 4 c + g holds rows g + 4 q of column c;
+    // X = L11^{-1} by row operations, then M1 = U11^{-1} X with the pivot
+    // reciprocals of the factorisation
+    const int c = lane >> 2, g = lane & 3;
     double2 x[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) x[q] = make_double2(lq + 4 * q == lr ? 1.0 : 0.0, 0.0);
+    for (int q = 0; q < 4; ++q) x[q] = make_double2(g + 4 * q == c ? 1.0 : 0.0, 0.0);
 #pragma unroll
     for (int r = 0; r < kGjeNb - 1; ++r) {
-      const double2 xr = make_double2(__shfl(x[r / 4].x, (r % 4) * 16 + lr, 64), __shfl(x[r / 4].y, (r % 4) * 16 + lr, 64));
+      const double2 xr = make_double2(quad_bcast(x[r / 4].x, r % 4), quad_bcast(x[r / 4].y, r % 4));
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int i = lq + 4 * q;
+        const int i = g + 4 * q;
         if (i > r) {
           const double2 l = lu11[i][r];
-          x[q].x -= l.x * xr.x - l.y * xr.y;
-          x[q].y -= l.x * xr.y + l.y * xr.x;
+          x[q].x = __builtin_fma(-l.x, xr.x, __builtin_fma(l.y, xr.y, x[q].x));
+          x[q].y = __builtin_fma(-l.x, xr.y, __builtin_fma(-l.y, xr.x, x[q].y));
         }
       }
     }
 #pragma unroll
     for (int r = kGjeNb - 1; r >= 0; --r) {
-      const double2 d = lu11[r][r];
-      const bool ok = r < nb && (d.x != 0.0 || d.y != 0.0);
-      double2 xr = make_double2(__shfl(x[r / 4].x, (r % 4) * 16 + lr, 64), __shfl(x[r / 4].y, (r % 4) * 16 + lr, 64));
-      xr = ok ? cmul2(xr, cinv2(d)) : make_double2(0.0, 0.0);
+      const double2 y = make_double2(quad_bcast(x[r / 4].x, r % 4), quad_bcast(x[r / 4].y, r % 4));
+      const double2 d = sh.ipiv[r];
+      const double2 xr = make_double2(y.x * d.x - y.y * d.y, y.x * d.y + y.y * d.x);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int i = lq + 4 * q;
+        const int i = g + 4 * q;
         if (i == r) {
           x[q] = xr;
         } else if (i < r) {
           const double2 u = lu11[i][r];
-          x[q].x -= u.x * xr.x - u.y * xr.y;
-          x[q].y -= u.x * xr.y + u.y * xr.x;
+          x[q].x = __builtin_fma(-u.x, xr.x, __builtin_fma(u.y, xr.y, x[q].x));
+          x[q].y = __builtin_fma(-u.x, xr.y, __builtin_fma(-u.y, xr.x, x[q].y));
         }
       }
     }
     cplx* M1 = D.M1 + (size_t)(k / kGjeNb) * kGjeNb * kGjeNb;
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      gst(M1 + (size_t)lr * kGjeNb + lq + 4 * q, lr < nb ? x[q] : make_double2(0.0, 0.0));
+    for (int q = 0; q < 4; ++q) gst(M1 + (size_t)c * kGjeNb + g + 4 * q, c < nb ? x[q] : make_double2(0.0, 0.0));
+  } else if (k > 0) {
+    // the previous step on rows above k: its pivot rows kp..k-1 receive Z,
+    // rows above them V - P Z (old values as the accumulators)
+    const int wt = tid - 128;
+    for (int e = wt; e < kGjeNb * kGjeNb; e += NT - 128) {
+      const int i = e % kGjeNb, c = e / kGjeNb;
+      if (c < nb) gst(W + (size_t)(k + c) * n + kp + i, zs[i][c]);
+    }
+    constexpr int G = 3;  // row blocks in flight per wave
+    const int nrb = kp / 16;
+    for (int b0 = wave - 2; b0 < nrb; b0 += G * (NW - 2)) {
+      double2 pa[G][4];
+      dvec4 vr[G], vi[G];
+#pragma unroll
+      for (int h = 0; h < G; ++h) {
+        const int rb = b0 + h * (NW - 2);
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+          pa[h][kk] = rb < nrb ? gld(W + (size_t)(kp + 4 * kk + lq) * n + rb * 16 + lr) : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double2 v = (rb < nrb && lr < nb) ? gld(W + (size_t)(k + lr) * n + rb * 16 + lq + 4 * q)
+                                                   : make_double2(0.0, 0.0);
+          vr[h][q] = v.x;
+          vi[h][q] = v.y;
+        }
+      }
+#pragma unroll
+      for (int h = 0; h < G; ++h) {
+        const int rb = b0 + h * (NW - 2);
+        if (rb >= nrb) break;
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const double2 a = pa[h][kk], b = zs[4 * kk + lq][lr];
+          vr[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.x, b.x, vr[h], 0, 0, 0);
+          vr[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, vr[h], 0, 0, 0);
+          vi[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.x, b.y, vi[h], 0, 0, 0);
+          vi[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.x, vi[h], 0, 0, 0);
+        }
+        if (lr < nb)
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            gst(W + (size_t)(k + lr) * n + rb * 16 + lq + 4 * q, make_double2(vr[h][q], vi[h][q]));
+      }
+    }
   }
 }
 
-// columns [k + nb + lo, min(n, k + nb + hi)) of the diagonal block; the
-// right-hand-side columns are left to gje_rhs_kernel, after all steps
-__global__ __launch_bounds__(kUpdThreads) void gje_update_kernel(const GjeDesc* __restrict__ descs, int k, int lo,
-                                                                 int hi) {
+// Update kernel: one workgroup of 12 waves per 16 columns of the diagonal
+// block, columns [k + nb + lo, min(n, k + nb + hi)), every row (orders up to
+// kUpdMaxN); the right-hand-side columns are left to gje_rhs_kernel, after
+// all steps.  Each wave owns up to kUpdRbw 16-row blocks.  Latency decides
+// this kernel at the deep levels of the reduction, so its global traffic
+// comes in two dependent rounds: (1) the interchanges, M1, the multipliers P
+// and the old values of its rows, all at once; (2) the rows the interchanges
+// move and the pivot rows Y1.  An interchanged row then takes its new value
+// from LDS instead of being scattered through memory first.  The workgroup
+// spans all rows because every row of its columns needs the old values of
+// the interchanged and pivot rows.
+constexpr int kUpdWaves = 12;
+constexpr int kUpdRbw = 3;
+constexpr int kUpdMaxN = kUpdWaves * kUpdRbw * 16;  // 576
+constexpr int kUpdCols = 16;
+constexpr int kUpdWideThreads = 1024;
+constexpr int kUpdWideWaves = kUpdWideThreads / 64;
+constexpr int kUpdWideCols = 32;
+
+__global__ __launch_bounds__(kUpdWaves * 64) void gje_update_kernel(const GjeDesc* __restrict__ descs, int k, int lo,
+                                                                    int hi) {
   const GjeDesc& D = descs[blockIdx.y];
   const int n = D.n;
   if (k >= n) return;
   const int nb = min(kGjeNb, n - k);
   const int cend = min(n, k + nb + hi);
-  const int c0 = k + nb + lo + blockIdx.x * kGjeCols;
+  const int c0 = k + nb + lo + blockIdx.x * kUpdCols;
   if (c0 >= cend) return;
-  const int nc = min(kGjeCols, cend - c0);
+  const int nc = min(kUpdCols, cend - c0);
+  const int* piv = D.piv + (size_t)(k / kGjeNb) * kGjePivStride;
+  const cplx* M1 = D.M1 + (size_t)(k / kGjeNb) * kGjeNb * kGjeNb;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int lr = lane & 15, lq = lane >> 4;
+  cplx* W = D.W;
+  __shared__ int sdst[2 * kGjeNb], ssrc[2 * kGjeNb], snaff;
+  __shared__ short rowmap[kUpdMaxN];  // stage slot of a row an interchange overwrites, else -1
+  __shared__ double2 m1[kGjeNb][kGjeNb];
+  __shared__ double2 stage[2 * kGjeNb][kUpdCols];
+  __shared__ double2 y1[kGjeNb][kUpdCols];
+  __shared__ double2 zs[kGjeNb][kUpdCols];
+  // round 1
+  if (tid == 0) snaff = piv[0];
+  if (tid < 2 * kGjeNb) {
+    sdst[tid] = piv[1 + tid];
+    ssrc[tid] = piv[1 + 2 * kGjeNb + tid];
+  }
+  if (tid < kGjeNb * kGjeNb) m1[tid % kGjeNb][tid / kGjeNb] = gld(M1 + tid);  // column-major M1
+  for (int i = tid; i < n; i += kUpdWaves * 64) rowmap[i] = -1;
+  // the old values are held as the accumulators of Y - P Z: register q of
+  // lane (lq, lr) is row r0 + lq + 4 q of column c0 + lr
+  double2 P[kUpdRbw][4];
+  dvec4 Vr[kUpdRbw], Vi[kUpdRbw];
+#pragma unroll
+  for (int j = 0; j < kUpdRbw; ++j) {
+    const int r0 = (wave + kUpdWaves * j) * 16;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int row = r0 + lr, kq = 4 * kk + lq;
+      P[j][kk] = (row < n && kq < nb) ? gld(W + (size_t)(k + kq) * n + row) : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int row = r0 + lq + 4 * q;
+      const double2 v = (row < n && lr < nc) ? gld(W + (size_t)(c0 + lr) * n + row) : make_double2(0.0, 0.0);
+      Vr[j][q] = v.x;
+      Vi[j][q] = v.y;
+    }
+  }
+  __syncthreads();
+  // round 2: the rows the interchanges move, and Y1 (the pivot rows after them)
+  const int naff = snaff;
+  if (tid < naff) rowmap[sdst[tid]] = (short)tid;
+  for (int e = tid; e < naff * kUpdCols; e += kUpdWaves * 64) {
+    const int t = e % naff, c = e / naff;
+    stage[t][c] = c < nc ? gld(W + (size_t)(c0 + c) * n + ssrc[t]) : make_double2(0.0, 0.0);
+  }
+  if (tid < kGjeNb * kUpdCols) {
+    const int r = tid % kGjeNb, c = tid / kGjeNb;
+    int src = k + r;
+    for (int t = 0; t < naff; ++t)
+      if (sdst[t] == k + r) src = ssrc[t];
+    y1[r][c] = (r < nb && c < nc) ? gld(W + (size_t)(c0 + c) * n + src) : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  if (tid < kGjeNb * kUpdCols) {  // Z = M1 Y1
+    const int r = tid % kGjeNb, c = tid / kGjeNb;
+    double sr = 0.0, si = 0.0;
+#pragma unroll
+    for (int q = 0; q < kGjeNb; ++q) {
+      const double2 a = m1[r][q], b = y1[q][c];
+      sr += a.x * b.x - a.y * b.y;
+      si += a.x * b.y + a.y * b.x;
+    }
+    zs[r][c] = make_double2(sr, si);
+  }
+  __syncthreads();
+  // Y(other rows) = Y(after the interchanges) - P Z on the matrix cores;
+  // the pivot rows receive Z
+#pragma unroll
+  for (int j = 0; j < kUpdRbw; ++j) {
+    const int r0 = (wave + kUpdWaves * j) * 16;
+    if (r0 >= n) break;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int row = r0 + lq + 4 * q;
+      const int m = row < n ? rowmap[row] : -1;
+      if (m >= 0) {
+        const double2 v = stage[m][lr];
+        Vr[j][q] = v.x;
+        Vi[j][q] = v.y;
+      }
+    }
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const double2 a = P[j][kk], b = zs[4 * kk + lq][lr];
+      Vr[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.x, b.x, Vr[j], 0, 0, 0);
+      Vr[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, Vr[j], 0, 0, 0);
+      Vi[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.x, b.y, Vi[j], 0, 0, 0);
+      Vi[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.x, Vi[j], 0, 0, 0);
+    }
+    if (lr < nc) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = r0 + lq + 4 * q;
+        if (row >= n) continue;
+        const double2 v = (row >= k && row < k + nb) ? zs[row - k][lr] : make_double2(Vr[j][q], Vi[j][q]);
+        gst(W + (size_t)(c0 + lr) * n + row, v);
+      }
+    }
+  }
+}
+
+// Orders above kUpdMaxN: one workgroup of 16 waves per 32 columns, each wave
+// walking its row blocks with the old values loaded as it goes.
+__global__ __launch_bounds__(kUpdWideThreads) void gje_update_wide_kernel(const GjeDesc* __restrict__ descs, int k,
+                                                                          int lo, int hi) {
+  const GjeDesc& D = descs[blockIdx.y];
+  const int n = D.n;
+  if (k >= n) return;
+  const int nb = min(kGjeNb, n - k);
+  const int cend = min(n, k + nb + hi);
+  const int c0 = k + nb + lo + blockIdx.x * kUpdWideCols;
+  if (c0 >= cend) return;
+  const int nc = min(kUpdWideCols, cend - c0);
   const int* piv = D.piv + (size_t)(k / kGjeNb) * kGjePivStride;
   const cplx* M1 = D.M1 + (size_t)(k / kGjeNb) * kGjeNb * kGjeNb;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   cplx* W = D.W;
-  __shared__ double zr[kGjeNb][kGjeCols + 1], zi[kGjeNb][kGjeCols + 1];
+  __shared__ double zr[kGjeNb][kUpdWideCols + 1], zi[kGjeNb][kUpdWideCols + 1];
   __shared__ double2 m1[kGjeNb][kGjeNb];
-  __shared__ double2 y1[kGjeNb][kGjeCols];
+  __shared__ double2 y1[kGjeNb][kUpdWideCols];
   // 1. row interchanges of this step on our columns, as (destination, source)
   //    pairs composed by the panel kernel: stage the sources, then write back
   __shared__ int sdst[2 * kGjeNb], ssrc[2 * kGjeNb];
-  __shared__ double2 stage[2 * kGjeNb][kGjeCols];
+  __shared__ double2 stage[2 * kGjeNb][kUpdWideCols];
   const int naff = piv[0];
   if (tid < naff) {
     sdst[tid] = piv[1 + tid];
     ssrc[tid] = piv[1 + 2 * kGjeNb + tid];
   }
-  for (int e = tid; e < kGjeNb * kGjeNb; e += kUpdThreads) m1[e % kGjeNb][e / kGjeNb] = gld(M1 + e);
+  for (int e = tid; e < kGjeNb * kGjeNb; e += kUpdWideThreads) m1[e % kGjeNb][e / kGjeNb] = gld(M1 + e);
   __syncthreads();
-  for (int e = tid; e < naff * nc; e += kUpdThreads) {
+  for (int e = tid; e < naff * nc; e += kUpdWideThreads) {
     const int t = e % naff, c = e / naff;
     stage[t][c] = gld(W + (size_t)(c0 + c) * n + ssrc[t]);
   }
   __syncthreads();
-  for (int e = tid; e < naff * nc; e += kUpdThreads) {
+  for (int e = tid; e < naff * nc; e += kUpdWideThreads) {
     const int t = e % naff, c = e / naff;
     gst(W + (size_t)(c0 + c) * n + sdst[t], stage[t][c]);
   }
   __syncthreads();
   // 2. Z = M1 Y1
-  for (int e = tid; e < kGjeNb * kGjeCols; e += kUpdThreads) {
+  for (int e = tid; e < kGjeNb * kUpdWideCols; e += kUpdWideThreads) {
     const int r = e % kGjeNb, c = e / kGjeNb;
     y1[r][c] = (r < nb && c < nc) ? gld(W + (size_t)(c0 + c) * n + k + r) : make_double2(0.0, 0.0);
   }
   __syncthreads();
-  for (int e = tid; e < kGjeNb * kGjeCols; e += kUpdThreads) {
+  for (int e = tid; e < kGjeNb * kUpdWideCols; e += kUpdWideThreads) {
     const int r = e % kGjeNb, c = e / kGjeNb;
     double sr = 0.0, si = 0.0;
 #pragma unroll
@@ -439,7 +693,7 @@ __global__ __launch_bounds__(kUpdThreads) void gje_update_kernel(const GjeDesc* 
   __syncthreads();
   // 3. Y(other rows) -= P Z on the matrix cores: 16-row blocks, two 16-column blocks
   const int nrb = (n + 15) / 16;
-  for (int rb = wave; rb < nrb; rb += kUpdWaves) {
+  for (int rb = wave; rb < nrb; rb += kUpdWideWaves) {
     const int r0 = rb * 16;  // the pivot rows have zero multipliers and are masked below
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb) {
@@ -475,7 +729,7 @@ __global__ __launch_bounds__(kUpdThreads) void gje_update_kernel(const GjeDesc* 
     }
   }
   // 4. pivot rows receive Z
-  for (int e = tid; e < nb * nc; e += kUpdThreads) {
+  for (int e = tid; e < nb * nc; e += kUpdWideThreads) {
     const int r = e % nb, c = e / nb;
     gst(W + (size_t)(c0 + c) * n + k + r, make_double2(zr[r][c], zi[r][c]));
   }
@@ -653,15 +907,22 @@ __global__ __launch_bounds__(kRhsWaves * 64) void gje_rhs_kernel(const GjeDesc* 
 void gje_init() {}
 
 void launch_gje_panel(const GjeDesc* d, int nbatch, int k, int max_n, hipStream_t st) {
-  const size_t lds = (size_t)(max_n - k) * kGjeNb * sizeof(double2);
-  (void)lds;
-  if (nbatch > 0 && max_n > k) hipLaunchKernelGGL(gje_panel_kernel, dim3(nbatch), dim3(kPanelThreads), 0, st, d, k);
+  if (nbatch <= 0 || max_n <= k) return;
+  if (max_n - k <= 640)
+    hipLaunchKernelGGL((gje_panel_kernel<640, 1>), dim3(nbatch), dim3(640), 0, st, d, k);
+  else
+    hipLaunchKernelGGL((gje_panel_kernel<512, 2>), dim3(nbatch), dim3(512), 0, st, d, k);
 }
 void launch_gje_update(const GjeDesc* d, int nbatch, int k, int max_n, int lo, int hi, hipStream_t st) {
   const int width = std::min(max_n - k - kGjeNb, hi) - lo;
   if (nbatch > 0 && width > 0) {
-    const int tiles = (width - 1) / kGjeCols + 1;
-    hipLaunchKernelGGL(gje_update_kernel, dim3(tiles, nbatch), dim3(kUpdThreads), 0, st, d, k, lo, hi);
+    if (max_n <= kUpdMaxN) {
+      const int tiles = (width - 1) / kUpdCols + 1;
+      hipLaunchKernelGGL(gje_update_kernel, dim3(tiles, nbatch), dim3(kUpdWaves * 64), 0, st, d, k, lo, hi);
+    } else {
+      const int tiles = (width - 1) / kUpdWideCols + 1;
+      hipLaunchKernelGGL(gje_update_wide_kernel, dim3(tiles, nbatch), dim3(kUpdWideThreads), 0, st, d, k, lo, hi);
+    }
   }
 }
 void launch_gje_rhs(const GjeDesc* d, int nbatch, int max_rhs, int max_n, int s0, int s1, int max_blocks,
