@@ -162,6 +162,32 @@ namespace mlh {
 // 1 to this tolerance (alpha = exp(i kappa_0 d) then agrees to about 1e-11)
 constexpr double kAlphaTol = 1e-12;
 
+// Kernels reach device memory through pointers held in descriptors, whose
+// address space the compiler cannot infer; these casts let it emit global
+// rather than flat memory instructions.  Global accesses count against the
+// vector-memory counter only, so a wait for LDS data does not also wait for
+// every load still in flight.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* gmem(const T* p) {
+  return (const __attribute__((address_space(1))) T*)p;
+}
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+typedef double gdouble2 __attribute__((ext_vector_type(2)));
+// one complex value from / to device memory, as a 16-byte global access
+__device__ __forceinline__ double2 ldc(const cplx* p) {
+  const gdouble2 v = *gmem(reinterpret_cast<const gdouble2*>(p));
+  return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void stc(cplx* p, double re, double im) {
+  gdouble2 v;
+  v.x = re;
+  v.y = im;
+  *gmem(reinterpret_cast<gdouble2*>(p)) = v;
+}
+
 constexpr int kGjeNb = 16;  // panel width
 constexpr int kGjeMaxN = 1024; // largest block order: the panel kernel holds 2 rows per thread (N_i <= 512)
 

@@ -36,7 +36,7 @@ __device__ inline int find_job(const T* jobs, int njobs, int key) {
   return lo;
 }
 
-__device__ inline void store(cplx* p, cplx v) { *reinterpret_cast<double2*>(p) = make_double2(v.re, v.im); }
+__device__ inline void store(cplx* p, cplx v) { stc(p, v.re, v.im); }
 
 __global__ __launch_bounds__(256) void fill_kernel(const FillJob* __restrict__ jobs, int njobs, int tile0) {
   const int tile = tile0 + (int)blockIdx.x;

@@ -32,8 +32,8 @@ namespace mlh {
 
 typedef double dvec4 __attribute__((ext_vector_type(4)));
 
-__device__ inline double2 gld(const cplx* p) { return *reinterpret_cast<const double2*>(p); }
-__device__ inline void gst(cplx* p, double2 v) { *reinterpret_cast<double2*>(p) = v; }
+__device__ inline double2 gld(const cplx* p) { return ldc(p); }
+__device__ inline void gst(cplx* p, double2 v) { stc(p, v.x, v.y); }
 __device__ inline double2 cmul2(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
@@ -64,40 +64,6 @@ __device__ inline double2 cinv2(double2 a) {
 //     above k (Z on its pivot rows, V - P Z above them).
 constexpr int kPanelMaxWaves = 10;
 
-template <int CTRL, int ROWS>
-__device__ inline uint64_t key_max_dpp(uint64_t x) {
-  const int lo = (int)(uint32_t)x, hi = (int)(uint32_t)(x >> 32);
-  const uint32_t lo2 = (uint32_t)__builtin_amdgcn_update_dpp(0, lo, CTRL, ROWS, 0xf, true);
-  const uint32_t hi2 = (uint32_t)__builtin_amdgcn_update_dpp(0, hi, CTRL, ROWS, 0xf, true);
-  const uint64_t y = ((uint64_t)hi2 << 32) | lo2;
-  return y > x ? y : x;
-}
-
-// maximum of x over the wavefront, returned in every lane
-__device__ inline uint64_t wave_key_max(uint64_t x) {
-  x = key_max_dpp<0x111, 0xf>(x);  // row_shr:1
-  x = key_max_dpp<0x112, 0xf>(x);  // row_shr:2
-  x = key_max_dpp<0x114, 0xf>(x);  // row_shr:4
-  x = key_max_dpp<0x118, 0xf>(x);  // row_shr:8  -> lane 15 of each row: row maximum
-  x = key_max_dpp<0x142, 0xa>(x);  // row_bcast:15 into rows 1, 3
-  x = key_max_dpp<0x143, 0xc>(x);  // row_bcast:31 into rows 2, 3 -> lane 63: wave maximum
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, 63);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), 63);
-  return ((uint64_t)hi << 32) | lo;
-}
-
-__device__ inline uint64_t pivot_key(double2 v, int rel) {
-  const double m2 = v.x * v.x + v.y * v.y;
-  const uint64_t hi = (uint64_t)(__double_as_longlong(m2)) >> 32;  // monotone for m2 >= 0
-  return (hi << 32) | (uint64_t)(0xffffffffu - (uint32_t)rel);
-}
-
-// 1/v, zero for v = 0
-__device__ inline double2 crecip(double2 v) {
-  const double d = v.x * v.x + v.y * v.y;
-  const double r = d != 0.0 ? 1.0 / d : 0.0;
-  return make_double2(v.x * r, -v.y * r);
-}
 
 // value of lane S of each group of four lanes (DPP quad permutation)
 __device__ inline double quad_bcast(double v, int S) {
@@ -140,55 +106,111 @@ struct PanelRows {
 };
 
 struct PanelShared {  // per-column exchange, double-buffered over columns
-  uint64_t key[2][kPanelMaxWaves];
+  uint32_t key[2][kPanelMaxWaves];
   double2 row[2][kPanelMaxWaves][kGjeNb];
   double2 ip[2][kPanelMaxWaves];
   int spiv[kGjeNb];       // global row of each pivot
   double2 ipiv[kGjeNb];   // reciprocal of each pivot
 };
 
+// maximum of x over the wavefront, returned in every lane
+__device__ inline uint32_t wave_max_u32(uint32_t x) {
+  x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, true));  // row_shr:1
+  x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, true));  // row_shr:2
+  x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, true));  // row_shr:4
+  x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xf, 0xf, true));  // row_shr:8
+  x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xa, 0xf, true));  // row_bcast:15
+  x = max(x, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xc, 0xf, true));  // row_bcast:31
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
+}
+
+__device__ inline double readlane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// 1/v for the pivot: hardware reciprocal of |v|^2 refined by two Newton
+// steps (zero for v = 0; an exactly singular column is reported anyway)
+__device__ inline double2 pivot_recip(double vx, double vy) {
+  const double d = vx * vx + vy * vy;
+  double r = __builtin_amdgcn_rcp(d);
+  r = __builtin_fma(r, __builtin_fma(-d, r, 1.0), r);
+  r = __builtin_fma(r, __builtin_fma(-d, r, 1.0), r);
+  r = d != 0.0 ? r : 0.0;
+  return make_double2(vx * r, -vy * r);
+}
+
+// Pivot key of a candidate row: the high word of |a|^2 without its ten
+// lowest bits, plus one (zero means no eligible row), over ten bits of
+// complemented row offset.  Keys are unique, the largest is the pivot, and
+// the pivot is within 2^-10 of the largest |a|^2 of the column (ties to the
+// lowest row), which keeps partial pivoting's growth bound.
+constexpr int kKeyRowBits = 10;
+__device__ inline uint32_t pivot_key32(double vx, double vy, int rel) {
+  const double m2 = vx * vx + vy * vy;
+  const uint32_t hi = (uint32_t)((uint64_t)__double_as_longlong(m2) >> 32);
+  return (((hi >> kKeyRowBits) + 1u) << kKeyRowBits) | (uint32_t)((1 << kKeyRowBits) - 1 - rel);
+}
+
 // one column of the panel LU; C is a template parameter so that every
-// register index is static
+// register index is static.  Waves without rows (all past n) only keep the
+// barriers; their keys stay zero.
 template <int NT, int SLOTS, int C>
-__device__ __forceinline__ void panel_column(PanelRows<SLOTS>& st, PanelShared& sh, int nb, int k, int tid) {
+__device__ __forceinline__ void panel_column(PanelRows<SLOTS>& st, PanelShared& sh, int nb, int k, int tid,
+                                             bool active) {
   if (C >= nb) return;
   constexpr int NW = NT / 64;
   const int lane = tid & 63, wave = tid >> 6;
   const int buf = C & 1;
-  uint64_t best = 0;
-  double2 cand = make_double2(0.0, 0.0);
+  if (active) {
+    uint32_t key = 0;
+    double cx = 0.0, cy = 0.0;  // scalar selects keep the rows in registers
+    int csl = 0;
 #pragma unroll
-  for (int sl = 0; sl < SLOTS; ++sl) {
-    const uint64_t key = st.pidx[sl] < 0 ? pivot_key(st.a[sl][C], tid + sl * NT) : 0;
-    if (key > best) {
-      best = key;
-      cand = st.a[sl][C];
+    for (int sl = 0; sl < SLOTS; ++sl) {
+      const double vx = st.a[sl][C].x, vy = st.a[sl][C].y;
+      const uint32_t kk = st.pidx[sl] < 0 ? pivot_key32(vx, vy, tid + sl * NT) : 0u;
+      const bool better = kk > key;
+      key = better ? kk : key;
+      csl = better ? sl : csl;
+      cx = better ? vx : cx;
+      cy = better ? vy : cy;
+    }
+    const double2 cip = pivot_recip(cx, cy);
+    const uint32_t wmax = wave_max_u32(key);
+    const int wrel = (1 << kKeyRowBits) - 1 - (int)(wmax & ((1u << kKeyRowBits) - 1));
+    const int wl = (SLOTS == 1 ? wrel : wrel % NT) & 63;  // lane holding the wave's candidate
+    // cross-lane reads stay in uniform control flow
+    const double2 wip = make_double2(readlane_d(cip.x, wl), readlane_d(cip.y, wl));
+    if (lane == 0) {
+      sh.key[buf][wave] = wmax;
+      sh.ip[buf][wave] = wip;
+    }
+    if (wmax != 0 && key == wmax) {
+      const bool s0 = SLOTS == 1 || csl == 0;
+#pragma unroll
+      for (int j = 0; j < kGjeNb; ++j) {
+        const double rx = s0 ? st.a[0][j].x : st.a[SLOTS - 1][j].x;
+        const double ry = s0 ? st.a[0][j].y : st.a[SLOTS - 1][j].y;
+        sh.row[buf][wave][j] = make_double2(rx, ry);
+      }
     }
   }
-  const double2 cip = crecip(cand);  // overlaps the reduction
-  const uint64_t wbest = wave_key_max(best);
-  if (lane == 0) sh.key[buf][wave] = wbest;
-  if (wbest != 0 && best == wbest) {  // this lane holds the wave's candidate row
-    const int rel = (int)(0xffffffffu - (uint32_t)wbest);
-#pragma unroll
-    for (int sl = 0; sl < SLOTS; ++sl)
-      if (rel == tid + sl * NT)
-#pragma unroll
-        for (int j = 0; j < kGjeNb; ++j) sh.row[buf][wave][j] = st.a[sl][j];
-    sh.ip[buf][wave] = cip;
-  }
   __syncthreads();
-  uint64_t kv[NW];
+  if (!active) return;
+  uint32_t kv[NW];
 #pragma unroll
   for (int w = 0; w < NW; ++w) kv[w] = sh.key[buf][w];
 #pragma unroll
   for (int s = 1; s < NW; s *= 2)
 #pragma unroll
-    for (int w = 0; w + s < NW; w += 2 * s) kv[w] = kv[w + s] > kv[w] ? kv[w + s] : kv[w];
-  const uint64_t kb = kv[0];
-  const int rel = (int)(0xffffffffu - (uint32_t)kb);  // pivot row - k
-  const int wb = (rel % NT) >> 6;                      // the wave that staged it
-  if ((kb >> 32) == 0 && st.singular == 0) st.singular = k + C + 1;
+    for (int w = 0; w + s < NW; w += 2 * s) kv[w] = max(kv[w], kv[w + s]);
+  const uint32_t kb = kv[0];
+  const int rel = (1 << kKeyRowBits) - 1 - (int)(kb & ((1u << kKeyRowBits) - 1));  // pivot row - k
+  const int wb = (SLOTS == 1 ? rel : rel % NT) >> 6;                                  // the wave that staged it
+  if ((kb >> kKeyRowBits) <= 1u && st.singular == 0) st.singular = k + C + 1;
   const double2 ip = sh.ip[buf][wb];
   double2 prow[kGjeNb];
 #pragma unroll
@@ -218,14 +240,15 @@ __device__ __forceinline__ void panel_column(PanelRows<SLOTS>& st, PanelShared& 
 
 template <int NT, int SLOTS, int C>
 struct PanelColumns {
-  static __device__ __forceinline__ void run(PanelRows<SLOTS>& st, PanelShared& sh, int nb, int k, int tid) {
-    panel_column<NT, SLOTS, C>(st, sh, nb, k, tid);
-    PanelColumns<NT, SLOTS, C + 1>::run(st, sh, nb, k, tid);
+  static __device__ __forceinline__ void run(PanelRows<SLOTS>& st, PanelShared& sh, int nb, int k, int tid,
+                                             bool active) {
+    panel_column<NT, SLOTS, C>(st, sh, nb, k, tid, active);
+    PanelColumns<NT, SLOTS, C + 1>::run(st, sh, nb, k, tid, active);
   }
 };
 template <int NT, int SLOTS>
 struct PanelColumns<NT, SLOTS, kGjeNb> {
-  static __device__ __forceinline__ void run(PanelRows<SLOTS>&, PanelShared&, int, int, int) {}
+  static __device__ __forceinline__ void run(PanelRows<SLOTS>&, PanelShared&, int, int, int, bool) {}
 };
 
 template <int NT, int SLOTS>
@@ -241,7 +264,7 @@ __global__ __launch_bounds__(NT) void gje_panel_kernel(const GjeDesc* __restrict
   cplx* W = D.W;
   __shared__ PanelShared sh;
   __shared__ int sdst[2 * kGjeNb], ssrc[2 * kGjeNb], snaff;
-  __shared__ double2 m1[kGjeNb][kGjeNb];
+  __shared__ double2 m1[kGjeNb][kGjeNb + 1];
   __shared__ double2 ys[kGjeNb][kGjeNb];
   __shared__ double2 zs[kGjeNb][kGjeNb];
   __shared__ double2 tile[NW][kGjeNb][kGjeNb + 1];
@@ -262,7 +285,7 @@ __global__ __launch_bounds__(NT) void gje_panel_kernel(const GjeDesc* __restrict
   if (k > 0) {
     // round 1: the previous step's interchanges and M1 (the old values of
     // our rows are in flight above)
-    const int* pivp = D.piv + (size_t)(kp / kGjeNb) * kGjePivStride;
+    const auto pivp = gmem(D.piv + (size_t)(kp / kGjeNb) * kGjePivStride);
     const cplx* M1p = D.M1 + (size_t)(kp / kGjeNb) * kGjeNb * kGjeNb;
     if (tid == 0) snaff = pivp[0];
     if (tid < 2 * kGjeNb) {
@@ -270,6 +293,20 @@ __global__ __launch_bounds__(NT) void gje_panel_kernel(const GjeDesc* __restrict
       ssrc[tid] = pivp[1 + 2 * kGjeNb + tid];
     }
     if (tid < kGjeNb * kGjeNb) m1[tid % kGjeNb][tid / kGjeNb] = gld(M1p + tid);  // column-major M1
+    // the multipliers of the previous step for our row blocks (MFMA A
+    // operand: lane (lq, lr) holds P[r0 + lr][4 kk + lq])
+    // (first slot only: registers)
+    double2 pa[4][4];
+    {
+      constexpr int sl = 0;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const int row = k + sl * NT + wave * 64 + i * 16 + lr;
+          pa[i][kk] = row < n ? gld(W + (size_t)(kp + 4 * kk + lq) * n + row) : make_double2(0.0, 0.0);
+        }
+    }
     __syncthreads();
     // round 2: Y1 = the previous pivot rows after the interchanges, and the
     // rows the interchanges bring into our rows (all from rows kp..k-1)
@@ -316,13 +353,14 @@ __global__ __launch_bounds__(NT) void gje_panel_kernel(const GjeDesc* __restrict
         dvec4 accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
-          const int row = r0 + lr, kq = 4 * kk + lq;
-          const double2 pa = row < n ? gld(W + (size_t)(kp + kq) * n + row) : make_double2(0.0, 0.0);
-          const double2 b = zs[kq][lr];
-          accr = __builtin_amdgcn_mfma_f64_16x16x4f64(pa.x, b.x, accr, 0, 0, 0);
-          accr = __builtin_amdgcn_mfma_f64_16x16x4f64(-pa.y, b.y, accr, 0, 0, 0);
-          acci = __builtin_amdgcn_mfma_f64_16x16x4f64(pa.x, b.y, acci, 0, 0, 0);
-          acci = __builtin_amdgcn_mfma_f64_16x16x4f64(pa.y, b.x, acci, 0, 0, 0);
+          const int row = r0 + lr;
+          const double2 a = sl == 0 ? pa[i][kk]
+                                    : (row < n ? gld(W + (size_t)(kp + 4 * kk + lq) * n + row) : make_double2(0.0, 0.0));
+          const double2 b = zs[4 * kk + lq][lr];
+          accr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, accr, 0, 0, 0);
+          accr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, accr, 0, 0, 0);
+          acci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, acci, 0, 0, 0);
+          acci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, acci, 0, 0, 0);
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) tile[wave][lq + 4 * q][lr] = make_double2(accr[q], acci[q]);
@@ -338,7 +376,9 @@ __global__ __launch_bounds__(NT) void gje_panel_kernel(const GjeDesc* __restrict
         wave_lds_sync();
       }
     }
-    // this step's start values back to W
+    // this step's start values back to W (their loads settled first, so
+    // that the stores issue back to back)
+    __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0)
 #pragma unroll
     for (int sl = 0; sl < SLOTS; ++sl) {
       const int r = k + tid + sl * NT;
@@ -347,8 +387,16 @@ __global__ __launch_bounds__(NT) void gje_panel_kernel(const GjeDesc* __restrict
         for (int j = 0; j < kGjeNb; ++j)
           if (j < nb) gst(W + (size_t)(k + j) * n + r, st.a[sl][j]);
     }
+  } else {
+    // the rows just loaded: wait here, so that the join below does not also
+    // wait for the start-value stores of the k > 0 path
+    __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0)
   }
-  PanelColumns<NT, SLOTS, 0>::run(st, sh, nb, k, tid);
+  // waves whose rows all lie past n sit out the column steps (their keys are zero)
+  const bool active = k + (tid & ~63) < n;
+  if (tid < 2 * kPanelMaxWaves) sh.key[tid / kPanelMaxWaves][tid % kPanelMaxWaves] = 0u;
+  __syncthreads();
+  PanelColumns<NT, SLOTS, 0>::run(st, sh, nb, k, tid, active);
   if (tid == 0 && st.singular != 0) atomicCAS(D.info, 0, st.singular);
   // the factored pivot block: row of pivot c holds L11 (j < c) and U11 (j >= c)
 #pragma unroll
@@ -380,7 +428,7 @@ __global__ __launch_bounds__(NT) void gje_panel_kernel(const GjeDesc* __restrict
     const int nA = __popcll(bA);
     if (isB) below[__popcll(bB & lt)] = p;
     wave_lds_sync();
-    int* piv = D.piv + (size_t)(k / kGjeNb) * kGjePivStride;
+    const auto piv = gmem(D.piv + (size_t)(k / kGjeNb) * kGjePivStride);
     if (isA) {
       const int t = __popcll(bA & lt);
       pdst[t] = k + q;
@@ -529,14 +577,14 @@ __global__ __launch_bounds__(kUpdWaves * 64) void gje_update_kernel(const GjeDes
   const int c0 = k + nb + lo + blockIdx.x * kUpdCols;
   if (c0 >= cend) return;
   const int nc = min(kUpdCols, cend - c0);
-  const int* piv = D.piv + (size_t)(k / kGjeNb) * kGjePivStride;
+  const auto piv = gmem(D.piv + (size_t)(k / kGjeNb) * kGjePivStride);
   const cplx* M1 = D.M1 + (size_t)(k / kGjeNb) * kGjeNb * kGjeNb;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int lr = lane & 15, lq = lane >> 4;
   cplx* W = D.W;
   __shared__ int sdst[2 * kGjeNb], ssrc[2 * kGjeNb], snaff;
   __shared__ short rowmap[kUpdMaxN];  // stage slot of a row an interchange overwrites, else -1
-  __shared__ double2 m1[kGjeNb][kGjeNb];
+  __shared__ double2 m1[kGjeNb][kGjeNb + 1];
   __shared__ double2 stage[2 * kGjeNb][kUpdCols];
   __shared__ double2 y1[kGjeNb][kUpdCols];
   __shared__ double2 zs[kGjeNb][kUpdCols];
@@ -644,7 +692,7 @@ __global__ __launch_bounds__(kUpdWideThreads) void gje_update_wide_kernel(const 
   const int c0 = k + nb + lo + blockIdx.x * kUpdWideCols;
   if (c0 >= cend) return;
   const int nc = min(kUpdWideCols, cend - c0);
-  const int* piv = D.piv + (size_t)(k / kGjeNb) * kGjePivStride;
+  const auto piv = gmem(D.piv + (size_t)(k / kGjeNb) * kGjePivStride);
   const cplx* M1 = D.M1 + (size_t)(k / kGjeNb) * kGjeNb * kGjeNb;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   cplx* W = D.W;
@@ -810,7 +858,7 @@ __global__ __launch_bounds__(kRhsWaves * 64) void gje_rhs_kernel(const GjeDesc* 
   for (int sidx = s0; sidx < nsteps; ++sidx) {
     const int k = sidx * kGjeNb;
     const int nb = min(kGjeNb, n - k);
-    const int* piv = D.piv + (size_t)sidx * kGjePivStride;
+    const auto piv = gmem(D.piv + (size_t)sidx * kGjePivStride);
     const cplx* M1 = D.M1 + (size_t)sidx * kGjeNb * kGjeNb;
     // 0. operands of this step into registers: multipliers of my row blocks
     //    (lane: row r0 + lr, column kk + lq) and M1 (lane: row lr, column kk + lq)

@@ -21,8 +21,8 @@
 
 namespace mlh {
 
-__device__ inline double2 hld(const cplx* p) { return *reinterpret_cast<const double2*>(p); }
-__device__ inline void hst(cplx* p, double2 v) { *reinterpret_cast<double2*>(p) = v; }
+__device__ inline double2 hld(const cplx* p) { return ldc(p); }
+__device__ inline void hst(cplx* p, double2 v) { stc(p, v.x, v.y); }
 
 __device__ inline double hwave_sum(double v) {
 #pragma unroll

@@ -31,9 +31,9 @@ __device__ inline int find_tile(const T* d, int n, int key) {
   return lo;
 }
 
-__device__ inline double2 ld2(const cplx* p) { return *reinterpret_cast<const double2*>(p); }
+__device__ inline double2 ld2(const cplx* p) { return ldc(p); }
 __device__ inline void st2(cplx* p, double re, double im) {
-  *reinterpret_cast<double2*>(p) = make_double2(re, im);
+  stc(p, re, im);
 }
 
 __device__ inline double wave_sum(double v) {

@@ -925,7 +925,7 @@ extern "C" mlh_status mlh_stack_create(mlh_ctx ctx, const mlh_stack_desc* D, mlh
     if (e2 != hipSuccess) fs = fail(MLH_E_DEVICE, std::string("fill: ") + hipGetErrorString(e2));
   }
   if (fs != MLH_OK) {
-    hipFree(s->dmem);
+    (void)hipFree(s->dmem);
     delete s;
     return fs;
   }
@@ -943,13 +943,14 @@ extern "C" mlh_status mlh_stack_refill(mlh_stack s) {
 
 extern "C" mlh_status mlh_stack_destroy(mlh_stack s) {
   if (!s) return MLH_OK;
-  hipSetDevice(s->ctx->device);
-  if (s->dmem) hipFree(s->dmem);
-  if (s->gexec) hipGraphExecDestroy(s->gexec);
-  if (s->cap_stream) hipStreamDestroy(s->cap_stream);
-  if (s->aux_stream) hipStreamDestroy(s->aux_stream);
-  for (hipEvent_t e : s->evpool) hipEventDestroy(e);
-  if (s->wmem) hipFree(s->wmem);
+  // teardown: errors here leave nothing to recover
+  (void)hipSetDevice(s->ctx->device);
+  if (s->dmem) (void)hipFree(s->dmem);
+  if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+  if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+  if (s->aux_stream) (void)hipStreamDestroy(s->aux_stream);
+  for (hipEvent_t e : s->evpool) (void)hipEventDestroy(e);
+  if (s->wmem) (void)hipFree(s->wmem);
   delete s;
   return MLH_OK;
 }
