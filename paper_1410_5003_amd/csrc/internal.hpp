@@ -91,6 +91,8 @@ constexpr int kAsmTile = 2048;  // elements per assembly workgroup (8 per thread
 // batched complex GEMM  C += alpha (A B + A2 B2)  (column-major); the second
 // product (k2 may be 0) lets one descriptor own its output tile, so no two
 // workgroups of a launch ever update the same C entry
+constexpr int kGemmTile = 64;  // output tile of one zgemm workgroup (kGemmTile x kGemmTile)
+
 struct GemmDesc {
   const cplx* A;
   const cplx* B;

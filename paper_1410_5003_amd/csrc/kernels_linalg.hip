@@ -43,66 +43,109 @@ __device__ inline double wave_sum(double v) {
 }
 
 // ---------------------------------------------------------------------------
-// batched complex GEMM: 32 x 32 output tile per workgroup, 4 wavefronts each
-// owning a 16 x 16 sub-tile; k staged through LDS in slabs of 16.
+// batched complex GEMM C = C0 + alpha (A B + A2 B2): one workgroup of four
+// wavefronts per kGemmTile x kGemmTile tile of C, each wavefront a 32 x 32
+// quarter as 2 x 2 blocks of 16 x 16 on the FP64 matrix cores.  K runs in
+// slabs of 16 staged in LDS; the next slab is loaded into registers while
+// the current one is multiplied.  A complex product takes three real ones
+// (T1 = Ar Br, T2 = Ai Bi, T3 = (Ar + Ai)(Br + Bi); re = T1 - T2,
+// im = T3 - T1 - T2), a quarter fewer matrix-core operations than four.
 // ---------------------------------------------------------------------------
-constexpr int kGT = 32;
 constexpr int kGK = 16;
 
-__global__ __launch_bounds__(256) void zgemm_kernel(const GemmDesc* __restrict__ descs, int ndesc, int tile0) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void zgemm_kernel(const GemmDesc* __restrict__ descs, int ndesc, int tile0) {
   const int tile = tile0 + (int)blockIdx.x;
   const GemmDesc& G = descs[find_tile(descs, ndesc, tile)];
   const int lt = tile - G.tile_begin;
-  const int row0 = (lt % G.tiles_m) * kGT, col0 = (lt / G.tiles_m) * kGT;
-  __shared__ double Ar[kGK][kGT + 1], Ai[kGK][kGT + 1];
-  __shared__ double Br[kGK][kGT + 1], Bi[kGK][kGT + 1];
+  const int row0 = (lt % G.tiles_m) * kGemmTile, col0 = (lt / G.tiles_m) * kGemmTile;
+  __shared__ double Ar[kGK][kGemmTile + 1], Ai[kGK][kGemmTile + 1];
+  __shared__ double Br[kGK][kGemmTile + 1], Bi[kGK][kGemmTile + 1];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int wm = (wave & 1) * 16, wn = (wave >> 1) * 16;
-  dvec4 cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+  const int lr = lane & 15, lq = lane >> 4;
+  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
   const int m = G.m, n = G.n, K1 = G.k, K = G.k + G.k2;
-  for (int k0 = 0; k0 < K; k0 += kGK) {
-    for (int e = tid; e < kGT * kGK; e += 256) {
-      const int r = e % kGT, kk = e / kGT;
-      const int gr = row0 + r, gk = k0 + kk;
-      double2 v = make_double2(0.0, 0.0);
-      if (gr < m && gk < K)
-        v = gk < K1 ? ld2(G.A + (size_t)gk * G.lda + gr) : ld2(G.A2 + (size_t)(gk - K1) * G.lda2 + gr);
-      Ar[kk][r] = v.x;
-      Ai[kk][r] = v.y;
+  dvec4 t1[2][2], t2[2][2], t3[2][2];
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      t1[b][c] = dvec4{0, 0, 0, 0};
+      t2[b][c] = dvec4{0, 0, 0, 0};
+      t3[b][c] = dvec4{0, 0, 0, 0};
     }
-    for (int e = tid; e < kGT * kGK; e += 256) {
-      const int kk = e % kGK, c = e / kGK;
-      const int gc = col0 + c, gk = k0 + kk;
-      double2 v = make_double2(0.0, 0.0);
-      if (gc < n && gk < K)
-        v = gk < K1 ? ld2(G.B + (size_t)gc * G.ldb + gk) : ld2(G.B2 + (size_t)gc * G.ldb2 + (gk - K1));
-      Br[kk][c] = v.x;
-      Bi[kk][c] = v.y;
+  // slab staging: thread tid holds A elements (r, kk) = (e % 64, e / 64) and
+  // B elements (kk, c) = (e % 16, e / 16) for e = tid + 256 q
+  double2 pa[4], pb[4];
+  auto load_slab = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      {
+        const int gr = row0 + e % kGemmTile, gk = k0 + e / kGemmTile;
+        pa[q] = make_double2(0.0, 0.0);
+        if (gr < m && gk < K)
+          pa[q] = gk < K1 ? ld2(G.A + (size_t)gk * G.lda + gr) : ld2(G.A2 + (size_t)(gk - K1) * G.lda2 + gr);
+      }
+      {
+        const int gk = k0 + e % kGK, gc = col0 + e / kGK;
+        pb[q] = make_double2(0.0, 0.0);
+        if (gc < n && gk < K)
+          pb[q] = gk < K1 ? ld2(G.B + (size_t)gc * G.ldb + gk) : ld2(G.B2 + (size_t)gc * G.ldb2 + (gk - K1));
+      }
+    }
+  };
+  if (K > 0) load_slab(0);
+  for (int k0 = 0; k0 < K; k0 += kGK) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + 256 * q;
+      Ar[e / kGemmTile][e % kGemmTile] = pa[q].x;
+      Ai[e / kGemmTile][e % kGemmTile] = pa[q].y;
+      Br[e % kGK][e / kGK] = pb[q].x;
+      Bi[e % kGK][e / kGK] = pb[q].y;
     }
     __syncthreads();
+    if (k0 + kGK < K) load_slab(k0 + kGK);
 #pragma unroll
-    for (int kk = 0; kk < kGK; kk += 4) {
-      const int ka = kk + (lane >> 4);
-      const double ar = Ar[ka][wm + (lane & 15)], ai = Ai[ka][wm + (lane & 15)];
-      const double br = Br[ka][wn + (lane & 15)], bi = Bi[ka][wn + (lane & 15)];
-      cr = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, cr, 0, 0, 0);
-      cr = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, bi, cr, 0, 0, 0);
-      ci = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, bi, ci, 0, 0, 0);
-      ci = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, br, ci, 0, 0, 0);
+    for (int ks = 0; ks < kGK; ks += 4) {
+      const int ka = ks + lq;
+      double ar[2], ai[2], as[2], br[2], bi[2], bs[2];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        ar[b] = Ar[ka][wm + 16 * b + lr];
+        ai[b] = Ai[ka][wm + 16 * b + lr];
+        as[b] = ar[b] + ai[b];
+        br[b] = Br[ka][wn + 16 * b + lr];
+        bi[b] = Bi[ka][wn + 16 * b + lr];
+        bs[b] = br[b] + bi[b];
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          t1[b][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[b], br[c], t1[b][c], 0, 0, 0);
+          t2[b][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[b], bi[c], t2[b][c], 0, 0, 0);
+          t3[b][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(as[b], bs[c], t3[b][c], 0, 0, 0);
+        }
     }
     __syncthreads();
   }
-  const int col = col0 + wn + (lane & 15);
-  if (col >= n) return;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int row = row0 + wm + (lane >> 4) + 4 * r;
-    if (row < m) {
-      cplx* p = G.C + (size_t)col * G.ldc + row;
-      const double2 c = G.C0 ? ld2(G.C0 + (size_t)col * G.ldc0 + row) : make_double2(0.0, 0.0);
-      const double xr = cr[r], xi = ci[r];
-      st2(p, c.x + G.alpha.re * xr - G.alpha.im * xi, c.y + G.alpha.re * xi + G.alpha.im * xr);
-    }
+  for (int c = 0; c < 2; ++c) {
+    const int col = col0 + wn + 16 * c + lr;
+    if (col >= n) continue;
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row0 + wm + 16 * b + lq + 4 * r;
+        if (row < m) {
+          cplx* p = G.C + (size_t)col * G.ldc + row;
+          const double2 c0 = G.C0 ? ld2(G.C0 + (size_t)col * G.ldc0 + row) : make_double2(0.0, 0.0);
+          const double xr = t1[b][c][r] - t2[b][c][r], xi = t3[b][c][r] - t1[b][c][r] - t2[b][c][r];
+          st2(p, c0.x + G.alpha.re * xr - G.alpha.im * xi, c0.y + G.alpha.re * xi + G.alpha.im * xr);
+        }
+      }
   }
 }
 

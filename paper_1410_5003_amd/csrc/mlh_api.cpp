@@ -1220,9 +1220,9 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
       G.alpha = cx(-1.0, 0.0);
       G.m = m;
       G.n = nn;
-      G.tiles_m = (m + 31) / 32;
+      G.tiles_m = (m + kGemmTile - 1) / kGemmTile;
       G.tile_begin = tiles;
-      tiles += G.tiles_m * ((nn + 31) / 32);
+      tiles += G.tiles_m * ((nn + kGemmTile - 1) / kGemmTile);
       vec.push_back(G);
     };
     std::vector<GemmDesc> gs;
@@ -1860,9 +1860,9 @@ extern "C" mlh_status mlh_debug_zgemm(mlh_ctx ctx, int32_t m, int32_t n, int32_t
   G.lda = m;
   G.ldb = k;
   G.ldc = m;
-  G.tiles_m = (m + 31) / 32;
+  G.tiles_m = (m + kGemmTile - 1) / kGemmTile;
   G.tile_begin = 0;
-  const int tiles = G.tiles_m * ((n + 31) / 32);
+  const int tiles = G.tiles_m * ((n + kGemmTile - 1) / kGemmTile);
   hipError_t e = hipMemcpy(dA, A, cbytes(na), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(dB, Bm, cbytes(nb), hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(dC, C, cbytes(nc), hipMemcpyHostToDevice);
