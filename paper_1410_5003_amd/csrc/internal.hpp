@@ -193,7 +193,7 @@ __device__ __forceinline__ void stc(cplx* p, double re, double im) {
 constexpr int kGjeNb = 16;  // panel width
 constexpr int kGjeMaxN = 1024; // largest block order: the panel kernel holds 2 rows per thread (N_i <= 512)
 
-constexpr int kGjePivStride = 68;  // ints per step: count, 2 NB destinations, 2 NB sources
+constexpr int kGjePivStride = 84;  // ints per step: count, 2 NB destinations, 2 NB sources, NB pivot rows
 constexpr int kRhsMaxN16 = 608;    // largest order whose 16-column right-hand-side tile fits in LDS
 
 // one matrix W = [D | right-hand sides] (n x ncol, ld n) reduced to [. | D^{-1} rhs]
@@ -223,6 +223,7 @@ void launch_gje_panel(const GjeDesc* d, int nbatch, int k, int max_n, hipStream_
 // columns [k + NB + lo, k + NB + hi) of the diagonal blocks (hi may exceed n)
 void launch_gje_update(const GjeDesc* d, int nbatch, int k, int max_n, int lo, int hi, hipStream_t st);
 // right-hand-side replay of steps [s0, s1); max_blocks > 0 caps the grid
+void launch_gje_premul(const GjeDesc* d, int nbatch, int max_n, hipStream_t st);
 void launch_gje_rhs(const GjeDesc* d, int nbatch, int max_rhs, int max_n, int s0, int s1, int max_blocks,
                     hipStream_t st);
 void launch_gemv_step(const GemvDesc* d, int nbatch, int max_n, int max_r, hipStream_t st);

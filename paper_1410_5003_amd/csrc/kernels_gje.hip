@@ -415,7 +415,8 @@ __global__ __launch_bounds__(NT) void gje_panel_kernel(const GjeDesc* __restrict
     // rows: pivot q (row spiv[q], never moved in registers) goes to k + q;
     // rows of positions k..k+nb-1 that were not chosen fill, in order, the
     // rows that the pivots from below the block vacated, in pivot order.
-    // piv[0] = count, piv[1..] destinations, piv[1+2NB..] sources.
+    // piv[0] = count, piv[1..] destinations, piv[1+2NB..] sources,
+    // piv[1+4NB+q] the row of pivot q.
     const int q = lane;
     const int p = q < nb ? sh.spiv[q] : -1;
     bool chosen = false;
@@ -445,6 +446,7 @@ __global__ __launch_bounds__(NT) void gje_panel_kernel(const GjeDesc* __restrict
     }
     const int na = nA + __popcll(bU);
     if (lane == 0) piv[0] = na;
+    if (q < nb) piv[1 + 4 * kGjeNb + q] = p;  // the row holding pivot q before the interchanges
     wave_lds_sync();
     // apply it to the panel columns of W (this step's start values): every
     // source is read before any destination is written
@@ -833,6 +835,50 @@ constexpr int kRhsWaves = 8;
 // Steps [s0, s1) are replayed (clipped to each matrix's step count); the
 // grid may be smaller than the number of tiles, workgroups then loop over
 // tiles, so that a launch can run beside the panel chain on part of the chip.
+// After the last step of a level: P' = P M1 for every step, in place in the
+// panel columns of W (read by nothing else afterwards).  A step's update of
+// the other rows is then Y -= P' Y(pivot rows), with no Z to form for them.
+__global__ __launch_bounds__(256) void gje_premul_kernel(const GjeDesc* __restrict__ descs) {
+  const GjeDesc& D = descs[blockIdx.z];
+  const int n = D.n, sidx = blockIdx.y, k = sidx * kGjeNb;
+  if (k >= n) return;
+  const int nb = min(kGjeNb, n - k);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int lr = lane & 15, lq = lane >> 4;
+  const int r0 = blockIdx.x * 64 + wave * 16;
+  if (r0 >= n) return;  // no barriers in this kernel
+  const cplx* M1 = D.M1 + (size_t)sidx * kGjeNb * kGjeNb;
+  cplx* W = D.W;
+  double2 a[4], b[4];
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const int row = r0 + lr, kq = 4 * kk + lq;
+    a[kk] = (row < n && kq < nb) ? gld(W + (size_t)(k + kq) * n + row) : make_double2(0.0, 0.0);
+    b[kk] = gld(M1 + (size_t)lr * kGjeNb + kq);  // M1[kq][lr], column-major
+  }
+  dvec4 t1 = {0, 0, 0, 0}, t2 = {0, 0, 0, 0}, t3 = {0, 0, 0, 0};
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    t1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk].x, b[kk].x, t1, 0, 0, 0);
+    t2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk].y, b[kk].y, t2, 0, 0, 0);
+    t3 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk].x + a[kk].y, b[kk].x + b[kk].y, t3, 0, 0, 0);
+  }
+  if (lr < nb)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int row = r0 + lq + 4 * q;
+      if (row < n) gst(W + (size_t)(k + lr) * n + row, make_double2(t1[q] - t2[q], t3[q] - t1[q] - t2[q]));
+    }
+}
+
+// Right-hand-side replay: one workgroup per TC columns keeps its tile Y in
+// LDS and applies every step to it.  Per step: (1) each wave reads the pivot
+// rows (from the rows that held the pivots, so before the interchanges) as
+// its MFMA B operand, and the interchanges that move rows below the pivot
+// block read their sources; (2) those rows are written; (3) the pivot block
+// receives Z = M1 Y(pivot rows) and every other row Y -= P' Y(pivot rows).
+// The multipliers of a wave's row blocks for the next step load while the
+// current step runs.  Complex products take three real MFMA products.
 template <int TC, int MAXN>
 __global__ __launch_bounds__(kRhsWaves * 64) void gje_rhs_kernel(const GjeDesc* __restrict__ descs, int nbatch,
                                                                  int tiles_per, int s0, int s1) {
@@ -843,112 +889,122 @@ __global__ __launch_bounds__(kRhsWaves * 64) void gje_rhs_kernel(const GjeDesc* 
   const bool cl = lr < TC;
   __shared__ double2 Y[MAXN][TC];
   for (int tile = blockIdx.x; tile < nbatch * tiles_per; tile += gridDim.x) {
-  const GjeDesc& D = descs[tile / tiles_per];
-  const int n = D.n;
-  const int c0 = n + (tile % tiles_per) * TC;
-  if (c0 >= D.ncol) continue;
-  const int nc = min(TC, D.ncol - c0);
-  cplx* W = D.W;
-  for (int e = tid; e < n * TC; e += kRhsWaves * 64) {
-    const int r = e % n, c = e / n;
-    Y[r][c] = c < nc ? gld(W + (size_t)(c0 + c) * n + r) : make_double2(0.0, 0.0);
-  }
-  __syncthreads();
-  const int nsteps = min(s1, (n + kGjeNb - 1) / kGjeNb);
-  for (int sidx = s0; sidx < nsteps; ++sidx) {
-    const int k = sidx * kGjeNb;
-    const int nb = min(kGjeNb, n - k);
-    const auto piv = gmem(D.piv + (size_t)sidx * kGjePivStride);
-    const cplx* M1 = D.M1 + (size_t)sidx * kGjeNb * kGjeNb;
-    // 0. operands of this step into registers: multipliers of my row blocks
-    //    (lane: row r0 + lr, column kk + lq) and M1 (lane: row lr, column kk + lq)
-    double2 pa[PF][4], ma[4];
-#pragma unroll
-    for (int j = 0; j < PF; ++j) {
+    const GjeDesc& D = descs[tile / tiles_per];
+    const int n = D.n;
+    const int c0 = n + (tile % tiles_per) * TC;
+    if (c0 >= D.ncol) continue;
+    const int nc = min(TC, D.ncol - c0);
+    cplx* W = D.W;
+    for (int e = tid; e < n * TC; e += kRhsWaves * 64) {
+      const int r = e % n, c = e / n;
+      Y[r][c] = c < nc ? gld(W + (size_t)(c0 + c) * n + r) : make_double2(0.0, 0.0);
+    }
+    const int nsteps = min(s1, (n + kGjeNb - 1) / kGjeNb);
+    // multipliers P' of a step for this wave's first PF row blocks
+    // (lane: row r0 + lr, column 4 kk + lq)
+    double2 pa[PF][4];
+    auto load_p = [&](int sidx, int j, double2* dst) {
+      const int k = sidx * kGjeNb, nb = min(kGjeNb, n - k);
       const int row = (wave + j * kRhsWaves) * 16 + lr;
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
         const int kq = 4 * kk + lq;
-        pa[j][kk] = (row < n && kq < nb) ? gld(W + (size_t)(k + kq) * n + row) : make_double2(0.0, 0.0);
+        dst[kk] = (row < n && kq < nb) ? gld(W + (size_t)(k + kq) * n + row) : make_double2(0.0, 0.0);
       }
-    }
+    };
+    if (s0 < nsteps)
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) ma[kk] = gld(M1 + (size_t)(4 * kk + lq) * kGjeNb + lr);
-    // 1. this step's row interchanges (at most 2 NB pairs x TC columns)
-    const int naff = piv[0];
-    const int e0 = tid;
-    const int cA = e0 % TC;
-    const int dA = e0 < naff * TC ? piv[1 + e0 / TC] : -1;
-    double2 vA = make_double2(0.0, 0.0);
-    if (dA >= 0) vA = Y[piv[1 + 2 * kGjeNb + e0 / TC]][cA];
+      for (int j = 0; j < PF; ++j) load_p(s0, j, pa[j]);
     __syncthreads();
-    if (dA >= 0) Y[dA][cA] = vA;
-    __syncthreads();
-    // 2. Z = M1 Y(pivot rows), rows of Y beyond nb read as zero
-    dvec4 zr = {0, 0, 0, 0}, zi = {0, 0, 0, 0};
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      const int q = 4 * kk + lq;
-      const double2 b = (q < nb && cl) ? Y[k + q][lr] : make_double2(0.0, 0.0);
-      const double2 a = ma[kk];
-      zr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, zr, 0, 0, 0);
-      zr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, zr, 0, 0, 0);
-      zi = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, zi, 0, 0, 0);
-      zi = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, zi, 0, 0, 0);
-    }
-    __syncthreads();  // every wave has read the pivot rows
-    // 3. Y(other rows) -= P Z; the pivot block (k is a multiple of 16, and
-    //    nb < 16 only in the last block) receives Z.  Register q of Z holds
-    //    row 4 q + lq, column lr: the B operand of step kk = q.
-#pragma unroll
-    for (int j = 0; j < NBLK; ++j) {
-      const int r0 = (wave + j * kRhsWaves) * 16;
-      if (r0 >= n) break;
-      if (r0 == k) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int rr = lq + 4 * q;
-          if (cl && r0 + rr < n) Y[r0 + rr][lr] = make_double2(zr[q], zi[q]);
-        }
-        continue;
-      }
-      double2 pb[4];
+    for (int sidx = s0; sidx < nsteps; ++sidx) {
+      const int k = sidx * kGjeNb;
+      const int nb = min(kGjeNb, n - k);
+      const auto piv = gmem(D.piv + (size_t)sidx * kGjePivStride);
+      // 1. the pivot rows as the B operand (lane: row 4 kk + lq, column lr)
+      double2 yb[4];
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
-        const int row = r0 + lr, kq = 4 * kk + lq;
-        if (j < PF)
-          pb[kk] = pa[j < PF ? j : 0][kk];
-        else
-          pb[kk] = (row < n && kq < nb) ? gld(W + (size_t)(k + kq) * n + row) : make_double2(0.0, 0.0);
+        const int q = 4 * kk + lq;
+        yb[kk] = (q < nb && cl) ? Y[piv[1 + 4 * kGjeNb + q]][lr] : make_double2(0.0, 0.0);
       }
-      dvec4 accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
+      const bool owner = ((k / 16) % kRhsWaves) == wave;  // this wave holds the pivot block
+      double2 ma[4];
+      if (owner) {
+        const cplx* M1 = D.M1 + (size_t)sidx * kGjeNb * kGjeNb;
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const double2 a = pb[kk];
-        const double br = zr[kk], bi = zi[kk];
-        accr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, br, accr, 0, 0, 0);
-        accr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, bi, accr, 0, 0, 0);
-        acci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, bi, acci, 0, 0, 0);
-        acci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, br, acci, 0, 0, 0);
+        for (int kk = 0; kk < 4; ++kk) ma[kk] = gld(M1 + (size_t)(4 * kk + lq) * kGjeNb + lr);  // M1[lr][4 kk + lq]
       }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int row = r0 + lq + 4 * q;
-        if (cl && row < n) {
-          double2 y = Y[row][lr];
-          y.x -= accr[q];
-          y.y -= acci[q];
-          Y[row][lr] = y;
+      //    interchanged rows that land below the pivot block
+      const int naff = piv[0];
+      int dA = -1;
+      double2 vA = make_double2(0.0, 0.0);
+      if (tid < naff * TC) {
+        const int t = tid / TC, c = tid % TC;
+        const int d = piv[1 + t];
+        if (d >= k + nb) {
+          dA = d;
+          vA = Y[piv[1 + 2 * kGjeNb + t]][c];
         }
       }
+      __syncthreads();
+      // 2.
+      if (dA >= 0) Y[dA][tid % TC] = vA;
+      __syncthreads();
+      // 3.
+      double ys[4];
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) ys[kk] = yb[kk].x + yb[kk].y;
+#pragma unroll
+      for (int j = 0; j < NBLK; ++j) {
+        const int r0 = (wave + j * kRhsWaves) * 16;
+        if (r0 >= n) break;
+        dvec4 t1 = {0, 0, 0, 0}, t2 = {0, 0, 0, 0}, t3 = {0, 0, 0, 0};
+        if (r0 == k) {  // Z = M1 Y(pivot rows)
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+            t1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ma[kk].x, yb[kk].x, t1, 0, 0, 0);
+            t2 = __builtin_amdgcn_mfma_f64_16x16x4f64(ma[kk].y, yb[kk].y, t2, 0, 0, 0);
+            t3 = __builtin_amdgcn_mfma_f64_16x16x4f64(ma[kk].x + ma[kk].y, ys[kk], t3, 0, 0, 0);
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int row = r0 + lq + 4 * q;
+            if (cl && row < n) Y[row][lr] = make_double2(t1[q] - t2[q], t3[q] - t1[q] - t2[q]);
+          }
+        } else {
+          double2 pb[4];
+          if (j < PF) {
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) pb[kk] = pa[j < PF ? j : 0][kk];
+          } else {
+            load_p(sidx, j, pb);
+          }
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+            t1 = __builtin_amdgcn_mfma_f64_16x16x4f64(pb[kk].x, yb[kk].x, t1, 0, 0, 0);
+            t2 = __builtin_amdgcn_mfma_f64_16x16x4f64(pb[kk].y, yb[kk].y, t2, 0, 0, 0);
+            t3 = __builtin_amdgcn_mfma_f64_16x16x4f64(pb[kk].x + pb[kk].y, ys[kk], t3, 0, 0, 0);
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int row = r0 + lq + 4 * q;
+            if (cl && row < n) {
+              double2 y = Y[row][lr];
+              y.x -= t1[q] - t2[q];
+              y.y -= t3[q] - t1[q] - t2[q];
+              Y[row][lr] = y;
+            }
+          }
+        }
+        if (j < PF && sidx + 1 < nsteps) load_p(sidx + 1, j, pa[j < PF ? j : 0]);
+      }
+      __syncthreads();
     }
-    __syncthreads();
-  }
-  for (int e = tid; e < n * TC; e += kRhsWaves * 64) {
-    const int r = e % n, c = e / n;
-    if (c < nc) gst(W + (size_t)(c0 + c) * n + r, Y[r][c]);
-  }
-  __syncthreads();  // before the next tile refills the LDS tile
+    for (int e = tid; e < n * TC; e += kRhsWaves * 64) {
+      const int r = e % n, c = e / n;
+      if (c < nc) gst(W + (size_t)(c0 + c) * n + r, Y[r][c]);
+    }
+    __syncthreads();  // before the next tile refills the LDS tile
   }
 }
 
@@ -972,6 +1028,11 @@ void launch_gje_update(const GjeDesc* d, int nbatch, int k, int max_n, int lo, i
       hipLaunchKernelGGL(gje_update_wide_kernel, dim3(tiles, nbatch), dim3(kUpdWideThreads), 0, st, d, k, lo, hi);
     }
   }
+}
+void launch_gje_premul(const GjeDesc* d, int nbatch, int max_n, hipStream_t st) {
+  if (nbatch > 0 && max_n > 0)
+    hipLaunchKernelGGL(gje_premul_kernel, dim3((max_n + 63) / 64, (max_n + kGjeNb - 1) / kGjeNb, nbatch), dim3(256),
+                       0, st, d);
 }
 void launch_gje_rhs(const GjeDesc* d, int nbatch, int max_rhs, int max_n, int s0, int s1, int max_blocks,
                     hipStream_t st) {

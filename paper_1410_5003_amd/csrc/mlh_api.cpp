@@ -1612,6 +1612,7 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
               prof->n_gje_update++;
             }
             tb(&prof->gje_rhs_ms);
+            launch_gje_premul(dg, ng, lv.maxn, ls);
             launch_gje_rhs(dg, lv.nsmall, lv.rhs_small, kRhsMaxN16, 0, nsteps, 0, ls);
             launch_gje_rhs(dg + lv.nsmall, ng - lv.nsmall, lv.rhs_large, lv.maxn, 0, nsteps, 0, ls);
             te();
@@ -1631,6 +1632,7 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
               rest1 = er;
             }
             if (rest1) HIP_TRY(hipStreamWaitEvent(ls, rest1, 0));
+            launch_gje_premul(dg, ng, lv.maxn, ls);
             launch_gje_rhs(dg, lv.nsmall, lv.rhs_small, kRhsMaxN16, 0, nsteps, 0, ls);
             launch_gje_rhs(dg + lv.nsmall, ng - lv.nsmall, lv.rhs_large, lv.maxn, 0, nsteps, 0, ls);
           }
