@@ -222,6 +222,10 @@ void gje_init();
 void launch_gje_panel(const GjeDesc* d, int nbatch, int k, int max_n, hipStream_t st);
 // columns [k + NB + lo, k + NB + hi) of the diagonal blocks (hi may exceed n)
 void launch_gje_update(const GjeDesc* d, int nbatch, int k, int max_n, int lo, int hi, hipStream_t st);
+// panel k and the update of step k - 16 in one launch (orders up to the
+// limit gje_step_fits checks)
+bool gje_step_fits(int max_n);
+void launch_gje_step(const GjeDesc* d, int nbatch, int k, int max_n, hipStream_t st);
 // right-hand-side replay of steps [s0, s1); max_blocks > 0 caps the grid
 void launch_gje_premul(const GjeDesc* d, int nbatch, int max_n, hipStream_t st);
 void launch_gje_rhs(const GjeDesc* d, int nbatch, int max_rhs, int max_n, int s0, int s1, int max_blocks,

@@ -62,7 +62,7 @@ __device__ inline double2 cinv2(double2 a) {
 //     with ballots and applies them to the panel columns of W; wave 1 forms
 //     M1 = (L11 U11)^-1; the other waves apply the previous step to the rows
 //     above k (Z on its pivot rows, V - P Z above them).
-constexpr int kPanelMaxWaves = 10;
+constexpr int kPanelMaxWaves = 12;
 
 
 // value of lane S of each group of four lanes (DPP quad permutation)
@@ -252,10 +252,10 @@ struct PanelColumns<NT, SLOTS, kGjeNb> {
 };
 
 template <int NT, int SLOTS>
-__global__ __launch_bounds__(NT) void gje_panel_kernel(const GjeDesc* __restrict__ descs, int k) {
+__device__ __forceinline__ void panel_body(const GjeDesc* __restrict__ descs, int k, int b) {
   static_assert(NT % 64 == 0 && NT / 64 <= kPanelMaxWaves && NT >= 256, "panel workgroup shape");
   constexpr int NW = NT / 64;
-  const GjeDesc& D = descs[blockIdx.x];
+  const GjeDesc& D = descs[b];
   const int n = D.n;
   if (k >= n) return;
   const int nb = min(kGjeNb, n - k);
@@ -550,6 +550,11 @@ __global__ __launch_bounds__(NT) void gje_panel_kernel(const GjeDesc* __restrict
   }
 }
 
+template <int NT, int SLOTS>
+__global__ __launch_bounds__(NT) void gje_panel_kernel(const GjeDesc* __restrict__ descs, int k) {
+  panel_body<NT, SLOTS>(descs, k, blockIdx.x);
+}
+
 // Update kernel: one workgroup of 12 waves per 16 columns of the diagonal
 // block, columns [k + nb + lo, min(n, k + nb + hi)), every row (orders up to
 // kUpdMaxN); the right-hand-side columns are left to gje_rhs_kernel, after
@@ -569,14 +574,14 @@ constexpr int kUpdWideThreads = 1024;
 constexpr int kUpdWideWaves = kUpdWideThreads / 64;
 constexpr int kUpdWideCols = 32;
 
-__global__ __launch_bounds__(kUpdWaves * 64) void gje_update_kernel(const GjeDesc* __restrict__ descs, int k, int lo,
-                                                                    int hi) {
-  const GjeDesc& D = descs[blockIdx.y];
+__device__ __forceinline__ void update_body(const GjeDesc* __restrict__ descs, int k, int lo, int hi, int tx,
+                                            int b) {
+  const GjeDesc& D = descs[b];
   const int n = D.n;
   if (k >= n) return;
   const int nb = min(kGjeNb, n - k);
   const int cend = min(n, k + nb + hi);
-  const int c0 = k + nb + lo + blockIdx.x * kUpdCols;
+  const int c0 = k + nb + lo + tx * kUpdCols;
   if (c0 >= cend) return;
   const int nc = min(kUpdCols, cend - c0);
   const auto piv = gmem(D.piv + (size_t)(k / kGjeNb) * kGjePivStride);
@@ -679,6 +684,27 @@ __global__ __launch_bounds__(kUpdWaves * 64) void gje_update_kernel(const GjeDes
         gst(W + (size_t)(c0 + lr) * n + row, v);
       }
     }
+  }
+}
+
+__global__ __launch_bounds__(kUpdWaves * 64) void gje_update_kernel(const GjeDesc* __restrict__ descs, int k, int lo,
+                                                                    int hi) {
+  update_body(descs, k, lo, hi, blockIdx.x, blockIdx.y);
+}
+
+// One launch per elimination step when every order is at most kUpdMaxN:
+// workgroups [0, nbatch) factor panel k, the others apply step k - 16 to
+// the columns from k + 16 on, one per (16 columns, matrix).  The two parts
+// touch disjoint columns and depend only on earlier launches, so a level
+// needs neither a second stream nor events, and the panel workgroups, which
+// dispatch first, find their compute units free.
+__global__ __launch_bounds__(kUpdWaves * 64) void gje_step_kernel(const GjeDesc* __restrict__ descs, int nbatch,
+                                                                  int k, int utiles) {
+  if ((int)blockIdx.x < nbatch) {
+    panel_body<kUpdWaves * 64, 1>(descs, k, blockIdx.x);
+  } else {
+    const int u = blockIdx.x - nbatch;
+    update_body(descs, k - kGjeNb, kGjeNb, 1 << 30, u % utiles, u / utiles);
   }
 }
 
@@ -1012,10 +1038,19 @@ void gje_init() {}
 
 void launch_gje_panel(const GjeDesc* d, int nbatch, int k, int max_n, hipStream_t st) {
   if (nbatch <= 0 || max_n <= k) return;
-  if (max_n - k <= 640)
-    hipLaunchKernelGGL((gje_panel_kernel<640, 1>), dim3(nbatch), dim3(640), 0, st, d, k);
+  if (max_n - k <= 768)
+    hipLaunchKernelGGL((gje_panel_kernel<768, 1>), dim3(nbatch), dim3(768), 0, st, d, k);
   else
     hipLaunchKernelGGL((gje_panel_kernel<512, 2>), dim3(nbatch), dim3(512), 0, st, d, k);
+}
+bool gje_step_fits(int max_n) { return max_n <= kUpdMaxN; }
+void launch_gje_step(const GjeDesc* d, int nbatch, int k, int max_n, hipStream_t st) {
+  if (nbatch <= 0 || max_n <= k) return;
+  // update of step k - 16: columns [k + 16, max_n)
+  const int width = k > 0 ? max_n - k - kGjeNb : 0;
+  const int utiles = width > 0 ? (width - 1) / kUpdCols + 1 : 0;
+  hipLaunchKernelGGL(gje_step_kernel, dim3(nbatch * (1 + utiles)), dim3(kUpdWaves * 64), 0, st, d, nbatch, k,
+                     utiles > 0 ? utiles : 1);
 }
 void launch_gje_update(const GjeDesc* d, int nbatch, int k, int max_n, int lo, int hi, hipStream_t st) {
   const int width = std::min(max_n - k - kGjeNb, hi) - lo;

@@ -1616,6 +1616,12 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
             launch_gje_rhs(dg, lv.nsmall, lv.rhs_small, kRhsMaxN16, 0, nsteps, 0, ls);
             launch_gje_rhs(dg + lv.nsmall, ng - lv.nsmall, lv.rhs_large, lv.maxn, 0, nsteps, 0, ls);
             te();
+          } else if (gje_step_fits(lv.maxn)) {
+            // one launch per step: panel s with the update of step s - 1
+            for (int st_i = 0; st_i < nsteps; ++st_i) launch_gje_step(dg, ng, st_i * kGjeNb, lv.maxn, ls);
+            launch_gje_premul(dg, ng, lv.maxn, ls);
+            launch_gje_rhs(dg, lv.nsmall, lv.rhs_small, kRhsMaxN16, 0, nsteps, 0, ls);
+            launch_gje_rhs(dg + lv.nsmall, ng - lv.nsmall, lv.rhs_large, lv.maxn, 0, nsteps, 0, ls);
           } else {
             hipEvent_t rest1 = nullptr, rest2 = nullptr;  // updates of steps s - 1, s - 2
             for (int st_i = 0; st_i < nsteps; ++st_i) {
