@@ -243,6 +243,7 @@ namespace mlh {
 constexpr int kHqNb = 16;
 constexpr int kHqCols = 32;
 constexpr int kHqMaxRows = 512;  // M  (LDS holds an M x 16 panel)
+constexpr int kHqRhsSmallRows = 384;  // layers up to this M take the lighter right-hand-side kernel
 constexpr int kHqMaxC = 256;     // c  (proxy plus Bragg unknowns of one layer)
 
 struct HqDesc {
@@ -255,6 +256,6 @@ struct HqDesc {
 void launch_hq_prep(const HqDesc* d, int n, hipStream_t st);
 void launch_hq_panel(const HqDesc* d, int n, int k, hipStream_t st);
 void launch_hq_update(const HqDesc* d, int n, int k, int max_cols, hipStream_t st);
-void launch_hq_rhs(const HqDesc* d, int n, int max_ncol, hipStream_t st);
+void launch_hq_rhs(const HqDesc* d, int n, int max_ncol, int max_c, int max_rows, hipStream_t st);
 
 }  // namespace mlh

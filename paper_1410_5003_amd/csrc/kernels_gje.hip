@@ -188,10 +188,10 @@ __device__ __forceinline__ void panel_column(PanelRows<SLOTS>& st, PanelShared& 
       sh.key[buf][wave] = wmax;
       sh.ip[buf][wave] = wip;
     }
-    if (wmax != 0 && key == wmax) {
+    if (wmax != 0 && key == wmax) {  // the later columns of the candidate row
       const bool s0 = SLOTS == 1 || csl == 0;
 #pragma unroll
-      for (int j = 0; j < kGjeNb; ++j) {
+      for (int j = C + 1; j < kGjeNb; ++j) {
         const double rx = s0 ? st.a[0][j].x : st.a[SLOTS - 1][j].x;
         const double ry = s0 ? st.a[0][j].y : st.a[SLOTS - 1][j].y;
         sh.row[buf][wave][j] = make_double2(rx, ry);

@@ -17,6 +17,8 @@
 //                      diagonal block, products on the FP64 matrix cores
 //                      elsewhere).  The right-hand sides cross HBM once
 //                      instead of once per panel.
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace mlh {
@@ -322,8 +324,38 @@ __device__ inline double2 hq_v(const cplx* A, int M, int k, int nb, int r, int i
 }
 
 constexpr int kHqRhsCols = 16;
-constexpr int kHqRhsWaves = 4;
+constexpr int kHqRhsWaves = 8;
+static_assert(kHqRhsSmallRows == kHqRhsWaves * 3 * 16 && kHqMaxRows <= kHqRhsWaves * 4 * 16, "row blocks per wave");
 
+// complex 16 x 16 x 4 step of D += op(A) B with three real MFMA products
+// (T1 = Ar Br, T2 = Ai Bi, T3 = (Ar + Ai)(Br + Bi); D = (T1 - T2, T3 - T1 - T2)):
+// callers pass Ai = -Im(A) for conj(A)
+struct Cacc {
+  hvec4 t1, t2, t3;
+};
+__device__ inline void cacc_zero(Cacc& c) {
+  c.t1 = hvec4{0, 0, 0, 0};
+  c.t2 = hvec4{0, 0, 0, 0};
+  c.t3 = hvec4{0, 0, 0, 0};
+}
+__device__ inline void cacc_step(Cacc& c, double ar, double ai, double br, double bi) {
+  c.t1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, c.t1, 0, 0, 0);
+  c.t2 = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bi, c.t2, 0, 0, 0);
+  c.t3 = __builtin_amdgcn_mfma_f64_16x16x4f64(ar + ai, br + bi, c.t3, 0, 0, 0);
+}
+
+// One workgroup of eight waves per 16 right-hand-side columns of one layer.
+// The M x 16 tile Y lives in registers: wave w holds row blocks w + 8 j, lane
+// (lq, lr) rows 16 b + lq + 4 q of column lr in register q, which is also
+// the B-operand layout of the matrix cores (k-step q), so every product
+// below reads Y, w and u where they already are.  Per panel of reflectors V
+// (one round of loads, both operand layouts): w = V^H Y, partial sums of the
+// waves reduced through LDS (double-buffered, one barrier per panel);
+// u = T^H w; Y -= V u.  Then R X = Y(0:c) by 16-row blocks from the bottom
+// in LDS: substitution inside each diagonal block (R's diagonal spans the
+// Tikhonov scale, so no explicit block inverse), the rows above updated on
+// the matrix cores.
+template <int kHqRhsRbw>  // row blocks per wave: 3 up to kHqRhsSmallRows rows, 4 up to kHqMaxRows
 __global__ __launch_bounds__(kHqRhsWaves * 64) void hq_rhs_kernel(const HqDesc* __restrict__ descs) {
   const HqDesc& D = descs[blockIdx.y];
   const int c = D.c, M = D.m + c;
@@ -334,100 +366,113 @@ __global__ __launch_bounds__(kHqRhsWaves * 64) void hq_rhs_kernel(const HqDesc* 
   const int lr = lane & 15, lq = lane >> 4;
   const cplx* A = D.A;
   cplx* B = D.A + (size_t)c * M;  // right-hand sides start after the c columns of S
-  __shared__ double2 Y[kHqMaxRows][kHqRhsCols];
-  __shared__ double red[kHqRhsWaves][2][4][64];
-  for (int e = tid; e < M * kHqRhsCols; e += kHqRhsWaves * 64) {
-    const int r = e % M, j = e / M;
-    Y[r][j] = j < nc ? hld(B + (size_t)(col0 + j) * M + r) : make_double2(0.0, 0.0);
-  }
-  __syncthreads();
+  extern __shared__ double pool[];  // 2 x waves x 2 x 4 x 64 partial sums, then the c x 16 tile
+  hvec4 yr[kHqRhsRbw], yi[kHqRhsRbw];
+#pragma unroll
+  for (int j = 0; j < kHqRhsRbw; ++j)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = (wave + kHqRhsWaves * j) * 16 + lq + 4 * q;
+      const double2 v = (r < M && lr < nc) ? hld(B + (size_t)(col0 + lr) * M + r) : make_double2(0.0, 0.0);
+      yr[j][q] = v.x;
+      yi[j][q] = v.y;
+    }
   const int npan = (c + kHqNb - 1) / kHqNb;
   for (int p = 0; p < npan; ++p) {
     const int k = p * kHqNb;
     const int nb = min(kHqNb, c - k);
-    const cplx* Tp = D.T + (size_t)p * kHqNb * kHqNb;
-    // 1. partial w = V^H Y over this wave's 4-row steps of rows k..M-1
-    hvec4 wr = {0, 0, 0, 0}, wi = {0, 0, 0, 0};
-    // four 4-row steps per batch, all loads issued before the products
-    for (int r0 = k + 4 * wave; r0 < M; r0 += 16 * kHqRhsWaves) {
-      double2 v[4], y[4];
+    // V operands of this wave's row blocks: vh for V^H (lane: reflector lr,
+    // row 4 kk + lq) now, vv for V (lane: row lr, reflector 4 kk + lq) after
+    // the first products, its loads covered by the reduction
+    double2 vh[kHqRhsRbw][4], vv[kHqRhsRbw][4];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int r = r0 + 4 * kHqRhsWaves * b + lq;
-        v[b] = r < M ? hq_v(A, M, k, nb, r, lr) : make_double2(0.0, 0.0);  // A[i=lr][k=r]
-        y[b] = r < M ? Y[r][lr] : make_double2(0.0, 0.0);                  // B[k=r][col=lr]
-      }
+    for (int j = 0; j < kHqRhsRbw; ++j) {
+      const int r0 = (wave + kHqRhsWaves * j) * 16;
+      const bool live = r0 + 15 >= k && r0 < M;
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {  // w = conj(V)^T Y
-        wr = __builtin_amdgcn_mfma_f64_16x16x4f64(v[b].x, y[b].x, wr, 0, 0, 0);
-        wr = __builtin_amdgcn_mfma_f64_16x16x4f64(v[b].y, y[b].y, wr, 0, 0, 0);
-        wi = __builtin_amdgcn_mfma_f64_16x16x4f64(v[b].x, y[b].y, wi, 0, 0, 0);
-        wi = __builtin_amdgcn_mfma_f64_16x16x4f64(-v[b].y, y[b].x, wi, 0, 0, 0);
-      }
+      for (int kk = 0; kk < 4; ++kk)
+        vh[j][kk] = live && r0 + 4 * kk + lq < M ? hq_v(A, M, k, nb, r0 + 4 * kk + lq, lr) : make_double2(0.0, 0.0);
     }
+    // 1. partial w = V^H Y over this wave's rows
+    Cacc w;
+    cacc_zero(w);
+#pragma unroll
+    for (int j = 0; j < kHqRhsRbw; ++j) {
+      const int r0 = (wave + kHqRhsWaves * j) * 16;
+      if (r0 >= M) break;
+      if (r0 + 15 < k) continue;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) cacc_step(w, vh[j][kk].x, -vh[j][kk].y, yr[j][kk], yi[j][kk]);
+    }
+#pragma unroll
+    for (int j = 0; j < kHqRhsRbw; ++j) {
+      const int r0 = (wave + kHqRhsWaves * j) * 16;
+      const bool live = r0 + 15 >= k && r0 < M;
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk)
+        vv[j][kk] = live && r0 + lr < M ? hq_v(A, M, k, nb, r0 + lr, 4 * kk + lq) : make_double2(0.0, 0.0);
+    }
+    double* red = pool + (size_t)(p & 1) * kHqRhsWaves * 2 * 4 * 64;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      red[wave][0][q][lane] = wr[q];
-      red[wave][1][q][lane] = wi[q];
+      red[((wave * 2 + 0) * 4 + q) * 64 + lane] = w.t1[q] - w.t2[q];
+      red[((wave * 2 + 1) * 4 + q) * 64 + lane] = w.t3[q] - w.t1[q] - w.t2[q];
     }
     __syncthreads();
-    // 2. full w in every wave (register q: row 4q + lq, column lr), then
-    //    u = T^H w on the matrix cores (the result is again in that layout)
-    double w_r[4], w_i[4];
+    // 2. full w (register q: reflector 4 q + lq, column lr), u = T^H w
+    double wr[4], wi[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       double a = 0.0, b = 0.0;
 #pragma unroll
-      for (int w = 0; w < kHqRhsWaves; ++w) {
-        a += red[w][0][q][lane];
-        b += red[w][1][q][lane];
+      for (int v = 0; v < kHqRhsWaves; ++v) {
+        a += red[((v * 2 + 0) * 4 + q) * 64 + lane];
+        b += red[((v * 2 + 1) * 4 + q) * 64 + lane];
       }
-      w_r[q] = a;
-      w_i[q] = b;
+      wr[q] = a;
+      wi[q] = b;
     }
-    hvec4 ur = {0, 0, 0, 0}, ui = {0, 0, 0, 0};
+    const cplx* Tp = D.T + (size_t)p * kHqNb * kHqNb;
+    Cacc u;
+    cacc_zero(u);
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
-      const int q = 4 * kk + lq;
-      const double2 t = hld(Tp + (size_t)lr * kHqNb + q);  // T[q][i = lr]; A = conj(T)^T
-      ur = __builtin_amdgcn_mfma_f64_16x16x4f64(t.x, w_r[kk], ur, 0, 0, 0);
-      ur = __builtin_amdgcn_mfma_f64_16x16x4f64(t.y, w_i[kk], ur, 0, 0, 0);
-      ui = __builtin_amdgcn_mfma_f64_16x16x4f64(t.x, w_i[kk], ui, 0, 0, 0);
-      ui = __builtin_amdgcn_mfma_f64_16x16x4f64(-t.y, w_r[kk], ui, 0, 0, 0);
+      const double2 t = hld(Tp + (size_t)lr * kHqNb + 4 * kk + lq);  // T[4 kk + lq][lr]; A = conj(T)^T
+      cacc_step(u, t.x, -t.y, wr[kk], wi[kk]);
     }
-    // 3. Y(rows k..M-1) -= V u, 16-row blocks (k is a multiple of 16)
-    for (int r0 = k + 16 * wave; r0 < M; r0 += 16 * kHqRhsWaves) {
-      hvec4 ar = {0, 0, 0, 0}, ai = {0, 0, 0, 0};
-      double2 v[4];
+    double ur[4], ui[4];
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const int i = 4 * kk + lq, r = r0 + lr;
-        v[kk] = r < M ? hq_v(A, M, k, nb, r, i) : make_double2(0.0, 0.0);
-      }
+    for (int q = 0; q < 4; ++q) {
+      ur[q] = u.t1[q] - u.t2[q];
+      ui[q] = u.t3[q] - u.t1[q] - u.t2[q];
+    }
+    // 3. Y -= V u on this wave's rows from k on
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        ar = __builtin_amdgcn_mfma_f64_16x16x4f64(v[kk].x, ur[kk], ar, 0, 0, 0);
-        ar = __builtin_amdgcn_mfma_f64_16x16x4f64(-v[kk].y, ui[kk], ar, 0, 0, 0);
-        ai = __builtin_amdgcn_mfma_f64_16x16x4f64(v[kk].x, ui[kk], ai, 0, 0, 0);
-        ai = __builtin_amdgcn_mfma_f64_16x16x4f64(v[kk].y, ur[kk], ai, 0, 0, 0);
-      }
+    for (int j = 0; j < kHqRhsRbw; ++j) {
+      const int r0 = (wave + kHqRhsWaves * j) * 16;
+      if (r0 >= M) break;
+      if (r0 + 15 < k) continue;
+      Cacc d;
+      cacc_zero(d);
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) cacc_step(d, vv[j][kk].x, vv[j][kk].y, ur[kk], ui[kk]);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int r = r0 + lq + 4 * q;
-        if (r < M) {
-          double2 y = Y[r][lr];
-          y.x -= ar[q];
-          y.y -= ai[q];
-          Y[r][lr] = y;
-        }
+        yr[j][q] -= d.t1[q] - d.t2[q];
+        yi[j][q] -= d.t3[q] - d.t1[q] - d.t2[q];
       }
     }
-    __syncthreads();
   }
-  // 4. R X = Y(0:c) by 16-row blocks from the bottom: substitution inside
-  //    the diagonal block (one thread per column; R's diagonal spans the
-  //    Tikhonov scale, so no explicit block inverse), then
-  //    Y(rows above) -= R(rows above, block) X_b on the matrix cores
+  // 4. the top c rows into LDS (the partial-sum buffers are done with)
+  __syncthreads();
+  double2* Ys = reinterpret_cast<double2*>(pool);  // Ys[r * 16 + col]
+#pragma unroll
+  for (int j = 0; j < kHqRhsRbw; ++j)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = (wave + kHqRhsWaves * j) * 16 + lq + 4 * q;
+      if (r < c) Ys[r * kHqRhsCols + lr] = make_double2(yr[j][q], yi[j][q]);
+    }
   __shared__ double2 Rb[kHqNb][kHqNb + 1];
   for (int b = npan - 1; b >= 0; --b) {
     const int j0 = b * kHqNb;
@@ -440,15 +485,16 @@ __global__ __launch_bounds__(kHqRhsWaves * 64) void hq_rhs_kernel(const HqDesc* 
     __syncthreads();
     if (tid < kHqRhsCols) {
       for (int r = nbb - 1; r >= 0; --r) {
-        double2 acc = Y[j0 + r][tid];
+        double2 acc = Ys[(j0 + r) * kHqRhsCols + tid];
         for (int q = r + 1; q < nbb; ++q) {
-          const double2 a = Rb[r][q], x = Y[j0 + q][tid];
+          const double2 a = Rb[r][q], x = Ys[(j0 + q) * kHqRhsCols + tid];
           acc.x -= a.x * x.x - a.y * x.y;
           acc.y -= a.x * x.y + a.y * x.x;
         }
         const double2 d = Rb[r][r];
         const double dd = d.x * d.x + d.y * d.y;
-        Y[j0 + r][tid] = make_double2((acc.x * d.x + acc.y * d.y) / dd, (acc.y * d.x - acc.x * d.y) / dd);
+        Ys[(j0 + r) * kHqRhsCols + tid] =
+            make_double2((acc.x * d.x + acc.y * d.y) / dd, (acc.y * d.x - acc.x * d.y) / dd);
       }
     }
     __syncthreads();
@@ -456,35 +502,33 @@ __global__ __launch_bounds__(kHqRhsWaves * 64) void hq_rhs_kernel(const HqDesc* 
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
       const int q = 4 * kk + lq;
-      const double2 x = q < nbb ? Y[j0 + q][lr] : make_double2(0.0, 0.0);
+      const double2 x = q < nbb ? Ys[(j0 + q) * kHqRhsCols + lr] : make_double2(0.0, 0.0);
       xr[kk] = x.x;
       xi[kk] = x.y;
     }
     for (int r0 = 16 * wave; r0 < j0; r0 += 16 * kHqRhsWaves) {
-      hvec4 ar = {0, 0, 0, 0}, ai = {0, 0, 0, 0};
+      Cacc d;
+      cacc_zero(d);
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
         const int q = 4 * kk + lq;
         const double2 a = q < nbb ? hld(A + (size_t)(j0 + q) * M + r0 + lr) : make_double2(0.0, 0.0);
-        ar = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, xr[kk], ar, 0, 0, 0);
-        ar = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, xi[kk], ar, 0, 0, 0);
-        ai = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, xi[kk], ai, 0, 0, 0);
-        ai = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, xr[kk], ai, 0, 0, 0);
+        cacc_step(d, a.x, a.y, xr[kk], xi[kk]);
       }
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int r = r0 + lq + 4 * q;
-        double2 y = Y[r][lr];
-        y.x -= ar[q];
-        y.y -= ai[q];
-        Y[r][lr] = y;
+        double2 y = Ys[r * kHqRhsCols + lr];
+        y.x -= d.t1[q] - d.t2[q];
+        y.y -= d.t3[q] - d.t1[q] - d.t2[q];
+        Ys[r * kHqRhsCols + lr] = y;
       }
     }
     __syncthreads();
   }
   for (int e = tid; e < c * kHqRhsCols; e += kHqRhsWaves * 64) {
     const int r = e % c, j = e / c;
-    if (j < nc) hst(B + (size_t)(col0 + j) * M + r, Y[r][j]);
+    if (j < nc) hst(B + (size_t)(col0 + j) * M + r, Ys[r * kHqRhsCols + j]);
   }
 }
 
@@ -498,10 +542,15 @@ void launch_hq_update(const HqDesc* d, int n, int k, int max_cols, hipStream_t s
   const int tiles = (max_cols - k - 1) / kHqCols + 1;
   if (n > 0 && tiles > 0) hipLaunchKernelGGL(hq_update_kernel, dim3(tiles, n), dim3(256), 0, st, d, k);
 }
-void launch_hq_rhs(const HqDesc* d, int n, int max_ncol, hipStream_t st) {
+void launch_hq_rhs(const HqDesc* d, int n, int max_ncol, int max_c, int max_rows, hipStream_t st) {
   const int tiles = (max_ncol + kHqRhsCols - 1) / kHqRhsCols;
-  if (n > 0 && tiles > 0)
-    hipLaunchKernelGGL(hq_rhs_kernel, dim3(tiles, n), dim3(kHqRhsWaves * 64), 0, st, d);
+  const size_t red = sizeof(double) * 2 * kHqRhsWaves * 2 * 4 * 64;
+  const size_t tile = sizeof(double2) * (size_t)max_c * kHqRhsCols;
+  if (n <= 0 || tiles <= 0) return;
+  if (max_rows <= kHqRhsSmallRows)
+    hipLaunchKernelGGL(hq_rhs_kernel<3>, dim3(tiles, n), dim3(kHqRhsWaves * 64), std::max(red, tile), st, d);
+  else
+    hipLaunchKernelGGL(hq_rhs_kernel<4>, dim3(tiles, n), dim3(kHqRhsWaves * 64), std::max(red, tile), st, d);
 }
 
 }  // namespace mlh

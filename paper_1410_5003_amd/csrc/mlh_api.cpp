@@ -1229,6 +1229,9 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
     int gtiles = 0;
     std::vector<HqDesc> hq;
     int maxc = 0, maxcols = 0, maxncol = 0;
+    struct HqClass {
+      int n = 0, maxc = 0, maxncol = 0, maxrows = 0;
+    } hq_small, hq_large;
     std::vector<AngleDesc> angs;
     const cplx one = cx(1, 0);
     for (int b = 0; b < nb; ++b) {
@@ -1337,6 +1340,17 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
         A.flux = v.flux + q;
         angs.push_back(A);
       }
+    }
+    // layers with at most kHqRhsSmallRows rows first: the right-hand-side
+    // kernel is launched once per size class (the other kernels take each
+    // descriptor on its own)
+    std::stable_partition(hq.begin(), hq.end(), [](const HqDesc& H) { return H.m + H.c <= kHqRhsSmallRows; });
+    for (const HqDesc& H : hq) {
+      HqClass& g = H.m + H.c <= kHqRhsSmallRows ? hq_small : hq_large;
+      ++g.n;
+      g.maxc = std::max(g.maxc, H.c);
+      g.maxncol = std::max(g.maxncol, H.ncol);
+      g.maxrows = std::max(g.maxrows, H.m + H.c);
     }
     // ---- block-tridiagonal solve by cyclic reduction (the paper's block LU,
     //      Sec. 3.3, reordered so that every level eliminates half of the
@@ -1581,7 +1595,8 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
           te();
         }
         tb(prof ? &prof->ls_rhs_ms : nullptr);
-        launch_hq_rhs(d_hq, nhq, maxncol, ls);
+        launch_hq_rhs(d_hq, hq_small.n, hq_small.maxncol, hq_small.maxc, hq_small.maxrows, ls);
+        launch_hq_rhs(d_hq + hq_small.n, hq_large.n, hq_large.maxncol, hq_large.maxc, hq_large.maxrows, ls);
         te();
       }
       if (stop_phase == 0 || stop_phase >= 3) {
@@ -1670,7 +1685,8 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
       // every launch shape of the sequence: a cached graph is replayed only
       // when all of them, and the workspace, are unchanged
       std::vector<int64_t> sig = {nb, B, nang, rchunk, (int64_t)doff, (int64_t)(intptr_t)s->wmem, (int64_t)elems,
-                                  gtiles, maxc, maxcols, maxncol, (int64_t)hq.size(), (int64_t)gs.size()};
+                                  gtiles, maxc, maxcols, maxncol, (int64_t)hq.size(), (int64_t)gs.size(),
+                                  hq_small.n, hq_small.maxc, hq_small.maxncol, hq_large.maxc, hq_large.maxncol};
       for (const Level& lv : levels) {
         sig.push_back(lv.maxn);
         sig.push_back(lv.maxcol);
