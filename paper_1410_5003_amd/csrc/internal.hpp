@@ -183,6 +183,13 @@ __device__ __forceinline__ double2 ldc(const cplx* p) {
   const gdouble2 v = *gmem(reinterpret_cast<const gdouble2*>(p));
   return make_double2(v.x, v.y);
 }
+// p's value when ok, zero otherwise.  p must be a valid address either way
+// (callers clamp their indices), so no branch guards the load and loads
+// issue back to back instead of one wait per guarded load.
+__device__ __forceinline__ double2 ldc_sel(const cplx* p, bool ok) {
+  const double2 v = ldc(p);
+  return make_double2(ok ? v.x : 0.0, ok ? v.y : 0.0);
+}
 __device__ __forceinline__ void stc(cplx* p, double re, double im) {
   gdouble2 v;
   v.x = re;

@@ -520,11 +520,11 @@ __device__ __forceinline__ void panel_body(const GjeDesc* __restrict__ descs, in
         const int rb = b0 + h * (NW - 2);
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk)
-          pa[h][kk] = rb < nrb ? gld(W + (size_t)(kp + 4 * kk + lq) * n + rb * 16 + lr) : make_double2(0.0, 0.0);
+          pa[h][kk] = ldc_sel(W + (size_t)(kp + 4 * kk + lq) * n + min(rb, nrb - 1) * 16 + lr, rb < nrb);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const double2 v = (rb < nrb && lr < nb) ? gld(W + (size_t)(k + lr) * n + rb * 16 + lq + 4 * q)
-                                                   : make_double2(0.0, 0.0);
+          const double2 v =
+              ldc_sel(W + (size_t)(k + min(lr, nb - 1)) * n + min(rb, nrb - 1) * 16 + lq + 4 * q, rb < nrb && lr < nb);
           vr[h][q] = v.x;
           vi[h][q] = v.y;
         }
@@ -613,14 +613,16 @@ __device__ __forceinline__ void update_body(const GjeDesc* __restrict__ descs, i
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
       const int row = r0 + lr, kq = 4 * kk + lq;
-      P[j][kk] = (row < n && kq < nb) ? gld(W + (size_t)(k + kq) * n + row) : make_double2(0.0, 0.0);
+      // clamped, not masked: a row past n only feeds results that are not
+      // stored, and a column past nb meets the zero rows of Z
+      P[j][kk] = ldc(W + (uint32_t)((k + min(kq, nb - 1)) * n + min(row, n - 1)));
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 4; ++q) {  // real and imaginary parts straight into the accumulators
       const int row = r0 + lq + 4 * q;
-      const double2 v = (row < n && lr < nc) ? gld(W + (size_t)(c0 + lr) * n + row) : make_double2(0.0, 0.0);
-      Vr[j][q] = v.x;
-      Vi[j][q] = v.y;
+      const auto vp = gmem(reinterpret_cast<const double*>(W + (uint32_t)((c0 + min(lr, nc - 1)) * n + min(row, n - 1))));
+      Vr[j][q] = vp[0];
+      Vi[j][q] = vp[1];
     }
   }
   __syncthreads();
@@ -879,7 +881,7 @@ __global__ __launch_bounds__(256) void gje_premul_kernel(const GjeDesc* __restri
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) {
     const int row = r0 + lr, kq = 4 * kk + lq;
-    a[kk] = (row < n && kq < nb) ? gld(W + (size_t)(k + kq) * n + row) : make_double2(0.0, 0.0);
+    a[kk] = ldc(W + (uint32_t)((k + min(kq, nb - 1)) * n + min(row, n - 1)));  // M1 is zero past nb
     b[kk] = gld(M1 + (size_t)lr * kGjeNb + kq);  // M1[kq][lr], column-major
   }
   dvec4 t1 = {0, 0, 0, 0}, t2 = {0, 0, 0, 0}, t3 = {0, 0, 0, 0};
@@ -923,7 +925,7 @@ __global__ __launch_bounds__(kRhsWaves * 64) void gje_rhs_kernel(const GjeDesc* 
     cplx* W = D.W;
     for (int e = tid; e < n * TC; e += kRhsWaves * 64) {
       const int r = e % n, c = e / n;
-      Y[r][c] = c < nc ? gld(W + (size_t)(c0 + c) * n + r) : make_double2(0.0, 0.0);
+      Y[r][c] = ldc_sel(W + (size_t)(c0 + min(c, nc - 1)) * n + r, c < nc);
     }
     const int nsteps = min(s1, (n + kGjeNb - 1) / kGjeNb);
     // multipliers P' of a step for this wave's first PF row blocks
@@ -935,7 +937,8 @@ __global__ __launch_bounds__(kRhsWaves * 64) void gje_rhs_kernel(const GjeDesc* 
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
         const int kq = 4 * kk + lq;
-        dst[kk] = (row < n && kq < nb) ? gld(W + (size_t)(k + kq) * n + row) : make_double2(0.0, 0.0);
+        // clamped: rows past n are not stored, columns past nb meet zero pivot rows
+        dst[kk] = ldc(W + (uint32_t)((k + min(kq, nb - 1)) * n + min(row, n - 1)));
       }
     };
     if (s0 < nsteps)

@@ -372,10 +372,12 @@ __global__ __launch_bounds__(kHqRhsWaves * 64) void hq_rhs_kernel(const HqDesc* 
   for (int j = 0; j < kHqRhsRbw; ++j)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
+      // clamped, not masked: rows past M meet zero reflector rows, columns
+      // past nc are not stored; parts loaded straight into the accumulators
       const int r = (wave + kHqRhsWaves * j) * 16 + lq + 4 * q;
-      const double2 v = (r < M && lr < nc) ? hld(B + (size_t)(col0 + lr) * M + r) : make_double2(0.0, 0.0);
-      yr[j][q] = v.x;
-      yi[j][q] = v.y;
+      const auto yp = gmem(reinterpret_cast<const double*>(B + (uint32_t)((col0 + min(lr, nc - 1)) * M + min(r, M - 1))));
+      yr[j][q] = yp[0];
+      yi[j][q] = yp[1];
     }
   const int npan = (c + kHqNb - 1) / kHqNb;
   for (int p = 0; p < npan; ++p) {
