@@ -141,10 +141,11 @@ def algorithmic_work(desc):
 # dispatch of the run.  An entry counts only while its kernel source is the
 # one the counters were taken on (SHA-1 prefix of the file).
 MEASURED_TRAFFIC = {
-    ("config2_resolved", "gje_panel_kernel"): ("kernels_gje.hip", "5a1a878f5463", 2272.6, 915.8),
-    ("config2_resolved", "gje_update_kernel"): ("kernels_gje.hip", "5a1a878f5463", 21200.5, 14641.4),
-    ("config2_resolved", "gje_rhs_kernel"): ("kernels_gje.hip", "5a1a878f5463", 352517.9, 57397.3),
-    ("config2_resolved", "hq_rhs_kernel"): ("kernels_hq.hip", "d560f11ed62b", 491646.5, 98345.0),
+    ("config2_resolved", "gje_panel_kernel"): ("kernels_gje.hip", "cb6a6f453e23", 2138.1, 916.4),
+    ("config2_resolved", "gje_update_kernel"): ("kernels_gje.hip", "cb6a6f453e23", 21532.1, 14393.2),
+    ("config2_resolved", "gje_rhs_kernel"): ("kernels_gje.hip", "cb6a6f453e23", 352723.1, 57397.3),
+    ("config2_resolved", "hq_rhs_kernel"): ("kernels_hq.hip", "00415db21eaf", 482254.1, 95550.0),
+    ("config2_resolved", "zgemm_kernel"): ("kernels_linalg.hip", "7d8805564610", 1922451.0, 176303.5),
 }
 
 
