@@ -44,8 +44,9 @@ __host__ __device__ inline void hankel_series(double x, cplx& h0, cplx& g1m) {
 #pragma unroll
   for (int m = 1; m <= 16; ++m) {
     const double dm = (double)m;
-    t0 *= q / (dm * dm);
-    t1 *= q / (dm * (dm + 1.0));
+    // reciprocals of constants fold once the loop is unrolled
+    t0 *= q * (1.0 / (dm * dm));
+    t1 *= q * (1.0 / (dm * (dm + 1.0)));
     harm += 1.0 / dm;
     sj0 += t0;
     sj1 += t1;
@@ -60,8 +61,16 @@ __host__ __device__ inline void hankel_series(double x, cplx& h0, cplx& g1m) {
   g1m.im = 0.5 * kPi * x * j1;
 }
 
+// 1/k for a small positive integer k: the hardware reciprocal refined by one
+// Newton step (within an ulp, a few instructions instead of a division)
+__device__ inline double inv_int(int k) {
+  const double d = (double)k;
+  const double r = __builtin_amdgcn_rcp(d);
+  return __builtin_fma(r, __builtin_fma(-d, r, 1.0), r);
+}
+
 // Miller backward recurrence, 2 < x < 20
-__host__ __device__ inline void hankel_miller(double x, cplx& h0, cplx& g1m) {
+__device__ inline void hankel_miller(double x, cplx& h0, cplx& g1m) {
   const int nstart = 2 * ((int)(x + 4.0 * sqrt(x) + 16.0) / 2);
   const double tx = 2.0 / x;
   double jn1 = 0.0;      // J_{n+1}
@@ -72,17 +81,17 @@ __host__ __device__ inline void hankel_miller(double x, cplx& h0, cplx& g1m) {
     if (n & 1) {
       const int ka = (n + 1) / 2;
       const double sgn_a = (ka & 1) ? -1.0 : 1.0;
-      sa += sgn_a * jn / (double)ka;
+      sa += sgn_a * jn * inv_int(ka);
       if (n >= 3) {
         const int kb = (n - 1) / 2;
         const double sgn_b = (kb & 1) ? -1.0 : 1.0;
-        sb += sgn_b * jn / (double)kb;
+        sb += sgn_b * jn * inv_int(kb);
       }
       if (n == 1) j1 = jn;
     } else {
       const int k = n / 2;
       norm += 2.0 * jn;
-      sy0 += ((k & 1) ? -1.0 : 1.0) * jn / (double)k;
+      sy0 += ((k & 1) ? -1.0 : 1.0) * jn * inv_int(k);
     }
     const double jm1 = (double)n * tx * jn - jn1;
     jn1 = jn;
@@ -110,8 +119,9 @@ __host__ __device__ inline void hankel_asymptotic(double x, cplx& h0, cplx& g1m)
 #pragma unroll
   for (int k = 1; k <= 22; ++k) {
     const double o = (double)(2 * k - 1);
-    t0 *= (0.0 - o * o) * e / (double)k;
-    t1 *= (4.0 - o * o) * e / (double)k;
+    // ((nu^2 - o^2) / k) folds to a constant once the loop is unrolled
+    t0 *= ((0.0 - o * o) / (double)k) * e;
+    t1 *= ((4.0 - o * o) / (double)k) * e;
     // P = sum_{k even} (-1)^{k/2} t_k ; Q = sum_{k odd} (-1)^{(k-1)/2} t_k
     const int r = k & 3;
     const double s = (r == 0 || r == 1) ? 1.0 : -1.0;
@@ -137,7 +147,7 @@ __host__ __device__ inline void hankel_asymptotic(double x, cplx& h0, cplx& g1m)
   g1m = {-hx * a1.im - 1.0, hx * a1.re};
 }
 
-__host__ __device__ inline void hankel_pieces(double x, cplx& h0, cplx& g1m) {
+__device__ inline void hankel_pieces(double x, cplx& h0, cplx& g1m) {
   if (x <= kHankelSeriesMax)
     hankel_series(x, h0, g1m);
   else if (x < kHankelAsympMin)
@@ -156,7 +166,7 @@ struct Kern4 {
   cplx S, D, Ds, T;
 };
 
-__host__ __device__ inline Kern4 lp_kernels(double k, double r2, double nd, double npd, double nn) {
+__device__ inline Kern4 lp_kernels(double k, double r2, double nd, double npd, double nn) {
   const double r = sqrt(r2);
   const double x = k * r;
   cplx h0, gm;
@@ -172,14 +182,14 @@ __host__ __device__ inline Kern4 lp_kernels(double k, double r2, double nd, doub
   const double x2 = x * x;
   const double c = nd * npd * ir2;
   // (i/4) x^2 H0 - g1/pi
-  const double wr = -0.25 * x2 * h0.im - g1.re / kPi;
-  const double wi = 0.25 * x2 * h0.re - g1.im / kPi;
+  const double wr = -0.25 * x2 * h0.im - g1.re * (1.0 / kPi);
+  const double wi = 0.25 * x2 * h0.re - g1.im * (1.0 / kPi);
   o.T = {(nn * c2 * g1.re + c * wr) * ir2, (nn * c2 * g1.im + c * wi) * ir2};
   return o;
 }
 
 // K^{ka} - K^{kb} with the k-independent singular parts cancelled exactly.
-__host__ __device__ inline Kern4 lp_kernels_diff(double ka, double kb, double r2, double nd,
+__device__ inline Kern4 lp_kernels_diff(double ka, double kb, double r2, double nd,
                                                  double npd, double nn) {
   const double r = sqrt(r2);
   const double xa = ka * r, xb = kb * r;
@@ -197,8 +207,8 @@ __host__ __device__ inline Kern4 lp_kernels_diff(double ka, double kb, double r2
   const double c = nd * npd * ir2;
   const double dx2r = xa * xa * ha.re - xb * xb * hb.re;
   const double dx2i = xa * xa * ha.im - xb * xb * hb.im;
-  const double wr = -0.25 * dx2i - dg.re / kPi;
-  const double wi = 0.25 * dx2r - dg.im / kPi;
+  const double wr = -0.25 * dx2i - dg.re * (1.0 / kPi);
+  const double wi = 0.25 * dx2r - dg.im * (1.0 / kPi);
   o.T = {(nn * c2 * dg.re + c * wr) * ir2, (nn * c2 * dg.im + c * wi) * ir2};
   return o;
 }
