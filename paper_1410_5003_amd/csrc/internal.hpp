@@ -262,7 +262,7 @@ struct HqDesc {
 
 void launch_hq_prep(const HqDesc* d, int n, hipStream_t st);
 void launch_hq_panel(const HqDesc* d, int n, int k, hipStream_t st);
-void launch_hq_update(const HqDesc* d, int n, int k, int max_cols, hipStream_t st);
+void launch_hq_update(const HqDesc* d, int n, int k, int max_c, int max_rows, hipStream_t st);
 void launch_hq_rhs(const HqDesc* d, int n, int max_ncol, int max_c, int max_rows, hipStream_t st);
 
 }  // namespace mlh

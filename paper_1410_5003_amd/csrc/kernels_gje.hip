@@ -923,9 +923,19 @@ __global__ __launch_bounds__(kRhsWaves * 64) void gje_rhs_kernel(const GjeDesc* 
     if (c0 >= D.ncol) continue;
     const int nc = min(TC, D.ncol - c0);
     cplx* W = D.W;
-    for (int e = tid; e < n * TC; e += kRhsWaves * 64) {
-      const int r = e % n, c = e / n;
-      Y[r][c] = ldc_sel(W + (size_t)(c0 + min(c, nc - 1)) * n + r, c < nc);
+    // eight loads in flight per thread (clamped addresses, no guarding branch)
+    for (int e0 = tid; e0 < n * TC; e0 += kRhsWaves * 64 * 8) {
+      double2 v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = min(e0 + kRhsWaves * 64 * u, n * TC - 1);
+        v[u] = ldc(W + (uint32_t)((c0 + min(e / n, nc - 1)) * n + e % n));
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + kRhsWaves * 64 * u;
+        if (e < n * TC) Y[e % n][e / n] = e / n < nc ? v[u] : make_double2(0.0, 0.0);
+      }
     }
     const int nsteps = min(s1, (n + kGjeNb - 1) / kGjeNb);
     // multipliers P' of a step for this wave's first PF row blocks

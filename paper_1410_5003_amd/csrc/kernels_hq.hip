@@ -90,9 +90,19 @@ __global__ __launch_bounds__(256) void hq_panel_kernel(const HqDesc* __restrict_
   __shared__ double2 gram[kHqNb][kHqNb + 1];
   __shared__ double2 T[kHqNb][kHqNb + 1];
   cplx* A = D.A;
-  for (int e = tid; e < L * kHqNb; e += 256) {
-    const int r = e % L, j = e / L;
-    pan[r][j] = j < nb ? hld(A + (size_t)(k + j) * M + k + r) : make_double2(0.0, 0.0);
+  // eight loads in flight per thread (clamped addresses, no guarding branch)
+  for (int e0 = tid; e0 < L * kHqNb; e0 += 256 * 8) {
+    double2 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = min(e0 + 256 * u, L * kHqNb - 1);
+      v[u] = hld(A + (uint32_t)((k + min(e / L, nb - 1)) * M + k + e % L));
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + 256 * u;
+      if (e < L * kHqNb) pan[e % L][e / L] = e / L < nb ? v[u] : make_double2(0.0, 0.0);
+    }
   }
   __syncthreads();
   for (int i = 0; i < nb; ++i) {
@@ -230,89 +240,6 @@ __global__ __launch_bounds__(256) void hq_panel_kernel(const HqDesc* __restrict_
   }
 }
 
-// Y <- Y - V (T^H (V^H Y)) for 32 columns: one wavefront per column, lanes
-// over rows; V (rows k..M-1, unit diagonal implicit) staged in LDS
-__global__ __launch_bounds__(256) void hq_update_kernel(const HqDesc* __restrict__ descs, int k) {
-  const HqDesc& D = descs[blockIdx.y];
-  const int c = D.c, M = D.m + c;
-  if (k >= c) return;
-  const int nb = min(kHqNb, c - k);
-  const int L = M - k;
-  const int total = c;  // right-hand sides: hq_rhs_kernel
-  const int c0 = k + nb + blockIdx.x * kHqCols;
-  if (c0 >= total) return;
-  const int nc = min(kHqCols, total - c0);
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  __shared__ double2 V[kHqMaxRows][kHqNb + 1];
-  __shared__ double2 T[kHqNb][kHqNb + 1];
-  cplx* A = D.A;
-  for (int e = tid; e < L * kHqNb; e += 256) {
-    const int r = e % L, j = e / L;
-    double2 v = make_double2(0.0, 0.0);
-    if (j < nb) {
-      if (r == j)
-        v = make_double2(1.0, 0.0);
-      else if (r > j)
-        v = hld(A + (size_t)(k + j) * M + k + r);
-    }
-    V[r][j] = v;
-  }
-  const cplx* Tk = D.T + (size_t)(k / kHqNb) * kHqNb * kHqNb;  // this panel's T
-  for (int e = tid; e < kHqNb * kHqNb; e += 256) T[e % kHqNb][e / kHqNb] = hld(Tk + e);
-  __syncthreads();
-  __shared__ double2 wsh[4][kHqNb], ush[4][kHqNb];
-  for (int cc = wave; cc < nc; cc += 4) {
-    cplx* y = A + (size_t)(c0 + cc) * M + k;
-    // w = V^H y  (16 partial sums per lane, then a wavefront reduction)
-    double2 w[kHqNb];
-#pragma unroll
-    for (int i = 0; i < kHqNb; ++i) w[i] = make_double2(0.0, 0.0);
-    for (int r = lane; r < L; r += 64) {
-      const double2 b = hld(y + r);
-#pragma unroll
-      for (int i = 0; i < kHqNb; ++i) {
-        const double2 v = V[r][i];
-        w[i].x += v.x * b.x + v.y * b.y;
-        w[i].y += v.x * b.y - v.y * b.x;
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < kHqNb; ++i) {
-      const double a = hwave_sum(w[i].x), b = hwave_sum(w[i].y);
-      if (lane == i) wsh[wave][i] = make_double2(a, b);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // u = T^H w
-    if (lane < kHqNb) {
-      double sr = 0.0, si = 0.0;
-#pragma unroll
-      for (int q = 0; q < kHqNb; ++q) {
-        const double2 t = T[q][lane], x = wsh[wave][q];  // conj(T[q][i]) w[q]
-        sr += t.x * x.x + t.y * x.y;
-        si += t.x * x.y - t.y * x.x;
-      }
-      ush[wave][lane] = make_double2(sr, si);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    // y -= V u
-    for (int r = lane; r < L; r += 64) {
-      double2 b = hld(y + r);
-#pragma unroll
-      for (int i = 0; i < kHqNb; ++i) {
-        const double2 v = V[r][i], u = ush[wave][i];
-        b.x -= v.x * u.x - v.y * u.y;
-        b.y -= v.x * u.y + v.y * u.x;
-      }
-      hst(y + r, b);
-    }
-    __builtin_amdgcn_wave_barrier();
-  }
-}
-
 typedef double hvec4 __attribute__((ext_vector_type(4)));
 
 // V of panel k as an MFMA operand value: column i, row r (global); unit
@@ -342,6 +269,96 @@ __device__ inline void cacc_step(Cacc& c, double ar, double ai, double br, doubl
   c.t1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, br, c.t1, 0, 0, 0);
   c.t2 = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, bi, c.t2, 0, 0, 0);
   c.t3 = __builtin_amdgcn_mfma_f64_16x16x4f64(ar + ai, br + bi, c.t3, 0, 0, 0);
+}
+
+// One block reflector H = I - V T V^H of panel k applied to the M x 16 tile
+// (yr, yi) that the eight waves of the workgroup hold in registers:
+// Y <- H^H Y = Y - V T^H (V^H Y).  Every wave of the workgroup calls it.
+template <int kHqRhsRbw>
+__device__ __forceinline__ void hq_apply_panel(hvec4 (&yr)[kHqRhsRbw], hvec4 (&yi)[kHqRhsRbw], const cplx* A, int M,
+                                               int k, int nb, const cplx* Tp, double* red) {
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int lr = lane & 15, lq = lane >> 4;
+  // V operands of this wave's row blocks: vh for V^H (lane: reflector lr,
+  // row 4 kk + lq) now, vv for V (lane: row lr, reflector 4 kk + lq) after
+  // the first products, its loads covered by the reduction
+  double2 vh[kHqRhsRbw][4], vv[kHqRhsRbw][4];
+#pragma unroll
+  for (int j = 0; j < kHqRhsRbw; ++j) {
+    const int r0 = (wave + kHqRhsWaves * j) * 16;
+    const bool live = r0 + 15 >= k && r0 < M;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+      vh[j][kk] = live && r0 + 4 * kk + lq < M ? hq_v(A, M, k, nb, r0 + 4 * kk + lq, lr) : make_double2(0.0, 0.0);
+  }
+  // 1. partial w = V^H Y over this wave's rows
+  Cacc w;
+  cacc_zero(w);
+#pragma unroll
+  for (int j = 0; j < kHqRhsRbw; ++j) {
+    const int r0 = (wave + kHqRhsWaves * j) * 16;
+    if (r0 >= M) break;
+    if (r0 + 15 < k) continue;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) cacc_step(w, vh[j][kk].x, -vh[j][kk].y, yr[j][kk], yi[j][kk]);
+  }
+#pragma unroll
+  for (int j = 0; j < kHqRhsRbw; ++j) {
+    const int r0 = (wave + kHqRhsWaves * j) * 16;
+    const bool live = r0 + 15 >= k && r0 < M;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+      vv[j][kk] = live && r0 + lr < M ? hq_v(A, M, k, nb, r0 + lr, 4 * kk + lq) : make_double2(0.0, 0.0);
+  }
+  // red: this panel's buffer of partial sums
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    red[((wave * 2 + 0) * 4 + q) * 64 + lane] = w.t1[q] - w.t2[q];
+    red[((wave * 2 + 1) * 4 + q) * 64 + lane] = w.t3[q] - w.t1[q] - w.t2[q];
+  }
+  __syncthreads();
+  // 2. full w (register q: reflector 4 q + lq, column lr), u = T^H w
+  double wr[4], wi[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    double a = 0.0, b = 0.0;
+#pragma unroll
+    for (int v = 0; v < kHqRhsWaves; ++v) {
+      a += red[((v * 2 + 0) * 4 + q) * 64 + lane];
+      b += red[((v * 2 + 1) * 4 + q) * 64 + lane];
+    }
+    wr[q] = a;
+    wi[q] = b;
+  }
+  Cacc u;
+  cacc_zero(u);
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    const double2 t = hld(Tp + (size_t)lr * kHqNb + 4 * kk + lq);  // T[4 kk + lq][lr]; A = conj(T)^T
+    cacc_step(u, t.x, -t.y, wr[kk], wi[kk]);
+  }
+  double ur[4], ui[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    ur[q] = u.t1[q] - u.t2[q];
+    ui[q] = u.t3[q] - u.t1[q] - u.t2[q];
+  }
+  // 3. Y -= V u on this wave's rows from k on
+#pragma unroll
+  for (int j = 0; j < kHqRhsRbw; ++j) {
+    const int r0 = (wave + kHqRhsWaves * j) * 16;
+    if (r0 >= M) break;
+    if (r0 + 15 < k) continue;
+    Cacc d;
+    cacc_zero(d);
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) cacc_step(d, vv[j][kk].x, vv[j][kk].y, ur[kk], ui[kk]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      yr[j][q] -= d.t1[q] - d.t2[q];
+      yi[j][q] -= d.t3[q] - d.t1[q] - d.t2[q];
+    }
+  }
 }
 
 // One workgroup of eight waves per 16 right-hand-side columns of one layer.
@@ -382,88 +399,8 @@ __global__ __launch_bounds__(kHqRhsWaves * 64) void hq_rhs_kernel(const HqDesc* 
   const int npan = (c + kHqNb - 1) / kHqNb;
   for (int p = 0; p < npan; ++p) {
     const int k = p * kHqNb;
-    const int nb = min(kHqNb, c - k);
-    // V operands of this wave's row blocks: vh for V^H (lane: reflector lr,
-    // row 4 kk + lq) now, vv for V (lane: row lr, reflector 4 kk + lq) after
-    // the first products, its loads covered by the reduction
-    double2 vh[kHqRhsRbw][4], vv[kHqRhsRbw][4];
-#pragma unroll
-    for (int j = 0; j < kHqRhsRbw; ++j) {
-      const int r0 = (wave + kHqRhsWaves * j) * 16;
-      const bool live = r0 + 15 >= k && r0 < M;
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk)
-        vh[j][kk] = live && r0 + 4 * kk + lq < M ? hq_v(A, M, k, nb, r0 + 4 * kk + lq, lr) : make_double2(0.0, 0.0);
-    }
-    // 1. partial w = V^H Y over this wave's rows
-    Cacc w;
-    cacc_zero(w);
-#pragma unroll
-    for (int j = 0; j < kHqRhsRbw; ++j) {
-      const int r0 = (wave + kHqRhsWaves * j) * 16;
-      if (r0 >= M) break;
-      if (r0 + 15 < k) continue;
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) cacc_step(w, vh[j][kk].x, -vh[j][kk].y, yr[j][kk], yi[j][kk]);
-    }
-#pragma unroll
-    for (int j = 0; j < kHqRhsRbw; ++j) {
-      const int r0 = (wave + kHqRhsWaves * j) * 16;
-      const bool live = r0 + 15 >= k && r0 < M;
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk)
-        vv[j][kk] = live && r0 + lr < M ? hq_v(A, M, k, nb, r0 + lr, 4 * kk + lq) : make_double2(0.0, 0.0);
-    }
-    double* red = pool + (size_t)(p & 1) * kHqRhsWaves * 2 * 4 * 64;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      red[((wave * 2 + 0) * 4 + q) * 64 + lane] = w.t1[q] - w.t2[q];
-      red[((wave * 2 + 1) * 4 + q) * 64 + lane] = w.t3[q] - w.t1[q] - w.t2[q];
-    }
-    __syncthreads();
-    // 2. full w (register q: reflector 4 q + lq, column lr), u = T^H w
-    double wr[4], wi[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      double a = 0.0, b = 0.0;
-#pragma unroll
-      for (int v = 0; v < kHqRhsWaves; ++v) {
-        a += red[((v * 2 + 0) * 4 + q) * 64 + lane];
-        b += red[((v * 2 + 1) * 4 + q) * 64 + lane];
-      }
-      wr[q] = a;
-      wi[q] = b;
-    }
-    const cplx* Tp = D.T + (size_t)p * kHqNb * kHqNb;
-    Cacc u;
-    cacc_zero(u);
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      const double2 t = hld(Tp + (size_t)lr * kHqNb + 4 * kk + lq);  // T[4 kk + lq][lr]; A = conj(T)^T
-      cacc_step(u, t.x, -t.y, wr[kk], wi[kk]);
-    }
-    double ur[4], ui[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      ur[q] = u.t1[q] - u.t2[q];
-      ui[q] = u.t3[q] - u.t1[q] - u.t2[q];
-    }
-    // 3. Y -= V u on this wave's rows from k on
-#pragma unroll
-    for (int j = 0; j < kHqRhsRbw; ++j) {
-      const int r0 = (wave + kHqRhsWaves * j) * 16;
-      if (r0 >= M) break;
-      if (r0 + 15 < k) continue;
-      Cacc d;
-      cacc_zero(d);
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) cacc_step(d, vv[j][kk].x, vv[j][kk].y, ur[kk], ui[kk]);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        yr[j][q] -= d.t1[q] - d.t2[q];
-        yi[j][q] -= d.t3[q] - d.t1[q] - d.t2[q];
-      }
-    }
+    hq_apply_panel<kHqRhsRbw>(yr, yi, A, M, k, min(kHqNb, c - k), D.T + (size_t)p * kHqNb * kHqNb,
+                              pool + (size_t)(p & 1) * kHqRhsWaves * 2 * 4 * 64);
   }
   // 4. the top c rows into LDS (the partial-sum buffers are done with)
   __syncthreads();
@@ -534,15 +471,59 @@ __global__ __launch_bounds__(kHqRhsWaves * 64) void hq_rhs_kernel(const HqDesc* 
   }
 }
 
+// The later columns of S for panel k: Y <- H^H Y on 16 columns per
+// workgroup, the tile in registers as in hq_rhs_kernel (rows below k only
+// are read back and changed).
+template <int kHqRhsRbw>
+__global__ __launch_bounds__(kHqRhsWaves * 64) void hq_update_kernel(const HqDesc* __restrict__ descs, int k) {
+  const HqDesc& D = descs[blockIdx.y];
+  const int c = D.c, M = D.m + c;
+  if (k >= c) return;
+  const int nb = min(kHqNb, c - k);
+  const int c0 = k + nb + blockIdx.x * kHqRhsCols;
+  if (c0 >= c) return;
+  const int nc = min(kHqRhsCols, c - c0);
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int lr = lane & 15, lq = lane >> 4;
+  cplx* A = D.A;
+  extern __shared__ double pool[];
+  hvec4 yr[kHqRhsRbw], yi[kHqRhsRbw];
+#pragma unroll
+  for (int j = 0; j < kHqRhsRbw; ++j)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      // clamped, not masked: rows past M meet zero reflector rows, columns
+      // past nc are not stored
+      const int r = (wave + kHqRhsWaves * j) * 16 + lq + 4 * q;
+      const auto yp = gmem(reinterpret_cast<const double*>(A + (uint32_t)((c0 + min(lr, nc - 1)) * M + min(r, M - 1))));
+      yr[j][q] = yp[0];
+      yi[j][q] = yp[1];
+    }
+  hq_apply_panel<kHqRhsRbw>(yr, yi, A, M, k, nb, D.T + (size_t)(k / kHqNb) * kHqNb * kHqNb, pool);
+  if (lr < nc)
+#pragma unroll
+    for (int j = 0; j < kHqRhsRbw; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = (wave + kHqRhsWaves * j) * 16 + lq + 4 * q;
+        if (r >= k && r < M) hst(A + (uint32_t)((c0 + lr) * M + r), make_double2(yr[j][q], yi[j][q]));
+      }
+}
+
 void launch_hq_prep(const HqDesc* d, int n, hipStream_t st) {
   if (n > 0) hipLaunchKernelGGL(hq_prep_kernel, dim3(n), dim3(256), 0, st, d);
 }
 void launch_hq_panel(const HqDesc* d, int n, int k, hipStream_t st) {
   if (n > 0) hipLaunchKernelGGL(hq_panel_kernel, dim3(n), dim3(256), 0, st, d, k);
 }
-void launch_hq_update(const HqDesc* d, int n, int k, int max_cols, hipStream_t st) {
-  const int tiles = (max_cols - k - 1) / kHqCols + 1;
-  if (n > 0 && tiles > 0) hipLaunchKernelGGL(hq_update_kernel, dim3(tiles, n), dim3(256), 0, st, d, k);
+void launch_hq_update(const HqDesc* d, int n, int k, int max_c, int max_rows, hipStream_t st) {
+  const int tiles = (max_c - k - kHqNb + kHqRhsCols - 1) / kHqRhsCols;
+  const size_t red = sizeof(double) * kHqRhsWaves * 2 * 4 * 64;
+  if (n <= 0 || tiles <= 0) return;
+  if (max_rows <= kHqRhsSmallRows)
+    hipLaunchKernelGGL(hq_update_kernel<3>, dim3(tiles, n), dim3(kHqRhsWaves * 64), red, st, d, k);
+  else
+    hipLaunchKernelGGL(hq_update_kernel<4>, dim3(tiles, n), dim3(kHqRhsWaves * 64), red, st, d, k);
 }
 void launch_hq_rhs(const HqDesc* d, int n, int max_ncol, int max_c, int max_rows, hipStream_t st) {
   const int tiles = (max_ncol + kHqRhsCols - 1) / kHqRhsCols;

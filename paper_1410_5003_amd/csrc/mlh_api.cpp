@@ -1591,7 +1591,8 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
           launch_hq_panel(d_hq, nhq, k, ls);
           te();
           tb(prof ? &prof->ls_update_ms : nullptr);
-          launch_hq_update(d_hq, nhq, k, maxc, ls);
+          launch_hq_update(d_hq, hq_small.n, k, hq_small.maxc, hq_small.maxrows, ls);
+          launch_hq_update(d_hq + hq_small.n, hq_large.n, k, hq_large.maxc, hq_large.maxrows, ls);
           te();
         }
         tb(prof ? &prof->ls_rhs_ms : nullptr);
