@@ -68,22 +68,40 @@ __device__ inline double row16_sum(double v) {
   v += dpp_shr_d<0x118>(v);  // row_shr:8
   return v;
 }
+template <int CTRL, int ROWS>
+__device__ inline double dpp_rows_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffff), CTRL, ROWS, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)((unsigned long long)b >> 32), CTRL, ROWS, 0xf, true);
+  return __longlong_as_double(((long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+// sum of v over the wavefront, returned in every lane (wave-uniform)
+__device__ inline double wave64_sum(double v) {
+  v = row16_sum(v);                   // lane 15 of each row: the row's sum
+  v += dpp_rows_d<0x142, 0xa>(v);     // row_bcast:15 into rows 1, 3
+  v += dpp_rows_d<0x143, 0xc>(v);     // row_bcast:31 into rows 2, 3 -> lane 63: the total
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffff), 63);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)((unsigned long long)b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | lo);
+}
 
 // Panel rows k..M-1 of columns k..k+15 in LDS (stride 17 against bank
-// conflicts).  Thread (j, q) = (tid / 16, tid % 16) owns column j of the rows
-// congruent to q modulo 16 below the current reflector, so each column step
-// is one pass (the norm of column i and the raw products of column i with
-// the later columns), sums over the 16 lanes of a DPP row, one barrier, and
-// one update pass.  The scaling of column i into its Householder vector is
-// deferred to the next pass, which does not read that column.
-__global__ __launch_bounds__(256) void hq_panel_kernel(const HqDesc* __restrict__ descs, int k) {
+// conflicts).  Wave j owns column j and lane q the rows congruent to q modulo
+// 64 below the current reflector, so each column step is one pass (the norm
+// of column i and the raw products of column i with the later columns),
+// wavefront sums by DPP, one barrier, and one update pass.  The scaling of
+// column i into its Householder vector is deferred to the next pass, which
+// does not read that column.
+constexpr int kHqPanelThreads = 64 * kHqNb;
+__global__ __launch_bounds__(kHqPanelThreads) void hq_panel_kernel(const HqDesc* __restrict__ descs, int k) {
   const HqDesc& D = descs[blockIdx.x];
   const int c = D.c, M = D.m + c;
   if (k >= c) return;
   const int nb = min(kHqNb, c - k);
   const int L = M - k;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int jc = tid >> 4, q16 = tid & 15;
+  const int jc = wave;  // the column this wave owns
   __shared__ double2 pan[kHqMaxRows][kHqNb + 1];
   __shared__ double2 red[2][kHqNb];
   __shared__ double2 tau[kHqNb], scl[kHqNb];
@@ -91,16 +109,16 @@ __global__ __launch_bounds__(256) void hq_panel_kernel(const HqDesc* __restrict_
   __shared__ double2 T[kHqNb][kHqNb + 1];
   cplx* A = D.A;
   // eight loads in flight per thread (clamped addresses, no guarding branch)
-  for (int e0 = tid; e0 < L * kHqNb; e0 += 256 * 8) {
+  for (int e0 = tid; e0 < L * kHqNb; e0 += kHqPanelThreads * 8) {
     double2 v[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int e = min(e0 + 256 * u, L * kHqNb - 1);
+      const int e = min(e0 + kHqPanelThreads * u, L * kHqNb - 1);
       v[u] = hld(A + (uint32_t)((k + min(e / L, nb - 1)) * M + k + e % L));
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int e = e0 + 256 * u;
+      const int e = e0 + kHqPanelThreads * u;
       if (e < L * kHqNb) pan[e % L][e / L] = e / L < nb ? v[u] : make_double2(0.0, 0.0);
     }
   }
@@ -110,17 +128,16 @@ __global__ __launch_bounds__(256) void hq_panel_kernel(const HqDesc* __restrict_
     // deferred: column i - 1 becomes its Householder vector
     if (i > 0 && jc == i - 1) {
       const double2 sc = scl[i - 1];
-      for (int r = i + q16; r < L; r += 16) {
+      for (int r = i + lane; r < L; r += 64) {
         const double2 x = pan[r][i - 1];
         pan[r][i - 1] = make_double2(x.x * sc.x - x.y * sc.y, x.x * sc.y + x.y * sc.x);
       }
     }
     // pass 1: |x|^2 below the diagonal of column i; raw products of column i
     // with the later columns (rows below i)
-    double ar = 0.0, ai = 0.0;
     if (jc >= i) {
-#pragma unroll 4
-      for (int r = i + 1 + q16; r < L; r += 16) {
+      double ar = 0.0, ai = 0.0;
+      for (int r = i + 1 + lane; r < L; r += 64) {
         const double2 x = pan[r][i];
         if (jc == i) {
           ar += x.x * x.x + x.y * x.y;
@@ -130,10 +147,10 @@ __global__ __launch_bounds__(256) void hq_panel_kernel(const HqDesc* __restrict_
           ai += x.x * y.y - x.y * y.x;
         }
       }
+      ar = wave64_sum(ar);
+      ai = wave64_sum(ai);
+      if (lane == 0) red[buf][jc] = make_double2(ar, ai);
     }
-    ar = row16_sum(ar);
-    ai = row16_sum(ai);
-    if (q16 == 15) red[buf][jc] = make_double2(ar, ai);
     __syncthreads();
     // the reflector of column i, formed identically in every thread
     const double xn2 = red[buf][i].x;
@@ -155,9 +172,8 @@ __global__ __launch_bounds__(256) void hq_panel_kernel(const HqDesc* __restrict_
       const double wr = yi.x + sr * raw.x + si * raw.y, wi = yi.y + sr * raw.y - si * raw.x;
       const double ur = tr * wr + ti * wi, ui = tr * wi - ti * wr;
       const double vr = sr * ur - si * ui, vi = sr * ui + si * ur;  // s u
-      if (q16 == 0) pan[i][jc] = make_double2(yi.x - ur, yi.y - ui);
-#pragma unroll 4
-      for (int r = i + 1 + q16; r < L; r += 16) {
+      if (lane == 0) pan[i][jc] = make_double2(yi.x - ur, yi.y - ui);
+      for (int r = i + 1 + lane; r < L; r += 64) {
         const double2 x = pan[r][i];
         double2 y = pan[r][jc];
         y.x -= x.x * vr - x.y * vi;
@@ -174,36 +190,35 @@ __global__ __launch_bounds__(256) void hq_panel_kernel(const HqDesc* __restrict_
   }
   if (jc == nb - 1) {  // the last column's scaling
     const double2 sc = scl[nb - 1];
-    for (int r = nb + q16; r < L; r += 16) {
+    for (int r = nb + lane; r < L; r += 64) {
       const double2 x = pan[r][nb - 1];
       pan[r][nb - 1] = make_double2(x.x * sc.x - x.y * sc.y, x.x * sc.y + x.y * sc.x);
     }
   }
   __syncthreads();
-  // Gram matrix G = V^H V (V unit lower trapezoidal): thread (b, q) sums
-  // conj(v_a) v_b over its rows for every a < b
-  {
+  // Gram matrix G = V^H V (V unit lower trapezoidal): wave b sums
+  // conj(v_a) v_b over its lanes' rows for every a < b
+  if (jc < nb) {
     double2 g[kHqNb];
 #pragma unroll
     for (int a = 0; a < kHqNb; ++a) g[a] = make_double2(0.0, 0.0);
-    if (jc < nb) {
-#pragma unroll 4
-      for (int r = jc + q16; r < L; r += 16) {
-        const double2 vb = r == jc ? make_double2(1.0, 0.0) : pan[r][jc];
+    for (int r = jc + lane; r < L; r += 64) {
+      const double2 vb = r == jc ? make_double2(1.0, 0.0) : pan[r][jc];
 #pragma unroll
-        for (int a = 0; a < kHqNb; ++a) {
-          if (a < jc) {
-            const double2 va = r == a ? make_double2(1.0, 0.0) : pan[r][a];  // r >= jc > a
-            g[a].x += va.x * vb.x + va.y * vb.y;
-            g[a].y += va.x * vb.y - va.y * vb.x;
-          }
+      for (int a = 0; a < kHqNb; ++a) {
+        if (a < jc) {
+          const double2 va = r == a ? make_double2(1.0, 0.0) : pan[r][a];  // r >= jc > a
+          g[a].x += va.x * vb.x + va.y * vb.y;
+          g[a].y += va.x * vb.y - va.y * vb.x;
         }
       }
     }
 #pragma unroll
     for (int a = 0; a < kHqNb; ++a) {
-      const double gr = row16_sum(g[a].x), gi = row16_sum(g[a].y);
-      if (q16 == 15 && a < jc && jc < nb) gram[a][jc] = make_double2(gr, gi);
+      if (a < jc) {  // wave-uniform
+        const double gr = wave64_sum(g[a].x), gi = wave64_sum(g[a].y);
+        if (lane == 0) gram[a][jc] = make_double2(gr, gi);
+      }
     }
   }
   __syncthreads();
@@ -233,8 +248,9 @@ __global__ __launch_bounds__(256) void hq_panel_kernel(const HqDesc* __restrict_
   }
   __syncthreads();
   const int pidx = k / kHqNb;
-  for (int e = tid; e < kHqNb * kHqNb; e += 256) hst(D.T + (size_t)pidx * kHqNb * kHqNb + e, T[e % kHqNb][e / kHqNb]);
-  for (int e = tid; e < L * nb; e += 256) {
+  for (int e = tid; e < kHqNb * kHqNb; e += kHqPanelThreads)
+    hst(D.T + (size_t)pidx * kHqNb * kHqNb + e, T[e % kHqNb][e / kHqNb]);
+  for (int e = tid; e < L * nb; e += kHqPanelThreads) {
     const int r = e % L, j = e / L;
     hst(A + (size_t)(k + j) * M + k + r, pan[r][j]);
   }
@@ -514,7 +530,7 @@ void launch_hq_prep(const HqDesc* d, int n, hipStream_t st) {
   if (n > 0) hipLaunchKernelGGL(hq_prep_kernel, dim3(n), dim3(256), 0, st, d);
 }
 void launch_hq_panel(const HqDesc* d, int n, int k, hipStream_t st) {
-  if (n > 0) hipLaunchKernelGGL(hq_panel_kernel, dim3(n), dim3(256), 0, st, d, k);
+  if (n > 0) hipLaunchKernelGGL(hq_panel_kernel, dim3(n), dim3(kHqPanelThreads), 0, st, d, k);
 }
 void launch_hq_update(const HqDesc* d, int n, int k, int max_c, int max_rows, hipStream_t st) {
   const int tiles = (max_c - k - kHqNb + kHqRhsCols - 1) / kHqRhsCols;
