@@ -74,30 +74,38 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void z
       t3[b][c] = dvec4{0, 0, 0, 0};
     }
   // slab staging: thread tid holds A elements (r, kk) = (e % 64, e / 64) and
-  // B elements (kk, c) = (e % 16, e / 16) for e = tid + 256 q
-  double2 pa[4], pb[4];
+  // B elements (kk, c) = (e % kGK, e / kGK) for e = tid + 256 q
+  constexpr int kPer = kGemmTile * kGK / 256;
+  double2 pa[kPer], pb[kPer];
+  // the descriptor's fields once, in registers; every address below is
+  // formed from clamped indices and a pointer select, with no branch
+  const cplx* const A1 = G.A;
+  const cplx* const A2 = G.A2;
+  const cplx* const B1 = G.B;
+  const cplx* const B2 = G.B2;
+  const int lda = G.lda, lda2 = G.lda2, ldb = G.ldb, ldb2 = G.ldb2;
   auto load_slab = [&](int k0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < kPer; ++q) {
       const int e = tid + 256 * q;
       {
         const int gr = row0 + e % kGemmTile, gk = k0 + e / kGemmTile;
-        pa[q] = make_double2(0.0, 0.0);
-        if (gr < m && gk < K)
-          pa[q] = gk < K1 ? ld2(G.A + (size_t)gk * G.lda + gr) : ld2(G.A2 + (size_t)(gk - K1) * G.lda2 + gr);
+        const int r = min(gr, m - 1), kc = min(gk, K - 1);
+        const cplx* src = kc < K1 ? A1 + (size_t)kc * lda + r : A2 + (size_t)(kc - K1) * lda2 + r;
+        pa[q] = ldc_sel(src, gr < m && gk < K);
       }
       {
         const int gk = k0 + e % kGK, gc = col0 + e / kGK;
-        pb[q] = make_double2(0.0, 0.0);
-        if (gc < n && gk < K)
-          pb[q] = gk < K1 ? ld2(G.B + (size_t)gc * G.ldb + gk) : ld2(G.B2 + (size_t)gc * G.ldb2 + (gk - K1));
+        const int cc = min(gc, n - 1), kc = min(gk, K - 1);
+        const cplx* src = kc < K1 ? B1 + (size_t)cc * ldb + kc : B2 + (size_t)cc * ldb2 + (kc - K1);
+        pb[q] = ldc_sel(src, gc < n && gk < K);
       }
     }
   };
   if (K > 0) load_slab(0);
   for (int k0 = 0; k0 < K; k0 += kGK) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < kPer; ++q) {
       const int e = tid + 256 * q;
       Ar[e / kGemmTile][e % kGemmTile] = pa[q].x;
       Ai[e / kGemmTile][e % kGemmTile] = pa[q].y;
@@ -130,6 +138,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void z
     }
     __syncthreads();
   }
+  // C0 first, every load in flight at once (clamped addresses), then C
+  const cplx* const C0 = G.C0;
+  cplx* const Cm = G.C;
+  const int ldc = G.ldc, ldc0 = G.ldc0;
+  const double alr = G.alpha.re, ali = G.alpha.im;
+  double2 c0v[2][2][4];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int col = min(col0 + wn + 16 * c + lr, n - 1), row = min(row0 + wm + 16 * b + lq + 4 * r, m - 1);
+        c0v[c][b][r] = C0 ? ld2(C0 + (size_t)col * ldc0 + row) : make_double2(0.0, 0.0);
+      }
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     const int col = col0 + wn + 16 * c + lr;
@@ -140,10 +163,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void z
       for (int r = 0; r < 4; ++r) {
         const int row = row0 + wm + 16 * b + lq + 4 * r;
         if (row < m) {
-          cplx* p = G.C + (size_t)col * G.ldc + row;
-          const double2 c0 = G.C0 ? ld2(G.C0 + (size_t)col * G.ldc0 + row) : make_double2(0.0, 0.0);
           const double xr = t1[b][c][r] - t2[b][c][r], xi = t3[b][c][r] - t1[b][c][r] - t2[b][c][r];
-          st2(p, c0.x + G.alpha.re * xr - G.alpha.im * xi, c0.y + G.alpha.re * xi + G.alpha.im * xr);
+          const double2 cv = c0v[c][b][r];
+          st2(Cm + (size_t)col * ldc + row, cv.x + alr * xr - ali * xi, cv.y + alr * xi + ali * xr);
         }
       }
   }
