@@ -75,6 +75,24 @@ __device__ inline double dpp_rows_d(double v) {
   const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)((unsigned long long)b >> 32), CTRL, ROWS, 0xf, true);
   return __longlong_as_double(((long long)(unsigned)hi << 32) | (unsigned)lo);
 }
+// lane R's value within each row of 16 lanes (DPP row_newbcast)
+__device__ inline double row_bcast16(double v, int R) {
+  const long long b = __double_as_longlong(v);
+  int lo = (int)(unsigned)(b & 0xffffffff), hi = (int)(unsigned)((unsigned long long)b >> 32);
+#define MLH_BCAST16(n)                                             \
+  case n:                                                          \
+    lo = __builtin_amdgcn_update_dpp(0, lo, 0x150 + n, 0xf, 0xf, false); \
+    hi = __builtin_amdgcn_update_dpp(0, hi, 0x150 + n, 0xf, 0xf, false); \
+    break;
+  switch (R) {
+    MLH_BCAST16(0) MLH_BCAST16(1) MLH_BCAST16(2) MLH_BCAST16(3) MLH_BCAST16(4) MLH_BCAST16(5) MLH_BCAST16(6)
+    MLH_BCAST16(7) MLH_BCAST16(8) MLH_BCAST16(9) MLH_BCAST16(10) MLH_BCAST16(11) MLH_BCAST16(12) MLH_BCAST16(13)
+    MLH_BCAST16(14) MLH_BCAST16(15)
+  }
+#undef MLH_BCAST16
+  return __longlong_as_double(((long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
 // sum of v over the wavefront, returned in every lane (wave-uniform)
 __device__ inline double wave64_sum(double v) {
   v = row16_sum(v);                   // lane 15 of each row: the row's sum
@@ -438,19 +456,29 @@ __global__ __launch_bounds__(kHqRhsWaves * 64) void hq_rhs_kernel(const HqDesc* 
                                                                 : make_double2(0.0, 0.0);
     }
     __syncthreads();
-    if (tid < kHqRhsCols) {
-      for (int r = nbb - 1; r >= 0; --r) {
-        double2 acc = Ys[(j0 + r) * kHqRhsCols + tid];
-        for (int q = r + 1; q < nbb; ++q) {
-          const double2 a = Rb[r][q], x = Ys[(j0 + q) * kHqRhsCols + tid];
-          acc.x -= a.x * x.x - a.y * x.y;
-          acc.y -= a.x * x.y + a.y * x.x;
+    if (wave < kHqRhsCols / 4) {
+      // waves 0..3: lane 16 g + i holds row i of column 4 wave + g; row r's
+      // value is final at step r and reaches its column's other rows by a
+      // DPP broadcast within the row of 16 lanes
+      const int col = 4 * wave + (lane >> 4), ri = lane & 15;
+      double2 y = ri < nbb ? Ys[(j0 + ri) * kHqRhsCols + col] : make_double2(0.0, 0.0);
+      const double2 d = Rb[ri][ri];
+      const double dd = d.x * d.x + d.y * d.y;
+      const double2 inv = ri < nbb && dd != 0.0 ? make_double2(d.x / dd, -d.y / dd) : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int r = kHqNb - 1; r >= 0; --r) {
+        if (r >= nbb) continue;  // uniform
+        const double2 xl = make_double2(y.x * inv.x - y.y * inv.y, y.x * inv.y + y.y * inv.x);
+        const double xr = row_bcast16(xl.x, r), xi = row_bcast16(xl.y, r);
+        if (ri == r) {
+          y = make_double2(xr, xi);
+        } else if (ri < r) {
+          const double2 a = Rb[ri][r];
+          y.x -= a.x * xr - a.y * xi;
+          y.y -= a.x * xi + a.y * xr;
         }
-        const double2 d = Rb[r][r];
-        const double dd = d.x * d.x + d.y * d.y;
-        Ys[(j0 + r) * kHqRhsCols + tid] =
-            make_double2((acc.x * d.x + acc.y * d.y) / dd, (acc.y * d.x - acc.x * d.y) / dd);
       }
+      if (ri < nbb) Ys[(j0 + ri) * kHqRhsCols + col] = y;
     }
     __syncthreads();
     double xr[4], xi[4];
