@@ -951,20 +951,38 @@ __global__ __launch_bounds__(kRhsWaves * 64) void gje_rhs_kernel(const GjeDesc* 
         dst[kk] = ldc(W + (uint32_t)((k + min(kq, nb - 1)) * n + min(row, n - 1)));
       }
     };
-    if (s0 < nsteps)
+    // this lane's part of a step's interchange record, loaded a step ahead:
+    // the rows holding pivots 4 kk + lq, the pair count and pair tid / TC
+    struct PivInfo {
+      int prow[4], naff, pd, ps;
+    };
+    auto load_piv = [&](int sidx, PivInfo& pi) {
+      const auto piv = gmem(D.piv + (size_t)sidx * kGjePivStride);
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) pi.prow[kk] = piv[1 + 4 * kGjeNb + 4 * kk + lq];
+      pi.naff = piv[0];
+      const int t = min(tid / TC, 2 * kGjeNb - 1);
+      pi.pd = piv[1 + t];
+      pi.ps = piv[1 + 2 * kGjeNb + t];
+    };
+    PivInfo pcur;
+    if (s0 < nsteps) {
+      load_piv(s0, pcur);
 #pragma unroll
       for (int j = 0; j < PF; ++j) load_p(s0, j, pa[j]);
+    }
     __syncthreads();
     for (int sidx = s0; sidx < nsteps; ++sidx) {
       const int k = sidx * kGjeNb;
       const int nb = min(kGjeNb, n - k);
-      const auto piv = gmem(D.piv + (size_t)sidx * kGjePivStride);
+      const PivInfo pi = pcur;
+      if (sidx + 1 < nsteps) load_piv(sidx + 1, pcur);
       // 1. the pivot rows as the B operand (lane: row 4 kk + lq, column lr)
       double2 yb[4];
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
         const int q = 4 * kk + lq;
-        yb[kk] = (q < nb && cl) ? Y[piv[1 + 4 * kGjeNb + q]][lr] : make_double2(0.0, 0.0);
+        yb[kk] = (q < nb && cl) ? Y[pi.prow[kk]][lr] : make_double2(0.0, 0.0);
       }
       const bool owner = ((k / 16) % kRhsWaves) == wave;  // this wave holds the pivot block
       double2 ma[4];
@@ -974,16 +992,11 @@ __global__ __launch_bounds__(kRhsWaves * 64) void gje_rhs_kernel(const GjeDesc* 
         for (int kk = 0; kk < 4; ++kk) ma[kk] = gld(M1 + (size_t)(4 * kk + lq) * kGjeNb + lr);  // M1[lr][4 kk + lq]
       }
       //    interchanged rows that land below the pivot block
-      const int naff = piv[0];
       int dA = -1;
       double2 vA = make_double2(0.0, 0.0);
-      if (tid < naff * TC) {
-        const int t = tid / TC, c = tid % TC;
-        const int d = piv[1 + t];
-        if (d >= k + nb) {
-          dA = d;
-          vA = Y[piv[1 + 2 * kGjeNb + t]][c];
-        }
+      if (tid < pi.naff * TC && pi.pd >= k + nb) {
+        dA = pi.pd;
+        vA = Y[pi.ps][tid % TC];
       }
       __syncthreads();
       // 2.
