@@ -533,14 +533,17 @@ __device__ __forceinline__ void panel_body(const GjeDesc* __restrict__ descs, in
       for (int h = 0; h < G; ++h) {
         const int rb = b0 + h * (NW - 2);
         if (rb >= nrb) break;
+        // V - P Z in three real products: V.r - K1 + K3, V.i - K1 - K2
+        dvec4 k1 = {0, 0, 0, 0};
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
           const double2 a = pa[h][kk], b = zs[4 * kk + lq][lr];
-          vr[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.x, b.x, vr[h], 0, 0, 0);
-          vr[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, vr[h], 0, 0, 0);
-          vi[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.x, b.y, vi[h], 0, 0, 0);
-          vi[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.x, vi[h], 0, 0, 0);
+          k1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x + a.y, b.x, k1, 0, 0, 0);
+          vi[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.x, b.y - b.x, vi[h], 0, 0, 0);
+          vr[h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x + b.y, vr[h], 0, 0, 0);
         }
+        vr[h] -= k1;
+        vi[h] -= k1;
         if (lr < nb)
 #pragma unroll
           for (int q = 0; q < 4; ++q)
@@ -669,14 +672,18 @@ __device__ __forceinline__ void update_body(const GjeDesc* __restrict__ descs, i
         Vi[j][q] = v.y;
       }
     }
+    // three real products per complex one: V.r - K1 + K3, V.i - K1 - K2 with
+    // K1 = (Pr + Pi) Zr, K2 = Pr (Zi - Zr), K3 = Pi (Zr + Zi)
+    dvec4 k1 = {0, 0, 0, 0};
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
       const double2 a = P[j][kk], b = zs[4 * kk + lq][lr];
-      Vr[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.x, b.x, Vr[j], 0, 0, 0);
-      Vr[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.y, Vr[j], 0, 0, 0);
-      Vi[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.x, b.y, Vi[j], 0, 0, 0);
-      Vi[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.x, Vi[j], 0, 0, 0);
+      k1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x + a.y, b.x, k1, 0, 0, 0);
+      Vi[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.x, b.y - b.x, Vi[j], 0, 0, 0);
+      Vr[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x + b.y, Vr[j], 0, 0, 0);
     }
+    Vr[j] -= k1;
+    Vi[j] -= k1;
     if (lr < nc) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
