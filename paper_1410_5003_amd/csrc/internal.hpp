@@ -227,12 +227,19 @@ struct GemvDesc {
 
 void gje_init();
 void launch_gje_panel(const GjeDesc* d, int nbatch, int k, int max_n, hipStream_t st);
-// columns [k + NB + lo, k + NB + hi) of the diagonal blocks (hi may exceed n)
-void launch_gje_update(const GjeDesc* d, int nbatch, int k, int max_n, int lo, int hi, hipStream_t st);
+// step k on columns [min(k + NB + lo, n), k + NB + hi) of the diagonal
+// blocks (hi may exceed n); with max_col > 0 (orders up to the limit
+// gje_step_fits checks) the range runs on through the right-hand-side
+// columns, up to ncol, and max_col / max_rhs bound ncol and ncol - n
+void launch_gje_update(const GjeDesc* d, int nbatch, int k, int max_n, int lo, int hi, hipStream_t st,
+                       int max_col = 0, int max_rhs = 0);
 // panel k and the update of step k - 16 in one launch (orders up to the
-// limit gje_step_fits checks)
+// limit gje_step_fits checks); max_col > 0 as for launch_gje_update
 bool gje_step_fits(int max_n);
-void launch_gje_step(const GjeDesc* d, int nbatch, int k, int max_n, hipStream_t st);
+void launch_gje_step(const GjeDesc* d, int nbatch, int k, int max_n, hipStream_t st, int max_col = 0,
+                     int max_rhs = 0);
+// workgroups of the largest launch_gje_step of a level (one fits a compute unit)
+int gje_step_max_blocks(int nbatch, int max_n, int max_col, int max_rhs);
 // right-hand-side replay of steps [s0, s1); max_blocks > 0 caps the grid
 void launch_gje_premul(const GjeDesc* d, int nbatch, int max_n, hipStream_t st);
 void launch_gje_rhs(const GjeDesc* d, int nbatch, int max_rhs, int max_n, int s0, int s1, int max_blocks,

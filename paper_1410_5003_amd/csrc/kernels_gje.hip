@@ -577,14 +577,18 @@ constexpr int kUpdWideThreads = 1024;
 constexpr int kUpdWideWaves = kUpdWideThreads / 64;
 constexpr int kUpdWideCols = 32;
 
+// Step k on the columns from min(k + nb + lo, n) on: up to k + nb + hi
+// within the diagonal block, or with rhs through the right-hand-side
+// columns as well (Gauss-Jordan on [D | B] leaves D^{-1} B in place of B).
+// The columns [k + nb, k + nb + lo) of the block are the next panel's.
 __device__ __forceinline__ void update_body(const GjeDesc* __restrict__ descs, int k, int lo, int hi, int tx,
-                                            int b) {
+                                            int b, bool rhs) {
   const GjeDesc& D = descs[b];
   const int n = D.n;
   if (k >= n) return;
   const int nb = min(kGjeNb, n - k);
-  const int cend = min(n, k + nb + hi);
-  const int c0 = k + nb + lo + tx * kUpdCols;
+  const int cend = min(rhs ? D.ncol : n, k + nb + hi);
+  const int c0 = min(k + nb + lo, n) + tx * kUpdCols;
   if (c0 >= cend) return;
   const int nc = min(kUpdCols, cend - c0);
   const auto piv = gmem(D.piv + (size_t)(k / kGjeNb) * kGjePivStride);
@@ -697,8 +701,8 @@ __device__ __forceinline__ void update_body(const GjeDesc* __restrict__ descs, i
 }
 
 __global__ __launch_bounds__(kUpdWaves * 64) void gje_update_kernel(const GjeDesc* __restrict__ descs, int k, int lo,
-                                                                    int hi) {
-  update_body(descs, k, lo, hi, blockIdx.x, blockIdx.y);
+                                                                    int hi, int rhs) {
+  update_body(descs, k, lo, hi, blockIdx.x, blockIdx.y, rhs != 0);
 }
 
 // One launch per elimination step when every order is at most kUpdMaxN:
@@ -708,12 +712,12 @@ __global__ __launch_bounds__(kUpdWaves * 64) void gje_update_kernel(const GjeDes
 // needs neither a second stream nor events, and the panel workgroups, which
 // dispatch first, find their compute units free.
 __global__ __launch_bounds__(kUpdWaves * 64) void gje_step_kernel(const GjeDesc* __restrict__ descs, int nbatch,
-                                                                  int k, int utiles) {
+                                                                  int k, int utiles, int rhs) {
   if ((int)blockIdx.x < nbatch) {
     panel_body<kUpdWaves * 64, 1>(descs, k, blockIdx.x);
   } else {
     const int u = blockIdx.x - nbatch;
-    update_body(descs, k - kGjeNb, kGjeNb, 1 << 30, u % utiles, u / utiles);
+    update_body(descs, k - kGjeNb, kGjeNb, 1 << 30, u % utiles, u / utiles, rhs != 0);
   }
 }
 
@@ -1077,20 +1081,33 @@ void launch_gje_panel(const GjeDesc* d, int nbatch, int k, int max_n, hipStream_
     hipLaunchKernelGGL((gje_panel_kernel<512, 2>), dim3(nbatch), dim3(512), 0, st, d, k);
 }
 bool gje_step_fits(int max_n) { return max_n <= kUpdMaxN; }
-void launch_gje_step(const GjeDesc* d, int nbatch, int k, int max_n, hipStream_t st) {
+// widest column range of an update of step k from column min(k + 16 + lo, n)
+// on: the diagonal block, or with max_col > 0 the right-hand sides too (a
+// matrix of order below k + 16 + lo starts at its own n)
+static int update_width(int k, int max_n, int lo, int hi, int max_col, int max_rhs) {
+  if (max_col <= 0) return std::min(max_n - k - kGjeNb, hi) - lo;
+  return std::max(max_col - std::min(k + kGjeNb + lo, max_n), max_rhs);
+}
+int gje_step_max_blocks(int nbatch, int max_n, int max_col, int max_rhs) {
+  const int width = update_width(0, max_n, kGjeNb, 1 << 30, max_col, max_rhs);  // the update of step 0
+  return nbatch * (1 + (width > 0 ? (width - 1) / kUpdCols + 1 : 0));
+}
+void launch_gje_step(const GjeDesc* d, int nbatch, int k, int max_n, hipStream_t st, int max_col, int max_rhs) {
   if (nbatch <= 0 || max_n <= k) return;
-  // update of step k - 16: columns [k + 16, max_n)
-  const int width = k > 0 ? max_n - k - kGjeNb : 0;
+  // update of step k - 16: columns [k + 16, max_n), and the right-hand sides
+  const int width = k > 0 ? update_width(k - kGjeNb, max_n, kGjeNb, 1 << 30, max_col, max_rhs) : 0;
   const int utiles = width > 0 ? (width - 1) / kUpdCols + 1 : 0;
   hipLaunchKernelGGL(gje_step_kernel, dim3(nbatch * (1 + utiles)), dim3(kUpdWaves * 64), 0, st, d, nbatch, k,
-                     utiles > 0 ? utiles : 1);
+                     utiles > 0 ? utiles : 1, max_col > 0 ? 1 : 0);
 }
-void launch_gje_update(const GjeDesc* d, int nbatch, int k, int max_n, int lo, int hi, hipStream_t st) {
-  const int width = std::min(max_n - k - kGjeNb, hi) - lo;
+void launch_gje_update(const GjeDesc* d, int nbatch, int k, int max_n, int lo, int hi, hipStream_t st, int max_col,
+                       int max_rhs) {
+  const int width = update_width(k, max_n, lo, hi, max_col, max_rhs);
   if (nbatch > 0 && width > 0) {
     if (max_n <= kUpdMaxN) {
       const int tiles = (width - 1) / kUpdCols + 1;
-      hipLaunchKernelGGL(gje_update_kernel, dim3(tiles, nbatch), dim3(kUpdWaves * 64), 0, st, d, k, lo, hi);
+      hipLaunchKernelGGL(gje_update_kernel, dim3(tiles, nbatch), dim3(kUpdWaves * 64), 0, st, d, k, lo, hi,
+                         max_col > 0 ? 1 : 0);
     } else {
       const int tiles = (width - 1) / kUpdWideCols + 1;
       hipLaunchKernelGGL(gje_update_wide_kernel, dim3(tiles, nbatch), dim3(kUpdWideThreads), 0, st, d, k, lo, hi);

@@ -350,6 +350,7 @@ struct mlh_stack_s {
   // second stream of the Gauss-Jordan look-ahead and its dependency events
   hipStream_t aux_stream = nullptr;
   std::vector<hipEvent_t> evpool;
+  int num_cu = 0;  // compute units of the device
   std::vector<int64_t> g_sig;
 
   // solve workspace (reused across calls with the same batch size)
@@ -1364,6 +1365,7 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
       std::vector<GjeDesc> gje;  // orders <= kRhsMaxN16 first (size classes of the right-hand-side kernel)
       int maxn = 0, maxcol = 0, maxrhs = 0;
       int nsmall = 0, rhs_small = 0, rhs_large = 0;
+      bool rhs_in_step = false;  // right-hand sides eliminated with the matrix, no replay
       std::vector<GemmDesc> upd;
       int upd_tiles = 0;
       std::vector<GemvDesc> back;
@@ -1509,6 +1511,19 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
       }
       S_act = K;
     }
+    // Levels with few matrices: the compute units idle beside the panels,
+    // whose chain sets the pace, so the update workgroups of each step take
+    // the right-hand-side columns as well (Gauss-Jordan on [D | B]) in place
+    // of the replay after the last step, when every workgroup of a step
+    // launch finds a compute unit at once.
+    if (s->num_cu == 0) {
+      int dev = 0;
+      HIP_TRY(hipGetDevice(&dev));
+      HIP_TRY(hipDeviceGetAttribute(&s->num_cu, hipDeviceAttributeMultiprocessorCount, dev));
+    }
+    for (Level& lv : levels)
+      lv.rhs_in_step = gje_step_fits(lv.maxn) &&
+                       gje_step_max_blocks((int)lv.gje.size(), lv.maxn, lv.maxcol, lv.maxrhs) <= s->num_cu;
     // ---- upload descriptors
     size_t doff = 0;
     std::vector<char> hdesc;
@@ -1616,28 +1631,36 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
           // only, so it runs while the update of step s - 1 is in flight on
           // the second stream.
           const int nsteps = (lv.maxn + kGjeNb - 1) / kGjeNb;
+          const int rcol = lv.rhs_in_step ? lv.maxcol : 0;  // > 0: the updates take the right-hand sides
           if (prof) {  // one stream, every launch timed on its own
             for (int k = 0; k < lv.maxn; k += kGjeNb) {
               tb(&prof->gje_panel_ms);
               launch_gje_panel(dg, ng, k, lv.maxn, ls);
               te();
               tb(&prof->gje_update_ms);
-              launch_gje_update(dg, ng, k, lv.maxn, kGjeNb, 1 << 30, ls);
+              launch_gje_update(dg, ng, k, lv.maxn, kGjeNb, 1 << 30, ls, rcol, lv.maxrhs);
               te();
               prof->n_gje_panel++;
               prof->n_gje_update++;
             }
-            tb(&prof->gje_rhs_ms);
-            launch_gje_premul(dg, ng, lv.maxn, ls);
-            launch_gje_rhs(dg, lv.nsmall, lv.rhs_small, kRhsMaxN16, 0, nsteps, 0, ls);
-            launch_gje_rhs(dg + lv.nsmall, ng - lv.nsmall, lv.rhs_large, lv.maxn, 0, nsteps, 0, ls);
-            te();
+            if (!lv.rhs_in_step) {
+              tb(&prof->gje_rhs_ms);
+              launch_gje_premul(dg, ng, lv.maxn, ls);
+              launch_gje_rhs(dg, lv.nsmall, lv.rhs_small, kRhsMaxN16, 0, nsteps, 0, ls);
+              launch_gje_rhs(dg + lv.nsmall, ng - lv.nsmall, lv.rhs_large, lv.maxn, 0, nsteps, 0, ls);
+              te();
+            }
           } else if (gje_step_fits(lv.maxn)) {
             // one launch per step: panel s with the update of step s - 1
-            for (int st_i = 0; st_i < nsteps; ++st_i) launch_gje_step(dg, ng, st_i * kGjeNb, lv.maxn, ls);
-            launch_gje_premul(dg, ng, lv.maxn, ls);
-            launch_gje_rhs(dg, lv.nsmall, lv.rhs_small, kRhsMaxN16, 0, nsteps, 0, ls);
-            launch_gje_rhs(dg + lv.nsmall, ng - lv.nsmall, lv.rhs_large, lv.maxn, 0, nsteps, 0, ls);
+            for (int st_i = 0; st_i < nsteps; ++st_i)
+              launch_gje_step(dg, ng, st_i * kGjeNb, lv.maxn, ls, rcol, lv.maxrhs);
+            if (lv.rhs_in_step) {  // the last step on the right-hand sides
+              launch_gje_update(dg, ng, (nsteps - 1) * kGjeNb, lv.maxn, kGjeNb, 1 << 30, ls, rcol, lv.maxrhs);
+            } else {
+              launch_gje_premul(dg, ng, lv.maxn, ls);
+              launch_gje_rhs(dg, lv.nsmall, lv.rhs_small, kRhsMaxN16, 0, nsteps, 0, ls);
+              launch_gje_rhs(dg + lv.nsmall, ng - lv.nsmall, lv.rhs_large, lv.maxn, 0, nsteps, 0, ls);
+            }
           } else {
             hipEvent_t rest1 = nullptr, rest2 = nullptr;  // updates of steps s - 1, s - 2
             for (int st_i = 0; st_i < nsteps; ++st_i) {
@@ -1698,6 +1721,7 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
         sig.push_back((int64_t)lv.upd.size());
         sig.push_back(lv.backn);
         sig.push_back((int64_t)lv.back.size());
+        sig.push_back(lv.rhs_in_step ? 1 : 0);
       }
       if (!(s->gexec && s->g_sig == sig)) {
         if (s->gexec) {
