@@ -1514,8 +1514,8 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
     // Levels with few matrices: the compute units idle beside the panels,
     // whose chain sets the pace, so the update workgroups of each step take
     // the right-hand-side columns as well (Gauss-Jordan on [D | B]) in place
-    // of the replay after the last step, when every workgroup of a step
-    // launch finds a compute unit at once.
+    // of the replay after the last step, when a step launch needs little
+    // more than one workgroup per compute unit (a workgroup fills a unit).
     if (s->num_cu == 0) {
       int dev = 0;
       HIP_TRY(hipGetDevice(&dev));
@@ -1523,7 +1523,7 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
     }
     for (Level& lv : levels)
       lv.rhs_in_step = gje_step_fits(lv.maxn) &&
-                       gje_step_max_blocks((int)lv.gje.size(), lv.maxn, lv.maxcol, lv.maxrhs) <= s->num_cu;
+                       gje_step_max_blocks((int)lv.gje.size(), lv.maxn, lv.maxcol, lv.maxrhs) <= s->num_cu * 5 / 4;
     // ---- upload descriptors
     size_t doff = 0;
     std::vector<char> hdesc;
