@@ -825,36 +825,56 @@ __global__ __launch_bounds__(kUpdWideThreads) void gje_update_wide_kernel(const 
 }
 
 // y = g - U1 x1 - U2 x2 for right-hand-side column blockIdx.z, one workgroup
-// per 64 rows, four wavefronts split the columns of U1, U2
-__global__ __launch_bounds__(256) void gemv_step_kernel(const GemvDesc* __restrict__ descs) {
-  const GemvDesc& D = descs[blockIdx.y];
-  const int rc = blockIdx.z;
-  if (rc >= D.r) return;
-  const int row = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int wave = threadIdx.x >> 6;
-  const cplx* x1 = D.x1 + (size_t)rc * D.m1;
-  const cplx* x2 = D.x2 + (size_t)rc * D.m2;
-  __shared__ double2 part[4][64];
-  double2 acc = make_double2(0.0, 0.0);
-  if (row < D.n) {
-    for (int j = wave; j < D.m1; j += 4) {
-      const double2 u = gld(D.U1 + (size_t)j * D.n + row), x = gld(x1 + j);
-      acc.x += u.x * x.x - u.y * x.y;
-      acc.y += u.x * x.y + u.y * x.x;
+// per 64 rows; its sixteen wavefronts split the columns of U1, U2, each lane
+// with four column loads in flight (clamped rows, no branch), and the
+// partial sums meet in LDS
+constexpr int kGemvWaves = 16;
+
+__device__ __forceinline__ void gemv_cols(const cplx* U, const cplx* x, int m, int n, int row, int wave,
+                                          double2& a0, double2& a1) {
+  int j = wave;
+  for (; j + 3 * kGemvWaves < m; j += 4 * kGemvWaves) {
+    double2 u[4], xv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      u[q] = ldc(U + (size_t)(j + q * kGemvWaves) * n + row);
+      xv[q] = ldc(x + j + q * kGemvWaves);
     }
-    for (int j = wave; j < D.m2; j += 4) {
-      const double2 u = gld(D.U2 + (size_t)j * D.n + row), x = gld(x2 + j);
-      acc.x += u.x * x.x - u.y * x.y;
-      acc.y += u.x * x.y + u.y * x.x;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double2& a = (q & 1) ? a1 : a0;
+      a.x += u[q].x * xv[q].x - u[q].y * xv[q].y;
+      a.y += u[q].x * xv[q].y + u[q].y * xv[q].x;
     }
   }
-  part[wave][threadIdx.x & 63] = acc;
+  for (; j < m; j += kGemvWaves) {
+    const double2 u = ldc(U + (size_t)j * n + row), xv = ldc(x + j);
+    a0.x += u.x * xv.x - u.y * xv.y;
+    a0.y += u.x * xv.y + u.y * xv.x;
+  }
+}
+
+__global__ __launch_bounds__(kGemvWaves * 64) void gemv_step_kernel(const GemvDesc* __restrict__ descs) {
+  const GemvDesc& D = descs[blockIdx.y];
+  const int rc = blockIdx.z;
+  if (rc >= D.r || D.n <= 0) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row = blockIdx.x * 64 + lane;
+  const int rr = min(row, D.n - 1);  // rows past n compute a copy of the last and store nothing
+  __shared__ double2 part[kGemvWaves][64];
+  double2 a0 = make_double2(0.0, 0.0), a1 = make_double2(0.0, 0.0);
+  if (blockIdx.x * 64 < D.n) {
+    gemv_cols(D.U1, D.x1 + (size_t)rc * D.m1, D.m1, D.n, rr, wave, a0, a1);
+    gemv_cols(D.U2, D.x2 + (size_t)rc * D.m2, D.m2, D.n, rr, wave, a0, a1);
+  }
+  part[wave][lane] = make_double2(a0.x + a1.x, a0.y + a1.y);
   __syncthreads();
   if (wave == 0 && row < D.n) {
     double2 s = gld(D.g + (size_t)rc * D.n + row);
-    for (int w = 0; w < 4; ++w) {
-      s.x -= part[w][threadIdx.x].x;
-      s.y -= part[w][threadIdx.x].y;
+#pragma unroll
+    for (int w = 0; w < kGemvWaves; ++w) {
+      s.x -= part[w][lane].x;
+      s.y -= part[w][lane].y;
     }
     gst(D.y + (size_t)rc * D.n + row, s);
   }
@@ -1135,7 +1155,8 @@ void launch_gje_rhs(const GjeDesc* d, int nbatch, int max_rhs, int max_n, int s0
 }
 void launch_gemv_step(const GemvDesc* d, int nbatch, int max_n, int max_r, hipStream_t st) {
   if (nbatch > 0 && max_n > 0 && max_r > 0)
-    hipLaunchKernelGGL(gemv_step_kernel, dim3((max_n + 63) / 64, nbatch, max_r), dim3(256), 0, st, d);
+    hipLaunchKernelGGL(gemv_step_kernel, dim3((max_n + 63) / 64, nbatch, max_r), dim3(kGemvWaves * 64), 0, st,
+                       d);
 }
 
 }  // namespace mlh
