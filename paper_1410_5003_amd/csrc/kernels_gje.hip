@@ -350,17 +350,29 @@ __device__ __forceinline__ void panel_body(const GjeDesc* __restrict__ descs, in
       for (int i = 0; i < 4; ++i) {
         const int r0 = k + sl * NT + wave * 64 + i * 16;
         if (r0 >= n) break;
-        dvec4 accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
+        // three real products per complex one: re = K1 - K3, im = K1 + K2
+        // with K1 = (Ar + Ai) Br, K2 = Ar (Bi - Br), K3 = Ai (Br + Bi); K2
+        // goes on top of K1 in a second pass, so that two accumulators suffice
+        double2 a[4];
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
           const int row = r0 + lr;
-          const double2 a = sl == 0 ? pa[i][kk]
-                                    : (row < n ? gld(W + (size_t)(kp + 4 * kk + lq) * n + row) : make_double2(0.0, 0.0));
+          a[kk] = sl == 0 ? pa[i][kk]
+                          : (row < n ? gld(W + (size_t)(kp + 4 * kk + lq) * n + row) : make_double2(0.0, 0.0));
+        }
+        dvec4 accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
           const double2 b = zs[4 * kk + lq][lr];
-          accr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.x, accr, 0, 0, 0);
-          accr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, b.y, accr, 0, 0, 0);
-          acci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, b.y, acci, 0, 0, 0);
-          acci = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, b.x, acci, 0, 0, 0);
+          acci = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk].x + a[kk].y, b.x, acci, 0, 0, 0);
+          accr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a[kk].y, b.x + b.y, accr, 0, 0, 0);
+        }
+        accr += acci;
+        asm volatile("" ::: "memory");  // Z is read again below rather than held in registers
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const double2 b = zs[4 * kk + lq][lr];
+          acci = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk].x, b.y - b.x, acci, 0, 0, 0);
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) tile[wave][lq + 4 * q][lr] = make_double2(accr[q], acci[q]);
