@@ -481,17 +481,21 @@ __device__ __forceinline__ void panel_body(const GjeDesc* __restrict__ descs, in
     double2 x[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) x[q] = make_double2(g + 4 * q == c ? 1.0 : 0.0, 0.0);
+    // branch-free: each lane reads its four entries of the pivot column and
+    // keeps the updates of its rows that step r touches; rows that no lane
+    // of a quad can touch at step r are skipped at compile time
 #pragma unroll
     for (int r = 0; r < kGjeNb - 1; ++r) {
       const double2 xr = make_double2(quad_bcast(x[r / 4].x, r % 4), quad_bcast(x[r / 4].y, r % 4));
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
+        if (4 * q + 3 <= r) continue;
         const int i = g + 4 * q;
-        if (i > r) {
-          const double2 l = lu11[i][r];
-          x[q].x = __builtin_fma(-l.x, xr.x, __builtin_fma(l.y, xr.y, x[q].x));
-          x[q].y = __builtin_fma(-l.x, xr.y, __builtin_fma(-l.y, xr.x, x[q].y));
-        }
+        const double2 l = lu11[i][r];
+        const double tx = __builtin_fma(-l.x, xr.x, __builtin_fma(l.y, xr.y, x[q].x));
+        const double ty = __builtin_fma(-l.x, xr.y, __builtin_fma(-l.y, xr.x, x[q].y));
+        x[q].x = i > r ? tx : x[q].x;
+        x[q].y = i > r ? ty : x[q].y;
       }
     }
 #pragma unroll
@@ -501,14 +505,13 @@ __device__ __forceinline__ void panel_body(const GjeDesc* __restrict__ descs, in
       const double2 xr = make_double2(y.x * d.x - y.y * d.y, y.x * d.y + y.y * d.x);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
+        if (4 * q > r) continue;
         const int i = g + 4 * q;
-        if (i == r) {
-          x[q] = xr;
-        } else if (i < r) {
-          const double2 u = lu11[i][r];
-          x[q].x = __builtin_fma(-u.x, xr.x, __builtin_fma(u.y, xr.y, x[q].x));
-          x[q].y = __builtin_fma(-u.x, xr.y, __builtin_fma(-u.y, xr.x, x[q].y));
-        }
+        const double2 u = lu11[i][r];
+        const double tx = __builtin_fma(-u.x, xr.x, __builtin_fma(u.y, xr.y, x[q].x));
+        const double ty = __builtin_fma(-u.x, xr.y, __builtin_fma(-u.y, xr.x, x[q].y));
+        x[q].x = i == r ? xr.x : (i < r ? tx : x[q].x);
+        x[q].y = i == r ? xr.y : (i < r ? ty : x[q].y);
       }
     }
     cplx* M1 = D.M1 + (size_t)(k / kGjeNb) * kGjeNb * kGjeNb;
