@@ -60,10 +60,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void z
   const int row0 = (lt % G.tiles_m) * kGemmTile, col0 = (lt / G.tiles_m) * kGemmTile;
   __shared__ double Ar[kGK][kGemmTile + 1], Ai[kGK][kGemmTile + 1];
   __shared__ double Br[kGK][kGemmTile + 1], Bi[kGK][kGemmTile + 1];
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int lr = lane & 15, lq = lane >> 4;
   const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
   const int m = G.m, n = G.n, K1 = G.k, K = G.k + G.k2;
+  // 16 x 16 blocks of the wave that hold rows / columns of C (the ragged
+  // edge tiles and the narrow right-hand-side products leave the others out)
+  const bool rin[2] = {row0 + wm < m, row0 + wm + 16 < m};
+  const bool cin[2] = {col0 + wn < n, col0 + wn + 16 < n};
   dvec4 t1[2][2], t2[2][2], t3[2][2];
 #pragma unroll
   for (int b = 0; b < 2; ++b)
@@ -131,6 +135,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void z
       for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
+          if (!(rin[b] && cin[c])) continue;
           t1[b][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[b], br[c], t1[b][c], 0, 0, 0);
           t2[b][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[b], bi[c], t2[b][c], 0, 0, 0);
           t3[b][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(as[b], bs[c], t3[b][c], 0, 0, 0);
