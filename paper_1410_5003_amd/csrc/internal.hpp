@@ -197,6 +197,72 @@ __device__ __forceinline__ void stc(cplx* p, double re, double im) {
   *gmem(reinterpret_cast<gdouble2*>(p)) = v;
 }
 
+// Assembly of one kAsmTile-element tile by 256 threads: 8 elements per
+// thread, consecutive threads on consecutive rows.  Every source load of a thread is issued
+// before the first result is formed (clamped addresses, no branch), and the
+// indices are 32-bit: a job holds at most a few million elements, since the
+// block orders are bounded when the stack is validated.
+template <int NP, int B>  // NP source pieces, B elements of a thread in flight at once
+__device__ __forceinline__ void assemble_tile(const AsmJob& J, int base) {
+  const int rows = J.rows, total = rows * J.cols, lds = J.lds, ldd = J.ldd;
+#pragma unroll
+  for (int g = 0; g < kAsmTile / 256; g += B) {
+    uint32_t so[B], dofs[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      const int e = min(base + 256 * (g + u), total - 1);
+      const int c = e / rows, r = e - c * rows;
+      so[u] = (uint32_t)(c * lds + r);
+      dofs[u] = (uint32_t)(c * ldd + r);
+    }
+    double2 v[NP > 0 ? NP : 1][B];
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int u = 0; u < B; ++u) v[p][u] = ldc(J.src[p] + so[u]);
+#pragma unroll
+    for (int u = 0; u < B; ++u) {
+      if (base + 256 * (g + u) >= total) break;
+      double re = 0.0, im = 0.0;
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        re += J.coef[p].re * v[p][u].x - J.coef[p].im * v[p][u].y;
+        im += J.coef[p].re * v[p][u].y + J.coef[p].im * v[p][u].x;
+      }
+      stc(J.dst + dofs[u], re, im);
+    }
+  }
+}
+
+// tile `tile` of a job list (jobs ordered by tile_begin), thread t of 256,
+// B elements of the thread in flight at once
+template <int B>
+__device__ __forceinline__ void assemble_one(const AsmJob* __restrict__ jobs, int njobs, int tile, int t) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].tile_begin <= tile)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const AsmJob& J = jobs[lo];
+  const int base = (tile - J.tile_begin) * kAsmTile + t;
+  switch (J.npieces) {  // 0: a block of zeros
+    case 0:
+      assemble_tile<0, B>(J, base);
+      break;
+    case 1:
+      assemble_tile<1, B>(J, base);
+      break;
+    case 2:
+      assemble_tile<2, B>(J, base);
+      break;
+    default:
+      assemble_tile<3, B>(J, base);
+  }
+}
+
 constexpr int kGjeNb = 16;  // panel width
 constexpr int kGjeMaxN = 1024; // largest block order: the panel kernel holds 2 rows per thread (N_i <= 512)
 
@@ -268,7 +334,10 @@ struct HqDesc {
 };
 
 void launch_hq_prep(const HqDesc* d, int n, hipStream_t st);
-void launch_hq_panel(const HqDesc* d, int n, int k, hipStream_t st);
+// with asm_t1 > asm_t0 the launch also assembles tiles [asm_t0, asm_t1) of
+// asm_jobs (work independent of the layer solves)
+void launch_hq_panel(const HqDesc* d, int n, int k, hipStream_t st, const AsmJob* asm_jobs = nullptr,
+                     int asm_njobs = 0, int asm_t0 = 0, int asm_t1 = 0);
 void launch_hq_update(const HqDesc* d, int n, int k, int max_c, int max_rows, hipStream_t st);
 void launch_hq_rhs(const HqDesc* d, int n, int max_ncol, int max_c, int max_rows, hipStream_t st);
 

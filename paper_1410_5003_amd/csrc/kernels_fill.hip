@@ -212,59 +212,9 @@ __global__ __launch_bounds__(64) void alpert_kernel(const AlpertJob* __restrict_
   }
 }
 
-// one workgroup per kAsmTile elements of one job (jobs own whole tiles), so
-// the job is found once per workgroup; 8 elements per thread, consecutive
-// threads on consecutive rows.  Every source load of a thread is issued
-// before the first result is formed (clamped addresses, no branch), and the
-// indices are 32-bit: a job holds at most a few million elements, since the
-// block orders are bounded when the stack is validated.
-template <int NP>
-__device__ __forceinline__ void assemble_tile(const AsmJob& J, int base) {
-  constexpr int U = kAsmTile / 256;
-  const int rows = J.rows, total = rows * J.cols, lds = J.lds, ldd = J.ldd;
-  uint32_t so[U], dofs[U];
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int e = min(base + 256 * u, total - 1);
-    const int c = e / rows, r = e - c * rows;
-    so[u] = (uint32_t)(c * lds + r);
-    dofs[u] = (uint32_t)(c * ldd + r);
-  }
-  double2 v[NP > 0 ? NP : 1][U];
-#pragma unroll
-  for (int p = 0; p < NP; ++p)
-#pragma unroll
-    for (int u = 0; u < U; ++u) v[p][u] = ldc(J.src[p] + so[u]);
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    if (base + 256 * u >= total) break;
-    double re = 0.0, im = 0.0;
-#pragma unroll
-    for (int p = 0; p < NP; ++p) {
-      re += J.coef[p].re * v[p][u].x - J.coef[p].im * v[p][u].y;
-      im += J.coef[p].re * v[p][u].y + J.coef[p].im * v[p][u].x;
-    }
-    stc(J.dst + dofs[u], re, im);
-  }
-}
-
+// one workgroup per kAsmTile elements of one job (jobs own whole tiles)
 __global__ __launch_bounds__(256) void assemble_kernel(const AsmJob* __restrict__ jobs, int njobs, int tile0) {
-  const int tile = tile0 + (int)blockIdx.x;
-  const AsmJob& J = jobs[find_job(jobs, njobs, tile)];
-  const int base = (tile - J.tile_begin) * kAsmTile + (int)threadIdx.x;
-  switch (J.npieces) {  // 0: a block of zeros
-    case 0:
-      assemble_tile<0>(J, base);
-      break;
-    case 1:
-      assemble_tile<1>(J, base);
-      break;
-    case 2:
-      assemble_tile<2>(J, base);
-      break;
-    default:
-      assemble_tile<3>(J, base);
-  }
+  assemble_one<kAsmTile / 256>(jobs, njobs, tile0 + (int)blockIdx.x, (int)threadIdx.x);
 }
 
 __global__ void hankel_eval_kernel(const double* x, double* out, int n) {

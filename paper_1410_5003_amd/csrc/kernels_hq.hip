@@ -112,7 +112,17 @@ __device__ inline double wave64_sum(double v) {
 // column i into its Householder vector is deferred to the next pass, which
 // does not read that column.
 constexpr int kHqPanelThreads = 64 * kHqNb;
-__global__ __launch_bounds__(kHqPanelThreads) void hq_panel_kernel(const HqDesc* __restrict__ descs, int k) {
+// Workgroups from n on assemble tiles [asm_t0, asm_t1) of an independent
+// job list, four per workgroup, on the compute units the n panels leave
+// idle.
+__global__ __launch_bounds__(kHqPanelThreads) void hq_panel_kernel(const HqDesc* __restrict__ descs, int n, int k,
+                                                                   const AsmJob* __restrict__ asm_jobs,
+                                                                   int asm_njobs, int asm_t0, int asm_t1) {
+  if ((int)blockIdx.x >= n) {
+    const int t = asm_t0 + ((int)blockIdx.x - n) * (kHqPanelThreads / 256) + (int)(threadIdx.x >> 8);
+    if (t < asm_t1) assemble_one<kAsmTile / 512>(asm_jobs, asm_njobs, t, (int)(threadIdx.x & 255));
+    return;
+  }
   const HqDesc& D = descs[blockIdx.x];
   const int c = D.c, M = D.m + c;
   if (k >= c) return;
@@ -557,8 +567,12 @@ __global__ __launch_bounds__(kHqRhsWaves * 64) void hq_update_kernel(const HqDes
 void launch_hq_prep(const HqDesc* d, int n, hipStream_t st) {
   if (n > 0) hipLaunchKernelGGL(hq_prep_kernel, dim3(n), dim3(256), 0, st, d);
 }
-void launch_hq_panel(const HqDesc* d, int n, int k, hipStream_t st) {
-  if (n > 0) hipLaunchKernelGGL(hq_panel_kernel, dim3(n), dim3(kHqPanelThreads), 0, st, d, k);
+void launch_hq_panel(const HqDesc* d, int n, int k, hipStream_t st, const AsmJob* asm_jobs, int asm_njobs,
+                     int asm_t0, int asm_t1) {
+  const int extra = asm_t1 > asm_t0 ? (asm_t1 - asm_t0 + kHqPanelThreads / 256 - 1) / (kHqPanelThreads / 256) : 0;
+  if (n > 0)
+    hipLaunchKernelGGL(hq_panel_kernel, dim3(n + extra), dim3(kHqPanelThreads), 0, st, d, n, k, asm_jobs, asm_njobs,
+                       asm_t0, asm_t1);
 }
 void launch_hq_update(const HqDesc* d, int n, int k, int max_c, int max_rows, hipStream_t st) {
   const int tiles = (max_c - k - kHqNb + kHqRhsCols - 1) / kHqRhsCols;

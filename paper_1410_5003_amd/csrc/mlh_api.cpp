@@ -1178,9 +1178,15 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
     auto Ublk = [&](int b, int i) { return V[b].W[0][i] + (size_t)n[i] * (n[i] + nL0[i]); };
     auto Fcol = [&](int b, int i) { return V[b].W[0][i] + (size_t)n[i] * (n[i] + nL0[i] + nU0[i]); };
     // ---- descriptors
-    std::vector<AsmJob> asmj;
-    int64_t elems = 0;
-    auto asm_add = [&](cplx* dst, int ldd, int rows, int cols, int np, const cplx* const* src, int lds,
+    // two job lists: the least-squares inputs, which the layer solves wait
+    // for, and the blocks of the block-tridiagonal system, which only the
+    // Schur updates read (so they assemble inside the panel launches of the
+    // layer solves, on the compute units those leave idle)
+    struct AsmList {
+      std::vector<AsmJob> jobs;
+      int64_t tiles = 0;
+    } asm_ls, asm_blk;
+    auto asm_add = [&](AsmList& L, cplx* dst, int ldd, int rows, int cols, int np, const cplx* const* src, int lds,
                        const cplx* coef) {
       if (rows <= 0 || cols <= 0) return;
       AsmJob J{};
@@ -1194,9 +1200,9 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
         J.src[p] = src[p];
         J.coef[p] = coef[p];
       }
-      J.tile_begin = (int)elems;
-      elems += ((int64_t)rows * cols + kAsmTile - 1) / kAsmTile;
-      asmj.push_back(J);
+      J.tile_begin = (int)L.tiles;
+      L.tiles += ((int64_t)rows * cols + kAsmTile - 1) / kAsmTile;
+      L.jobs.push_back(J);
     };
     // C = C0 + alpha (A B + A2 B2); m x nn output, inner sizes k and k2
     auto gemm_add = [&](std::vector<GemmDesc>& vec, int& tiles, cplx* Cm, int ldc, const cplx* C0, int ldc0, int m,
@@ -1247,14 +1253,14 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
       for (int i = 0; i < I; ++i) {
         const size_t pe = (size_t)n[i] * n[i];
         const cplx* src[3] = {s->A_self[i], s->A_self[i] + pe, s->A_self[i] + 2 * pe};
-        asm_add(Dblk(b, i), n[i], n[i], n[i], 3, src, n[i], c3);
-        if (i > 0) asm_add(Fcol(b, i), n[i], n[i], rb, 0, src, n[i], c3);  // f_i = 0 below Gamma_1
+        asm_add(asm_blk, Dblk(b, i), n[i], n[i], n[i], 3, src, n[i], c3);
+        if (i > 0) asm_add(asm_blk, Fcol(b, i), n[i], n[i], rb, 0, src, n[i], c3);  // f_i = 0 below Gamma_1
         if (i + 1 < I) {
           const size_t pu = (size_t)n[i] * n[i + 1];
           const cplx* su[3] = {s->A_up[i], s->A_up[i] + pu, s->A_up[i] + 2 * pu};
-          asm_add(Ublk(b, i), n[i], n[i], n[i + 1], 3, su, n[i], c3);
+          asm_add(asm_blk, Ublk(b, i), n[i], n[i], n[i + 1], 3, su, n[i], c3);
           const cplx* sd[3] = {s->A_dn[i], s->A_dn[i] + pu, s->A_dn[i] + 2 * pu};
-          asm_add(Lblk(b, i + 1), n[i + 1], n[i + 1], n[i], 3, sd, n[i + 1], c3);
+          asm_add(asm_blk, Lblk(b, i + 1), n[i + 1], n[i + 1], n[i], 3, sd, n[i + 1], c3);
         }
       }
       for (int j = 0; j <= I; ++j) {
@@ -1264,28 +1270,28 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
         const int mw2 = 2 * s->Mw, mud2 = 2 * s->Mud;
         const size_t qe = (size_t)mw2 * P;
         const cplx* sq[2] = {s->Q[j], s->Q[j] + qe};
-        asm_add(v.S[j], M, mw2, P, 2, sq, mw2, cQ);
+        asm_add(asm_ls, v.S[j], M, mw2, P, 2, sq, mw2, cQ);
         if (j == 0 || j == I) {
           const cplx* vv[1] = {j == 0 ? s->V_U : s->V_D};
-          asm_add(v.S[j] + mw2, M, mud2, P, 1, vv, mud2, &one);
-          asm_add(v.S[j] + (size_t)P * M, M, mw2, nK, 0, vv, mud2, &one);
+          asm_add(asm_ls, v.S[j] + mw2, M, mud2, P, 1, vv, mud2, &one);
+          asm_add(asm_ls, v.S[j] + (size_t)P * M, M, mw2, nK, 0, vv, mud2, &one);
           const int ci = j == 0 ? 0 : I - 1;
           const size_t ce = (size_t)mw2 * n[ci];
           const cplx* cs = j == 0 ? s->C_own[0] : s->C_above[I];
           const cplx* sc[2] = {cs, cs + ce};
-          asm_add(v.RHS[j], M, mw2, n[ci], 2, sc, mw2, cC);
+          asm_add(asm_ls, v.RHS[j], M, mw2, n[ci], 2, sc, mw2, cC);
           const size_t ze = (size_t)mud2 * n[ci];
           const cplx* zb = j == 0 ? s->Z_U : s->Z_D;
           const cplx* sz[3] = {zb, zb + ze, zb + 2 * ze};
-          asm_add(v.RHS[j] + mw2, M, mud2, n[ci], 3, sz, mud2, c3);
-          asm_add(v.RHS[j] + m, M, c, n[ci], 0, sz, mud2, c3);
+          asm_add(asm_ls, v.RHS[j] + mw2, M, mud2, n[ci], 3, sz, mud2, c3);
+          asm_add(asm_ls, v.RHS[j] + m, M, c, n[ci], 0, sz, mud2, c3);
         } else {
           const size_t ea = (size_t)mw2 * n[j - 1], eo = (size_t)mw2 * n[j];
           const cplx* sa[2] = {s->C_above[j], s->C_above[j] + ea};
           const cplx* so[2] = {s->C_own[j], s->C_own[j] + eo};
-          asm_add(v.RHS[j], M, mw2, n[j - 1], 2, sa, mw2, cC);
-          asm_add(v.RHS[j] + (size_t)n[j - 1] * M, M, mw2, n[j], 2, so, mw2, cC);
-          asm_add(v.RHS[j] + m, M, c, nc, 0, sa, mw2, cC);
+          asm_add(asm_ls, v.RHS[j], M, mw2, n[j - 1], 2, sa, mw2, cC);
+          asm_add(asm_ls, v.RHS[j] + (size_t)n[j - 1] * M, M, mw2, n[j], 2, so, mw2, cC);
+          asm_add(asm_ls, v.RHS[j] + m, M, c, nc, 0, sa, mw2, cC);
         }
         HqDesc H{};
         H.A = v.S[j];
@@ -1539,7 +1545,8 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
     int* d_info = reinterpret_cast<int*>(dbase + oi);
     for (auto& lv : levels)
       for (auto& G : lv.gje) G.info = d_info;
-    const size_t o_asm = push(asmj.data(), sizeof(AsmJob) * asmj.size());
+    const size_t o_asm_ls = push(asm_ls.jobs.data(), sizeof(AsmJob) * asm_ls.jobs.size());
+    const size_t o_asm_blk = push(asm_blk.jobs.data(), sizeof(AsmJob) * asm_blk.jobs.size());
     const size_t o_gs = push(gs.data(), sizeof(GemmDesc) * gs.size());
     const size_t o_hq = push(hq.data(), sizeof(HqDesc) * hq.size());
     const size_t o_ang = push(angs.data(), sizeof(AngleDesc) * angs.size());
@@ -1588,8 +1595,14 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
       auto te = [&]() {
         if (prof) T.end();
       };
+      const AsmJob* d_blk = reinterpret_cast<AsmJob*>(dbase + o_asm_blk);
+      const int nblk = (int)asm_blk.jobs.size(), blk_tiles = (int)asm_blk.tiles;
+      // the blocks ride in the panel launches unless those do not run or
+      // every launch is timed on its own
+      const bool blk_in_panels = !prof && (stop_phase == 0 || stop_phase >= 2) && maxc > 0;
       tb(prof ? &prof->assemble_ms : nullptr);
-      launch_assemble(reinterpret_cast<AsmJob*>(dbase + o_asm), (int)asmj.size(), (int)elems, ls);
+      launch_assemble(reinterpret_cast<AsmJob*>(dbase + o_asm_ls), (int)asm_ls.jobs.size(), (int)asm_ls.tiles, ls);
+      if (!blk_in_panels) launch_assemble(d_blk, nblk, blk_tiles, ls);
       te();
       const AngleDesc* d_ang = reinterpret_cast<AngleDesc*>(dbase + o_ang);
       tb(prof ? &prof->rb_setup_ms : nullptr);
@@ -1601,9 +1614,12 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
         tb(prof ? &prof->ls_panel_ms : nullptr);
         launch_hq_prep(d_hq, nhq, ls);
         te();
-        for (int k = 0; k < maxc; k += kHqNb) {
+        const int npanels = (maxc + kHqNb - 1) / kHqNb;
+        const int per = blk_in_panels ? (blk_tiles + npanels - 1) / npanels : 0;
+        for (int k = 0, p = 0; k < maxc; k += kHqNb, ++p) {
           tb(prof ? &prof->ls_panel_ms : nullptr);
-          launch_hq_panel(d_hq, nhq, k, ls);
+          const int t0 = std::min(p * per, blk_tiles), t1 = std::min(t0 + per, blk_tiles);
+          launch_hq_panel(d_hq, nhq, k, ls, d_blk, nblk, t0, t1);
           te();
           tb(prof ? &prof->ls_update_ms : nullptr);
           launch_hq_update(d_hq, hq_small.n, k, hq_small.maxc, hq_small.maxrows, ls);
@@ -1708,7 +1724,7 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
     } else {
       // every launch shape of the sequence: a cached graph is replayed only
       // when all of them, and the workspace, are unchanged
-      std::vector<int64_t> sig = {nb, B, nang, rchunk, (int64_t)doff, (int64_t)(intptr_t)s->wmem, (int64_t)elems,
+      std::vector<int64_t> sig = {nb, B, nang, rchunk, (int64_t)doff, (int64_t)(intptr_t)s->wmem, asm_ls.tiles, asm_blk.tiles,
                                   gtiles, maxc, maxcols, maxncol, (int64_t)hq.size(), (int64_t)gs.size(),
                                   hq_small.n, hq_small.maxc, hq_small.maxncol, hq_large.maxc, hq_large.maxncol};
       for (const Level& lv : levels) {
