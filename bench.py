@@ -141,11 +141,16 @@ def algorithmic_work(desc):
 # dispatch of the run.  An entry counts only while its kernel source is the
 # one the counters were taken on (SHA-1 prefix of the file).
 MEASURED_TRAFFIC = {
-    ("config2_resolved", "gje_panel_kernel"): ("kernels_gje.hip", "cb6a6f453e23", 2138.1, 916.4),
-    ("config2_resolved", "gje_update_kernel"): ("kernels_gje.hip", "cb6a6f453e23", 21532.1, 14393.2),
-    ("config2_resolved", "gje_rhs_kernel"): ("kernels_gje.hip", "cb6a6f453e23", 352723.1, 57397.3),
-    ("config2_resolved", "hq_rhs_kernel"): ("kernels_hq.hip", "00415db21eaf", 482254.1, 95550.0),
-    ("config2_resolved", "zgemm_kernel"): ("kernels_linalg.hip", "7d8805564610", 1922451.0, 176303.5),
+    ("config2_resolved", "gje_panel_kernel"): ("kernels_gje.hip", "68c73f4e98d6", 2145.4, 916.4),
+    ("config2_resolved", "gje_update_kernel"): ("kernels_gje.hip", "68c73f4e98d6", 27095.3, 20031.1),
+    ("config2_resolved", "gje_rhs_kernel"): ("kernels_gje.hip", "68c73f4e98d6", 737302.7, 119824.8),
+    ("config2_resolved", "gemv_step_kernel"): ("kernels_gje.hip", "68c73f4e98d6", 58268.3, 58.0),
+    ("config2_resolved", "hq_rhs_kernel"): ("kernels_hq.hip", "587e0c87c801", 482000.1, 95550.0),
+    # the panel launches also carry the block-system assembly
+    ("config2_resolved", "hq_panel_kernel"): ("kernels_hq.hip", "587e0c87c801", 44978.2, 16454.9),
+    ("config2_resolved", "zgemm_kernel"): ("kernels_linalg.hip", "d1b9bb6bbf93", 2201941.4, 176307.9),
+    ("config2_resolved", "self_kernel"): ("kernels_fill.hip", "4354f724784b", 4415.6, 633750.0),
+    ("config2_resolved", "fill_kernel"): ("kernels_fill.hip", "4354f724784b", 16520.9, 1636550.0),
 }
 
 
