@@ -222,6 +222,9 @@ def main():
     ap.add_argument("--cpu-sample-layers", type=int, default=6)
     ap.add_argument("--plain-sample", type=int, default=4,
                     help="sweeps: angles timed one by one (refill + one-angle solve each)")
+    ap.add_argument("--autotune", choices=("auto", "on", "off"), default="auto",
+                    help="time the solve under candidate launch choices before the warmup and keep the "
+                         "fastest (auto: for one-angle steps; a sweep's candidates take minutes)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (calibrates the HBM "
                          "byte counters of a profiler against a known size) and exit")
@@ -255,6 +258,13 @@ def main():
     print("workload %s: I=%d n_tot=%d device MB %.1f angles %d distinct alpha %d" %
           (args.workload, desc.I, info["n_tot"], info["device_bytes"] / 2 ** 20, len(thetas), n_sys),
           file=sys.stderr, flush=True)
+    autotuned = args.autotune == "on" or (args.autotune == "auto" and not sweep)
+    if autotuned:  # outside the timed region
+        ta = time.perf_counter()
+        st.refill()
+        st.autotune(thetas, reps=3)
+        print("autotune %s in %.2f s" % (st.get_tuning(), time.perf_counter() - ta), file=sys.stderr, flush=True)
+    tuning = dict(st.get_tuning(), autotuned=autotuned)
     out = None
     for _ in range(warmup):
         st.refill()
@@ -291,6 +301,7 @@ def main():
         "flux_err_max": float(flux.max()),
         "phase_ms": {k: round(v, 4) for k, v in prof.items() if k.endswith("_ms")},
         "roofline": roof,
+        "tuning": tuning,
     }
     if sweep and args.plain_sample > 0:
         # the same angles solved one at a time, each with its own refill

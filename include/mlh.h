@@ -196,6 +196,45 @@ mlh_status mlh_profile_step(mlh_stack s, double theta, mlh_profile* out);
  * instrumented run is not graph-captured. */
 mlh_status mlh_profile_solve(mlh_stack s, int32_t n_angles, const double* theta, mlh_profile* out);
 
+/* Launch choices of the solve (the dense factorisations of Sec. 3.2-3.3
+ * and the batched sweep of Sec. 3.4).  None changes what is computed; the
+ * placement of the right-hand sides changes the rounding order only.
+ *   rhs_in_step_pct  a cyclic-reduction level eliminates its right-hand
+ *                    sides inside the Gauss-Jordan steps (no replay after
+ *                    the last step) when its widest step launch needs at
+ *                    most rhs_in_step_pct workgroups per 100 compute units;
+ *                    0 = never.  Range 0..1000.
+ *   ls_row_blocks    16-row blocks per wavefront of the least-squares
+ *                    right-hand-side kernels for layers of at most 384
+ *                    rows: 3 or 4 (larger layers always take 4).
+ *   gje_rhs_cols     columns per workgroup of the Gauss-Jordan replay for
+ *                    orders up to 608: 16 or 8 (larger orders take 8).
+ *   asm_in_panels    1: the block-system assembly runs inside the
+ *                    least-squares panel launches, on the compute units
+ *                    they leave idle; 0: in a launch of its own.
+ * A new stack starts with {300, 3, 16, 1}. */
+typedef struct {
+  int32_t rhs_in_step_pct;
+  int32_t ls_row_blocks;
+  int32_t gje_rhs_cols;
+  int32_t asm_in_panels;
+} mlh_tuning;
+
+/* Read or replace the stack's launch choices.  set: MLH_E_INVALID_ARG for a
+ * value outside the ranges above (the stack keeps its choices). */
+mlh_status mlh_stack_get_tuning(mlh_stack s, mlh_tuning* out);
+mlh_status mlh_stack_set_tuning(mlh_stack s, const mlh_tuning* t);
+
+/* Autotune: time mlh_solve of these n_angles angles (host array, as for
+ * mlh_solve) under candidate launch choices, one field at a time with the
+ * others at their best so far (every field's values above; rhs_in_step_pct
+ * from {0, 100, 150, 200, 300, 500, 1000}), taking the fastest of `reps` timed
+ * solves (reps >= 1) after one untimed solve per candidate; keep the
+ * fastest choices in the stack and return them in out (may be NULL).
+ * Errors: those of mlh_solve; the stack then keeps its previous choices. */
+mlh_status mlh_stack_autotune(mlh_stack s, int32_t n_angles, const double* theta, int32_t reps,
+                              mlh_tuning* out);
+
 const char* mlh_last_error(void);
 
 #ifdef __cplusplus

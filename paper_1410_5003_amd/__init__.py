@@ -14,7 +14,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from ._lib import (ABI_VERSION, MLH_IFACE_FOURIER, MLH_IFACE_POLYGON, PIECES, MlhError, check,
-                   dptr, iptr, lib, mlh_interface, mlh_profile, mlh_stack_desc)
+                   dptr, iptr, lib, mlh_interface, mlh_profile, mlh_stack_desc, mlh_tuning)
 
 __all__ = ["Context", "Stack", "SolveOutput", "MlhError", "lib"]
 
@@ -173,6 +173,30 @@ class Stack:
         p = mlh_profile()
         check(lib().mlh_profile_solve(self._h, th.size, dptr(th), C.byref(p)))
         return {name: getattr(p, name) for name, _ in p._fields_}
+
+    def get_tuning(self) -> dict:
+        """The stack's launch choices (see ``mlh_tuning`` in mlh.h)."""
+        t = mlh_tuning()
+        check(lib().mlh_stack_get_tuning(self._h, C.byref(t)))
+        return {name: getattr(t, name) for name, _ in t._fields_}
+
+    def set_tuning(self, **choices):
+        """Replace some of the launch choices; the others stay."""
+        cur = self.get_tuning()
+        unknown = set(choices) - set(cur)
+        if unknown:
+            raise KeyError("unknown launch choices: %s" % sorted(unknown))
+        cur.update(choices)
+        t = mlh_tuning(**{k: int(v) for k, v in cur.items()})
+        check(lib().mlh_stack_set_tuning(self._h, C.byref(t)))
+
+    def autotune(self, thetas, reps: int = 2) -> dict:
+        """Time solves of ``thetas`` under candidate launch choices, keep and
+        return the fastest."""
+        th = np.ascontiguousarray(np.atleast_1d(thetas), dtype=np.float64)
+        t = mlh_tuning()
+        check(lib().mlh_stack_autotune(self._h, th.size, dptr(th), int(reps), C.byref(t)))
+        return {name: getattr(t, name) for name, _ in t._fields_}
 
     def solve_partial(self, theta: float, stop_phase: int):
         """Inspection: run one angle up to a phase (1 assembly, 2 least squares,

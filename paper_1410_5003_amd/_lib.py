@@ -54,6 +54,11 @@ class mlh_profile(C.Structure):
          ("total_ms", C.c_double)]
 
 
+class mlh_tuning(C.Structure):
+    _fields_ = [("rhs_in_step_pct", C.c_int32), ("ls_row_blocks", C.c_int32), ("gje_rhs_cols", C.c_int32),
+                ("asm_in_panels", C.c_int32)]
+
+
 _lib = None
 
 # name -> (restype, argtypes)
@@ -80,6 +85,9 @@ SIGNATURES = {
                                        C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
     "mlh_profile_step": (C.c_int32, [C.c_void_p, C.c_double, C.c_void_p]),
     "mlh_profile_solve": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.c_void_p]),
+    "mlh_stack_get_tuning": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "mlh_stack_set_tuning": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "mlh_stack_autotune": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.c_int32, C.c_void_p]),
     "mlh_last_error": (C.c_char_p, []),
 }
 

@@ -308,8 +308,9 @@ void launch_gje_step(const GjeDesc* d, int nbatch, int k, int max_n, hipStream_t
 int gje_step_max_blocks(int nbatch, int max_n, int max_col, int max_rhs);
 // right-hand-side replay of steps [s0, s1); max_blocks > 0 caps the grid
 void launch_gje_premul(const GjeDesc* d, int nbatch, int max_n, hipStream_t st);
+// narrow: 8-column tiles at every order (else 16 up to kRhsMaxN16)
 void launch_gje_rhs(const GjeDesc* d, int nbatch, int max_rhs, int max_n, int s0, int s1, int max_blocks,
-                    hipStream_t st);
+                    hipStream_t st, bool narrow = false);
 void launch_gemv_step(const GemvDesc* d, int nbatch, int max_n, int max_r, hipStream_t st);
 
 }  // namespace mlh
@@ -338,7 +339,10 @@ void launch_hq_prep(const HqDesc* d, int n, hipStream_t st);
 // asm_jobs (work independent of the layer solves)
 void launch_hq_panel(const HqDesc* d, int n, int k, hipStream_t st, const AsmJob* asm_jobs = nullptr,
                      int asm_njobs = 0, int asm_t0 = 0, int asm_t1 = 0);
-void launch_hq_update(const HqDesc* d, int n, int k, int max_c, int max_rows, hipStream_t st);
-void launch_hq_rhs(const HqDesc* d, int n, int max_ncol, int max_c, int max_rows, hipStream_t st);
+// row_blocks: 16-row blocks per wavefront (3 or 4) for layers up to
+// kHqRhsSmallRows rows; larger layers always take 4
+void launch_hq_update(const HqDesc* d, int n, int k, int max_c, int max_rows, hipStream_t st, int row_blocks = 3);
+void launch_hq_rhs(const HqDesc* d, int n, int max_ncol, int max_c, int max_rows, hipStream_t st,
+                   int row_blocks = 3);
 
 }  // namespace mlh

@@ -1155,9 +1155,9 @@ void launch_gje_premul(const GjeDesc* d, int nbatch, int max_n, hipStream_t st) 
                        0, st, d);
 }
 void launch_gje_rhs(const GjeDesc* d, int nbatch, int max_rhs, int max_n, int s0, int s1, int max_blocks,
-                    hipStream_t st) {
+                    hipStream_t st, bool narrow) {
   if (nbatch <= 0 || max_rhs <= 0 || s1 <= s0) return;
-  const bool wide = max_n <= kRhsMaxN16;
+  const bool wide = max_n <= kRhsMaxN16 && !narrow;
   const int tiles_per = wide ? (max_rhs + 15) / 16 : (max_rhs + 7) / 8;
   const int total = nbatch * tiles_per;
   const int grid = max_blocks > 0 ? std::min(total, max_blocks) : total;

@@ -574,21 +574,21 @@ void launch_hq_panel(const HqDesc* d, int n, int k, hipStream_t st, const AsmJob
     hipLaunchKernelGGL(hq_panel_kernel, dim3(n + extra), dim3(kHqPanelThreads), 0, st, d, n, k, asm_jobs, asm_njobs,
                        asm_t0, asm_t1);
 }
-void launch_hq_update(const HqDesc* d, int n, int k, int max_c, int max_rows, hipStream_t st) {
+void launch_hq_update(const HqDesc* d, int n, int k, int max_c, int max_rows, hipStream_t st, int row_blocks) {
   const int tiles = (max_c - k - kHqNb + kHqRhsCols - 1) / kHqRhsCols;
   const size_t red = sizeof(double) * kHqRhsWaves * 2 * 4 * 64;
   if (n <= 0 || tiles <= 0) return;
-  if (max_rows <= kHqRhsSmallRows)
+  if (max_rows <= kHqRhsSmallRows && row_blocks == 3)
     hipLaunchKernelGGL(hq_update_kernel<3>, dim3(tiles, n), dim3(kHqRhsWaves * 64), red, st, d, k);
   else
     hipLaunchKernelGGL(hq_update_kernel<4>, dim3(tiles, n), dim3(kHqRhsWaves * 64), red, st, d, k);
 }
-void launch_hq_rhs(const HqDesc* d, int n, int max_ncol, int max_c, int max_rows, hipStream_t st) {
+void launch_hq_rhs(const HqDesc* d, int n, int max_ncol, int max_c, int max_rows, hipStream_t st, int row_blocks) {
   const int tiles = (max_ncol + kHqRhsCols - 1) / kHqRhsCols;
   const size_t red = sizeof(double) * 2 * kHqRhsWaves * 2 * 4 * 64;
   const size_t tile = sizeof(double2) * (size_t)max_c * kHqRhsCols;
   if (n <= 0 || tiles <= 0) return;
-  if (max_rows <= kHqRhsSmallRows)
+  if (max_rows <= kHqRhsSmallRows && row_blocks == 3)
     hipLaunchKernelGGL(hq_rhs_kernel<3>, dim3(tiles, n), dim3(kHqRhsWaves * 64), std::max(red, tile), st, d);
   else
     hipLaunchKernelGGL(hq_rhs_kernel<4>, dim3(tiles, n), dim3(kHqRhsWaves * 64), std::max(red, tile), st, d);

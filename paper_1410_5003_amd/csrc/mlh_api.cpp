@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cstdlib>
 #include <cmath>
 #include <cstdio>
@@ -309,6 +310,7 @@ struct Arena {
 // ---------------------------------------------------------------------------
 struct mlh_stack_s {
   mlh_ctx ctx = nullptr;
+  mlh_tuning tune{300, 3, 16, 1};  // launch choices (mlh_stack_set_tuning / mlh_stack_autotune)
   int I = 0, P = 0, Mw = 0, Mud = 0, K = 0, nK = 0;
   double d = 0, yU = 0, yD = 0, R = 0, mu = 1e-14;
   std::vector<double> k;
@@ -1520,16 +1522,18 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
     // Levels with few matrices: the compute units idle beside the panels,
     // whose chain sets the pace, so the update workgroups of each step take
     // the right-hand-side columns as well (Gauss-Jordan on [D | B]) in place
-    // of the replay after the last step, when a step launch needs little
-    // more than one workgroup per compute unit (a workgroup fills a unit).
+    // of the replay after the last step, when a step launch needs at most a
+    // few workgroups per compute unit (a workgroup fills a unit; the bound
+    // is a launch choice, 300 per 100 units unless tuned).
     if (s->num_cu == 0) {
       int dev = 0;
       HIP_TRY(hipGetDevice(&dev));
       HIP_TRY(hipDeviceGetAttribute(&s->num_cu, hipDeviceAttributeMultiprocessorCount, dev));
     }
     for (Level& lv : levels)
-      lv.rhs_in_step = gje_step_fits(lv.maxn) &&
-                       gje_step_max_blocks((int)lv.gje.size(), lv.maxn, lv.maxcol, lv.maxrhs) <= s->num_cu * 5 / 4;
+      lv.rhs_in_step =
+          gje_step_fits(lv.maxn) && (int64_t)gje_step_max_blocks((int)lv.gje.size(), lv.maxn, lv.maxcol, lv.maxrhs) *
+                                            100 <= (int64_t)s->num_cu * s->tune.rhs_in_step_pct;
     // ---- upload descriptors
     size_t doff = 0;
     std::vector<char> hdesc;
@@ -1599,7 +1603,7 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
       const int nblk = (int)asm_blk.jobs.size(), blk_tiles = (int)asm_blk.tiles;
       // the blocks ride in the panel launches unless those do not run or
       // every launch is timed on its own
-      const bool blk_in_panels = !prof && (stop_phase == 0 || stop_phase >= 2) && maxc > 0;
+      const bool blk_in_panels = s->tune.asm_in_panels && !prof && (stop_phase == 0 || stop_phase >= 2) && maxc > 0;
       tb(prof ? &prof->assemble_ms : nullptr);
       launch_assemble(reinterpret_cast<AsmJob*>(dbase + o_asm_ls), (int)asm_ls.jobs.size(), (int)asm_ls.tiles, ls);
       if (!blk_in_panels) launch_assemble(d_blk, nblk, blk_tiles, ls);
@@ -1622,13 +1626,15 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
           launch_hq_panel(d_hq, nhq, k, ls, d_blk, nblk, t0, t1);
           te();
           tb(prof ? &prof->ls_update_ms : nullptr);
-          launch_hq_update(d_hq, hq_small.n, k, hq_small.maxc, hq_small.maxrows, ls);
-          launch_hq_update(d_hq + hq_small.n, hq_large.n, k, hq_large.maxc, hq_large.maxrows, ls);
+          launch_hq_update(d_hq, hq_small.n, k, hq_small.maxc, hq_small.maxrows, ls, s->tune.ls_row_blocks);
+          launch_hq_update(d_hq + hq_small.n, hq_large.n, k, hq_large.maxc, hq_large.maxrows, ls,
+                           s->tune.ls_row_blocks);
           te();
         }
         tb(prof ? &prof->ls_rhs_ms : nullptr);
-        launch_hq_rhs(d_hq, hq_small.n, hq_small.maxncol, hq_small.maxc, hq_small.maxrows, ls);
-        launch_hq_rhs(d_hq + hq_small.n, hq_large.n, hq_large.maxncol, hq_large.maxc, hq_large.maxrows, ls);
+        launch_hq_rhs(d_hq, hq_small.n, hq_small.maxncol, hq_small.maxc, hq_small.maxrows, ls, s->tune.ls_row_blocks);
+        launch_hq_rhs(d_hq + hq_small.n, hq_large.n, hq_large.maxncol, hq_large.maxc, hq_large.maxrows, ls,
+                      s->tune.ls_row_blocks);
         te();
       }
       if (stop_phase == 0 || stop_phase >= 3) {
@@ -1648,6 +1654,7 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
           // the second stream.
           const int nsteps = (lv.maxn + kGjeNb - 1) / kGjeNb;
           const int rcol = lv.rhs_in_step ? lv.maxcol : 0;  // > 0: the updates take the right-hand sides
+          const bool narrow = s->tune.gje_rhs_cols == 8;
           if (prof) {  // one stream, every launch timed on its own
             for (int k = 0; k < lv.maxn; k += kGjeNb) {
               tb(&prof->gje_panel_ms);
@@ -1662,8 +1669,8 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
             if (!lv.rhs_in_step) {
               tb(&prof->gje_rhs_ms);
               launch_gje_premul(dg, ng, lv.maxn, ls);
-              launch_gje_rhs(dg, lv.nsmall, lv.rhs_small, kRhsMaxN16, 0, nsteps, 0, ls);
-              launch_gje_rhs(dg + lv.nsmall, ng - lv.nsmall, lv.rhs_large, lv.maxn, 0, nsteps, 0, ls);
+              launch_gje_rhs(dg, lv.nsmall, lv.rhs_small, kRhsMaxN16, 0, nsteps, 0, ls, narrow);
+              launch_gje_rhs(dg + lv.nsmall, ng - lv.nsmall, lv.rhs_large, lv.maxn, 0, nsteps, 0, ls, narrow);
               te();
             }
           } else if (gje_step_fits(lv.maxn)) {
@@ -1674,8 +1681,8 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
               launch_gje_update(dg, ng, (nsteps - 1) * kGjeNb, lv.maxn, kGjeNb, 1 << 30, ls, rcol, lv.maxrhs);
             } else {
               launch_gje_premul(dg, ng, lv.maxn, ls);
-              launch_gje_rhs(dg, lv.nsmall, lv.rhs_small, kRhsMaxN16, 0, nsteps, 0, ls);
-              launch_gje_rhs(dg + lv.nsmall, ng - lv.nsmall, lv.rhs_large, lv.maxn, 0, nsteps, 0, ls);
+              launch_gje_rhs(dg, lv.nsmall, lv.rhs_small, kRhsMaxN16, 0, nsteps, 0, ls, narrow);
+              launch_gje_rhs(dg + lv.nsmall, ng - lv.nsmall, lv.rhs_large, lv.maxn, 0, nsteps, 0, ls, narrow);
             }
           } else {
             hipEvent_t rest1 = nullptr, rest2 = nullptr;  // updates of steps s - 1, s - 2
@@ -1694,8 +1701,8 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
             }
             if (rest1) HIP_TRY(hipStreamWaitEvent(ls, rest1, 0));
             launch_gje_premul(dg, ng, lv.maxn, ls);
-            launch_gje_rhs(dg, lv.nsmall, lv.rhs_small, kRhsMaxN16, 0, nsteps, 0, ls);
-            launch_gje_rhs(dg + lv.nsmall, ng - lv.nsmall, lv.rhs_large, lv.maxn, 0, nsteps, 0, ls);
+            launch_gje_rhs(dg, lv.nsmall, lv.rhs_small, kRhsMaxN16, 0, nsteps, 0, ls, narrow);
+            launch_gje_rhs(dg + lv.nsmall, ng - lv.nsmall, lv.rhs_large, lv.maxn, 0, nsteps, 0, ls, narrow);
           }
           if (!lv.upd.empty()) {
             tb(prof ? &prof->sweep_gemm_ms : nullptr);
@@ -1726,7 +1733,9 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
       // when all of them, and the workspace, are unchanged
       std::vector<int64_t> sig = {nb, B, nang, rchunk, (int64_t)doff, (int64_t)(intptr_t)s->wmem, asm_ls.tiles, asm_blk.tiles,
                                   gtiles, maxc, maxcols, maxncol, (int64_t)hq.size(), (int64_t)gs.size(),
-                                  hq_small.n, hq_small.maxc, hq_small.maxncol, hq_large.maxc, hq_large.maxncol};
+                                  hq_small.n, hq_small.maxc, hq_small.maxncol, hq_large.maxc, hq_large.maxncol,
+                                  s->tune.rhs_in_step_pct, s->tune.ls_row_blocks, s->tune.gje_rhs_cols,
+                                  s->tune.asm_in_panels};
       for (const Level& lv : levels) {
         sig.push_back(lv.maxn);
         sig.push_back(lv.maxcol);
@@ -1799,6 +1808,81 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
 extern "C" mlh_status mlh_solve(mlh_stack s, int32_t n_angles, const double* theta, double* aU, double* aD,
                                 int32_t* orders, double* flux_err) {
   return solve_impl(s, n_angles, theta, aU, aD, orders, flux_err, 0);
+}
+
+// ---------------------------------------------------------------------------
+// launch choices and their autotuning
+// ---------------------------------------------------------------------------
+static bool tuning_valid(const mlh_tuning& t) {
+  return t.rhs_in_step_pct >= 0 && t.rhs_in_step_pct <= 1000 && (t.ls_row_blocks == 3 || t.ls_row_blocks == 4) &&
+         (t.gje_rhs_cols == 16 || t.gje_rhs_cols == 8) && (t.asm_in_panels == 0 || t.asm_in_panels == 1);
+}
+
+extern "C" mlh_status mlh_stack_get_tuning(mlh_stack s, mlh_tuning* out) {
+  if (!s || !out) return fail(MLH_E_INVALID_ARG, "mlh_stack_get_tuning: NULL argument");
+  *out = s->tune;
+  return MLH_OK;
+}
+
+extern "C" mlh_status mlh_stack_set_tuning(mlh_stack s, const mlh_tuning* t) {
+  if (!s || !t) return fail(MLH_E_INVALID_ARG, "mlh_stack_set_tuning: NULL argument");
+  if (!tuning_valid(*t)) return fail(MLH_E_INVALID_ARG, "mlh_stack_set_tuning: value out of range");
+  s->tune = *t;
+  return MLH_OK;
+}
+
+// One pass of coordinate descent over the fields, each candidate timed as
+// whole mlh_solve calls (host planning, graph launch and result copy: what
+// a caller waits for), fastest of `reps` after one untimed solve that also
+// captures the candidate's graph.
+extern "C" mlh_status mlh_stack_autotune(mlh_stack s, int32_t n_angles, const double* theta, int32_t reps,
+                                         mlh_tuning* out) {
+  if (!s || !theta || n_angles < 1 || reps < 1) return fail(MLH_E_INVALID_ARG, "mlh_stack_autotune: bad arguments");
+  const mlh_tuning start = s->tune;
+  const size_t nc = (size_t)2 * s->nK * n_angles;
+  std::vector<double> aU(nc), aD(nc);
+  auto time_of = [&](const mlh_tuning& t, double& best) -> mlh_status {
+    s->tune = t;
+    MLH_TRY(solve_impl(s, n_angles, theta, aU.data(), aD.data(), nullptr, nullptr, 0));
+    best = 1e300;
+    for (int r = 0; r < reps; ++r) {
+      const auto t0 = std::chrono::steady_clock::now();
+      MLH_TRY(solve_impl(s, n_angles, theta, aU.data(), aD.data(), nullptr, nullptr, 0));
+      best = std::min(best, std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+    }
+    return MLH_OK;
+  };
+  mlh_tuning best_t = start;
+  double best = 0;
+  mlh_status r = time_of(best_t, best);
+  const int pct[] = {0, 100, 150, 200, 300, 500, 1000};
+  const int rows[] = {3, 4};
+  const int cols[] = {16, 8};
+  const int asmp[] = {1, 0};
+  auto sweep = [&](int32_t mlh_tuning::*field, const int* vals, int nv) {
+    for (int i = 0; i < nv && r == MLH_OK; ++i) {
+      mlh_tuning t = best_t;
+      t.*field = vals[i];
+      if (t.*field == best_t.*field) continue;
+      double ti = 0;
+      r = time_of(t, ti);
+      if (r == MLH_OK && ti < best) {
+        best = ti;
+        best_t = t;
+      }
+    }
+  };
+  sweep(&mlh_tuning::rhs_in_step_pct, pct, 7);
+  sweep(&mlh_tuning::ls_row_blocks, rows, 2);
+  sweep(&mlh_tuning::gje_rhs_cols, cols, 2);
+  sweep(&mlh_tuning::asm_in_panels, asmp, 2);
+  if (r != MLH_OK) {
+    s->tune = start;
+    return r;
+  }
+  s->tune = best_t;
+  if (out) *out = best_t;
+  return MLH_OK;
 }
 
 // ---------------------------------------------------------------------------
