@@ -239,16 +239,38 @@ __global__ __launch_bounds__(512) void bragg_kernel(const AngleDesc* __restrict_
   for (int q0 = 0; q0 < nK; q0 += 64) {
     const int q = q0 + lane;
     double ur = 0.0, ui = 0.0, dr = 0.0, di = 0.0;
-    if (q < nK) {
-      for (int j = wave; j < n1; j += 8) {
-        const double2 x = ld2(A.X0 + (size_t)j * A.ldX0 + sc.P + q), e = ld2(A.eta0 + j);
-        ur -= x.x * e.x - x.y * e.y;
-        ui -= x.x * e.y + x.y * e.x;
+    // eight columns in flight per lane (clamped indices; lanes past nK
+    // compute a copy of the last order and store nothing)
+    const int qc = min(q, nK - 1);
+    constexpr int kU = 8;
+    for (int j0 = wave; j0 < n1; j0 += 8 * kU) {
+      double2 x[kU], e[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int j = min(j0 + 8 * u, n1 - 1);
+        x[u] = ld2(A.X0 + (size_t)j * A.ldX0 + sc.P + qc);
+        e[u] = ld2(A.eta0 + j);
       }
-      for (int j = wave; j < nI; j += 8) {
-        const double2 x = ld2(A.XI + (size_t)j * A.ldXI + sc.P + q), e = ld2(A.etaI + j);
-        dr -= x.x * e.x - x.y * e.y;
-        di -= x.x * e.y + x.y * e.x;
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const bool in = j0 + 8 * u < n1;
+        ur -= in ? x[u].x * e[u].x - x[u].y * e[u].y : 0.0;
+        ui -= in ? x[u].x * e[u].y + x[u].y * e[u].x : 0.0;
+      }
+    }
+    for (int j0 = wave; j0 < nI; j0 += 8 * kU) {
+      double2 x[kU], e[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int j = min(j0 + 8 * u, nI - 1);
+        x[u] = ld2(A.XI + (size_t)j * A.ldXI + sc.P + qc);
+        e[u] = ld2(A.etaI + j);
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const bool in = j0 + 8 * u < nI;
+        dr -= in ? x[u].x * e[u].x - x[u].y * e[u].y : 0.0;
+        di -= in ? x[u].x * e[u].y + x[u].y * e[u].x : 0.0;
       }
     }
     pu[wave][lane] = make_double2(ur, ui);
