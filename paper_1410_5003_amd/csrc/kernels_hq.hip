@@ -5,18 +5,21 @@
 // i.e. the QR factorisation of [Q; mu I] applied to [C; 0].
 //
 //   hq_prep_kernel     mu = mu_rel ||Q||_F and the mu I rows;
-//   hq_panel_kernel    Householder QR of a 16-column panel in LDS, and the
-//                      triangular factor T of its block reflector
-//                      H = I - V T V^H (compact WY form);
+//   hq_panel_kernel    Householder QR of a 16-column panel in LDS (one
+//                      wavefront per column), and the triangular factor T of
+//                      its block reflector H = I - V T V^H (compact WY form);
+//                      extra workgroups of the launch assemble independent
+//                      tiles on the compute units the panels leave idle;
 //   hq_update_kernel   the later columns of S: Y <- H^H Y = Y - V T^H (V^H Y),
-//                      32 columns per workgroup, one wavefront per column;
+//                      16 columns per workgroup of 8 wavefronts, the tile in
+//                      registers in the matrix-core accumulator layout;
 //   hq_rhs_kernel      after the last panel, one workgroup per 16 right-hand
-//                      sides: the (M x 16) tile stays in LDS while every block
-//                      reflector is applied to it and R X = (Q^H C)[0:c] is
-//                      solved by 16-row blocks (substitution inside each
-//                      diagonal block, products on the FP64 matrix cores
-//                      elsewhere).  The right-hand sides cross HBM once
-//                      instead of once per panel.
+//                      sides: the (M x 16) tile stays in registers while
+//                      every block reflector is applied to it, and
+//                      R X = (Q^H C)[0:c] is solved by 16-row blocks in LDS
+//                      (substitution inside each diagonal block, products
+//                      on the FP64 matrix cores elsewhere).  The right-hand
+//                      sides cross HBM once instead of once per panel.
 #include <algorithm>
 
 #include "internal.hpp"
