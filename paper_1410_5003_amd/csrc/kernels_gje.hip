@@ -14,16 +14,23 @@
 //                      The multipliers of the update are the panel values
 //                      themselves (original values for rows >= k, current
 //                      values above k), read from W;
-//   gje_update_kernel  one workgroup per 32 trailing columns of the diagonal
-//                      block: applies the row swaps, Z = M1 Y(pivot rows),
+//   gje_update_kernel  one workgroup of 12 wavefronts per 16 trailing
+//                      columns (32 columns and 16 wavefronts above order
+//                      576): applies the row swaps, Z = M1 Y(pivot rows),
 //                      Y(other rows) -= P Z on the FP64 matrix cores,
-//                      Y(pivot rows) = Z.
-//   gje_rhs_kernel     after the last step: one workgroup per 16 (8 for
-//                      n > 608) right-hand-side columns keeps its tile in LDS and applies
-//                      every step's interchanges and update to it, reading the
-//                      multipliers P (the panel columns of W, unchanged after
-//                      their step) and M1 of each step.  The right-hand sides
-//                      thus cross HBM once instead of once per step.
+//                      Y(pivot rows) = Z; on levels with few matrices the
+//                      trailing columns run on through the right-hand sides;
+//   gje_step_kernel    panel k and the update of step k - NB in one launch
+//                      (disjoint columns);
+//   gje_premul_kernel  after the last step: P' = P M1 for every step, in
+//                      place;
+//   gje_rhs_kernel     then one workgroup per 16 (8 for n > 608) right-hand-
+//                      side columns keeps its tile in LDS and applies every
+//                      step's interchanges and Y -= P' Y(pivot rows) to it.
+//                      The right-hand sides thus cross HBM once instead of
+//                      once per step;
+//   gemv_step_kernel   back substitution of the cyclic reduction,
+//                      y = g - U1 x1 - U2 x2.
 #include <algorithm>
 
 #include "internal.hpp"
@@ -54,7 +61,7 @@ __device__ inline double2 cinv2(double2 a) {
 //  2. LU with partial pivoting of rows k..n-1.  Rows are not moved: a row
 //     that wins the pivot search for column c is marked and its values are
 //     staged in LDS, so each column costs one workgroup barrier.  Every wave
-//     reduces its candidates to one 64-bit key (high word of |a|^2, then the
+//     reduces its candidates to one 32-bit key (|a|^2 to 2^-10, then the
 //     complemented row offset, so that ties go to the lowest row) with DPP
 //     moves; the candidate lanes form the reciprocal of their pivot while the
 //     reduction runs, and the winning lane stages it with its row.

@@ -1,8 +1,9 @@
 // Dense complex float64 linear algebra of the solve phase (Sec. 3):
 //
-//  zgemm_kernel     batched C += alpha A B on the FP64 matrix cores
-//                   (v_mfma_f64_16x16x4f64, four real products per complex
-//                   product); Schur updates eq. (74)-(78) and the sweep update.
+//  zgemm_kernel     batched C = C0 + alpha (A B + A2 B2) on the FP64 matrix
+//                   cores (v_mfma_f64_16x16x4f64, three real products per
+//                   complex product); Schur updates eq. (74)-(78) and the
+//                   sweep update.
 //                   Operand layout of the 16x16x4 f64 instruction: lane l holds
 //                   A[l%16][l/16] and B[l/16][l%16]; accumulator register r of
 //                   lane l holds D[l/16 + 4r][l%16].
