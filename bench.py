@@ -150,8 +150,8 @@ MEASURED_TRAFFIC = {
     # the panel launches also carry the block-system assembly
     ("config2_resolved", "hq_panel_kernel"): ("kernels_hq.hip", "0f7d417f547e", 44979.0, 16454.9),
     ("config2_resolved", "zgemm_kernel"): ("kernels_linalg.hip", "950c962799e9", 2202984.3, 176308.0),
-    ("config2_resolved", "self_kernel"): ("kernels_fill.hip", "4354f724784b", 4415.8, 633750.0),
-    ("config2_resolved", "fill_kernel"): ("kernels_fill.hip", "4354f724784b", 16515.2, 1636550.0),
+    ("config2_resolved", "self_kernel"): ("kernels_fill.hip", "a03388359e80", 4415.8, 633750.0),
+    ("config2_resolved", "fill_kernel"): ("kernels_fill.hip", "a03388359e80", 16515.2, 1636550.0),
 }
 
 

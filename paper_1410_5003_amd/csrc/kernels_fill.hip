@@ -17,6 +17,11 @@
 //                 Bloch phase), and the interpolated quantity is the density
 //                 times the graded Jacobian, so the stencil weights multiply
 //                 the node weights w_j.
+//  assemble_kernel  the blocks for one Bloch phase alpha as weighted sums of
+//                 the pieces (Sec. 3.4), one workgroup per 2048 elements; the
+//                 tile routine is shared with the least-squares panel
+//                 launches, which carry the blocks of the block-tridiagonal
+//                 system.
 #include <algorithm>
 
 #include "internal.hpp"
