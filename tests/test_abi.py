@@ -44,3 +44,29 @@ def test_no_oracle_import_in_product():
             if f.endswith((".py", ".cpp", ".hip", ".hpp", ".h")):
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, f
+
+
+def _header_struct_fields(name):
+    """Field names, in order, of `typedef struct { ... } name;` in mlh.h."""
+    src = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    m = re.search(r"typedef struct \{([^{}]*)\}\s*" + name + r"\s*;", src)
+    assert m, name
+    fields = []
+    for decl in m.group(1).split(";"):
+        decl = decl.strip()
+        if decl:
+            fields += [v.strip().lstrip("*") for v in decl.split(None, 1)[1].split(",")]
+    return fields
+
+
+@pytest.mark.parametrize("struct", ["mlh_tuning", "mlh_profile"])
+def test_binding_structs_follow_the_header(struct):
+    """ctypes mirrors of the header's structs: same fields in the same order
+    (a swapped pair would silently exchange two values across the boundary)."""
+    from paper_1410_5003_amd import _lib
+    assert [f for f, _ in getattr(_lib, struct)._fields_] == _header_struct_fields(struct)
+
+
+def test_tuning_struct_is_four_int32():
+    from paper_1410_5003_amd import _lib
+    assert ctypes.sizeof(_lib.mlh_tuning) == 16
