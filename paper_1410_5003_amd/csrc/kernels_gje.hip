@@ -1150,7 +1150,7 @@ void launch_gje_update(const GjeDesc* d, int nbatch, int k, int max_n, int lo, i
       const int tiles = (width - 1) / kUpdCols + 1;
       hipLaunchKernelGGL(gje_update_kernel, dim3(tiles, nbatch), dim3(kUpdWaves * 64), 0, st, d, k, lo, hi,
                          max_col > 0 ? 1 : 0);
-    } else {
+    } else {  // the diagonal block only: callers pass max_col > 0 only where gje_step_fits holds
       const int tiles = (width - 1) / kUpdWideCols + 1;
       hipLaunchKernelGGL(gje_update_wide_kernel, dim3(tiles, nbatch), dim3(kUpdWideThreads), 0, st, d, k, lo, hi);
     }
