@@ -80,3 +80,24 @@ def test_autotune_keeps_a_valid_choice_that_matches_oracle(ctx, case):
     g = st.solve([th])
     assert rel_amp_err(g.aU[0], g.aD[0], o.aU, o.aD) < TOL
     st.close()
+
+
+def test_batched_shared_alpha_angles_under_non_default_choices(ctx):
+    # three angles, two of them sharing alpha (kappa_0 one grid step apart),
+    # so one system carries two right-hand sides; every placement choice is
+    # off its default: replay after the last step with 8-column tiles, four
+    # row blocks, assembly in its own launch
+    import paper_1410_5003_amd as mlh
+    desc = workloads.small_stack(seed=6, I=4, N=77, P=45, M_w=35, M_ud=40, K=9)
+    g = 2 * np.pi / desc.d
+    k0 = float(np.cos(desc.thetas[0]) * desc.k[0])
+    th = -np.arccos(np.array([k0, k0 - g, 0.5 * k0]) / desc.k[0])
+    assert np.all(np.isfinite(th))
+    st = mlh.Stack(ctx, desc)
+    st.set_tuning(rhs_in_step_pct=0, gje_rhs_cols=8, ls_row_blocks=4, asm_in_panels=0)
+    out = st.solve(th)
+    for a, t in enumerate(th):
+        o = oracle.solve_stack(desc, theta=t)
+        assert np.array_equal(out.orders[a], o.orders)
+        assert rel_amp_err(out.aU[a], out.aD[a], o.aU, o.aD) < TOL
+    st.close()
