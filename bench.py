@@ -142,10 +142,10 @@ def algorithmic_work(desc):
 # dispatch of the run.  An entry counts only while its kernel source is the
 # one the counters were taken on (SHA-1 prefix of the file).
 MEASURED_TRAFFIC = {
-    ("config2_resolved", "gje_panel_kernel"): ("kernels_gje.hip", "f5eedecab3ae", 2145.4, 916.4),
-    ("config2_resolved", "gje_update_kernel"): ("kernels_gje.hip", "f5eedecab3ae", 34548.4, 27226.1),
-    ("config2_resolved", "gje_rhs_kernel"): ("kernels_gje.hip", "f5eedecab3ae", 958196.2, 154362.8),
-    ("config2_resolved", "gemv_step_kernel"): ("kernels_gje.hip", "f5eedecab3ae", 58267.9, 58.0),
+    ("config2_resolved", "gje_panel_kernel"): ("kernels_gje.hip", "9a80b99f7aea", 2145.4, 916.4),
+    ("config2_resolved", "gje_update_kernel"): ("kernels_gje.hip", "9a80b99f7aea", 34548.4, 27226.1),
+    ("config2_resolved", "gje_rhs_kernel"): ("kernels_gje.hip", "9a80b99f7aea", 958196.2, 154362.8),
+    ("config2_resolved", "gemv_step_kernel"): ("kernels_gje.hip", "9a80b99f7aea", 58267.9, 58.0),
     ("config2_resolved", "hq_rhs_kernel"): ("kernels_hq.hip", "0f7d417f547e", 482474.9, 95550.0),
     # the panel launches also carry the block-system assembly
     ("config2_resolved", "hq_panel_kernel"): ("kernels_hq.hip", "0f7d417f547e", 44979.0, 16454.9),
@@ -241,7 +241,7 @@ def main():
         print(json.dumps({"copy_probe_bytes": args.copy_probe, "copies": 3}), flush=True)
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
+        print("bench.py: the solver runs on one GPU (there is no multi-GPU path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

@@ -290,7 +290,7 @@ __device__ __forceinline__ void panel_body(const GjeDesc* __restrict__ descs, in
   }
   const int kp = k - kGjeNb;
   if (k > 0) {
-    // round 1: the previous step's interchanges and M1 (the old values of
+    // first load round: the previous step's interchanges and M1 (the old values of
     // our rows are in flight above)
     const auto pivp = gmem(D.piv + (size_t)(kp / kGjeNb) * kGjePivStride);
     const cplx* M1p = D.M1 + (size_t)(kp / kGjeNb) * kGjeNb * kGjeNb;
@@ -315,7 +315,7 @@ __device__ __forceinline__ void panel_body(const GjeDesc* __restrict__ descs, in
         }
     }
     __syncthreads();
-    // round 2: Y1 = the previous pivot rows after the interchanges, and the
+    // second load round: Y1 = the previous pivot rows after the interchanges, and the
     // rows the interchanges bring into our rows (all from rows kp..k-1)
     const int naff = snaff;
     if (tid < kGjeNb * kGjeNb) {
@@ -624,7 +624,7 @@ __device__ __forceinline__ void update_body(const GjeDesc* __restrict__ descs, i
   __shared__ double2 stage[2 * kGjeNb][kUpdCols];
   __shared__ double2 y1[kGjeNb][kUpdCols];
   __shared__ double2 zs[kGjeNb][kUpdCols];
-  // round 1
+  // first load round
   if (tid == 0) snaff = piv[0];
   if (tid < 2 * kGjeNb) {
     sdst[tid] = piv[1 + tid];
@@ -655,7 +655,7 @@ __device__ __forceinline__ void update_body(const GjeDesc* __restrict__ descs, i
     }
   }
   __syncthreads();
-  // round 2: the rows the interchanges move, and Y1 (the pivot rows after them)
+  // second load round: the rows the interchanges move, and Y1 (the pivot rows after them)
   const int naff = snaff;
   if (tid < naff) rowmap[sdst[tid]] = (short)tid;
   for (int e = tid; e < naff * kUpdCols; e += kUpdWaves * 64) {
