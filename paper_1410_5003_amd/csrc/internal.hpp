@@ -38,6 +38,7 @@ constexpr int kMaxLaunchBlocks = 1 << 22;
 
 constexpr int kFillTileM = 64;
 constexpr int kFillTileN = 4;
+constexpr int kSelfTile = 16;  // self blocks: 16 x 16 blocks of the upper triangle
 
 // self block of one interface: difference kernels at ka (above) and kb (below)
 struct SelfJob {
@@ -51,7 +52,7 @@ struct SelfJob {
   double ka, kb, d;
   cplx* out[3];   // pieces l = -1, 0, 1 (n x n, ld = n)
   int N;
-  int tile_begin, tiles_m;
+  int tile_begin, tiles_m;  // tiles_m: 16-node blocks per side (upper-triangle tiles)
 };
 
 // Alpert correction of one interface: aux invariants per (target, aux)

@@ -83,21 +83,31 @@ __global__ __launch_bounds__(256) void fill_kernel(const FillJob* __restrict__ j
   }
 }
 
+// Self blocks by pairs: entry (m, j) of copy l and entry (j, m) of copy -l
+// have the same distance, so one Hankel evaluation serves both.  Swapping
+// target and source negates both normal projections, which leaves S and T
+// and exchanges D with D* (the source weight becomes w_m); the Alpert window
+// is symmetric too.  Workgroups take the 16 x 16 blocks (bm, bn), bm <= bn,
+// of the upper triangle; thread t the pair (bm 16 + t % 16, bn 16 + t / 16),
+// and on a diagonal block only pairs with m <= j.
 __global__ __launch_bounds__(256) void self_kernel(const SelfJob* __restrict__ jobs, int njobs, int a, int tile0) {
   const int tile = tile0 + (int)blockIdx.x;
   const SelfJob& J = jobs[find_job(jobs, njobs, tile)];
   const int lt = tile - J.tile_begin;
-  const int tm = lt % J.tiles_m, tn = lt / J.tiles_m;
+  int bn = (int)((sqrt(8.0 * lt + 1.0) - 1.0) * 0.5);  // lt = bn (bn + 1) / 2 + bm, bm <= bn
+  while (bn * (bn + 1) / 2 > lt) --bn;
+  while ((bn + 1) * (bn + 2) / 2 <= lt) ++bn;
+  const int bm = lt - bn * (bn + 1) / 2;
   const int N = J.N;
-  const int m = tm * kFillTileM + (threadIdx.x & (kFillTileM - 1));
-  const int j = tn * kFillTileN + threadIdx.x / kFillTileM;
-  if (m >= N || j >= N) return;
+  const int m = bm * kSelfTile + (int)(threadIdx.x % kSelfTile);
+  const int j = bn * kSelfTile + (int)(threadIdx.x / kSelfTile);
+  if (m >= N || j >= N || m > j) return;
   const double tnx = J.nx[m], tny = J.ny[m];
   const double snx = J.nx[j], sny = J.ny[j];
   const double dy = J.y[m] - J.y[j];
   const double dx0 = J.x[m] - J.x[j];
   const double nn = tnx * snx + tny * sny;
-  const double w = J.w[j];
+  const double wj = J.w[j], wm = J.w[m];
   const int ld = 2 * N;
   // Alpert window: smooth curves exclude |J - m| < a over the extended index
   // J = j + l N; a cornered curve excludes, in copy l = 0 only, the nodes of
@@ -107,22 +117,21 @@ __global__ __launch_bounds__(256) void self_kernel(const SelfJob* __restrict__ j
   if (J.seg_lo) {
     same_seg = J.seg_lo[j] == J.seg_lo[m];
     const int len = J.seg_len[m];
-    const int dd = j >= m ? j - m : m - j;
+    const int dd = j - m;
     cyc = dd < len - dd ? dd : len - dd;
   }
   for (int l = -1; l <= 1; ++l) {
     const int off = j + l * N - m;
-    cplx D = {0, 0}, S = {0, 0}, T = {0, 0}, Ds = {0, 0};
+    Kern4 K = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
     const bool plain = J.seg_lo ? !(l == 0 && same_seg && cyc < a) : (off >= a || off <= -a);
     if (plain) {
       const double dx = dx0 - l * J.d;
       const double r2 = dx * dx + dy * dy;
-      const Kern4 K = lp_kernels_diff(J.ka, J.kb, r2, tnx * dx + tny * dy, snx * dx + sny * dy, nn);
-      D = {K.D.re * w, K.D.im * w};
-      S = {K.S.re * w, K.S.im * w};
-      T = {K.T.re * w, K.T.im * w};
-      Ds = {K.Ds.re * w, K.Ds.im * w};
+      K = lp_kernels_diff(J.ka, J.kb, r2, tnx * dx + tny * dy, snx * dx + sny * dy, nn);
     }
+    // (m, j) of copy l, source weight w_j
+    cplx D = {K.D.re * wj, K.D.im * wj}, S = {K.S.re * wj, K.S.im * wj};
+    cplx T = {K.T.re * wj, K.T.im * wj}, Ds = {K.Ds.re * wj, K.Ds.im * wj};
     if (l == 0 && j == m) {  // jump relations: -tau / +sigma
       D.re -= 1.0;
       Ds.re += 1.0;
@@ -132,6 +141,13 @@ __global__ __launch_bounds__(256) void self_kernel(const SelfJob* __restrict__ j
     store(o + (size_t)(N + j) * ld + m, S);
     store(o + (size_t)j * ld + N + m, T);
     store(o + (size_t)(N + j) * ld + N + m, Ds);
+    if (j != m) {  // (j, m) of copy -l: D and D* exchanged, source weight w_m
+      cplx* p = J.out[1 - l];
+      store(p + (size_t)m * ld + j, {K.Ds.re * wm, K.Ds.im * wm});
+      store(p + (size_t)(N + m) * ld + j, {K.S.re * wm, K.S.im * wm});
+      store(p + (size_t)m * ld + N + j, {K.T.re * wm, K.T.im * wm});
+      store(p + (size_t)(N + m) * ld + N + j, {K.D.re * wm, K.D.im * wm});
+    }
   }
 }
 

@@ -636,9 +636,9 @@ static void build_fill_tables(mlh_stack_s* s, std::vector<FillJob>& fj, std::vec
     S.N = s->N[i];
     const size_t pe = (size_t)s->n[i] * s->n[i];
     for (int l = 0; l < 3; ++l) S.out[l] = s->A_self[i] + l * pe;
-    S.tiles_m = (S.N + kFillTileM - 1) / kFillTileM;
+    S.tiles_m = (S.N + kSelfTile - 1) / kSelfTile;
     S.tile_begin = st;
-    st += S.tiles_m * ((S.N + kFillTileN - 1) / kFillTileN);
+    st += S.tiles_m * (S.tiles_m + 1) / 2;
     sj.push_back(S);
     AlpertJob A{};
     A.r2 = s->ar2[i];
