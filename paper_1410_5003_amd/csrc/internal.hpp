@@ -10,7 +10,10 @@ namespace mlh {
 // ---------------------------------------------------------------------------
 // fill jobs: one (target set) x (source set) block, up to three shifted pieces
 // ---------------------------------------------------------------------------
-enum FillKind : int { kFillLayerPotential = 0, kFillProxy = 1 };
+// kFillPair: the layer potentials between two curves in both directions at
+// once (targets on the first as the job's out, targets on the second as
+// out_t), one Hankel evaluation per pair and copy
+enum FillKind : int { kFillLayerPotential = 0, kFillProxy = 1, kFillPair = 2 };
 
 struct FillJob {
   const double* tx;
@@ -30,7 +33,14 @@ struct FillJob {
   double sshift[3];
   cplx* out[3];
   int Mt, Ns, ld, kind, npieces;
-  int tile_begin, tiles_m;
+  int tile_begin, tiles_m;  // kFillPair: 16 x 16 tiles, else kFillTileM x kFillTileN
+  // kFillPair only: the reverse block (targets = sources above), its pieces
+  // in reverse copy order, leading dimension, weights (of the targets above)
+  // and sign
+  cplx* out_t[3];
+  int ld_t;
+  const double* tw;
+  double scale_t;
 };
 
 // largest grid of one launch (workgroups); bigger launches are split

@@ -43,10 +43,47 @@ __device__ inline int find_job(const T* jobs, int njobs, int key) {
 
 __device__ inline void store(cplx* p, cplx v) { stc(p, v.re, v.im); }
 
+// Both neighbour blocks of a pair of curves from one Hankel evaluation per
+// (m, j, copy): entry (m, j) of copy p and entry (j, m) of copy 2 - p have the
+// same distance, and swapping target and source negates both normal
+// projections, which leaves S and T and exchanges D with D*.  16 x 16 tiles,
+// so that both blocks are written in runs of consecutive rows.
+__device__ __forceinline__ void fill_pair(const FillJob& J, int lt) {
+  const int tm = lt % J.tiles_m, tn = lt / J.tiles_m;
+  const int m = tm * kSelfTile + (int)(threadIdx.x % kSelfTile);
+  const int j = tn * kSelfTile + (int)(threadIdx.x / kSelfTile);
+  if (m >= J.Mt || j >= J.Ns) return;
+  const double tx = J.tx[m], ty = J.ty[m] + J.dy0, tnx = J.tnx[m], tny = J.tny[m];
+  const double sx = J.sx[j], sy = J.sy[j], snx = J.snx[j], sny = J.sny[j];
+  const double dy = ty - sy;
+  const double nn = tnx * snx + tny * sny;
+  const double w = J.sw[j] * J.scale, wt = J.tw[m] * J.scale_t;
+  const int ld = J.ld, ldt = J.ld_t;
+  for (int p = 0; p < J.npieces; ++p) {
+    const double dx = (tx - sx) + (J.tshift[p] - J.sshift[p]);
+    const double r2 = dx * dx + dy * dy;
+    const Kern4 K = lp_kernels(J.k, r2, tnx * dx + tny * dy, snx * dx + sny * dy, nn);
+    cplx* o = J.out[p];
+    store(o + (size_t)j * ld + m, {K.D.re * w, K.D.im * w});
+    store(o + (size_t)(J.Ns + j) * ld + m, {K.S.re * w, K.S.im * w});
+    store(o + (size_t)j * ld + J.Mt + m, {K.T.re * w, K.T.im * w});
+    store(o + (size_t)(J.Ns + j) * ld + J.Mt + m, {K.Ds.re * w, K.Ds.im * w});
+    cplx* q = J.out_t[J.npieces - 1 - p];
+    store(q + (size_t)m * ldt + j, {K.Ds.re * wt, K.Ds.im * wt});
+    store(q + (size_t)(J.Mt + m) * ldt + j, {K.S.re * wt, K.S.im * wt});
+    store(q + (size_t)m * ldt + J.Ns + j, {K.T.re * wt, K.T.im * wt});
+    store(q + (size_t)(J.Mt + m) * ldt + J.Ns + j, {K.D.re * wt, K.D.im * wt});
+  }
+}
+
 __global__ __launch_bounds__(256) void fill_kernel(const FillJob* __restrict__ jobs, int njobs, int tile0) {
   const int tile = tile0 + (int)blockIdx.x;
   const FillJob& J = jobs[find_job(jobs, njobs, tile)];
   const int lt = tile - J.tile_begin;
+  if (J.kind == kFillPair) {
+    fill_pair(J, lt);
+    return;
+  }
   const int tm = lt % J.tiles_m, tn = lt / J.tiles_m;
   const int m = tm * kFillTileM + (threadIdx.x & (kFillTileM - 1));
   const int j = tn * kFillTileN + threadIdx.x / kFillTileM;

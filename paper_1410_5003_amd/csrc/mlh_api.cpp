@@ -458,9 +458,10 @@ static void build_fill_tables(mlh_stack_s* s, std::vector<FillJob>& fj, std::vec
   const double d = s->d;
   int tiles = 0;
   auto add = [&](FillJob J) {
-    J.tiles_m = (J.Mt + kFillTileM - 1) / kFillTileM;
+    const int tm = J.kind == kFillPair ? kSelfTile : kFillTileM, tn = J.kind == kFillPair ? kSelfTile : kFillTileN;
+    J.tiles_m = (J.Mt + tm - 1) / tm;
     J.tile_begin = tiles;
-    tiles += J.tiles_m * ((J.Ns + kFillTileN - 1) / kFillTileN);
+    tiles += J.tiles_m * ((J.Ns + tn - 1) / tn);
     fj.push_back(J);
   };
   auto curve_src = [&](FillJob& J, int i) {
@@ -494,28 +495,23 @@ static void build_fill_tables(mlh_stack_s* s, std::vector<FillJob>& fj, std::vec
       J.out[l] = base + l * piece_elems;
     }
   };
-  // neighbour blocks A_{i,i+1} = -[...]^{k_{i+1}}, A_{i+1,i} = +[...]^{k_{i+1}}
+  // neighbour blocks A_{i,i+1} = -[...]^{k_{i+1}}, A_{i+1,i} = +[...]^{k_{i+1}},
+  // both from one job: A_{i+1,i} copy l is A_{i,i+1} copy -l transposed
   for (int i = 0; i + 1 < I; ++i) {
     FillJob J{};
     curve_tgt(J, i);
     curve_src(J, i + 1);
-    J.kind = kFillLayerPotential;
+    J.kind = kFillPair;
     J.k = s->k[i + 1];
     J.scale = -1.0;
     J.dy0 = s->curves[i].y0 - s->curves[i + 1].y0;
     J.ld = s->n[i];
     three(J, s->A_up[i], (size_t)s->n[i] * s->n[i + 1]);
+    J.ld_t = s->n[i + 1];
+    J.tw = s->gw[i];
+    J.scale_t = 1.0;
+    for (int l = 0; l < 3; ++l) J.out_t[l] = s->A_dn[i] + (size_t)l * s->n[i + 1] * s->n[i];
     add(J);
-    FillJob K{};
-    curve_tgt(K, i + 1);
-    curve_src(K, i);
-    K.kind = kFillLayerPotential;
-    K.k = s->k[i + 1];
-    K.scale = 1.0;
-    K.dy0 = s->curves[i + 1].y0 - s->curves[i].y0;
-    K.ld = s->n[i + 1];
-    three(K, s->A_dn[i], (size_t)s->n[i + 1] * s->n[i]);
-    add(K);
   }
   // proxy blocks B_{i,i} (layer above) and B_{i,i+1} (layer below, negated)
   for (int i = 0; i < I; ++i) {
