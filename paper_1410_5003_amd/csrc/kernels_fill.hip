@@ -208,7 +208,14 @@ __global__ __launch_bounds__(64) void alpert_kernel(const AlpertJob* __restrict_
   const int m_idx = seg ? m - s_lo : m;
   __shared__ cplx kv[kAlpertAux][4];
   __shared__ double tpos[kAlpertAux];
+  __shared__ double invden[kAlpertStencil];  // 1 / prod_{s != r} (r - s) of the Lagrange basis
   const int lane = threadIdx.x;
+  if (lane < kAlpertStencil) {
+    double den = 1.0;  // an integer below 16!, exact in double
+    for (int s = 0; s < kAlpertStencil; ++s)
+      if (s != lane) den *= (double)(lane - s);
+    invden[lane] = 1.0 / den;
+  }
   if (lane < kAlpertAux) {
     const size_t q = (size_t)m * kAlpertAux + lane;
     const Kern4 K = lp_kernels_diff(J.ka, J.kb, J.r2[q], J.nd[q], J.npd[q], J.nn[q]);
@@ -230,11 +237,9 @@ __global__ __launch_bounds__(64) void alpert_kernel(const AlpertJob* __restrict_
     const int j0 = (int)floor(t) - (kAlpertStencil / 2 - 1);
     const int r = Jx - j0;
     if (r < 0 || r >= kAlpertStencil) continue;
-    double L = 1.0;
-    for (int s = 0; s < kAlpertStencil; ++s) {
-      if (s == r) continue;
-      L *= (t - (double)(j0 + s)) / (double)(r - s);
-    }
+    double L = invden[r];
+    for (int s = 0; s < kAlpertStencil; ++s)
+      if (s != r) L *= t - (double)(j0 + s);
     any = true;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
