@@ -350,10 +350,13 @@ void launch_hq_prep(const HqDesc* d, int n, hipStream_t st);
 // asm_jobs (work independent of the layer solves)
 void launch_hq_panel(const HqDesc* d, int n, int k, hipStream_t st, const AsmJob* asm_jobs = nullptr,
                      int asm_njobs = 0, int asm_t0 = 0, int asm_t1 = 0);
-// row_blocks: 16-row blocks per wavefront (3 or 4) for layers up to
-// kHqRhsSmallRows rows; larger layers always take 4
-void launch_hq_update(const HqDesc* d, int n, int k, int max_c, int max_rows, hipStream_t st, int row_blocks = 3);
-void launch_hq_rhs(const HqDesc* d, int n, int max_ncol, int max_c, int max_rows, hipStream_t st,
+// One launch over both layer size classes: descs [0, n_small) have at most
+// kHqRhsSmallRows rows and take row_blocks (3 or 4) 16-row blocks per
+// wavefront, descs [n_small, n_small + n_large) always 4; max_c and max_ncol
+// are maxima over both classes
+void launch_hq_update(const HqDesc* d, int n_small, int n_large, int k, int max_c, hipStream_t st,
+                      int row_blocks = 3);
+void launch_hq_rhs(const HqDesc* d, int n_small, int n_large, int max_ncol, int max_c, hipStream_t st,
                    int row_blocks = 3);
 
 }  // namespace mlh

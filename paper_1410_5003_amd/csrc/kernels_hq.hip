@@ -420,10 +420,9 @@ __device__ __forceinline__ void hq_apply_panel(hvec4 (&yr)[kHqRhsRbw], hvec4 (&y
 // Tikhonov scale, so no explicit block inverse), the rows above updated on
 // the matrix cores.
 template <int kHqRhsRbw>  // row blocks per wave: 3 up to kHqRhsSmallRows rows, 4 up to kHqMaxRows
-__global__ __launch_bounds__(kHqRhsWaves * 64) void hq_rhs_kernel(const HqDesc* __restrict__ descs) {
-  const HqDesc& D = descs[blockIdx.y];
+__device__ __forceinline__ void hq_rhs_body(const HqDesc& D, int tx) {
   const int c = D.c, M = D.m + c;
-  const int col0 = blockIdx.x * kHqRhsCols;
+  const int col0 = tx * kHqRhsCols;
   if (col0 >= D.ncol) return;
   const int nc = min(kHqRhsCols, D.ncol - col0);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -528,16 +527,25 @@ __global__ __launch_bounds__(kHqRhsWaves * 64) void hq_rhs_kernel(const HqDesc* 
   }
 }
 
+// Both size classes in one launch: layers [0, n3) (at most kHqRhsSmallRows
+// rows, listed first) take three row blocks per wave, the others four, so
+// the few large layers do not wait for a launch of their own.
+__global__ __launch_bounds__(kHqRhsWaves * 64) void hq_rhs_kernel(const HqDesc* __restrict__ descs, int n3) {
+  if ((int)blockIdx.y < n3)
+    hq_rhs_body<3>(descs[blockIdx.y], blockIdx.x);
+  else
+    hq_rhs_body<4>(descs[blockIdx.y], blockIdx.x);
+}
+
 // The later columns of S for panel k: Y <- H^H Y on 16 columns per
 // workgroup, the tile in registers as in hq_rhs_kernel (rows below k only
 // are read back and changed).
 template <int kHqRhsRbw>
-__global__ __launch_bounds__(kHqRhsWaves * 64) void hq_update_kernel(const HqDesc* __restrict__ descs, int k) {
-  const HqDesc& D = descs[blockIdx.y];
+__device__ __forceinline__ void hq_update_body(const HqDesc& D, int k, int tx) {
   const int c = D.c, M = D.m + c;
   if (k >= c) return;
   const int nb = min(kHqNb, c - k);
-  const int c0 = k + nb + blockIdx.x * kHqRhsCols;
+  const int c0 = k + nb + tx * kHqRhsCols;
   if (c0 >= c) return;
   const int nc = min(kHqRhsCols, c - c0);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -567,6 +575,15 @@ __global__ __launch_bounds__(kHqRhsWaves * 64) void hq_update_kernel(const HqDes
       }
 }
 
+// both size classes in one launch, as for hq_rhs_kernel
+__global__ __launch_bounds__(kHqRhsWaves * 64) void hq_update_kernel(const HqDesc* __restrict__ descs, int k,
+                                                                     int n3) {
+  if ((int)blockIdx.y < n3)
+    hq_update_body<3>(descs[blockIdx.y], k, blockIdx.x);
+  else
+    hq_update_body<4>(descs[blockIdx.y], k, blockIdx.x);
+}
+
 void launch_hq_prep(const HqDesc* d, int n, hipStream_t st) {
   if (n > 0) hipLaunchKernelGGL(hq_prep_kernel, dim3(n), dim3(256), 0, st, d);
 }
@@ -577,24 +594,26 @@ void launch_hq_panel(const HqDesc* d, int n, int k, hipStream_t st, const AsmJob
     hipLaunchKernelGGL(hq_panel_kernel, dim3(n + extra), dim3(kHqPanelThreads), 0, st, d, n, k, asm_jobs, asm_njobs,
                        asm_t0, asm_t1);
 }
-void launch_hq_update(const HqDesc* d, int n, int k, int max_c, int max_rows, hipStream_t st, int row_blocks) {
+// One launch over both size classes: descs[0, n_small) have at most
+// kHqRhsSmallRows rows and take three row blocks per wave (unless
+// row_blocks is 4), descs[n_small, n_small + n_large) take four.
+void launch_hq_update(const HqDesc* d, int n_small, int n_large, int k, int max_c, hipStream_t st, int row_blocks) {
   const int tiles = (max_c - k - kHqNb + kHqRhsCols - 1) / kHqRhsCols;
   const size_t red = sizeof(double) * kHqRhsWaves * 2 * 4 * 64;
+  const int n = n_small + n_large;
   if (n <= 0 || tiles <= 0) return;
-  if (max_rows <= kHqRhsSmallRows && row_blocks == 3)
-    hipLaunchKernelGGL(hq_update_kernel<3>, dim3(tiles, n), dim3(kHqRhsWaves * 64), red, st, d, k);
-  else
-    hipLaunchKernelGGL(hq_update_kernel<4>, dim3(tiles, n), dim3(kHqRhsWaves * 64), red, st, d, k);
+  hipLaunchKernelGGL(hq_update_kernel, dim3(tiles, n), dim3(kHqRhsWaves * 64), red, st, d, k,
+                     row_blocks == 3 ? n_small : 0);
 }
-void launch_hq_rhs(const HqDesc* d, int n, int max_ncol, int max_c, int max_rows, hipStream_t st, int row_blocks) {
+void launch_hq_rhs(const HqDesc* d, int n_small, int n_large, int max_ncol, int max_c, hipStream_t st,
+                   int row_blocks) {
   const int tiles = (max_ncol + kHqRhsCols - 1) / kHqRhsCols;
   const size_t red = sizeof(double) * 2 * kHqRhsWaves * 2 * 4 * 64;
   const size_t tile = sizeof(double2) * (size_t)max_c * kHqRhsCols;
+  const int n = n_small + n_large;
   if (n <= 0 || tiles <= 0) return;
-  if (max_rows <= kHqRhsSmallRows && row_blocks == 3)
-    hipLaunchKernelGGL(hq_rhs_kernel<3>, dim3(tiles, n), dim3(kHqRhsWaves * 64), std::max(red, tile), st, d);
-  else
-    hipLaunchKernelGGL(hq_rhs_kernel<4>, dim3(tiles, n), dim3(kHqRhsWaves * 64), std::max(red, tile), st, d);
+  hipLaunchKernelGGL(hq_rhs_kernel, dim3(tiles, n), dim3(kHqRhsWaves * 64), std::max(red, tile), st, d,
+                     row_blocks == 3 ? n_small : 0);
 }
 
 }  // namespace mlh

@@ -1622,15 +1622,13 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
           launch_hq_panel(d_hq, nhq, k, ls, d_blk, nblk, t0, t1);
           te();
           tb(prof ? &prof->ls_update_ms : nullptr);
-          launch_hq_update(d_hq, hq_small.n, k, hq_small.maxc, hq_small.maxrows, ls, s->tune.ls_row_blocks);
-          launch_hq_update(d_hq + hq_small.n, hq_large.n, k, hq_large.maxc, hq_large.maxrows, ls,
+          launch_hq_update(d_hq, hq_small.n, hq_large.n, k, std::max(hq_small.maxc, hq_large.maxc), ls,
                            s->tune.ls_row_blocks);
           te();
         }
         tb(prof ? &prof->ls_rhs_ms : nullptr);
-        launch_hq_rhs(d_hq, hq_small.n, hq_small.maxncol, hq_small.maxc, hq_small.maxrows, ls, s->tune.ls_row_blocks);
-        launch_hq_rhs(d_hq + hq_small.n, hq_large.n, hq_large.maxncol, hq_large.maxc, hq_large.maxrows, ls,
-                      s->tune.ls_row_blocks);
+        launch_hq_rhs(d_hq, hq_small.n, hq_large.n, std::max(hq_small.maxncol, hq_large.maxncol),
+                      std::max(hq_small.maxc, hq_large.maxc), ls, s->tune.ls_row_blocks);
         te();
       }
       if (stop_phase == 0 || stop_phase >= 3) {
