@@ -143,15 +143,15 @@ def algorithmic_work(desc):
 # one the counters were taken on (SHA-1 prefix of the file).
 MEASURED_TRAFFIC = {
     ("config2_resolved", "gje_panel_kernel"): ("kernels_gje.hip", "9a80b99f7aea", 2145.4, 916.4),
-    ("config2_resolved", "gje_update_kernel"): ("kernels_gje.hip", "9a80b99f7aea", 34550.5, 27226.1),
-    ("config2_resolved", "gje_rhs_kernel"): ("kernels_gje.hip", "9a80b99f7aea", 958211.3, 154362.8),
-    ("config2_resolved", "gemv_step_kernel"): ("kernels_gje.hip", "9a80b99f7aea", 58269.4, 58.0),
-    ("config2_resolved", "hq_rhs_kernel"): ("kernels_hq.hip", "0f7d417f547e", 482330.5, 95550.0),
+    ("config2_resolved", "gje_update_kernel"): ("kernels_gje.hip", "9a80b99f7aea", 34547.5, 27226.0),
+    ("config2_resolved", "gje_rhs_kernel"): ("kernels_gje.hip", "9a80b99f7aea", 958200.3, 154362.8),
+    ("config2_resolved", "gemv_step_kernel"): ("kernels_gje.hip", "9a80b99f7aea", 58268.1, 58.0),
+    ("config2_resolved", "hq_rhs_kernel"): ("kernels_hq.hip", "5c57e8752f1e", 518092.2, 105209.0),
     # the panel launches also carry the block-system assembly
-    ("config2_resolved", "hq_panel_kernel"): ("kernels_hq.hip", "0f7d417f547e", 44978.4, 16454.9),
-    ("config2_resolved", "zgemm_kernel"): ("kernels_linalg.hip", "950c962799e9", 2203608.2, 176308.2),
-    ("config2_resolved", "self_kernel"): ("kernels_fill.hip", "c4ed21075aa2", 4464.1, 641854.8),
-    ("config2_resolved", "fill_kernel"): ("kernels_fill.hip", "c4ed21075aa2", 18222.2, 1642341.0),
+    ("config2_resolved", "hq_panel_kernel"): ("kernels_hq.hip", "5c57e8752f1e", 44997.3, 16454.9),
+    ("config2_resolved", "zgemm_kernel"): ("kernels_linalg.hip", "950c962799e9", 2205049.9, 176307.9),
+    ("config2_resolved", "self_kernel"): ("kernels_fill.hip", "c4ed21075aa2", 4465.2, 641872.8),
+    ("config2_resolved", "fill_kernel"): ("kernels_fill.hip", "c4ed21075aa2", 18274.8, 1642474.5),
 }
 
 
