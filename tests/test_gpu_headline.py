@@ -88,15 +88,16 @@ def test_config3_first40_resolved_shared_alpha(ctx):
 
 @pytest.mark.parametrize("row_blocks", [3, 4])
 def test_both_least_squares_size_classes(ctx, row_blocks):
-    # interior layer system 2 M_w + P = 280 rows (<= 384: the small class),
-    # end layers 2 M_w + 2 M_ud + P + 2K + 1 = 451 rows (the large class)
+    # interior layer system [Q; mu I] of 2 M_w + P = 340 rows (<= 384: the
+    # small class), end layers 2 M_w + 2 M_ud + P + 2K + 1 = 511 rows (the
+    # large class)
     import paper_1410_5003_amd as mlh
-    desc = workloads.config1(N=160, P=120, M_w=80)
+    desc = workloads.config1(N=160, P=140, M_w=100)
     o = oracle.solve_stack(desc)
     st = mlh.Stack(ctx, desc)
     st.set_tuning(ls_row_blocks=row_blocks)
     ref = {"orders": o.orders, "aU": o.aU, "aD": o.aD, "flux_err": o.flux_err}
-    _compare(st.solve(desc.thetas[:1]), 0, ref, "config1 N=160 P=120 M_w=80, %d row blocks" % row_blocks)
+    _compare(st.solve(desc.thetas[:1]), 0, ref, "config1 N=160 P=140 M_w=100, %d row blocks" % row_blocks)
     st.close()
 
 

@@ -189,22 +189,43 @@ def test_config3_head_resolved_twin(ctx):
 
 
 def test_config3_head_literal(ctx):
-    # the same interfaces at the literal sizes (N = 120 smooth, 250 cornered,
-    # P = 60 at k d up to 126: far from resolved).  There the amplitudes are
-    # fixed by the method only up to what an equally valid least-squares
-    # definition changes (the Remark after eq. (78)): the bar is the larger of
-    # the flux error and the oracle's own spread between Tikhonov weights
-    # 1e-14 and 1e-13
+    # The first interfaces of the 1000-layer workload at the literal sizes
+    # (N = 120 smooth, 250 cornered, P = 60 at k d up to 126: far from
+    # resolved), three angles.  There the least-squares Schur solves are rank
+    # deficient and the amplitudes are fixed by the method only up to what an
+    # equally valid choice in them changes (the Remark closing Sec. 3.2):
+    # noise 100 times below the fill parity bar moves them by more than 5e-4
+    # (tests/test_oracle_solve.py).  So the path is held stage by stage:
+    #   1. every fill piece entrywise to 1e-12 of the oracle's;
+    #   2. the amplitudes to 5e-5 of the oracle's solve stages applied to the
+    #      GPU's own fill pieces (their rounding spread, up to 2e-5 when the
+    #      least-squares rows are rotated by random unitaries, is also pinned
+    #      in tests/test_oracle_solve.py);
+    #   3. the amplitudes to 5e-4 of the oracle's end-to-end solve.
+    import paper_1410_5003_amd as mlh
+    from oracle import alpert, fills
+    from oracle.geometry import make_geometry
+    from tests.gpu_common import gpu_pieces, max_piece_diff
     s = workloads.config3(I=4, n_angles=3)
-    t = s.thetas[0]
-    g = _gpu(ctx, s, [t])
-    o = oracle.solve_stack(s, theta=t)
-    o2 = oracle.solve_stack(s, theta=t, mu_rel=1e-13)
-    spread = rel_amp_err(o2.aU, o2.aD, o.aU, o.aD)
-    tol = max(TOL, abs(o.flux_err), spread)
-    err = rel_amp_err(g.aU[0], g.aD[0], o.aU, o.aD)
-    print("config3 literal head rel err %.2e (flux %.1e, LS spread %.1e)" % (err, o.flux_err, spread))
-    assert err < tol
+    st = mlh.Stack(ctx, s)
+    g = st.solve(s.thetas)
+    rule = alpert.load_rule()
+    op = fills.stack_pieces(s, make_geometry(s), rule)
+    gp = gpu_pieces(st, s.I)
+    st.close()
+    dfill = max_piece_diff(gp, op)
+    print("config3 literal head: fill pieces max rel diff %.2e" % dfill)
+    assert dfill < 1e-12
+    for a, t in enumerate(s.thetas):
+        o = oracle.solve_stack(s, theta=t, rule=rule, pieces=op)
+        og = oracle.solve_stack(s, theta=t, rule=rule, pieces=gp)
+        assert np.array_equal(g.orders[a], o.orders)
+        e_stage = rel_amp_err(g.aU[a], g.aD[a], og.aU, og.aD)
+        e_full = rel_amp_err(g.aU[a], g.aD[a], o.aU, o.aD)
+        print("config3 literal head angle %d: vs oracle on GPU pieces %.2e, vs oracle %.2e (flux %.1e)" %
+              (a, e_stage, e_full, o.flux_err))
+        assert e_stage < 5e-5
+        assert e_full < 5e-4
 
 
 def test_shared_alpha_angles_solved_as_one_system(ctx):
