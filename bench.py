@@ -1,19 +1,21 @@
 #!/usr/bin/env python3
 """Throughput of the multilayer quasi-periodic Helmholtz solve on one MI355X.
 
-One step = one pass of the whole hot path for one incident angle: the
-alpha-independent fills (Nystrom self/neighbour blocks with the Alpert
+One step = one pass of the whole hot path over one batch of incident angles:
+the alpha-independent fills (Nystrom self/neighbour blocks with the Alpert
 correction, proxy, wall and radiation blocks), alpha assembly, the per-layer
 Tikhonov least-squares Schur eliminations, the Schur-complement GEMMs, the
-block-tridiagonal LU sweep, the backward sweep and the Bragg/flux extraction.
-Inputs (interface geometry, wavenumbers) are resident on the device before
-timing starts; the Bragg amplitudes are copied back each step.
+block-tridiagonal solve, the back substitution and the Bragg/flux
+extraction.  Inputs (interface geometry, wavenumbers) are resident on the
+device before timing starts; the Bragg amplitudes are copied back each step.
 
-Default workload: 50 random smooth interfaces (Fourier modes 1..5, peak 0.3,
-spacing 1.5, d = 2 pi), k_j = 10 n_j with n_j ~ U[1,2] and one interior layer
-at a Wood anomaly, theta = -pi/6, discretised finely enough for a flux error
-<= 1e-9 (N = 260 nodes per interface, P = 120 proxies, M_w = 80, M_ud = 60,
-K = 25).
+Default workload: the 1000-interface stack, 70 % random smooth interfaces
+(Fourier modes 1..5, peak 0.3) and 30 % cornered ones (triangle, trapezoid,
+triangle on a flat; Kress-graded segments, q = 6), spacing 1.5, d = 2 pi,
+k_j = 10 n_j with n_j ~ U[1,2], discretised at N = 260 (smooth) / 500
+(cornered) nodes, P = 140, M_w = 100, M_ud = 60, K = 25 (804242 unknowns per
+angle); one step is a sweep of 100 incident angles on a kappa_0 grid that
+holds 20 distinct Bloch phases (Sec. 3.4), 5 angles each.
 """
 import argparse
 import json
@@ -120,8 +122,7 @@ def algorithmic_work(desc):
         ncol = n[0] if j == 0 else (n[I - 1] if j == I else n[j - 1] + n[j])
         qr += 8.0 * M * c * c - 8.0 * c ** 3 / 3.0
         ap += ncol * (16.0 * M * c - 4.0 * c * c)
-    w["ls_panel"] = qr
-    w["ls_update"] = qr
+    w["ls_qr"] = qr
     w["ls_rhs"] = ap
     w["backsub"] = sum(8.0 * n[i] * n[i + 1] for i in range(I - 1))
     # fill: complex entries written (three copies for A and Z, two for C and Q)
@@ -167,50 +168,113 @@ def measured_traffic(workload, kernel):
     return (rd + wr) * 1024.0
 
 
-GROUPS = [  # (name, profile time key, launch-count key, work key, bound)
-    ("gje_update_kernel", "gje_update_ms", "n_gje_update", "gje_update", "mfma"),
-    ("gje_rhs_kernel", "gje_rhs_ms", None, "gje_rhs", "mfma"),
-    ("gje_panel_kernel", "gje_panel_ms", "n_gje_panel", "gje_panel", "alu"),
-    ("zgemm_kernel (sweep update)", "sweep_gemm_ms", "n_sweep_gemm", "sweep_gemm", "mfma"),
-    ("zgemm_kernel (Schur complements)", "schur_ms", None, "schur", "mfma"),
-    ("hq_panel_kernel", "ls_panel_ms", None, "ls_panel", "alu"),
-    ("hq_update_kernel", "ls_update_ms", None, "ls_update", "alu"),
-    ("hq_rhs_kernel", "ls_rhs_ms", None, "ls_rhs", "mfma"),
-    ("gemv_step_kernel", "backsub_ms", None, "backsub", "alu"),
-    ("self_kernel", "fill_self_ms", None, "fill_self_bytes", "hbm"),
-    ("fill_kernel", "fill_pairs_ms", None, "fill_pairs_bytes", "hbm"),
+# Kernel groups of the timed path: (kernel name as the profiler reports it,
+# profile time keys, launch-count keys, work keys, bound).  Work keys name
+# either counts the library returns with the profile (flops of the
+# descriptors each launch processed) or entries of algorithmic_work().
+GROUPS = [
+    ("zgemm_kernel", ("schur_ms", "sweep_gemm_ms"), ("n_schur_gemm", "n_sweep_gemm"),
+     ("schur_flops", "sweep_gemm_flops"), "mfma"),
+    ("gje_step_kernel", ("gje_step_ms",), ("n_gje_step",), ("gje_step_flops",), "mfma"),
+    ("gje_rhs_kernel (with gje_premul_kernel)", ("gje_rhs_ms",), ("n_gje_rhs",), ("gje_rhs_flops",), "mfma"),
+    ("gje_panel_kernel + gje_update_kernel", ("gje_panel_ms", "gje_update_ms"), ("n_gje_panel",),
+     ("gje_panel_update_flops",), "mfma"),
+    ("hq_panel_kernel", ("ls_panel_ms",), (), ("@ls_qr",), "alu"),
+    ("hq_rhs_kernel", ("ls_rhs_ms",), (), ("@ls_rhs",), "mfma"),
+    ("gemv_step_kernel", ("backsub_ms",), ("n_backsub",), ("@backsub",), "alu"),
+    ("self_kernel", ("fill_self_ms",), (), ("@fill_self_bytes",), "hbm"),
+    ("fill_kernel", ("fill_pairs_ms",), (), ("@fill_pairs_bytes",), "hbm"),
 ]
 
 
 def roofline(desc, prof, n_sys=1, workload=None):
-    work = {k: (v if k.startswith("fill") else v * n_sys) for k, v in algorithmic_work(desc).items()}
-    name, tkey, nkey, wkey, bound = max(GROUPS, key=lambda g: prof[g[1]])
-    t = prof[tkey] * 1e-3
-    launches = int(prof[nkey]) if nkey else 1
+    """Roofline of the kernel with the largest device time in the profile."""
+    alg = algorithmic_work(desc)
+
+    def work(keys):
+        tot = 0.0
+        for k in keys:
+            if k.startswith("@"):
+                v = alg[k[1:]]
+                tot += v if k.startswith("@fill") else v * n_sys
+            else:
+                tot += prof[k]
+        return tot
+
+    def t_ms(g):
+        return sum(prof[k] for k in g[1])
+
+    name, tkeys, nkeys, wkeys, bound = max(GROUPS, key=t_ms)
+    t = t_ms((name, tkeys)) * 1e-3
+    launches = int(sum(prof[k] for k in nkeys)) if nkeys else 1
+    w = work(wkeys)
     if bound == "hbm":
-        ach, peak, unit = work[wkey] / t / 1e9, HBM_PEAK_GBS, "GB/s"
+        ach, peak, unit = w / t / 1e9, HBM_PEAK_GBS, "GB/s"
     else:
-        ach, peak, unit = work[wkey] / t / 1e12, FP64_PEAK_TFS, "TFLOP/s"
+        ach, peak, unit = w / t / 1e12, FP64_PEAK_TFS, "TFLOP/s"
     traffic = measured_traffic(workload, name.split(" ")[0])
     return {"bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak, "traffic": traffic,
-            "kernel": name, "launches_per_step": launches, "avg_launch_ms": prof[tkey] / launches,
-            "work_per_launch": work[wkey] / launches}
+            "kernel": name, "launches_per_step": launches, "avg_launch_ms": t * 1e3 / launches,
+            "work_per_launch": w / launches}
 
 
-def cpu_baseline(name, sample_I):
+def phase_fractions(desc, prof, n_sys):
+    """FP64 fraction of the least-squares, Schur and block-solve phase in the
+    method's own flops (a block Thomas sweep, not cyclic reduction's extra
+    work), and the HBM fraction of the fills in bytes written."""
+    w = algorithmic_work(desc)
+    flops = n_sys * (w["ls_qr"] + w["ls_rhs"] + w["schur"] + w["gje_panel"] + w["gje_update"] + w["gje_rhs"] +
+                     w["sweep_gemm"] + w["backsub"])
+    t = 1e-3 * sum(prof[k] for k in ("ls_panel_ms", "ls_update_ms", "ls_rhs_ms", "schur_ms", "sweep_gemm_ms",
+                                     "gje_step_ms", "gje_panel_ms", "gje_update_ms", "gje_rhs_ms", "backsub_ms"))
+    fb = w["fill_self_bytes"] + w["fill_pairs_bytes"]
+    tf = 1e-3 * (prof["fill_self_ms"] + prof["fill_alpert_ms"] + prof["fill_pairs_ms"])
+    return {"schur_blocklu_fp64": {"method_flops": flops, "device_s": t, "achieved_tflops": flops / t / 1e12,
+                                   "peak_tflops": FP64_PEAK_TFS, "frac": flops / t / 1e12 / FP64_PEAK_TFS},
+            "fill_hbm": {"bytes_written": fb, "device_s": tf, "achieved_gbs": fb / tf / 1e9,
+                         "peak_gbs": HBM_PEAK_GBS, "frac": fb / tf / 1e9 / HBM_PEAK_GBS}}
+
+
+def available_cores():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(name, sample_I, threads):
     """Time the oracle on the first `sample_I` interfaces of the workload, one
-    angle (one thread, separate process); the caller scales linearly in the
-    number of layers and angles."""
+    angle, with `threads` BLAS/OpenMP threads (separate process); the caller
+    scales linearly in the number of layers."""
     code = (
         "import os,sys,time;sys.path.insert(0,%r);"
         "import bench,oracle;d=bench.make_desc(%r,I=%d);"
-        "t=time.perf_counter();r=oracle.solve_stack(d);print(time.perf_counter()-t)"
-    ) % (ROOT, name, sample_I)
-    env = dict(os.environ, OPENBLAS_NUM_THREADS="1", OMP_NUM_THREADS="1", MKL_NUM_THREADS="1")
+        "t=time.perf_counter();r=oracle.solve_stack(d,theta=float(bench.step_thetas(%r,d)[0]));"
+        "print(time.perf_counter()-t)"
+    ) % (ROOT, name, sample_I, name)
+    n = str(threads)
+    env = dict(os.environ, OPENBLAS_NUM_THREADS=n, OMP_NUM_THREADS=n, MKL_NUM_THREADS=n)
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=600)
     if out.returncode != 0:
         raise RuntimeError(out.stderr)
     return float(out.stdout.strip().splitlines()[-1])
+
+
+def tuning_angles(desc, thetas, systems=2, tol=1e-12):
+    """The angles of the sweep's first `systems` distinct Bloch phases."""
+    import math
+    import numpy as np
+    fr, keep = [], []
+    for t in thetas:
+        x = desc.d * desc.k[0] * math.cos(t) / (2 * math.pi)
+        f = x - math.floor(x)
+        hit = [g for g in fr if min(abs(f - g), 1 - abs(f - g)) < tol]
+        if not hit and len(fr) >= systems:
+            continue
+        if not hit:
+            fr.append(f)
+        keep.append(t)
+    return np.asarray(keep, dtype=float)
 
 
 def main():
@@ -218,14 +282,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="config2_resolved", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="config3_kgrid_resolved", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-layers", type=int, default=6)
+    ap.add_argument("--cpu-sample-layers", type=int, default=None,
+                    help="interfaces of the workload the oracle solves for the CPU baseline "
+                         "(default: 8 for sweeps, 6 otherwise)")
     ap.add_argument("--plain-sample", type=int, default=4,
                     help="sweeps: angles timed one by one (refill + one-angle solve each)")
     ap.add_argument("--autotune", choices=("auto", "on", "off"), default="auto",
                     help="time the solve under candidate launch choices before the warmup and keep the "
-                         "fastest (auto: for one-angle steps; a sweep's candidates take minutes)")
+                         "fastest (auto/on: sweeps are tuned on the angles of their first two Bloch "
+                         "phases, which run the launch shapes of one batch of the sweep)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (calibrates the HBM "
                          "byte counters of a profiler against a known size) and exit")
@@ -250,8 +317,9 @@ def main():
     desc = make_desc(args.workload)
     thetas = step_thetas(args.workload, desc)
     sweep = len(thetas) > 1
-    steps = args.steps if args.steps is not None else (1 if sweep else 20)
+    steps = args.steps if args.steps is not None else (5 if sweep else 20)
     warmup = args.warmup if args.warmup is not None else (1 if sweep else 3)
+    sample_layers = args.cpu_sample_layers or (8 if sweep else 6)
     ctx = mlh.Context(0)
     st = mlh.Stack(ctx, desc)
     info = st.info()
@@ -259,12 +327,14 @@ def main():
     print("workload %s: I=%d n_tot=%d device MB %.1f angles %d distinct alpha %d" %
           (args.workload, desc.I, info["n_tot"], info["device_bytes"] / 2 ** 20, len(thetas), n_sys),
           file=sys.stderr, flush=True)
-    autotuned = args.autotune == "on" or (args.autotune == "auto" and not sweep)
+    autotuned = args.autotune in ("auto", "on")
     if autotuned:  # outside the timed region
         ta = time.perf_counter()
         st.refill()
-        st.autotune(thetas, reps=3)
-        print("autotune %s in %.2f s" % (st.get_tuning(), time.perf_counter() - ta), file=sys.stderr, flush=True)
+        tune_th = tuning_angles(desc, thetas) if sweep else thetas
+        st.autotune(tune_th, reps=1 if sweep else 3)
+        print("autotune %s on %d angles in %.2f s" % (st.get_tuning(), len(tune_th), time.perf_counter() - ta),
+              file=sys.stderr, flush=True)
     tuning = dict(st.get_tuning(), autotuned=autotuned)
     out = None
     for _ in range(warmup):
@@ -283,7 +353,8 @@ def main():
     print("step %.3f ms  flux err max %.2e median %.2e" % (ms, flux.max(), np.median(flux)),
           file=sys.stderr, flush=True)
 
-    # per-kernel device times (HIP events on the library's stream)
+    # per-kernel device times (HIP events on the library's stream, around
+    # the launches of the timed path run one at a time)
     if sweep:
         prof = st.profile_solve(thetas)
     else:
@@ -291,6 +362,7 @@ def main():
         prof = {k: float(np.mean([p[k] for p in profs])) for k in profs[0]}
     print("profile " + json.dumps({k: round(v, 4) for k, v in prof.items()}), file=sys.stderr, flush=True)
     roof = roofline(desc, prof, n_sys, args.workload)
+    phases = phase_fractions(desc, prof, n_sys)
     line = {
         "metric": METRIC, "value": solves_per_s, "unit": "solves/s", "n_gpus": 1, "steps": steps,
         "warmup": warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
@@ -302,6 +374,8 @@ def main():
         "flux_err_max": float(flux.max()),
         "phase_ms": {k: round(v, 4) for k, v in prof.items() if k.endswith("_ms")},
         "roofline": roof,
+        "schur_blocklu_fp64": phases["schur_blocklu_fp64"],
+        "fill_hbm": phases["fill_hbm"],
         "tuning": tuning,
     }
     if sweep and args.plain_sample > 0:
@@ -323,12 +397,16 @@ def main():
         print("sweep: plain %.3f s/angle, batched %.3f s/angle, speed-up %.2fx" % (plain, batched, plain / batched),
               file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
-        ts = cpu_baseline(args.workload, args.cpu_sample_layers)
-        t_full = ts * desc.I / args.cpu_sample_layers
-        line["cpu_baseline"] = {"value": 1.0 / t_full, "unit": "solves/s", "cores": 1, "kind": "oracle",
-                                "sample": "first %d of %d interfaces of the same stack, one angle, %.2f s, "
-                                          "scaled linearly in the number of layers" % (args.cpu_sample_layers,
-                                                                                       desc.I, ts)}
+        cores = available_cores()
+        t1 = cpu_baseline(args.workload, sample_layers, 1)
+        tn = cpu_baseline(args.workload, sample_layers, cores)
+        scale = desc.I / sample_layers
+        line["cpu_baseline"] = {"value": 1.0 / (tn * scale), "unit": "solves/s", "cores": cores, "kind": "oracle",
+                                "sample": "oracle solve of the first %d of %d interfaces of the same stack, one "
+                                          "angle: %.2f s on %d threads (%.2f s on 1 thread, %.4f solves/s); scaled "
+                                          "linearly in the number of layers" % (sample_layers, desc.I, tn, cores,
+                                                                                t1, 1.0 / (t1 * scale)),
+                                "value_1_core": 1.0 / (t1 * scale)}
     print(json.dumps(line), flush=True)
 
 

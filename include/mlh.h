@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define MLH_ABI_VERSION 1
+#define MLH_ABI_VERSION 2
 
 typedef int32_t mlh_status;
 enum {
@@ -53,6 +53,8 @@ enum {
   MLH_E_NOMEM = 3,       /* device allocation failed                         */
   MLH_E_DEVICE = 4,      /* a HIP call failed                                */
   MLH_E_SINGULAR = 5,    /* exact zero pivot in the block LU                 */
+  MLH_E_ACCURACY = 6,    /* flux error beyond the tolerance the caller set
+                            (mlh_stack_set_flux_tolerance; outputs written)  */
   MLH_E_UNSUPPORTED = 7  /* sizes beyond this library's limits              */
 };
 
@@ -133,58 +135,66 @@ mlh_status mlh_stack_destroy(mlh_stack s);
 mlh_status mlh_stack_info(mlh_stack s, int64_t* n_den, int64_t* n_tot, int64_t* device_bytes);
 
 /* Solve for n_angles incident angles theta[0..n_angles-1] (host array, each
- * in (-pi, 0)).  Angles are processed in batches that share the per-layer
- * kernels.  Outputs (host arrays, caller-allocated):
+ * in (-pi, 0)): the Schur eliminations of Sec. 3.2, the block-tridiagonal
+ * solve of Sec. 3.3 for the densities eta, and the Bragg amplitudes
+ * x_1 = -X_1 eta_1, x_{I+1} = -X_{I+1} eta_I with the flux error eq. (86).
+ * Angles whose Bloch phases alpha agree share one factorisation (Sec. 3.4);
+ * batches of systems share the per-layer launches.
+ *
+ * outputs_on_device: 0 = the output pointers are host memory and the call
+ * returns once they are written; 1 = they are device memory of the
+ * context's device (e.g. torch tensors) and the call returns once the work
+ * and the output copies are enqueued on the context's stream (the caller
+ * synchronises that stream before reading them; an exact zero pivot is then
+ * not reported).  Outputs, caller-allocated:
  *   aU, aD     [n_angles][2K+1] complex (interleaved), orders ascending;
  *   orders     [n_angles][2K+1] physical order labels n (may be NULL);
  *   flux_err   [n_angles] relative flux error eq. (86) with the incident
- *              vertical flux k_1 |sin theta| (may be NULL).
- * Errors: MLH_E_INVALID_ARG, MLH_E_SINGULAR, MLH_E_NOMEM, MLH_E_DEVICE. */
-mlh_status mlh_solve(mlh_stack s, int32_t n_angles, const double* theta, double* aU,
-                     double* aD, int32_t* orders, double* flux_err);
+ *              vertical flux k_1 |sin theta| (may be NULL);
+ *   eta        [n_angles][N_den] complex densities [tau_1; sigma_1; ...;
+ *              tau_I; sigma_I] of eq. (64), interfaces top to bottom (may be
+ *              NULL).  The densities are fixed only up to the least-squares
+ *              choice of Sec. 3.2 (its closing Remark); the amplitudes are not.
+ * Errors: MLH_E_INVALID_ARG, MLH_E_SINGULAR, MLH_E_ACCURACY (only after
+ * mlh_stack_set_flux_tolerance; every output is still written), MLH_E_NOMEM,
+ * MLH_E_DEVICE. */
+mlh_status mlh_solve(mlh_stack s, int32_t n_angles, const double* theta, int32_t outputs_on_device,
+                     double* aU, double* aD, int32_t* orders, double* flux_err, double* eta);
 
-/* Inspection (used by the parity tests): copy one alpha-independent fill
- * piece to host memory `out` (column-major, leading dimension = rows,
- * complex interleaved).  which: 0 A_self[i] (piece p = 0,1,2 for copies
- * l = -1,0,1), 1 A_up[i] (rows Gamma_i, cols Gamma_{i+1}), 2 A_dn[i] (rows
- * Gamma_{i+1}, cols Gamma_i), 3 B_own[i], 4 B_below[i], 5 C_own[j]
- * (p = 0: target x+2d, 1: x-d), 6 C_above[j], 7 Q[j] (p = 0: x+d, 1: x),
- * 8 Z_U (p = copy), 9 Z_D, 10 V_U, 11 V_D.  rows/cols receive the shape
- * (out may be NULL to query it). */
-mlh_status mlh_debug_get_piece(mlh_stack s, int32_t which, int32_t index, int32_t piece,
-                               double* out, int32_t* rows, int32_t* cols);
+/* Opt in to an accuracy report: with tol > 0, mlh_solve returns
+ * MLH_E_ACCURACY when some angle's |flux error| (eq. (86)) exceeds tol; with
+ * device outputs it then waits for the stream to read the flux errors.
+ * tol = 0 (the default) turns the check off.  Errors: MLH_E_INVALID_ARG for a
+ * negative or non-finite tol. */
+mlh_status mlh_stack_set_flux_tolerance(mlh_stack s, double tol);
 
-/* Inspection: evaluate the device Hankel routine at n host arguments x > 0:
- * out[4*i..4*i+3] = (Re, Im) of H0^(1)(x) and of g1m(x) = (i pi x/2) H1^(1)(x) - 1. */
-mlh_status mlh_debug_hankel(mlh_ctx ctx, int32_t n, const double* x, double* out);
-
-/* Inspection: complex batched GEMM C = C + alpha A B (column-major, host
- * arrays, m x k times k x n), run with the library's FP64-MFMA kernel. */
-mlh_status mlh_debug_zgemm(mlh_ctx ctx, int32_t m, int32_t n, int32_t k, const double* alpha,
-                           const double* A, const double* B, double* C);
-
-/* Inspection: run the solve for one angle up to phase `stop_phase`
- * (1: blocks assembled for alpha, 2: + per-layer least squares, 3: + Schur
- * complements, 4: + sweep) and keep that angle's workspace for
- * mlh_debug_get_work. */
-mlh_status mlh_debug_solve_partial(mlh_stack s, double theta, int32_t stop_phase);
-
-/* Inspection: copy a workspace block of the last mlh_debug_solve_partial:
- * which 0 [A'_ii | f~_i] (n_i x (n_i+1)), 1 A'_{i,i+1}, 2 A'_{i+1,i},
- * 3 stacked least-squares matrix of layer j ((m+c) x c), 4 its right-hand
- * side / solution ((m+c) x ncol), 6 eta_i (densities, phase 4).  Column-major,
- * complex interleaved; out may be NULL to query the shape. */
-mlh_status mlh_debug_get_work(mlh_stack s, int32_t which, int32_t index, double* out, int32_t* rows,
-                              int32_t* cols);
-
-/* Per-kernel device times of one full step (refill + one-angle solve),
- * measured with HIP events on the context's stream around every launch. */
+/* Per-kernel device times of one full step (refill + solve), measured with
+ * HIP events on the context's stream around every launch.  The launches are
+ * those of the captured graph, run one at a time on one stream: the fused
+ * Gauss-Jordan step kernel where the graph uses it (gje_step_ms), the panel
+ * and update kernels where the graph runs them on two streams.
+ *   *_ms         summed device time of the group's launches;
+ *   n_*          its launch count;
+ *   *_flops      the real float64 flops of the group's complex products,
+ *                8 m n k per product of an m x k by a k x n matrix (the
+ *                descriptors' own sizes; the three-real-product evaluation
+ *                is not what is counted). */
 typedef struct {
   double fill_self_ms, fill_alpert_ms, fill_pairs_ms;
   double assemble_ms, rb_setup_ms, ls_panel_ms, ls_update_ms, ls_rhs_ms, schur_ms;
   double sweep_gemm_ms, gje_panel_ms, gje_update_ms, gje_rhs_ms, backsub_ms, bragg_ms;
   int32_t n_sweep_gemm, n_gje_panel, n_gje_update;
   double total_ms;
+  double gje_step_ms;
+  int32_t n_gje_step, n_schur_gemm, n_gje_rhs, n_backsub;
+  double schur_flops, sweep_gemm_flops;
+  /* Gauss-Jordan work counted as LU with partial pivoting plus triangular
+   * solves, (8/3) n^3 + 8 n^2 r for an order-n block with r right-hand-side
+   * columns: gje_step_flops for the levels run by the step kernel (their
+   * right-hand sides included when eliminated inside the steps),
+   * gje_panel_update_flops for the levels run by the panel and update
+   * kernels, gje_rhs_flops for right-hand sides replayed afterwards. */
+  double gje_step_flops, gje_panel_update_flops, gje_rhs_flops;
 } mlh_profile;
 
 /* Run one step (mlh_stack_refill + mlh_solve of angle theta) with HIP events

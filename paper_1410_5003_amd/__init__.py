@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes as C
 from dataclasses import dataclass
+from typing import Optional
 
 import numpy as np
 
@@ -80,6 +81,7 @@ class SolveOutput:
     aD: np.ndarray
     orders: np.ndarray   # (n_angles, 2K+1) int
     flux_err: np.ndarray  # (n_angles,)
+    eta: Optional[np.ndarray] = None  # (n_angles, N_den) complex densities, if asked for
 
 
 class Stack:
@@ -150,16 +152,47 @@ class Stack:
         check(lib().mlh_stack_info(self._h, C.byref(a), C.byref(b), C.byref(c)))
         return {"n_den": a.value, "n_tot": b.value, "device_bytes": c.value}
 
-    def solve(self, thetas) -> SolveOutput:
+    def solve(self, thetas, eta: bool = False) -> SolveOutput:
+        """Bragg amplitudes, order labels and flux errors of the angles
+        ``thetas`` in host arrays (and the densities if ``eta``)."""
         th = np.ascontiguousarray(np.atleast_1d(thetas), dtype=np.float64)
         na, nK = th.size, 2 * self.K + 1
         aU = np.zeros((na, nK), dtype=np.complex128)
         aD = np.zeros((na, nK), dtype=np.complex128)
         orders = np.zeros((na, nK), dtype=np.int32)
         flux = np.zeros(na)
-        check(lib().mlh_solve(self._h, na, dptr(th), dptr(aU), dptr(aD),
-                              iptr(orders), dptr(flux)))
-        return SolveOutput(aU, aD, orders, flux)
+        dens = np.zeros((na, self.info()["n_den"]), dtype=np.complex128) if eta else None
+        check(lib().mlh_solve(self._h, na, dptr(th), 0, aU.ctypes.data, aD.ctypes.data, orders.ctypes.data,
+                              flux.ctypes.data, dens.ctypes.data if eta else None))
+        return SolveOutput(aU, aD, orders, flux, dens)
+
+    def solve_into(self, thetas, aU, aD, orders=None, flux_err=None, eta=None):
+        """Solve with device-resident outputs: ``aU``, ``aD`` (complex128,
+        (n_angles, 2K+1)), ``orders`` (int32), ``flux_err`` (float64,
+        (n_angles,)) and ``eta`` (complex128, (n_angles, N_den)) are
+        contiguous torch tensors on the context's device; None skips an
+        optional output.  Returns once the work is enqueued on the context's
+        stream."""
+        th = np.ascontiguousarray(np.atleast_1d(thetas), dtype=np.float64)
+        na, nK = th.size, 2 * self.K + 1
+
+        def ptr(t, dtype, shape):
+            if t is None:
+                return None
+            if not (t.is_cuda and t.is_contiguous() and t.dtype == dtype and tuple(t.shape) == shape):
+                raise ValueError("output tensor must be a contiguous %s device tensor of shape %s" % (dtype, shape))
+            return t.data_ptr()
+
+        import torch
+        check(lib().mlh_solve(self._h, na, dptr(th), 1, ptr(aU, torch.complex128, (na, nK)),
+                              ptr(aD, torch.complex128, (na, nK)), ptr(orders, torch.int32, (na, nK)),
+                              ptr(flux_err, torch.float64, (na,)),
+                              ptr(eta, torch.complex128, (na, self.info()["n_den"]))))
+
+    def set_flux_tolerance(self, tol: float):
+        """Report MLH_E_ACCURACY from solves whose |flux error| exceeds tol
+        (0 turns the check off)."""
+        check(lib().mlh_stack_set_flux_tolerance(self._h, float(tol)))
 
     def profile_step(self, theta: float) -> dict:
         """Per-kernel device times (ms) of one refill + one-angle solve."""

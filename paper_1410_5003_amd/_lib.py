@@ -12,13 +12,13 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmlh.so")
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 MLH_IFACE_FOURIER = 0
 MLH_IFACE_POLYGON = 1
 
 STATUS = {0: "MLH_OK", 1: "MLH_E_INVALID_ARG", 2: "MLH_E_GEOMETRY", 3: "MLH_E_NOMEM",
-          4: "MLH_E_DEVICE", 5: "MLH_E_SINGULAR", 7: "MLH_E_UNSUPPORTED"}
+          4: "MLH_E_DEVICE", 5: "MLH_E_SINGULAR", 6: "MLH_E_ACCURACY", 7: "MLH_E_UNSUPPORTED"}
 
 PIECES = {"A_self": 0, "A_up": 1, "A_dn": 2, "B_own": 3, "B_below": 4, "C_own": 5, "C_above": 6,
           "Q": 7, "Z_U": 8, "Z_D": 9, "V_U": 10, "V_D": 11}
@@ -51,7 +51,10 @@ class mlh_profile(C.Structure):
         "ls_update_ms", "ls_rhs_ms", "schur_ms", "sweep_gemm_ms", "gje_panel_ms", "gje_update_ms", "gje_rhs_ms", "backsub_ms",
         "bragg_ms")] + \
         [("n_sweep_gemm", C.c_int32), ("n_gje_panel", C.c_int32), ("n_gje_update", C.c_int32),
-         ("total_ms", C.c_double)]
+         ("total_ms", C.c_double), ("gje_step_ms", C.c_double), ("n_gje_step", C.c_int32),
+         ("n_schur_gemm", C.c_int32), ("n_gje_rhs", C.c_int32), ("n_backsub", C.c_int32),
+         ("schur_flops", C.c_double), ("sweep_gemm_flops", C.c_double), ("gje_step_flops", C.c_double),
+         ("gje_panel_update_flops", C.c_double), ("gje_rhs_flops", C.c_double)]
 
 
 class mlh_tuning(C.Structure):
@@ -70,8 +73,9 @@ SIGNATURES = {
     "mlh_stack_destroy": (C.c_int32, [C.c_void_p]),
     "mlh_stack_info": (C.c_int32, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                    C.POINTER(C.c_int64)]),
-    "mlh_solve": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double),
-                              C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+    "mlh_solve": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.c_int32, C.c_void_p,
+                              C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mlh_stack_set_flux_tolerance": (C.c_int32, [C.c_void_p, C.c_double]),
     "mlh_debug_get_piece": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
                                         C.POINTER(C.c_double), C.POINTER(C.c_int32),
                                         C.POINTER(C.c_int32)]),

@@ -165,6 +165,19 @@ struct StackConsts {
 void launch_rb_setup(const AngleDesc* d_ang, int nang, StackConsts sc, hipStream_t st);
 void launch_bragg(const AngleDesc* d_ang, int nang, StackConsts sc, hipStream_t st);
 
+// densities eta of a batch gathered into one row of N_den entries per angle
+struct EtaSeg {      // per interface (the same for every system of a batch)
+  int64_t src_off;   // byte offset of eta_i in a system's workspace
+  int64_t dst_off;   // offset of interface i within an angle's row
+  int n;             // n_i
+};
+struct EtaDst {      // per angle
+  const char* sys_base;  // its system's workspace
+  int col;               // its column in the system's eta blocks
+  cplx* dst;             // its output row (N_den entries)
+};
+void launch_gather_eta(const EtaSeg* d_seg, int nseg, int max_n, const EtaDst* d_dst, int ndst, hipStream_t st);
+
 }  // namespace mlh
 
 namespace mlh {

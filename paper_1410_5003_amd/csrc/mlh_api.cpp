@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/mlh.h"
+#include "../../include/mlh_debug.h"
 #include "alpert_rule.inc"
 #include "internal.hpp"
 
@@ -311,6 +312,7 @@ struct Arena {
 struct mlh_stack_s {
   mlh_ctx ctx = nullptr;
   mlh_tuning tune{300, 3, 16, 1};  // launch choices (mlh_stack_set_tuning / mlh_stack_autotune)
+  double flux_tol = 0.0;           // > 0: a solve whose flux error exceeds it reports MLH_E_ACCURACY
   int I = 0, P = 0, Mw = 0, Mud = 0, K = 0, nK = 0;
   double d = 0, yU = 0, yD = 0, R = 0, mu = 1e-14;
   std::vector<double> k;
@@ -1023,13 +1025,32 @@ struct EvTimer {
 };
 }  // namespace
 
+// real float64 flops of a batch of complex products C = C0 + alpha (A B + A2 B2):
+// 8 m n k per product
+static double gemm_flops(const std::vector<GemmDesc>& v) {
+  double f = 0.0;
+  for (const GemmDesc& G : v) f += 8.0 * G.m * G.n * (double)(G.k + G.k2);
+  return f;
+}
+
 static int row_width(const mlh_stack_s* s, int i) {
   // columns of the level-0 row block [A'_ii | A'_{i,i-1} | A'_{i,i+1} | f~_i]
   return s->n[i] + (i > 0 ? s->n[i - 1] : 0) + (i + 1 < s->I ? s->n[i + 1] : 0) + 1;
 }
 
+// how one solve call runs and where its outputs go
+struct SolveOpts {
+  int stop_phase = 0;            // inspection: stop after this phase (0 = whole solve)
+  mlh_profile* prof = nullptr;   // time every launch (one stream, no graph)
+  bool on_device = false;        // outputs are device pointers; no host wait
+  double* eta = nullptr;         // optional [n_angles][N_den] complex densities
+  bool check_flux = false;       // report MLH_E_ACCURACY past the stack's flux tolerance
+};
+
 static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta, double* aU, double* aD,
-                             int32_t* orders, double* flux_err, int stop_phase, mlh_profile* prof = nullptr) {
+                             int32_t* orders, double* flux_err, const SolveOpts& opt) {
+  const int stop_phase = opt.stop_phase;
+  mlh_profile* const prof = opt.prof;
   if (!s) return fail(MLH_E_INVALID_ARG, "NULL stack");
   if (n_angles < 1 || !theta || !aU || !aD) return fail(MLH_E_INVALID_ARG, "mlh_solve: bad arguments");
   for (int a = 0; a < n_angles; ++a)
@@ -1065,6 +1086,10 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
   const int n_sys = (int)groups.size();
   int rmax = 1;
   for (const auto& g : groups) rmax = std::max(rmax, (int)g.size());
+  std::vector<int64_t> den_off(I + 1, 0);  // offset of eta_i in a row of N_den densities
+  for (int i = 0; i < I; ++i) den_off[i + 1] = den_off[i] + n[i];
+  const int64_t nden = den_off[I];
+  const bool eta_stage = opt.eta && !opt.on_device;  // host densities go through a device row per angle
   std::vector<int> wmax(I), nL0(I), nU0(I);
   for (int i = 0; i < I; ++i) {
     wmax[i] = n[i] + 2 * maxn + rmax;
@@ -1097,6 +1122,7 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
     R(cbytes((size_t)2 * nK * rmax));
     R(sizeof(double) * rmax);
     R(sizeof(int) * nK * rmax);
+    if (eta_stage) R(cbytes((size_t)nden * rmax));
   };
   Arena ar;
   plan(ar, nullptr);
@@ -1104,7 +1130,7 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
   const size_t desc_per = sizeof(AsmJob) * (size_t)(10 * (I + 2)) + sizeof(GemmDesc) * (size_t)(8 * I + 8) +
                           sizeof(HqDesc) * (size_t)(I + 1) + sizeof(GjeDesc) * (size_t)(I + 1) +
                           sizeof(GemvDesc) * (size_t)(I + 1) + sizeof(AngleDesc) * (size_t)rmax +
-                          256 * (size_t)(3 * 40 + 16);
+                          sizeof(EtaSeg) * (size_t)I + sizeof(EtaDst) * (size_t)rmax + 256 * (size_t)(3 * 40 + 18);
   size_t freeb = 0, totb = 0;
   HIP_TRY(hipMemGetInfo(&freeb, &totb));
   int B = n_sys;
@@ -1145,6 +1171,7 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
       cplx* out;  // per angle: a^U (nK) then a^D (nK)
       double* flux;
       int* orders;
+      cplx* eta_rows = nullptr;  // host densities: one row of N_den per angle
     };
     std::vector<View> V(nb);
     for (int b = 0; b < nb; ++b) {
@@ -1170,6 +1197,7 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
       v.out = C();
       v.flux = reinterpret_cast<double*>(wb + offs[k++]);
       v.orders = reinterpret_cast<int*>(wb + offs[k++]);
+      if (eta_stage) v.eta_rows = C();
     }
     auto Dblk = [&](int b, int i) { return V[b].W[0][i]; };
     auto Lblk = [&](int b, int i) { return V[b].W[0][i] + (size_t)n[i] * n[i]; };
@@ -1550,6 +1578,31 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
     const size_t o_gs = push(gs.data(), sizeof(GemmDesc) * gs.size());
     const size_t o_hq = push(hq.data(), sizeof(HqDesc) * hq.size());
     const size_t o_ang = push(angs.data(), sizeof(AngleDesc) * angs.size());
+    // densities: where eta_i sits in every system's workspace, and each
+    // angle's output row
+    size_t o_eseg = 0, o_edst = 0;
+    int n_edst = 0;
+    if (opt.eta && stop_phase == 0) {
+      std::vector<EtaSeg> eseg(I);
+      for (int i = 0; i < I; ++i) {
+        eseg[i].src_off = (int64_t)(reinterpret_cast<char*>(V[0].eta[i]) - s->wmem);
+        eseg[i].dst_off = den_off[i];
+        eseg[i].n = n[i];
+      }
+      std::vector<EtaDst> edst;
+      for (int b = 0; b < nb; ++b)
+        for (int q = 0; q < R_of(b); ++q) {
+          EtaDst E{};
+          E.sys_base = s->wmem + (size_t)b * per;
+          E.col = q;
+          E.dst = opt.on_device ? reinterpret_cast<cplx*>(opt.eta) + (size_t)nden * groups[s0 + b][q]
+                                : V[b].eta_rows + (size_t)nden * q;
+          edst.push_back(E);
+        }
+      o_eseg = push(eseg.data(), sizeof(EtaSeg) * eseg.size());
+      o_edst = push(edst.data(), sizeof(EtaDst) * edst.size());
+      n_edst = (int)edst.size();
+    }
     const int NL = (int)levels.size();
     std::vector<size_t> o_gje(NL), o_upd(NL), o_back(NL);
     for (int l = 0; l < NL; ++l) {
@@ -1635,6 +1688,10 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
         tb(prof ? &prof->schur_ms : nullptr);
         launch_gemm(reinterpret_cast<GemmDesc*>(dbase + o_gs), (int)gs.size(), gtiles, ls);
         te();
+        if (prof) {
+          prof->n_schur_gemm++;
+          prof->schur_flops += gemm_flops(gs);
+        }
       }
       if (stop_phase == 0 || stop_phase >= 4) {
         for (int l = 0; l < NL; ++l) {
@@ -1649,7 +1706,27 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
           const int nsteps = (lv.maxn + kGjeNb - 1) / kGjeNb;
           const int rcol = lv.rhs_in_step ? lv.maxcol : 0;  // > 0: the updates take the right-hand sides
           const bool narrow = s->tune.gje_rhs_cols == 8;
-          if (prof) {  // one stream, every launch timed on its own
+          if (prof && gje_step_fits(lv.maxn)) {  // the graph's step launches, each timed on its own
+            for (int st_i = 0; st_i < nsteps; ++st_i) {
+              tb(&prof->gje_step_ms);
+              launch_gje_step(dg, ng, st_i * kGjeNb, lv.maxn, ls, rcol, lv.maxrhs);
+              te();
+              prof->n_gje_step++;
+            }
+            if (lv.rhs_in_step) {
+              tb(&prof->gje_update_ms);
+              launch_gje_update(dg, ng, (nsteps - 1) * kGjeNb, lv.maxn, kGjeNb, 1 << 30, ls, rcol, lv.maxrhs);
+              te();
+              prof->n_gje_update++;
+            } else {
+              tb(&prof->gje_rhs_ms);
+              launch_gje_premul(dg, ng, lv.maxn, ls);
+              launch_gje_rhs(dg, lv.nsmall, lv.rhs_small, kRhsMaxN16, 0, nsteps, 0, ls, narrow);
+              launch_gje_rhs(dg + lv.nsmall, ng - lv.nsmall, lv.rhs_large, lv.maxn, 0, nsteps, 0, ls, narrow);
+              te();
+              prof->n_gje_rhs++;
+            }
+          } else if (prof) {  // panel and update on one stream, every launch timed on its own
             for (int k = 0; k < lv.maxn; k += kGjeNb) {
               tb(&prof->gje_panel_ms);
               launch_gje_panel(dg, ng, k, lv.maxn, ls);
@@ -1666,6 +1743,7 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
               launch_gje_rhs(dg, lv.nsmall, lv.rhs_small, kRhsMaxN16, 0, nsteps, 0, ls, narrow);
               launch_gje_rhs(dg + lv.nsmall, ng - lv.nsmall, lv.rhs_large, lv.maxn, 0, nsteps, 0, ls, narrow);
               te();
+              prof->n_gje_rhs++;
             }
           } else if (gje_step_fits(lv.maxn)) {
             // one launch per step: panel s with the update of step s - 1
@@ -1698,11 +1776,26 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
             launch_gje_rhs(dg, lv.nsmall, lv.rhs_small, kRhsMaxN16, 0, nsteps, 0, ls, narrow);
             launch_gje_rhs(dg + lv.nsmall, ng - lv.nsmall, lv.rhs_large, lv.maxn, 0, nsteps, 0, ls, narrow);
           }
+          if (prof) {
+            double lu = 0.0, rhs = 0.0;
+            for (const GjeDesc& G : lv.gje) {
+              lu += 8.0 / 3.0 * (double)G.n * G.n * G.n;
+              rhs += 8.0 * (double)G.n * G.n * (G.ncol - G.n);
+            }
+            if (gje_step_fits(lv.maxn))
+              prof->gje_step_flops += lu + (lv.rhs_in_step ? rhs : 0.0);
+            else
+              prof->gje_panel_update_flops += lu;
+            if (!lv.rhs_in_step) prof->gje_rhs_flops += rhs;
+          }
           if (!lv.upd.empty()) {
             tb(prof ? &prof->sweep_gemm_ms : nullptr);
             launch_gemm(reinterpret_cast<GemmDesc*>(dbase + o_upd[l]), (int)lv.upd.size(), lv.upd_tiles, ls);
             te();
-            if (prof) prof->n_sweep_gemm++;
+            if (prof) {
+              prof->n_sweep_gemm++;
+              prof->sweep_gemm_flops += gemm_flops(lv.upd);
+            }
           }
         }
         tb(prof ? &prof->backsub_ms : nullptr);
@@ -1710,9 +1803,13 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
           launch_gemv_step(reinterpret_cast<GemvDesc*>(dbase + o_back[l]), (int)levels[l].back.size(), levels[l].backn,
                            rchunk, ls);
         te();
+        if (prof) prof->n_backsub += NL;
         tb(prof ? &prof->bragg_ms : nullptr);
         launch_bragg(d_ang, nang, sc, ls);
         te();
+        if (n_edst > 0)
+          launch_gather_eta(reinterpret_cast<EtaSeg*>(dbase + o_eseg), I, maxn, reinterpret_cast<EtaDst*>(dbase + o_edst),
+                            n_edst, ls);
       }
       HIP_TRY(hipGetLastError());
 
@@ -1729,7 +1826,7 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
                                   gtiles, maxc, maxcols, maxncol, (int64_t)hq.size(), (int64_t)gs.size(),
                                   hq_small.n, hq_small.maxc, hq_small.maxncol, hq_large.maxc, hq_large.maxncol,
                                   s->tune.rhs_in_step_pct, s->tune.ls_row_blocks, s->tune.gje_rhs_cols,
-                                  s->tune.asm_in_panels};
+                                  s->tune.asm_in_panels, n_edst, (int64_t)o_eseg, (int64_t)o_edst};
       for (const Level& lv : levels) {
         sig.push_back(lv.maxn);
         sig.push_back(lv.maxcol);
@@ -1777,31 +1874,69 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
       HIP_TRY(hipStreamSynchronize(st));
       return MLH_OK;
     }
-    // ---- results
+    // ---- results (stream-ordered; the workspace of the next batch is
+    //      written only after these copies)
+    const hipMemcpyKind kind = opt.on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    const bool check = opt.check_flux && s->flux_tol > 0;
+    const bool want_flux_host = !opt.on_device || check;
     for (int b = 0; b < nb; ++b)
       for (int q = 0; q < R_of(b); ++q) {
         const int a = groups[s0 + b][q];
         const cplx* o = V[b].out + (size_t)2 * nK * q;
-        HIP_TRY(hipMemcpyAsync(aU + (size_t)2 * nK * a, o, cbytes(nK), hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipMemcpyAsync(aD + (size_t)2 * nK * a, o + nK, cbytes(nK), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(aU + (size_t)2 * nK * a, o, cbytes(nK), kind, st));
+        HIP_TRY(hipMemcpyAsync(aD + (size_t)2 * nK * a, o + nK, cbytes(nK), kind, st));
         if (orders)
-          HIP_TRY(hipMemcpyAsync(orders + (size_t)nK * a, V[b].orders + (size_t)nK * q, sizeof(int) * nK,
+          HIP_TRY(hipMemcpyAsync(orders + (size_t)nK * a, V[b].orders + (size_t)nK * q, sizeof(int) * nK, kind, st));
+        if (opt.on_device && flux_err)
+          HIP_TRY(hipMemcpyAsync(flux_err + a, V[b].flux + q, sizeof(double), kind, st));
+        if (want_flux_host)
+          HIP_TRY(hipMemcpyAsync(&h_flux[a], V[b].flux + q, sizeof(double), hipMemcpyDeviceToHost, st));
+        if (eta_stage)
+          HIP_TRY(hipMemcpyAsync(opt.eta + (size_t)2 * nden * a, V[b].eta_rows + (size_t)nden * q, cbytes(nden),
                                  hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipMemcpyAsync(&h_flux[a], V[b].flux + q, sizeof(double), hipMemcpyDeviceToHost, st));
       }
-    int info[4] = {0, 0, 0, 0};
-    HIP_TRY(hipMemcpyAsync(info, d_info, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    if (info[0] != 0) return fail(MLH_E_SINGULAR, "exact zero pivot in the block-tridiagonal solve");
+    if (!opt.on_device) {
+      int info[4] = {0, 0, 0, 0};
+      HIP_TRY(hipMemcpyAsync(info, d_info, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      if (info[0] != 0) return fail(MLH_E_SINGULAR, "exact zero pivot in the block-tridiagonal solve");
+    }
   }
-  if (flux_err)
+  const bool check = opt.check_flux && s->flux_tol > 0;
+  if (opt.on_device && check) HIP_TRY(hipStreamSynchronize(st));
+  if (flux_err && !opt.on_device)
     for (int a = 0; a < n_angles; ++a) flux_err[a] = h_flux[a];
+  if (check) {
+    int worst = -1;
+    for (int a = 0; a < n_angles; ++a)
+      if (!(std::fabs(h_flux[a]) <= s->flux_tol) && (worst < 0 || !(std::fabs(h_flux[a]) <= std::fabs(h_flux[worst]))))
+        worst = a;
+    if (worst >= 0) {
+      char msg[160];
+      std::snprintf(msg, sizeof msg, "flux error %.3e at angle %d exceeds the tolerance %.3e", h_flux[worst], worst,
+                    s->flux_tol);
+      return fail(MLH_E_ACCURACY, msg);
+    }
+  }
   return MLH_OK;
 }
 
-extern "C" mlh_status mlh_solve(mlh_stack s, int32_t n_angles, const double* theta, double* aU, double* aD,
-                                int32_t* orders, double* flux_err) {
-  return solve_impl(s, n_angles, theta, aU, aD, orders, flux_err, 0);
+extern "C" mlh_status mlh_solve(mlh_stack s, int32_t n_angles, const double* theta, int32_t outputs_on_device,
+                                double* aU, double* aD, int32_t* orders, double* flux_err, double* eta) {
+  if (outputs_on_device != 0 && outputs_on_device != 1)
+    return fail(MLH_E_INVALID_ARG, "mlh_solve: outputs_on_device must be 0 or 1");
+  SolveOpts o;
+  o.on_device = outputs_on_device == 1;
+  o.eta = eta;
+  o.check_flux = true;
+  return solve_impl(s, n_angles, theta, aU, aD, orders, flux_err, o);
+}
+
+extern "C" mlh_status mlh_stack_set_flux_tolerance(mlh_stack s, double tol) {
+  if (!s) return fail(MLH_E_INVALID_ARG, "NULL stack");
+  if (!(tol >= 0) || !std::isfinite(tol)) return fail(MLH_E_INVALID_ARG, "flux tolerance must be finite and >= 0");
+  s->flux_tol = tol;
+  return MLH_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -1837,11 +1972,11 @@ extern "C" mlh_status mlh_stack_autotune(mlh_stack s, int32_t n_angles, const do
   std::vector<double> aU(nc), aD(nc);
   auto time_of = [&](const mlh_tuning& t, double& best) -> mlh_status {
     s->tune = t;
-    MLH_TRY(solve_impl(s, n_angles, theta, aU.data(), aD.data(), nullptr, nullptr, 0));
+    MLH_TRY(solve_impl(s, n_angles, theta, aU.data(), aD.data(), nullptr, nullptr, SolveOpts()));
     best = 1e300;
     for (int r = 0; r < reps; ++r) {
       const auto t0 = std::chrono::steady_clock::now();
-      MLH_TRY(solve_impl(s, n_angles, theta, aU.data(), aD.data(), nullptr, nullptr, 0));
+      MLH_TRY(solve_impl(s, n_angles, theta, aU.data(), aD.data(), nullptr, nullptr, SolveOpts()));
       best = std::min(best, std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
     }
     return MLH_OK;
@@ -2025,7 +2160,9 @@ extern "C" mlh_status mlh_debug_solve_partial(mlh_stack s, double theta, int32_t
   double aU[2 * 512], aD[2 * 512], fl[1];
   int ord[512];
   if (!s || 2 * s->K + 1 > 512) return fail(MLH_E_INVALID_ARG, "bad stack");
-  return solve_impl(s, 1, &theta, aU, aD, ord, fl, stop_phase);
+  SolveOpts o;
+  o.stop_phase = stop_phase;
+  return solve_impl(s, 1, &theta, aU, aD, ord, fl, o);
 }
 
 extern "C" mlh_status mlh_debug_get_work(mlh_stack s, int32_t which, int32_t index, double* out, int32_t* rows,
@@ -2103,7 +2240,9 @@ extern "C" mlh_status mlh_profile_solve(mlh_stack s, int32_t n_angles, const dou
   std::vector<double> aU((size_t)2 * nK * n_angles), aD((size_t)2 * nK * n_angles);
   std::vector<int> ord((size_t)nK * n_angles);
   std::vector<double> fl(n_angles);
-  mlh_status r = solve_impl(s, n_angles, theta, aU.data(), aD.data(), ord.data(), fl.data(), 0, out);
+  SolveOpts o;
+  o.prof = out;
+  mlh_status r = solve_impl(s, n_angles, theta, aU.data(), aD.data(), ord.data(), fl.data(), o);
   HIP_TRY(hipEventRecord(e1, st));
   HIP_TRY(hipEventSynchronize(e1));
   float ms = 0;
