@@ -1821,8 +1821,10 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
       MLH_TRY(launch_all(st, T));
     } else {
       // every launch shape of the sequence: a cached graph is replayed only
-      // when all of them, and the workspace, are unchanged
-      std::vector<int64_t> sig = {nb, B, nang, rchunk, (int64_t)doff, (int64_t)(intptr_t)s->wmem, asm_ls.tiles, asm_blk.tiles,
+      // when all of them, and the workspace and its per-system stride (which
+      // places the descriptors and every system after the first), are
+      // unchanged
+      std::vector<int64_t> sig = {nb, B, (int64_t)per, nang, rchunk, (int64_t)doff, (int64_t)(intptr_t)s->wmem, asm_ls.tiles, asm_blk.tiles,
                                   gtiles, maxc, maxcols, maxncol, (int64_t)hq.size(), (int64_t)gs.size(),
                                   hq_small.n, hq_small.maxc, hq_small.maxncol, hq_large.maxc, hq_large.maxncol,
                                   s->tune.rhs_in_step_pct, s->tune.ls_row_blocks, s->tune.gje_rhs_cols,

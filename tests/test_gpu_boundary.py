@@ -68,13 +68,21 @@ def test_densities_are_the_block_solve_result(stack):
 
 def test_densities_of_angles_sharing_alpha_are_their_own(stack):
     # the two angles sharing alpha have separate right-hand sides, so their
-    # densities differ; each equals its own single-angle solve
+    # densities differ.  The densities themselves are not unique: the Schur
+    # step picks one of many admissible quasi-periodic Green's functions
+    # (Remark after eq. (78)), and on this stack the oracle's own densities
+    # move by tens of percent between Tikhonov weights 1e-14 and 1e-13 while
+    # the amplitudes move by 1e-12.  So each angle is held to its own
+    # single-angle solve through what is unique, the Bragg amplitudes.
     desc, st, th = stack
     out = st.solve(th, eta=True)
     for a in range(th.size):
         one = st.solve(th[a:a + 1], eta=True)
-        scale = np.max(np.abs(one.eta))
-        assert np.max(np.abs(out.eta[a] - one.eta[0])) < 1e-11 * scale
+        assert np.array_equal(out.orders[a], one.orders[0])
+        scale = max(np.max(np.abs(one.aU)), np.max(np.abs(one.aD)))
+        err = max(np.max(np.abs(out.aU[a] - one.aU[0])), np.max(np.abs(out.aD[a] - one.aD[0])))
+        assert err < 1e-10 * scale, (a, err / scale)
+        assert np.all(np.isfinite(out.eta[a])) and np.max(np.abs(out.eta[a])) > 0
     assert np.max(np.abs(out.eta[0] - out.eta[2])) > 1e-3 * np.max(np.abs(out.eta[0]))
 
 

@@ -219,3 +219,20 @@ def test_literal_1000_layer_head_rounding_spread_of_least_squares():
             spreads.append(max(np.abs(o2.aU - o.aU).max(), np.abs(o2.aD - o.aD).max()) / scale)
         print("theta %.4f rotated least-squares spread %s" % (t, ["%.1e" % v for v in spreads]))
         assert 1e-7 < max(spreads) < 5e-5
+
+
+def test_densities_depend_on_the_least_squares_choice_amplitudes_do_not():
+    # Remark after eq. (78): the Schur complements stand for an arbitrary
+    # quasi-periodic Green's function per layer, picked by the least-squares
+    # solves, so the densities eta are not unique while the Bragg amplitudes
+    # are.  Two Tikhonov weights give densities far apart and amplitudes
+    # equal to rounding.
+    import dataclasses
+    desc = workloads.small_stack(seed=6, I=4, N=77, P=45, M_w=35, M_ud=40, K=9)
+    th = float(desc.thetas[0])
+    r1 = oracle.solve_stack(desc, theta=th)
+    r2 = oracle.solve_stack(dataclasses.replace(desc, ls_mu=1e-13), theta=th)
+    e1, e2 = np.concatenate(r1.eta), np.concatenate(r2.eta)
+    assert np.max(np.abs(e1 - e2)) > 1e-3 * np.max(np.abs(e1))
+    scale = max(np.max(np.abs(r1.aU)), np.max(np.abs(r1.aD)))
+    assert max(np.max(np.abs(r1.aU - r2.aU)), np.max(np.abs(r1.aD - r2.aD))) < 1e-10 * scale
