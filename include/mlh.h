@@ -161,6 +161,22 @@ mlh_status mlh_stack_info(mlh_stack s, int64_t* n_den, int64_t* n_tot, int64_t* 
 mlh_status mlh_solve(mlh_stack s, int32_t n_angles, const double* theta, int32_t outputs_on_device,
                      double* aU, double* aD, int32_t* orders, double* flux_err, double* eta);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): mlh_solve
+ * with the same arguments, outputs and errors, whose solve workspace lives
+ * in a fixed per-device area of 64 MiB reserved when the library is loaded
+ * on that device (held until the process ends) instead of memory the stack
+ * allocates.  The call allocates nothing on the device, captures no graph and
+ * launches its kernels on the context's stream one by one.  The stack's own
+ * fill pieces stay where mlh_stack_create put them.  Angles are solved in as
+ * many passes as the area needs; a stack one of whose systems (one Bloch
+ * phase and its angles) needs more than 64 MiB of workspace is rejected with
+ * MLH_E_UNSUPPORTED before any device work.  Every call on one device uses
+ * the same area: calls that overlap in time on one device (two host threads,
+ * or two streams) race and must be serialised by the caller. */
+mlh_status mlh_solve_noalloc(mlh_stack s, int32_t n_angles, const double* theta, int32_t outputs_on_device,
+                             double* aU, double* aD, int32_t* orders, double* flux_err, double* eta);
+
 /* Opt in to an accuracy report: with tol > 0, mlh_solve returns
  * MLH_E_ACCURACY when some angle's |flux error| (eq. (86)) exceeds tol; with
  * device outputs it then waits for the stream to read the flux errors.

@@ -152,9 +152,11 @@ class Stack:
         check(lib().mlh_stack_info(self._h, C.byref(a), C.byref(b), C.byref(c)))
         return {"n_den": a.value, "n_tot": b.value, "device_bytes": c.value}
 
-    def solve(self, thetas, eta: bool = False) -> SolveOutput:
+    def solve(self, thetas, eta: bool = False, noalloc: bool = False) -> SolveOutput:
         """Bragg amplitudes, order labels and flux errors of the angles
-        ``thetas`` in host arrays (and the densities if ``eta``)."""
+        ``thetas`` in host arrays (and the densities if ``eta``).  With
+        ``noalloc`` the call goes to mlh_solve_noalloc, whose workspace is the
+        library's fixed per-device area."""
         th = np.ascontiguousarray(np.atleast_1d(thetas), dtype=np.float64)
         na, nK = th.size, 2 * self.K + 1
         aU = np.zeros((na, nK), dtype=np.complex128)
@@ -162,8 +164,9 @@ class Stack:
         orders = np.zeros((na, nK), dtype=np.int32)
         flux = np.zeros(na)
         dens = np.zeros((na, self.info()["n_den"]), dtype=np.complex128) if eta else None
-        check(lib().mlh_solve(self._h, na, dptr(th), 0, aU.ctypes.data, aD.ctypes.data, orders.ctypes.data,
-                              flux.ctypes.data, dens.ctypes.data if eta else None))
+        fn = lib().mlh_solve_noalloc if noalloc else lib().mlh_solve
+        check(fn(self._h, na, dptr(th), 0, aU.ctypes.data, aD.ctypes.data, orders.ctypes.data,
+                 flux.ctypes.data, dens.ctypes.data if eta else None))
         return SolveOutput(aU, aD, orders, flux, dens)
 
     def solve_into(self, thetas, aU, aD, orders=None, flux_err=None, eta=None):

@@ -75,6 +75,8 @@ SIGNATURES = {
                                    C.POINTER(C.c_int64)]),
     "mlh_solve": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.c_int32, C.c_void_p,
                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mlh_solve_noalloc": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.c_int32, C.c_void_p,
+                                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "mlh_stack_set_flux_tolerance": (C.c_int32, [C.c_void_p, C.c_double]),
     "mlh_debug_get_piece": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
                                         C.POINTER(C.c_double), C.POINTER(C.c_int32),

@@ -178,6 +178,13 @@ struct EtaDst {      // per angle
 };
 void launch_gather_eta(const EtaSeg* d_seg, int nseg, int max_n, const EtaDst* d_dst, int ndst, hipStream_t st);
 
+// Fixed workspace of the allocation-free solve: kScratchBytes per device,
+// shared by every such call on that device (calls that overlap on one device
+// race).  scratch_address returns the device's own copy; the device must be
+// current.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+hipError_t scratch_address(int device, char** ptr);
+
 }  // namespace mlh
 
 namespace mlh {

@@ -51,6 +51,7 @@ extern "C" const char* mlh_last_error(void) { return g_err.c_str(); }
 struct mlh_ctx_s {
   int device;
   hipStream_t stream;
+  char* scratch;  // this device's fixed workspace (allocation-free solve)
 };
 
 extern "C" mlh_status mlh_ctx_create(int32_t device, void* hip_stream, mlh_ctx* out) {
@@ -60,7 +61,9 @@ extern "C" mlh_status mlh_ctx_create(int32_t device, void* hip_stream, mlh_ctx* 
   if (device < 0 || device >= ndev) return fail(MLH_E_INVALID_ARG, "mlh_ctx_create: no such device");
   HIP_TRY(hipSetDevice(device));
   gje_init();
-  *out = new mlh_ctx_s{device, (hipStream_t)hip_stream};
+  char* scratch = nullptr;
+  HIP_TRY(scratch_address(device, &scratch));
+  *out = new mlh_ctx_s{device, (hipStream_t)hip_stream, scratch};
   return MLH_OK;
 }
 
@@ -1045,6 +1048,7 @@ struct SolveOpts {
   bool on_device = false;        // outputs are device pointers; no host wait
   double* eta = nullptr;         // optional [n_angles][N_den] complex densities
   bool check_flux = false;       // report MLH_E_ACCURACY past the stack's flux tolerance
+  bool noalloc = false;          // workspace in the context's fixed scratch; no allocation, no graph
 };
 
 static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta, double* aU, double* aD,
@@ -1131,9 +1135,24 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
                           sizeof(HqDesc) * (size_t)(I + 1) + sizeof(GjeDesc) * (size_t)(I + 1) +
                           sizeof(GemvDesc) * (size_t)(I + 1) + sizeof(AngleDesc) * (size_t)rmax +
                           sizeof(EtaSeg) * (size_t)I + sizeof(EtaDst) * (size_t)rmax + 256 * (size_t)(3 * 40 + 18);
+  int B = n_sys;
+  char* wbase = nullptr;
+  if (opt.noalloc) {
+    // the fixed scratch holds as many systems as fit, at least one
+    while (B > 1 && (size_t)B * (per + desc_per) + 4096 > kScratchBytes) B = (B + 1) / 2;
+    while (B > 1 && (size_t)B * (I + 1) > 65535) B = (B + 1) / 2;
+    const size_t need = (size_t)B * (per + desc_per) + 4096;
+    if (need > kScratchBytes) {
+      char msg[200];
+      std::snprintf(msg, sizeof msg,
+                    "one system of this stack needs %.1f MiB of workspace; the allocation-free solve holds at "
+                    "most %.1f MiB", need / 1048576.0, kScratchBytes / 1048576.0);
+      return fail(MLH_E_UNSUPPORTED, msg);
+    }
+    wbase = s->ctx->scratch;
+  } else {
   size_t freeb = 0, totb = 0;
   HIP_TRY(hipMemGetInfo(&freeb, &totb));
-  int B = n_sys;
   const size_t budget = (size_t)(0.8 * (double)(freeb + s->wbytes));
   while (B > 1 && (size_t)B * (per + desc_per) > budget) B = (B + 1) / 2;
   // batched launches put one matrix per grid row: at most 65535 of them
@@ -1150,6 +1169,8 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
     HIP_TRY(hipMalloc((void**)&s->wmem, need));
     s->wbytes = need;
   }
+  wbase = s->wmem;
+  }
   std::vector<size_t> offs;
   {
     Arena A;
@@ -1164,7 +1185,7 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
       rchunk = std::max(rchunk, (int)groups[s0 + b].size());
     }
     auto R_of = [&](int b) { return (int)groups[s0 + b].size(); };
-    char* dbase = s->wmem + (size_t)B * per;
+    char* dbase = wbase + (size_t)B * per;
     struct View {
       std::vector<cplx*> W[2], S, Th, RHS, eta, M1;
       std::vector<int*> piv;
@@ -1175,7 +1196,7 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
     };
     std::vector<View> V(nb);
     for (int b = 0; b < nb; ++b) {
-      char* wb = s->wmem + (size_t)b * per;
+      char* wb = wbase + (size_t)b * per;
       size_t k = 0;
       auto C = [&]() { return reinterpret_cast<cplx*>(wb + offs[k++]); };
       View& v = V[b];
@@ -1585,7 +1606,7 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
     if (opt.eta && stop_phase == 0) {
       std::vector<EtaSeg> eseg(I);
       for (int i = 0; i < I; ++i) {
-        eseg[i].src_off = (int64_t)(reinterpret_cast<char*>(V[0].eta[i]) - s->wmem);
+        eseg[i].src_off = (int64_t)(reinterpret_cast<char*>(V[0].eta[i]) - wbase);
         eseg[i].dst_off = den_off[i];
         eseg[i].n = n[i];
       }
@@ -1593,7 +1614,7 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
       for (int b = 0; b < nb; ++b)
         for (int q = 0; q < R_of(b); ++q) {
           EtaDst E{};
-          E.sys_base = s->wmem + (size_t)b * per;
+          E.sys_base = wbase + (size_t)b * per;
           E.col = q;
           E.dst = opt.on_device ? reinterpret_cast<cplx*>(opt.eta) + (size_t)nden * groups[s0 + b][q]
                                 : V[b].eta_rows + (size_t)nden * q;
@@ -1629,7 +1650,7 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
     sc.P = P;
     sc.K = s->K;
     // ---- launch sequence (captured into a graph and replayed when possible)
-    if (!s->aux_stream) HIP_TRY(hipStreamCreateWithFlags(&s->aux_stream, hipStreamNonBlocking));
+    if (!opt.noalloc && !s->aux_stream) HIP_TRY(hipStreamCreateWithFlags(&s->aux_stream, hipStreamNonBlocking));
     size_t ev_used = 0;
     auto ev_next = [&]() -> hipEvent_t {
       if (ev_used == s->evpool.size()) {
@@ -1726,24 +1747,27 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
               te();
               prof->n_gje_rhs++;
             }
-          } else if (prof) {  // panel and update on one stream, every launch timed on its own
+          } else if (prof || (opt.noalloc && !gje_step_fits(lv.maxn))) {
+            // panel and update on one stream (each launch timed when profiling)
             for (int k = 0; k < lv.maxn; k += kGjeNb) {
-              tb(&prof->gje_panel_ms);
+              tb(prof ? &prof->gje_panel_ms : nullptr);
               launch_gje_panel(dg, ng, k, lv.maxn, ls);
               te();
-              tb(&prof->gje_update_ms);
+              tb(prof ? &prof->gje_update_ms : nullptr);
               launch_gje_update(dg, ng, k, lv.maxn, kGjeNb, 1 << 30, ls, rcol, lv.maxrhs);
               te();
-              prof->n_gje_panel++;
-              prof->n_gje_update++;
+              if (prof) {
+                prof->n_gje_panel++;
+                prof->n_gje_update++;
+              }
             }
             if (!lv.rhs_in_step) {
-              tb(&prof->gje_rhs_ms);
+              tb(prof ? &prof->gje_rhs_ms : nullptr);
               launch_gje_premul(dg, ng, lv.maxn, ls);
               launch_gje_rhs(dg, lv.nsmall, lv.rhs_small, kRhsMaxN16, 0, nsteps, 0, ls, narrow);
               launch_gje_rhs(dg + lv.nsmall, ng - lv.nsmall, lv.rhs_large, lv.maxn, 0, nsteps, 0, ls, narrow);
               te();
-              prof->n_gje_rhs++;
+              if (prof) prof->n_gje_rhs++;
             }
           } else if (gje_step_fits(lv.maxn)) {
             // one launch per step: panel s with the update of step s - 1
@@ -1817,7 +1841,7 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
     };
     EvTimer T{st};
     static const bool no_graph = std::getenv("MLH_NO_GRAPH") != nullptr;
-    if (prof || stop_phase != 0 || no_graph) {
+    if (prof || stop_phase != 0 || no_graph || opt.noalloc) {
       MLH_TRY(launch_all(st, T));
     } else {
       // every launch shape of the sequence: a cached graph is replayed only
@@ -1931,6 +1955,19 @@ extern "C" mlh_status mlh_solve(mlh_stack s, int32_t n_angles, const double* the
   o.on_device = outputs_on_device == 1;
   o.eta = eta;
   o.check_flux = true;
+  return solve_impl(s, n_angles, theta, aU, aD, orders, flux_err, o);
+}
+
+extern "C" mlh_status mlh_solve_noalloc(mlh_stack s, int32_t n_angles, const double* theta,
+                                        int32_t outputs_on_device, double* aU, double* aD, int32_t* orders,
+                                        double* flux_err, double* eta) {
+  if (outputs_on_device != 0 && outputs_on_device != 1)
+    return fail(MLH_E_INVALID_ARG, "mlh_solve_noalloc: outputs_on_device must be 0 or 1");
+  SolveOpts o;
+  o.on_device = outputs_on_device == 1;
+  o.eta = eta;
+  o.check_flux = true;
+  o.noalloc = true;
   return solve_impl(s, n_angles, theta, aU, aD, orders, flux_err, o);
 }
 
