@@ -19,7 +19,7 @@ from __future__ import annotations
 import numpy as np
 
 
-def flat_stack_amplitudes(k, y_if, theta, y_U, y_D):
+def _solve(k, y_if, theta, y_U, y_D):
     k = np.asarray(k, float)
     I = len(y_if)
     kappa0 = k[0] * np.cos(theta)
@@ -62,4 +62,37 @@ def flat_stack_amplitudes(k, y_if, theta, y_U, y_D):
         M[2 * i + 1] = dva - dvb
         rhs[2 * i + 1] = dcb - dca
     sol = np.linalg.solve(M, rhs)
-    return sol[0], sol[-1], q
+    return sol[0], sol[-1], q, sol
+
+
+def flat_stack_total_field(k, y_if, theta, y_U, y_D, x, y):
+    """Total field (incident included in layer 1) of the flat stack at the
+    points (x, y), from the closed-form layer amplitudes above."""
+    k = np.asarray(k, float)
+    I = len(y_if)
+    aU, aD, q, sol = _solve(k, y_if, theta, y_U, y_D)
+    kappa0 = k[0] * np.cos(theta)
+    x = np.atleast_1d(np.asarray(x, float))
+    y = np.atleast_1d(np.asarray(y, float))
+    out = np.zeros(x.size, dtype=complex)
+    for t in range(x.size):
+        yy = y[t]
+        j = 0
+        while j < I and yy < y_if[j]:
+            j += 1
+        if j == 0:
+            v = np.exp(-1j * q[0] * yy) + aU * np.exp(1j * q[0] * (yy - y_U))
+        elif j == I:
+            v = aD * np.exp(-1j * q[I] * (yy - y_D))
+        else:
+            A, B = sol[1 + 2 * (j - 1)], sol[2 + 2 * (j - 1)]
+            v = A * np.exp(-1j * q[j] * (yy - y_if[j - 1])) + B * np.exp(1j * q[j] * (yy - y_if[j]))
+        out[t] = v * np.exp(1j * kappa0 * x[t])
+    return out
+
+
+def flat_stack_amplitudes(k, y_if, theta, y_U, y_D):
+    """(a^U, a^D, q): the zeroth-order Bragg amplitudes and the vertical
+    wavenumbers q_j of the flat stack."""
+    aU, aD, q, _ = _solve(k, y_if, theta, y_U, y_D)
+    return aU, aD, q
