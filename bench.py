@@ -51,6 +51,11 @@ WORKLOADS = {
     "config3": ("config3", dict(),
                 "I=1000, 70% random Fourier (N=120) / 30% cornered (N=250), P=60, M_w=60, M_ud=60, K=25; "
                 "sweep of 100 angles uniform in (-pi/2, 0)", "all"),
+    # a batch of independent stacks: solved by mlh_batch_solve, one angle each
+    "config4": ("config4", dict(),
+                "64 independent stacks, I ~ U{10..200}, N ~ U{60..250} per interface, 70% random Fourier / 30% "
+                "cornered, k = omega n with omega ~ U[5,20], n ~ U[1,2.5], P=60, M_w=60, M_ud=60, K=25; one "
+                "random angle per stack", "batch"),
 }
 
 
@@ -277,6 +282,75 @@ def tuning_angles(desc, thetas, systems=2, tol=1e-12):
     return np.asarray(keep, dtype=float)
 
 
+def pct(x, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(x, dtype=float), q))
+
+
+def bench_batch(args):
+    """Many independent stacks: one step = refill of every stack's pieces and
+    one batched solve of all of them (one angle each), in shared launches."""
+    import numpy as np
+    import torch
+    import workloads
+    import paper_1410_5003_amd as mlh
+    descs = workloads.config4()
+    ctx = mlh.Context(0)
+    sts = [mlh.Stack(ctx, d) for d in descs]
+    b = mlh.Batch(ctx, sts)
+    th = np.array([float(d.thetas[0]) for d in descs])
+    n_tot = sum(s.info()["n_tot"] for s in sts)
+    steps = args.steps if args.steps is not None else 10
+    warmup = args.warmup if args.warmup is not None else 2
+    print("workload config4: %d stacks, %d interfaces, %d unknowns" % (len(descs), sum(d.I for d in descs), n_tot),
+          file=sys.stderr, flush=True)
+    autotuned = args.autotune in ("auto", "on")
+    if autotuned:
+        ta = time.perf_counter()
+        b.autotune(th, reps=1)
+        print("autotune %s in %.2f s" % (b.get_tuning(), time.perf_counter() - ta), file=sys.stderr, flush=True)
+    out = None
+    for _ in range(warmup):
+        out = b.solve(th, refill=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = b.solve(th, refill=True)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    lat = out.stack_ms
+    flux = np.abs(out.flux_err)
+    # the same stacks one at a time (refill + one-angle solve each, each
+    # timed to its own completion)
+    plain = []
+    for i, st in enumerate(sts):
+        st.refill()
+        st.solve(th[i:i + 1])
+    torch.cuda.synchronize()
+    for i, st in enumerate(sts):
+        tp = time.perf_counter()
+        st.refill()
+        st.solve(th[i:i + 1])
+        plain.append((time.perf_counter() - tp) * 1e3)
+    plain_total = float(np.sum(plain))
+    line = {
+        "metric": METRIC, "value": len(descs) / (ms * 1e-3), "unit": "solves/s", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 (complex128)", "data": "synthetic (seeded stacks)",
+        "config": {"workload": "config4", "description": WORKLOADS["config4"][2], "stacks": len(descs),
+                   "interfaces": int(sum(d.I for d in descs)), "unknowns": int(n_tot)},
+        "unknowns_per_s": n_tot / (ms * 1e-3), "flux_err_median": float(np.median(flux)),
+        "flux_err_max": float(flux.max()),
+        "latency_ms": {"batched_p50": pct(lat, 50), "batched_p99": pct(lat, 99), "plain_p50": pct(plain, 50),
+                       "plain_p99": pct(plain, 99), "plain_total": plain_total},
+        "speedup_vs_plain": plain_total / ms,
+        "tuning": dict(b.get_tuning(), autotuned=autotuned),
+    }
+    print("batched %.2f ms per step (%d stacks); plain %.2f ms; latency p50 %.2f p99 %.2f ms" %
+          (ms, len(descs), plain_total, pct(lat, 50), pct(lat, 99)), file=sys.stderr, flush=True)
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -310,6 +384,8 @@ def main():
     if args.gpus != 1:
         print("bench.py: the solver runs on one GPU (there is no multi-GPU path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if WORKLOADS[args.workload][3] == "batch":
+        return bench_batch(args)
     import numpy as np
     import torch
     import paper_1410_5003_amd as mlh

@@ -60,6 +60,7 @@ enum {
 
 typedef struct mlh_ctx_s* mlh_ctx;
 typedef struct mlh_stack_s* mlh_stack;
+typedef struct mlh_batch_s* mlh_batch;
 
 enum { MLH_IFACE_FOURIER = 0, MLH_IFACE_POLYGON = 1 };
 
@@ -260,6 +261,46 @@ mlh_status mlh_stack_set_tuning(mlh_stack s, const mlh_tuning* t);
  * Errors: those of mlh_solve; the stack then keeps its previous choices. */
 mlh_status mlh_stack_autotune(mlh_stack s, int32_t n_angles, const double* theta, int32_t reps,
                               mlh_tuning* out);
+
+/* Batches of independent stacks (many unrelated structures at once; the
+ * per-layer independence of the Schur eliminations, Sec. 3.2, and of the
+ * block eliminations, Sec. 3.3, holds across stacks too).  A batch solves
+ * one incident angle per stack with the work of all its stacks sharing
+ * every launch: the fill launches (with refill), the least-squares, Schur
+ * and assembly launches, and level l of every stack's block-tridiagonal
+ * reduction in the launches of level l.  The launch sequence is captured in
+ * a HIP graph and replayed while the batch and its launch choices stay the
+ * same.
+ *
+ * mlh_batch_create: the stacks (n_stacks >= 1, distinct, created on the
+ * context's device) stay owned by the caller and must outlive the batch;
+ * the batch holds their merged fill job tables.  Errors: MLH_E_INVALID_ARG,
+ * MLH_E_NOMEM, MLH_E_DEVICE. */
+mlh_status mlh_batch_create(mlh_ctx ctx, int32_t n_stacks, const mlh_stack* stacks, mlh_batch* out);
+mlh_status mlh_batch_destroy(mlh_batch b);
+
+/* Solve stack s of the batch for incident angle theta[s] (host array of
+ * n_stacks angles, each in (-pi, 0)).  refill = 1 first recomputes every
+ * stack's alpha-independent fill pieces (mlh_stack_refill of all of them,
+ * in three launches); 0 uses the pieces in place.  outputs_on_device as for
+ * mlh_solve.  Outputs, caller-allocated, stacks in batch order:
+ *   aU, aD    the 2K_s+1 Bragg amplitudes of each stack, concatenated
+ *             (sum_s (2K_s+1) complex, interleaved);
+ *   orders    their order labels, concatenated (may be NULL);
+ *   flux_err  [n_stacks] flux errors eq. (86) (may be NULL);
+ *   stack_ms  [n_stacks] host array (may be NULL): device clock time from
+ *             the first launch of the solve to the write of each stack's
+ *             results, in ms (the call then waits for the stream).
+ * Errors: those of mlh_solve (no accuracy report). */
+mlh_status mlh_batch_solve(mlh_batch b, const double* theta, int32_t refill, int32_t outputs_on_device, double* aU,
+                           double* aD, int32_t* orders, double* flux_err, double* stack_ms);
+
+/* Launch choices of a batch (the fields of mlh_tuning; a new batch starts
+ * with {300, 3, 16, 1}), and their autotune: mlh_stack_autotune's search,
+ * timing whole mlh_batch_solve calls (no refill) of the angles theta[s]. */
+mlh_status mlh_batch_get_tuning(mlh_batch b, mlh_tuning* out);
+mlh_status mlh_batch_set_tuning(mlh_batch b, const mlh_tuning* t);
+mlh_status mlh_batch_autotune(mlh_batch b, const double* theta, int32_t reps, mlh_tuning* out);
 
 const char* mlh_last_error(void);
 

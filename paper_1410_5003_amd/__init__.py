@@ -17,7 +17,7 @@ import numpy as np
 from ._lib import (ABI_VERSION, MLH_IFACE_FOURIER, MLH_IFACE_POLYGON, PIECES, MlhError, check,
                    dptr, iptr, lib, mlh_interface, mlh_profile, mlh_stack_desc, mlh_tuning)
 
-__all__ = ["Context", "Stack", "SolveOutput", "MlhError", "lib"]
+__all__ = ["Context", "Stack", "Batch", "SolveOutput", "BatchOutput", "MlhError", "lib"]
 
 
 def _current_stream_handle():
@@ -257,3 +257,69 @@ class Stack:
         check(lib().mlh_debug_get_piece(self._h, which, index, piece, dptr(out),
                                         C.byref(r), C.byref(c)))
         return out.T
+
+
+@dataclass
+class BatchOutput:
+    aU: list              # per stack: (2K_s+1,) complex
+    aD: list
+    orders: list          # per stack: (2K_s+1,) int
+    flux_err: np.ndarray  # (n_stacks,)
+    stack_ms: np.ndarray  # (n_stacks,) device time from the solve's start to each stack's results
+
+
+class Batch:
+    """Independent stacks solved together, one incident angle each, with the
+    per-layer work of all of them sharing every launch (mlh_batch_*)."""
+
+    def __init__(self, ctx: Context, stacks):
+        self.ctx = ctx
+        self.stacks = list(stacks)  # the stacks must outlive the batch
+        self._nK = [2 * s.K + 1 for s in self.stacks]
+        hs = (C.c_void_p * len(self.stacks))(*[s._h.value for s in self.stacks])
+        self._h = C.c_void_p()
+        check(lib().mlh_batch_create(ctx.handle, len(self.stacks), hs, C.byref(self._h)))
+
+    def close(self):
+        if self._h:
+            lib().mlh_batch_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, thetas, refill: bool = False) -> BatchOutput:
+        th = np.ascontiguousarray(thetas, dtype=np.float64)
+        assert th.size == len(self.stacks)
+        tot = sum(self._nK)
+        aU = np.zeros(tot, dtype=np.complex128)
+        aD = np.zeros(tot, dtype=np.complex128)
+        orders = np.zeros(tot, dtype=np.int32)
+        flux = np.zeros(th.size)
+        ms = np.zeros(th.size)
+        check(lib().mlh_batch_solve(self._h, dptr(th), int(bool(refill)), 0, aU.ctypes.data, aD.ctypes.data,
+                                    orders.ctypes.data, flux.ctypes.data, ms.ctypes.data))
+        cut = np.cumsum([0] + self._nK)
+        sp = lambda a: [a[cut[i]:cut[i + 1]] for i in range(len(self._nK))]
+        return BatchOutput(sp(aU), sp(aD), sp(orders), flux, ms)
+
+    def get_tuning(self) -> dict:
+        t = mlh_tuning()
+        check(lib().mlh_batch_get_tuning(self._h, C.byref(t)))
+        return {name: getattr(t, name) for name, _ in t._fields_}
+
+    def set_tuning(self, **kw):
+        t = mlh_tuning()
+        check(lib().mlh_batch_get_tuning(self._h, C.byref(t)))
+        for k, v in kw.items():
+            setattr(t, k, int(v))
+        check(lib().mlh_batch_set_tuning(self._h, C.byref(t)))
+
+    def autotune(self, thetas, reps: int = 1) -> dict:
+        th = np.ascontiguousarray(thetas, dtype=np.float64)
+        t = mlh_tuning()
+        check(lib().mlh_batch_autotune(self._h, dptr(th), int(reps), C.byref(t)))
+        return {name: getattr(t, name) for name, _ in t._fields_}

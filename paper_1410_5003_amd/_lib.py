@@ -78,6 +78,13 @@ SIGNATURES = {
     "mlh_solve_noalloc": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.c_int32, C.c_void_p,
                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "mlh_stack_set_flux_tolerance": (C.c_int32, [C.c_void_p, C.c_double]),
+    "mlh_batch_create": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]),
+    "mlh_batch_destroy": (C.c_int32, [C.c_void_p]),
+    "mlh_batch_solve": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.c_int32, C.c_void_p,
+                                    C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "mlh_batch_get_tuning": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "mlh_batch_set_tuning": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "mlh_batch_autotune": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.c_void_p]),
     "mlh_debug_get_piece": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
                                         C.POINTER(C.c_double), C.POINTER(C.c_int32),
                                         C.POINTER(C.c_int32)]),

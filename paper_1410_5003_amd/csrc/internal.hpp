@@ -131,8 +131,21 @@ void launch_hankel_eval(const double* x, double* out, int n, hipStream_t st);
 
 namespace mlh {
 
+// constants of the stack an angle belongs to
+struct StackConsts {
+  const double* x1;     // Gamma_1 nodes (x, y relative to y0_1, normals)
+  const double* y1;
+  const double* nx1;
+  const double* ny1;
+  const double* xud;    // U / D node abscissae
+  double y0_1;
+  double d, k1, kI1;
+  int N1, NI, Mw, Mud, P, K;
+};
+
 // per-angle radiation rows, right-hand side and Bragg/flux extraction
 struct AngleDesc {
+  StackConsts sc;
   double theta;
   int owner;      // first angle of its system: writes the shared W rows
   cplx* S0;       // layer-1 stacked LS matrix (W_U goes at rows 2 M_w.., cols P..)
@@ -148,35 +161,30 @@ struct AngleDesc {
   cplx* aD;
   int* orders;
   double* flux;
-};
-
-struct StackConsts {
-  const double* x1;     // Gamma_1 nodes (x, y relative to y0_1, normals)
-  const double* y1;
-  const double* nx1;
-  const double* ny1;
-  const double* xud;    // U / D node abscissae
-  double y0_1;
-  double d, k1, kI1;
-  int N1, NI, Mw, Mud, P, K;
+  unsigned long long* tdone;  // null, or: device clock when the angle's results are written
 };
 
 
-void launch_rb_setup(const AngleDesc* d_ang, int nang, StackConsts sc, hipStream_t st);
-void launch_bragg(const AngleDesc* d_ang, int nang, StackConsts sc, hipStream_t st);
+
+void launch_rb_setup(const AngleDesc* d_ang, int nang, hipStream_t st);
+// device clock (wall_clock64) into *p
+void launch_stamp(unsigned long long* p, hipStream_t st);
+void launch_bragg(const AngleDesc* d_ang, int nang, hipStream_t st);
 
 // densities eta of a batch gathered into one row of N_den entries per angle
-struct EtaSeg {      // per interface (the same for every system of a batch)
-  int64_t src_off;   // byte offset of eta_i in a system's workspace
+struct EtaSeg {      // per interface of each system of a batch
+  int64_t src_off;   // byte offset of eta_i in the system's workspace
   int64_t dst_off;   // offset of interface i within an angle's row
   int n;             // n_i
 };
 struct EtaDst {      // per angle
   const char* sys_base;  // its system's workspace
   int col;               // its column in the system's eta blocks
+  int seg0, nseg;        // its system's segments
   cplx* dst;             // its output row (N_den entries)
 };
-void launch_gather_eta(const EtaSeg* d_seg, int nseg, int max_n, const EtaDst* d_dst, int ndst, hipStream_t st);
+// grid: max_seg segments (of at most max_n entries) per angle
+void launch_gather_eta(const EtaSeg* d_seg, int max_seg, int max_n, const EtaDst* d_dst, int ndst, hipStream_t st);
 
 // Fixed workspace of the allocation-free solve: kScratchBytes per device,
 // shared by every such call on that device (calls that overlap on one device

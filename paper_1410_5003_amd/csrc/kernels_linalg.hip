@@ -193,8 +193,9 @@ __device__ inline cplx vert_wavenumber(double k, double kappa) {
   return {0.0, sqrt(-q)};
 }
 
-__global__ __launch_bounds__(256) void rb_setup_kernel(const AngleDesc* __restrict__ ang, StackConsts sc) {
+__global__ __launch_bounds__(256) void rb_setup_kernel(const AngleDesc* __restrict__ ang) {
   const AngleDesc& A = ang[blockIdx.x];
+  const StackConsts& sc = A.sc;
   const int nK = 2 * sc.K + 1;
   const double kappa0 = sc.k1 * cos(A.theta);
   const int n0 = rb_n0(kappa0, sc.d);
@@ -228,8 +229,9 @@ __global__ __launch_bounds__(256) void rb_setup_kernel(const AngleDesc* __restri
 
 // one workgroup per angle: lane q of every wave takes order q, the 8 waves
 // split the density index and their partial sums meet in LDS
-__global__ __launch_bounds__(512) void bragg_kernel(const AngleDesc* __restrict__ ang, StackConsts sc) {
+__global__ __launch_bounds__(512) void bragg_kernel(const AngleDesc* __restrict__ ang) {
   const AngleDesc& A = ang[blockIdx.x];
+  const StackConsts& sc = A.sc;
   const int nK = 2 * sc.K + 1;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const double kappa0 = sc.k1 * cos(A.theta);
@@ -300,6 +302,7 @@ __global__ __launch_bounds__(512) void bragg_kernel(const AngleDesc* __restrict_
     if (lane == 0) {
       const double inc = sc.k1 * fabs(sin(A.theta));
       A.flux[0] = (fl - inc) / inc;
+      if (A.tdone) A.tdone[0] = (unsigned long long)wall_clock64();
     }
   }
 }
@@ -309,11 +312,17 @@ void launch_gemm(const GemmDesc* d_desc, int ndesc, int total_tiles, hipStream_t
     hipLaunchKernelGGL(zgemm_kernel, dim3(std::min(kMaxLaunchBlocks, total_tiles - t0)), dim3(256), 0, st, d_desc,
                        ndesc, t0);
 }
-void launch_rb_setup(const AngleDesc* d_ang, int nang, StackConsts sc, hipStream_t st) {
-  if (nang > 0) hipLaunchKernelGGL(rb_setup_kernel, dim3(nang), dim3(256), 0, st, d_ang, sc);
+__global__ void stamp_kernel(unsigned long long* p) {
+  if (threadIdx.x == 0) p[0] = (unsigned long long)wall_clock64();
 }
-void launch_bragg(const AngleDesc* d_ang, int nang, StackConsts sc, hipStream_t st) {
-  if (nang > 0) hipLaunchKernelGGL(bragg_kernel, dim3(nang), dim3(512), 0, st, d_ang, sc);
+
+void launch_stamp(unsigned long long* p, hipStream_t st) { hipLaunchKernelGGL(stamp_kernel, dim3(1), dim3(64), 0, st, p); }
+
+void launch_rb_setup(const AngleDesc* d_ang, int nang, hipStream_t st) {
+  if (nang > 0) hipLaunchKernelGGL(rb_setup_kernel, dim3(nang), dim3(256), 0, st, d_ang);
+}
+void launch_bragg(const AngleDesc* d_ang, int nang, hipStream_t st) {
+  if (nang > 0) hipLaunchKernelGGL(bragg_kernel, dim3(nang), dim3(512), 0, st, d_ang);
 }
 
 }  // namespace mlh

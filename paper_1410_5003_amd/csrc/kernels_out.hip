@@ -44,8 +44,9 @@ hipError_t scratch_address(int device, char** ptr) {
 
 __global__ __launch_bounds__(256) void gather_eta_kernel(const EtaSeg* __restrict__ seg,
                                                          const EtaDst* __restrict__ dst) {
-  const EtaSeg S = seg[blockIdx.y];
   const EtaDst D = dst[blockIdx.z];
+  if ((int)blockIdx.y >= D.nseg) return;
+  const EtaSeg S = seg[D.seg0 + blockIdx.y];
   const int r = blockIdx.x * 256 + threadIdx.x;
   if (r >= S.n) return;
   const cplx* src = reinterpret_cast<const cplx*>(D.sys_base + S.src_off) + (size_t)D.col * S.n + r;
@@ -53,9 +54,9 @@ __global__ __launch_bounds__(256) void gather_eta_kernel(const EtaSeg* __restric
   stc(D.dst + S.dst_off + r, v.x, v.y);
 }
 
-void launch_gather_eta(const EtaSeg* d_seg, int nseg, int max_n, const EtaDst* d_dst, int ndst, hipStream_t st) {
-  if (nseg <= 0 || ndst <= 0 || max_n <= 0) return;
-  dim3 grid((max_n + 255) / 256, nseg, ndst);
+void launch_gather_eta(const EtaSeg* d_seg, int max_seg, int max_n, const EtaDst* d_dst, int ndst, hipStream_t st) {
+  if (max_seg <= 0 || ndst <= 0 || max_n <= 0) return;
+  dim3 grid((max_n + 255) / 256, max_seg, ndst);
   hipLaunchKernelGGL(gather_eta_kernel, grid, dim3(256), 0, st, d_seg, d_dst);
 }
 

@@ -9,6 +9,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -296,6 +298,33 @@ void build_fourier_curve(const mlh_interface& in, double d, HostCurve& c) {
   }
 }
 
+// Device state solves run in: the workspace, reused across calls that fit
+// it, and the captured launch sequence, replayed while the batch shape and
+// the workspace stay the same (only the descriptor contents change).
+struct Runner {
+  char* wmem = nullptr;
+  size_t wbytes = 0;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<int64_t> g_sig;
+  hipStream_t cap_stream = nullptr;
+  hipStream_t aux_stream = nullptr;  // second stream of the Gauss-Jordan look-ahead
+  std::vector<hipEvent_t> evpool;    // its dependency events
+  int num_cu = 0;                    // compute units of the device
+  // teardown: errors here leave nothing to recover
+  void release() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (aux_stream) (void)hipStreamDestroy(aux_stream);
+    for (hipEvent_t e : evpool) (void)hipEventDestroy(e);
+    if (wmem) (void)hipFree(wmem);
+    gexec = nullptr;
+    cap_stream = aux_stream = nullptr;
+    evpool.clear();
+    wmem = nullptr;
+    wbytes = 0;
+  }
+};
+
 // simple bump allocator over one device arena
 struct Arena {
   char* base = nullptr;
@@ -350,19 +379,12 @@ struct mlh_stack_s {
   // workspace views of the first angle of the last inspection solve
   std::vector<cplx*> dbg_R, dbg_S, dbg_RHS, dbg_eta;
 
-  // captured launch sequence of the solve (replayed while the batch shape and
-  // the workspace stay the same; only the descriptor contents change)
-  hipGraphExec_t gexec = nullptr;
-  hipStream_t cap_stream = nullptr;
-  // second stream of the Gauss-Jordan look-ahead and its dependency events
-  hipStream_t aux_stream = nullptr;
-  std::vector<hipEvent_t> evpool;
-  int num_cu = 0;  // compute units of the device
-  std::vector<int64_t> g_sig;
+  // host copies of the fill job tables (merged into batch launches)
+  std::vector<FillJob> h_fill;
+  std::vector<SelfJob> h_self;
+  std::vector<AlpertJob> h_alp;
 
-  // solve workspace (reused across calls with the same batch size)
-  char* wmem = nullptr;
-  size_t wbytes = 0;
+  Runner run;  // workspace and captured launch sequence of this stack's solves
 };
 
 static size_t cbytes(size_t n) { return n * sizeof(cplx); }
@@ -923,6 +945,9 @@ extern "C" mlh_status mlh_stack_create(mlh_ctx ctx, const mlh_stack_desc* D, mlh
   HIP_TRY(hipMemcpy(s->d_fill, fj.data(), sizeof(FillJob) * fj.size(), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(s->d_self, sj.data(), sizeof(SelfJob) * sj.size(), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(s->d_alp, aj.data(), sizeof(AlpertJob) * aj.size(), hipMemcpyHostToDevice));
+  s->h_fill = fj;
+  s->h_self = sj;
+  s->h_alp = aj;
   mlh_status fs = run_fills(s);
   if (fs == MLH_OK) {
     hipError_t e2 = hipStreamSynchronize(st);
@@ -950,11 +975,7 @@ extern "C" mlh_status mlh_stack_destroy(mlh_stack s) {
   // teardown: errors here leave nothing to recover
   (void)hipSetDevice(s->ctx->device);
   if (s->dmem) (void)hipFree(s->dmem);
-  if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
-  if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
-  if (s->aux_stream) (void)hipStreamDestroy(s->aux_stream);
-  for (hipEvent_t e : s->evpool) (void)hipEventDestroy(e);
-  if (s->wmem) (void)hipFree(s->wmem);
+  s->run.release();
   delete s;
   return MLH_OK;
 }
@@ -965,7 +986,7 @@ extern "C" mlh_status mlh_stack_info(mlh_stack s, int64_t* n_den, int64_t* n_tot
   for (int v : s->n) nd += v;
   if (n_den) *n_den = nd;
   if (n_tot) *n_tot = nd + (int64_t)(s->I + 1) * s->P + 2 * s->nK;
-  if (device_bytes) *device_bytes = (int64_t)(s->dbytes + s->wbytes);
+  if (device_bytes) *device_bytes = (int64_t)(s->dbytes + s->run.wbytes);
   return MLH_OK;
 }
 
@@ -1046,146 +1067,209 @@ struct SolveOpts {
   int stop_phase = 0;            // inspection: stop after this phase (0 = whole solve)
   mlh_profile* prof = nullptr;   // time every launch (one stream, no graph)
   bool on_device = false;        // outputs are device pointers; no host wait
-  double* eta = nullptr;         // optional [n_angles][N_den] complex densities
-  bool check_flux = false;       // report MLH_E_ACCURACY past the stack's flux tolerance
   bool noalloc = false;          // workspace in the context's fixed scratch; no allocation, no graph
+  unsigned long long* tstamp = nullptr;  // device [1 + n_angles]: clock at the start, then per angle at its end
 };
 
-static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta, double* aU, double* aD,
-                             int32_t* orders, double* flux_err, const SolveOpts& opt) {
+// one system of a solve: the angles of one stack whose Bloch phases alpha
+// agree (kappa_0 on one grid of spacing 2 pi/d, Sec. 3.4); they share every
+// matrix and take one right-hand-side column each
+struct SysSpec {
+  mlh_stack_s* s;
+  std::vector<int> ang;  // indices into the call's angle list
+};
+
+// where one angle's results go (host or device memory, per SolveOpts)
+struct AngleOut {
+  double* aU;       // 2K+1 complex
+  double* aD;
+  int32_t* orders;  // 2K+1 labels, may be null
+  double* flux;     // may be null
+  double* eta;      // N_den complex, may be null
+};
+
+static void group_by_alpha(mlh_stack_s* s, int n_angles, const double* theta, int first, std::vector<SysSpec>& out) {
+  std::vector<double> tfrac;
+  const size_t base = out.size();
+  for (int a = 0; a < n_angles; ++a) {
+    const double t = s->d * s->k[0] * std::cos(theta[first + a]) / (2.0 * kPi);
+    const double f = t - std::floor(t);
+    int g = -1;
+    for (size_t q = 0; q < tfrac.size() && g < 0; ++q) {
+      const double dd = std::fabs(f - tfrac[q]);
+      if (std::min(dd, 1.0 - dd) < kAlphaTol) g = (int)q;
+    }
+    if (g < 0) {
+      out.push_back(SysSpec{s, {}});
+      tfrac.push_back(f);
+      g = (int)tfrac.size() - 1;
+    }
+    out[base + g].ang.push_back(first + a);
+  }
+}
+
+// Solve the systems `sys` (of one or several stacks) in batches that share
+// every launch.  theta[a] and outs[a] belong to angle a of the call;
+// h_flux[a] receives each angle's flux error on the host unless the outputs
+// are on the device and no accuracy check asked for them (flux_to_host).
+static mlh_status solve_systems(Runner& RN, mlh_ctx ctx, const mlh_tuning& tune, const std::vector<SysSpec>& sys,
+                                const double* theta, const std::vector<AngleOut>& outs, const SolveOpts& opt,
+                                bool flux_to_host, std::vector<double>& h_flux, mlh_stack_s* inspect) {
   const int stop_phase = opt.stop_phase;
   mlh_profile* const prof = opt.prof;
-  if (!s) return fail(MLH_E_INVALID_ARG, "NULL stack");
-  if (n_angles < 1 || !theta || !aU || !aD) return fail(MLH_E_INVALID_ARG, "mlh_solve: bad arguments");
-  for (int a = 0; a < n_angles; ++a)
-    if (!(theta[a] > -kPi && theta[a] < 0.0)) return fail(MLH_E_INVALID_ARG, "incident angle must lie in (-pi, 0)");
-  HIP_TRY(hipSetDevice(s->ctx->device));
-  hipStream_t st = s->ctx->stream;
-  const int I = s->I, P = s->P, nK = s->nK;
-  const std::vector<int>& n = s->n;
-  int maxn = 0;
-  for (int i = 0; i < I; ++i) maxn = std::max(maxn, n[i]);
-  // ---- angles whose Bloch phases alpha agree (kappa_0 on one grid of spacing
-  //      2 pi/d, Sec. 3.4) share every matrix of the solve: they form one
-  //      system, with one right-hand side column per angle
-  std::vector<std::vector<int>> groups;
-  {
-    std::vector<double> tfrac;
-    for (int a = 0; a < n_angles; ++a) {
-      const double t = s->d * s->k[0] * std::cos(theta[a]) / (2.0 * kPi);
-      const double f = t - std::floor(t);
-      int g = -1;
-      for (size_t q = 0; q < groups.size() && g < 0; ++q) {
-        const double dd = std::fabs(f - tfrac[q]);
-        if (std::min(dd, 1.0 - dd) < kAlphaTol) g = (int)q;
+  HIP_TRY(hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  const int NS = (int)sys.size();
+  bool want_eta = false;
+  for (const AngleOut& o : outs) want_eta = want_eta || o.eta;
+  const bool eta_stage = want_eta && !opt.on_device;  // host densities go through a device row per angle
+  // ---- per-stack shapes
+  struct Shape {
+    const mlh_stack_s* s;
+    int I = 0, maxn = 0;
+    std::vector<int> nL0, nU0;
+    std::vector<int64_t> den_off;  // offset of eta_i in a row of N_den densities
+  };
+  std::vector<Shape> shp;
+  std::vector<int> sidx(NS);
+  for (int b = 0; b < NS; ++b) {
+    int q = -1;
+    for (size_t t = 0; t < shp.size() && q < 0; ++t)
+      if (shp[t].s == sys[b].s) q = (int)t;
+    if (q < 0) {
+      Shape sh;
+      const mlh_stack_s* s = sys[b].s;
+      sh.s = s;
+      sh.I = s->I;
+      sh.nL0.resize(s->I);
+      sh.nU0.resize(s->I);
+      sh.den_off.assign(s->I + 1, 0);
+      for (int i = 0; i < s->I; ++i) {
+        sh.maxn = std::max(sh.maxn, s->n[i]);
+        sh.nL0[i] = i > 0 ? s->n[i - 1] : 0;
+        sh.nU0[i] = i + 1 < s->I ? s->n[i + 1] : 0;
+        sh.den_off[i + 1] = sh.den_off[i] + s->n[i];
       }
-      if (g < 0) {
-        groups.emplace_back();
-        tfrac.push_back(f);
-        g = (int)groups.size() - 1;
-      }
-      groups[g].push_back(a);
+      shp.push_back(std::move(sh));
+      q = (int)shp.size() - 1;
     }
-  }
-  const int n_sys = (int)groups.size();
-  int rmax = 1;
-  for (const auto& g : groups) rmax = std::max(rmax, (int)g.size());
-  std::vector<int64_t> den_off(I + 1, 0);  // offset of eta_i in a row of N_den densities
-  for (int i = 0; i < I; ++i) den_off[i + 1] = den_off[i] + n[i];
-  const int64_t nden = den_off[I];
-  const bool eta_stage = opt.eta && !opt.on_device;  // host densities go through a device row per angle
-  std::vector<int> wmax(I), nL0(I), nU0(I);
-  for (int i = 0; i < I; ++i) {
-    wmax[i] = n[i] + 2 * maxn + rmax;
-    nL0[i] = i > 0 ? n[i - 1] : 0;
-    nU0[i] = i + 1 < I ? n[i + 1] : 0;
+    sidx[b] = q;
   }
   // ---- workspace of one system: two row-block buffers per interface (the
   //      reduction reads one and writes the other), least-squares systems,
   //      eta (one column per angle), Gauss-Jordan scratch per interface,
   //      outputs per angle
-  auto plan = [&](Arena& A, std::vector<size_t>* offs) {
+  auto plan = [&](int b, Arena& A, std::vector<size_t>* offs) {
+    const mlh_stack_s* s = sys[b].s;
+    const Shape& sh = shp[sidx[b]];
+    const int I = sh.I, rb = (int)sys[b].ang.size();
+    const std::vector<int>& n = s->n;
     auto R = [&](size_t bytes) {
       const size_t o = A.reserve(bytes);
       if (offs) offs->push_back(o);
     };
-    for (int i = 0; i < I; ++i) R(cbytes((size_t)n[i] * wmax[i]));
-    for (int i = 0; i < I; ++i) R(cbytes((size_t)n[i] * wmax[i]));
+    for (int w = 0; w < 2; ++w)
+      for (int i = 0; i < I; ++i) R(cbytes((size_t)n[i] * (n[i] + 2 * sh.maxn + rb)));
     for (int j = 0; j <= I; ++j) {
       int m, c, nc;
       layer_dims(s, j, m, c, nc);
       R(cbytes((size_t)(m + c) * (c + nc)));  // [S | RHS]
       R(cbytes((size_t)((c + kHqNb - 1) / kHqNb) * kHqNb * kHqNb));
     }
-    for (int i = 0; i < I; ++i) R(cbytes((size_t)n[i] * rmax));
+    for (int i = 0; i < I; ++i) R(cbytes((size_t)n[i] * rb));
     for (int i = 0; i < I; ++i) {
       const size_t steps = (size_t)(n[i] + kGjeNb - 1) / kGjeNb;
       R(cbytes(steps * kGjeNb * kGjeNb));
       R(sizeof(int) * steps * kGjePivStride);
     }
-    R(cbytes((size_t)2 * nK * rmax));
-    R(sizeof(double) * rmax);
-    R(sizeof(int) * nK * rmax);
-    if (eta_stage) R(cbytes((size_t)nden * rmax));
+    R(cbytes((size_t)2 * s->nK * rb));
+    R(sizeof(double) * rb);
+    R(sizeof(int) * s->nK * rb);
+    if (eta_stage) R(cbytes((size_t)sh.den_off[I] * rb));
   };
-  Arena ar;
-  plan(ar, nullptr);
-  const size_t per = (ar.off + 255) & ~size_t(255);
-  const size_t desc_per = sizeof(AsmJob) * (size_t)(10 * (I + 2)) + sizeof(GemmDesc) * (size_t)(8 * I + 8) +
-                          sizeof(HqDesc) * (size_t)(I + 1) + sizeof(GjeDesc) * (size_t)(I + 1) +
-                          sizeof(GemvDesc) * (size_t)(I + 1) + sizeof(AngleDesc) * (size_t)rmax +
-                          sizeof(EtaSeg) * (size_t)I + sizeof(EtaDst) * (size_t)rmax + 256 * (size_t)(3 * 40 + 18);
-  int B = n_sys;
+  std::vector<size_t> per(NS), dper(NS);
+  for (int b = 0; b < NS; ++b) {
+    Arena A;
+    plan(b, A, nullptr);
+    per[b] = (A.off + 255) & ~size_t(255);
+    const size_t I = (size_t)shp[sidx[b]].I, rb = sys[b].ang.size();
+    dper[b] = sizeof(AsmJob) * (10 * (I + 2)) + sizeof(GemmDesc) * (8 * I + 8) + sizeof(HqDesc) * (I + 1) +
+              sizeof(GjeDesc) * (I + 1) + sizeof(GemvDesc) * (I + 1) + sizeof(AngleDesc) * rb + sizeof(EtaSeg) * I +
+              sizeof(EtaDst) * rb;
+  }
+  // alignment slack of one batch's descriptor uploads (3 lists per level)
+  const size_t slack = (size_t)256 * (3 * 64 + 24) + 4096;
+  // ---- batches of consecutive systems: as many as the memory holds, and at
+  //      most 65535 matrices per launch (one per grid row)
+  size_t budget;
+  if (opt.noalloc) {
+    budget = kScratchBytes - slack;
+  } else {
+    size_t freeb = 0, totb = 0;
+    HIP_TRY(hipMemGetInfo(&freeb, &totb));
+    budget = (size_t)(0.8 * (double)(freeb + RN.wbytes));
+    budget = budget > slack ? budget - slack : 0;
+  }
+  std::vector<int> bstart = {0};
+  size_t need = 0;
+  {
+    size_t acc = 0;
+    int64_t rows = 0;
+    for (int b = 0; b < NS; ++b) {
+      const size_t sz = per[b] + dper[b];
+      const int64_t r = shp[sidx[b]].I + 1;
+      if (b > bstart.back() && (acc + sz > budget || rows + r > 65535)) {
+        bstart.push_back(b);
+        acc = 0;
+        rows = 0;
+      }
+      acc += sz;
+      rows += r;
+      need = std::max(need, acc);
+    }
+    bstart.push_back(NS);
+    need += slack;
+  }
   char* wbase = nullptr;
   if (opt.noalloc) {
-    // the fixed scratch holds as many systems as fit, at least one
-    while (B > 1 && (size_t)B * (per + desc_per) + 4096 > kScratchBytes) B = (B + 1) / 2;
-    while (B > 1 && (size_t)B * (I + 1) > 65535) B = (B + 1) / 2;
-    const size_t need = (size_t)B * (per + desc_per) + 4096;
     if (need > kScratchBytes) {
       char msg[200];
       std::snprintf(msg, sizeof msg,
-                    "one system of this stack needs %.1f MiB of workspace; the allocation-free solve holds at "
+                    "one system of this solve needs %.1f MiB of workspace; the allocation-free solve holds at "
                     "most %.1f MiB", need / 1048576.0, kScratchBytes / 1048576.0);
       return fail(MLH_E_UNSUPPORTED, msg);
     }
-    wbase = s->ctx->scratch;
+    wbase = ctx->scratch;
   } else {
-  size_t freeb = 0, totb = 0;
-  HIP_TRY(hipMemGetInfo(&freeb, &totb));
-  const size_t budget = (size_t)(0.8 * (double)(freeb + s->wbytes));
-  while (B > 1 && (size_t)B * (per + desc_per) > budget) B = (B + 1) / 2;
-  // batched launches put one matrix per grid row: at most 65535 of them
-  while (B > 1 && (size_t)B * (I + 1) > 65535) B = (B + 1) / 2;
-  const size_t need = (size_t)B * (per + desc_per) + 4096;
-  if (need > s->wbytes) {
-    if (s->gexec) {
-      hipGraphExecDestroy(s->gexec);
-      s->gexec = nullptr;
+    if (need > RN.wbytes) {
+      if (RN.gexec) {
+        hipGraphExecDestroy(RN.gexec);
+        RN.gexec = nullptr;
+      }
+      if (RN.wmem) HIP_TRY(hipFree(RN.wmem));
+      RN.wmem = nullptr;
+      RN.wbytes = 0;
+      hipError_t e = hipMalloc((void**)&RN.wmem, need);
+      if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? MLH_E_NOMEM : MLH_E_DEVICE, "solve workspace");
+      RN.wbytes = need;
     }
-    if (s->wmem) HIP_TRY(hipFree(s->wmem));
-    s->wmem = nullptr;
-    s->wbytes = 0;
-    HIP_TRY(hipMalloc((void**)&s->wmem, need));
-    s->wbytes = need;
+    wbase = RN.wmem;
   }
-  wbase = s->wmem;
-  }
-  std::vector<size_t> offs;
-  {
-    Arena A;
-    plan(A, &offs);
-  }
-  std::vector<double> h_flux(n_angles);
-  for (int s0 = 0; s0 < n_sys; s0 += B) {
-    const int nb = std::min(B, n_sys - s0);
+  if (RN.num_cu == 0) HIP_TRY(hipDeviceGetAttribute(&RN.num_cu, hipDeviceAttributeMultiprocessorCount, ctx->device));
+  h_flux.assign(outs.size(), 0.0);
+  for (size_t bi = 0; bi + 1 < bstart.size(); ++bi) {
+    const int b0 = bstart[bi], nb = bstart[bi + 1] - b0;
+    auto SY = [&](int b) -> const SysSpec& { return sys[b0 + b]; };
+    auto SH = [&](int b) -> const Shape& { return shp[sidx[b0 + b]]; };
+    auto R_of = [&](int b) { return (int)SY(b).ang.size(); };
     int nang = 0, rchunk = 1;
+    std::vector<size_t> sys_off(nb + 1, 0);
     for (int b = 0; b < nb; ++b) {
-      nang += (int)groups[s0 + b].size();
-      rchunk = std::max(rchunk, (int)groups[s0 + b].size());
+      nang += R_of(b);
+      rchunk = std::max(rchunk, R_of(b));
+      sys_off[b + 1] = sys_off[b] + per[b0 + b];
     }
-    auto R_of = [&](int b) { return (int)groups[s0 + b].size(); };
-    char* dbase = wbase + (size_t)B * per;
+    char* dbase = wbase + sys_off[nb];
     struct View {
       std::vector<cplx*> W[2], S, Th, RHS, eta, M1;
       std::vector<int*> piv;
@@ -1196,15 +1280,21 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
     };
     std::vector<View> V(nb);
     for (int b = 0; b < nb; ++b) {
-      char* wb = wbase + (size_t)b * per;
+      std::vector<size_t> offs;
+      {
+        Arena A;
+        plan(b0 + b, A, &offs);
+      }
+      char* wb = wbase + sys_off[b];
       size_t k = 0;
       auto C = [&]() { return reinterpret_cast<cplx*>(wb + offs[k++]); };
       View& v = V[b];
+      const int I = SH(b).I;
       for (int i = 0; i < I; ++i) v.W[0].push_back(C());
       for (int i = 0; i < I; ++i) v.W[1].push_back(C());
       for (int j = 0; j <= I; ++j) {
         int m, c, nc;
-        layer_dims(s, j, m, c, nc);
+        layer_dims(SY(b).s, j, m, c, nc);
         cplx* aug = C();
         v.S.push_back(aug);
         v.RHS.push_back(aug + (size_t)(m + c) * c);
@@ -1221,9 +1311,15 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
       if (eta_stage) v.eta_rows = C();
     }
     auto Dblk = [&](int b, int i) { return V[b].W[0][i]; };
-    auto Lblk = [&](int b, int i) { return V[b].W[0][i] + (size_t)n[i] * n[i]; };
-    auto Ublk = [&](int b, int i) { return V[b].W[0][i] + (size_t)n[i] * (n[i] + nL0[i]); };
-    auto Fcol = [&](int b, int i) { return V[b].W[0][i] + (size_t)n[i] * (n[i] + nL0[i] + nU0[i]); };
+    auto Lblk = [&](int b, int i) { return V[b].W[0][i] + (size_t)SY(b).s->n[i] * SY(b).s->n[i]; };
+    auto Ublk = [&](int b, int i) {
+      const std::vector<int>& n = SY(b).s->n;
+      return V[b].W[0][i] + (size_t)n[i] * (n[i] + SH(b).nL0[i]);
+    };
+    auto Fcol = [&](int b, int i) {
+      const std::vector<int>& n = SY(b).s->n;
+      return V[b].W[0][i] + (size_t)n[i] * (n[i] + SH(b).nL0[i] + SH(b).nU0[i]);
+    };
     // ---- descriptors
     // two job lists: the least-squares inputs, which the layer solves wait
     // for, and the blocks of the block-tridiagonal system, which only the
@@ -1290,8 +1386,11 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
     const cplx one = cx(1, 0);
     for (int b = 0; b < nb; ++b) {
       View& v = V[b];
+      const mlh_stack_s* s = SY(b).s;
+      const int I = s->I, P = s->P, nK = s->nK;
+      const std::vector<int>& n = s->n;
       const int rb = R_of(b);
-      const double th = theta[groups[s0 + b][0]];
+      const double th = theta[SY(b).ang[0]];
       const double ph = s->d * s->k[0] * std::cos(th);  // alpha = e^{i ph}, eq. (2)
       const cplx a_m1 = cpow_alpha(ph, -1), a_p1 = cpow_alpha(ph, 1), a_m2 = cpow_alpha(ph, -2);
       const cplx c3[3] = {a_m1, one, a_p1};
@@ -1373,9 +1472,26 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
       int m0, c0, nc0, mI, cI, ncI;
       layer_dims(s, 0, m0, c0, nc0);
       layer_dims(s, I, mI, cI, ncI);
+      StackConsts sc{};
+      sc.x1 = s->gx[0];
+      sc.y1 = s->gy[0];
+      sc.nx1 = s->gnx[0];
+      sc.ny1 = s->gny[0];
+      sc.xud = s->ud_x;
+      sc.y0_1 = s->curves[0].y0;
+      sc.d = s->d;
+      sc.k1 = s->k[0];
+      sc.kI1 = s->k[I];
+      sc.N1 = s->N[0];
+      sc.NI = s->N[I - 1];
+      sc.Mw = s->Mw;
+      sc.Mud = s->Mud;
+      sc.P = P;
+      sc.K = s->K;
       for (int q = 0; q < rb; ++q) {  // one descriptor per angle of the system
         AngleDesc A{};
-        A.theta = theta[groups[s0 + b][q]];
+        A.sc = sc;
+        A.theta = theta[SY(b).ang[q]];
         A.owner = q == 0;
         A.S0 = v.S[0];
         A.ldS0 = m0 + c0;
@@ -1392,6 +1508,7 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
         A.aD = A.aU + nK;
         A.orders = v.orders + (size_t)nK * q;
         A.flux = v.flux + q;
+        A.tdone = opt.tstamp ? opt.tstamp + 1 + SY(b).ang[q] : nullptr;
         angs.push_back(A);
       }
     }
@@ -1414,6 +1531,8 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
     //      a kept neighbour j then becomes
     //        D_j - L_j XU_{e_l} - U_j XL_{e_r},  f_j - L_j xf_{e_l} - U_j xf_{e_r},
     //        L_j' = -L_j XL_{e_l},  U_j' = -U_j XU_{e_r}.
+    //      Each stack of the batch has its own sequence of levels; level l of
+    //      every stack shares the launches of level l.
     struct Level {
       std::vector<GjeDesc> gje;  // orders <= kRhsMaxN16 first (size classes of the right-hand-side kernel)
       int maxn = 0, maxcol = 0, maxrhs = 0;
@@ -1425,11 +1544,157 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
       int backn = 0;
     };
     std::vector<Level> levels;
-    std::vector<int> cur(I, 0), nLc(nL0), nUc(nU0);
-    std::vector<int> S_act(I);
-    for (int i = 0; i < I; ++i) S_act[i] = i;
     auto Wp = [&](int b, int i, int which) { return V[b].W[which][i]; };
-    auto size_classes = [](Level& lv) {
+    auto merge_level = [&](size_t l, Level& lv) {
+      if (levels.size() <= l) levels.resize(l + 1);
+      Level& M = levels[l];
+      for (GemmDesc G : lv.upd) {
+        G.tile_begin += M.upd_tiles;
+        M.upd.push_back(G);
+      }
+      M.upd_tiles += lv.upd_tiles;
+      M.gje.insert(M.gje.end(), lv.gje.begin(), lv.gje.end());
+      M.back.insert(M.back.end(), lv.back.begin(), lv.back.end());
+      M.maxn = std::max(M.maxn, lv.maxn);
+      M.maxcol = std::max(M.maxcol, lv.maxcol);
+      M.maxrhs = std::max(M.maxrhs, lv.maxrhs);
+      M.backn = std::max(M.backn, lv.backn);
+    };
+    for (size_t t = 0; t < shp.size(); ++t) {
+      std::vector<int> bs;  // systems of this batch on stack t
+      for (int b = 0; b < nb; ++b)
+        if (sidx[b0 + b] == (int)t) bs.push_back(b);
+      if (bs.empty()) continue;
+      const Shape& sh = shp[t];
+      const int I = sh.I;
+      const std::vector<int>& n = sh.s->n;
+      std::vector<int> cur(I, 0), nLc(sh.nL0), nUc(sh.nU0);
+      std::vector<int> S_act(I);
+      for (int i = 0; i < I; ++i) S_act[i] = i;
+      for (size_t lidx = 0;; ++lidx) {
+        Level lv;
+        const int m = (int)S_act.size();
+        if (m == 1) {
+          const int j = S_act[0];
+          for (int b : bs) {
+            GjeDesc G{};
+            G.W = Wp(b, j, cur[j]);
+            G.M1 = V[b].M1[j];
+            G.piv = V[b].piv[j];
+            G.n = n[j];
+            G.ncol = n[j] + nLc[j] + nUc[j] + R_of(b);
+            lv.gje.push_back(G);
+            lv.maxcol = std::max(lv.maxcol, G.ncol);
+            lv.maxrhs = std::max(lv.maxrhs, G.ncol - G.n);
+            GemvDesc Gv{};
+            Gv.g = G.W + (size_t)n[j] * (n[j] + nLc[j] + nUc[j]);
+            Gv.y = V[b].eta[j];
+            Gv.n = n[j];
+            Gv.r = R_of(b);
+            lv.back.push_back(Gv);
+          }
+          lv.maxn = n[j];
+          lv.backn = n[j];
+          merge_level(lidx, lv);
+          break;
+        }
+        // eliminate odd positions
+        for (int p = 1; p < m; p += 2) {
+          const int e = S_act[p], left = S_act[p - 1], right = (p + 1 < m) ? S_act[p + 1] : -1;
+          for (int b : bs) {
+            GjeDesc G{};
+            G.W = Wp(b, e, cur[e]);
+            G.M1 = V[b].M1[e];
+            G.piv = V[b].piv[e];
+            G.n = n[e];
+            G.ncol = n[e] + nLc[e] + nUc[e] + R_of(b);
+            lv.gje.push_back(G);
+            lv.maxcol = std::max(lv.maxcol, G.ncol);
+            lv.maxrhs = std::max(lv.maxrhs, G.ncol - G.n);
+            const cplx* X = G.W + (size_t)n[e] * n[e];
+            GemvDesc Gv{};
+            Gv.U1 = X;
+            Gv.m1 = nLc[e];
+            Gv.x1 = V[b].eta[left];
+            Gv.U2 = X + (size_t)n[e] * nLc[e];
+            Gv.m2 = right >= 0 ? nUc[e] : 0;
+            Gv.x2 = right >= 0 ? V[b].eta[right] : nullptr;
+            Gv.g = X + (size_t)n[e] * (nLc[e] + nUc[e]);
+            Gv.y = V[b].eta[e];
+            Gv.n = n[e];
+            Gv.r = R_of(b);
+            lv.back.push_back(Gv);
+          }
+          lv.maxn = std::max(lv.maxn, n[e]);
+          lv.backn = std::max(lv.backn, n[e]);
+        }
+        // update the kept blocks
+        std::vector<int> newL(I), newU(I);
+        for (int p = 0; p < m; p += 2) {
+          const int j = S_act[p];
+          const int el = p >= 1 ? S_act[p - 1] : -1, er = p + 1 < m ? S_act[p + 1] : -1;
+          const int ll = p >= 2 ? S_act[p - 2] : -1, rr = p + 2 < m ? S_act[p + 2] : -1;
+          const int nLn = ll >= 0 ? n[ll] : 0, nUn = rr >= 0 ? n[rr] : 0;
+          newL[j] = nLn;
+          newU[j] = nUn;
+          const int nj = n[j];
+          for (int b : bs) {
+            cplx* Wc = Wp(b, j, cur[j]);
+            cplx* Wn = Wp(b, j, cur[j] ^ 1);
+            const cplx* Lj = Wc + (size_t)nj * nj;
+            const cplx* Uj = Wc + (size_t)nj * (nj + nLc[j]);
+            const cplx* fj = Wc + (size_t)nj * (nj + nLc[j] + nUc[j]);
+            const cplx *XLl = nullptr, *XUl = nullptr, *xfl = nullptr, *XLr = nullptr, *XUr = nullptr, *xfr = nullptr;
+            int nel = 0, ner = 0;
+            if (el >= 0) {
+              nel = n[el];
+              const cplx* X = Wp(b, el, cur[el]) + (size_t)nel * nel;
+              XLl = X;
+              XUl = X + (size_t)nel * nLc[el];
+              xfl = X + (size_t)nel * (nLc[el] + nUc[el]);
+            }
+            if (er >= 0) {
+              ner = n[er];
+              const cplx* X = Wp(b, er, cur[er]) + (size_t)ner * ner;
+              XLr = X;
+              XUr = X + (size_t)ner * nLc[er];
+              xfr = X + (size_t)ner * (nLc[er] + nUc[er]);
+            }
+            // D and f (one or two products each)
+            if (el >= 0 && er >= 0) {
+              gemm_add(lv.upd, lv.upd_tiles, Wn, nj, Wc, nj, nj, nj, Lj, nj, XUl, nel, nel, Uj, nj, XLr, ner, ner);
+              gemm_add(lv.upd, lv.upd_tiles, Wn + (size_t)nj * (nj + nLn + nUn), nj, fj, nj, nj, R_of(b), Lj, nj, xfl,
+                       nel, nel, Uj, nj, xfr, ner, ner);
+            } else if (el >= 0) {
+              gemm_add(lv.upd, lv.upd_tiles, Wn, nj, Wc, nj, nj, nj, Lj, nj, XUl, nel, nel, nullptr, 1, nullptr, 1, 0);
+              gemm_add(lv.upd, lv.upd_tiles, Wn + (size_t)nj * (nj + nLn + nUn), nj, fj, nj, nj, R_of(b), Lj, nj, xfl,
+                       nel, nel, nullptr, 1, nullptr, 1, 0);
+            } else {
+              gemm_add(lv.upd, lv.upd_tiles, Wn, nj, Wc, nj, nj, nj, Uj, nj, XLr, ner, ner, nullptr, 1, nullptr, 1, 0);
+              gemm_add(lv.upd, lv.upd_tiles, Wn + (size_t)nj * (nj + nLn + nUn), nj, fj, nj, nj, R_of(b), Uj, nj, xfr,
+                       ner, ner, nullptr, 1, nullptr, 1, 0);
+            }
+            if (ll >= 0)
+              gemm_add(lv.upd, lv.upd_tiles, Wn + (size_t)nj * nj, nj, nullptr, nj, nj, nLn, Lj, nj, XLl, nel, nel,
+                       nullptr, 1, nullptr, 1, 0);
+            if (rr >= 0)
+              gemm_add(lv.upd, lv.upd_tiles, Wn + (size_t)nj * (nj + nLn), nj, nullptr, nj, nj, nUn, Uj, nj, XUr, ner,
+                       ner, nullptr, 1, nullptr, 1, 0);
+          }
+        }
+        merge_level(lidx, lv);
+        std::vector<int> K;
+        for (int p = 0; p < m; p += 2) {
+          const int j = S_act[p];
+          cur[j] ^= 1;
+          nLc[j] = newL[j];
+          nUc[j] = newU[j];
+          K.push_back(j);
+        }
+        S_act = K;
+      }
+    }
+    for (Level& lv : levels) {
       std::stable_partition(lv.gje.begin(), lv.gje.end(), [](const GjeDesc& G) { return G.n <= kRhsMaxN16; });
       for (const GjeDesc& G : lv.gje) {
         if (G.n <= kRhsMaxN16) {
@@ -1439,130 +1704,6 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
           lv.rhs_large = std::max(lv.rhs_large, G.ncol - G.n);
         }
       }
-    };
-    while (true) {
-      Level lv;
-      const int m = (int)S_act.size();
-      if (m == 1) {
-        const int j = S_act[0];
-        for (int b = 0; b < nb; ++b) {
-          GjeDesc G{};
-          G.W = Wp(b, j, cur[j]);
-          G.M1 = V[b].M1[j];
-          G.piv = V[b].piv[j];
-          G.n = n[j];
-          G.ncol = n[j] + nLc[j] + nUc[j] + R_of(b);
-          lv.gje.push_back(G);
-          lv.maxcol = std::max(lv.maxcol, G.ncol);
-          lv.maxrhs = std::max(lv.maxrhs, G.ncol - G.n);
-          GemvDesc Gv{};
-          Gv.g = G.W + (size_t)n[j] * (n[j] + nLc[j] + nUc[j]);
-          Gv.y = V[b].eta[j];
-          Gv.n = n[j];
-          Gv.r = R_of(b);
-          lv.back.push_back(Gv);
-        }
-        lv.maxn = n[j];
-        lv.backn = n[j];
-        size_classes(lv);
-        levels.push_back(lv);
-        break;
-      }
-      // eliminate odd positions
-      for (int p = 1; p < m; p += 2) {
-        const int e = S_act[p], left = S_act[p - 1], right = (p + 1 < m) ? S_act[p + 1] : -1;
-        for (int b = 0; b < nb; ++b) {
-          GjeDesc G{};
-          G.W = Wp(b, e, cur[e]);
-          G.M1 = V[b].M1[e];
-          G.piv = V[b].piv[e];
-          G.n = n[e];
-          G.ncol = n[e] + nLc[e] + nUc[e] + R_of(b);
-          lv.gje.push_back(G);
-          lv.maxcol = std::max(lv.maxcol, G.ncol);
-          lv.maxrhs = std::max(lv.maxrhs, G.ncol - G.n);
-          const cplx* X = G.W + (size_t)n[e] * n[e];
-          GemvDesc Gv{};
-          Gv.U1 = X;
-          Gv.m1 = nLc[e];
-          Gv.x1 = V[b].eta[left];
-          Gv.U2 = X + (size_t)n[e] * nLc[e];
-          Gv.m2 = right >= 0 ? nUc[e] : 0;
-          Gv.x2 = right >= 0 ? V[b].eta[right] : nullptr;
-          Gv.g = X + (size_t)n[e] * (nLc[e] + nUc[e]);
-          Gv.y = V[b].eta[e];
-          Gv.n = n[e];
-          Gv.r = R_of(b);
-          lv.back.push_back(Gv);
-        }
-        lv.maxn = std::max(lv.maxn, n[e]);
-        lv.backn = std::max(lv.backn, n[e]);
-      }
-      // update the kept blocks
-      std::vector<int> newL(I), newU(I);
-      for (int p = 0; p < m; p += 2) {
-        const int j = S_act[p];
-        const int el = p >= 1 ? S_act[p - 1] : -1, er = p + 1 < m ? S_act[p + 1] : -1;
-        const int ll = p >= 2 ? S_act[p - 2] : -1, rr = p + 2 < m ? S_act[p + 2] : -1;
-        const int nLn = ll >= 0 ? n[ll] : 0, nUn = rr >= 0 ? n[rr] : 0;
-        newL[j] = nLn;
-        newU[j] = nUn;
-        const int nj = n[j];
-        for (int b = 0; b < nb; ++b) {
-          cplx* Wc = Wp(b, j, cur[j]);
-          cplx* Wn = Wp(b, j, cur[j] ^ 1);
-          const cplx* Lj = Wc + (size_t)nj * nj;
-          const cplx* Uj = Wc + (size_t)nj * (nj + nLc[j]);
-          const cplx* fj = Wc + (size_t)nj * (nj + nLc[j] + nUc[j]);
-          const cplx *XLl = nullptr, *XUl = nullptr, *xfl = nullptr, *XLr = nullptr, *XUr = nullptr, *xfr = nullptr;
-          int nel = 0, ner = 0;
-          if (el >= 0) {
-            nel = n[el];
-            const cplx* X = Wp(b, el, cur[el]) + (size_t)nel * nel;
-            XLl = X;
-            XUl = X + (size_t)nel * nLc[el];
-            xfl = X + (size_t)nel * (nLc[el] + nUc[el]);
-          }
-          if (er >= 0) {
-            ner = n[er];
-            const cplx* X = Wp(b, er, cur[er]) + (size_t)ner * ner;
-            XLr = X;
-            XUr = X + (size_t)ner * nLc[er];
-            xfr = X + (size_t)ner * (nLc[er] + nUc[er]);
-          }
-          // D and f (one or two products each)
-          if (el >= 0 && er >= 0) {
-            gemm_add(lv.upd, lv.upd_tiles, Wn, nj, Wc, nj, nj, nj, Lj, nj, XUl, nel, nel, Uj, nj, XLr, ner, ner);
-            gemm_add(lv.upd, lv.upd_tiles, Wn + (size_t)nj * (nj + nLn + nUn), nj, fj, nj, nj, R_of(b), Lj, nj, xfl, nel,
-                     nel, Uj, nj, xfr, ner, ner);
-          } else if (el >= 0) {
-            gemm_add(lv.upd, lv.upd_tiles, Wn, nj, Wc, nj, nj, nj, Lj, nj, XUl, nel, nel, nullptr, 1, nullptr, 1, 0);
-            gemm_add(lv.upd, lv.upd_tiles, Wn + (size_t)nj * (nj + nLn + nUn), nj, fj, nj, nj, R_of(b), Lj, nj, xfl, nel,
-                     nel, nullptr, 1, nullptr, 1, 0);
-          } else {
-            gemm_add(lv.upd, lv.upd_tiles, Wn, nj, Wc, nj, nj, nj, Uj, nj, XLr, ner, ner, nullptr, 1, nullptr, 1, 0);
-            gemm_add(lv.upd, lv.upd_tiles, Wn + (size_t)nj * (nj + nLn + nUn), nj, fj, nj, nj, R_of(b), Uj, nj, xfr, ner,
-                     ner, nullptr, 1, nullptr, 1, 0);
-          }
-          if (ll >= 0)
-            gemm_add(lv.upd, lv.upd_tiles, Wn + (size_t)nj * nj, nj, nullptr, nj, nj, nLn, Lj, nj, XLl, nel, nel,
-                     nullptr, 1, nullptr, 1, 0);
-          if (rr >= 0)
-            gemm_add(lv.upd, lv.upd_tiles, Wn + (size_t)nj * (nj + nLn), nj, nullptr, nj, nj, nUn, Uj, nj, XUr, ner,
-                     ner, nullptr, 1, nullptr, 1, 0);
-        }
-      }
-      size_classes(lv);
-      levels.push_back(lv);
-      std::vector<int> K;
-      for (int p = 0; p < m; p += 2) {
-        const int j = S_act[p];
-        cur[j] ^= 1;
-        nLc[j] = newL[j];
-        nUc[j] = newU[j];
-        K.push_back(j);
-      }
-      S_act = K;
     }
     // Levels with few matrices: the compute units idle beside the panels,
     // whose chain sets the pace, so the update workgroups of each step take
@@ -1570,15 +1711,10 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
     // of the replay after the last step, when a step launch needs at most a
     // few workgroups per compute unit (a workgroup fills a unit; the bound
     // is a launch choice, 300 per 100 units unless tuned).
-    if (s->num_cu == 0) {
-      int dev = 0;
-      HIP_TRY(hipGetDevice(&dev));
-      HIP_TRY(hipDeviceGetAttribute(&s->num_cu, hipDeviceAttributeMultiprocessorCount, dev));
-    }
     for (Level& lv : levels)
       lv.rhs_in_step =
           gje_step_fits(lv.maxn) && (int64_t)gje_step_max_blocks((int)lv.gje.size(), lv.maxn, lv.maxcol, lv.maxrhs) *
-                                            100 <= (int64_t)s->num_cu * s->tune.rhs_in_step_pct;
+                                            100 <= (int64_t)RN.num_cu * tune.rhs_in_step_pct;
     // ---- upload descriptors
     size_t doff = 0;
     std::vector<char> hdesc;
@@ -1599,27 +1735,37 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
     const size_t o_gs = push(gs.data(), sizeof(GemmDesc) * gs.size());
     const size_t o_hq = push(hq.data(), sizeof(HqDesc) * hq.size());
     const size_t o_ang = push(angs.data(), sizeof(AngleDesc) * angs.size());
-    // densities: where eta_i sits in every system's workspace, and each
+    // densities: where eta_i sits in each system's workspace, and each
     // angle's output row
     size_t o_eseg = 0, o_edst = 0;
-    int n_edst = 0;
-    if (opt.eta && stop_phase == 0) {
-      std::vector<EtaSeg> eseg(I);
-      for (int i = 0; i < I; ++i) {
-        eseg[i].src_off = (int64_t)(reinterpret_cast<char*>(V[0].eta[i]) - wbase);
-        eseg[i].dst_off = den_off[i];
-        eseg[i].n = n[i];
-      }
+    int n_edst = 0, max_seg = 0, max_segn = 0;
+    if (want_eta && stop_phase == 0) {
+      std::vector<EtaSeg> eseg;
       std::vector<EtaDst> edst;
-      for (int b = 0; b < nb; ++b)
+      for (int b = 0; b < nb; ++b) {
+        const Shape& sh = SH(b);
+        const int seg0 = (int)eseg.size();
+        for (int i = 0; i < sh.I; ++i) {
+          EtaSeg E{};
+          E.src_off = (int64_t)(reinterpret_cast<char*>(V[b].eta[i]) - (wbase + sys_off[b]));
+          E.dst_off = sh.den_off[i];
+          E.n = sh.s->n[i];
+          eseg.push_back(E);
+          max_segn = std::max(max_segn, E.n);
+        }
+        max_seg = std::max(max_seg, sh.I);
         for (int q = 0; q < R_of(b); ++q) {
+          const AngleOut& o = outs[SY(b).ang[q]];
+          if (!o.eta) continue;
           EtaDst E{};
-          E.sys_base = wbase + (size_t)b * per;
+          E.sys_base = wbase + sys_off[b];
           E.col = q;
-          E.dst = opt.on_device ? reinterpret_cast<cplx*>(opt.eta) + (size_t)nden * groups[s0 + b][q]
-                                : V[b].eta_rows + (size_t)nden * q;
+          E.seg0 = seg0;
+          E.nseg = sh.I;
+          E.dst = opt.on_device ? reinterpret_cast<cplx*>(o.eta) : V[b].eta_rows + (size_t)sh.den_off[sh.I] * q;
           edst.push_back(E);
         }
+      }
       o_eseg = push(eseg.data(), sizeof(EtaSeg) * eseg.size());
       o_edst = push(edst.data(), sizeof(EtaDst) * edst.size());
       n_edst = (int)edst.size();
@@ -1631,34 +1777,19 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
       o_upd[l] = push(levels[l].upd.data(), sizeof(GemmDesc) * levels[l].upd.size());
       o_back[l] = push(levels[l].back.data(), sizeof(GemvDesc) * levels[l].back.size());
     }
-    if (doff > (size_t)B * desc_per) return fail(MLH_E_DEVICE, "descriptor space exhausted");
+    if (dbase + doff > wbase + (opt.noalloc ? kScratchBytes : RN.wbytes))
+      return fail(MLH_E_DEVICE, "descriptor space exhausted");
     HIP_TRY(hipMemcpyAsync(dbase, hdesc.data(), doff, hipMemcpyHostToDevice, st));
-    StackConsts sc{};
-    sc.x1 = s->gx[0];
-    sc.y1 = s->gy[0];
-    sc.nx1 = s->gnx[0];
-    sc.ny1 = s->gny[0];
-    sc.xud = s->ud_x;
-    sc.y0_1 = s->curves[0].y0;
-    sc.d = s->d;
-    sc.k1 = s->k[0];
-    sc.kI1 = s->k[I];
-    sc.N1 = s->N[0];
-    sc.NI = s->N[I - 1];
-    sc.Mw = s->Mw;
-    sc.Mud = s->Mud;
-    sc.P = P;
-    sc.K = s->K;
     // ---- launch sequence (captured into a graph and replayed when possible)
-    if (!opt.noalloc && !s->aux_stream) HIP_TRY(hipStreamCreateWithFlags(&s->aux_stream, hipStreamNonBlocking));
+    if (!opt.noalloc && !RN.aux_stream) HIP_TRY(hipStreamCreateWithFlags(&RN.aux_stream, hipStreamNonBlocking));
     size_t ev_used = 0;
     auto ev_next = [&]() -> hipEvent_t {
-      if (ev_used == s->evpool.size()) {
+      if (ev_used == RN.evpool.size()) {
         hipEvent_t e = nullptr;
         if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
-        s->evpool.push_back(e);
+        RN.evpool.push_back(e);
       }
-      return s->evpool[ev_used++];
+      return RN.evpool[ev_used++];
     };
     auto launch_all = [&](hipStream_t ls, EvTimer& T) -> mlh_status {
       ev_used = 0;
@@ -1673,14 +1804,15 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
       const int nblk = (int)asm_blk.jobs.size(), blk_tiles = (int)asm_blk.tiles;
       // the blocks ride in the panel launches unless those do not run or
       // every launch is timed on its own
-      const bool blk_in_panels = s->tune.asm_in_panels && !prof && (stop_phase == 0 || stop_phase >= 2) && maxc > 0;
+      const bool blk_in_panels = tune.asm_in_panels && !prof && (stop_phase == 0 || stop_phase >= 2) && maxc > 0;
+      if (opt.tstamp && bi == 0) launch_stamp(opt.tstamp, ls);
       tb(prof ? &prof->assemble_ms : nullptr);
       launch_assemble(reinterpret_cast<AsmJob*>(dbase + o_asm_ls), (int)asm_ls.jobs.size(), (int)asm_ls.tiles, ls);
       if (!blk_in_panels) launch_assemble(d_blk, nblk, blk_tiles, ls);
       te();
       const AngleDesc* d_ang = reinterpret_cast<AngleDesc*>(dbase + o_ang);
       tb(prof ? &prof->rb_setup_ms : nullptr);
-      launch_rb_setup(d_ang, nang, sc, ls);
+      launch_rb_setup(d_ang, nang, ls);
       te();
       const HqDesc* d_hq = reinterpret_cast<HqDesc*>(dbase + o_hq);
       const int nhq = (int)hq.size();
@@ -1697,12 +1829,12 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
           te();
           tb(prof ? &prof->ls_update_ms : nullptr);
           launch_hq_update(d_hq, hq_small.n, hq_large.n, k, std::max(hq_small.maxc, hq_large.maxc), ls,
-                           s->tune.ls_row_blocks);
+                           tune.ls_row_blocks);
           te();
         }
         tb(prof ? &prof->ls_rhs_ms : nullptr);
         launch_hq_rhs(d_hq, hq_small.n, hq_large.n, std::max(hq_small.maxncol, hq_large.maxncol),
-                      std::max(hq_small.maxc, hq_large.maxc), ls, s->tune.ls_row_blocks);
+                      std::max(hq_small.maxc, hq_large.maxc), ls, tune.ls_row_blocks);
         te();
       }
       if (stop_phase == 0 || stop_phase >= 3) {
@@ -1726,7 +1858,7 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
           // the second stream.
           const int nsteps = (lv.maxn + kGjeNb - 1) / kGjeNb;
           const int rcol = lv.rhs_in_step ? lv.maxcol : 0;  // > 0: the updates take the right-hand sides
-          const bool narrow = s->tune.gje_rhs_cols == 8;
+          const bool narrow = tune.gje_rhs_cols == 8;
           if (prof && gje_step_fits(lv.maxn)) {  // the graph's step launches, each timed on its own
             for (int st_i = 0; st_i < nsteps; ++st_i) {
               tb(&prof->gje_step_ms);
@@ -1788,10 +1920,10 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
               launch_gje_panel(dg, ng, k, lv.maxn, ls);
               hipEvent_t ep = ev_next();
               HIP_TRY(hipEventRecord(ep, ls));
-              HIP_TRY(hipStreamWaitEvent(s->aux_stream, ep, 0));
-              launch_gje_update(dg, ng, k, lv.maxn, kGjeNb, 1 << 30, s->aux_stream);
+              HIP_TRY(hipStreamWaitEvent(RN.aux_stream, ep, 0));
+              launch_gje_update(dg, ng, k, lv.maxn, kGjeNb, 1 << 30, RN.aux_stream);
               hipEvent_t er = ev_next();
-              HIP_TRY(hipEventRecord(er, s->aux_stream));
+              HIP_TRY(hipEventRecord(er, RN.aux_stream));
               rest2 = rest1;
               rest1 = er;
             }
@@ -1829,10 +1961,10 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
         te();
         if (prof) prof->n_backsub += NL;
         tb(prof ? &prof->bragg_ms : nullptr);
-        launch_bragg(d_ang, nang, sc, ls);
+        launch_bragg(d_ang, nang, ls);
         te();
         if (n_edst > 0)
-          launch_gather_eta(reinterpret_cast<EtaSeg*>(dbase + o_eseg), I, maxn, reinterpret_cast<EtaDst*>(dbase + o_edst),
+          launch_gather_eta(reinterpret_cast<EtaSeg*>(dbase + o_eseg), max_seg, max_segn, reinterpret_cast<EtaDst*>(dbase + o_edst),
                             n_edst, ls);
       }
       HIP_TRY(hipGetLastError());
@@ -1845,19 +1977,22 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
       MLH_TRY(launch_all(st, T));
     } else {
       // every launch shape of the sequence: a cached graph is replayed only
-      // when all of them, and the workspace and its per-system stride (which
-      // places the descriptors and every system after the first), are
-      // unchanged
-      std::vector<int64_t> sig = {nb, B, (int64_t)per, nang, rchunk, (int64_t)doff, (int64_t)(intptr_t)s->wmem, asm_ls.tiles, asm_blk.tiles,
-                                  gtiles, maxc, maxcols, maxncol, (int64_t)hq.size(), (int64_t)gs.size(),
-                                  hq_small.n, hq_small.maxc, hq_small.maxncol, hq_large.maxc, hq_large.maxncol,
-                                  s->tune.rhs_in_step_pct, s->tune.ls_row_blocks, s->tune.gje_rhs_cols,
-                                  s->tune.asm_in_panels, n_edst, (int64_t)o_eseg, (int64_t)o_edst};
+      // when all of them, the workspace and its layout (which places the
+      // descriptors and every system), are unchanged
+      std::vector<int64_t> sig = {nb, nang, rchunk, (int64_t)doff, (int64_t)(intptr_t)wbase, asm_ls.tiles,
+                                  asm_blk.tiles, gtiles, maxc, maxcols, maxncol, (int64_t)hq.size(),
+                                  (int64_t)gs.size(), hq_small.n, hq_small.maxc, hq_small.maxncol, hq_large.maxc,
+                                  hq_large.maxncol, tune.rhs_in_step_pct, tune.ls_row_blocks, tune.gje_rhs_cols,
+                                  tune.asm_in_panels, n_edst, max_seg, max_segn, (int64_t)o_eseg, (int64_t)o_edst,
+                                  (int64_t)(intptr_t)opt.tstamp, bi == 0 ? 1 : 0};
+      for (int b = 0; b <= nb; ++b) sig.push_back((int64_t)sys_off[b]);
       for (const Level& lv : levels) {
         sig.push_back(lv.maxn);
         sig.push_back(lv.maxcol);
         sig.push_back(lv.maxrhs);
         sig.push_back(lv.nsmall);
+        sig.push_back(lv.rhs_small);
+        sig.push_back(lv.rhs_large);
         sig.push_back((int64_t)lv.gje.size());
         sig.push_back(lv.upd_tiles);
         sig.push_back((int64_t)lv.upd.size());
@@ -1865,62 +2000,64 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
         sig.push_back((int64_t)lv.back.size());
         sig.push_back(lv.rhs_in_step ? 1 : 0);
       }
-      if (!(s->gexec && s->g_sig == sig)) {
-        if (s->gexec) {
-          hipGraphExecDestroy(s->gexec);
-          s->gexec = nullptr;
+      if (!(RN.gexec && RN.g_sig == sig)) {
+        if (RN.gexec) {
+          hipGraphExecDestroy(RN.gexec);
+          RN.gexec = nullptr;
         }
-        if (!s->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+        if (!RN.cap_stream) HIP_TRY(hipStreamCreateWithFlags(&RN.cap_stream, hipStreamNonBlocking));
         // the capture stream waits for the descriptor upload
         hipEvent_t up;
         HIP_TRY(hipEventCreateWithFlags(&up, hipEventDisableTiming));
         HIP_TRY(hipEventRecord(up, st));
-        HIP_TRY(hipStreamWaitEvent(s->cap_stream, up, 0));
-        HIP_TRY(hipStreamSynchronize(s->cap_stream));
+        HIP_TRY(hipStreamWaitEvent(RN.cap_stream, up, 0));
+        HIP_TRY(hipStreamSynchronize(RN.cap_stream));
         hipEventDestroy(up);
         hipGraph_t g = nullptr;
-        HIP_TRY(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal));
-        mlh_status ls_ = launch_all(s->cap_stream, T);
-        hipError_t ce = hipStreamEndCapture(s->cap_stream, &g);
+        HIP_TRY(hipStreamBeginCapture(RN.cap_stream, hipStreamCaptureModeThreadLocal));
+        mlh_status ls_ = launch_all(RN.cap_stream, T);
+        hipError_t ce = hipStreamEndCapture(RN.cap_stream, &g);
         if (ls_ != MLH_OK) return ls_;
         if (ce != hipSuccess) return fail(MLH_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
-        hipError_t ie = hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0);
+        hipError_t ie = hipGraphInstantiate(&RN.gexec, g, nullptr, nullptr, 0);
         hipGraphDestroy(g);
         if (ie != hipSuccess) return fail(MLH_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(ie));
-        s->g_sig = sig;
+        RN.g_sig = sig;
       }
-      HIP_TRY(hipGraphLaunch(s->gexec, st));
+      HIP_TRY(hipGraphLaunch(RN.gexec, st));
     }
     if (prof) T.collect();
     if (stop_phase != 0) {
-      s->dbg_R = V[0].W[0];
-      s->dbg_S = V[0].S;
-      s->dbg_RHS = V[0].RHS;
-      s->dbg_eta = V[0].eta;
+      if (inspect) {
+        inspect->dbg_R = V[0].W[0];
+        inspect->dbg_S = V[0].S;
+        inspect->dbg_RHS = V[0].RHS;
+        inspect->dbg_eta = V[0].eta;
+      }
       HIP_TRY(hipStreamSynchronize(st));
       return MLH_OK;
     }
     // ---- results (stream-ordered; the workspace of the next batch is
     //      written only after these copies)
     const hipMemcpyKind kind = opt.on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-    const bool check = opt.check_flux && s->flux_tol > 0;
-    const bool want_flux_host = !opt.on_device || check;
-    for (int b = 0; b < nb; ++b)
+    for (int b = 0; b < nb; ++b) {
+      const int nK = SY(b).s->nK;
+      const int64_t nden = SH(b).den_off[SH(b).I];
       for (int q = 0; q < R_of(b); ++q) {
-        const int a = groups[s0 + b][q];
-        const cplx* o = V[b].out + (size_t)2 * nK * q;
-        HIP_TRY(hipMemcpyAsync(aU + (size_t)2 * nK * a, o, cbytes(nK), kind, st));
-        HIP_TRY(hipMemcpyAsync(aD + (size_t)2 * nK * a, o + nK, cbytes(nK), kind, st));
-        if (orders)
-          HIP_TRY(hipMemcpyAsync(orders + (size_t)nK * a, V[b].orders + (size_t)nK * q, sizeof(int) * nK, kind, st));
-        if (opt.on_device && flux_err)
-          HIP_TRY(hipMemcpyAsync(flux_err + a, V[b].flux + q, sizeof(double), kind, st));
-        if (want_flux_host)
+        const int a = SY(b).ang[q];
+        const AngleOut& o = outs[a];
+        const cplx* src = V[b].out + (size_t)2 * nK * q;
+        HIP_TRY(hipMemcpyAsync(o.aU, src, cbytes(nK), kind, st));
+        HIP_TRY(hipMemcpyAsync(o.aD, src + nK, cbytes(nK), kind, st));
+        if (o.orders)
+          HIP_TRY(hipMemcpyAsync(o.orders, V[b].orders + (size_t)nK * q, sizeof(int) * nK, kind, st));
+        if (opt.on_device && o.flux) HIP_TRY(hipMemcpyAsync(o.flux, V[b].flux + q, sizeof(double), kind, st));
+        if (flux_to_host)
           HIP_TRY(hipMemcpyAsync(&h_flux[a], V[b].flux + q, sizeof(double), hipMemcpyDeviceToHost, st));
-        if (eta_stage)
-          HIP_TRY(hipMemcpyAsync(opt.eta + (size_t)2 * nden * a, V[b].eta_rows + (size_t)nden * q, cbytes(nden),
-                                 hipMemcpyDeviceToHost, st));
+        if (eta_stage && o.eta)
+          HIP_TRY(hipMemcpyAsync(o.eta, V[b].eta_rows + (size_t)nden * q, cbytes(nden), hipMemcpyDeviceToHost, st));
       }
+    }
     if (!opt.on_device) {
       int info[4] = {0, 0, 0, 0};
       HIP_TRY(hipMemcpyAsync(info, d_info, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
@@ -1928,8 +2065,37 @@ static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta,
       if (info[0] != 0) return fail(MLH_E_SINGULAR, "exact zero pivot in the block-tridiagonal solve");
     }
   }
-  const bool check = opt.check_flux && s->flux_tol > 0;
-  if (opt.on_device && check) HIP_TRY(hipStreamSynchronize(st));
+  if (opt.on_device && flux_to_host) HIP_TRY(hipStreamSynchronize(st));
+  return MLH_OK;
+}
+
+static bool theta_ok(double t) { return t > -kPi && t < 0.0; }
+
+// mlh_solve and its variants on one stack: angles grouped by alpha, results
+// at angle a of the caller's arrays
+static mlh_status solve_impl(mlh_stack s, int32_t n_angles, const double* theta, double* aU, double* aD,
+                             int32_t* orders, double* flux_err, double* eta, bool check_flux, const SolveOpts& opt) {
+  if (!s) return fail(MLH_E_INVALID_ARG, "NULL stack");
+  if (n_angles < 1 || !theta || !aU || !aD) return fail(MLH_E_INVALID_ARG, "mlh_solve: bad arguments");
+  for (int a = 0; a < n_angles; ++a)
+    if (!theta_ok(theta[a])) return fail(MLH_E_INVALID_ARG, "incident angle must lie in (-pi, 0)");
+  std::vector<SysSpec> sys;
+  group_by_alpha(s, n_angles, theta, 0, sys);
+  int64_t nden = 0;
+  for (int v : s->n) nden += v;
+  std::vector<AngleOut> outs(n_angles);
+  for (int a = 0; a < n_angles; ++a) {
+    AngleOut& o = outs[a];
+    o.aU = aU + (size_t)2 * s->nK * a;
+    o.aD = aD + (size_t)2 * s->nK * a;
+    o.orders = orders ? orders + (size_t)s->nK * a : nullptr;
+    o.flux = flux_err ? flux_err + a : nullptr;
+    o.eta = eta ? eta + (size_t)2 * nden * a : nullptr;
+  }
+  const bool check = check_flux && s->flux_tol > 0;
+  std::vector<double> h_flux;
+  MLH_TRY(solve_systems(s->run, s->ctx, s->tune, sys, theta, outs, opt, !opt.on_device || check, h_flux, s));
+  if (opt.stop_phase != 0) return MLH_OK;
   if (flux_err && !opt.on_device)
     for (int a = 0; a < n_angles; ++a) flux_err[a] = h_flux[a];
   if (check) {
@@ -1953,9 +2119,7 @@ extern "C" mlh_status mlh_solve(mlh_stack s, int32_t n_angles, const double* the
     return fail(MLH_E_INVALID_ARG, "mlh_solve: outputs_on_device must be 0 or 1");
   SolveOpts o;
   o.on_device = outputs_on_device == 1;
-  o.eta = eta;
-  o.check_flux = true;
-  return solve_impl(s, n_angles, theta, aU, aD, orders, flux_err, o);
+  return solve_impl(s, n_angles, theta, aU, aD, orders, flux_err, eta, true, o);
 }
 
 extern "C" mlh_status mlh_solve_noalloc(mlh_stack s, int32_t n_angles, const double* theta,
@@ -1965,10 +2129,150 @@ extern "C" mlh_status mlh_solve_noalloc(mlh_stack s, int32_t n_angles, const dou
     return fail(MLH_E_INVALID_ARG, "mlh_solve_noalloc: outputs_on_device must be 0 or 1");
   SolveOpts o;
   o.on_device = outputs_on_device == 1;
-  o.eta = eta;
-  o.check_flux = true;
   o.noalloc = true;
-  return solve_impl(s, n_angles, theta, aU, aD, orders, flux_err, o);
+  return solve_impl(s, n_angles, theta, aU, aD, orders, flux_err, eta, true, o);
+}
+
+// ---------------------------------------------------------------------------
+// batches of independent stacks
+// ---------------------------------------------------------------------------
+struct mlh_batch_s {
+  mlh_ctx ctx = nullptr;
+  std::vector<mlh_stack_s*> st;
+  mlh_tuning tune{300, 3, 16, 1};
+  Runner run;
+  std::vector<int64_t> out_off;  // first Bragg order of each stack in the concatenated outputs
+  int64_t n_orders = 0;
+  // merged fill job tables of every stack, and the clock stamps of a solve
+  char* dmem = nullptr;
+  FillJob* d_fill = nullptr;
+  SelfJob* d_self = nullptr;
+  AlpertJob* d_alp = nullptr;
+  int n_fill = 0, fill_tiles = 0, n_self = 0, self_tiles = 0, n_alp = 0, alp_blocks = 0;
+  unsigned long long* d_clock = nullptr;  // [1 + n_stacks]
+  int clock_khz = 0;
+};
+
+extern "C" mlh_status mlh_batch_create(mlh_ctx ctx, int32_t n_stacks, const mlh_stack* stacks, mlh_batch* out) {
+  if (!ctx || !stacks || !out || n_stacks < 1) return fail(MLH_E_INVALID_ARG, "mlh_batch_create: bad arguments");
+  for (int i = 0; i < n_stacks; ++i) {
+    if (!stacks[i]) return fail(MLH_E_INVALID_ARG, "mlh_batch_create: NULL stack");
+    if (stacks[i]->ctx->device != ctx->device)
+      return fail(MLH_E_INVALID_ARG, "mlh_batch_create: every stack must live on the context's device");
+    for (int j = 0; j < i; ++j)
+      if (stacks[j] == stacks[i]) return fail(MLH_E_INVALID_ARG, "mlh_batch_create: a stack appears twice");
+  }
+  HIP_TRY(hipSetDevice(ctx->device));
+  std::unique_ptr<mlh_batch_s> b(new mlh_batch_s());
+  b->ctx = ctx;
+  b->st.assign(stacks, stacks + n_stacks);
+  std::vector<FillJob> fj;
+  std::vector<SelfJob> sj;
+  std::vector<AlpertJob> aj;
+  for (mlh_stack_s* s : b->st) {
+    b->out_off.push_back(b->n_orders);
+    b->n_orders += s->nK;
+    for (FillJob J : s->h_fill) {
+      J.tile_begin += b->fill_tiles;
+      fj.push_back(J);
+    }
+    b->fill_tiles += s->fill_tiles;
+    for (SelfJob J : s->h_self) {
+      J.tile_begin += b->self_tiles;
+      sj.push_back(J);
+    }
+    b->self_tiles += s->self_tiles;
+    for (AlpertJob J : s->h_alp) {
+      J.block_begin += b->alp_blocks;
+      aj.push_back(J);
+    }
+    b->alp_blocks += s->alp_blocks;
+  }
+  b->n_fill = (int)fj.size();
+  b->n_self = (int)sj.size();
+  b->n_alp = (int)aj.size();
+  Arena ar;
+  const size_t o_f = ar.reserve(sizeof(FillJob) * fj.size()), o_s = ar.reserve(sizeof(SelfJob) * sj.size()),
+               o_a = ar.reserve(sizeof(AlpertJob) * aj.size()),
+               o_c = ar.reserve(sizeof(unsigned long long) * (size_t)(n_stacks + 1));
+  hipError_t e = hipMalloc((void**)&b->dmem, ar.off);
+  if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? MLH_E_NOMEM : MLH_E_DEVICE, "batch allocation failed");
+  b->d_fill = reinterpret_cast<FillJob*>(b->dmem + o_f);
+  b->d_self = reinterpret_cast<SelfJob*>(b->dmem + o_s);
+  b->d_alp = reinterpret_cast<AlpertJob*>(b->dmem + o_a);
+  b->d_clock = reinterpret_cast<unsigned long long*>(b->dmem + o_c);
+  mlh_status r = MLH_OK;
+  if (hipMemcpy(b->d_fill, fj.data(), sizeof(FillJob) * fj.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->d_self, sj.data(), sizeof(SelfJob) * sj.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b->d_alp, aj.data(), sizeof(AlpertJob) * aj.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipDeviceGetAttribute(&b->clock_khz, hipDeviceAttributeWallClockRate, ctx->device) != hipSuccess)
+    r = fail(MLH_E_DEVICE, "batch set-up failed");
+  if (r != MLH_OK) {
+    (void)hipFree(b->dmem);
+    return r;
+  }
+  *out = b.release();
+  return MLH_OK;
+}
+
+extern "C" mlh_status mlh_batch_destroy(mlh_batch b) {
+  if (!b) return MLH_OK;
+  (void)hipSetDevice(b->ctx->device);
+  if (b->dmem) (void)hipFree(b->dmem);
+  b->run.release();
+  delete b;
+  return MLH_OK;
+}
+
+extern "C" mlh_status mlh_batch_solve(mlh_batch b, const double* theta, int32_t refill, int32_t outputs_on_device,
+                                      double* aU, double* aD, int32_t* orders, double* flux_err, double* stack_ms) {
+  if (!b || !theta || !aU || !aD) return fail(MLH_E_INVALID_ARG, "mlh_batch_solve: bad arguments");
+  if (outputs_on_device != 0 && outputs_on_device != 1)
+    return fail(MLH_E_INVALID_ARG, "mlh_batch_solve: outputs_on_device must be 0 or 1");
+  if (refill != 0 && refill != 1) return fail(MLH_E_INVALID_ARG, "mlh_batch_solve: refill must be 0 or 1");
+  const int ns = (int)b->st.size();
+  for (int i = 0; i < ns; ++i)
+    if (!theta_ok(theta[i])) return fail(MLH_E_INVALID_ARG, "incident angle must lie in (-pi, 0)");
+  HIP_TRY(hipSetDevice(b->ctx->device));
+  hipStream_t st = b->ctx->stream;
+  if (refill) {  // every stack's alpha-independent pieces, in three launches
+    launch_self(b->d_self, b->n_self, b->self_tiles, kAlpertA, st);
+    launch_alpert(b->d_alp, b->n_alp, b->alp_blocks, kAlpertA, st);
+    launch_fill(b->d_fill, b->n_fill, b->fill_tiles, st);
+    HIP_TRY(hipGetLastError());
+  }
+  std::vector<SysSpec> sys(ns);
+  std::vector<AngleOut> outs(ns);
+  for (int i = 0; i < ns; ++i) {
+    sys[i] = SysSpec{b->st[i], {i}};
+    AngleOut& o = outs[i];
+    o.aU = aU + 2 * b->out_off[i];
+    o.aD = aD + 2 * b->out_off[i];
+    o.orders = orders ? orders + b->out_off[i] : nullptr;
+    o.flux = flux_err ? flux_err + i : nullptr;
+    o.eta = nullptr;
+  }
+  SolveOpts opt;
+  opt.on_device = outputs_on_device == 1;
+  opt.tstamp = b->d_clock;
+  std::vector<double> h_flux;
+  MLH_TRY(solve_systems(b->run, b->ctx, b->tune, sys, theta, outs, opt, !opt.on_device, h_flux, nullptr));
+  if (flux_err && !opt.on_device)
+    for (int i = 0; i < ns; ++i) flux_err[i] = h_flux[i];
+  if (stack_ms) {
+    std::vector<unsigned long long> clk((size_t)ns + 1);
+    HIP_TRY(hipMemcpyAsync(clk.data(), b->d_clock, sizeof(unsigned long long) * clk.size(), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int i = 0; i < ns; ++i)
+      stack_ms[i] = (double)(clk[i + 1] - clk[0]) / (double)b->clock_khz;
+  }
+  return MLH_OK;
+}
+
+extern "C" mlh_status mlh_batch_get_tuning(mlh_batch b, mlh_tuning* out) {
+  if (!b || !out) return fail(MLH_E_INVALID_ARG, "mlh_batch_get_tuning: NULL argument");
+  *out = b->tune;
+  return MLH_OK;
 }
 
 extern "C" mlh_status mlh_stack_set_flux_tolerance(mlh_stack s, double tol) {
@@ -2000,22 +2304,20 @@ extern "C" mlh_status mlh_stack_set_tuning(mlh_stack s, const mlh_tuning* t) {
 }
 
 // One pass of coordinate descent over the fields, each candidate timed as
-// whole mlh_solve calls (host planning, graph launch and result copy: what
-// a caller waits for), fastest of `reps` after one untimed solve that also
-// captures the candidate's graph.
-extern "C" mlh_status mlh_stack_autotune(mlh_stack s, int32_t n_angles, const double* theta, int32_t reps,
-                                         mlh_tuning* out) {
-  if (!s || !theta || n_angles < 1 || reps < 1) return fail(MLH_E_INVALID_ARG, "mlh_stack_autotune: bad arguments");
-  const mlh_tuning start = s->tune;
-  const size_t nc = (size_t)2 * s->nK * n_angles;
-  std::vector<double> aU(nc), aD(nc);
+// whole solve calls (host planning, graph launch and result copy: what a
+// caller waits for), fastest of `reps` after one untimed solve that also
+// captures the candidate's graph.  `tune` is the live choice the solve
+// reads; it ends at the fastest choice, or where it started on an error.
+static mlh_status autotune_loop(mlh_tuning& tune, const std::function<mlh_status()>& solve_once, int reps,
+                                mlh_tuning* out) {
+  const mlh_tuning start = tune;
   auto time_of = [&](const mlh_tuning& t, double& best) -> mlh_status {
-    s->tune = t;
-    MLH_TRY(solve_impl(s, n_angles, theta, aU.data(), aD.data(), nullptr, nullptr, SolveOpts()));
+    tune = t;
+    MLH_TRY(solve_once());
     best = 1e300;
     for (int r = 0; r < reps; ++r) {
       const auto t0 = std::chrono::steady_clock::now();
-      MLH_TRY(solve_impl(s, n_angles, theta, aU.data(), aD.data(), nullptr, nullptr, SolveOpts()));
+      MLH_TRY(solve_once());
       best = std::min(best, std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
     }
     return MLH_OK;
@@ -2045,12 +2347,38 @@ extern "C" mlh_status mlh_stack_autotune(mlh_stack s, int32_t n_angles, const do
   sweep(&mlh_tuning::gje_rhs_cols, cols, 2);
   sweep(&mlh_tuning::asm_in_panels, asmp, 2);
   if (r != MLH_OK) {
-    s->tune = start;
+    tune = start;
     return r;
   }
-  s->tune = best_t;
+  tune = best_t;
   if (out) *out = best_t;
   return MLH_OK;
+}
+
+extern "C" mlh_status mlh_stack_autotune(mlh_stack s, int32_t n_angles, const double* theta, int32_t reps,
+                                         mlh_tuning* out) {
+  if (!s || !theta || n_angles < 1 || reps < 1) return fail(MLH_E_INVALID_ARG, "mlh_stack_autotune: bad arguments");
+  const size_t nc = (size_t)2 * s->nK * n_angles;
+  std::vector<double> aU(nc), aD(nc);
+  return autotune_loop(
+      s->tune,
+      [&]() { return solve_impl(s, n_angles, theta, aU.data(), aD.data(), nullptr, nullptr, nullptr, false, SolveOpts()); },
+      reps, out);
+}
+
+extern "C" mlh_status mlh_batch_set_tuning(mlh_batch b, const mlh_tuning* t) {
+  if (!b || !t) return fail(MLH_E_INVALID_ARG, "mlh_batch_set_tuning: NULL argument");
+  if (!tuning_valid(*t)) return fail(MLH_E_INVALID_ARG, "mlh_batch_set_tuning: value out of range");
+  b->tune = *t;
+  return MLH_OK;
+}
+
+extern "C" mlh_status mlh_batch_autotune(mlh_batch b, const double* theta, int32_t reps, mlh_tuning* out) {
+  if (!b || !theta || reps < 1) return fail(MLH_E_INVALID_ARG, "mlh_batch_autotune: bad arguments");
+  std::vector<double> aU((size_t)2 * b->n_orders), aD((size_t)2 * b->n_orders);
+  return autotune_loop(
+      b->tune, [&]() { return mlh_batch_solve(b, theta, 0, 0, aU.data(), aD.data(), nullptr, nullptr, nullptr); },
+      reps, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -2201,7 +2529,7 @@ extern "C" mlh_status mlh_debug_solve_partial(mlh_stack s, double theta, int32_t
   if (!s || 2 * s->K + 1 > 512) return fail(MLH_E_INVALID_ARG, "bad stack");
   SolveOpts o;
   o.stop_phase = stop_phase;
-  return solve_impl(s, 1, &theta, aU, aD, ord, fl, o);
+  return solve_impl(s, 1, &theta, aU, aD, ord, fl, nullptr, false, o);
 }
 
 extern "C" mlh_status mlh_debug_get_work(mlh_stack s, int32_t which, int32_t index, double* out, int32_t* rows,
@@ -2281,7 +2609,7 @@ extern "C" mlh_status mlh_profile_solve(mlh_stack s, int32_t n_angles, const dou
   std::vector<double> fl(n_angles);
   SolveOpts o;
   o.prof = out;
-  mlh_status r = solve_impl(s, n_angles, theta, aU.data(), aD.data(), ord.data(), fl.data(), o);
+  mlh_status r = solve_impl(s, n_angles, theta, aU.data(), aD.data(), ord.data(), fl.data(), nullptr, false, o);
   HIP_TRY(hipEventRecord(e1, st));
   HIP_TRY(hipEventSynchronize(e1));
   float ms = 0;

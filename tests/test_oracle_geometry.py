@@ -94,3 +94,17 @@ def test_unknown_count_matches_printed_matrix_sizes():
     rows = n_den + 2 * Mw * (I + 1) + 4 * M
     cols = n_den + (I + 1) * P + 2 * (2 * K + 1)
     assert (rows, cols) == (468260, 287922)
+
+
+def test_batch_workload_is_within_the_library_limits():
+    # the 64-stack batch: every interface has 37..512 nodes and every polygon
+    # segment at least 37 (the Alpert window plus its stencil)
+    import workloads
+    stacks = workloads.config4()
+    assert len(stacks) == 64
+    for st in stacks:
+        assert 10 <= st.I <= 200
+        for f in st.interfaces:
+            assert 37 <= f.N <= 512
+            if f.kind == "polygon":
+                assert int(np.min(f.seg_nodes)) >= 37 and int(np.sum(f.seg_nodes)) == f.N

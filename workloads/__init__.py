@@ -7,9 +7,9 @@ oracle and the GPU path can both read the same inputs without sharing any
 method code.
 """
 from .stacks import (Interface, Stack, config1, config1_flat, config2,
-                     config3, homogeneous, kappa_grid_thetas, small_mixed_stack, small_polygon_stack,
+                     config3, config4, homogeneous, kappa_grid_thetas, small_mixed_stack, small_polygon_stack,
                      small_stack)
 
 __all__ = ["Interface", "Stack", "config1", "config1_flat", "config2",
-           "config3", "homogeneous", "kappa_grid_thetas", "small_mixed_stack", "small_polygon_stack",
+           "config3", "config4", "homogeneous", "kappa_grid_thetas", "small_mixed_stack", "small_polygon_stack",
            "small_stack"]
