@@ -243,6 +243,96 @@ def config4(seed: int = 4, n_stacks: int = 64, I_range=(10, 200), N_range=(60, 2
     return out
 
 
+@dataclass
+class ShapeProblem:
+    """A stack parametrised for differentiation: interface i is the graph
+    y = y0_i + sum_{m=1..M} c[i, m-1] sin(2 pi m x/d + psi[i, m-1]) with the
+    phases psi fixed, and layer j has wavenumber k_j = omega n[j].  The
+    parameters are the amplitudes c (I x M) and the indices n (I+1)."""
+    c: np.ndarray
+    psi: np.ndarray
+    n: np.ndarray
+    omega: float
+    base: Stack                    # sizes, lines, proxies; its shapes and k are replaced
+
+    @property
+    def n_params(self) -> int:
+        return self.c.size + self.n.size
+
+    def params(self) -> np.ndarray:
+        """Flat parameter vector: c row by row, then n."""
+        return np.concatenate([self.c.ravel(), self.n])
+
+    def stack(self, p: Optional[np.ndarray] = None) -> Stack:
+        """The stack at parameter vector p (default: the problem's own)."""
+        p = self.params() if p is None else np.asarray(p, float)
+        c = p[:self.c.size].reshape(self.c.shape)
+        n = p[self.c.size:]
+        ifs = []
+        for i, f in enumerate(self.base.interfaces):
+            ifs.append(Interface("fourier", f.y0, n_nodes=f.n_nodes, cos_coef=c[i] * np.sin(self.psi[i]),
+                                 sin_coef=c[i] * np.cos(self.psi[i])))
+        b = self.base
+        return Stack(b.name, b.d, self.omega * n, ifs, y_U=b.y_U, y_D=b.y_D, P=b.P, R=b.R, M_w=b.M_w,
+                     M_ud=b.M_ud, K=b.K, thetas=b.thetas, ls_mu=b.ls_mu)
+
+
+def config5(seed: int = 5, I: int = 100, N: int = 100, P: int = 50, M_w: int = 50, M_ud: int = 60, K: int = 25,
+            omega: float = 10.0, n_modes: int = 5, n_angles: int = 10, spacing: float = 1.5,
+            peak: float = 0.3) -> ShapeProblem:
+    """The differentiation workload: I smooth interfaces, interface i the
+    graph sum_{m=1..5} c_{i,m} sin(m x + psi_{i,m}) (d = 2 pi) about
+    y0 = -spacing i, with c_{i,m} ~ N(0,1) scaled so that the profile's peak
+    is ``peak`` and psi ~ U[0, 2 pi) fixed; n_j ~ U[1,2], k_j = omega n_j;
+    ``n_angles`` angles theta_j = -(pi/3)(j - 1/2)/n_angles.
+
+    Draw order: per interface 5 amplitudes then 5 phases; then I+1 indices."""
+    d = 2 * np.pi
+    rng = np.random.default_rng(seed)
+    c = np.zeros((I, n_modes))
+    psi = np.zeros((I, n_modes))
+    xs = np.linspace(-d / 2, d / 2, 4096, endpoint=False)
+    m = np.arange(1, n_modes + 1)
+    for i in range(I):
+        ci = rng.standard_normal(n_modes)
+        pi_ = rng.uniform(0.0, 2 * np.pi, n_modes)
+        prof = (ci[None, :] * np.sin(2 * np.pi * m[None, :] * xs[:, None] / d + pi_[None, :])).sum(1)
+        c[i] = ci * peak / np.max(np.abs(prof))
+        psi[i] = pi_
+    n = rng.uniform(1.0, 2.0, I + 1)
+    thetas = -(np.pi / 3) * (np.arange(n_angles) + 0.5) / n_angles
+    ifs = [Interface("fourier", -spacing * i, n_nodes=N) for i in range(I)]
+    base = Stack("config5", d, omega * n, ifs, y_U=spacing, y_D=-spacing * (I - 1) - spacing, P=P, R=d,
+                 M_w=M_w, M_ud=M_ud, K=K, thetas=thetas)
+    return ShapeProblem(c, psi, n, omega, base)
+
+
+def small_shape_problem(seed: int = 12, I: int = 3, N: int = 64, P: int = 40, M_w: int = 40, M_ud: int = 40,
+                        K: int = 8, omega: float = 8.0, peak: float = 0.06, n_modes: int = 3,
+                        thetas=(-0.6, -1.1), flat: bool = False) -> ShapeProblem:
+    """Paper-scale (d = 1) version of config5 for tests: spacing 0.5,
+    n_0 = 1 in the top layer, n_j ~ U[1, 1.5] below; ``flat`` zeroes the
+    amplitudes (the phases are still drawn)."""
+    d = 1.0
+    rng = np.random.default_rng(seed)
+    c = np.zeros((I, n_modes))
+    psi = np.zeros((I, n_modes))
+    xs = np.linspace(-d / 2, d / 2, 4096, endpoint=False)
+    m = np.arange(1, n_modes + 1)
+    for i in range(I):
+        ci = rng.standard_normal(n_modes)
+        pi_ = rng.uniform(0.0, 2 * np.pi, n_modes)
+        prof = (ci[None, :] * np.sin(2 * np.pi * m[None, :] * xs[:, None] / d + pi_[None, :])).sum(1)
+        c[i] = 0.0 if flat else ci * peak / np.max(np.abs(prof))
+        psi[i] = pi_
+    n = rng.uniform(1.0, 1.5, I + 1)
+    n[0] = 1.0
+    ifs = [Interface("fourier", -0.5 * i, n_nodes=N) for i in range(I)]
+    base = Stack("small_shape", d, omega * n, ifs, y_U=0.5, y_D=-0.5 * I, P=P, R=1.5 * d, M_w=M_w,
+                 M_ud=M_ud, K=K, thetas=np.asarray(thetas, dtype=float))
+    return ShapeProblem(c, psi, n, omega, base)
+
+
 def small_polygon_stack(flat: bool = False, nper: int = 60, q: float = 6.0, k=(8.0, 10.0, 11.0),
                         P: int = 60, M_w: int = 40, M_ud: int = 40, K: int = 8,
                         height: float = 0.08, theta: float = -np.pi / 5) -> Stack:
