@@ -321,17 +321,19 @@ def bench_batch(args):
     lat = out.stack_ms
     flux = np.abs(out.flux_err)
     # the same stacks one at a time (refill + one-angle solve each, each
-    # timed to its own completion)
+    # timed to its own completion after an untimed solve that captures its
+    # graph); each is created on its own and destroyed after, since every
+    # stack keeps a solve workspace of its own
     plain = []
-    for i, st in enumerate(sts):
-        st.refill()
+    for i, d in enumerate(descs):
+        st = mlh.Stack(ctx, d)
         st.solve(th[i:i + 1])
-    torch.cuda.synchronize()
-    for i, st in enumerate(sts):
+        torch.cuda.synchronize()
         tp = time.perf_counter()
         st.refill()
         st.solve(th[i:i + 1])
         plain.append((time.perf_counter() - tp) * 1e3)
+        st.close()
     plain_total = float(np.sum(plain))
     line = {
         "metric": METRIC, "value": len(descs) / (ms * 1e-3), "unit": "solves/s", "n_gpus": 1, "steps": steps,

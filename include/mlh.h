@@ -262,6 +262,29 @@ mlh_status mlh_stack_set_tuning(mlh_stack s, const mlh_tuning* t);
 mlh_status mlh_stack_autotune(mlh_stack s, int32_t n_angles, const double* theta, int32_t reps,
                               mlh_tuning* out);
 
+/* Field evaluation (Sec. 3.3, last paragraph): solve the stack for incident
+ * angle theta, then evaluate the scattered field u at n_pts targets
+ * (x[t], y[t]) (host arrays; n_pts >= 0).  A target inside layer j takes
+ * that layer's representation eq. (16)-(18): the near-field single- and
+ * double-layer potentials of the interfaces bounding it, each over the
+ * copies l = -1, 0, 1 with phase alpha^l (eq. (14)), plus the layer's proxy
+ * expansion with the strengths of the least-squares solve (eq. (15)).  A
+ * target with y >= y_U takes the Rayleigh-Bloch expansion eq. (7) with the
+ * computed a^U, one with y <= y_D eq. (8) with a^D.  Targets outside the unit
+ * cell are mapped into it by quasi-periodicity (eq. (6)).  The incident wave
+ * eq. (1) is not included: the total field is u plus the incident wave in
+ * layer 1 and above U.  The potentials use the plain quadrature of the
+ * off-diagonal Nystrom entries: spectrally accurate a few node spacings
+ * away from the interfaces, not corrected closer to them.
+ * Outputs: u [n_pts] complex (interleaved); layer [n_pts] region of each
+ * target, -1 above U, 0..I the layers top to bottom, I+1 below D (may be
+ * NULL); host or device memory per outputs_on_device (the call returns
+ * once they are written either way).  The stack's solve workspace then
+ * holds this angle's solution.  Errors: MLH_E_INVALID_ARG (also for a
+ * non-finite target), MLH_E_NOMEM, MLH_E_DEVICE, those of mlh_solve. */
+mlh_status mlh_field(mlh_stack s, double theta, int64_t n_pts, const double* x, const double* y,
+                     int32_t outputs_on_device, double* u, int32_t* layer);
+
 /* Batches of independent stacks (many unrelated structures at once; the
  * per-layer independence of the Schur eliminations, Sec. 3.2, and of the
  * block eliminations, Sec. 3.3, holds across stacks too).  A batch solves

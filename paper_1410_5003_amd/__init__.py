@@ -192,6 +192,19 @@ class Stack:
                               ptr(flux_err, torch.float64, (na,)),
                               ptr(eta, torch.complex128, (na, self.info()["n_den"]))))
 
+    def field(self, theta: float, x, y):
+        """Scattered field at the targets (x, y) after solving for ``theta``
+        (mlh_field): returns (u complex, region int32: -1 above U, 0..I the
+        layers, I+1 below D)."""
+        xs = np.ascontiguousarray(np.ravel(x), dtype=np.float64)
+        ys = np.ascontiguousarray(np.ravel(y), dtype=np.float64)
+        assert xs.size == ys.size
+        u = np.zeros(xs.size, dtype=np.complex128)
+        reg = np.zeros(xs.size, dtype=np.int32)
+        check(lib().mlh_field(self._h, float(theta), xs.size, dptr(xs), dptr(ys), 0, u.ctypes.data,
+                              reg.ctypes.data))
+        return u, reg
+
     def set_flux_tolerance(self, tol: float):
         """Report MLH_E_ACCURACY from solves whose |flux error| exceeds tol
         (0 turns the check off)."""

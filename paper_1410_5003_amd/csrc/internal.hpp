@@ -186,6 +186,58 @@ struct EtaDst {      // per angle
 // grid: max_seg segments (of at most max_n entries) per angle
 void launch_gather_eta(const EtaSeg* d_seg, int max_seg, int max_n, const EtaDst* d_dst, int ndst, hipStream_t st);
 
+// ---------------------------------------------------------------------------
+// field evaluation (kernels_field.hip)
+// ---------------------------------------------------------------------------
+// c = -X[0:P, 0:n0] eta0 - X[0:P, n0:n0+n1] eta1 for one layer
+struct ProxyStrengthJob {
+  const cplx* X;  // least-squares solution, ld ldX
+  const cplx* eta0;
+  const cplx* eta1;
+  cplx* c;        // P proxy strengths
+  int ldX, n0, n1, P;
+};
+struct FieldCurve {  // one bounding interface of a layer (N = 0: none)
+  const double* x;
+  const double* y;   // relative to y0
+  const double* nx;
+  const double* ny;
+  const double* w;
+  const cplx* eta;   // [tau; sigma], 2N entries
+  double y0;
+  int N;
+};
+struct FieldRegion {
+  int kind;          // 0: a layer; 1: above U; 2: below D
+  int label;         // -1 above U, 0..I the layers, I+1 below D
+  double k;          // the region's wavenumber
+  FieldCurve above, below;
+  const double* px;  // proxies (y relative to centre)
+  const double* py;
+  const double* pnx;
+  const double* pny;
+  double centre;
+  const cplx* coef;  // proxy strengths of the layer
+  const cplx* amp;   // kind 1 / 2: Bragg amplitudes a^U / a^D
+  double yline;      // kind 1 / 2: y_U / y_D
+};
+struct FieldTarget {  // a target mapped into the unit cell
+  double x, y;
+  double ph_re, ph_im;  // alpha^m of its cell
+  int64_t idx;          // position in the caller's arrays
+};
+struct FieldTile {
+  int region, first, count;
+};
+struct FieldConsts {
+  cplx alpha_pow[3];  // alpha^{-1}, 1, alpha
+  double d, kappa0;
+  int n0, K, nK, P;
+};
+void launch_proxy_strength(const ProxyStrengthJob* d_jobs, int njobs, hipStream_t st);
+void launch_field(const FieldTile* d_tiles, int ntiles, const FieldRegion* d_regions, const FieldTarget* d_tgt,
+                  double* u, int* layer_out, const FieldConsts& fc, hipStream_t st);
+
 // Fixed workspace of the allocation-free solve: kScratchBytes per device,
 // shared by every such call on that device (calls that overlap on one device
 // race).  scratch_address returns the device's own copy; the device must be

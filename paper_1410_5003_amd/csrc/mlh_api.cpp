@@ -1069,6 +1069,7 @@ struct SolveOpts {
   bool on_device = false;        // outputs are device pointers; no host wait
   bool noalloc = false;          // workspace in the context's fixed scratch; no allocation, no graph
   unsigned long long* tstamp = nullptr;  // device [1 + n_angles]: clock at the start, then per angle at its end
+  bool keep_views = false;       // leave the first system's workspace views in the inspected stack
 };
 
 // one system of a solve: the angles of one stack whose Bloch phases alpha
@@ -2058,6 +2059,12 @@ static mlh_status solve_systems(Runner& RN, mlh_ctx ctx, const mlh_tuning& tune,
           HIP_TRY(hipMemcpyAsync(o.eta, V[b].eta_rows + (size_t)nden * q, cbytes(nden), hipMemcpyDeviceToHost, st));
       }
     }
+    if (opt.keep_views && inspect && bi == 0) {
+      inspect->dbg_R = V[0].W[0];
+      inspect->dbg_S = V[0].S;
+      inspect->dbg_RHS = V[0].RHS;
+      inspect->dbg_eta = V[0].eta;
+    }
     if (!opt.on_device) {
       int info[4] = {0, 0, 0, 0};
       HIP_TRY(hipMemcpyAsync(info, d_info, sizeof(int) * 4, hipMemcpyDeviceToHost, st));
@@ -2131,6 +2138,175 @@ extern "C" mlh_status mlh_solve_noalloc(mlh_stack s, int32_t n_angles, const dou
   o.on_device = outputs_on_device == 1;
   o.noalloc = true;
   return solve_impl(s, n_angles, theta, aU, aD, orders, flux_err, eta, true, o);
+}
+
+// ---------------------------------------------------------------------------
+// field evaluation
+// ---------------------------------------------------------------------------
+extern "C" mlh_status mlh_field(mlh_stack s, double theta, int64_t n_pts, const double* x, const double* y,
+                                int32_t outputs_on_device, double* u, int32_t* layer) {
+  if (!s) return fail(MLH_E_INVALID_ARG, "NULL stack");
+  if (!theta_ok(theta)) return fail(MLH_E_INVALID_ARG, "incident angle must lie in (-pi, 0)");
+  if (outputs_on_device != 0 && outputs_on_device != 1)
+    return fail(MLH_E_INVALID_ARG, "mlh_field: outputs_on_device must be 0 or 1");
+  if (n_pts < 0 || (n_pts > 0 && (!x || !y || !u))) return fail(MLH_E_INVALID_ARG, "mlh_field: bad arguments");
+  for (int64_t t = 0; t < n_pts; ++t)
+    if (!std::isfinite(x[t]) || !std::isfinite(y[t])) return fail(MLH_E_INVALID_ARG, "mlh_field: non-finite target");
+  const int I = s->I, P = s->P, nK = s->nK;
+  const double d = s->d;
+  // ---- the solve, its workspace left in place
+  std::vector<double> aU(2 * nK), aD(2 * nK), fl(1);
+  std::vector<int32_t> ord(nK);
+  {
+    SolveOpts o;
+    o.keep_views = true;
+    MLH_TRY(solve_impl(s, 1, &theta, aU.data(), aD.data(), ord.data(), fl.data(), nullptr, false, o));
+  }
+  if (n_pts == 0) return MLH_OK;
+  HIP_TRY(hipSetDevice(s->ctx->device));
+  hipStream_t st = s->ctx->stream;
+  // ---- targets into the unit cell, by region (-1 above U, layers, I+1 below D)
+  const double ph = d * s->k[0] * std::cos(theta);  // alpha = e^{i ph}
+  std::vector<int> reg(n_pts);
+  std::vector<FieldTarget> tg(n_pts);
+  std::vector<int64_t> count(I + 3, 0);
+  for (int64_t t = 0; t < n_pts; ++t) {
+    const double m = std::floor((x[t] + 0.5 * d) / d);
+    const double xc = x[t] - m * d;
+    int r;
+    if (y[t] >= s->yU) {
+      r = -1;
+    } else if (y[t] <= s->yD) {
+      r = I + 1;
+    } else {  // heights decrease with the interface index at every x
+      int lo = 0, hi = I;  // first interface below the point
+      while (lo < hi) {
+        const int mid = (lo + hi) / 2;
+        if (y[t] > s->curves[mid].height(xc))
+          hi = mid;
+        else
+          lo = mid + 1;
+      }
+      r = lo;
+    }
+    reg[t] = r;
+    FieldTarget& T = tg[t];
+    T.x = xc;
+    T.y = y[t];
+    T.ph_re = std::cos(m * ph);
+    T.ph_im = std::sin(m * ph);
+    T.idx = t;
+    ++count[r + 1];
+  }
+  std::vector<int64_t> start(I + 4, 0);
+  for (int r = 0; r < I + 3; ++r) start[r + 1] = start[r] + count[r];
+  std::vector<FieldTarget> sorted(n_pts);
+  {
+    std::vector<int64_t> pos(start.begin(), start.end() - 1);
+    for (int64_t t = 0; t < n_pts; ++t) sorted[pos[reg[t] + 1]++] = tg[t];
+  }
+  std::vector<FieldTile> tiles;
+  for (int r = 0; r < I + 3; ++r)
+    for (int64_t f = start[r]; f < start[r + 1]; f += 256)
+      tiles.push_back(FieldTile{r, (int)f, (int)std::min<int64_t>(256, start[r + 1] - f)});
+  if (n_pts > (int64_t)INT32_MAX - 256) return fail(MLH_E_UNSUPPORTED, "mlh_field: too many targets");
+  // ---- device buffer: targets, tiles, regions, proxy jobs, strengths,
+  //      amplitudes, and the outputs when the caller's are on the host
+  Arena ar;
+  const size_t o_tg = ar.reserve(sizeof(FieldTarget) * n_pts), o_ti = ar.reserve(sizeof(FieldTile) * tiles.size()),
+               o_rg = ar.reserve(sizeof(FieldRegion) * (I + 3)), o_pj = ar.reserve(sizeof(ProxyStrengthJob) * (I + 1)),
+               o_cf = ar.reserve(cbytes((size_t)(I + 1) * P)), o_am = ar.reserve(cbytes(2 * (size_t)nK)),
+               o_u = outputs_on_device ? 0 : ar.reserve(cbytes(n_pts)),
+               o_l = (outputs_on_device || !layer) ? 0 : ar.reserve(sizeof(int) * n_pts);
+  char* buf = nullptr;
+  hipError_t e = hipMalloc((void**)&buf, ar.off);
+  if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? MLH_E_NOMEM : MLH_E_DEVICE, "mlh_field: allocation");
+  struct Free {
+    char* p;
+    ~Free() { (void)hipFree(p); }
+  } guard{buf};
+  cplx* coef = reinterpret_cast<cplx*>(buf + o_cf);
+  cplx* amp = reinterpret_cast<cplx*>(buf + o_am);
+  std::vector<ProxyStrengthJob> pj(I + 1);
+  std::vector<FieldRegion> rg(I + 3);
+  for (int j = 0; j <= I; ++j) {
+    int m, c, nc;
+    layer_dims(s, j, m, c, nc);
+    ProxyStrengthJob& J = pj[j];
+    J.X = s->dbg_RHS[j];
+    J.ldX = m + c;
+    J.eta0 = j > 0 ? s->dbg_eta[j - 1] : s->dbg_eta[0];
+    J.n0 = j > 0 ? s->n[j - 1] : s->n[0];
+    J.eta1 = (j > 0 && j < I) ? s->dbg_eta[j] : nullptr;
+    J.n1 = (j > 0 && j < I) ? s->n[j] : 0;
+    J.c = coef + (size_t)j * P;
+    J.P = P;
+    FieldRegion& R = rg[j + 1];
+    R.kind = 0;
+    R.label = j;
+    R.k = s->k[j];
+    auto curve = [&](int i) {
+      FieldCurve C{};
+      if (i < 0 || i >= I) return C;
+      C.x = s->gx[i];
+      C.y = s->gy[i];
+      C.nx = s->gnx[i];
+      C.ny = s->gny[i];
+      C.w = s->gw[i];
+      C.eta = s->dbg_eta[i];
+      C.y0 = s->curves[i].y0;
+      C.N = s->N[i];
+      return C;
+    };
+    R.above = curve(j - 1);
+    R.below = curve(j);
+    R.px = s->px[j];
+    R.py = s->py[j];
+    R.pnx = s->pnx[j];
+    R.pny = s->pny[j];
+    R.centre = s->centre[j];
+    R.coef = J.c;
+  }
+  rg[0].kind = 1;
+  rg[0].label = -1;
+  rg[0].k = s->k[0];
+  rg[0].amp = amp;
+  rg[0].yline = s->yU;
+  rg[I + 2].kind = 2;
+  rg[I + 2].label = I + 1;
+  rg[I + 2].k = s->k[I];
+  rg[I + 2].amp = amp + nK;
+  rg[I + 2].yline = s->yD;
+  std::vector<double> amps(aU);
+  amps.insert(amps.end(), aD.begin(), aD.end());
+  HIP_TRY(hipMemcpyAsync(buf + o_tg, sorted.data(), sizeof(FieldTarget) * n_pts, hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(buf + o_ti, tiles.data(), sizeof(FieldTile) * tiles.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(buf + o_rg, rg.data(), sizeof(FieldRegion) * rg.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(buf + o_pj, pj.data(), sizeof(ProxyStrengthJob) * pj.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(amp, amps.data(), cbytes(2 * (size_t)nK), hipMemcpyHostToDevice, st));
+  FieldConsts fc{};
+  fc.alpha_pow[0] = cpow_alpha(ph, -1);
+  fc.alpha_pow[1] = cx(1.0, 0.0);
+  fc.alpha_pow[2] = cpow_alpha(ph, 1);
+  fc.d = d;
+  fc.kappa0 = s->k[0] * std::cos(theta);
+  fc.K = s->K;
+  fc.nK = nK;
+  fc.n0 = ord[0] + s->K;  // the solve's own order window
+  fc.P = P;
+  launch_proxy_strength(reinterpret_cast<ProxyStrengthJob*>(buf + o_pj), I + 1, st);
+  double* ud = outputs_on_device ? u : reinterpret_cast<double*>(buf + o_u);
+  int* ld = outputs_on_device ? layer : (layer ? reinterpret_cast<int*>(buf + o_l) : nullptr);
+  launch_field(reinterpret_cast<FieldTile*>(buf + o_ti), (int)tiles.size(), reinterpret_cast<FieldRegion*>(buf + o_rg),
+               reinterpret_cast<FieldTarget*>(buf + o_tg), ud, ld, fc, st);
+  HIP_TRY(hipGetLastError());
+  if (!outputs_on_device) {
+    HIP_TRY(hipMemcpyAsync(u, ud, cbytes(n_pts), hipMemcpyDeviceToHost, st));
+    if (layer) HIP_TRY(hipMemcpyAsync(layer, ld, sizeof(int) * n_pts, hipMemcpyDeviceToHost, st));
+  }
+  // the buffer is freed on return: wait for the work that reads it
+  HIP_TRY(hipStreamSynchronize(st));
+  return MLH_OK;
 }
 
 // ---------------------------------------------------------------------------
