@@ -285,6 +285,25 @@ mlh_status mlh_stack_autotune(mlh_stack s, int32_t n_angles, const double* theta
 mlh_status mlh_field(mlh_stack s, double theta, int64_t n_pts, const double* x, const double* y,
                      int32_t outputs_on_device, double* u, int32_t* layer);
 
+/* Gradient of J = sum_a e^U_0(theta[a]), the zeroth-order reflected
+ * efficiencies (eq. (86); e^U_0 = |a^U_0|^2 since k^U_0 = k_1 |sin theta|),
+ * with respect to the layer wavenumbers k_2..k_{I+1}, by the adjoint of the
+ * solve (Sec. 3.2-3.3 transposed): the forward solve; the transposed
+ * block-tridiagonal solve A'^T z = w with w the row of X_1 that yields a^U_0;
+ * the least-squares adjoint vectors l_j = (Q'_j^+)^T v_j from the layers'
+ * QR factors; and the wavenumber derivatives of every alpha-independent fill
+ * piece, recomputed into a scratch arena (dS/dk = -g1/(2 pi k), dD/dk =
+ * n'.dv (i/4) k H0, ...; the self blocks with the Alpert correction applied
+ * to the derivative kernels) and contracted with the adjoint and forward
+ * vectors.  The incident medium's k_1 also sets the Bloch phase and the
+ * Rayleigh-Bloch orders; its derivative is not formed (grad_k[0] = NaN).
+ * theta: n_angles host angles in (-pi, 0), all in one batch of systems.
+ * Outputs (host): J_out (may be NULL) and grad_k[I+1].  Smooth and
+ * cornered interfaces alike.  Errors: MLH_E_INVALID_ARG (also when the
+ * zeroth order leaves the window), MLH_E_UNSUPPORTED (too many angles for
+ * one batch), MLH_E_NOMEM, MLH_E_DEVICE. */
+mlh_status mlh_adjoint(mlh_stack s, int32_t n_angles, const double* theta, double* J_out, double* grad_k);
+
 /* Batches of independent stacks (many unrelated structures at once; the
  * per-layer independence of the Schur eliminations, Sec. 3.2, and of the
  * block eliminations, Sec. 3.3, holds across stacks too).  A batch solves

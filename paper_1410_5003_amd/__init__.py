@@ -129,6 +129,7 @@ class Stack:
         d.M_w, d.M_ud, d.K = int(desc.M_w), int(desc.M_ud), int(desc.K)
         d.ls_mu = float(getattr(desc, "ls_mu", 0.0))
         self.K = int(desc.K)
+        self._k = np.array(k)
         self._h = C.c_void_p()
         check(lib().mlh_stack_create(ctx.handle, C.byref(d), C.byref(self._h)))
         self._keep = []
@@ -204,6 +205,16 @@ class Stack:
         check(lib().mlh_field(self._h, float(theta), xs.size, dptr(xs), dptr(ys), 0, u.ctypes.data,
                               reg.ctypes.data))
         return u, reg
+
+    def adjoint(self, thetas):
+        """J = sum of the zeroth-order reflected efficiencies at ``thetas``
+        and dJ/dk_j for the layers below the top one (mlh_adjoint; entry 0
+        is NaN)."""
+        th = np.ascontiguousarray(np.atleast_1d(thetas), dtype=np.float64)
+        g = np.zeros(len(self._k))
+        J = C.c_double()
+        check(lib().mlh_adjoint(self._h, th.size, dptr(th), C.byref(J), dptr(g)))
+        return J.value, g
 
     def set_flux_tolerance(self, tol: float):
         """Report MLH_E_ACCURACY from solves whose |flux error| exceeds tol
@@ -336,3 +347,35 @@ class Batch:
         t = mlh_tuning()
         check(lib().mlh_batch_autotune(self._h, dptr(th), int(reps), C.byref(t)))
         return {name: getattr(t, name) for name, _ in t._fields_}
+
+
+class EfficiencyObjective:
+    """J(n) = sum over the angles of the zeroth-order reflected efficiency of
+    a workloads.ShapeProblem at layer indices n, as a torch.autograd.Function:
+    the forward pass solves on the GPU, the backward pass returns
+    dJ/dn_j = omega dJ/dk_j from the adjoint (mlh_adjoint).  The top layer's
+    index is the incident medium's and gets no gradient (zero)."""
+
+    @staticmethod
+    def function():
+        import torch
+
+        class _F(torch.autograd.Function):
+            @staticmethod
+            def forward(fctx, n, problem, ctx, thetas):
+                p = problem.params()
+                p[problem.c.size:] = n.detach().cpu().numpy()
+                st = Stack(ctx, problem.stack(p))
+                J, gk = st.adjoint(thetas)
+                st.close()
+                g = problem.omega * gk
+                g[0] = 0.0
+                fctx.save_for_backward(torch.as_tensor(g, dtype=n.dtype))
+                return torch.as_tensor(J, dtype=n.dtype)
+
+            @staticmethod
+            def backward(fctx, gout):
+                (g,) = fctx.saved_tensors
+                return gout * g, None, None, None
+
+        return _F

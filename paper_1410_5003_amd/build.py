@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmlh.so")
 SOURCES = ["mlh_api.cpp", "kernels_fill.hip", "kernels_linalg.hip", "kernels_gje.hip", "kernels_hq.hip",
-           "kernels_out.hip", "kernels_field.hip"]
+           "kernels_out.hip", "kernels_field.hip", "kernels_adjoint.hip"]
 ARCH = os.environ.get("MLH_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=" + ARCH,
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -188,6 +188,29 @@ __device__ inline Kern4 lp_kernels(double k, double r2, double nd, double npd, d
   return o;
 }
 
+// Wavenumber derivatives dK/dk of the four kernels at fixed geometry, from
+// dH0(kr)/dk = -r H1 and d[x H1(x)]/dx = x H0 (so that d g1/dk = (i pi/2) k r^2 H0):
+//   dS/dk  = -g1/(2 pi k)
+//   dD/dk  = npd (i/4) k H0,   dD*/dk = -nd (i/4) k H0
+//   dT/dk  = nn (i/4) k H0 - nd npd k g1/(2 pi r^2)
+// The k-independent singular parts of S, D, D*, T drop out: dS/dk is bounded
+// and dT/dk is log-singular, like the self-block difference kernels.
+__device__ inline Kern4 lp_kernels_dk(double k, double r2, double nd, double npd, double nn) {
+  const double r = sqrt(r2);
+  cplx h0, gm;
+  hankel_pieces(k * r, h0, gm);
+  const cplx g1 = {1.0 + gm.re, gm.im};
+  const cplx ikh0 = {-0.25 * k * h0.im, 0.25 * k * h0.re};  // (i/4) k H0
+  const double c2k = 1.0 / (2.0 * kPi * k);
+  Kern4 o;
+  o.S = {-g1.re * c2k, -g1.im * c2k};
+  o.D = {npd * ikh0.re, npd * ikh0.im};
+  o.Ds = {-nd * ikh0.re, -nd * ikh0.im};
+  const double f = nd * npd * k / (2.0 * kPi * r2);
+  o.T = {nn * ikh0.re - f * g1.re, nn * ikh0.im - f * g1.im};
+  return o;
+}
+
 // K^{ka} - K^{kb} with the k-independent singular parts cancelled exactly.
 __device__ inline Kern4 lp_kernels_diff(double ka, double kb, double r2, double nd,
                                                  double npd, double nn) {

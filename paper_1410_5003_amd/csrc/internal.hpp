@@ -41,6 +41,7 @@ struct FillJob {
   int ld_t;
   const double* tw;
   double scale_t;
+  int dk;  // 1: write the wavenumber derivative dK/dk of every entry instead (no jump terms)
 };
 
 // largest grid of one launch (workgroups); bigger launches are split
@@ -63,6 +64,7 @@ struct SelfJob {
   cplx* out[3];   // pieces l = -1, 0, 1 (n x n, ld = n)
   int N;
   int tile_begin, tiles_m;  // tiles_m: 16-node blocks per side (upper-triangle tiles)
+  int dk;         // 0: the block; 1: its derivative in ka; 2: in kb (no jump terms)
 };
 
 // Alpert correction of one interface: aux invariants per (target, aux)
@@ -80,6 +82,7 @@ struct AlpertJob {
   cplx* out[3];
   int N;
   int block_begin;
+  int dk;         // as SelfJob::dk
 };
 
 constexpr int kAlpertAux = 30;     // 2 x 15 auxiliary nodes per target
@@ -120,9 +123,11 @@ struct GemmDesc {
 
 
 // host-side launchers (kernels_*.hip)
-void launch_fill(const FillJob* d_jobs, int njobs, int total_tiles, hipStream_t st);
-void launch_self(const SelfJob* d_jobs, int njobs, int total_tiles, int a_excl, hipStream_t st);
-void launch_alpert(const AlpertJob* d_jobs, int njobs, int total_blocks, int a_excl, hipStream_t st);
+// dk: the wavenumber-derivative pieces of jobs whose dk field is set
+void launch_fill(const FillJob* d_jobs, int njobs, int total_tiles, hipStream_t st, bool dk = false);
+void launch_self(const SelfJob* d_jobs, int njobs, int total_tiles, int a_excl, hipStream_t st, bool dk = false);
+void launch_alpert(const AlpertJob* d_jobs, int njobs, int total_blocks, int a_excl, hipStream_t st,
+                   bool dk = false);
 void launch_assemble(const AsmJob* d_jobs, int njobs, int total_tiles, hipStream_t st);
 void launch_gemm(const GemmDesc* d_desc, int ndesc, int total_tiles, hipStream_t st);
 void launch_hankel_eval(const double* x, double* out, int n, hipStream_t st);
@@ -237,6 +242,44 @@ struct FieldConsts {
 void launch_proxy_strength(const ProxyStrengthJob* d_jobs, int njobs, hipStream_t st);
 void launch_field(const FieldTile* d_tiles, int ntiles, const FieldRegion* d_regions, const FieldTarget* d_tgt,
                   double* u, int* layer_out, const FieldConsts& fc, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// adjoint (kernels_adjoint.hip)
+// ---------------------------------------------------------------------------
+struct TransposeJob {  // dst (rows x cols, ld ldd) = src^T (src cols x rows, ld lds); src null: zeros
+  const cplx* src;
+  cplx* dst;
+  int lds, ldd, rows, cols;
+  int tile_begin;      // first 32 x 32 tile of the job in the launch
+};
+struct BtzJob {        // v[0:c]: v[p] = sum_r B1[p ld1 + r] z1[r] + B2[..] z2[..] (p < P), + 1 at unit
+  const cplx* B1;
+  const cplx* z1;
+  const cplx* B2;
+  const cplx* z2;
+  cplx* v;
+  int ld1, n1, ld2, n2, P, c, unit;
+};
+struct LsAdjJob {      // ell[0:m] = (Q'^+)^T v from the QR [Q'; mu I] = Q_f R kept in S, T
+  const cplx* S;       // M x c factored matrix (R above the diagonal, reflectors below)
+  const cplx* T;       // per panel 16 x 16 block-reflector factor
+  const cplx* v;
+  cplx* ell;
+  int M, m, c;
+};
+struct BilinJob {      // acc[out] += scale * left^T (sum_p coef_p P_p) right
+  const cplx* P[3];
+  cplx coef[3];
+  const cplx* left;
+  const cplx* right;
+  double scale;
+  int np, rows, cols, ld, out;
+  int tile_begin;      // first 64 x 64 tile of the job in the launch
+};
+void launch_transpose(const TransposeJob* d, int njobs, int tiles, hipStream_t st);
+void launch_btz(const BtzJob* d, int njobs, hipStream_t st);
+void launch_ls_adjoint(const LsAdjJob* d, int njobs, hipStream_t st);
+void launch_bilinear(const BilinJob* d, int njobs, int tiles, double* acc, hipStream_t st);
 
 // Fixed workspace of the allocation-free solve: kScratchBytes per device,
 // shared by every such call on that device (calls that overlap on one device

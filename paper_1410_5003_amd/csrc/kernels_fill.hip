@@ -43,11 +43,26 @@ __device__ inline int find_job(const T* jobs, int njobs, int key) {
 
 __device__ inline void store(cplx* p, cplx v) { stc(p, v.re, v.im); }
 
+// the self-block kernel K^{ka} - K^{kb} (dk = 0) or its derivative in ka
+// (dk = 1: dK/dk at ka) or in kb (dk = 2: -dK/dk at kb)
+__device__ inline Kern4 self_kern(int dk, double ka, double kb, double r2, double nd, double npd, double nn) {
+  if (dk == 0) return lp_kernels_diff(ka, kb, r2, nd, npd, nn);
+  Kern4 K = lp_kernels_dk(dk == 1 ? ka : kb, r2, nd, npd, nn);
+  if (dk == 2) {
+    K.S = {-K.S.re, -K.S.im};
+    K.D = {-K.D.re, -K.D.im};
+    K.Ds = {-K.Ds.re, -K.Ds.im};
+    K.T = {-K.T.re, -K.T.im};
+  }
+  return K;
+}
+
 // Both neighbour blocks of a pair of curves from one Hankel evaluation per
 // (m, j, copy): entry (m, j) of copy p and entry (j, m) of copy 2 - p have the
 // same distance, and swapping target and source negates both normal
 // projections, which leaves S and T and exchanges D with D*.  16 x 16 tiles,
 // so that both blocks are written in runs of consecutive rows.
+template <bool DK>
 __device__ __forceinline__ void fill_pair(const FillJob& J, int lt) {
   const int tm = lt % J.tiles_m, tn = lt / J.tiles_m;
   const int m = tm * kSelfTile + (int)(threadIdx.x % kSelfTile);
@@ -62,7 +77,8 @@ __device__ __forceinline__ void fill_pair(const FillJob& J, int lt) {
   for (int p = 0; p < J.npieces; ++p) {
     const double dx = (tx - sx) + (J.tshift[p] - J.sshift[p]);
     const double r2 = dx * dx + dy * dy;
-    const Kern4 K = lp_kernels(J.k, r2, tnx * dx + tny * dy, snx * dx + sny * dy, nn);
+    const Kern4 K = DK ? lp_kernels_dk(J.k, r2, tnx * dx + tny * dy, snx * dx + sny * dy, nn)
+                       : lp_kernels(J.k, r2, tnx * dx + tny * dy, snx * dx + sny * dy, nn);
     cplx* o = J.out[p];
     store(o + (size_t)j * ld + m, {K.D.re * w, K.D.im * w});
     store(o + (size_t)(J.Ns + j) * ld + m, {K.S.re * w, K.S.im * w});
@@ -76,12 +92,14 @@ __device__ __forceinline__ void fill_pair(const FillJob& J, int lt) {
   }
 }
 
+// DK: the wavenumber-derivative pieces (jobs with dk set) instead of the pieces
+template <bool DK>
 __global__ __launch_bounds__(256) void fill_kernel(const FillJob* __restrict__ jobs, int njobs, int tile0) {
   const int tile = tile0 + (int)blockIdx.x;
   const FillJob& J = jobs[find_job(jobs, njobs, tile)];
   const int lt = tile - J.tile_begin;
   if (J.kind == kFillPair) {
-    fill_pair(J, lt);
+    fill_pair<DK>(J, lt);
     return;
   }
   const int tm = lt % J.tiles_m, tn = lt / J.tiles_m;
@@ -101,9 +119,26 @@ __global__ __launch_bounds__(256) void fill_kernel(const FillJob* __restrict__ j
     const double r2 = dx * dx + dy * dy;
     const double nd = tnx * dx + tny * dy;
     const double npd = snx * dx + sny * dy;
-    const Kern4 K = lp_kernels(J.k, r2, nd, npd, nn);
     cplx* o = J.out[p];
-    if (J.kind == kFillLayerPotential) {
+    if (DK && J.kind == kFillLayerPotential) {
+      const Kern4 Kk = lp_kernels_dk(J.k, r2, nd, npd, nn);
+      const double w = J.sw[j] * J.scale;
+      store(o + (size_t)j * ld + m, {Kk.D.re * w, Kk.D.im * w});
+      store(o + (size_t)(J.Ns + j) * ld + m, {Kk.S.re * w, Kk.S.im * w});
+      store(o + (size_t)j * ld + J.Mt + m, {Kk.T.re * w, Kk.T.im * w});
+      store(o + (size_t)(J.Ns + j) * ld + J.Mt + m, {Kk.Ds.re * w, Kk.Ds.im * w});
+      continue;
+    }
+    const Kern4 K = lp_kernels(J.k, r2, nd, npd, nn);
+    if (DK) {
+      // d/dk of phi = D + i k S and of dphi/dn = T + i k D*
+      const Kern4 Kk = lp_kernels_dk(J.k, r2, nd, npd, nn);
+      const double k = J.k, s = J.scale;
+      const cplx phi = {Kk.D.re - K.S.im - k * Kk.S.im, Kk.D.im + K.S.re + k * Kk.S.re};
+      const cplx dphi = {Kk.T.re - K.Ds.im - k * Kk.Ds.im, Kk.T.im + K.Ds.re + k * Kk.Ds.re};
+      store(o + (size_t)j * ld + m, {phi.re * s, phi.im * s});
+      store(o + (size_t)j * ld + J.Mt + m, {dphi.re * s, dphi.im * s});
+    } else if (J.kind == kFillLayerPotential) {
       const double w = J.sw[j] * J.scale;
       store(o + (size_t)j * ld + m, {K.D.re * w, K.D.im * w});
       store(o + (size_t)(J.Ns + j) * ld + m, {K.S.re * w, K.S.im * w});
@@ -127,6 +162,7 @@ __global__ __launch_bounds__(256) void fill_kernel(const FillJob* __restrict__ j
 // is symmetric too.  Workgroups take the 16 x 16 blocks (bm, bn), bm <= bn,
 // of the upper triangle; thread t the pair (bm 16 + t % 16, bn 16 + t / 16),
 // and on a diagonal block only pairs with m <= j.
+template <bool DK>
 __global__ __launch_bounds__(256) void self_kernel(const SelfJob* __restrict__ jobs, int njobs, int a, int tile0) {
   const int tile = tile0 + (int)blockIdx.x;
   const SelfJob& J = jobs[find_job(jobs, njobs, tile)];
@@ -164,12 +200,12 @@ __global__ __launch_bounds__(256) void self_kernel(const SelfJob* __restrict__ j
     if (plain) {
       const double dx = dx0 - l * J.d;
       const double r2 = dx * dx + dy * dy;
-      K = lp_kernels_diff(J.ka, J.kb, r2, tnx * dx + tny * dy, snx * dx + sny * dy, nn);
+      K = self_kern(DK ? J.dk : 0, J.ka, J.kb, r2, tnx * dx + tny * dy, snx * dx + sny * dy, nn);
     }
     // (m, j) of copy l, source weight w_j
     cplx D = {K.D.re * wj, K.D.im * wj}, S = {K.S.re * wj, K.S.im * wj};
     cplx T = {K.T.re * wj, K.T.im * wj}, Ds = {K.Ds.re * wj, K.Ds.im * wj};
-    if (l == 0 && j == m) {  // jump relations: -tau / +sigma
+    if (!DK && l == 0 && j == m) {  // jump relations: -tau / +sigma
       D.re -= 1.0;
       Ds.re += 1.0;
     }
@@ -188,6 +224,7 @@ __global__ __launch_bounds__(256) void self_kernel(const SelfJob* __restrict__ j
   }
 }
 
+template <bool DK>
 __global__ __launch_bounds__(64) void alpert_kernel(const AlpertJob* __restrict__ jobs, int njobs, int a, int blk0) {
   const int blk = blk0 + (int)blockIdx.x;
   int lo = 0, hi = njobs - 1;
@@ -218,7 +255,7 @@ __global__ __launch_bounds__(64) void alpert_kernel(const AlpertJob* __restrict_
   }
   if (lane < kAlpertAux) {
     const size_t q = (size_t)m * kAlpertAux + lane;
-    const Kern4 K = lp_kernels_diff(J.ka, J.kb, J.r2[q], J.nd[q], J.npd[q], J.nn[q]);
+    const Kern4 K = self_kern(DK ? J.dk : 0, J.ka, J.kb, J.r2[q], J.nd[q], J.npd[q], J.nn[q]);
     const double c = J.cw[q];
     kv[lane][0] = {K.D.re * c, K.D.im * c};
     kv[lane][1] = {K.S.re * c, K.S.im * c};
@@ -293,20 +330,35 @@ __global__ void hankel_eval_kernel(const double* x, double* out, int n) {
 
 // launches larger than kMaxLaunchBlocks workgroups are split, each part
 // passing its first tile index
-void launch_fill(const FillJob* d_jobs, int njobs, int total_tiles, hipStream_t st) {
-  for (int t0 = 0; t0 < total_tiles; t0 += kMaxLaunchBlocks)
-    hipLaunchKernelGGL(fill_kernel, dim3(std::min(kMaxLaunchBlocks, total_tiles - t0)), dim3(256), 0, st, d_jobs,
-                       njobs, t0);
+void launch_fill(const FillJob* d_jobs, int njobs, int total_tiles, hipStream_t st, bool dk) {
+  for (int t0 = 0; t0 < total_tiles; t0 += kMaxLaunchBlocks) {
+    if (dk)
+      hipLaunchKernelGGL(fill_kernel<true>, dim3(std::min(kMaxLaunchBlocks, total_tiles - t0)), dim3(256), 0, st,
+                         d_jobs, njobs, t0);
+    else
+      hipLaunchKernelGGL(fill_kernel<false>, dim3(std::min(kMaxLaunchBlocks, total_tiles - t0)), dim3(256), 0, st,
+                         d_jobs, njobs, t0);
+  }
 }
-void launch_self(const SelfJob* d_jobs, int njobs, int total_tiles, int a_excl, hipStream_t st) {
-  for (int t0 = 0; t0 < total_tiles; t0 += kMaxLaunchBlocks)
-    hipLaunchKernelGGL(self_kernel, dim3(std::min(kMaxLaunchBlocks, total_tiles - t0)), dim3(256), 0, st, d_jobs,
-                       njobs, a_excl, t0);
+void launch_self(const SelfJob* d_jobs, int njobs, int total_tiles, int a_excl, hipStream_t st, bool dk) {
+  for (int t0 = 0; t0 < total_tiles; t0 += kMaxLaunchBlocks) {
+    if (dk)
+      hipLaunchKernelGGL(self_kernel<true>, dim3(std::min(kMaxLaunchBlocks, total_tiles - t0)), dim3(256), 0, st,
+                         d_jobs, njobs, a_excl, t0);
+    else
+      hipLaunchKernelGGL(self_kernel<false>, dim3(std::min(kMaxLaunchBlocks, total_tiles - t0)), dim3(256), 0, st,
+                         d_jobs, njobs, a_excl, t0);
+  }
 }
-void launch_alpert(const AlpertJob* d_jobs, int njobs, int total_blocks, int a_excl, hipStream_t st) {
-  for (int b0 = 0; b0 < total_blocks; b0 += kMaxLaunchBlocks)
-    hipLaunchKernelGGL(alpert_kernel, dim3(std::min(kMaxLaunchBlocks, total_blocks - b0)), dim3(64), 0, st, d_jobs,
-                       njobs, a_excl, b0);
+void launch_alpert(const AlpertJob* d_jobs, int njobs, int total_blocks, int a_excl, hipStream_t st, bool dk) {
+  for (int b0 = 0; b0 < total_blocks; b0 += kMaxLaunchBlocks) {
+    if (dk)
+      hipLaunchKernelGGL(alpert_kernel<true>, dim3(std::min(kMaxLaunchBlocks, total_blocks - b0)), dim3(64), 0, st,
+                         d_jobs, njobs, a_excl, b0);
+    else
+      hipLaunchKernelGGL(alpert_kernel<false>, dim3(std::min(kMaxLaunchBlocks, total_blocks - b0)), dim3(64), 0, st,
+                         d_jobs, njobs, a_excl, b0);
+  }
 }
 void launch_assemble(const AsmJob* d_jobs, int njobs, int total_tiles, hipStream_t st) {
   for (int t0 = 0; t0 < total_tiles; t0 += kMaxLaunchBlocks)

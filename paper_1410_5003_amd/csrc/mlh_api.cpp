@@ -1070,6 +1070,20 @@ struct SolveOpts {
   bool noalloc = false;          // workspace in the context's fixed scratch; no allocation, no graph
   unsigned long long* tstamp = nullptr;  // device [1 + n_angles]: clock at the start, then per angle at its end
   bool keep_views = false;       // leave the first system's workspace views in the inspected stack
+  // adjoint: after the Schur complements, solve the transposed block system
+  // A'^T z = w, w_1 = the row of X_1 that gives each angle's zeroth reflected
+  // amplitude (adj_q0[a]: its index in the angle's order window); z is
+  // returned as the densities; no Bragg extraction
+  bool adjoint = false;
+  const std::vector<int>* adj_q0 = nullptr;
+  struct SysViews* views = nullptr;  // per system: the workspace left by the solve (one batch only)
+};
+
+// the workspace of one system after a solve: least-squares solutions X_j
+// (ld ldX[j]) and factors S_j, T_j per layer, densities eta_i per interface
+struct SysViews {
+  std::vector<std::vector<cplx*>> X, S, Th, eta;
+  std::vector<std::vector<int>> ldX;
 };
 
 // one system of a solve: the angles of one stack whose Bloch phases alpha
@@ -1196,7 +1210,7 @@ static mlh_status solve_systems(Runner& RN, mlh_ctx ctx, const mlh_tuning& tune,
     const size_t I = (size_t)shp[sidx[b]].I, rb = sys[b].ang.size();
     dper[b] = sizeof(AsmJob) * (10 * (I + 2)) + sizeof(GemmDesc) * (8 * I + 8) + sizeof(HqDesc) * (I + 1) +
               sizeof(GjeDesc) * (I + 1) + sizeof(GemvDesc) * (I + 1) + sizeof(AngleDesc) * rb + sizeof(EtaSeg) * I +
-              sizeof(EtaDst) * rb;
+              sizeof(EtaDst) * rb + sizeof(TransposeJob) * (4 * I + rb + 4);
   }
   // alignment slack of one batch's descriptor uploads (3 lists per level)
   const size_t slack = (size_t)256 * (3 * 64 + 24) + 4096;
@@ -1231,6 +1245,8 @@ static mlh_status solve_systems(Runner& RN, mlh_ctx ctx, const mlh_tuning& tune,
     bstart.push_back(NS);
     need += slack;
   }
+  if (opt.views && bstart.size() > 2)
+    return fail(MLH_E_UNSUPPORTED, "the adjoint needs every system of the call in one batch: fewer angles per call");
   char* wbase = nullptr;
   if (opt.noalloc) {
     if (need > kScratchBytes) {
@@ -1513,6 +1529,50 @@ static mlh_status solve_systems(Runner& RN, mlh_ctx ctx, const mlh_tuning& tune,
         angs.push_back(A);
       }
     }
+    // adjoint: the transposed block system in the second row-block buffer,
+    // [D_i^T | U_{i-1}^T | L_{i+1}^T | w_i], which the reduction then reads
+    // first (A'^T has (A'^T)_{i,i-1} = A'_{i-1,i}^T and (A'^T)_{i,i+1} =
+    // A'_{i+1,i}^T, of the same shapes as L_i and U_i)
+    std::vector<TransposeJob> tjobs;
+    int ttiles = 0;
+    auto tadd = [&](const cplx* src, int lds, cplx* dst, int ldd, int rows, int cols) {
+      if (rows <= 0 || cols <= 0) return;
+      TransposeJob T{};
+      T.src = src;
+      T.lds = lds;
+      T.dst = dst;
+      T.ldd = ldd;
+      T.rows = rows;
+      T.cols = cols;
+      T.tile_begin = ttiles;
+      ttiles += ((rows + 31) / 32) * ((cols + 31) / 32);
+      tjobs.push_back(T);
+    };
+    if (opt.adjoint) {
+      for (int b = 0; b < nb; ++b) {
+        const mlh_stack_s* s = SY(b).s;
+        const std::vector<int>& n = s->n;
+        const Shape& sh = SH(b);
+        for (int i = 0; i < sh.I; ++i) {
+          cplx* W1 = V[b].W[1][i];
+          tadd(Dblk(b, i), n[i], W1, n[i], n[i], n[i]);
+          if (i > 0) tadd(Ublk(b, i - 1), n[i - 1], W1 + (size_t)n[i] * n[i], n[i], n[i], n[i - 1]);
+          if (i + 1 < sh.I)
+            tadd(Lblk(b, i + 1), n[i + 1], W1 + (size_t)n[i] * (n[i] + sh.nL0[i]), n[i], n[i], n[i + 1]);
+          cplx* F1 = W1 + (size_t)n[i] * (n[i] + sh.nL0[i] + sh.nU0[i]);
+          int m0, c0, nc0;
+          layer_dims(s, 0, m0, c0, nc0);
+          for (int q = 0; q < R_of(b); ++q) {
+            if (i == 0) {  // the a0 row of X_1, as a column
+              const int q0 = (*opt.adj_q0)[SY(b).ang[q]];
+              tadd(V[b].RHS[0] + s->P + q0, m0 + c0, F1 + (size_t)q * n[0], n[0], n[0], 1);
+            } else {
+              tadd(nullptr, 1, F1 + (size_t)q * n[i], n[i], n[i], 1);
+            }
+          }
+        }
+      }
+    }
     // layers with at most kHqRhsSmallRows rows first: the right-hand-side
     // kernel is launched once per size class (the other kernels take each
     // descriptor on its own)
@@ -1569,7 +1629,7 @@ static mlh_status solve_systems(Runner& RN, mlh_ctx ctx, const mlh_tuning& tune,
       const Shape& sh = shp[t];
       const int I = sh.I;
       const std::vector<int>& n = sh.s->n;
-      std::vector<int> cur(I, 0), nLc(sh.nL0), nUc(sh.nU0);
+      std::vector<int> cur(I, opt.adjoint ? 1 : 0), nLc(sh.nL0), nUc(sh.nU0);
       std::vector<int> S_act(I);
       for (int i = 0; i < I; ++i) S_act[i] = i;
       for (size_t lidx = 0;; ++lidx) {
@@ -1736,6 +1796,7 @@ static mlh_status solve_systems(Runner& RN, mlh_ctx ctx, const mlh_tuning& tune,
     const size_t o_gs = push(gs.data(), sizeof(GemmDesc) * gs.size());
     const size_t o_hq = push(hq.data(), sizeof(HqDesc) * hq.size());
     const size_t o_ang = push(angs.data(), sizeof(AngleDesc) * angs.size());
+    const size_t o_tj = push(tjobs.data(), sizeof(TransposeJob) * tjobs.size());
     // densities: where eta_i sits in each system's workspace, and each
     // angle's output row
     size_t o_eseg = 0, o_edst = 0;
@@ -1846,6 +1907,7 @@ static mlh_status solve_systems(Runner& RN, mlh_ctx ctx, const mlh_tuning& tune,
           prof->n_schur_gemm++;
           prof->schur_flops += gemm_flops(gs);
         }
+        if (opt.adjoint) launch_transpose(reinterpret_cast<TransposeJob*>(dbase + o_tj), (int)tjobs.size(), ttiles, ls);
       }
       if (stop_phase == 0 || stop_phase >= 4) {
         for (int l = 0; l < NL; ++l) {
@@ -1962,7 +2024,7 @@ static mlh_status solve_systems(Runner& RN, mlh_ctx ctx, const mlh_tuning& tune,
         te();
         if (prof) prof->n_backsub += NL;
         tb(prof ? &prof->bragg_ms : nullptr);
-        launch_bragg(d_ang, nang, ls);
+        if (!opt.adjoint) launch_bragg(d_ang, nang, ls);
         te();
         if (n_edst > 0)
           launch_gather_eta(reinterpret_cast<EtaSeg*>(dbase + o_eseg), max_seg, max_segn, reinterpret_cast<EtaDst*>(dbase + o_edst),
@@ -1974,7 +2036,7 @@ static mlh_status solve_systems(Runner& RN, mlh_ctx ctx, const mlh_tuning& tune,
     };
     EvTimer T{st};
     static const bool no_graph = std::getenv("MLH_NO_GRAPH") != nullptr;
-    if (prof || stop_phase != 0 || no_graph || opt.noalloc) {
+    if (prof || stop_phase != 0 || no_graph || opt.noalloc || opt.adjoint) {
       MLH_TRY(launch_all(st, T));
     } else {
       // every launch shape of the sequence: a cached graph is replayed only
@@ -2057,6 +2119,22 @@ static mlh_status solve_systems(Runner& RN, mlh_ctx ctx, const mlh_tuning& tune,
           HIP_TRY(hipMemcpyAsync(&h_flux[a], V[b].flux + q, sizeof(double), hipMemcpyDeviceToHost, st));
         if (eta_stage && o.eta)
           HIP_TRY(hipMemcpyAsync(o.eta, V[b].eta_rows + (size_t)nden * q, cbytes(nden), hipMemcpyDeviceToHost, st));
+      }
+    }
+    if (opt.views) {
+      SysViews& W = *opt.views;
+      for (int b = 0; b < nb; ++b) {
+        W.X.push_back(V[b].RHS);
+        W.S.push_back(V[b].S);
+        W.Th.push_back(V[b].Th);
+        W.eta.push_back(V[b].eta);
+        std::vector<int> ld;
+        for (int j = 0; j <= SH(b).I; ++j) {
+          int m, c, nc;
+          layer_dims(SY(b).s, j, m, c, nc);
+          ld.push_back(m + c);
+        }
+        W.ldX.push_back(ld);
       }
     }
     if (opt.keep_views && inspect && bi == 0) {
@@ -2306,6 +2384,354 @@ extern "C" mlh_status mlh_field(mlh_stack s, double theta, int64_t n_pts, const 
   }
   // the buffer is freed on return: wait for the work that reads it
   HIP_TRY(hipStreamSynchronize(st));
+  return MLH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// adjoint: gradient of the summed zeroth-order reflected efficiency
+// ---------------------------------------------------------------------------
+extern "C" mlh_status mlh_adjoint(mlh_stack s, int32_t n_angles, const double* theta, double* J_out,
+                                  double* grad_k) {
+  if (!s || n_angles < 1 || !theta || !grad_k) return fail(MLH_E_INVALID_ARG, "mlh_adjoint: bad arguments");
+  for (int a = 0; a < n_angles; ++a)
+    if (!theta_ok(theta[a])) return fail(MLH_E_INVALID_ARG, "incident angle must lie in (-pi, 0)");
+  HIP_TRY(hipSetDevice(s->ctx->device));
+  hipStream_t st = s->ctx->stream;
+  const int I = s->I, P = s->P, nK = s->nK;
+  int64_t nden = 0;
+  std::vector<int64_t> doff(I + 1, 0);
+  for (int i = 0; i < I; ++i) doff[i + 1] = doff[i] + s->n[i];
+  nden = doff[I];
+  std::vector<SysSpec> sys;
+  group_by_alpha(s, n_angles, theta, 0, sys);
+  // ---- forward solve: amplitudes, order labels and densities on the host
+  std::vector<double> aU((size_t)2 * nK * n_angles), aD(aU.size()), flux(n_angles);
+  std::vector<int32_t> ord((size_t)nK * n_angles);
+  std::vector<double> eta((size_t)2 * nden * n_angles);
+  std::vector<AngleOut> outs(n_angles);
+  for (int a = 0; a < n_angles; ++a)
+    outs[a] = AngleOut{aU.data() + (size_t)2 * nK * a, aD.data() + (size_t)2 * nK * a, ord.data() + (size_t)nK * a,
+                       flux.data() + a, eta.data() + (size_t)2 * nden * a};
+  std::vector<double> h_flux;
+  MLH_TRY(solve_systems(s->run, s->ctx, s->tune, sys, theta, outs, SolveOpts(), true, h_flux, nullptr));
+  std::vector<int> q0(n_angles, -1);
+  for (int a = 0; a < n_angles; ++a)
+    for (int q = 0; q < nK; ++q)
+      if (ord[(size_t)nK * a + q] == 0) q0[a] = q;
+  for (int a = 0; a < n_angles; ++a)
+    if (q0[a] < 0) return fail(MLH_E_INVALID_ARG, "mlh_adjoint: order 0 lies outside the Rayleigh-Bloch window");
+  // ---- device buffers: forward densities, adjoint densities z, proxy
+  //      strengths, v and l_w per layer, derivative pieces and their jobs
+  std::vector<int> mrows(I + 1), crows(I + 1);
+  size_t csum = 0, msum = 0;
+  for (int j = 0; j <= I; ++j) {
+    int m, c, nc;
+    layer_dims(s, j, m, c, nc);
+    mrows[j] = m;
+    crows[j] = c;
+    csum += c;
+    msum += m;
+  }
+  size_t kb_extra = 0;
+  for (int i = 0; i < I; ++i) kb_extra += (size_t)3 * s->n[i] * s->n[i];
+  const size_t nacc = (size_t)n_angles * (I + 1);
+  Arena ar;
+  const size_t o_eta = ar.reserve(cbytes((size_t)nden * n_angles)), o_z = ar.reserve(cbytes((size_t)nden * n_angles)),
+               o_c = ar.reserve(cbytes((size_t)n_angles * (I + 1) * P)), o_v = ar.reserve(cbytes(n_angles * csum)),
+               o_l = ar.reserve(cbytes(n_angles * msum)), o_dum = ar.reserve(cbytes((size_t)2 * nK * n_angles)),
+               o_acc = ar.reserve(sizeof(double) * 2 * nacc), o_dk = ar.reserve(s->dbytes),
+               o_kb = ar.reserve(cbytes(kb_extra)), o_fj = ar.reserve(sizeof(FillJob) * s->h_fill.size()),
+               o_sj = ar.reserve(sizeof(SelfJob) * 2 * s->h_self.size()),
+               o_aj = ar.reserve(sizeof(AlpertJob) * 2 * s->h_alp.size());
+  char* buf = nullptr;
+  hipError_t e = hipMalloc((void**)&buf, ar.off);
+  if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? MLH_E_NOMEM : MLH_E_DEVICE, "mlh_adjoint: allocation");
+  struct Free {
+    char* p;
+    ~Free() { (void)hipFree(p); }
+  } guard{buf};
+  cplx* d_eta = reinterpret_cast<cplx*>(buf + o_eta);
+  cplx* d_z = reinterpret_cast<cplx*>(buf + o_z);
+  cplx* d_c = reinterpret_cast<cplx*>(buf + o_c);
+  cplx* d_v = reinterpret_cast<cplx*>(buf + o_v);
+  cplx* d_l = reinterpret_cast<cplx*>(buf + o_l);
+  double* d_acc = reinterpret_cast<double*>(buf + o_acc);
+  char* dk = buf + o_dk;
+  cplx* kb = reinterpret_cast<cplx*>(buf + o_kb);
+  HIP_TRY(hipMemcpyAsync(d_eta, eta.data(), cbytes((size_t)nden * n_angles), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemsetAsync(d_acc, 0, sizeof(double) * 2 * nacc, st));
+  // ---- derivative pieces dP/dk of every alpha-independent piece, at the
+  //      same offsets as the pieces in the stack's arena; the self blocks
+  //      have two (in k above and in k below the interface)
+  auto mapc = [&](const cplx* p) -> cplx* {
+    return p ? reinterpret_cast<cplx*>(dk + (reinterpret_cast<const char*>(p) - s->dmem)) : nullptr;
+  };
+  std::vector<FillJob> fj = s->h_fill;
+  for (FillJob& F : fj) {
+    F.dk = 1;
+    for (int l = 0; l < 3; ++l) {
+      F.out[l] = mapc(F.out[l]);
+      F.out_t[l] = mapc(F.out_t[l]);
+    }
+  }
+  std::vector<SelfJob> sj;
+  std::vector<AlpertJob> aj;
+  std::vector<cplx*> self_kb(I);
+  {
+    size_t off = 0;
+    int tiles = 0, blocks = 0;
+    for (int pass = 1; pass <= 2; ++pass)
+      for (int i = 0; i < I; ++i) {
+        SelfJob S = s->h_self[i];
+        AlpertJob A = s->h_alp[i];
+        S.dk = A.dk = pass;
+        const size_t pe = (size_t)s->n[i] * s->n[i];
+        for (int l = 0; l < 3; ++l) {
+          S.out[l] = pass == 1 ? mapc(S.out[l]) : kb + off + l * pe;
+          A.out[l] = S.out[l];
+        }
+        if (pass == 2) {
+          self_kb[i] = kb + off;
+          off += 3 * pe;
+        }
+        S.tile_begin = tiles;
+        tiles += S.tiles_m * (S.tiles_m + 1) / 2;
+        A.block_begin = blocks;
+        blocks += A.N;
+        sj.push_back(S);
+        aj.push_back(A);
+      }
+    HIP_TRY(hipMemcpyAsync(buf + o_fj, fj.data(), sizeof(FillJob) * fj.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(buf + o_sj, sj.data(), sizeof(SelfJob) * sj.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(buf + o_aj, aj.data(), sizeof(AlpertJob) * aj.size(), hipMemcpyHostToDevice, st));
+    launch_self(reinterpret_cast<SelfJob*>(buf + o_sj), (int)sj.size(), tiles, kAlpertA, st, true);
+    launch_alpert(reinterpret_cast<AlpertJob*>(buf + o_aj), (int)aj.size(), blocks, kAlpertA, st, true);
+    launch_fill(reinterpret_cast<FillJob*>(buf + o_fj), (int)fj.size(), s->fill_tiles, st, true);
+    HIP_TRY(hipGetLastError());
+  }
+  // ---- adjoint solve: A'^T z = w; z lands in the density rows of d_z, the
+  //      workspace keeps X, the least-squares factors and z
+  SysViews views;
+  {
+    std::vector<AngleOut> o2(n_angles);
+    cplx* dum = reinterpret_cast<cplx*>(buf + o_dum);
+    for (int a = 0; a < n_angles; ++a)
+      o2[a] = AngleOut{reinterpret_cast<double*>(dum + (size_t)2 * nK * a),
+                       reinterpret_cast<double*>(dum + (size_t)2 * nK * a + nK), nullptr, nullptr,
+                       reinterpret_cast<double*>(d_z + (size_t)nden * a)};
+    SolveOpts o;
+    o.on_device = true;
+    o.adjoint = true;
+    o.adj_q0 = &q0;
+    o.views = &views;
+    std::vector<double> hf;
+    MLH_TRY(solve_systems(s->run, s->ctx, s->tune, sys, theta, o2, o, false, hf, nullptr));
+  }
+  // ---- per angle: proxy strengths, v_j, l_w,j, and the contractions
+  std::vector<ProxyStrengthJob> pj;
+  std::vector<BtzJob> bj;
+  std::vector<LsAdjJob> lj;
+  std::vector<BilinJob> blj;
+  int btiles = 0;
+  std::vector<size_t> voff(I + 1), loff(I + 1);
+  {
+    size_t vo = 0, lo = 0;
+    for (int j = 0; j <= I; ++j) {
+      voff[j] = vo;
+      loff[j] = lo;
+      vo += crows[j];
+      lo += mrows[j];
+    }
+  }
+  auto bil = [&](const cplx* const* P, const cplx* coef, int np, int rows, int cols, int ld, const cplx* left,
+                 const cplx* right, double scale, int out) {
+    BilinJob B{};
+    for (int p = 0; p < np; ++p) {
+      B.P[p] = P[p];
+      B.coef[p] = coef[p];
+    }
+    B.np = np;
+    B.rows = rows;
+    B.cols = cols;
+    B.ld = ld;
+    B.left = left;
+    B.right = right;
+    B.scale = scale;
+    B.out = out;
+    B.tile_begin = btiles;
+    btiles += ((rows + 63) / 64) * ((cols + 63) / 64);
+    blj.push_back(B);
+  };
+  const cplx one = cx(1.0, 0.0);
+  for (size_t b = 0; b < sys.size(); ++b)
+    for (size_t q = 0; q < sys[b].ang.size(); ++q) {
+      const int a = sys[b].ang[q];
+      const cplx* eta_a = d_eta + (size_t)nden * a;
+      const cplx* z_a = d_z + (size_t)nden * a;
+      cplx* c_a = d_c + (size_t)a * (I + 1) * P;
+      cplx* v_a = d_v + (size_t)a * csum;
+      cplx* l_a = d_l + (size_t)a * msum;
+      for (int j = 0; j <= I; ++j) {
+        ProxyStrengthJob J{};
+        J.X = views.X[b][j];
+        J.ldX = views.ldX[b][j];
+        J.eta0 = j > 0 ? eta_a + doff[j - 1] : eta_a;
+        J.n0 = j > 0 ? s->n[j - 1] : s->n[0];
+        J.eta1 = (j > 0 && j < I) ? eta_a + doff[j] : nullptr;
+        J.n1 = (j > 0 && j < I) ? s->n[j] : 0;
+        J.c = c_a + (size_t)j * P;
+        J.P = P;
+        pj.push_back(J);
+        BtzJob Bz{};
+        if (j < I) {
+          Bz.B1 = s->B_own[j];
+          Bz.ld1 = s->n[j];
+          Bz.z1 = z_a + doff[j];
+          Bz.n1 = s->n[j];
+        }
+        if (j > 0) {
+          Bz.B2 = s->B_below[j - 1];
+          Bz.ld2 = s->n[j - 1];
+          Bz.z2 = z_a + doff[j - 1];
+          Bz.n2 = s->n[j - 1];
+        }
+        Bz.v = v_a + voff[j];
+        Bz.P = P;
+        Bz.c = crows[j];
+        Bz.unit = j == 0 ? P + q0[a] : -1;
+        bj.push_back(Bz);
+        LsAdjJob L{};
+        L.S = views.S[b][j];
+        L.T = views.Th[b][j];
+        L.v = v_a + voff[j];
+        L.ell = l_a + loff[j];
+        L.M = mrows[j] + crows[j];
+        L.m = mrows[j];
+        L.c = crows[j];
+        lj.push_back(L);
+      }
+      // contractions, accumulated at acc[a (I+1) + layer]: density rows with
+      // left = z (= -l_eta), wall rows with left = l_w and scale -1
+      const double ph = s->d * s->k[0] * std::cos(theta[a]);
+      const cplx am1 = cpow_alpha(ph, -1), ap1 = cpow_alpha(ph, 1), am2 = cpow_alpha(ph, -2);
+      const cplx c3[3] = {am1, one, ap1};
+      const cplx cC[2] = {am2, cx(-ap1.re, -ap1.im)};
+      const cplx cQ[2] = {am1, cx(-1.0, 0.0)};
+      const int base = a * (I + 1);
+      for (int i = 0; i < I; ++i) {
+        const int n = s->n[i];
+        const size_t pe = (size_t)n * n;
+        const cplx* zi = z_a + doff[i];
+        const cplx* ei = eta_a + doff[i];
+        const cplx* sa[3] = {mapc(s->A_self[i]), mapc(s->A_self[i]) + pe, mapc(s->A_self[i]) + 2 * pe};
+        bil(sa, c3, 3, n, n, n, zi, ei, 1.0, base + i);
+        const cplx* sb[3] = {self_kb[i], self_kb[i] + pe, self_kb[i] + 2 * pe};
+        bil(sb, c3, 3, n, n, n, zi, ei, 1.0, base + i + 1);
+        if (i + 1 < I) {
+          const int n1 = s->n[i + 1];
+          const size_t pu = (size_t)n * n1;
+          const cplx* su[3] = {mapc(s->A_up[i]), mapc(s->A_up[i]) + pu, mapc(s->A_up[i]) + 2 * pu};
+          bil(su, c3, 3, n, n1, n, zi, eta_a + doff[i + 1], 1.0, base + i + 1);
+          const cplx* sd[3] = {mapc(s->A_dn[i]), mapc(s->A_dn[i]) + pu, mapc(s->A_dn[i]) + 2 * pu};
+          bil(sd, c3, 3, n1, n, n1, z_a + doff[i + 1], ei, 1.0, base + i + 1);
+        }
+        const cplx* bo[1] = {mapc(s->B_own[i])};
+        bil(bo, &one, 1, n, P, n, zi, c_a + (size_t)i * P, 1.0, base + i);
+        const cplx* bb[1] = {mapc(s->B_below[i])};
+        bil(bb, &one, 1, n, P, n, zi, c_a + (size_t)(i + 1) * P, 1.0, base + i + 1);
+      }
+      const int mw2 = 2 * s->Mw, mud2 = 2 * s->Mud;
+      for (int j = 0; j <= I; ++j) {
+        const cplx* lw = l_a + loff[j];
+        if (j > 0) {
+          const size_t ea = (size_t)mw2 * s->n[j - 1];
+          const cplx* ca[2] = {mapc(s->C_above[j]), mapc(s->C_above[j]) + ea};
+          bil(ca, cC, 2, mw2, s->n[j - 1], mw2, lw, eta_a + doff[j - 1], -1.0, base + j);
+        }
+        if (j < I) {
+          const size_t eo = (size_t)mw2 * s->n[j];
+          const cplx* co[2] = {mapc(s->C_own[j]), mapc(s->C_own[j]) + eo};
+          bil(co, cC, 2, mw2, s->n[j], mw2, lw, eta_a + doff[j], -1.0, base + j);
+        }
+        const size_t qe = (size_t)mw2 * P;
+        const cplx* sq[2] = {mapc(s->Q[j]), mapc(s->Q[j]) + qe};
+        bil(sq, cQ, 2, mw2, P, mw2, lw, c_a + (size_t)j * P, -1.0, base + j);
+      }
+      {  // the rows on D (radiation condition of the bottom layer)
+        const cplx* lw = l_a + loff[I] + mw2;
+        const size_t ze = (size_t)mud2 * s->n[I - 1];
+        const cplx* zd[3] = {mapc(s->Z_D), mapc(s->Z_D) + ze, mapc(s->Z_D) + 2 * ze};
+        bil(zd, c3, 3, mud2, s->n[I - 1], mud2, lw, eta_a + doff[I - 1], -1.0, base + I);
+        const cplx* vd[1] = {mapc(s->V_D)};
+        bil(vd, &one, 1, mud2, P, mud2, lw, c_a + (size_t)I * P, -1.0, base + I);
+      }
+    }
+  Arena ja;
+  const size_t o_pj = ja.reserve(sizeof(ProxyStrengthJob) * pj.size()), o_bj = ja.reserve(sizeof(BtzJob) * bj.size()),
+               o_lj = ja.reserve(sizeof(LsAdjJob) * lj.size()), o_blj = ja.reserve(sizeof(BilinJob) * blj.size());
+  char* jbuf = nullptr;
+  e = hipMalloc((void**)&jbuf, ja.off);
+  if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? MLH_E_NOMEM : MLH_E_DEVICE, "mlh_adjoint: allocation");
+  Free guard2{jbuf};
+  HIP_TRY(hipMemcpyAsync(jbuf + o_pj, pj.data(), sizeof(ProxyStrengthJob) * pj.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(jbuf + o_bj, bj.data(), sizeof(BtzJob) * bj.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(jbuf + o_lj, lj.data(), sizeof(LsAdjJob) * lj.size(), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(jbuf + o_blj, blj.data(), sizeof(BilinJob) * blj.size(), hipMemcpyHostToDevice, st));
+  launch_proxy_strength(reinterpret_cast<ProxyStrengthJob*>(jbuf + o_pj), (int)pj.size(), st);
+  launch_btz(reinterpret_cast<BtzJob*>(jbuf + o_bj), (int)bj.size(), st);
+  launch_ls_adjoint(reinterpret_cast<LsAdjJob*>(jbuf + o_lj), (int)lj.size(), st);
+  launch_bilinear(reinterpret_cast<BilinJob*>(jbuf + o_blj), (int)blj.size(), btiles, d_acc, st);
+  HIP_TRY(hipGetLastError());
+  std::vector<double> acc(2 * nacc);
+  std::vector<double> lD((size_t)2 * n_angles * 2 * s->Mud);
+  HIP_TRY(hipMemcpyAsync(acc.data(), d_acc, sizeof(double) * acc.size(), hipMemcpyDeviceToHost, st));
+  for (int a = 0; a < n_angles; ++a)
+    HIP_TRY(hipMemcpyAsync(lD.data() + (size_t)2 * a * 2 * s->Mud, d_l + (size_t)a * msum + loff[I] + 2 * s->Mw,
+                           cbytes(2 * (size_t)s->Mud), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  // ---- gradient: dJ/dk_j = sum_a 2 Re(conj(a0) da0/dk_j); the rows on D
+  //      also hold W_D = -[e; -i k^D e] (eq. (59)), whose second half moves
+  //      with k_{I+1}: d(i k^D_n)/dk = i k/k^D_n
+  double Jsum = 0.0;
+  for (int j = 0; j <= I; ++j) grad_k[j] = 0.0;
+  grad_k[0] = std::nan("");
+  for (int a = 0; a < n_angles; ++a) {
+    const double a0r = aU[(size_t)2 * nK * a + 2 * q0[a]], a0i = aU[(size_t)2 * nK * a + 2 * q0[a] + 1];
+    Jsum += a0r * a0r + a0i * a0i;
+    auto add = [&](int j, double dr, double di) { grad_k[j] += 2.0 * (a0r * dr + a0i * di); };
+    for (int j = 1; j <= I; ++j) add(j, acc[2 * ((size_t)a * (I + 1) + j)], acc[2 * ((size_t)a * (I + 1) + j) + 1]);
+    const double kI = s->k[I];
+    const double kap0 = s->k[0] * std::cos(theta[a]);
+    double wr = 0.0, wi = 0.0;  // l_D2^T dW a^D
+    for (int q = 0; q < nK; ++q) {
+      const int nq = ord[(size_t)nK * a + q];
+      const double kap = kap0 + 2.0 * kPi * nq / s->d;
+      const double kk = kI * kI - kap * kap;
+      if (std::fabs(kk) <= 1e-14 * kI * kI) continue;  // grazing order: no derivative
+      // i k/k^D_n: k^D real (propagating) or i|.| (evanescent)
+      double fr, fi;
+      if (kk > 0) {
+        fr = 0.0;
+        fi = kI / std::sqrt(kk);
+      } else {
+        fr = kI / std::sqrt(-kk);
+        fi = 0.0;
+      }
+      const double adr = aD[(size_t)2 * nK * a + 2 * q], adi = aD[(size_t)2 * nK * a + 2 * q + 1];
+      const double gr = fr * adr - fi * adi, gi = fr * adi + fi * adr;  // f a^D_n
+      for (int mm = 0; mm < s->Mud; ++mm) {
+        const double x = -0.5 * s->d + s->d * (mm + 0.5) / s->Mud;
+        const double er = std::cos(kap * x), ei = std::sin(kap * x);
+        const double tr = er * gr - ei * gi, ti = er * gi + ei * gr;
+        const double lr = lD[(size_t)2 * a * 2 * s->Mud + 2 * (s->Mud + mm)];
+        const double li = lD[(size_t)2 * a * 2 * s->Mud + 2 * (s->Mud + mm) + 1];
+        wr += lr * tr - li * ti;
+        wi += lr * ti + li * tr;
+      }
+    }
+    add(I, -wr, -wi);
+  }
+  if (J_out) *J_out = Jsum;
   return MLH_OK;
 }
 
