@@ -287,22 +287,35 @@ mlh_status mlh_field(mlh_stack s, double theta, int64_t n_pts, const double* x, 
 
 /* Gradient of J = sum_a e^U_0(theta[a]), the zeroth-order reflected
  * efficiencies (eq. (86); e^U_0 = |a^U_0|^2 since k^U_0 = k_1 |sin theta|),
- * with respect to the layer wavenumbers k_2..k_{I+1}, by the adjoint of the
- * solve (Sec. 3.2-3.3 transposed): the forward solve; the transposed
- * block-tridiagonal solve A'^T z = w with w the row of X_1 that yields a^U_0;
- * the least-squares adjoint vectors l_j = (Q'_j^+)^T v_j from the layers'
- * QR factors; and the wavenumber derivatives of every alpha-independent fill
- * piece, recomputed into a scratch arena (dS/dk = -g1/(2 pi k), dD/dk =
- * n'.dv (i/4) k H0, ...; the self blocks with the Alpert correction applied
- * to the derivative kernels) and contracted with the adjoint and forward
- * vectors.  The incident medium's k_1 also sets the Bloch phase and the
- * Rayleigh-Bloch orders; its derivative is not formed (grad_k[0] = NaN).
+ * by the adjoint of the solve (Sec. 3.2-3.3 transposed): the forward solve;
+ * the transposed block-tridiagonal solve A'^T z = w with w the row of X_1
+ * that yields a^U_0; the least-squares adjoint vectors l_j = (Q'_j^+)^T v_j
+ * from the layers' QR factors; then the derivative of every block contracted
+ * with the adjoint and forward vectors, da0 = -l^T dE u (the fills are
+ * recomputed, not stored):
+ *   grad_k[I+1]  dJ/dk_j from the wavenumber derivatives of every
+ *                alpha-independent piece (dS/dk = -g1/(2 pi k), dD/dk =
+ *                n'.dv (i/4) k H0, ...; the self blocks with the Alpert
+ *                correction applied to the derivative kernels).  The incident
+ *                medium's k_1 also sets the Bloch phase and the Rayleigh-Bloch
+ *                orders; its derivative is not formed: grad_k[0] = NaN;
+ *   grad_shape   (may be NULL) dJ/d(cos_coef), dJ/d(sin_coef) of every
+ *                FOURIER interface, interface by interface, n_modes cos
+ *                entries then n_modes sin entries (POLYGON interfaces take no
+ *                entries): the pieces of the blocks that touch the interface
+ *                (its self block, the neighbour pairs, the proxy rows, the
+ *                wall columns, the U/D rows and the incident right-hand side
+ *                on interface 1) differentiated by central differences of
+ *                the fill kernels at perturbed node geometry (step 1e-5 of the
+ *                largest coefficient); the wall nodes, whose end points follow
+ *                the interface heights at x = -d/2, are held fixed.
  * theta: n_angles host angles in (-pi, 0), all in one batch of systems.
- * Outputs (host): J_out (may be NULL) and grad_k[I+1].  Smooth and
- * cornered interfaces alike.  Errors: MLH_E_INVALID_ARG (also when the
- * zeroth order leaves the window), MLH_E_UNSUPPORTED (too many angles for
- * one batch), MLH_E_NOMEM, MLH_E_DEVICE. */
-mlh_status mlh_adjoint(mlh_stack s, int32_t n_angles, const double* theta, double* J_out, double* grad_k);
+ * Outputs (host): J_out (may be NULL), grad_k, grad_shape.  Errors:
+ * MLH_E_INVALID_ARG (also when the zeroth order leaves the window),
+ * MLH_E_UNSUPPORTED (too many angles for one batch), MLH_E_NOMEM,
+ * MLH_E_DEVICE. */
+mlh_status mlh_adjoint(mlh_stack s, int32_t n_angles, const double* theta, double* J_out, double* grad_k,
+                       double* grad_shape);
 
 /* Batches of independent stacks (many unrelated structures at once; the
  * per-layer independence of the Schur eliminations, Sec. 3.2, and of the

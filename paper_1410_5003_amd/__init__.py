@@ -130,6 +130,7 @@ class Stack:
         d.ls_mu = float(getattr(desc, "ls_mu", 0.0))
         self.K = int(desc.K)
         self._k = np.array(k)
+        self._n_shape = sum(2 * len(f.cos_coef) for f in desc.interfaces if f.kind == "fourier")
         self._h = C.c_void_p()
         check(lib().mlh_stack_create(ctx.handle, C.byref(d), C.byref(self._h)))
         self._keep = []
@@ -206,15 +207,18 @@ class Stack:
                               reg.ctypes.data))
         return u, reg
 
-    def adjoint(self, thetas):
-        """J = sum of the zeroth-order reflected efficiencies at ``thetas``
-        and dJ/dk_j for the layers below the top one (mlh_adjoint; entry 0
-        is NaN)."""
+    def adjoint(self, thetas, shape: bool = False):
+        """J = sum of the zeroth-order reflected efficiencies at ``thetas``,
+        dJ/dk_j (entry 0, the incident medium, is NaN) and, with ``shape``,
+        dJ/d(cos_coef, sin_coef) of the Fourier interfaces, interface by
+        interface (mlh_adjoint)."""
         th = np.ascontiguousarray(np.atleast_1d(thetas), dtype=np.float64)
         g = np.zeros(len(self._k))
+        gs = np.zeros(self._n_shape) if shape else None
         J = C.c_double()
-        check(lib().mlh_adjoint(self._h, th.size, dptr(th), C.byref(J), dptr(g)))
-        return J.value, g
+        check(lib().mlh_adjoint(self._h, th.size, dptr(th), C.byref(J), dptr(g),
+                                gs.ctypes.data if shape else None))
+        return (J.value, g, gs) if shape else (J.value, g)
 
     def set_flux_tolerance(self, tol: float):
         """Report MLH_E_ACCURACY from solves whose |flux error| exceeds tol
@@ -350,11 +354,14 @@ class Batch:
 
 
 class EfficiencyObjective:
-    """J(n) = sum over the angles of the zeroth-order reflected efficiency of
-    a workloads.ShapeProblem at layer indices n, as a torch.autograd.Function:
-    the forward pass solves on the GPU, the backward pass returns
-    dJ/dn_j = omega dJ/dk_j from the adjoint (mlh_adjoint).  The top layer's
-    index is the incident medium's and gets no gradient (zero)."""
+    """J(c, n) = sum over the angles of the zeroth-order reflected efficiency
+    of a workloads.ShapeProblem at sine amplitudes c (I x M) and layer
+    indices n, as a torch.autograd.Function: the forward pass solves on the
+    GPU, the backward pass returns the adjoint gradient (mlh_adjoint):
+    dJ/dn_j = omega dJ/dk_j, and dJ/dc_{i,m} from the gradient in the
+    interface's cos / sin coefficients (cos_coef = c sin psi, sin_coef =
+    c cos psi).  The top layer's index is the incident medium's and gets no
+    gradient (zero)."""
 
     @staticmethod
     def function():
@@ -362,20 +369,22 @@ class EfficiencyObjective:
 
         class _F(torch.autograd.Function):
             @staticmethod
-            def forward(fctx, n, problem, ctx, thetas):
-                p = problem.params()
-                p[problem.c.size:] = n.detach().cpu().numpy()
+            def forward(fctx, c, n, problem, ctx, thetas):
+                p = np.concatenate([c.detach().cpu().numpy().ravel(), n.detach().cpu().numpy()])
                 st = Stack(ctx, problem.stack(p))
-                J, gk = st.adjoint(thetas)
+                J, gk, gs = st.adjoint(thetas, shape=True)
                 st.close()
-                g = problem.omega * gk
-                g[0] = 0.0
-                fctx.save_for_backward(torch.as_tensor(g, dtype=n.dtype))
+                gn = problem.omega * gk
+                gn[0] = 0.0
+                M = problem.c.shape[1]
+                gs = gs.reshape(-1, 2, M)  # per interface: cos then sin
+                gc = gs[:, 0, :] * np.sin(problem.psi) + gs[:, 1, :] * np.cos(problem.psi)
+                fctx.save_for_backward(torch.as_tensor(gc, dtype=c.dtype), torch.as_tensor(gn, dtype=n.dtype))
                 return torch.as_tensor(J, dtype=n.dtype)
 
             @staticmethod
             def backward(fctx, gout):
-                (g,) = fctx.saved_tensors
-                return gout * g, None, None, None
+                gc, gn = fctx.saved_tensors
+                return gout * gc, gout * gn, None, None, None
 
         return _F

@@ -81,7 +81,7 @@ SIGNATURES = {
     "mlh_field": (C.c_int32, [C.c_void_p, C.c_double, C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double),
                               C.c_int32, C.c_void_p, C.c_void_p]),
     "mlh_adjoint": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double),
-                                C.POINTER(C.c_double)]),
+                                C.POINTER(C.c_double), C.c_void_p]),
     "mlh_batch_create": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]),
     "mlh_batch_destroy": (C.c_int32, [C.c_void_p]),
     "mlh_batch_solve": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.c_int32, C.c_void_p,

@@ -268,8 +268,8 @@ struct LsAdjJob {      // ell[0:m] = (Q'^+)^T v from the QR [Q'; mu I] = Q_f R k
   int M, m, c;
 };
 struct BilinJob {      // acc[out] += scale * left^T (sum_p coef_p P_p) right
-  const cplx* P[3];
-  cplx coef[3];
+  const cplx* P[6];
+  cplx coef[6];
   const cplx* left;
   const cplx* right;
   double scale;

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <map>
 #include <memory>
 #include <string>
 #include <vector>
@@ -2390,8 +2391,16 @@ extern "C" mlh_status mlh_field(mlh_stack s, double theta, int64_t n_pts, const 
 // ---------------------------------------------------------------------------
 // adjoint: gradient of the summed zeroth-order reflected efficiency
 // ---------------------------------------------------------------------------
+// the shape part of the adjoint (below): derivative pieces of the blocks that
+// touch one smooth interface, in one shape coefficient, by central
+// differences of the fill kernels at perturbed node geometry
+static mlh_status adjoint_shape(mlh_stack s, int32_t n_angles, const double* theta, const std::vector<SysSpec>& sys,
+                                const std::vector<int64_t>& doff, const cplx* d_eta, const cplx* d_z, const cplx* d_c,
+                                const cplx* d_l, const std::vector<size_t>& loff, size_t msum,
+                                const std::vector<double>& aU, const std::vector<int>& q0, double* grad_shape);
+
 extern "C" mlh_status mlh_adjoint(mlh_stack s, int32_t n_angles, const double* theta, double* J_out,
-                                  double* grad_k) {
+                                  double* grad_k, double* grad_shape) {
   if (!s || n_angles < 1 || !theta || !grad_k) return fail(MLH_E_INVALID_ARG, "mlh_adjoint: bad arguments");
   for (int a = 0; a < n_angles; ++a)
     if (!theta_ok(theta[a])) return fail(MLH_E_INVALID_ARG, "incident angle must lie in (-pi, 0)");
@@ -2567,6 +2576,7 @@ extern "C" mlh_status mlh_adjoint(mlh_stack s, int32_t n_angles, const double* t
     for (size_t q = 0; q < sys[b].ang.size(); ++q) {
       const int a = sys[b].ang[q];
       const cplx* eta_a = d_eta + (size_t)nden * a;
+      (void)eta_a;
       const cplx* z_a = d_z + (size_t)nden * a;
       cplx* c_a = d_c + (size_t)a * (I + 1) * P;
       cplx* v_a = d_v + (size_t)a * csum;
@@ -2732,6 +2742,342 @@ extern "C" mlh_status mlh_adjoint(mlh_stack s, int32_t n_angles, const double* t
     add(I, -wr, -wi);
   }
   if (J_out) *J_out = Jsum;
+  if (grad_shape)
+    MLH_TRY(adjoint_shape(s, n_angles, theta, sys, doff, d_eta, d_z, d_c, d_l, loff, msum, aU, q0, grad_shape));
+  return MLH_OK;
+}
+
+static mlh_status adjoint_shape(mlh_stack s, int32_t n_angles, const double* theta, const std::vector<SysSpec>& sys,
+                                const std::vector<int64_t>& doff, const cplx* d_eta, const cplx* d_z, const cplx* d_c,
+                                const cplx* d_l, const std::vector<size_t>& loff, size_t msum,
+                                const std::vector<double>& aU, const std::vector<int>& q0, double* grad_shape) {
+  hipStream_t st = s->ctx->stream;
+  const int I = s->I, P = s->P, nK = s->nK;
+  const int64_t nden = doff[I];
+  const int mw2 = 2 * s->Mw, mud2 = 2 * s->Mud;
+  // the parameters: cos then sin coefficients of every smooth interface
+  struct Par {
+    int i, m, sinpart;
+    int64_t out;
+  };
+  std::vector<Par> par;
+  int64_t nout = 0;
+  for (int i = 0; i < I; ++i) {
+    const HostCurve& c = s->curves[i];
+    if (c.cornered) continue;
+    const int nm = (int)c.prof.om.size();
+    for (int sp = 0; sp < 2; ++sp)
+      for (int m = 0; m < nm; ++m) par.push_back(Par{i, m, sp, nout + sp * nm + m});
+    nout += 2 * nm;
+  }
+  for (int64_t t = 0; t < nout; ++t) grad_shape[t] = 0.0;
+  if (par.empty()) return MLH_OK;
+  // central differences in the coefficient: step relative to the profile's size
+  double hstep = 1e-6;
+  {
+    double amp = 0.0;
+    for (int i = 0; i < I; ++i)
+      for (double v : s->curves[i].prof.ca) amp = std::max(amp, std::fabs(v));
+    for (int i = 0; i < I; ++i)
+      for (double v : s->curves[i].prof.sa) amp = std::max(amp, std::fabs(v));
+    if (amp > 0) hstep = 1e-5 * std::max(amp, 1e-3 * s->d);
+  }
+  // adjoint densities z of interface 1 on the host (right-hand-side term)
+  std::vector<double> z1((size_t)2 * s->n[0] * n_angles);
+  for (int a = 0; a < n_angles; ++a)
+    HIP_TRY(hipMemcpyAsync(z1.data() + (size_t)2 * s->n[0] * a, d_z + (size_t)nden * a, cbytes(s->n[0]),
+                           hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  const int chunk = 16;  // parameters per pass (two perturbed geometries each)
+  for (size_t p0 = 0; p0 < par.size(); p0 += chunk) {
+    const int np_ = (int)std::min(par.size() - p0, (size_t)chunk);
+    // ---- perturbed geometry and the pieces of the blocks that touch it
+    std::vector<HostCurve> cur(2 * np_);
+    Arena ar;
+    std::vector<size_t> o_geo(2 * np_), o_aux(2 * np_);
+    for (int t = 0; t < 2 * np_; ++t) {
+      const Par& pp = par[p0 + t / 2];
+      const HostCurve& c0 = s->curves[pp.i];
+      std::vector<double> ca(c0.prof.ca), sa(c0.prof.sa);
+      (pp.sinpart ? sa : ca)[pp.m] += (t % 2 == 0 ? 1.0 : -1.0) * hstep;
+      mlh_interface in{};
+      in.kind = MLH_IFACE_FOURIER;
+      in.y0 = c0.y0;
+      in.n_modes = (int)ca.size();
+      in.cos_coef = ca.data();
+      in.sin_coef = sa.data();
+      in.n_nodes = c0.N;
+      build_fourier_curve(in, s->d, cur[t]);
+      o_geo[t] = ar.reserve(sizeof(double) * 5 * c0.N);
+      o_aux[t] = ar.reserve(sizeof(double) * 6 * (size_t)c0.N * kAlpertAux);
+    }
+    // jobs: for every perturbation, the self and Alpert jobs of its interface
+    // and the fill jobs whose targets or sources lie on it, with the
+    // perturbed geometry and outputs in scratch pieces of the same shapes
+    std::vector<std::map<const cplx*, size_t>> omap(2 * np_);
+    auto scratch = [&](int t, const cplx* orig, size_t elems) -> size_t {
+      auto it = omap[t].find(orig);
+      if (it != omap[t].end()) return it->second;
+      const size_t o = ar.reserve(cbytes(elems));
+      omap[t][orig] = o;
+      return o;
+    };
+    struct FJ {
+      FillJob J;
+      int t;
+      size_t out[3], out_t[3];
+    };
+    std::vector<FJ> fjobs;
+    std::vector<std::pair<SelfJob, int>> sjobs;
+    std::vector<std::pair<AlpertJob, int>> ajobs;
+    std::vector<size_t> sout(2 * np_);
+    for (int t = 0; t < 2 * np_; ++t) {
+      const int i = par[p0 + t / 2].i;
+      const int n = s->n[i];
+      sout[t] = scratch(t, s->A_self[i], (size_t)3 * n * n);
+      for (const FillJob& F : s->h_fill) {
+        const bool tg = F.tx == s->gx[i], sr = F.sx == s->gx[i];
+        if (!tg && !sr) continue;
+        FJ f{F, t, {0, 0, 0}, {0, 0, 0}};
+        const size_t cols = F.kind == kFillProxy ? (size_t)F.Ns : (size_t)2 * F.Ns;
+        for (int l = 0; l < F.npieces; ++l) f.out[l] = scratch(t, F.out[l], (size_t)F.ld * cols);
+        if (F.kind == kFillPair)
+          for (int l = 0; l < F.npieces; ++l) f.out_t[l] = scratch(t, F.out_t[l], (size_t)F.ld_t * 2 * F.Mt);
+        fjobs.push_back(f);
+      }
+    }
+    const size_t o_fj = ar.reserve(sizeof(FillJob) * fjobs.size()),
+                 o_sj = ar.reserve(sizeof(SelfJob) * 2 * np_), o_aj = ar.reserve(sizeof(AlpertJob) * 2 * np_);
+    char* buf = nullptr;
+    hipError_t e = hipMalloc((void**)&buf, ar.off);
+    if (e != hipSuccess)
+      return fail(e == hipErrorOutOfMemory ? MLH_E_NOMEM : MLH_E_DEVICE, "mlh_adjoint: shape allocation");
+    struct Free {
+      char* p;
+      ~Free() { (void)hipFree(p); }
+    } guard{buf};
+    auto dp = [&](size_t o) { return reinterpret_cast<double*>(buf + o); };
+    auto cpp = [&](size_t o) { return reinterpret_cast<cplx*>(buf + o); };
+    std::vector<double> hb;
+    std::vector<FillJob> fj;
+    std::vector<SelfJob> sj;
+    std::vector<AlpertJob> aj;
+    int ftiles = 0, stiles = 0, ablocks = 0;
+    for (int t = 0; t < 2 * np_; ++t) {
+      const int i = par[p0 + t / 2].i;
+      const int N = s->N[i];
+      const HostCurve& c = cur[t];
+      hb.clear();
+      for (auto* v : {&c.x, &c.y, &c.nx, &c.ny, &c.w}) hb.insert(hb.end(), v->begin(), v->end());
+      HIP_TRY(hipMemcpyAsync(dp(o_geo[t]), hb.data(), hb.size() * sizeof(double), hipMemcpyHostToDevice, st));
+      hb.clear();
+      for (auto* v : {&c.ar2, &c.and_, &c.anpd, &c.ann, &c.acw, &c.at}) hb.insert(hb.end(), v->begin(), v->end());
+      HIP_TRY(hipMemcpyAsync(dp(o_aux[t]), hb.data(), hb.size() * sizeof(double), hipMemcpyHostToDevice, st));
+      const double* gx = dp(o_geo[t]);
+      const double *gy = gx + N, *gnx = gx + 2 * N, *gny = gx + 3 * N, *gw = gx + 4 * N;
+      const size_t na = (size_t)N * kAlpertAux;
+      const double* ax = dp(o_aux[t]);
+      SelfJob S = s->h_self[i];
+      S.x = gx;
+      S.y = gy;
+      S.nx = gnx;
+      S.ny = gny;
+      S.w = gw;
+      const size_t pe = (size_t)s->n[i] * s->n[i];
+      for (int l = 0; l < 3; ++l) S.out[l] = cpp(sout[t]) + l * pe;
+      S.tile_begin = stiles;
+      stiles += S.tiles_m * (S.tiles_m + 1) / 2;
+      sj.push_back(S);
+      AlpertJob A = s->h_alp[i];
+      A.r2 = ax;
+      A.nd = ax + na;
+      A.npd = ax + 2 * na;
+      A.nn = ax + 3 * na;
+      A.cw = ax + 4 * na;
+      A.t = ax + 5 * na;
+      for (int l = 0; l < 3; ++l) A.out[l] = S.out[l];
+      A.block_begin = ablocks;
+      ablocks += A.N;
+      aj.push_back(A);
+    }
+    for (FJ& f : fjobs) {
+      FillJob J = f.J;
+      const int i = par[p0 + f.t / 2].i;
+      const int N = s->N[i];
+      const double* gx = dp(o_geo[f.t]);
+      if (J.tx == s->gx[i]) {
+        J.tx = gx;
+        J.ty = gx + N;
+        J.tnx = gx + 2 * N;
+        J.tny = gx + 3 * N;
+        if (J.kind == kFillPair) J.tw = gx + 4 * N;
+      }
+      if (J.sx == s->gx[i]) {
+        J.sx = gx;
+        J.sy = gx + N;
+        J.snx = gx + 2 * N;
+        J.sny = gx + 3 * N;
+        J.sw = gx + 4 * N;
+      }
+      for (int l = 0; l < J.npieces; ++l) {
+        J.out[l] = cpp(f.out[l]);
+        if (J.kind == kFillPair) J.out_t[l] = cpp(f.out_t[l]);
+      }
+      J.dk = 0;
+      const int tm = J.kind == kFillPair ? kSelfTile : kFillTileM, tn = J.kind == kFillPair ? kSelfTile : kFillTileN;
+      J.tile_begin = ftiles;
+      ftiles += J.tiles_m * ((J.Ns + tn - 1) / tn);
+      (void)tm;
+      fj.push_back(J);
+    }
+    HIP_TRY(hipMemcpyAsync(buf + o_fj, fj.data(), sizeof(FillJob) * fj.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(buf + o_sj, sj.data(), sizeof(SelfJob) * sj.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(buf + o_aj, aj.data(), sizeof(AlpertJob) * aj.size(), hipMemcpyHostToDevice, st));
+    launch_self(reinterpret_cast<SelfJob*>(buf + o_sj), (int)sj.size(), stiles, kAlpertA, st);
+    launch_alpert(reinterpret_cast<AlpertJob*>(buf + o_aj), (int)aj.size(), ablocks, kAlpertA, st);
+    launch_fill(reinterpret_cast<FillJob*>(buf + o_fj), (int)fj.size(), ftiles, st);
+    HIP_TRY(hipGetLastError());
+    // ---- contractions: (P+ - P-)/2h of every touched block with the adjoint
+    //      and forward vectors, per angle and parameter
+    std::vector<BilinJob> blj;
+    int btiles = 0;
+    const size_t nacc = (size_t)n_angles * np_;
+    auto bil = [&](int pidx, int a, const cplx* const* Pp, const cplx* const* Pm, const cplx* coef, int np, int rows,
+                   int cols, int ld, const cplx* left, const cplx* right, double scale) {
+      BilinJob B{};
+      const double ih = 0.5 / hstep;
+      for (int q = 0; q < np; ++q) {
+        B.P[q] = Pp[q];
+        B.coef[q] = cx(coef[q].re * ih, coef[q].im * ih);
+        B.P[np + q] = Pm[q];
+        B.coef[np + q] = cx(-coef[q].re * ih, -coef[q].im * ih);
+      }
+      B.np = 2 * np;
+      B.rows = rows;
+      B.cols = cols;
+      B.ld = ld;
+      B.left = left;
+      B.right = right;
+      B.scale = scale;
+      B.out = (int)((size_t)a * np_ + pidx);
+      B.tile_begin = btiles;
+      btiles += ((rows + 63) / 64) * ((cols + 63) / 64);
+      blj.push_back(B);
+    };
+    const cplx one = cx(1.0, 0.0);
+    for (int pidx = 0; pidx < np_; ++pidx) {
+      const int i = par[p0 + pidx].i;
+      const int tp = 2 * pidx, tm_ = 2 * pidx + 1;
+      auto piece = [&](int t, const cplx* orig) { return cpp(omap[t].at(orig)); };
+      for (int a = 0; a < n_angles; ++a) {
+        const cplx* eta_a = d_eta + (size_t)nden * a;
+        const cplx* z_a = d_z + (size_t)nden * a;
+        const cplx* c_a = d_c + (size_t)a * (I + 1) * P;
+        const cplx* l_a = d_l + (size_t)a * msum;
+        const double ph = s->d * s->k[0] * std::cos(theta[a]);
+        const cplx am1 = cpow_alpha(ph, -1), ap1 = cpow_alpha(ph, 1), am2 = cpow_alpha(ph, -2);
+        const cplx c3[3] = {am1, one, ap1};
+        const cplx cC[2] = {am2, cx(-ap1.re, -ap1.im)};
+        const int n = s->n[i];
+        const size_t pe = (size_t)n * n;
+        {
+          const cplx* pp[3] = {cpp(sout[tp]), cpp(sout[tp]) + pe, cpp(sout[tp]) + 2 * pe};
+          const cplx* pm[3] = {cpp(sout[tm_]), cpp(sout[tm_]) + pe, cpp(sout[tm_]) + 2 * pe};
+          bil(pidx, a, pp, pm, c3, 3, n, n, n, z_a + doff[i], eta_a + doff[i], 1.0);
+        }
+        auto pair3 = [&](const cplx* base, size_t pel, int rows, int cols, const cplx* left, const cplx* right) {
+          const cplx* pp[3] = {piece(tp, base), piece(tp, base + pel), piece(tp, base + 2 * pel)};
+          const cplx* pm[3] = {piece(tm_, base), piece(tm_, base + pel), piece(tm_, base + 2 * pel)};
+          bil(pidx, a, pp, pm, c3, 3, rows, cols, rows, left, right, 1.0);
+        };
+        if (i > 0) {
+          const size_t pu = (size_t)s->n[i - 1] * n;
+          pair3(s->A_up[i - 1], pu, s->n[i - 1], n, z_a + doff[i - 1], eta_a + doff[i]);
+          pair3(s->A_dn[i - 1], pu, n, s->n[i - 1], z_a + doff[i], eta_a + doff[i - 1]);
+        }
+        if (i + 1 < I) {
+          const size_t pu = (size_t)n * s->n[i + 1];
+          pair3(s->A_up[i], pu, n, s->n[i + 1], z_a + doff[i], eta_a + doff[i + 1]);
+          pair3(s->A_dn[i], pu, s->n[i + 1], n, z_a + doff[i + 1], eta_a + doff[i]);
+        }
+        {
+          const cplx* pp[1] = {piece(tp, s->B_own[i])};
+          const cplx* pm[1] = {piece(tm_, s->B_own[i])};
+          bil(pidx, a, pp, pm, &one, 1, n, P, n, z_a + doff[i], c_a + (size_t)i * P, 1.0);
+          const cplx* qp[1] = {piece(tp, s->B_below[i])};
+          const cplx* qm[1] = {piece(tm_, s->B_below[i])};
+          bil(pidx, a, qp, qm, &one, 1, n, P, n, z_a + doff[i], c_a + (size_t)(i + 1) * P, 1.0);
+        }
+        {  // walls of the layers above (i) and below (i + 1) the interface
+          const size_t eo = (size_t)mw2 * n;
+          const cplx* pp[2] = {piece(tp, s->C_own[i]), piece(tp, s->C_own[i] + eo)};
+          const cplx* pm[2] = {piece(tm_, s->C_own[i]), piece(tm_, s->C_own[i] + eo)};
+          bil(pidx, a, pp, pm, cC, 2, mw2, n, mw2, l_a + loff[i], eta_a + doff[i], -1.0);
+          const cplx* qp[2] = {piece(tp, s->C_above[i + 1]), piece(tp, s->C_above[i + 1] + eo)};
+          const cplx* qm[2] = {piece(tm_, s->C_above[i + 1]), piece(tm_, s->C_above[i + 1] + eo)};
+          bil(pidx, a, qp, qm, cC, 2, mw2, n, mw2, l_a + loff[i + 1], eta_a + doff[i], -1.0);
+        }
+        const size_t ze = (size_t)mud2 * n;
+        if (i == 0) {
+          const cplx* pp[3] = {piece(tp, s->Z_U), piece(tp, s->Z_U + ze), piece(tp, s->Z_U + 2 * ze)};
+          const cplx* pm[3] = {piece(tm_, s->Z_U), piece(tm_, s->Z_U + ze), piece(tm_, s->Z_U + 2 * ze)};
+          bil(pidx, a, pp, pm, c3, 3, mud2, n, mud2, l_a + loff[0] + mw2, eta_a + doff[0], -1.0);
+        }
+        if (i == I - 1) {
+          const cplx* pp[3] = {piece(tp, s->Z_D), piece(tp, s->Z_D + ze), piece(tp, s->Z_D + 2 * ze)};
+          const cplx* pm[3] = {piece(tm_, s->Z_D), piece(tm_, s->Z_D + ze), piece(tm_, s->Z_D + 2 * ze)};
+          bil(pidx, a, pp, pm, c3, 3, mud2, n, mud2, l_a + loff[I] + mw2, eta_a + doff[I - 1], -1.0);
+        }
+      }
+    }
+    Arena jb;
+    const size_t o_b = jb.reserve(sizeof(BilinJob) * blj.size()), o_acc = jb.reserve(sizeof(double) * 2 * nacc);
+    char* jbuf = nullptr;
+    e = hipMalloc((void**)&jbuf, jb.off);
+    if (e != hipSuccess)
+      return fail(e == hipErrorOutOfMemory ? MLH_E_NOMEM : MLH_E_DEVICE, "mlh_adjoint: shape allocation");
+    Free guard2{jbuf};
+    double* d_acc = reinterpret_cast<double*>(jbuf + o_acc);
+    HIP_TRY(hipMemcpyAsync(jbuf + o_b, blj.data(), sizeof(BilinJob) * blj.size(), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemsetAsync(d_acc, 0, sizeof(double) * 2 * nacc, st));
+    launch_bilinear(reinterpret_cast<BilinJob*>(jbuf + o_b), (int)blj.size(), btiles, d_acc, st);
+    HIP_TRY(hipGetLastError());
+    std::vector<double> acc(2 * nacc);
+    HIP_TRY(hipMemcpyAsync(acc.data(), d_acc, sizeof(double) * acc.size(), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    // ---- the right-hand side f on interface 1 (incident field and its
+    //      normal derivative, negated) moves with that interface's nodes:
+    //      its term is l_eta^T df = -z_1^T df
+    for (int pidx = 0; pidx < np_; ++pidx) {
+      const Par& pp = par[p0 + pidx];
+      for (int a = 0; a < n_angles; ++a) {
+        double dr = acc[2 * ((size_t)a * np_ + pidx)], di = acc[2 * ((size_t)a * np_ + pidx) + 1];
+        if (pp.i == 0) {
+          const double kx = s->k[0] * std::cos(theta[a]), ky = s->k[0] * std::sin(theta[a]);
+          const int N1 = s->N[0];
+          double fr = 0.0, fi = 0.0;  // z_1^T (f+ - f-)
+          for (int sg = 0; sg < 2; ++sg) {
+            const HostCurve& c = cur[2 * pidx + sg];
+            const double w = (sg == 0 ? 1.0 : -1.0) * 0.5 / hstep;
+            for (int j = 0; j < N1; ++j) {
+              const double ang = kx * c.x[j] + ky * (c.y0 + c.y[j]);
+              const double cs = std::cos(ang), sn = std::sin(ang);
+              const double dn = kx * c.nx[j] + ky * c.ny[j];
+              const double f0r = -cs, f0i = -sn;     // -e
+              const double f1r = dn * sn, f1i = -dn * cs;  // -(i dn) e
+              const double* z = z1.data() + (size_t)2 * s->n[0] * a;
+              fr += w * (z[2 * j] * f0r - z[2 * j + 1] * f0i + z[2 * (N1 + j)] * f1r - z[2 * (N1 + j) + 1] * f1i);
+              fi += w * (z[2 * j] * f0i + z[2 * j + 1] * f0r + z[2 * (N1 + j)] * f1i + z[2 * (N1 + j) + 1] * f1r);
+            }
+          }
+          dr -= fr;
+          di -= fi;
+        }
+        const double a0r = aU[(size_t)2 * nK * a + 2 * q0[a]], a0i = aU[(size_t)2 * nK * a + 2 * q0[a] + 1];
+        grad_shape[pp.out] += 2.0 * (a0r * dr + a0i * di);
+      }
+    }
+  }
   return MLH_OK;
 }
 
