@@ -14,8 +14,14 @@ Default workload: the 1000-interface stack, 70 % random smooth interfaces
 triangle on a flat; Kress-graded segments, q = 6), spacing 1.5, d = 2 pi,
 k_j = 10 n_j with n_j ~ U[1,2], discretised at N = 260 (smooth) / 500
 (cornered) nodes, P = 140, M_w = 100, M_ud = 60, K = 25 (804242 unknowns per
-angle); one step is a sweep of 100 incident angles on a kappa_0 grid that
-holds 20 distinct Bloch phases (Sec. 3.4), 5 angles each.
+angle); one step is a sweep of 100 incident angles uniform in (-pi/2, 0),
+each with its own Bloch phase, in one graph-captured launch sequence
+(Sec. 3.4: the alpha-independent pieces are filled once per step).
+
+Other workloads (--workload): the same stack on a kappa_0 grid of 20 Bloch
+phases (angles that share a phase share one factorisation), the literal
+sizes, the 50-interface stack, the 64-stack batch (mlh_batch_solve) and the
+adjoint gradient of the 100-interface problem (mlh_adjoint).
 """
 import argparse
 import json
@@ -56,6 +62,15 @@ WORKLOADS = {
                 "64 independent stacks, I ~ U{10..200}, N ~ U{60..250} per interface, 70% random Fourier / 30% "
                 "cornered, k = omega n with omega ~ U[5,20], n ~ U[1,2.5], P=60, M_w=60, M_ud=60, K=25; one "
                 "random angle per stack", "batch"),
+    # the adjoint gradient of a ShapeProblem (mlh_adjoint)
+    "config5_resolved": ("config5", dict(N=260, P=120, M_w=80),
+                         "I=100 smooth interfaces, 5 sine amplitudes each (500) and 101 layer indices, omega=10, "
+                         "N=260, P=120, M_w=80, M_ud=60, K=25; J = summed zeroth-order reflected efficiency over 10 "
+                         "angles in (-pi/3, 0)", "adjoint"),
+    "config5": ("config5", dict(),
+                "I=100 smooth interfaces, 5 sine amplitudes each and 101 layer indices, omega=10, N=100, P=50, "
+                "M_w=50, M_ud=60, K=25 (literal sizes, under-resolved); J over 10 angles in (-pi/3, 0)",
+                "adjoint"),
 }
 
 
@@ -353,12 +368,79 @@ def bench_batch(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_adjoint(args):
+    """One step = the gradient of J (summed zeroth-order reflected
+    efficiency over the problem's angles) in every shape amplitude and
+    layer index below the top: refill, forward solve, transposed solve,
+    least-squares adjoint, derivative fills and contractions (mlh_adjoint).
+    Beside it: the same gradient by central differences of the GPU forward
+    solve, timed on a few parameters and scaled to all of them."""
+    import numpy as np
+    import torch
+    import workloads
+    import paper_1410_5003_amd as mlh
+    gen, kw, desc_txt, _ = WORKLOADS[args.workload]
+    pb = getattr(workloads, gen)(**kw)
+    desc = pb.stack()
+    th = np.asarray(desc.thetas, dtype=float)
+    ctx = mlh.Context(0)
+    st = mlh.Stack(ctx, desc)
+    info = st.info()
+    n_par = pb.c.size + pb.n.size - 1
+    steps = args.steps if args.steps is not None else 5
+    warmup = args.warmup if args.warmup is not None else 1
+    print("workload %s: I=%d n_tot=%d angles %d parameters %d" % (args.workload, desc.I, info["n_tot"], th.size,
+                                                                 n_par), file=sys.stderr, flush=True)
+    for _ in range(warmup):
+        st.refill()
+        st.adjoint(th, shape=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st.refill()
+        J, gk, gs = st.adjoint(th, shape=True)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    out = st.solve(th)
+    flux = np.abs(out.flux_err)
+    st.close()
+    # central differences of the forward solve (stack built and solved per
+    # evaluation, as a caller without the adjoint would)
+    nfd = 4
+    p0 = pb.params()
+    torch.cuda.synchronize()
+    tf = time.perf_counter()
+    for q in range(nfd):
+        for sgn in (1.0, -1.0):
+            e = np.zeros_like(p0)
+            e[q] = sgn * 1e-6
+            s2 = mlh.Stack(ctx, pb.stack(p0 + e))
+            s2.solve(th)
+            s2.close()
+    torch.cuda.synchronize()
+    fd_per_param = (time.perf_counter() - tf) / nfd
+    fd_total = fd_per_param * n_par
+    line = {
+        "metric": METRIC, "value": 1e3 / ms, "unit": "grads/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 (complex128)", "data": "synthetic (seeded stacks)",
+        "config": {"workload": args.workload, "description": desc_txt, "interfaces": desc.I,
+                   "unknowns": info["n_tot"], "angles": int(th.size), "parameters": int(n_par)},
+        "J": J, "flux_err_max": float(flux.max()),
+        "fd_by_gpu": {"s_per_gradient": fd_total, "s_per_parameter": fd_per_param, "sampled_parameters": nfd},
+        "speedup_vs_fd": fd_total / (ms * 1e-3),
+    }
+    print("adjoint %.1f ms per gradient; central differences %.1f s (%.3f s per parameter)" %
+          (ms, fd_total, fd_per_param), file=sys.stderr, flush=True)
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="config3_kgrid_resolved", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="config3_resolved", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-layers", type=int, default=None,
                     help="interfaces of the workload the oracle solves for the CPU baseline "
@@ -388,6 +470,8 @@ def main():
         sys.exit(2)
     if WORKLOADS[args.workload][3] == "batch":
         return bench_batch(args)
+    if WORKLOADS[args.workload][3] == "adjoint":
+        return bench_adjoint(args)
     import numpy as np
     import torch
     import paper_1410_5003_amd as mlh
@@ -395,7 +479,9 @@ def main():
     desc = make_desc(args.workload)
     thetas = step_thetas(args.workload, desc)
     sweep = len(thetas) > 1
-    steps = args.steps if args.steps is not None else (5 if sweep else 20)
+    # a sweep of 100 distinct Bloch phases is about a minute per step
+    n_sys0 = distinct_alpha(desc, thetas)
+    steps = args.steps if args.steps is not None else (1 if n_sys0 > 40 else (5 if sweep else 20))
     warmup = args.warmup if args.warmup is not None else (1 if sweep else 3)
     sample_layers = args.cpu_sample_layers or (8 if sweep else 6)
     ctx = mlh.Context(0)
