@@ -402,6 +402,7 @@ constexpr int kGjeMaxN = 1024; // largest block order: the panel kernel holds 2 
 
 constexpr int kGjePivStride = 84;  // ints per step: count, 2 NB destinations, 2 NB sources, NB pivot rows
 constexpr int kRhsMaxN16 = 608;    // largest order whose 16-column right-hand-side tile fits in LDS
+constexpr int kRhsMaxN10 = 1008;   // and a 10-column tile (157.5 KiB of the 160 KiB)
 
 // one matrix W = [D | right-hand sides] (n x ncol, ld n) reduced to [. | D^{-1} rhs]
 struct GjeDesc {

@@ -1113,6 +1113,195 @@ __global__ __launch_bounds__(kRhsWaves * 64) void gje_rhs_kernel(const GjeDesc* 
   }
 }
 
+// Register-resident replay for orders above kRhsMaxN16 (up to kGjeMaxN):
+// a 16-column tile of such an order does not fit in LDS, but it does fit in
+// the matrix-core accumulators of eight wavefronts, two per SIMD (256
+// registers each).  Wave w holds the 16-row blocks w, w + 8, ... (up to 8
+// of them) of the tile, real and imaginary parts apart: register q of lane
+// (lq, lr) is row r0 + lq + 4 q of column lr.  So all 16 lanes of a column
+// do useful products (the LDS tile of these orders only had room for 8 or
+// 10 columns) and the tile never passes through LDS.  Per step:
+//   (1) the owners of the pivot rows and of the rows the interchanges move
+//       below the pivot block write them to an LDS stage (double-buffered
+//       over steps, one barrier per step);
+//   (2) every wave reads the pivot rows as its B operand, the owners of
+//       interchange destinations take their new values from the stage;
+//   (3) the pivot block becomes M1 Y(pivot rows), every other block
+//       Y -= P' Y(pivot rows), four real products per complex one
+//       accumulating straight into the tile (three, as elsewhere, would
+//       need temporaries the register budget does not have); the
+//       multipliers of the next block load while the current block's
+//       products run (the scheduling barriers keep the compiler from
+//       hoisting more loads than the budget holds).
+// The step's interchange record is read one step ahead, one entry per lane,
+// and broadcast with readlane.
+constexpr int kRegWaves = 8;
+constexpr int kRegBlk = kGjeMaxN / 16 / kRegWaves;  // 8 row blocks per wave
+constexpr int kRegAhead = 1;                         // multiplier blocks in flight
+
+__device__ __forceinline__ double2 tile_get(const dvec4* Yr, const dvec4* Yi, int j, int q) {
+  double2 v = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int jj = 0; jj < kRegBlk; ++jj)
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq)
+      if (jj == j && qq == q) v = make_double2(Yr[jj][qq], Yi[jj][qq]);
+  return v;
+}
+__device__ __forceinline__ void tile_set(dvec4* Yr, dvec4* Yi, int j, int q, double2 v) {
+#pragma unroll
+  for (int jj = 0; jj < kRegBlk; ++jj)
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq)
+      if (jj == j && qq == q) {
+        Yr[jj][qq] = v.x;
+        Yi[jj][qq] = v.y;
+      }
+}
+
+__global__ __launch_bounds__(kRegWaves * 64) __attribute__((amdgpu_waves_per_eu(2, 2))) void gje_rhs_reg_kernel(
+    const GjeDesc* __restrict__ descs, int nbatch, int tiles_per, int s0, int s1) {
+  constexpr int TC = 16;
+  const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  const int lr = lane & 15, lq = lane >> 4;
+  // stage slots: 16 pivot rows, then up to 2 NB interchange sources
+  __shared__ double2 stage[2][3 * kGjeNb][TC];
+  for (int tile = blockIdx.x; tile < nbatch * tiles_per; tile += gridDim.x) {
+    const GjeDesc& D = descs[tile / tiles_per];
+    const int n = D.n;
+    const int c0 = n + (tile % tiles_per) * TC;
+    if (c0 >= D.ncol) continue;
+    const int nc = min(TC, D.ncol - c0);
+    cplx* W = D.W;
+    dvec4 Yr[kRegBlk], Yi[kRegBlk];
+    {
+      const int col = c0 + min(lr, nc - 1);  // clamped: columns past nc are not stored
+#pragma unroll
+      for (int j = 0; j < kRegBlk; ++j) {
+        const int r0 = (wave + j * kRegWaves) * 16;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double2 v = ldc(W + (uint32_t)(col * n + min(r0 + lq + 4 * q, n - 1)));
+          Yr[j][q] = v.x;
+          Yi[j][q] = v.y;
+        }
+      }
+    }
+    const int nsteps = min(s1, (n + kGjeNb - 1) / kGjeNb);
+    // interchange record of a step: lane t holds entry 1 + t (destinations
+    // 0..31, then sources 0..31) in ra and entry 65 + t (pivot rows) in rb
+    auto load_rec = [&](int sidx, int& ra, int& rb, int& naff) {
+      const auto piv = gmem(D.piv + (size_t)sidx * kGjePivStride);
+      ra = piv[1 + lane];
+      rb = piv[1 + 4 * kGjeNb + min(lane, kGjeNb - 1)];
+      naff = piv[0];
+    };
+    // multipliers P' of step k for row block j (lane: row r0 + lr, column 4 kk + lq)
+    auto load_p = [&](int k, int nb, int j, double2* dst) {
+      const int row = min((wave + j * kRegWaves) * 16 + lr, n - 1);
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk)
+        dst[kk] = ldc(W + (uint32_t)((k + min(4 * kk + lq, nb - 1)) * n + row));
+    };
+    int ra = 0, rb = 0, naff = 0;
+    double2 pbuf[kRegAhead + 1][4];
+    if (s0 < nsteps) {
+      load_rec(s0, ra, rb, naff);
+#pragma unroll
+      for (int j = 0; j < kRegAhead; ++j) load_p(s0 * kGjeNb, min(kGjeNb, n - s0 * kGjeNb), j, pbuf[j]);
+    }
+    for (int sidx = s0; sidx < nsteps; ++sidx) {
+      const int k = sidx * kGjeNb;
+      const int nb = min(kGjeNb, n - k);
+      const int cra = ra, crb = rb, cnaff = min(__builtin_amdgcn_readfirstlane(naff), 2 * kGjeNb);
+      if (sidx + 1 < nsteps) load_rec(sidx + 1, ra, rb, naff);
+      const int buf = sidx & 1;
+      __builtin_amdgcn_sched_barrier(0);
+      // (1) stage the pivot rows and the sources of rows moved below the block
+      for (int c = 0; c < nb; ++c) {
+        const int R = __builtin_amdgcn_readlane(crb, c);
+        if (((R >> 4) & (kRegWaves - 1)) == wave && lq == (R & 3))
+          stage[buf][c][lr] = tile_get(Yr, Yi, (R >> 4) / kRegWaves, (R & 15) >> 2);
+      }
+      for (int t = 0; t < cnaff; ++t) {
+        const int dst = __builtin_amdgcn_readlane(cra, t);
+        const int R = __builtin_amdgcn_readlane(cra, 2 * kGjeNb + t);
+        if (dst >= k + nb && ((R >> 4) & (kRegWaves - 1)) == wave && lq == (R & 3))
+          stage[buf][kGjeNb + t][lr] = tile_get(Yr, Yi, (R >> 4) / kRegWaves, (R & 15) >> 2);
+      }
+      __syncthreads();
+      __builtin_amdgcn_sched_barrier(0);
+      // (2) the pivot rows as the B operand (lane: row 4 kk + lq, column lr),
+      //     with their negatives; interchange destinations below the block
+      double yr[4], yi[4], nyr[4], nyi[4];
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const double2 v = 4 * kk + lq < nb ? stage[buf][4 * kk + lq][lr] : make_double2(0.0, 0.0);
+        yr[kk] = v.x;
+        yi[kk] = v.y;
+        nyr[kk] = -v.x;
+        nyi[kk] = -v.y;
+      }
+      for (int t = 0; t < cnaff; ++t) {
+        const int R = __builtin_amdgcn_readlane(cra, t);
+        if (R >= k + nb && ((R >> 4) & (kRegWaves - 1)) == wave && lq == (R & 3))
+          tile_set(Yr, Yi, (R >> 4) / kRegWaves, (R & 15) >> 2, stage[buf][kGjeNb + t][lr]);
+      }
+      // (3) products straight into the tile's accumulators (four real
+      //     products per complex one), block by block, the multipliers
+      //     kRegAhead blocks ahead in flight
+      const int pblk = k >> 4;  // the pivot block
+#pragma unroll
+      for (int j = 0; j < kRegBlk; ++j) {
+        __builtin_amdgcn_sched_barrier(0);
+        const int blk = wave + j * kRegWaves;
+        if (j + kRegAhead < kRegBlk) load_p(k, nb, j + kRegAhead, pbuf[(j + kRegAhead) % (kRegAhead + 1)]);
+        if (blk * 16 >= n) continue;
+        double2* a = pbuf[j % (kRegAhead + 1)];
+        if (blk == pblk) {  // Z = M1 Y(pivot rows); M1 is zero past nb
+          const cplx* M1 = D.M1 + (size_t)sidx * kGjeNb * kGjeNb;
+          double2* m = a;
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) m[kk] = gld(M1 + (size_t)(4 * kk + lq) * kGjeNb + lr);  // M1[lr][4 kk + lq]
+          Yr[j] = dvec4{0, 0, 0, 0};
+          Yi[j] = dvec4{0, 0, 0, 0};
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+            Yr[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(m[kk].x, yr[kk], Yr[j], 0, 0, 0);
+            Yi[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(m[kk].x, yi[kk], Yi[j], 0, 0, 0);
+            Yr[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(m[kk].y, nyi[kk], Yr[j], 0, 0, 0);
+            Yi[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(m[kk].y, yr[kk], Yi[j], 0, 0, 0);
+          }
+        } else {  // Y -= P' Y(pivot rows)
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+            Yr[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk].x, nyr[kk], Yr[j], 0, 0, 0);
+            Yi[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk].x, nyi[kk], Yi[j], 0, 0, 0);
+            Yr[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk].y, yi[kk], Yr[j], 0, 0, 0);
+            Yi[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk].y, nyr[kk], Yi[j], 0, 0, 0);
+          }
+        }
+      }
+      if (sidx + 1 < nsteps) {
+#pragma unroll
+        for (int j = 0; j < kRegAhead; ++j) load_p(k + kGjeNb, min(kGjeNb, n - k - kGjeNb), j, pbuf[j]);
+      }
+    }
+    if (lr < nc) {
+#pragma unroll
+      for (int j = 0; j < kRegBlk; ++j) {
+        const int r0 = (wave + j * kRegWaves) * 16;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int row = r0 + lq + 4 * q;
+          if (row < n) gst(W + (size_t)(c0 + lr) * n + row, make_double2(Yr[j][q], Yi[j][q]));
+        }
+      }
+    }
+    __syncthreads();  // the next tile's first step may write the stage buffer read last
+  }
+}
+
 void gje_init() {}
 
 void launch_gje_panel(const GjeDesc* d, int nbatch, int k, int max_n, hipStream_t st) {
@@ -1164,12 +1353,21 @@ void launch_gje_premul(const GjeDesc* d, int nbatch, int max_n, hipStream_t st) 
 void launch_gje_rhs(const GjeDesc* d, int nbatch, int max_rhs, int max_n, int s0, int s1, int max_blocks,
                     hipStream_t st, bool narrow) {
   if (nbatch <= 0 || max_rhs <= 0 || s1 <= s0) return;
-  const bool wide = max_n <= kRhsMaxN16 && !narrow;
-  const int tiles_per = wide ? (max_rhs + 15) / 16 : (max_rhs + 7) / 8;
+  // column tile: 16 (unless narrow), in LDS up to order kRhsMaxN16 and in
+  // registers above; narrow: as many columns as the 160 KiB of LDS hold,
+  // 8 up to order kRhsMaxN16, 10 up to kRhsMaxN10, 8 above
+  const bool big = max_n > kRhsMaxN16;
+  const int tc = !narrow ? 16 : (big && max_n <= kRhsMaxN10 ? 10 : 8);
+  const int tiles_per = (max_rhs + tc - 1) / tc;
   const int total = nbatch * tiles_per;
   const int grid = max_blocks > 0 ? std::min(total, max_blocks) : total;
-  if (wide)
+  if (tc == 16 && big)
+    hipLaunchKernelGGL(gje_rhs_reg_kernel, dim3(grid), dim3(kRegWaves * 64), 0, st, d, nbatch, tiles_per, s0, s1);
+  else if (tc == 16)
     hipLaunchKernelGGL((gje_rhs_kernel<16, kRhsMaxN16>), dim3(grid), dim3(kRhsWaves * 64), 0, st, d, nbatch,
+                       tiles_per, s0, s1);
+  else if (tc == 10)
+    hipLaunchKernelGGL((gje_rhs_kernel<10, kRhsMaxN10>), dim3(grid), dim3(kRhsWaves * 64), 0, st, d, nbatch,
                        tiles_per, s0, s1);
   else
     hipLaunchKernelGGL((gje_rhs_kernel<8, kGjeMaxN>), dim3(grid), dim3(kRhsWaves * 64), 0, st, d, nbatch, tiles_per,

@@ -175,11 +175,19 @@ def test_mixed_smooth_and_cornered_resolved(ctx):
 RES3 = dict(N_smooth=260, N_corner=500, P=140, M_w=100)
 
 
-def test_config3_head_resolved_twin(ctx):
+@pytest.mark.parametrize("replay_cols", [16, 8])
+def test_config3_head_resolved_twin(ctx, replay_cols):
     # first interfaces of the 1000-layer mixed smooth / cornered workload,
-    # refined until the oracle's flux error is below 1e-9, three angles
+    # refined until the oracle's flux error is below 1e-9, three angles.  The
+    # cornered interfaces give diagonal blocks of order 1000: their
+    # right-hand-side replay keeps a 16-column tile in registers by default
+    # and a 10-column LDS tile with the narrow launch choice
+    import paper_1410_5003_amd as mlh
     s = workloads.config3(I=4, n_angles=3, **RES3)
-    g = _gpu(ctx, s, s.thetas)
+    st = mlh.Stack(ctx, s)
+    st.set_tuning(gje_rhs_cols=replay_cols)
+    g = st.solve(s.thetas)
+    st.close()
     for a, t in enumerate(s.thetas):
         o = oracle.solve_stack(s, theta=t)
         assert abs(o.flux_err) < 1e-9 and abs(g.flux_err[a]) < 1e-9
