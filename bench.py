@@ -62,6 +62,15 @@ WORKLOADS = {
                 "64 independent stacks, I ~ U{10..200}, N ~ U{60..250} per interface, 70% random Fourier / 30% "
                 "cornered, k = omega n with omega ~ U[5,20], n ~ U[1,2.5], P=60, M_w=60, M_ud=60, K=25; one "
                 "random angle per stack", "batch"),
+    # resolved twin: omega ~ U[5,8] (k <= 20), I ~ U{10..100} (the device
+    # memory of all 64 stacks at once), every interface raised to 18 k_max
+    # (smooth) / 25 k_max (cornered) nodes, k_max the larger adjacent wavenumber
+    "config4_resolved": ("config4", dict(omega_range=(5.0, 8.0), I_range=(10, 100), P=140, M_w=100,
+                                         nodes_per_k=(18.0, 25.0)),
+                         "64 independent stacks, I ~ U{10..100}, N ~ U{60..250} per interface raised to 18 k_max "
+                         "(smooth) / 25 k_max (cornered), 70% random Fourier / 30% cornered, k = omega n with "
+                         "omega ~ U[5,8], n ~ U[1,2.5], P=140, M_w=100, M_ud=60, K=25; one random angle per stack",
+                         "batch"),
     # the adjoint gradient of a ShapeProblem (mlh_adjoint)
     "config5_resolved": ("config5", dict(N=260, P=120, M_w=80),
                          "I=100 smooth interfaces, 5 sine amplitudes each (500) and 101 layer indices, omega=10, "
@@ -155,24 +164,20 @@ def algorithmic_work(desc):
     return w
 
 
-# HBM bytes moved per dispatch, from one rocprofv3 --pmc FETCH_SIZE pass and
-# one WRITE_SIZE pass over `bench.py --steps 1 --warmup 0 --autotune off` (the
-# default launch choices, which the autotuner keeps on this workload) on the named
-# workload, each scaled by what the same counter reads for a plain 256 MiB
-# device copy (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000); averaged over every
-# dispatch of the run.  An entry counts only while its kernel source is the
-# one the counters were taken on (SHA-1 prefix of the file).
+# HBM bytes moved per dispatch (KiB read, KiB written), from one rocprofv3
+# --pmc FETCH_SIZE pass and one WRITE_SIZE pass over the named workload's
+# `bench.py --workload W --steps 1 --warmup 0 --no-cpu-baseline --autotune off`
+# (default launch choices), each scaled by what the same counter reads for a
+# plain 256 MiB device copy (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000) and
+# averaged over every dispatch of the run.  An entry counts only while its
+# kernel source is the one the counters were taken on (SHA-1 prefix).
 MEASURED_TRAFFIC = {
-    ("config2_resolved", "gje_panel_kernel"): ("kernels_gje.hip", "9a80b99f7aea", 2145.4, 916.4),
-    ("config2_resolved", "gje_update_kernel"): ("kernels_gje.hip", "9a80b99f7aea", 34547.5, 27226.0),
-    ("config2_resolved", "gje_rhs_kernel"): ("kernels_gje.hip", "9a80b99f7aea", 958200.3, 154362.8),
-    ("config2_resolved", "gemv_step_kernel"): ("kernels_gje.hip", "9a80b99f7aea", 58268.1, 58.0),
+    # the least-squares kernels, on the 50-interface stack
     ("config2_resolved", "hq_rhs_kernel"): ("kernels_hq.hip", "5c57e8752f1e", 518092.2, 105209.0),
-    # the panel launches also carry the block-system assembly
+    # (the panel launches also carry the block-system assembly)
     ("config2_resolved", "hq_panel_kernel"): ("kernels_hq.hip", "5c57e8752f1e", 44997.3, 16454.9),
-    ("config2_resolved", "zgemm_kernel"): ("kernels_linalg.hip", "950c962799e9", 2205049.9, 176307.9),
-    ("config2_resolved", "self_kernel"): ("kernels_fill.hip", "c4ed21075aa2", 4465.2, 641872.8),
-    ("config2_resolved", "fill_kernel"): ("kernels_fill.hip", "c4ed21075aa2", 18274.8, 1642474.5),
+    # the 1000-interface, 100-angle sweep (counters on zgemm_kernel dispatches only)
+    ("config3_resolved", "zgemm_kernel"): ("kernels_linalg.hip", "e17c1ccdfb2e", 94636399.4, 7691724.3),
 }
 
 
@@ -309,7 +314,8 @@ def bench_batch(args):
     import torch
     import workloads
     import paper_1410_5003_amd as mlh
-    descs = workloads.config4()
+    gen, kw, desc_txt, _ = WORKLOADS[args.workload]
+    descs = getattr(workloads, gen)(**kw)
     ctx = mlh.Context(0)
     sts = [mlh.Stack(ctx, d) for d in descs]
     b = mlh.Batch(ctx, sts)
@@ -317,7 +323,8 @@ def bench_batch(args):
     n_tot = sum(s.info()["n_tot"] for s in sts)
     steps = args.steps if args.steps is not None else 10
     warmup = args.warmup if args.warmup is not None else 2
-    print("workload config4: %d stacks, %d interfaces, %d unknowns" % (len(descs), sum(d.I for d in descs), n_tot),
+    print("workload %s: %d stacks, %d interfaces, %d unknowns" % (args.workload, len(descs), sum(d.I for d in descs),
+                                                                  n_tot),
           file=sys.stderr, flush=True)
     autotuned = args.autotune in ("auto", "on")
     if autotuned:
@@ -335,6 +342,11 @@ def bench_batch(args):
     ms = (time.perf_counter() - t0) * 1e3 / steps
     lat = out.stack_ms
     flux = np.abs(out.flux_err)
+    tuning = b.get_tuning()
+    # the batch's workspace and pieces are released before the plain solves
+    b.close()
+    for s in sts:
+        s.close()
     # the same stacks one at a time (refill + one-angle solve each, each
     # timed to its own completion after an untimed solve that captures its
     # graph); each is created on its own and destroyed after, since every
@@ -354,14 +366,14 @@ def bench_batch(args):
         "metric": METRIC, "value": len(descs) / (ms * 1e-3), "unit": "solves/s", "n_gpus": 1, "steps": steps,
         "warmup": warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64 (complex128)", "data": "synthetic (seeded stacks)",
-        "config": {"workload": "config4", "description": WORKLOADS["config4"][2], "stacks": len(descs),
+        "config": {"workload": args.workload, "description": desc_txt, "stacks": len(descs),
                    "interfaces": int(sum(d.I for d in descs)), "unknowns": int(n_tot)},
         "unknowns_per_s": n_tot / (ms * 1e-3), "flux_err_median": float(np.median(flux)),
         "flux_err_max": float(flux.max()),
         "latency_ms": {"batched_p50": pct(lat, 50), "batched_p99": pct(lat, 99), "plain_p50": pct(plain, 50),
                        "plain_p99": pct(plain, 99), "plain_total": plain_total},
         "speedup_vs_plain": plain_total / ms,
-        "tuning": dict(b.get_tuning(), autotuned=autotuned),
+        "tuning": dict(tuning, autotuned=autotuned),
     }
     print("batched %.2f ms per step (%d stacks); plain %.2f ms; latency p50 %.2f p99 %.2f ms" %
           (ms, len(descs), plain_total, pct(lat, 50), pct(lat, 99)), file=sys.stderr, flush=True)

@@ -40,11 +40,18 @@ def config3_res40_thetas(desc):
     return -np.arccos(kap / k1)
 
 
+# the resolved 64-stack batch: omega ~ U[5,8], I ~ U{10..100} and every
+# interface raised to 18 k_max (smooth) / 25 k_max (cornered) nodes
+C4R = dict(omega_range=(5.0, 8.0), I_range=(10, 100), P=140, M_w=100, nodes_per_k=(18.0, 25.0))
+C4R_STACKS = (58, 34, 36)  # the three with the fewest interfaces (10, 10, 12)
+
 CASES = {
     # name: (stack generator, angle chooser)
     "config2_resolved": (lambda: workloads.config2(N=260, P=120, M_w=80), lambda d: d.thetas[:1]),
     "config3_res40": (lambda: workloads.config3(I=40, n_angles=3, **RES3), config3_res40_thetas),
 }
+for _j in C4R_STACKS:
+    CASES["config4_resolved_s%d" % _j] = ((lambda j=_j: workloads.config4(**C4R)[j]), lambda d: d.thetas)
 
 
 def make(name):

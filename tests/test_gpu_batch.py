@@ -97,6 +97,34 @@ def test_batch_against_the_oracle():
         s.close()
 
 
+def test_resolved_batch_stacks_against_stored_oracle_results():
+    # three stacks of the resolved 64-stack workload (omega ~ U[5,8], nodes
+    # raised to 18 k_max smooth / 25 k_max cornered, P = 140, M_w = 100; the
+    # oracle's flux error is below 1e-9 on each) in one batch, against the
+    # oracle results that tests/golden/make_golden.py stores
+    import paper_1410_5003_amd as mlh
+    from tests.golden.make_golden import C4R, C4R_STACKS, load as load_golden
+    ctx = context()
+    every = workloads.config4(**C4R)
+    descs = [every[j] for j in C4R_STACKS]
+    sts = [mlh.Stack(ctx, d) for d in descs]
+    b = mlh.Batch(ctx, sts)
+    th = np.array([float(d.thetas[0]) for d in descs])
+    out = b.solve(th)
+    for i, j in enumerate(C4R_STACKS):
+        gold = load_golden("config4_resolved_s%d" % j)[0]
+        assert abs(gold["theta"] - th[i]) < 1e-15
+        assert np.array_equal(out.orders[i], gold["orders"]), j
+        err = rel_amp_err(out.aU[i], out.aD[i], gold["aU"], gold["aD"])
+        print("stack %d (I=%d): rel amp err %.2e  flux gpu %.2e oracle %.2e" % (j, descs[i].I, err, out.flux_err[i],
+                                                                             gold["flux_err"]))
+        assert abs(gold["flux_err"]) <= 1e-9 and abs(out.flux_err[i]) <= 1e-9, j
+        assert err < TOL, (j, err)
+    b.close()
+    for s in sts:
+        s.close()
+
+
 def test_batch_autotune_keeps_results(batch):
     descs, sts, b, th = batch
     t = b.autotune(th, reps=1)

@@ -108,3 +108,17 @@ def test_batch_workload_is_within_the_library_limits():
             assert 37 <= f.N <= 512
             if f.kind == "polygon":
                 assert int(np.min(f.seg_nodes)) >= 37 and int(np.sum(f.seg_nodes)) == f.N
+    # the resolved variant: omega in [5, 8], I in 10..100, the same draws
+    # otherwise, every interface at least 18 k_max (smooth) or 25 k_max
+    # (cornered) nodes and still within the limits
+    kw = dict(omega_range=(5.0, 8.0), I_range=(10, 100), P=140, M_w=100)
+    res = workloads.config4(nodes_per_k=(18.0, 25.0), **kw)
+    for st, st0 in zip(res, workloads.config4(**kw)):
+        assert 10 <= st.I <= 100 and st.I == st0.I and st.thetas[0] == st0.thetas[0]
+        assert np.all(st.k <= 8.0 * 2.5)
+        for i, (f, f0) in enumerate(zip(st.interfaces, st0.interfaces)):
+            assert f.kind == f0.kind and f.N >= f0.N and 37 <= f.N <= 512
+            kmax = max(st.k[i], st.k[i + 1])
+            assert f.N >= (18.0 if f.kind == "fourier" else 25.0) * kmax - 1e-9
+            if f.kind == "polygon":
+                assert int(np.min(f.seg_nodes)) >= 37 and int(np.sum(f.seg_nodes)) == f.N

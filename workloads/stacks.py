@@ -18,7 +18,7 @@ from __future__ import annotations
 
 import math
 from dataclasses import dataclass, field
-from typing import List, Optional
+from typing import List, Optional, Tuple
 
 import numpy as np
 
@@ -200,13 +200,17 @@ def config3(seed: int = 3, I: int = 1000, n_angles: int = 100, N_smooth: int = 1
 
 def config4(seed: int = 4, n_stacks: int = 64, I_range=(10, 200), N_range=(60, 250), omega_range=(5.0, 20.0),
             n_range=(1.0, 2.5), P: int = 60, M_w: int = 60, M_ud: int = 60, K: int = 25,
-            min_seg: int = 40) -> List[Stack]:
+            min_seg: int = 40, nodes_per_k: Optional[Tuple[float, float]] = None) -> List[Stack]:
     """``n_stacks`` independent stacks, each with I ~ U{I_range} interfaces of
     N ~ U{N_range} nodes (drawn per interface), a seeded 70/30 mix of smooth
     random-Fourier and cornered profiles (as config3; a cornered interface
     takes at least ``min_seg`` nodes per segment), spacing 1.5, d = 2 pi,
     k_j = omega n_j with omega ~ U[omega_range] per stack and
     n_j ~ U[n_range], and one incident angle ~ U(-pi/2, 0) per stack.
+
+    ``nodes_per_k = (c_smooth, c_corner)`` raises an interface's drawn N to
+    at least c k_max, k_max the larger wavenumber of the two layers it
+    separates (the resolved variant; N stays uneven through the draw).
 
     Draw order per stack: I, omega, theta; then per interface N, the smooth /
     cornered choice, 5 cos and 5 sin N(0,1) coefficients and a shape index;
@@ -220,13 +224,20 @@ def config4(seed: int = 4, n_stacks: int = 64, I_range=(10, 200), N_range=(60, 2
         omega = float(rng.uniform(*omega_range))
         theta = -float(rng.uniform(0.0, np.pi / 2))
         theta = min(max(theta, -np.pi / 2 + 1e-3), -1e-3)
-        ifs = []
+        drawn = []
         for i in range(I):
-            y0 = -1.5 * i
             N = int(rng.integers(N_range[0], N_range[1] + 1))
             cornered = rng.uniform() < 0.3
             a, b = _scaled_fourier(rng, d, 5, 0.3)
             kind = kinds[int(rng.integers(0, 3))]
+            drawn.append((N, cornered, a, b, kind))
+        n = rng.uniform(n_range[0], n_range[1], I + 1)
+        ifs = []
+        for i, (N, cornered, a, b, kind) in enumerate(drawn):
+            y0 = -1.5 * i
+            if nodes_per_k is not None:
+                kmax = omega * max(n[i], n[i + 1])
+                N = max(N, int(math.ceil(nodes_per_k[1 if cornered else 0] * kmax)))
             if not cornered:
                 ifs.append(Interface("fourier", y0, n_nodes=N, cos_coef=a, sin_coef=b))
                 continue
@@ -237,7 +248,6 @@ def config4(seed: int = 4, n_stacks: int = 64, I_range=(10, 200), N_range=(60, 2
             nodes = min_seg + np.floor(extra * seglen / seglen.sum()).astype(np.int32)
             nodes[np.argmax(seglen)] += N - int(nodes.sum())
             ifs.append(Interface("polygon", y0, vx=vx, vy=vy, seg_nodes=nodes.astype(np.int32), q=6.0))
-        n = rng.uniform(n_range[0], n_range[1], I + 1)
         out.append(Stack("config4", d, omega * n, ifs, y_U=1.5, y_D=-1.5 * (I - 1) - 1.5, P=P, R=d,
                          M_w=M_w, M_ud=M_ud, K=K, thetas=np.array([theta])))
     return out
