@@ -329,7 +329,8 @@ def bench_batch(args):
     autotuned = args.autotune in ("auto", "on")
     if autotuned:
         ta = time.perf_counter()
-        b.autotune(th, reps=1)
+        if not (args.autotune == "auto" and b.tune_cached()[0]):
+            b.autotune(th, reps=1)
         print("autotune %s in %.2f s" % (b.get_tuning(), time.perf_counter() - ta), file=sys.stderr, flush=True)
     out = None
     for _ in range(warmup):
@@ -369,7 +370,8 @@ def bench_batch(args):
         "config": {"workload": args.workload, "description": desc_txt, "stacks": len(descs),
                    "interfaces": int(sum(d.I for d in descs)), "unknowns": int(n_tot)},
         "unknowns_per_s": n_tot / (ms * 1e-3), "flux_err_median": float(np.median(flux)),
-        "flux_err_max": float(flux.max()),
+        "flux_err_max": float(flux.max()), "stacks_flux_le_1e-9": int(np.sum(flux <= 1e-9)),
+        "interfaces_of_worst_stack": int(descs[int(np.argmax(flux))].I),
         "latency_ms": {"batched_p50": pct(lat, 50), "batched_p99": pct(lat, 99), "plain_p50": pct(plain, 50),
                        "plain_p99": pct(plain, 99), "plain_total": plain_total},
         "speedup_vs_plain": plain_total / ms,
@@ -461,8 +463,10 @@ def main():
                     help="sweeps: angles timed one by one (refill + one-angle solve each)")
     ap.add_argument("--autotune", choices=("auto", "on", "off"), default="auto",
                     help="time the solve under candidate launch choices before the warmup and keep the "
-                         "fastest (auto/on: sweeps are tuned on the angles of their first two Bloch "
-                         "phases, which run the launch shapes of one batch of the sweep)")
+                         "fastest (sweeps are tuned on the angles of their first two Bloch phases, which "
+                         "run the launch shapes of one batch of the sweep); auto takes the choices the "
+                         "library has recorded for this size class instead, if any (MLH_TUNING_CACHE), "
+                         "on always times them")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (calibrates the HBM "
                          "byte counters of a profiler against a known size) and exit")
@@ -504,14 +508,19 @@ def main():
           (args.workload, desc.I, info["n_tot"], info["device_bytes"] / 2 ** 20, len(thetas), n_sys),
           file=sys.stderr, flush=True)
     autotuned = args.autotune in ("auto", "on")
+    cached = False
     if autotuned:  # outside the timed region
         ta = time.perf_counter()
         st.refill()
         tune_th = tuning_angles(desc, thetas) if sweep else thetas
-        st.autotune(tune_th, reps=1 if sweep else 3)
-        print("autotune %s on %d angles in %.2f s" % (st.get_tuning(), len(tune_th), time.perf_counter() - ta),
+        # choices recorded for this size class (MLH_TUNING_CACHE) are taken as they are
+        cached = args.autotune == "auto" and st.tune_cached(tune_th)[0]
+        if not cached:
+            st.autotune(tune_th, reps=1 if sweep else 3)
+        print("autotune %s on %d angles in %.2f s%s" % (st.get_tuning(), len(tune_th), time.perf_counter() - ta,
+                                                        " (recorded choices)" if cached else ""),
               file=sys.stderr, flush=True)
-    tuning = dict(st.get_tuning(), autotuned=autotuned)
+    tuning = dict(st.get_tuning(), autotuned=autotuned, from_cache=bool(cached))
     out = None
     for _ in range(warmup):
         st.refill()

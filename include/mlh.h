@@ -234,8 +234,9 @@ mlh_status mlh_profile_solve(mlh_stack s, int32_t n_angles, const double* theta,
  *   ls_row_blocks    16-row blocks per wavefront of the least-squares
  *                    right-hand-side kernels for layers of at most 384
  *                    rows: 3 or 4 (larger layers always take 4).
- *   gje_rhs_cols     columns per workgroup of the Gauss-Jordan replay for
- *                    orders up to 608: 16 or 8 (larger orders take 8).
+ *   gje_rhs_cols     columns per workgroup of the Gauss-Jordan replay: 16
+ *                    (an LDS tile up to order 608, a register tile above)
+ *                    or 8 (LDS tiles: 8 columns, 10 for orders 609-1008).
  *   asm_in_panels    1: the block-system assembly runs inside the
  *                    least-squares panel launches, on the compute units
  *                    they leave idle; 0: in a launch of its own.
@@ -261,6 +262,24 @@ mlh_status mlh_stack_set_tuning(mlh_stack s, const mlh_tuning* t);
  * Errors: those of mlh_solve; the stack then keeps its previous choices. */
 mlh_status mlh_stack_autotune(mlh_stack s, int32_t n_angles, const double* theta, int32_t reps,
                               mlh_tuning* out);
+
+/* Launch-choice cache.  Every successful autotune (stack or batch) records
+ * the choices it kept under a key made of the device's architecture name
+ * (hipDeviceProp_t::gcnArchName) and the size class of the work: interface
+ * count (power-of-two bucket), block orders (all up to 576, up to 608, above,
+ * or mixed), least-squares rows (all up to 384, above, or mixed) and the
+ * number of systems solved at once (distinct Bloch phases among the angles,
+ * or the batch's stacks; buckets 1, 2-4, 5-16, 17-64, more).  The cache
+ * lives for the process; when the environment variable MLH_TUNING_CACHE
+ * names a file, each record is also appended to it and the file is read
+ * (later lines win, invalid ones are skipped) before the first lookup.
+ * mlh_stack_tune_cached: if a record exists for this stack and these angles
+ * (host array, each in (-pi, 0)), the stack takes it and *found = 1;
+ * otherwise *found = 0 and the stack keeps its choices.  out (may be NULL)
+ * receives the stack's choices either way.  MLH_E_INVALID_ARG for NULL
+ * s/theta/found, n_angles < 1 or an angle out of range. */
+mlh_status mlh_stack_tune_cached(mlh_stack s, int32_t n_angles, const double* theta, mlh_tuning* out,
+                                 int32_t* found);
 
 /* Field evaluation (Sec. 3.3, last paragraph): solve the stack for incident
  * angle theta, then evaluate the scattered field u at n_pts targets
@@ -356,6 +375,10 @@ mlh_status mlh_batch_solve(mlh_batch b, const double* theta, int32_t refill, int
 mlh_status mlh_batch_get_tuning(mlh_batch b, mlh_tuning* out);
 mlh_status mlh_batch_set_tuning(mlh_batch b, const mlh_tuning* t);
 mlh_status mlh_batch_autotune(mlh_batch b, const double* theta, int32_t reps, mlh_tuning* out);
+/* The cache lookup of mlh_stack_tune_cached for a batch (its size class:
+ * all its stacks' interfaces, block orders and layers, one system per
+ * stack). */
+mlh_status mlh_batch_tune_cached(mlh_batch b, mlh_tuning* out, int32_t* found);
 
 const char* mlh_last_error(void);
 

@@ -256,11 +256,19 @@ class Stack:
 
     def autotune(self, thetas, reps: int = 2) -> dict:
         """Time solves of ``thetas`` under candidate launch choices, keep and
-        return the fastest."""
+        return the fastest (also recorded in the launch-choice cache)."""
         th = np.ascontiguousarray(np.atleast_1d(thetas), dtype=np.float64)
         t = mlh_tuning()
         check(lib().mlh_stack_autotune(self._h, th.size, dptr(th), int(reps), C.byref(t)))
         return {name: getattr(t, name) for name, _ in t._fields_}
+
+    def tune_cached(self, thetas):
+        """Take the launch choices recorded for this stack's size class and
+        these angles, if any: returns (found, choices)."""
+        th = np.ascontiguousarray(np.atleast_1d(thetas), dtype=np.float64)
+        t, found = mlh_tuning(), C.c_int32()
+        check(lib().mlh_stack_tune_cached(self._h, th.size, dptr(th), C.byref(t), C.byref(found)))
+        return bool(found.value), {name: getattr(t, name) for name, _ in t._fields_}
 
     def solve_partial(self, theta: float, stop_phase: int):
         """Inspection: run one angle up to a phase (1 assembly, 2 least squares,
@@ -351,6 +359,12 @@ class Batch:
         t = mlh_tuning()
         check(lib().mlh_batch_autotune(self._h, dptr(th), int(reps), C.byref(t)))
         return {name: getattr(t, name) for name, _ in t._fields_}
+
+    def tune_cached(self):
+        """The batch's recorded launch choices, if any: (found, choices)."""
+        t, found = mlh_tuning(), C.c_int32()
+        check(lib().mlh_batch_tune_cached(self._h, C.byref(t), C.byref(found)))
+        return bool(found.value), {name: getattr(t, name) for name, _ in t._fields_}
 
 
 class EfficiencyObjective:

@@ -89,6 +89,7 @@ SIGNATURES = {
     "mlh_batch_get_tuning": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "mlh_batch_set_tuning": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "mlh_batch_autotune": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.c_void_p]),
+    "mlh_batch_tune_cached": (C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]),
     "mlh_debug_get_piece": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
                                         C.POINTER(C.c_double), C.POINTER(C.c_int32),
                                         C.POINTER(C.c_int32)]),
@@ -105,6 +106,8 @@ SIGNATURES = {
     "mlh_stack_get_tuning": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "mlh_stack_set_tuning": (C.c_int32, [C.c_void_p, C.c_void_p]),
     "mlh_stack_autotune": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.c_int32, C.c_void_p]),
+    "mlh_stack_tune_cached": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.c_void_p,
+                                          C.POINTER(C.c_int32)]),
     "mlh_last_error": (C.c_char_p, []),
 }
 

@@ -12,6 +12,7 @@
 #include <functional>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -3256,6 +3257,106 @@ extern "C" mlh_status mlh_stack_set_tuning(mlh_stack s, const mlh_tuning* t) {
 // caller waits for), fastest of `reps` after one untimed solve that also
 // captures the candidate's graph.  `tune` is the live choice the solve
 // reads; it ends at the fastest choice, or where it started on an error.
+// ---------------------------------------------------------------------------
+// launch-choice cache: the choices an autotune picked, keyed by the device's
+// architecture name and the size class of the work, so that work of the same
+// class takes them without being timed again.  The class: interface count
+// (power-of-two bucket), block orders (all up to 576 / up to 608 / above,
+// or mixed), least-squares rows (all up to 384 / above / mixed), systems
+// solved at once (bucket 1, 2-4, 5-16, 17-64, more).  With MLH_TUNING_CACHE
+// naming a file, entries are appended to it and read back by the next process.
+// ---------------------------------------------------------------------------
+struct SizeClass {
+  int interfaces = 0, maxn = 0, minn = 1 << 30, maxrows = 0, minrows = 1 << 30, systems = 0;
+  void add_stack(const mlh_stack_s* s) {
+    interfaces += s->I;
+    for (int i = 0; i < s->I; ++i) {
+      maxn = std::max(maxn, s->n[i]);
+      minn = std::min(minn, s->n[i]);
+    }
+    for (int j = 0; j <= s->I; ++j) {
+      int m, c, nc;
+      layer_dims(s, j, m, c, nc);
+      maxrows = std::max(maxrows, m + c);
+      minrows = std::min(minrows, m + c);
+    }
+  }
+};
+
+static std::string tuning_key(int device, const SizeClass& c) {
+  hipDeviceProp_t prop;
+  std::string arch = "unknown";
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) arch = prop.gcnArchName;
+  for (char& ch : arch)
+    if (ch == ' ' || ch == '\t') ch = '_';
+  int ib = 0;
+  while ((1 << (ib + 1)) <= c.interfaces) ++ib;
+  auto ncls = [](int n) { return gje_step_fits(n) ? 0 : (n <= kRhsMaxN16 ? 1 : 2); };
+  const int nlo = ncls(c.minn), nhi = ncls(c.maxn);
+  const int rlo = c.minrows > 384, rhi = c.maxrows > 384;
+  const int sb = c.systems <= 1 ? 0 : c.systems <= 4 ? 1 : c.systems <= 16 ? 2 : c.systems <= 64 ? 3 : 4;
+  char buf[256];
+  std::snprintf(buf, sizeof buf, "%s/I%d/n%d%d/r%d%d/s%d", arch.c_str(), ib, nlo, nhi, rlo, rhi, sb);
+  return buf;
+}
+
+static std::mutex g_tune_mu;
+static std::map<std::string, mlh_tuning> g_tune_cache;
+static bool g_tune_loaded = false;
+
+static void tune_cache_load_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = std::getenv("MLH_TUNING_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char key[256];
+  mlh_tuning t;
+  while (std::fscanf(f, "%255s %d %d %d %d", key, &t.rhs_in_step_pct, &t.ls_row_blocks, &t.gje_rhs_cols,
+                     &t.asm_in_panels) == 5)
+    if (tuning_valid(t)) g_tune_cache[key] = t;  // later lines win
+  std::fclose(f);
+}
+
+static bool tune_cache_find(const std::string& key, mlh_tuning& out) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_cache_load_locked();
+  auto it = g_tune_cache.find(key);
+  if (it == g_tune_cache.end()) return false;
+  out = it->second;
+  return true;
+}
+
+static void tune_cache_store(const std::string& key, const mlh_tuning& t) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_cache_load_locked();
+  g_tune_cache[key] = t;
+  const char* path = std::getenv("MLH_TUNING_CACHE");
+  if (!path || !*path) return;
+  if (FILE* f = std::fopen(path, "a")) {
+    std::fprintf(f, "%s %d %d %d %d\n", key.c_str(), t.rhs_in_step_pct, t.ls_row_blocks, t.gje_rhs_cols,
+                 t.asm_in_panels);
+    std::fclose(f);
+  }
+}
+
+static std::string stack_tuning_key(mlh_stack s, int32_t n_angles, const double* theta) {
+  SizeClass c;
+  c.add_stack(s);
+  std::vector<SysSpec> sys;
+  group_by_alpha(s, n_angles, theta, 0, sys);
+  c.systems = (int)sys.size();
+  return tuning_key(s->ctx->device, c);
+}
+
+static std::string batch_tuning_key(mlh_batch b) {
+  SizeClass c;
+  for (const mlh_stack_s* s : b->st) c.add_stack(s);
+  c.systems = (int)b->st.size();
+  return tuning_key(b->ctx->device, c);
+}
+
 static mlh_status autotune_loop(mlh_tuning& tune, const std::function<mlh_status()>& solve_once, int reps,
                                 mlh_tuning* out) {
   const mlh_tuning start = tune;
@@ -3306,12 +3407,28 @@ static mlh_status autotune_loop(mlh_tuning& tune, const std::function<mlh_status
 extern "C" mlh_status mlh_stack_autotune(mlh_stack s, int32_t n_angles, const double* theta, int32_t reps,
                                          mlh_tuning* out) {
   if (!s || !theta || n_angles < 1 || reps < 1) return fail(MLH_E_INVALID_ARG, "mlh_stack_autotune: bad arguments");
+  for (int a = 0; a < n_angles; ++a)
+    if (!theta_ok(theta[a])) return fail(MLH_E_INVALID_ARG, "incident angle must lie in (-pi, 0)");
   const size_t nc = (size_t)2 * s->nK * n_angles;
   std::vector<double> aU(nc), aD(nc);
-  return autotune_loop(
+  MLH_TRY(autotune_loop(
       s->tune,
       [&]() { return solve_impl(s, n_angles, theta, aU.data(), aD.data(), nullptr, nullptr, nullptr, false, SolveOpts()); },
-      reps, out);
+      reps, out));
+  tune_cache_store(stack_tuning_key(s, n_angles, theta), s->tune);
+  return MLH_OK;
+}
+
+extern "C" mlh_status mlh_stack_tune_cached(mlh_stack s, int32_t n_angles, const double* theta, mlh_tuning* out,
+                                            int32_t* found) {
+  if (!s || !theta || n_angles < 1 || !found) return fail(MLH_E_INVALID_ARG, "mlh_stack_tune_cached: bad arguments");
+  for (int a = 0; a < n_angles; ++a)
+    if (!theta_ok(theta[a])) return fail(MLH_E_INVALID_ARG, "incident angle must lie in (-pi, 0)");
+  mlh_tuning t;
+  *found = tune_cache_find(stack_tuning_key(s, n_angles, theta), t) ? 1 : 0;
+  if (*found) s->tune = t;
+  if (out) *out = s->tune;
+  return MLH_OK;
 }
 
 extern "C" mlh_status mlh_batch_set_tuning(mlh_batch b, const mlh_tuning* t) {
@@ -3324,9 +3441,20 @@ extern "C" mlh_status mlh_batch_set_tuning(mlh_batch b, const mlh_tuning* t) {
 extern "C" mlh_status mlh_batch_autotune(mlh_batch b, const double* theta, int32_t reps, mlh_tuning* out) {
   if (!b || !theta || reps < 1) return fail(MLH_E_INVALID_ARG, "mlh_batch_autotune: bad arguments");
   std::vector<double> aU((size_t)2 * b->n_orders), aD((size_t)2 * b->n_orders);
-  return autotune_loop(
+  MLH_TRY(autotune_loop(
       b->tune, [&]() { return mlh_batch_solve(b, theta, 0, 0, aU.data(), aD.data(), nullptr, nullptr, nullptr); },
-      reps, out);
+      reps, out));
+  tune_cache_store(batch_tuning_key(b), b->tune);
+  return MLH_OK;
+}
+
+extern "C" mlh_status mlh_batch_tune_cached(mlh_batch b, mlh_tuning* out, int32_t* found) {
+  if (!b || !found) return fail(MLH_E_INVALID_ARG, "mlh_batch_tune_cached: bad arguments");
+  mlh_tuning t;
+  *found = tune_cache_find(batch_tuning_key(b), t) ? 1 : 0;
+  if (*found) b->tune = t;
+  if (out) *out = b->tune;
+  return MLH_OK;
 }
 
 // ---------------------------------------------------------------------------

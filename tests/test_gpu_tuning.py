@@ -101,3 +101,69 @@ def test_batched_shared_alpha_angles_under_non_default_choices(ctx):
         assert np.array_equal(out.orders[a], o.orders)
         assert rel_amp_err(out.aU[a], out.aD[a], o.aU, o.aD) < TOL
     st.close()
+
+
+def test_autotuned_choices_are_reused_by_size_class(ctx, case):
+    # an autotune records its choices under (device architecture, size class);
+    # a second stack of the same class takes them without timing, a stack of
+    # another class (other block orders) finds nothing and keeps its own
+    import paper_1410_5003_amd as mlh
+    desc, th, o = case
+    st = mlh.Stack(ctx, desc)
+    t = st.autotune([th], reps=1)
+    st.close()
+    twin = workloads.small_stack(seed=7, I=4, N=80, P=45, M_w=35, M_ud=40, K=9, theta=th)
+    s2 = mlh.Stack(ctx, twin)
+    s2.set_tuning(rhs_in_step_pct=0, ls_row_blocks=4, gje_rhs_cols=8, asm_in_panels=0)
+    found, got = s2.tune_cached([th])
+    assert found and got == t and s2.get_tuning() == t
+    g = s2.solve([th])
+    ot = oracle.solve_stack(twin, theta=th)
+    assert rel_amp_err(g.aU[0], g.aD[0], ot.aU, ot.aD) < TOL
+    s2.close()
+    other = workloads.config1(N=160, P=140, M_w=100)  # block order 320, 2 interfaces
+    s3 = mlh.Stack(ctx, other)
+    before = s3.get_tuning()
+    found, got = s3.tune_cached([float(other.thetas[0])])
+    assert not found and got == before == s3.get_tuning()
+    s3.close()
+
+
+_CACHE_SCRIPT = r"""
+import json, sys
+sys.path.insert(0, %(root)r)
+import workloads
+import paper_1410_5003_amd as mlh
+ctx = mlh.Context(0)
+d = workloads.small_stack(seed=6, I=4, N=77, P=45, M_w=35, M_ud=40, K=9)
+st = mlh.Stack(ctx, d)
+th = [float(d.thetas[0])]
+if sys.argv[1] == "tune":
+    print(json.dumps(st.autotune(th, reps=1)))
+else:
+    print(json.dumps(st.tune_cached(th)))
+st.close()
+"""
+
+
+def test_tuning_cache_file_carries_choices_to_the_next_process(tmp_path):
+    # with MLH_TUNING_CACHE set, one process's autotune is found by the next
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    script = tmp_path / "cache_probe.py"
+    script.write_text(_CACHE_SCRIPT % {"root": root})
+    env = dict(os.environ, MLH_TUNING_CACHE=str(tmp_path / "tuning.txt"))
+    run = lambda mode: subprocess.run([sys.executable, str(script), mode], env=env, capture_output=True, text=True,
+                                      timeout=240)
+    a = run("tune")
+    assert a.returncode == 0, a.stderr[-2000:]
+    tuned = json.loads(a.stdout.strip().splitlines()[-1])
+    lines = (tmp_path / "tuning.txt").read_text().split("\n")
+    assert len([l for l in lines if l.strip()]) == 1
+    b = run("lookup")
+    assert b.returncode == 0, b.stderr[-2000:]
+    found, got = json.loads(b.stdout.strip().splitlines()[-1])
+    assert found and got == tuned
