@@ -15,7 +15,7 @@
 //                      themselves (original values for rows >= k, current
 //                      values above k), read from W;
 //   gje_update_kernel  one workgroup of 12 wavefronts per 16 trailing
-//                      columns (32 columns and 16 wavefronts above order
+//                      columns (32 columns and 8 wavefronts above order
 //                      576): applies the row swaps, Z = M1 Y(pivot rows),
 //                      Y(other rows) -= P Z on the FP64 matrix cores,
 //                      Y(pivot rows) = Z; on levels with few matrices the
@@ -595,7 +595,7 @@ constexpr int kUpdWaves = 12;
 constexpr int kUpdRbw = 3;
 constexpr int kUpdMaxN = kUpdWaves * kUpdRbw * 16;  // 576
 constexpr int kUpdCols = 16;
-constexpr int kUpdWideThreads = 1024;
+constexpr int kUpdWideThreads = 512;
 constexpr int kUpdWideWaves = kUpdWideThreads / 64;
 constexpr int kUpdWideCols = 32;
 
@@ -802,15 +802,15 @@ __global__ __launch_bounds__(kUpdWideThreads) void gje_update_wide_kernel(const 
     zi[r][c] = si;
   }
   __syncthreads();
-  // 3. Y(other rows) -= P Z on the matrix cores: 16-row blocks, two 16-column
-  //    blocks; each row block's old values and multipliers are loaded in one
-  //    round, before its products (8 % faster than loading the old values
-  //    after the products)
+  // 3. Y(other rows) -= P Z on the matrix cores: 16-row blocks times the
+  //    16-column blocks of the tile; each row block's old values and
+  //    multipliers are loaded in one round, before its products (8 % faster
+  //    than loading the old values after the products)
   const int nrb = (n + 15) / 16;
 #pragma unroll 1
   for (int rb = wave; rb < nrb; rb += kUpdWideWaves) {
     const int r0 = rb * 16;  // the pivot rows have zero multipliers and are masked below
-    double2 a[kGjeNb / 4], v[2][4];
+    double2 a[kGjeNb / 4], v[kUpdWideCols / 16][4];
 #pragma unroll
     for (int kk = 0; kk < kGjeNb; kk += 4) {
       // multipliers: the panel columns of W (rows below k: current values;
@@ -820,14 +820,14 @@ __global__ __launch_bounds__(kUpdWideThreads) void gje_update_wide_kernel(const 
       a[kk / 4] = (row < n && kq < nb) ? gld(W + (size_t)(k + kq) * n + row) : make_double2(0.0, 0.0);
     }
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb)
+    for (int cb = 0; cb < kUpdWideCols / 16; ++cb)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int c = min(cb * 16 + (lane & 15), nc - 1), row = min(r0 + (lane >> 4) + 4 * q, n - 1);
         v[cb][q] = gld(W + (size_t)(c0 + c) * n + row);  // clamped: entries past nc or n are not stored
       }
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb) {
+    for (int cb = 0; cb < kUpdWideCols / 16; ++cb) {
       if (cb * 16 >= nc) break;
       dvec4 accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
 #pragma unroll
