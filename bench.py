@@ -420,7 +420,7 @@ def bench_adjoint(args):
     st.close()
     # central differences of the forward solve (stack built and solved per
     # evaluation, as a caller without the adjoint would)
-    nfd = 4
+    nfd = 8
     p0 = pb.params()
     torch.cuda.synchronize()
     tf = time.perf_counter()

@@ -14,6 +14,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/mlh.h"
@@ -298,6 +299,20 @@ void build_fourier_curve(const mlh_interface& in, double d, HostCurve& c) {
       c.at[i] = m + sg * chi;
     }
   }
+}
+
+// f(0..n-1) on up to 16 host threads (the calling thread included); f must
+// touch only state of its own index
+template <class F>
+static void parallel_for(int n, F f) {
+  const int nt = std::max(1, std::min({16, (int)std::thread::hardware_concurrency(), n}));
+  std::vector<std::thread> pool;
+  for (int w = 1; w < nt; ++w)
+    pool.emplace_back([&f, w, nt, n]() {
+      for (int i = w; i < n; i += nt) f(i);
+    });
+  for (int i = 0; i < n; i += nt) f(i);
+  for (std::thread& th : pool) th.join();
 }
 
 // Device state solves run in: the workspace, reused across calls that fit
@@ -719,11 +734,14 @@ extern "C" mlh_status mlh_stack_create(mlh_ctx ctx, const mlh_stack_desc* D, mlh
   s->curves.resize(I);
   s->N.resize(I);
   s->n.resize(I);
-  for (int i = 0; i < I; ++i) {
+  // the curves, with their Alpert auxiliary invariants, on host threads
+  parallel_for(I, [&](int i) {
     if (D->iface[i].kind == MLH_IFACE_POLYGON)
       build_polygon_curve(D->iface[i], s->curves[i]);
     else
       build_fourier_curve(D->iface[i], s->d, s->curves[i]);
+  });
+  for (int i = 0; i < I; ++i) {
     s->N[i] = s->curves[i].N;
     s->n[i] = 2 * s->N[i];
     // strongly graded nodes of adjacent segments (also across x = +-d/2)
@@ -2789,14 +2807,12 @@ static mlh_status adjoint_shape(mlh_stack s, int32_t n_angles, const double* the
     HIP_TRY(hipMemcpyAsync(z1.data() + (size_t)2 * s->n[0] * a, d_z + (size_t)nden * a, cbytes(s->n[0]),
                            hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  const int chunk = 16;  // parameters per pass (two perturbed geometries each)
+  const int chunk = 32;  // parameters per pass (two perturbed geometries each)
   for (size_t p0 = 0; p0 < par.size(); p0 += chunk) {
     const int np_ = (int)std::min(par.size() - p0, (size_t)chunk);
     // ---- perturbed geometry and the pieces of the blocks that touch it
     std::vector<HostCurve> cur(2 * np_);
-    Arena ar;
-    std::vector<size_t> o_geo(2 * np_), o_aux(2 * np_);
-    for (int t = 0; t < 2 * np_; ++t) {
+    auto build = [&](int t) {
       const Par& pp = par[p0 + t / 2];
       const HostCurve& c0 = s->curves[pp.i];
       std::vector<double> ca(c0.prof.ca), sa(c0.prof.sa);
@@ -2808,9 +2824,16 @@ static mlh_status adjoint_shape(mlh_stack s, int32_t n_angles, const double* the
       in.cos_coef = ca.data();
       in.sin_coef = sa.data();
       in.n_nodes = c0.N;
-      build_fourier_curve(in, s->d, cur[t]);
-      o_geo[t] = ar.reserve(sizeof(double) * 5 * c0.N);
-      o_aux[t] = ar.reserve(sizeof(double) * 6 * (size_t)c0.N * kAlpertAux);
+      build_fourier_curve(in, s->d, cur[t]);  // writes cur[t] only
+    };
+    // each curve with its Alpert auxiliary invariants costs milliseconds
+    parallel_for(2 * np_, build);
+    Arena ar;
+    std::vector<size_t> o_geo(2 * np_), o_aux(2 * np_);
+    for (int t = 0; t < 2 * np_; ++t) {
+      const int N = s->curves[par[p0 + t / 2].i].N;
+      o_geo[t] = ar.reserve(sizeof(double) * 5 * N);
+      o_aux[t] = ar.reserve(sizeof(double) * 6 * (size_t)N * kAlpertAux);
     }
     // jobs: for every perturbation, the self and Alpert jobs of its interface
     // and the fill jobs whose targets or sources lie on it, with the
