@@ -410,29 +410,36 @@ def bench_adjoint(args):
         st.adjoint(th, shape=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    step_ms = []
     for _ in range(steps):
+        ts = time.perf_counter()
         st.refill()
         J, gk, gs = st.adjoint(th, shape=True)
+        step_ms.append((time.perf_counter() - ts) * 1e3)  # mlh_adjoint returns its results on the host
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
     out = st.solve(th)
     flux = np.abs(out.flux_err)
     st.close()
     # central differences of the forward solve (stack built and solved per
-    # evaluation, as a caller without the adjoint would)
+    # evaluation, as a caller without the adjoint would; the release of each
+    # stack's device memory is left out of the time)
     nfd = 8
     p0 = pb.params()
-    torch.cuda.synchronize()
-    tf = time.perf_counter()
+    fd_s = 0.0
     for q in range(nfd):
         for sgn in (1.0, -1.0):
             e = np.zeros_like(p0)
             e[q] = sgn * 1e-6
-            s2 = mlh.Stack(ctx, pb.stack(p0 + e))
+            desc_q = pb.stack(p0 + e)
+            torch.cuda.synchronize()
+            tf = time.perf_counter()
+            s2 = mlh.Stack(ctx, desc_q)
             s2.solve(th)
+            torch.cuda.synchronize()
+            fd_s += time.perf_counter() - tf
             s2.close()
-    torch.cuda.synchronize()
-    fd_per_param = (time.perf_counter() - tf) / nfd
+    fd_per_param = fd_s / nfd
     fd_total = fd_per_param * n_par
     line = {
         "metric": METRIC, "value": 1e3 / ms, "unit": "grads/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
@@ -440,7 +447,7 @@ def bench_adjoint(args):
         "dtype": "f64 (complex128)", "data": "synthetic (seeded stacks)",
         "config": {"workload": args.workload, "description": desc_txt, "interfaces": desc.I,
                    "unknowns": info["n_tot"], "angles": int(th.size), "parameters": int(n_par)},
-        "J": J, "flux_err_max": float(flux.max()),
+        "step_ms": [round(v, 1) for v in step_ms], "J": J, "flux_err_max": float(flux.max()),
         "fd_by_gpu": {"s_per_gradient": fd_total, "s_per_parameter": fd_per_param, "sampled_parameters": nfd},
         "speedup_vs_fd": fd_total / (ms * 1e-3),
     }

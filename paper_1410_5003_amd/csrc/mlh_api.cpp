@@ -2835,6 +2835,7 @@ static mlh_status adjoint_shape(mlh_stack s, int32_t n_angles, const double* the
       o_geo[t] = ar.reserve(sizeof(double) * 5 * N);
       o_aux[t] = ar.reserve(sizeof(double) * 6 * (size_t)N * kAlpertAux);
     }
+    const size_t o_geo_end = ar.off;
     // jobs: for every perturbation, the self and Alpert jobs of its interface
     // and the fill jobs whose targets or sources lie on it, with the
     // perturbed geometry and outputs in scratch pieces of the same shapes
@@ -2882,7 +2883,17 @@ static mlh_status adjoint_shape(mlh_stack s, int32_t n_angles, const double* the
     } guard{buf};
     auto dp = [&](size_t o) { return reinterpret_cast<double*>(buf + o); };
     auto cpp = [&](size_t o) { return reinterpret_cast<cplx*>(buf + o); };
-    std::vector<double> hb;
+    // the geometry of every perturbed curve, laid out as in the arena (it
+    // opens the arena), goes over in one copy
+    std::vector<double> hb(o_geo_end / sizeof(double));
+    for (int t = 0; t < 2 * np_; ++t) {
+      const HostCurve& c = cur[t];
+      double* g = hb.data() + o_geo[t] / sizeof(double);
+      for (auto* v : {&c.x, &c.y, &c.nx, &c.ny, &c.w}) g = std::copy(v->begin(), v->end(), g);
+      double* x = hb.data() + o_aux[t] / sizeof(double);
+      for (auto* v : {&c.ar2, &c.and_, &c.anpd, &c.ann, &c.acw, &c.at}) x = std::copy(v->begin(), v->end(), x);
+    }
+    HIP_TRY(hipMemcpyAsync(buf, hb.data(), o_geo_end, hipMemcpyHostToDevice, st));
     std::vector<FillJob> fj;
     std::vector<SelfJob> sj;
     std::vector<AlpertJob> aj;
@@ -2890,13 +2901,6 @@ static mlh_status adjoint_shape(mlh_stack s, int32_t n_angles, const double* the
     for (int t = 0; t < 2 * np_; ++t) {
       const int i = par[p0 + t / 2].i;
       const int N = s->N[i];
-      const HostCurve& c = cur[t];
-      hb.clear();
-      for (auto* v : {&c.x, &c.y, &c.nx, &c.ny, &c.w}) hb.insert(hb.end(), v->begin(), v->end());
-      HIP_TRY(hipMemcpyAsync(dp(o_geo[t]), hb.data(), hb.size() * sizeof(double), hipMemcpyHostToDevice, st));
-      hb.clear();
-      for (auto* v : {&c.ar2, &c.and_, &c.anpd, &c.ann, &c.acw, &c.at}) hb.insert(hb.end(), v->begin(), v->end());
-      HIP_TRY(hipMemcpyAsync(dp(o_aux[t]), hb.data(), hb.size() * sizeof(double), hipMemcpyHostToDevice, st));
       const double* gx = dp(o_geo[t]);
       const double *gy = gx + N, *gnx = gx + 2 * N, *gny = gx + 3 * N, *gw = gx + 4 * N;
       const size_t na = (size_t)N * kAlpertAux;
