@@ -329,6 +329,10 @@ mlh_status mlh_field(mlh_stack s, double theta, int64_t n_pts, const double* x, 
  *                largest coefficient); the wall nodes, whose end points follow
  *                the interface heights at x = -d/2, are held fixed.
  * theta: n_angles host angles in (-pi, 0), all in one batch of systems.
+ * The device scratch the call needs (about the size of the stack's
+ * alpha-free pieces, plus a few GB for the shape passes) stays with the
+ * stack for later calls until mlh_stack_destroy; a call that needs more
+ * replaces it.
  * Outputs (host): J_out (may be NULL), grad_k, grad_shape.  Errors:
  * MLH_E_INVALID_ARG (also when the zeroth order leaves the window),
  * MLH_E_UNSUPPORTED (too many angles for one batch), MLH_E_NOMEM,

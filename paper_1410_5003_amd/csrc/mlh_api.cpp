@@ -360,6 +360,9 @@ struct Arena {
 // ---------------------------------------------------------------------------
 struct mlh_stack_s {
   mlh_ctx ctx = nullptr;
+  // device scratch of mlh_adjoint, kept between calls and grown on demand:
+  // its buffers, their job tables, a shape-gradient pass, its contractions
+  std::pair<char*, size_t> adj_buf[4] = {};
   mlh_tuning tune{300, 3, 16, 1};  // launch choices (mlh_stack_set_tuning / mlh_stack_autotune)
   double flux_tol = 0.0;           // > 0: a solve whose flux error exceeds it reports MLH_E_ACCURACY
   int I = 0, P = 0, Mw = 0, Mud = 0, K = 0, nK = 0;
@@ -995,6 +998,8 @@ extern "C" mlh_status mlh_stack_destroy(mlh_stack s) {
   // teardown: errors here leave nothing to recover
   (void)hipSetDevice(s->ctx->device);
   if (s->dmem) (void)hipFree(s->dmem);
+  for (auto& b : s->adj_buf)
+    if (b.first) (void)hipFree(b.first);
   s->run.release();
   delete s;
   return MLH_OK;
@@ -2413,6 +2418,24 @@ extern "C" mlh_status mlh_field(mlh_stack s, double theta, int64_t n_pts, const 
 // the shape part of the adjoint (below): derivative pieces of the blocks that
 // touch one smooth interface, in one shape coefficient, by central
 // differences of the fill kernels at perturbed node geometry
+// slot of the adjoint's device scratch, at least `bytes` long (a larger
+// one replaces the old, which hipFree waits for)
+static mlh_status adj_scratch(mlh_stack s, int slot, size_t bytes, char** out) {
+  auto& b = s->adj_buf[slot];
+  if (bytes > b.second) {
+    if (b.first) HIP_TRY(hipFree(b.first));
+    b = {nullptr, 0};
+    const hipError_t e = hipMalloc((void**)&b.first, bytes);
+    if (e != hipSuccess) {
+      b = {nullptr, 0};
+      return fail(e == hipErrorOutOfMemory ? MLH_E_NOMEM : MLH_E_DEVICE, "mlh_adjoint: allocation");
+    }
+    b.second = bytes;
+  }
+  *out = b.first;
+  return MLH_OK;
+}
+
 static mlh_status adjoint_shape(mlh_stack s, int32_t n_angles, const double* theta, const std::vector<SysSpec>& sys,
                                 const std::vector<int64_t>& doff, const cplx* d_eta, const cplx* d_z, const cplx* d_c,
                                 const cplx* d_l, const std::vector<size_t>& loff, size_t msum,
@@ -2472,12 +2495,7 @@ extern "C" mlh_status mlh_adjoint(mlh_stack s, int32_t n_angles, const double* t
                o_sj = ar.reserve(sizeof(SelfJob) * 2 * s->h_self.size()),
                o_aj = ar.reserve(sizeof(AlpertJob) * 2 * s->h_alp.size());
   char* buf = nullptr;
-  hipError_t e = hipMalloc((void**)&buf, ar.off);
-  if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? MLH_E_NOMEM : MLH_E_DEVICE, "mlh_adjoint: allocation");
-  struct Free {
-    char* p;
-    ~Free() { (void)hipFree(p); }
-  } guard{buf};
+  MLH_TRY(adj_scratch(s, 0, ar.off, &buf));
   cplx* d_eta = reinterpret_cast<cplx*>(buf + o_eta);
   cplx* d_z = reinterpret_cast<cplx*>(buf + o_z);
   cplx* d_c = reinterpret_cast<cplx*>(buf + o_c);
@@ -2699,9 +2717,7 @@ extern "C" mlh_status mlh_adjoint(mlh_stack s, int32_t n_angles, const double* t
   const size_t o_pj = ja.reserve(sizeof(ProxyStrengthJob) * pj.size()), o_bj = ja.reserve(sizeof(BtzJob) * bj.size()),
                o_lj = ja.reserve(sizeof(LsAdjJob) * lj.size()), o_blj = ja.reserve(sizeof(BilinJob) * blj.size());
   char* jbuf = nullptr;
-  e = hipMalloc((void**)&jbuf, ja.off);
-  if (e != hipSuccess) return fail(e == hipErrorOutOfMemory ? MLH_E_NOMEM : MLH_E_DEVICE, "mlh_adjoint: allocation");
-  Free guard2{jbuf};
+  MLH_TRY(adj_scratch(s, 1, ja.off, &jbuf));
   HIP_TRY(hipMemcpyAsync(jbuf + o_pj, pj.data(), sizeof(ProxyStrengthJob) * pj.size(), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(jbuf + o_bj, bj.data(), sizeof(BtzJob) * bj.size(), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(jbuf + o_lj, lj.data(), sizeof(LsAdjJob) * lj.size(), hipMemcpyHostToDevice, st));
@@ -2874,13 +2890,7 @@ static mlh_status adjoint_shape(mlh_stack s, int32_t n_angles, const double* the
     const size_t o_fj = ar.reserve(sizeof(FillJob) * fjobs.size()),
                  o_sj = ar.reserve(sizeof(SelfJob) * 2 * np_), o_aj = ar.reserve(sizeof(AlpertJob) * 2 * np_);
     char* buf = nullptr;
-    hipError_t e = hipMalloc((void**)&buf, ar.off);
-    if (e != hipSuccess)
-      return fail(e == hipErrorOutOfMemory ? MLH_E_NOMEM : MLH_E_DEVICE, "mlh_adjoint: shape allocation");
-    struct Free {
-      char* p;
-      ~Free() { (void)hipFree(p); }
-    } guard{buf};
+    MLH_TRY(adj_scratch(s, 2, ar.off, &buf));  // the previous pass ended with a stream wait
     auto dp = [&](size_t o) { return reinterpret_cast<double*>(buf + o); };
     auto cpp = [&](size_t o) { return reinterpret_cast<cplx*>(buf + o); };
     // the geometry of every perturbed curve, laid out as in the arena (it
@@ -3061,10 +3071,7 @@ static mlh_status adjoint_shape(mlh_stack s, int32_t n_angles, const double* the
     Arena jb;
     const size_t o_b = jb.reserve(sizeof(BilinJob) * blj.size()), o_acc = jb.reserve(sizeof(double) * 2 * nacc);
     char* jbuf = nullptr;
-    e = hipMalloc((void**)&jbuf, jb.off);
-    if (e != hipSuccess)
-      return fail(e == hipErrorOutOfMemory ? MLH_E_NOMEM : MLH_E_DEVICE, "mlh_adjoint: shape allocation");
-    Free guard2{jbuf};
+    MLH_TRY(adj_scratch(s, 3, jb.off, &jbuf));
     double* d_acc = reinterpret_cast<double*>(jbuf + o_acc);
     HIP_TRY(hipMemcpyAsync(jbuf + o_b, blj.data(), sizeof(BilinJob) * blj.size(), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemsetAsync(d_acc, 0, sizeof(double) * 2 * nacc, st));
