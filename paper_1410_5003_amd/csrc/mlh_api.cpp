@@ -2824,12 +2824,14 @@ static mlh_status adjoint_shape(mlh_stack s, int32_t n_angles, const double* the
                            hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   const int chunk = 32;  // parameters per pass (two perturbed geometries each)
-  for (size_t p0 = 0; p0 < par.size(); p0 += chunk) {
-    const int np_ = (int)std::min(par.size() - p0, (size_t)chunk);
-    // ---- perturbed geometry and the pieces of the blocks that touch it
-    std::vector<HostCurve> cur(2 * np_);
-    auto build = [&](int t) {
-      const Par& pp = par[p0 + t / 2];
+  // the perturbed curves of the pass starting at parameter q0, on host
+  // threads (each curve with its Alpert auxiliary invariants costs
+  // milliseconds); the next pass's curves are built while this pass runs
+  auto build_pass = [&](size_t q0, std::vector<HostCurve>& out) {
+    const int nq = (int)std::min(par.size() - q0, (size_t)chunk);
+    out.assign(2 * nq, HostCurve());
+    parallel_for(2 * nq, [&](int t) {
+      const Par& pp = par[q0 + t / 2];
       const HostCurve& c0 = s->curves[pp.i];
       std::vector<double> ca(c0.prof.ca), sa(c0.prof.sa);
       (pp.sinpart ? sa : ca)[pp.m] += (t % 2 == 0 ? 1.0 : -1.0) * hstep;
@@ -2840,10 +2842,21 @@ static mlh_status adjoint_shape(mlh_stack s, int32_t n_angles, const double* the
       in.cos_coef = ca.data();
       in.sin_coef = sa.data();
       in.n_nodes = c0.N;
-      build_fourier_curve(in, s->d, cur[t]);  // writes cur[t] only
-    };
-    // each curve with its Alpert auxiliary invariants costs milliseconds
-    parallel_for(2 * np_, build);
+      build_fourier_curve(in, s->d, out[t]);  // writes out[t] only
+    });
+  };
+  std::vector<HostCurve> cur, next;
+  build_pass(0, cur);
+  for (size_t p0 = 0; p0 < par.size(); p0 += chunk, cur.swap(next)) {
+    const int np_ = (int)std::min(par.size() - p0, (size_t)chunk);
+    struct Joiner {  // joined on every way out of the pass, early returns included
+      std::thread th;
+      ~Joiner() {
+        if (th.joinable()) th.join();
+      }
+    } prefetch;
+    if (p0 + chunk < par.size()) prefetch.th = std::thread([&, p0]() { build_pass(p0 + chunk, next); });
+    // ---- perturbed geometry and the pieces of the blocks that touch it
     Arena ar;
     std::vector<size_t> o_geo(2 * np_), o_aux(2 * np_);
     for (int t = 0; t < 2 * np_; ++t) {
