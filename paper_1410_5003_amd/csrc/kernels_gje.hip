@@ -1130,30 +1130,28 @@ __global__ __launch_bounds__(kRhsWaves * 64) void gje_rhs_kernel(const GjeDesc* 
 
 // Register-resident replay for orders above kRhsMaxN16 (up to kGjeMaxN):
 // a 16-column tile of such an order does not fit in LDS, but it does fit in
-// the matrix-core accumulators of eight wavefronts, two per SIMD (256
-// registers each).  Wave w holds the 16-row blocks w, w + 8, ... (up to 8
-// of them) of the tile, real and imaginary parts apart: register q of lane
-// (lq, lr) is row r0 + lq + 4 q of column lr.  So all 16 lanes of a column
-// do useful products (the LDS tile of these orders only had room for 8 or
-// 10 columns) and the tile never passes through LDS.  Per step:
+// the registers of eight wavefronts, two per SIMD (256 registers each).
+// Wave w holds the 16-row blocks w, w + 8, ... (up to 8 of them) of the tile
+// in the matrix-core accumulator layout, real and imaginary parts apart:
+// register q of lane (lq, lr) is row r0 + lq + 4 q of column lr.  So all 16
+// lanes of a column do useful products (the LDS tile of these orders only
+// had room for 8 or 10 columns) and the tile never passes through LDS.  Per
+// step:
 //   (1) the owners of the pivot rows and of the rows the interchanges move
 //       below the pivot block write them to an LDS stage (double-buffered
 //       over steps, one barrier per step);
 //   (2) every wave reads the pivot rows as its B operand, the owners of
 //       interchange destinations take their new values from the stage;
 //   (3) the pivot block becomes M1 Y(pivot rows), every other block
-//       Y -= P' Y(pivot rows), four real products per complex one
-//       accumulating straight into the tile (three, as elsewhere, would
-//       need temporaries the register budget does not have); the
-//       multipliers of the block two ahead load while the current block's
+//       Y -= P' Y(pivot rows), three real products per complex one; the
+//       multipliers of the next block load while the current block's
 //       products run (scheduling barriers every second block keep the
-//       compiler from hoisting more loads than the budget holds, and let it
-//       interleave the products of two blocks).
+//       compiler from hoisting more loads than the register budget holds).
 // The step's interchange record is read one step ahead, one entry per lane,
 // and broadcast with readlane.
 constexpr int kRegWaves = 8;
 constexpr int kRegBlk = kGjeMaxN / 16 / kRegWaves;  // 8 row blocks per wave
-constexpr int kRegAhead = 2;                         // multiplier blocks in flight
+constexpr int kRegAhead = 1;                         // multiplier blocks in flight
 
 __device__ __forceinline__ double2 tile_get(const dvec4* Yr, const dvec4* Yi, int j, int q) {
   double2 v = make_double2(0.0, 0.0);
@@ -1248,24 +1246,23 @@ __global__ __launch_bounds__(kRegWaves * 64) __attribute__((amdgpu_waves_per_eu(
       __syncthreads();
       __builtin_amdgcn_sched_barrier(0);
       // (2) the pivot rows as the B operand (lane: row 4 kk + lq, column lr),
-      //     with their negatives; interchange destinations below the block
-      double yr[4], yi[4], nyr[4], nyi[4];
+      //     and their sums for the three-product form; interchange
+      //     destinations below the block
+      double yr[4], yi[4], ys[4];
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
         const double2 v = 4 * kk + lq < nb ? stage[buf][4 * kk + lq][lr] : make_double2(0.0, 0.0);
         yr[kk] = v.x;
         yi[kk] = v.y;
-        nyr[kk] = -v.x;
-        nyi[kk] = -v.y;
+        ys[kk] = v.x + v.y;
       }
       for (int t = 0; t < cnaff; ++t) {
         const int R = __builtin_amdgcn_readlane(cra, t);
         if (R >= k + nb && ((R >> 4) & (kRegWaves - 1)) == wave && lq == (R & 3))
           tile_set(Yr, Yi, (R >> 4) / kRegWaves, (R & 15) >> 2, stage[buf][kGjeNb + t][lr]);
       }
-      // (3) products straight into the tile's accumulators (four real
-      //     products per complex one), block by block, the multipliers
-      //     kRegAhead blocks ahead in flight
+      // (3) products, three real ones per complex one, block by block, the
+      //     multipliers kRegAhead blocks ahead in flight
       const int pblk = k >> 4;  // the pivot block
 #pragma unroll
       for (int j = 0; j < kRegBlk; ++j) {
@@ -1274,27 +1271,30 @@ __global__ __launch_bounds__(kRegWaves * 64) __attribute__((amdgpu_waves_per_eu(
         if (j + kRegAhead < kRegBlk) load_p(k, nb, j + kRegAhead, pbuf[(j + kRegAhead) % (kRegAhead + 1)]);
         if (blk * 16 >= n) continue;
         double2* a = pbuf[j % (kRegAhead + 1)];
-        if (blk == pblk) {  // Z = M1 Y(pivot rows); M1 is zero past nb
+        const bool piv = blk == pblk;
+        if (piv) {  // Z = M1 Y(pivot rows); M1 is zero past nb
           const cplx* M1 = D.M1 + (size_t)sidx * kGjeNb * kGjeNb;
-          double2* m = a;
 #pragma unroll
-          for (int kk = 0; kk < 4; ++kk) m[kk] = gld(M1 + (size_t)(4 * kk + lq) * kGjeNb + lr);  // M1[lr][4 kk + lq]
-          Yr[j] = dvec4{0, 0, 0, 0};
-          Yi[j] = dvec4{0, 0, 0, 0};
+          for (int kk = 0; kk < 4; ++kk) a[kk] = gld(M1 + (size_t)(4 * kk + lq) * kGjeNb + lr);  // M1[lr][4 kk + lq]
+        }
+        dvec4 t1 = {0, 0, 0, 0}, t2 = {0, 0, 0, 0}, t3 = {0, 0, 0, 0};
 #pragma unroll
-          for (int kk = 0; kk < 4; ++kk) {
-            Yr[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(m[kk].x, yr[kk], Yr[j], 0, 0, 0);
-            Yi[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(m[kk].x, yi[kk], Yi[j], 0, 0, 0);
-            Yr[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(m[kk].y, nyi[kk], Yr[j], 0, 0, 0);
-            Yi[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(m[kk].y, yr[kk], Yi[j], 0, 0, 0);
+        for (int kk = 0; kk < 4; ++kk) {
+          t1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk].x, yr[kk], t1, 0, 0, 0);
+          t2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk].y, yi[kk], t2, 0, 0, 0);
+          t3 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk].x + a[kk].y, ys[kk], t3, 0, 0, 0);
+        }
+        if (piv) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            Yr[j][q] = t1[q] - t2[q];
+            Yi[j][q] = t3[q] - t1[q] - t2[q];
           }
         } else {  // Y -= P' Y(pivot rows)
 #pragma unroll
-          for (int kk = 0; kk < 4; ++kk) {
-            Yr[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk].x, nyr[kk], Yr[j], 0, 0, 0);
-            Yi[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk].x, nyi[kk], Yi[j], 0, 0, 0);
-            Yr[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk].y, yi[kk], Yr[j], 0, 0, 0);
-            Yi[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk].y, nyr[kk], Yi[j], 0, 0, 0);
+          for (int q = 0; q < 4; ++q) {
+            Yr[j][q] -= t1[q] - t2[q];
+            Yi[j][q] -= t3[q] - t1[q] - t2[q];
           }
         }
       }
