@@ -140,7 +140,11 @@ mlh_status mlh_stack_info(mlh_stack s, int64_t* n_den, int64_t* n_tot, int64_t* 
  * solve of Sec. 3.3 for the densities eta, and the Bragg amplitudes
  * x_1 = -X_1 eta_1, x_{I+1} = -X_{I+1} eta_I with the flux error eq. (86).
  * Angles whose Bloch phases alpha agree share one factorisation (Sec. 3.4);
- * batches of systems share the per-layer launches.
+ * batches of systems share the per-layer launches.  A batch holds as many
+ * systems as 80 % of the free device memory takes, or, when the environment
+ * variable MLH_WORKSPACE_LIMIT_MB is a positive number, as that many MiB
+ * take (at least one system per batch); the stack keeps its workspace for
+ * later calls.
  *
  * outputs_on_device: 0 = the output pointers are host memory and the call
  * returns once they are written; 1 = they are device memory of the

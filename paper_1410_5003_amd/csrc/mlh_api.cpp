@@ -1249,6 +1249,12 @@ static mlh_status solve_systems(Runner& RN, mlh_ctx ctx, const mlh_tuning& tune,
     HIP_TRY(hipMemGetInfo(&freeb, &totb));
     budget = (size_t)(0.8 * (double)(freeb + RN.wbytes));
     budget = budget > slack ? budget - slack : 0;
+    // a caller's cap on the workspace (batches shrink to fit; a batch
+    // always holds at least one system)
+    if (const char* lim = std::getenv("MLH_WORKSPACE_LIMIT_MB")) {
+      const double mb = std::atof(lim);
+      if (mb > 0) budget = std::min(budget, (size_t)(mb * 1048576.0));
+    }
   }
   std::vector<int> bstart = {0};
   size_t need = 0;

@@ -259,3 +259,31 @@ def test_shared_alpha_angles_solved_as_one_system(ctx):
         assert err < TOL and err1 < 1e-11
         assert abs(out.flux_err[a]) < 1e-9
     st.close()
+
+
+def test_solve_in_several_workspace_batches_matches_one_batch(ctx, monkeypatch):
+    # distinct Bloch phases are independent systems; a workspace cap that
+    # fits one system at a time splits the call into a batch per system
+    # (a fresh stack then holds a workspace for one system only), with the
+    # same arithmetic per system
+    import paper_1410_5003_amd as mlh
+    desc = workloads.small_stack(seed=6, I=4, N=77, P=45, M_w=35, M_ud=40, K=9)  # flux error ~1e-11
+    th = np.linspace(-1.3, -0.2, 6)
+    st = mlh.Stack(ctx, desc)
+    one = st.solve(th)
+    bytes_one = st.info()["device_bytes"]
+    st.close()
+    monkeypatch.setenv("MLH_WORKSPACE_LIMIT_MB", "0.01")
+    st = mlh.Stack(ctx, desc)
+    many = st.solve(th)
+    bytes_many = st.info()["device_bytes"]
+    monkeypatch.delenv("MLH_WORKSPACE_LIMIT_MB")
+    again = st.solve(th)  # the workspace grows back to one batch
+    st.close()
+    assert bytes_many < bytes_one
+    for a in range(th.size):
+        assert np.array_equal(one.orders[a], many.orders[a])
+        assert rel_amp_err(many.aU[a], many.aD[a], one.aU[a], one.aD[a]) < 1e-13
+        assert rel_amp_err(again.aU[a], again.aD[a], one.aU[a], one.aD[a]) < 1e-13
+    o = oracle.solve_stack(desc, theta=float(th[2]))
+    assert rel_amp_err(many.aU[2], many.aD[2], o.aU, o.aD) < TOL
