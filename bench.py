@@ -71,6 +71,10 @@ WORKLOADS = {
                          "(smooth) / 25 k_max (cornered), 70% random Fourier / 30% cornered, k = omega n with "
                          "omega ~ U[5,8], n ~ U[1,2.5], P=140, M_w=100, M_ud=60, K=25; one random angle per stack",
                          "batch"),
+    # the scattered field at a million targets of the 50-interface resolved stack (mlh_field)
+    "field": ("config2", dict(N=260, P=120, M_w=80),
+              "I=50 random Fourier interfaces, N=260, P=120, M_w=80, M_ud=60, K=25, one angle; scattered field "
+              "at 1e6 seeded targets uniform in the cell from y_D - 1 to y_U + 1", "field"),
     # the adjoint gradient of a ShapeProblem (mlh_adjoint)
     "config5_resolved": ("config5", dict(N=260, P=120, M_w=80),
                          "I=100 smooth interfaces, 5 sine amplitudes each (500) and 101 layer indices, omega=10, "
@@ -382,6 +386,62 @@ def bench_batch(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_field(args):
+    """One step = mlh_field at a million targets: the solve for the angle,
+    the proxy strengths, then the layer representations (or Rayleigh-Bloch
+    sums) at every target.  Beside it the plain solve of the same angle, so
+    that the evaluation's own rate can be read off."""
+    import numpy as np
+    import torch
+    import paper_1410_5003_amd as mlh
+    desc = make_desc(args.workload)
+    theta = float(desc.thetas[0])
+    rng = np.random.default_rng(7)
+    n_pts = 1_000_000
+    x = rng.uniform(-desc.d / 2, desc.d / 2, n_pts)
+    y = rng.uniform(desc.y_D - 1.0, desc.y_U + 1.0, n_pts)
+    ctx = mlh.Context(0)
+    st = mlh.Stack(ctx, desc)
+    steps = args.steps if args.steps is not None else 5
+    warmup = args.warmup if args.warmup is not None else 1
+    for _ in range(warmup):
+        u, reg = st.field(theta, x, y)
+        st.solve([theta])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        u, reg = st.field(theta, x, y)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st.solve([theta])
+    torch.cuda.synchronize()
+    solve_ms = (time.perf_counter() - t0) * 1e3 / steps
+    # kernel evaluations: a target in layer j sums S and D over the three
+    # copies of each bounding interface (6 N each) and the layer's P proxies
+    N = [f.N for f in desc.interfaces]
+    evals = 0
+    for j in range(desc.I + 1):
+        cnt = int(np.sum(reg == j))
+        evals += cnt * (6 * ((N[j - 1] if j > 0 else 0) + (N[j] if j < desc.I else 0)) + desc.P)
+    st.close()
+    eval_ms = max(ms - solve_ms, 1e-9)
+    line = {
+        "metric": METRIC, "value": n_pts / (ms * 1e-3), "unit": "targets/s", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 (complex128)", "data": "synthetic (seeded stacks and targets)",
+        "config": {"workload": args.workload, "description": WORKLOADS[args.workload][2], "interfaces": desc.I,
+                   "targets": n_pts},
+        "solve_ms": solve_ms, "evaluation_ms": eval_ms, "targets_per_s_evaluation": n_pts / (eval_ms * 1e-3),
+        "kernel_evals_per_s": evals / (eval_ms * 1e-3),
+        "targets_above_U": int(np.sum(reg == -1)), "targets_below_D": int(np.sum(reg == desc.I + 1)),
+    }
+    print("field %.1f ms per call (solve %.1f ms, evaluation %.1f ms); %.3g targets/s, %.3g kernel evaluations/s" %
+          (ms, solve_ms, eval_ms, line["value"], line["kernel_evals_per_s"]), file=sys.stderr, flush=True)
+    print(json.dumps(line), flush=True)
+
+
 def bench_adjoint(args):
     """One step = the gradient of J (summed zeroth-order reflected
     efficiency over the problem's angles) in every shape amplitude and
@@ -495,6 +555,8 @@ def main():
         return bench_batch(args)
     if WORKLOADS[args.workload][3] == "adjoint":
         return bench_adjoint(args)
+    if WORKLOADS[args.workload][3] == "field":
+        return bench_field(args)
     import numpy as np
     import torch
     import paper_1410_5003_amd as mlh
