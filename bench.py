@@ -20,8 +20,9 @@ each with its own Bloch phase, in one graph-captured launch sequence
 
 Other workloads (--workload): the same stack on a kappa_0 grid of 20 Bloch
 phases (angles that share a phase share one factorisation), the literal
-sizes, the 50-interface stack, the 64-stack batch (mlh_batch_solve) and the
-adjoint gradient of the 100-interface problem (mlh_adjoint).
+sizes, the 50-interface stack, the 64-stack batch (mlh_batch_solve), the
+adjoint gradient of the 100-interface problem (mlh_adjoint) and the field at
+a million targets (mlh_field).
 """
 import argparse
 import json
