@@ -2309,10 +2309,39 @@ extern "C" mlh_status mlh_field(mlh_stack s, double theta, int64_t n_pts, const 
   }
   std::vector<int64_t> start(I + 4, 0);
   for (int r = 0; r < I + 3; ++r) start[r + 1] = start[r] + count[r];
+  // order: by region, and inside a region by the cells of a grid of spacing
+  // d/64 (row by row), so that the targets of a wavefront lie close together
+  // and take the same branch of the Hankel routine for each source (two
+  // stable counting sorts: by cell, then by region).  In the input order a
+  // wavefront's lanes diverge over the series, recurrence and asymptotic
+  // branches: a million random targets took 4.6 times as long.
+  std::vector<int64_t> by_cell(n_pts);
+  {
+    const int gxn = 64;
+    const double hx = d / gxn;
+    double ylo = y[0], yhi = y[0];
+    for (int64_t t = 1; t < n_pts; ++t) {
+      ylo = std::min(ylo, y[t]);
+      yhi = std::max(yhi, y[t]);
+    }
+    const int64_t rows = std::min<int64_t>(65536, std::max<int64_t>(1, n_pts / 64));  // grid rows at most
+    const double hy = std::max(hx, (yhi - ylo) / (double)rows);
+    const int64_t gyn = std::min<int64_t>((int64_t)((yhi - ylo) / hy) + 1, rows);
+    std::vector<int64_t> cpos(gyn * gxn + 1, 0);
+    std::vector<int32_t> cell(n_pts);
+    for (int64_t t = 0; t < n_pts; ++t) {
+      const int64_t cy = std::min<int64_t>(gyn - 1, (int64_t)((y[t] - ylo) / hy));
+      const int cx = std::min(gxn - 1, std::max(0, (int)((tg[t].x + 0.5 * d) / hx)));
+      cell[t] = (int32_t)(cy * gxn + cx);
+      ++cpos[cell[t] + 1];
+    }
+    for (size_t c = 1; c < cpos.size(); ++c) cpos[c] += cpos[c - 1];
+    for (int64_t t = 0; t < n_pts; ++t) by_cell[cpos[cell[t]]++] = t;
+  }
   std::vector<FieldTarget> sorted(n_pts);
   {
     std::vector<int64_t> pos(start.begin(), start.end() - 1);
-    for (int64_t t = 0; t < n_pts; ++t) sorted[pos[reg[t] + 1]++] = tg[t];
+    for (int64_t t : by_cell) sorted[pos[reg[t] + 1]++] = tg[t];
   }
   std::vector<FieldTile> tiles;
   for (int r = 0; r < I + 3; ++r)
