@@ -327,9 +327,10 @@ __device__ __forceinline__ void hq_apply_panel(hvec4 (&yr)[kHqRhsRbw], hvec4 (&y
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int lr = lane & 15, lq = lane >> 4;
   // V operands of this wave's row blocks: vh for V^H (lane: reflector lr,
-  // row 4 kk + lq) now, vv for V (lane: row lr, reflector 4 kk + lq) after
-  // the first products, its loads covered by the reduction
-  double2 vh[kHqRhsRbw][4], vv[kHqRhsRbw][4];
+  // row 4 kk + lq) now, vv for V (lane: row lr, reflector 4 kk + lq) one
+  // row block at a time in step 3, so that the two layouts are never held
+  // together (holding both spilled the tile Y inside the panel loop)
+  double2 vh[kHqRhsRbw][4];
 #pragma unroll
   for (int j = 0; j < kHqRhsRbw; ++j) {
     const int r0 = (wave + kHqRhsWaves * j) * 16;
@@ -348,14 +349,6 @@ __device__ __forceinline__ void hq_apply_panel(hvec4 (&yr)[kHqRhsRbw], hvec4 (&y
     if (r0 + 15 < k) continue;
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) cacc_step(w, vh[j][kk].x, -vh[j][kk].y, yr[j][kk], yi[j][kk]);
-  }
-#pragma unroll
-  for (int j = 0; j < kHqRhsRbw; ++j) {
-    const int r0 = (wave + kHqRhsWaves * j) * 16;
-    const bool live = r0 + 15 >= k && r0 < M;
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk)
-      vv[j][kk] = live && r0 + lr < M ? hq_v(A, M, k, nb, r0 + lr, 4 * kk + lq) : make_double2(0.0, 0.0);
   }
   // red: this panel's buffer of partial sums
 #pragma unroll
@@ -396,10 +389,14 @@ __device__ __forceinline__ void hq_apply_panel(hvec4 (&yr)[kHqRhsRbw], hvec4 (&y
     const int r0 = (wave + kHqRhsWaves * j) * 16;
     if (r0 >= M) break;
     if (r0 + 15 < k) continue;
+    double2 vv[4];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk)
+      vv[kk] = r0 + lr < M ? hq_v(A, M, k, nb, r0 + lr, 4 * kk + lq) : make_double2(0.0, 0.0);
     Cacc d;
     cacc_zero(d);
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) cacc_step(d, vv[j][kk].x, vv[j][kk].y, ur[kk], ui[kk]);
+    for (int kk = 0; kk < 4; ++kk) cacc_step(d, vv[kk].x, vv[kk].y, ur[kk], ui[kk]);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       yr[j][q] -= d.t1[q] - d.t2[q];
