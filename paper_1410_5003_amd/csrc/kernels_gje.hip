@@ -1152,6 +1152,7 @@ __global__ __launch_bounds__(kRhsWaves * 64) void gje_rhs_kernel(const GjeDesc* 
 constexpr int kRegWaves = 8;
 constexpr int kRegBlk = kGjeMaxN / 16 / kRegWaves;  // 8 row blocks per wave
 constexpr int kRegAhead = 1;                         // multiplier blocks in flight
+static_assert(kGjeNb == 16, "the register replay's pivot block of step k is row block k >> 4");
 
 __device__ __forceinline__ double2 tile_get(const dvec4* Yr, const dvec4* Yi, int j, int q) {
   double2 v = make_double2(0.0, 0.0);
@@ -1210,12 +1211,17 @@ __global__ __launch_bounds__(kRegWaves * 64) __attribute__((amdgpu_waves_per_eu(
       rb = piv[1 + 4 * kGjeNb + min(lane, kGjeNb - 1)];
       naff = piv[0];
     };
-    // multipliers P' of step k for row block j (lane: row r0 + lr, column 4 kk + lq)
+    // multipliers P' of step k for row block j (lane: row r0 + lr, column
+    // 4 kk + lq); the pivot block takes M1 instead (lane: M1[lr][4 kk + lq],
+    // zero past nb), so that every block's operand is the one loaded ahead
     auto load_p = [&](int k, int nb, int j, double2* dst) {
-      const int row = min((wave + j * kRegWaves) * 16 + lr, n - 1);
+      const int blk = wave + j * kRegWaves;
+      const bool pv = blk == (k >> 4);  // uniform over the wave: a pointer select, no branch
+      const cplx* M1 = D.M1 + (size_t)(k >> 4) * kGjeNb * kGjeNb + lr;
+      const int row = min(blk * 16 + lr, n - 1);
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk)
-        dst[kk] = ldc(W + (uint32_t)((k + min(4 * kk + lq, nb - 1)) * n + row));
+        dst[kk] = ldc(pv ? M1 + (4 * kk + lq) * kGjeNb : W + (uint32_t)((k + min(4 * kk + lq, nb - 1)) * n + row));
     };
     int ra = 0, rb = 0, naff = 0;
     double2 pbuf[kRegAhead + 1][4];
@@ -1270,13 +1276,8 @@ __global__ __launch_bounds__(kRegWaves * 64) __attribute__((amdgpu_waves_per_eu(
         const int blk = wave + j * kRegWaves;
         if (j + kRegAhead < kRegBlk) load_p(k, nb, j + kRegAhead, pbuf[(j + kRegAhead) % (kRegAhead + 1)]);
         if (blk * 16 >= n) continue;
-        double2* a = pbuf[j % (kRegAhead + 1)];
-        const bool piv = blk == pblk;
-        if (piv) {  // Z = M1 Y(pivot rows); M1 is zero past nb
-          const cplx* M1 = D.M1 + (size_t)sidx * kGjeNb * kGjeNb;
-#pragma unroll
-          for (int kk = 0; kk < 4; ++kk) a[kk] = gld(M1 + (size_t)(4 * kk + lq) * kGjeNb + lr);  // M1[lr][4 kk + lq]
-        }
+        const double2* a = pbuf[j % (kRegAhead + 1)];
+        const bool piv = blk == pblk;  // Z = M1 Y(pivot rows), a holding M1
         dvec4 t1 = {0, 0, 0, 0}, t2 = {0, 0, 0, 0}, t3 = {0, 0, 0, 0};
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {

@@ -53,6 +53,7 @@ __device__ inline double wave_sum(double v) {
 // im = T3 - T1 - T2), a quarter fewer matrix-core operations than four.
 // ---------------------------------------------------------------------------
 constexpr int kGK = 16;
+static_assert(kGemmTile == 64 && kGemmTile * kGK == 4 * 256, "slab staging: A element e = tid + 256 q has k = wave + 4 q");
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void zgemm_kernel(const GemmDesc* __restrict__ descs, int ndesc, int tile0) {
   const int tile = tile0 + (int)blockIdx.x;
@@ -89,6 +90,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void z
   const cplx* const B1 = G.B;
   const cplx* const B2 = G.B2;
   const int lda = G.lda, lda2 = G.lda2, ldb = G.ldb, ldb2 = G.ldb2;
+  // Raw loads, no select: a select right after a load makes the wave wait
+  // for it there, before the products of the current slab.  Rows of A past
+  // m and columns of B past n read clamped (finite) copies that reach only
+  // rows and columns of C that are never stored; k past K is zeroed in A
+  // when the slab is written to LDS (k of A element e is k0 + wave + 4 q,
+  // uniform over the wave).
   auto load_slab = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
@@ -97,13 +104,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void z
         const int gr = row0 + e % kGemmTile, gk = k0 + e / kGemmTile;
         const int r = min(gr, m - 1), kc = min(gk, K - 1);
         const cplx* src = kc < K1 ? A1 + (size_t)kc * lda + r : A2 + (size_t)(kc - K1) * lda2 + r;
-        pa[q] = ldc_sel(src, gr < m && gk < K);
+        pa[q] = ldc(src);
       }
       {
         const int gk = k0 + e % kGK, gc = col0 + e / kGK;
         const int cc = min(gc, n - 1), kc = min(gk, K - 1);
         const cplx* src = kc < K1 ? B1 + (size_t)cc * ldb + kc : B2 + (size_t)cc * ldb2 + (kc - K1);
-        pb[q] = ldc_sel(src, gc < n && gk < K);
+        pb[q] = ldc(src);
       }
     }
   };
@@ -112,8 +119,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void z
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
       const int e = tid + 256 * q;
-      Ar[e / kGemmTile][e % kGemmTile] = pa[q].x;
-      Ai[e / kGemmTile][e % kGemmTile] = pa[q].y;
+      const bool kin = k0 + wave + 4 * q < K;
+      Ar[e / kGemmTile][e % kGemmTile] = kin ? pa[q].x : 0.0;
+      Ai[e / kGemmTile][e % kGemmTile] = kin ? pa[q].y : 0.0;
       Br[e % kGK][e / kGK] = pb[q].x;
       Bi[e % kGK][e / kGK] = pb[q].y;
     }
