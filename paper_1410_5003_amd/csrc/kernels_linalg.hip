@@ -55,21 +55,23 @@ __device__ inline double wave_sum(double v) {
 constexpr int kGK = 16;
 static_assert(kGemmTile == 64 && kGemmTile * kGK == 4 * 256, "slab staging: A element e = tid + 256 q has k = wave + 4 q");
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void zgemm_kernel(const GemmDesc* __restrict__ descs, int ndesc, int tile0) {
-  const int tile = tile0 + (int)blockIdx.x;
-  const GemmDesc& G = descs[find_tile(descs, ndesc, tile)];
-  const int lt = tile - G.tile_begin;
-  const int row0 = (lt % G.tiles_m) * kGemmTile, col0 = (lt / G.tiles_m) * kGemmTile;
-  __shared__ double Ar[kGK][kGemmTile + 1], Ai[kGK][kGemmTile + 1];
-  __shared__ double Br[kGK][kGemmTile + 1], Bi[kGK][kGemmTile + 1];
+typedef double GemmSlab[kGK][kGemmTile + 1];
+
+// One tile.  kFull: the tile lies wholly inside C, so no 16 x 16 block is
+// skipped and the four k-steps of a slab have no branch between their
+// products (the LDS reads of one k-step can then be scheduled among the
+// products of the one before); edge tiles take the checked form.
+template <bool kFull>
+__device__ __forceinline__ void zgemm_tile(const GemmDesc& G, int row0, int col0, GemmSlab& Ar, GemmSlab& Ai,
+                                           GemmSlab& Br, GemmSlab& Bi) {
   const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int lr = lane & 15, lq = lane >> 4;
   const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
   const int m = G.m, n = G.n, K1 = G.k, K = G.k + G.k2;
   // 16 x 16 blocks of the wave that hold rows / columns of C (the ragged
   // edge tiles and the narrow right-hand-side products leave the others out)
-  const bool rin[2] = {row0 + wm < m, row0 + wm + 16 < m};
-  const bool cin[2] = {col0 + wn < n, col0 + wn + 16 < n};
+  const bool rin[2] = {kFull || row0 + wm < m, kFull || row0 + wm + 16 < m};
+  const bool cin[2] = {kFull || col0 + wn < n, kFull || col0 + wn + 16 < n};
   dvec4 t1[2][2], t2[2][2], t3[2][2];
 #pragma unroll
   for (int b = 0; b < 2; ++b)
@@ -170,19 +172,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void z
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     const int col = col0 + wn + 16 * c + lr;
-    if (col >= n) continue;
+    if (!kFull && col >= n) continue;
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = row0 + wm + 16 * b + lq + 4 * r;
-        if (row < m) {
+        if (kFull || row < m) {
           const double xr = t1[b][c][r] - t2[b][c][r], xi = t3[b][c][r] - t1[b][c][r] - t2[b][c][r];
           const double2 cv = c0v[c][b][r];
           st2(Cm + (size_t)col * ldc + row, cv.x + alr * xr - ali * xi, cv.y + alr * xi + ali * xr);
         }
       }
   }
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void zgemm_kernel(const GemmDesc* __restrict__ descs, int ndesc, int tile0) {
+  const int tile = tile0 + (int)blockIdx.x;
+  const GemmDesc& G = descs[find_tile(descs, ndesc, tile)];
+  const int lt = tile - G.tile_begin;
+  const int row0 = (lt % G.tiles_m) * kGemmTile, col0 = (lt / G.tiles_m) * kGemmTile;
+  __shared__ GemmSlab Ar, Ai, Br, Bi;
+  if (row0 + kGemmTile <= G.m && col0 + kGemmTile <= G.n)  // uniform over the workgroup
+    zgemm_tile<true>(G, row0, col0, Ar, Ai, Br, Bi);
+  else
+    zgemm_tile<false>(G, row0, col0, Ar, Ai, Br, Bi);
 }
 
 // ---------------------------------------------------------------------------
