@@ -1137,9 +1137,13 @@ __global__ __launch_bounds__(kRhsWaves * 64) void gje_rhs_kernel(const GjeDesc* 
 // lanes of a column do useful products (the LDS tile of these orders only
 // had room for 8 or 10 columns) and the tile never passes through LDS.  Per
 // step:
-//   (1) the owners of the pivot rows and of the rows the interchanges move
-//       below the pivot block write them to an LDS stage (double-buffered
-//       over steps, one barrier per step);
+//   (0) one wave enters the step's pivot rows, the sources of the rows the
+//       interchanges move below the pivot block and their destinations in
+//       two row maps in LDS (tagged with the step, double-buffered);
+//   (1) every lane looks up its own 32 rows (all 16 lanes of a row read
+//       the same entry) and writes those the map names to an LDS stage
+//       (double-buffered over steps), so no register of the tile is ever
+//       picked by a runtime index;
 //   (2) every wave reads the pivot rows as its B operand, the owners of
 //       interchange destinations take their new values from the stage;
 //   (3) the pivot block becomes M1 Y(pivot rows), every other block
@@ -1147,32 +1151,12 @@ __global__ __launch_bounds__(kRhsWaves * 64) void gje_rhs_kernel(const GjeDesc* 
 //       multipliers of the next block load while the current block's
 //       products run (scheduling barriers every second block keep the
 //       compiler from hoisting more loads than the register budget holds).
-// The step's interchange record is read one step ahead, one entry per lane,
-// and broadcast with readlane.
+// The step's interchange record is read one step ahead, one entry per lane.
+// Two barriers per step: after the maps, after the stage.
 constexpr int kRegWaves = 8;
 constexpr int kRegBlk = kGjeMaxN / 16 / kRegWaves;  // 8 row blocks per wave
 constexpr int kRegAhead = 1;                         // multiplier blocks in flight
 static_assert(kGjeNb == 16, "the register replay's pivot block of step k is row block k >> 4");
-
-__device__ __forceinline__ double2 tile_get(const dvec4* Yr, const dvec4* Yi, int j, int q) {
-  double2 v = make_double2(0.0, 0.0);
-#pragma unroll
-  for (int jj = 0; jj < kRegBlk; ++jj)
-#pragma unroll
-    for (int qq = 0; qq < 4; ++qq)
-      if (jj == j && qq == q) v = make_double2(Yr[jj][qq], Yi[jj][qq]);
-  return v;
-}
-__device__ __forceinline__ void tile_set(dvec4* Yr, dvec4* Yi, int j, int q, double2 v) {
-#pragma unroll
-  for (int jj = 0; jj < kRegBlk; ++jj)
-#pragma unroll
-    for (int qq = 0; qq < 4; ++qq)
-      if (jj == j && qq == q) {
-        Yr[jj][qq] = v.x;
-        Yi[jj][qq] = v.y;
-      }
-}
 
 __global__ __launch_bounds__(kRegWaves * 64) __attribute__((amdgpu_waves_per_eu(2, 2))) void gje_rhs_reg_kernel(
     const GjeDesc* __restrict__ descs, int nbatch, int tiles_per, int s0, int s1) {
@@ -1181,6 +1165,12 @@ __global__ __launch_bounds__(kRegWaves * 64) __attribute__((amdgpu_waves_per_eu(
   const int lr = lane & 15, lq = lane >> 4;
   // stage slots: 16 pivot rows, then up to 2 NB interchange sources
   __shared__ double2 stage[2][3 * kGjeNb][TC];
+  // a step's rows, double-buffered over steps: smap[r] = 64 (s + 1) + slot
+  // when step s stages row r into that slot (its pivot rows and the sources
+  // of the rows moved below the pivot block), dmap[r] likewise when row r
+  // takes its new value from the slot; entries of earlier steps carry a
+  // smaller tag, so they need no clearing within a tile
+  __shared__ unsigned short smap[2][kGjeMaxN], dmap[2][kGjeMaxN];
   for (int tile = blockIdx.x; tile < nbatch * tiles_per; tile += gridDim.x) {
     const GjeDesc& D = descs[tile / tiles_per];
     const int n = D.n;
@@ -1202,6 +1192,11 @@ __global__ __launch_bounds__(kRegWaves * 64) __attribute__((amdgpu_waves_per_eu(
         }
       }
     }
+    for (int i = tid; i < 2 * kGjeMaxN; i += kRegWaves * 64) {
+      (&smap[0][0])[i] = 0;
+      (&dmap[0][0])[i] = 0;
+    }
+    __syncthreads();
     const int nsteps = min(s1, (n + kGjeNb - 1) / kGjeNb);
     // interchange record of a step: lane t holds entry 1 + t (destinations
     // 0..31, then sources 0..31) in ra and entry 65 + t (pivot rows) in rb
@@ -1236,19 +1231,28 @@ __global__ __launch_bounds__(kRegWaves * 64) __attribute__((amdgpu_waves_per_eu(
       const int cra = ra, crb = rb, cnaff = min(__builtin_amdgcn_readfirstlane(naff), 2 * kGjeNb);
       if (sidx + 1 < nsteps) load_rec(sidx + 1, ra, rb, naff);
       const int buf = sidx & 1;
+      const int tag = 64 * (sidx + 1);
       __builtin_amdgcn_sched_barrier(0);
-      // (1) stage the pivot rows and the sources of rows moved below the block
-      for (int c = 0; c < nb; ++c) {
-        const int R = __builtin_amdgcn_readlane(crb, c);
-        if (((R >> 4) & (kRegWaves - 1)) == wave && lq == (R & 3))
-          stage[buf][c][lr] = tile_get(Yr, Yi, (R >> 4) / kRegWaves, (R & 15) >> 2);
+      // (0) wave 0 enters the step's rows in the maps: pivot c (lane c), and
+      //     pair t (lane t: destination; lane 2 NB + t: source) when its
+      //     destination lies below the pivot block
+      if (wave == 0) {
+        const int src = __shfl(cra, min(lane + 2 * kGjeNb, 63), 64);
+        if (lane < nb && (unsigned)crb < (unsigned)n) smap[buf][crb] = (unsigned short)(tag + lane);
+        if (lane < cnaff && cra >= k + nb && cra < n && (unsigned)src < (unsigned)n) {
+          smap[buf][src] = (unsigned short)(tag + kGjeNb + lane);
+          dmap[buf][cra] = (unsigned short)(tag + kGjeNb + lane);
+        }
       }
-      for (int t = 0; t < cnaff; ++t) {
-        const int dst = __builtin_amdgcn_readlane(cra, t);
-        const int R = __builtin_amdgcn_readlane(cra, 2 * kGjeNb + t);
-        if (dst >= k + nb && ((R >> 4) & (kRegWaves - 1)) == wave && lq == (R & 3))
-          stage[buf][kGjeNb + t][lr] = tile_get(Yr, Yi, (R >> 4) / kRegWaves, (R & 15) >> 2);
-      }
+      __syncthreads();
+      // (1) every lane stages those of its rows that the map names
+#pragma unroll
+      for (int j = 0; j < kRegBlk; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int v = smap[buf][(wave + j * kRegWaves) * 16 + lq + 4 * q];
+          if (v >= tag) stage[buf][v - tag][lr] = make_double2(Yr[j][q], Yi[j][q]);
+        }
       __syncthreads();
       __builtin_amdgcn_sched_barrier(0);
       // (2) the pivot rows as the B operand (lane: row 4 kk + lq, column lr),
@@ -1262,11 +1266,17 @@ __global__ __launch_bounds__(kRegWaves * 64) __attribute__((amdgpu_waves_per_eu(
         yi[kk] = v.y;
         ys[kk] = v.x + v.y;
       }
-      for (int t = 0; t < cnaff; ++t) {
-        const int R = __builtin_amdgcn_readlane(cra, t);
-        if (R >= k + nb && ((R >> 4) & (kRegWaves - 1)) == wave && lq == (R & 3))
-          tile_set(Yr, Yi, (R >> 4) / kRegWaves, (R & 15) >> 2, stage[buf][kGjeNb + t][lr]);
-      }
+#pragma unroll
+      for (int j = 0; j < kRegBlk; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int v = dmap[buf][(wave + j * kRegWaves) * 16 + lq + 4 * q];
+          if (v >= tag) {
+            const double2 y = stage[buf][v - tag][lr];
+            Yr[j][q] = y.x;
+            Yi[j][q] = y.y;
+          }
+        }
       // (3) products, three real ones per complex one, block by block, the
       //     multipliers kRegAhead blocks ahead in flight
       const int pblk = k >> 4;  // the pivot block
