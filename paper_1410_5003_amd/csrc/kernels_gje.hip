@@ -805,7 +805,12 @@ __global__ __launch_bounds__(kUpdWideThreads) void gje_update_wide_kernel(const 
   // 3. Y(other rows) -= P Z on the matrix cores: 16-row blocks times the
   //    16-column blocks of the tile; each row block's old values and
   //    multipliers are loaded in one round, before its products (8 % faster
-  //    than loading the old values after the products)
+  //    than loading the old values after the products).  The loads are
+  //    clamped and unmasked, and every column block is multiplied, so that
+  //    no select or branch makes the wave wait for a load before the last
+  //    one is issued: rows past n and columns past nc are not stored, and
+  //    multiplier columns past nb meet rows of Z that are zero (M1 is zero
+  //    there)
   const int nrb = (n + 15) / 16;
 #pragma unroll 1
   for (int rb = wave; rb < nrb; rb += kUpdWideWaves) {
@@ -816,8 +821,8 @@ __global__ __launch_bounds__(kUpdWideThreads) void gje_update_wide_kernel(const 
       // multipliers: the panel columns of W (rows below k: current values;
       // rows below the pivot block: their original values, already
       // interchanged by the panel kernel; pivot rows are masked below)
-      const int row = r0 + (lane & 15), kq = kk + (lane >> 4);
-      a[kk / 4] = (row < n && kq < nb) ? gld(W + (size_t)(k + kq) * n + row) : make_double2(0.0, 0.0);
+      const int row = min(r0 + (lane & 15), n - 1), kq = min(kk + (lane >> 4), nb - 1);
+      a[kk / 4] = gld(W + (size_t)(k + kq) * n + row);
     }
 #pragma unroll
     for (int cb = 0; cb < kUpdWideCols / 16; ++cb)
@@ -826,9 +831,9 @@ __global__ __launch_bounds__(kUpdWideThreads) void gje_update_wide_kernel(const 
         const int c = min(cb * 16 + (lane & 15), nc - 1), row = min(r0 + (lane >> 4) + 4 * q, n - 1);
         v[cb][q] = gld(W + (size_t)(c0 + c) * n + row);  // clamped: entries past nc or n are not stored
       }
+    asm volatile("" ::: "memory");  // compiler barrier: the loads above are not sunk to their stores
 #pragma unroll
     for (int cb = 0; cb < kUpdWideCols / 16; ++cb) {
-      if (cb * 16 >= nc) break;
       dvec4 accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
 #pragma unroll
       for (int kk = 0; kk < kGjeNb; kk += 4) {
