@@ -289,12 +289,18 @@ __global__ __launch_bounds__(kHqPanelThreads) void hq_panel_kernel(const HqDesc*
 
 typedef double hvec4 __attribute__((ext_vector_type(4)));
 
-// V of panel k as an MFMA operand value: column i, row r (global); unit
-// diagonal and zeros above it, Householder vectors below
-__device__ inline double2 hq_v(const cplx* A, int M, int k, int nb, int r, int i) {
-  if (i >= nb || r < k + i) return make_double2(0.0, 0.0);
+// V of panel k as an MFMA operand value, column i, row r (global): unit
+// diagonal, zeros above it and past row M, Householder vectors below.  In
+// two parts, so that a load can be in flight while other work runs:
+// hq_v_raw loads the stored entry at clamped indices (inside the panel's
+// columns and the M rows), hq_v_mask turns it into V's value.
+__device__ inline double2 hq_v_raw(const cplx* A, int M, int k, int nb, int r, int i) {
+  return hld(A + (size_t)(k + min(i, nb - 1)) * M + min(r, M - 1));
+}
+__device__ inline double2 hq_v_mask(double2 raw, int M, int k, int nb, int r, int i) {
+  if (i >= nb || r < k + i || r >= M) return make_double2(0.0, 0.0);
   if (r == k + i) return make_double2(1.0, 0.0);
-  return hld(A + (size_t)(k + i) * M + r);
+  return raw;
 }
 
 constexpr int kHqRhsCols = 16;
@@ -327,17 +333,18 @@ __device__ __forceinline__ void hq_apply_panel(hvec4 (&yr)[kHqRhsRbw], hvec4 (&y
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int lr = lane & 15, lq = lane >> 4;
   // V operands of this wave's row blocks: vh for V^H (lane: reflector lr,
-  // row 4 kk + lq) now, vv for V (lane: row lr, reflector 4 kk + lq) one
-  // row block at a time in step 3, so that the two layouts are never held
-  // together (holding both spilled the tile Y inside the panel loop)
+  // row 4 kk + lq), all loaded at once; vv for V (lane: row lr, reflector
+  // 4 kk + lq) in step 3, one row block ahead of the products, so that the
+  // two layouts are never held together (holding both spilled the tile Y
+  // inside the panel loop).  Loads are raw; each block's values are masked
+  // just before its products (scheduling barriers keep the selects there),
+  // so the wave waits for one block's loads at a time.
   double2 vh[kHqRhsRbw][4];
 #pragma unroll
   for (int j = 0; j < kHqRhsRbw; ++j) {
     const int r0 = (wave + kHqRhsWaves * j) * 16;
-    const bool live = r0 + 15 >= k && r0 < M;
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk)
-      vh[j][kk] = live && r0 + 4 * kk + lq < M ? hq_v(A, M, k, nb, r0 + 4 * kk + lq, lr) : make_double2(0.0, 0.0);
+    for (int kk = 0; kk < 4; ++kk) vh[j][kk] = hq_v_raw(A, M, k, nb, r0 + 4 * kk + lq, lr);
   }
   // 1. partial w = V^H Y over this wave's rows
   Cacc w;
@@ -345,11 +352,20 @@ __device__ __forceinline__ void hq_apply_panel(hvec4 (&yr)[kHqRhsRbw], hvec4 (&y
 #pragma unroll
   for (int j = 0; j < kHqRhsRbw; ++j) {
     const int r0 = (wave + kHqRhsWaves * j) * 16;
+    __builtin_amdgcn_sched_barrier(0);
     if (r0 >= M) break;
     if (r0 + 15 < k) continue;
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) cacc_step(w, vh[j][kk].x, -vh[j][kk].y, yr[j][kk], yi[j][kk]);
+    for (int kk = 0; kk < 4; ++kk) {
+      const double2 v = hq_v_mask(vh[j][kk], M, k, nb, r0 + 4 * kk + lq, lr);
+      cacc_step(w, v.x, -v.y, yr[j][kk], yi[j][kk]);
+    }
   }
+  __builtin_amdgcn_sched_barrier(0);
+  // T of the panel (lane: T[4 kk + lq][lr]), in flight across the reduction
+  double2 tt[4];
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) tt[kk] = hld(Tp + (size_t)lr * kHqNb + 4 * kk + lq);
   // red: this panel's buffer of partial sums
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -370,13 +386,14 @@ __device__ __forceinline__ void hq_apply_panel(hvec4 (&yr)[kHqRhsRbw], hvec4 (&y
     wr[q] = a;
     wi[q] = b;
   }
+  // the first row block's V for step 3, in flight during u = T^H w
+  double2 vv[2][4];
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) vv[0][kk] = hq_v_raw(A, M, k, nb, wave * 16 + lr, 4 * kk + lq);
   Cacc u;
   cacc_zero(u);
 #pragma unroll
-  for (int kk = 0; kk < 4; ++kk) {
-    const double2 t = hld(Tp + (size_t)lr * kHqNb + 4 * kk + lq);  // T[4 kk + lq][lr]; A = conj(T)^T
-    cacc_step(u, t.x, -t.y, wr[kk], wi[kk]);
-  }
+  for (int kk = 0; kk < 4; ++kk) cacc_step(u, tt[kk].x, -tt[kk].y, wr[kk], wi[kk]);  // A = conj(T)^T
   double ur[4], ui[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -387,22 +404,29 @@ __device__ __forceinline__ void hq_apply_panel(hvec4 (&yr)[kHqRhsRbw], hvec4 (&y
 #pragma unroll
   for (int j = 0; j < kHqRhsRbw; ++j) {
     const int r0 = (wave + kHqRhsWaves * j) * 16;
+    __builtin_amdgcn_sched_barrier(0);
+    if (j + 1 < kHqRhsRbw) {
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk)
+        vv[(j + 1) & 1][kk] = hq_v_raw(A, M, k, nb, r0 + kHqRhsWaves * 16 + lr, 4 * kk + lq);
+    }
+    __builtin_amdgcn_sched_barrier(0);
     if (r0 >= M) break;
     if (r0 + 15 < k) continue;
-    double2 vv[4];
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk)
-      vv[kk] = r0 + lr < M ? hq_v(A, M, k, nb, r0 + lr, 4 * kk + lq) : make_double2(0.0, 0.0);
     Cacc d;
     cacc_zero(d);
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) cacc_step(d, vv[kk].x, vv[kk].y, ur[kk], ui[kk]);
+    for (int kk = 0; kk < 4; ++kk) {
+      const double2 v = hq_v_mask(vv[j & 1][kk], M, k, nb, r0 + lr, 4 * kk + lq);
+      cacc_step(d, v.x, v.y, ur[kk], ui[kk]);
+    }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       yr[j][q] -= d.t1[q] - d.t2[q];
       yi[j][q] -= d.t3[q] - d.t1[q] - d.t2[q];
     }
   }
+  __builtin_amdgcn_sched_barrier(0);
 }
 
 // One workgroup of eight waves per 16 right-hand-side columns of one layer.
