@@ -1104,6 +1104,16 @@ __global__ __launch_bounds__(kRhsWaves * 64) void gje_rhs_kernel(const GjeDesc* 
           } else {
             load_p(sidx, j, pb);
           }
+          // with every block's multipliers prefetched there are registers
+          // for the block's old values: read before the products at clamped
+          // indices (inside the tile; rows past n and columns past TC are
+          // not stored), so the wave does not wait on LDS row by row after
+          constexpr bool kEarly = PF == NBLK;
+          double2 yo[4];
+          if (kEarly) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) yo[q] = Y[min(r0 + lq + 4 * q, n - 1)][min(lr, TC - 1)];
+          }
 #pragma unroll
           for (int kk = 0; kk < 4; ++kk) {
             t1 = __builtin_amdgcn_mfma_f64_16x16x4f64(pb[kk].x, yb[kk].x, t1, 0, 0, 0);
@@ -1114,10 +1124,8 @@ __global__ __launch_bounds__(kRhsWaves * 64) void gje_rhs_kernel(const GjeDesc* 
           for (int q = 0; q < 4; ++q) {
             const int row = r0 + lq + 4 * q;
             if (cl && row < n) {
-              double2 y = Y[row][lr];
-              y.x -= t1[q] - t2[q];
-              y.y -= t3[q] - t1[q] - t2[q];
-              Y[row][lr] = y;
+              const double2 y = kEarly ? yo[q] : Y[row][lr];
+              Y[row][lr] = make_double2(y.x - (t1[q] - t2[q]), y.y - (t3[q] - t1[q] - t2[q]));
             }
           }
         }
