@@ -2276,37 +2276,43 @@ extern "C" mlh_status mlh_field(mlh_stack s, double theta, int64_t n_pts, const 
   hipStream_t st = s->ctx->stream;
   // ---- targets into the unit cell, by region (-1 above U, layers, I+1 below D)
   const double ph = d * s->k[0] * std::cos(theta);  // alpha = e^{i ph}
+  // (the interface heights cost a Fourier sum each, several per target:
+  // chunks of targets on the host threads)
   std::vector<int> reg(n_pts);
   std::vector<FieldTarget> tg(n_pts);
   std::vector<int64_t> count(I + 3, 0);
-  for (int64_t t = 0; t < n_pts; ++t) {
-    const double m = std::floor((x[t] + 0.5 * d) / d);
-    const double xc = x[t] - m * d;
-    int r;
-    if (y[t] >= s->yU) {
-      r = -1;
-    } else if (y[t] <= s->yD) {
-      r = I + 1;
-    } else {  // heights decrease with the interface index at every x
-      int lo = 0, hi = I;  // first interface below the point
-      while (lo < hi) {
-        const int mid = (lo + hi) / 2;
-        if (y[t] > s->curves[mid].height(xc))
-          hi = mid;
-        else
-          lo = mid + 1;
+  const int64_t chunk = 16384;
+  parallel_for((int)((n_pts + chunk - 1) / chunk), [&](int c) {
+    const int64_t t1 = std::min(n_pts, (int64_t)(c + 1) * chunk);
+    for (int64_t t = (int64_t)c * chunk; t < t1; ++t) {
+      const double m = std::floor((x[t] + 0.5 * d) / d);
+      const double xc = x[t] - m * d;
+      int r;
+      if (y[t] >= s->yU) {
+        r = -1;
+      } else if (y[t] <= s->yD) {
+        r = I + 1;
+      } else {  // heights decrease with the interface index at every x
+        int lo = 0, hi = I;  // first interface below the point
+        while (lo < hi) {
+          const int mid = (lo + hi) / 2;
+          if (y[t] > s->curves[mid].height(xc))
+            hi = mid;
+          else
+            lo = mid + 1;
+        }
+        r = lo;
       }
-      r = lo;
+      reg[t] = r;
+      FieldTarget& T = tg[t];
+      T.x = xc;
+      T.y = y[t];
+      T.ph_re = std::cos(m * ph);
+      T.ph_im = std::sin(m * ph);
+      T.idx = t;
     }
-    reg[t] = r;
-    FieldTarget& T = tg[t];
-    T.x = xc;
-    T.y = y[t];
-    T.ph_re = std::cos(m * ph);
-    T.ph_im = std::sin(m * ph);
-    T.idx = t;
-    ++count[r + 1];
-  }
+  });
+  for (int64_t t = 0; t < n_pts; ++t) ++count[reg[t] + 1];
   std::vector<int64_t> start(I + 4, 0);
   for (int r = 0; r < I + 3; ++r) start[r + 1] = start[r] + count[r];
   // order: by region, and inside a region by the cells of a grid of spacing
