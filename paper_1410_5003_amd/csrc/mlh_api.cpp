@@ -1044,32 +1044,39 @@ struct EvTimer {
   hipStream_t st;
   std::vector<hipEvent_t> ev;
   std::vector<double*> dst;
-  std::vector<int> pairs;  // index of start event per interval
+  std::vector<int> pairs;     // index of start event per interval
+  hipError_t err = hipSuccess;  // the first failure; collect() returns it
+  void keep(hipError_t e) {
+    if (err == hipSuccess) err = e;
+  }
+  void record() {
+    hipEvent_t e = nullptr;
+    const hipError_t ce = hipEventCreate(&e);
+    keep(ce);
+    if (ce == hipSuccess) keep(hipEventRecord(e, st));
+    ev.push_back(e);
+  }
   void begin(double* acc) {
-    hipEvent_t e;
-    hipEventCreate(&e);
-    hipEventRecord(e, st);
     pairs.push_back((int)ev.size());
-    ev.push_back(e);
     dst.push_back(acc);
+    record();
   }
-  void end() {
-    hipEvent_t e;
-    hipEventCreate(&e);
-    hipEventRecord(e, st);
-    ev.push_back(e);
-  }
-  void collect() {
-    hipStreamSynchronize(st);
-    for (size_t i = 0; i < pairs.size(); ++i) {
+  void end() { record(); }
+  hipError_t collect() {
+    keep(hipStreamSynchronize(st));
+    for (size_t i = 0; i < pairs.size() && err == hipSuccess; ++i) {
       float ms = 0.f;
-      hipEventElapsedTime(&ms, ev[pairs[i]], ev[pairs[i] + 1]);
+      keep(hipEventElapsedTime(&ms, ev[pairs[i]], ev[pairs[i] + 1]));
       *dst[i] += ms;
     }
-    for (auto e : ev) hipEventDestroy(e);
+    for (auto e : ev)
+      if (e) keep(hipEventDestroy(e));
     ev.clear();
     dst.clear();
     pairs.clear();
+    const hipError_t r = err;
+    err = hipSuccess;
+    return r;
   }
 };
 }  // namespace
@@ -1291,8 +1298,9 @@ static mlh_status solve_systems(Runner& RN, mlh_ctx ctx, const mlh_tuning& tune,
   } else {
     if (need > RN.wbytes) {
       if (RN.gexec) {
-        hipGraphExecDestroy(RN.gexec);
+        const hipError_t de = hipGraphExecDestroy(RN.gexec);
         RN.gexec = nullptr;
+        HIP_TRY(de);
       }
       if (RN.wmem) HIP_TRY(hipFree(RN.wmem));
       RN.wmem = nullptr;
@@ -2096,8 +2104,9 @@ static mlh_status solve_systems(Runner& RN, mlh_ctx ctx, const mlh_tuning& tune,
       }
       if (!(RN.gexec && RN.g_sig == sig)) {
         if (RN.gexec) {
-          hipGraphExecDestroy(RN.gexec);
+          const hipError_t de = hipGraphExecDestroy(RN.gexec);
           RN.gexec = nullptr;
+          HIP_TRY(de);
         }
         if (!RN.cap_stream) HIP_TRY(hipStreamCreateWithFlags(&RN.cap_stream, hipStreamNonBlocking));
         // the capture stream waits for the descriptor upload
@@ -2106,21 +2115,25 @@ static mlh_status solve_systems(Runner& RN, mlh_ctx ctx, const mlh_tuning& tune,
         HIP_TRY(hipEventRecord(up, st));
         HIP_TRY(hipStreamWaitEvent(RN.cap_stream, up, 0));
         HIP_TRY(hipStreamSynchronize(RN.cap_stream));
-        hipEventDestroy(up);
+        HIP_TRY(hipEventDestroy(up));
         hipGraph_t g = nullptr;
         HIP_TRY(hipStreamBeginCapture(RN.cap_stream, hipStreamCaptureModeThreadLocal));
         mlh_status ls_ = launch_all(RN.cap_stream, T);
         hipError_t ce = hipStreamEndCapture(RN.cap_stream, &g);
-        if (ls_ != MLH_OK) return ls_;
-        if (ce != hipSuccess) return fail(MLH_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
+        if (ls_ != MLH_OK || ce != hipSuccess) {
+          if (g) (void)hipGraphDestroy(g);  // the error already being reported is the one that matters
+          if (ls_ != MLH_OK) return ls_;
+          return fail(MLH_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
+        }
         hipError_t ie = hipGraphInstantiate(&RN.gexec, g, nullptr, nullptr, 0);
-        hipGraphDestroy(g);
+        const hipError_t gd = hipGraphDestroy(g);
         if (ie != hipSuccess) return fail(MLH_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(ie));
+        HIP_TRY(gd);
         RN.g_sig = sig;
       }
       HIP_TRY(hipGraphLaunch(RN.gexec, st));
     }
-    if (prof) T.collect();
+    if (prof) HIP_TRY(T.collect());
     if (stop_phase != 0) {
       if (inspect) {
         inspect->dbg_R = V[0].W[0];
@@ -3633,11 +3646,14 @@ extern "C" mlh_status mlh_debug_hankel(mlh_ctx ctx, int32_t n, const double* x, 
   HIP_TRY(hipSetDevice(ctx->device));
   double* d = nullptr;
   HIP_TRY(hipMalloc((void**)&d, sizeof(double) * 5 * n));
-  hipMemcpy(d, x, sizeof(double) * n, hipMemcpyHostToDevice);
-  launch_hankel_eval(d, d + n, n, ctx->stream);
-  hipError_t e = hipStreamSynchronize(ctx->stream);
+  hipError_t e = hipMemcpy(d, x, sizeof(double) * n, hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    launch_hankel_eval(d, d + n, n, ctx->stream);
+    e = hipStreamSynchronize(ctx->stream);
+  }
   if (e == hipSuccess) e = hipMemcpy(out, d + n, sizeof(double) * 4 * n, hipMemcpyDeviceToHost);
-  hipFree(d);
+  const hipError_t fe = hipFree(d);
+  if (e == hipSuccess) e = fe;
   if (e != hipSuccess) return fail(MLH_E_DEVICE, hipGetErrorString(e));
   return MLH_OK;
 }
@@ -3681,7 +3697,8 @@ extern "C" mlh_status mlh_debug_zgemm(mlh_ctx ctx, int32_t m, int32_t n, int32_t
     e = hipStreamSynchronize(ctx->stream);
   }
   if (e == hipSuccess) e = hipMemcpy(C, dC, cbytes(nc), hipMemcpyDeviceToHost);
-  hipFree(d);
+  const hipError_t fe = hipFree(d);
+  if (e == hipSuccess) e = fe;
   if (e != hipSuccess) return fail(MLH_E_DEVICE, hipGetErrorString(e));
   return MLH_OK;
 }
@@ -3766,7 +3783,7 @@ extern "C" mlh_status mlh_profile_solve(mlh_stack s, int32_t n_angles, const dou
   launch_fill(s->d_fill, s->n_fill, s->fill_tiles, st);
   T.end();
   HIP_TRY(hipGetLastError());
-  T.collect();
+  HIP_TRY(T.collect());
   const int nK = 2 * s->K + 1;
   std::vector<double> aU((size_t)2 * nK * n_angles), aD((size_t)2 * nK * n_angles);
   std::vector<int> ord((size_t)nK * n_angles);
@@ -3777,9 +3794,11 @@ extern "C" mlh_status mlh_profile_solve(mlh_stack s, int32_t n_angles, const dou
   HIP_TRY(hipEventRecord(e1, st));
   HIP_TRY(hipEventSynchronize(e1));
   float ms = 0;
-  hipEventElapsedTime(&ms, e0, e1);
+  hipError_t te = hipEventElapsedTime(&ms, e0, e1);
   out->total_ms = ms;
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  const hipError_t d0 = hipEventDestroy(e0), d1 = hipEventDestroy(e1);
+  if (r != MLH_OK) return r;
+  if (te == hipSuccess) te = d0 != hipSuccess ? d0 : d1;
+  HIP_TRY(te);
   return r;
 }
