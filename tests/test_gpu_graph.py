@@ -27,3 +27,27 @@ def test_graph_replay_matches_oracle_for_new_angles():
     g2 = st.solve([-1.1])
     assert np.array_equal(g1.aU, g2.aU) and np.array_equal(g1.aD, g2.aD)
     st.close()
+
+
+def test_profiled_solve_times_its_phases_and_leaves_the_results_alone():
+    """The per-kernel profile runs the solve's launches one at a time, each
+    bracketed by HIP events, inside a bracket of its own: every phase of a
+    4-interface stack has a finite positive time, the phases add up to no
+    more than the total, and the graph path's amplitudes are unchanged."""
+    import paper_1410_5003_amd as mlh
+    ctx = context()
+    desc = workloads.small_stack(I=4)
+    st = mlh.Stack(ctx, desc)
+    th = [-0.4, -1.1]
+    g1 = st.solve(th)
+    p = st.profile_solve(th)
+    for k in ("fill_self_ms", "fill_alpert_ms", "fill_pairs_ms", "ls_panel_ms", "ls_rhs_ms", "schur_ms",
+              "bragg_ms", "total_ms"):
+        assert np.isfinite(p[k]) and p[k] > 0, k
+    parts = sum(v for k, v in p.items() if k.endswith("_ms") and k != "total_ms")
+    assert parts <= p["total_ms"]
+    q = st.profile_step(-0.4)
+    assert np.isfinite(q["total_ms"]) and q["total_ms"] > 0
+    g2 = st.solve(th)
+    assert np.array_equal(g1.aU, g2.aU) and np.array_equal(g1.aD, g2.aD)
+    st.close()
