@@ -47,23 +47,36 @@ __device__ inline double wave_sum(double v) {
 // batched complex GEMM C = C0 + alpha (A B + A2 B2): one workgroup of four
 // wavefronts per kGemmTile x kGemmTile tile of C, each wavefront a 32 x 32
 // quarter as 2 x 2 blocks of 16 x 16 on the FP64 matrix cores.  K runs in
-// slabs of 16 staged in LDS; the next slab is loaded into registers while
-// the current one is multiplied.  A complex product takes three real ones
+// slabs of 8 in two LDS buffers; the next slab goes from global memory
+// straight into the other buffer while the current one is multiplied (one
+// barrier per slab).  A complex product takes three real ones
 // (T1 = Ar Br, T2 = Ai Bi, T3 = (Ar + Ai)(Br + Bi); re = T1 - T2,
 // im = T3 - T1 - T2), a quarter fewer matrix-core operations than four.
 // ---------------------------------------------------------------------------
-constexpr int kGK = 16;
-static_assert(kGemmTile == 64 && kGemmTile * kGK == 4 * 256, "slab staging: A element e = tid + 256 q has k = wave + 4 q");
+constexpr int kGK = 8;  // k per slab
+static_assert(kGemmTile == 64 && kGK == 8, "slab loads: one A instruction per k, one B instruction per 8 columns");
 
-typedef double GemmSlab[kGK][kGemmTile + 1];
+// The slab buffers, two of each, filled straight from global memory by
+// 16-byte global-to-LDS loads (lane i of an instruction lands at base +
+// 16 i), so the next slab needs no staging registers: A as [k][row] (one
+// instruction per k: 64 consecutive rows), B as [col][k ^ (col & 7)] (one
+// instruction per 8 columns x 8 k, each column's 128 bytes read in one
+// piece; the XOR puts the operand reads of 16 consecutive columns on
+// distinct banks).
+typedef double2 SlabA[kGK][kGemmTile];
+typedef double2 SlabB[kGemmTile][kGK];
+typedef const void __attribute__((address_space(1)))* gvoid_p;
+typedef void __attribute__((address_space(3)))* lvoid_p;
+__device__ __forceinline__ void lds_load16(const cplx* src, double2* lds_base) {
+  __builtin_amdgcn_global_load_lds((gvoid_p)src, (lvoid_p)lds_base, 16, 0, 0);
+}
 
 // One tile.  kFull: the tile lies wholly inside C, so no 16 x 16 block is
-// skipped and the four k-steps of a slab have no branch between their
-// products (the LDS reads of one k-step can then be scheduled among the
-// products of the one before); edge tiles take the checked form.
+// skipped and the k-steps of a slab have no branch between their products;
+// edge tiles take the checked form.
 template <bool kFull>
-__device__ __forceinline__ void zgemm_tile(const GemmDesc& G, int row0, int col0, GemmSlab& Ar, GemmSlab& Ai,
-                                           GemmSlab& Br, GemmSlab& Bi) {
+__device__ __forceinline__ void zgemm_tile(const GemmDesc& G, int row0, int col0, SlabA& a0, SlabB& b0, SlabA& a1,
+                                           SlabB& b1) {
   const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int lr = lane & 15, lq = lane >> 4;
   const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
@@ -81,78 +94,81 @@ __device__ __forceinline__ void zgemm_tile(const GemmDesc& G, int row0, int col0
       t2[b][c] = dvec4{0, 0, 0, 0};
       t3[b][c] = dvec4{0, 0, 0, 0};
     }
-  // slab staging: thread tid holds A elements (r, kk) = (e % 64, e / 64) and
-  // B elements (kk, c) = (e % kGK, e / kGK) for e = tid + 256 q
-  constexpr int kPer = kGemmTile * kGK / 256;
-  double2 pa[kPer], pb[kPer];
-  // the descriptor's fields once, in registers; every address below is
-  // formed from clamped indices and a pointer select, with no branch
   const cplx* const A1 = G.A;
   const cplx* const A2 = G.A2;
   const cplx* const B1 = G.B;
   const cplx* const B2 = G.B2;
   const int lda = G.lda, lda2 = G.lda2, ldb = G.ldb, ldb2 = G.ldb2;
-  // Raw loads, no select: a select right after a load makes the wave wait
-  // for it there, before the products of the current slab.  Rows of A past
-  // m and columns of B past n read clamped (finite) copies that reach only
-  // rows and columns of C that are never stored; k past K is zeroed in A
-  // when the slab is written to LDS (k of A element e is k0 + wave + 4 q,
-  // uniform over the wave).
-  auto load_slab = [&](int k0) {
+  // Slab k0 into (Sa, Sb): wave w loads A's k rows w and w + 4 and B's
+  // columns 16 w .. 16 w + 15.  Indices are clamped: rows of A past m and
+  // columns of B past n only reach entries of C that are not stored, and k
+  // past K is zeroed in A once the slab has landed.
+  const int arow = min(row0 + lane, m - 1);
+  auto issue = [&](int k0, SlabA& Sa, SlabB& Sb) {
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int e = tid + 256 * q;
-      {
-        const int gr = row0 + e % kGemmTile, gk = k0 + e / kGemmTile;
-        const int r = min(gr, m - 1), kc = min(gk, K - 1);
-        const cplx* src = kc < K1 ? A1 + (size_t)kc * lda + r : A2 + (size_t)(kc - K1) * lda2 + r;
-        pa[q] = ldc(src);
-      }
-      {
-        const int gk = k0 + e % kGK, gc = col0 + e / kGK;
-        const int cc = min(gc, n - 1), kc = min(gk, K - 1);
-        const cplx* src = kc < K1 ? B1 + (size_t)cc * ldb + kc : B2 + (size_t)cc * ldb2 + (kc - K1);
-        pb[q] = ldc(src);
-      }
+    for (int h = 0; h < 2; ++h) {
+      const int kl = wave + 4 * h;
+      const int kc = min(k0 + kl, K - 1);
+      const cplx* src = kc < K1 ? A1 + (size_t)kc * lda + arow : A2 + (size_t)(kc - K1) * lda2 + arow;
+      lds_load16(src, &Sa[kl][0]);
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int cl = 16 * wave + 8 * h + (lane >> 3);
+      const int kk = (lane & 7) ^ (cl & 7);
+      const int cc = min(col0 + cl, n - 1), kc = min(k0 + kk, K - 1);
+      const cplx* src = kc < K1 ? B1 + (size_t)cc * ldb + kc : B2 + (size_t)cc * ldb2 + (kc - K1);
+      lds_load16(src, &Sb[16 * wave + 8 * h][0]);
     }
   };
-  if (K > 0) load_slab(0);
-  for (int k0 = 0; k0 < K; k0 += kGK) {
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int e = tid + 256 * q;
-      const bool kin = k0 + wave + 4 * q < K;
-      Ar[e / kGemmTile][e % kGemmTile] = kin ? pa[q].x : 0.0;
-      Ai[e / kGemmTile][e % kGemmTile] = kin ? pa[q].y : 0.0;
-      Br[e % kGK][e / kGK] = pb[q].x;
-      Bi[e % kGK][e / kGK] = pb[q].y;
-    }
-    __syncthreads();
-    if (k0 + kGK < K) load_slab(k0 + kGK);
+  auto slab = [&](const SlabA& Sa, const SlabB& Sb) {
 #pragma unroll
     for (int ks = 0; ks < kGK; ks += 4) {
       const int ka = ks + lq;
       double ar[2], ai[2], as[2], br[2], bi[2], bs[2];
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
-        ar[b] = Ar[ka][wm + 16 * b + lr];
-        ai[b] = Ai[ka][wm + 16 * b + lr];
-        as[b] = ar[b] + ai[b];
-        br[b] = Br[ka][wn + 16 * b + lr];
-        bi[b] = Bi[ka][wn + 16 * b + lr];
-        bs[b] = br[b] + bi[b];
+        const double2 va = Sa[ka][wm + 16 * b + lr];
+        const int col = wn + 16 * b + lr;
+        const double2 vb = Sb[col][ka ^ (col & 7)];
+        ar[b] = va.x;
+        ai[b] = va.y;
+        as[b] = va.x + va.y;
+        br[b] = vb.x;
+        bi[b] = vb.y;
+        bs[b] = vb.x + vb.y;
       }
 #pragma unroll
       for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-          if (!(rin[b] && cin[c])) continue;
+          if (!kFull && !(rin[b] && cin[c])) continue;
           t1[b][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[b], br[c], t1[b][c], 0, 0, 0);
           t2[b][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[b], bi[c], t2[b][c], 0, 0, 0);
           t3[b][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(as[b], bs[c], t3[b][c], 0, 0, 0);
         }
     }
-    __syncthreads();
+  };
+  // slab k0 has landed in (Sa, Sb): zero A's k past K on the last slab,
+  // start the next slab's loads into (Na, Nb), multiply
+  auto step = [&](int k0, SlabA& Sa, SlabB& Sb, SlabA& Na, SlabB& Nb) {
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of the slab have landed
+    __syncthreads();                // every wave's have; every wave is done with (Na, Nb)
+    if (k0 + kGK > K) {             // uniform over the workgroup
+      for (int e = tid; e < kGK * kGemmTile; e += 256)
+        if (k0 + e / kGemmTile >= K) Sa[e / kGemmTile][e % kGemmTile] = make_double2(0.0, 0.0);
+      __syncthreads();
+    }
+    if (k0 + kGK < K) issue(k0 + kGK, Na, Nb);
+    slab(Sa, Sb);
+  };
+  // slabs in pairs, so that each buffer is a named array at every use (no
+  // select between the two for the loads' destinations or the reads)
+  if (K > 0) issue(0, a0, b0);
+  for (int k0 = 0; k0 < K; k0 += 2 * kGK) {
+    step(k0, a0, b0, a1, b1);
+    if (k0 + kGK >= K) break;
+    step(k0 + kGK, a1, b1, a0, b0);
   }
   // C0 first, every load in flight at once (clamped addresses), then C
   const cplx* const C0 = G.C0;
@@ -192,11 +208,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void z
   const GemmDesc& G = descs[find_tile(descs, ndesc, tile)];
   const int lt = tile - G.tile_begin;
   const int row0 = (lt % G.tiles_m) * kGemmTile, col0 = (lt / G.tiles_m) * kGemmTile;
-  __shared__ GemmSlab Ar, Ai, Br, Bi;
+  __shared__ SlabA a0, a1;
+  __shared__ SlabB b0, b1;
   if (row0 + kGemmTile <= G.m && col0 + kGemmTile <= G.n)  // uniform over the workgroup
-    zgemm_tile<true>(G, row0, col0, Ar, Ai, Br, Bi);
+    zgemm_tile<true>(G, row0, col0, a0, b0, a1, b1);
   else
-    zgemm_tile<false>(G, row0, col0, Ar, Ai, Br, Bi);
+    zgemm_tile<false>(G, row0, col0, a0, b0, a1, b1);
 }
 
 // ---------------------------------------------------------------------------
