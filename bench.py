@@ -182,7 +182,7 @@ MEASURED_TRAFFIC = {
     # (the panel launches also carry the block-system assembly)
     ("config2_resolved", "hq_panel_kernel"): ("kernels_hq.hip", "5c57e8752f1e", 44997.3, 16454.9),
     # the 1000-interface, 100-angle sweep (counters on zgemm_kernel dispatches only)
-    ("config3_resolved", "zgemm_kernel"): ("kernels_linalg.hip", "e2d30a7a1480", 104649255.9, 7694294.1),
+    ("config3_resolved", "zgemm_kernel"): ("kernels_linalg.hip", "8a7b2ec360d9", 105633771.4, 7694270.4),
 }
 
 
