@@ -177,10 +177,6 @@ def algorithmic_work(desc):
 # averaged over every dispatch of the run.  An entry counts only while its
 # kernel source is the one the counters were taken on (SHA-1 prefix).
 MEASURED_TRAFFIC = {
-    # the least-squares kernels, on the 50-interface stack
-    ("config2_resolved", "hq_rhs_kernel"): ("kernels_hq.hip", "5c57e8752f1e", 518092.2, 105209.0),
-    # (the panel launches also carry the block-system assembly)
-    ("config2_resolved", "hq_panel_kernel"): ("kernels_hq.hip", "5c57e8752f1e", 44997.3, 16454.9),
     # the 1000-interface, 100-angle sweep (counters on zgemm_kernel dispatches only)
     ("config3_resolved", "zgemm_kernel"): ("kernels_linalg.hip", "8a7b2ec360d9", 105633771.4, 7694270.4),
 }
