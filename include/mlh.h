@@ -244,12 +244,16 @@ mlh_status mlh_profile_solve(mlh_stack s, int32_t n_angles, const double* theta,
  *   asm_in_panels    1: the block-system assembly runs inside the
  *                    least-squares panel launches, on the compute units
  *                    they leave idle; 0: in a launch of its own.
- * A new stack starts with {300, 3, 16, 1}. */
+ *   gemm_slab_k      depth of the K slabs of the complex GEMMs (Schur
+ *                    updates and cyclic-reduction products), staged in two
+ *                    LDS buffers: 8 (32 KiB a workgroup) or 16 (64 KiB).
+ * A new stack starts with {300, 3, 16, 1, 8}. */
 typedef struct {
   int32_t rhs_in_step_pct;
   int32_t ls_row_blocks;
   int32_t gje_rhs_cols;
   int32_t asm_in_panels;
+  int32_t gemm_slab_k;
 } mlh_tuning;
 
 /* Read or replace the stack's launch choices.  set: MLH_E_INVALID_ARG for a
@@ -378,7 +382,7 @@ mlh_status mlh_batch_solve(mlh_batch b, const double* theta, int32_t refill, int
                            double* aD, int32_t* orders, double* flux_err, double* stack_ms);
 
 /* Launch choices of a batch (the fields of mlh_tuning; a new batch starts
- * with {300, 3, 16, 1}), and their autotune: mlh_stack_autotune's search,
+ * with {300, 3, 16, 1, 8}), and their autotune: mlh_stack_autotune's search,
  * timing whole mlh_batch_solve calls (no refill) of the angles theta[s]. */
 mlh_status mlh_batch_get_tuning(mlh_batch b, mlh_tuning* out);
 mlh_status mlh_batch_set_tuning(mlh_batch b, const mlh_tuning* t);

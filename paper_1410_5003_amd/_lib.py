@@ -59,7 +59,7 @@ class mlh_profile(C.Structure):
 
 class mlh_tuning(C.Structure):
     _fields_ = [("rhs_in_step_pct", C.c_int32), ("ls_row_blocks", C.c_int32), ("gje_rhs_cols", C.c_int32),
-                ("asm_in_panels", C.c_int32)]
+                ("asm_in_panels", C.c_int32), ("gemm_slab_k", C.c_int32)]
 
 
 _lib = None

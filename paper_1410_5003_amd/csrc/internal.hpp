@@ -129,7 +129,7 @@ void launch_self(const SelfJob* d_jobs, int njobs, int total_tiles, int a_excl, 
 void launch_alpert(const AlpertJob* d_jobs, int njobs, int total_blocks, int a_excl, hipStream_t st,
                    bool dk = false);
 void launch_assemble(const AsmJob* d_jobs, int njobs, int total_tiles, hipStream_t st);
-void launch_gemm(const GemmDesc* d_desc, int ndesc, int total_tiles, hipStream_t st);
+void launch_gemm(const GemmDesc* d_desc, int ndesc, int total_tiles, hipStream_t st, int slab_k = 8);
 void launch_hankel_eval(const double* x, double* out, int n, hipStream_t st);
 
 }  // namespace mlh

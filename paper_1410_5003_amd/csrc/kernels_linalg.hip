@@ -47,24 +47,25 @@ __device__ inline double wave_sum(double v) {
 // batched complex GEMM C = C0 + alpha (A B + A2 B2): one workgroup of four
 // wavefronts per kGemmTile x kGemmTile tile of C, each wavefront a 32 x 32
 // quarter as 2 x 2 blocks of 16 x 16 on the FP64 matrix cores.  K runs in
-// slabs of 8 in two LDS buffers; the next slab goes from global memory
+// slabs of 8 or 16 in two LDS buffers; the next slab goes from global memory
 // straight into the other buffer while the current one is multiplied (one
 // barrier per slab).  A complex product takes three real ones
 // (T1 = Ar Br, T2 = Ai Bi, T3 = (Ar + Ai)(Br + Bi); re = T1 - T2,
 // im = T3 - T1 - T2), a quarter fewer matrix-core operations than four.
 // ---------------------------------------------------------------------------
-constexpr int kGK = 8;  // k per slab
-static_assert(kGemmTile == 64 && kGK == 8, "slab loads: one A instruction per k, one B instruction per 8 columns");
+static_assert(kGemmTile == 64, "slab loads: one A instruction per k of 64 rows");
 
-// The slab buffers, two of each, filled straight from global memory by
-// 16-byte global-to-LDS loads (lane i of an instruction lands at base +
-// 16 i), so the next slab needs no staging registers: A as [k][row] (one
-// instruction per k: 64 consecutive rows), B as [col][k ^ (col & 7)] (one
-// instruction per 8 columns x 8 k, each column's 128 bytes read in one
-// piece; the XOR puts the operand reads of 16 consecutive columns on
-// distinct banks).
-typedef double2 SlabA[kGK][kGemmTile];
-typedef double2 SlabB[kGemmTile][kGK];
+// The slab buffers, two of each, kGK deep (8 or 16: a launch choice),
+// filled straight from global memory by 16-byte global-to-LDS loads (lane i
+// of an instruction lands at base + 16 i), so the next slab needs no staging
+// registers: A as [k][row] (one instruction per k: 64 consecutive rows), B
+// as [col][k ^ (col mod kGK)] (one instruction per 64 / kGK columns x kGK
+// k, each column's slab read in one piece; the XOR puts the operand reads
+// of consecutive columns on distinct banks).
+template <int kGK>
+using SlabA = double2[kGK][kGemmTile];
+template <int kGK>
+using SlabB = double2[kGemmTile][kGK];
 typedef const void __attribute__((address_space(1)))* gvoid_p;
 typedef void __attribute__((address_space(3)))* lvoid_p;
 __device__ __forceinline__ void lds_load16(const cplx* src, double2* lds_base) {
@@ -74,9 +75,11 @@ __device__ __forceinline__ void lds_load16(const cplx* src, double2* lds_base) {
 // One tile.  kFull: the tile lies wholly inside C, so no 16 x 16 block is
 // skipped and the k-steps of a slab have no branch between their products;
 // edge tiles take the checked form.
-template <bool kFull>
-__device__ __forceinline__ void zgemm_tile(const GemmDesc& G, int row0, int col0, SlabA& a0, SlabB& b0, SlabA& a1,
-                                           SlabB& b1) {
+template <bool kFull, int kGK>
+__device__ __forceinline__ void zgemm_tile(const GemmDesc& G, int row0, int col0, SlabA<kGK>& a0, SlabB<kGK>& b0,
+                                           SlabA<kGK>& a1, SlabB<kGK>& b1) {
+  static_assert(kGK == 8 || kGK == 16, "slab depth");
+  constexpr int kBCols = kGemmTile / kGK;  // B columns per load instruction
   const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
   const int lr = lane & 15, lq = lane >> 4;
   const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
@@ -99,29 +102,29 @@ __device__ __forceinline__ void zgemm_tile(const GemmDesc& G, int row0, int col0
   const cplx* const B1 = G.B;
   const cplx* const B2 = G.B2;
   const int lda = G.lda, lda2 = G.lda2, ldb = G.ldb, ldb2 = G.ldb2;
-  // Slab k0 into (Sa, Sb): wave w loads A's k rows w and w + 4 and B's
+  // Slab k0 into (Sa, Sb): wave w loads A's k rows w, w + 4, ... and B's
   // columns 16 w .. 16 w + 15.  Indices are clamped: rows of A past m and
   // columns of B past n only reach entries of C that are not stored, and k
   // past K is zeroed in A once the slab has landed.
   const int arow = min(row0 + lane, m - 1);
-  auto issue = [&](int k0, SlabA& Sa, SlabB& Sb) {
+  auto issue = [&](int k0, SlabA<kGK>& Sa, SlabB<kGK>& Sb) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < kGK / 4; ++h) {
       const int kl = wave + 4 * h;
       const int kc = min(k0 + kl, K - 1);
       const cplx* src = kc < K1 ? A1 + (size_t)kc * lda + arow : A2 + (size_t)(kc - K1) * lda2 + arow;
       lds_load16(src, &Sa[kl][0]);
     }
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int cl = 16 * wave + 8 * h + (lane >> 3);
-      const int kk = (lane & 7) ^ (cl & 7);
+    for (int h = 0; h < kGK / 4; ++h) {
+      const int cl = 16 * wave + kBCols * h + lane / kGK;
+      const int kk = (lane % kGK) ^ (cl % kGK);
       const int cc = min(col0 + cl, n - 1), kc = min(k0 + kk, K - 1);
       const cplx* src = kc < K1 ? B1 + (size_t)cc * ldb + kc : B2 + (size_t)cc * ldb2 + (kc - K1);
-      lds_load16(src, &Sb[16 * wave + 8 * h][0]);
+      lds_load16(src, &Sb[16 * wave + kBCols * h][0]);
     }
   };
-  auto slab = [&](const SlabA& Sa, const SlabB& Sb) {
+  auto slab = [&](const SlabA<kGK>& Sa, const SlabB<kGK>& Sb) {
 #pragma unroll
     for (int ks = 0; ks < kGK; ks += 4) {
       const int ka = ks + lq;
@@ -130,7 +133,7 @@ __device__ __forceinline__ void zgemm_tile(const GemmDesc& G, int row0, int col0
       for (int b = 0; b < 2; ++b) {
         const double2 va = Sa[ka][wm + 16 * b + lr];
         const int col = wn + 16 * b + lr;
-        const double2 vb = Sb[col][ka ^ (col & 7)];
+        const double2 vb = Sb[col][ka ^ (col % kGK)];
         ar[b] = va.x;
         ai[b] = va.y;
         as[b] = va.x + va.y;
@@ -151,7 +154,7 @@ __device__ __forceinline__ void zgemm_tile(const GemmDesc& G, int row0, int col0
   };
   // slab k0 has landed in (Sa, Sb): zero A's k past K on the last slab,
   // start the next slab's loads into (Na, Nb), multiply
-  auto step = [&](int k0, SlabA& Sa, SlabB& Sb, SlabA& Na, SlabB& Nb) {
+  auto step = [&](int k0, SlabA<kGK>& Sa, SlabB<kGK>& Sb, SlabA<kGK>& Na, SlabB<kGK>& Nb) {
     __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of the slab have landed
     __syncthreads();                // every wave's have; every wave is done with (Na, Nb)
     if (k0 + kGK > K) {             // uniform over the workgroup
@@ -203,17 +206,18 @@ __device__ __forceinline__ void zgemm_tile(const GemmDesc& G, int row0, int col0
   }
 }
 
+template <int kGK>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void zgemm_kernel(const GemmDesc* __restrict__ descs, int ndesc, int tile0) {
   const int tile = tile0 + (int)blockIdx.x;
   const GemmDesc& G = descs[find_tile(descs, ndesc, tile)];
   const int lt = tile - G.tile_begin;
   const int row0 = (lt % G.tiles_m) * kGemmTile, col0 = (lt / G.tiles_m) * kGemmTile;
-  __shared__ SlabA a0, a1;
-  __shared__ SlabB b0, b1;
+  __shared__ SlabA<kGK> a0, a1;
+  __shared__ SlabB<kGK> b0, b1;
   if (row0 + kGemmTile <= G.m && col0 + kGemmTile <= G.n)  // uniform over the workgroup
-    zgemm_tile<true>(G, row0, col0, a0, b0, a1, b1);
+    zgemm_tile<true, kGK>(G, row0, col0, a0, b0, a1, b1);
   else
-    zgemm_tile<false>(G, row0, col0, a0, b0, a1, b1);
+    zgemm_tile<false, kGK>(G, row0, col0, a0, b0, a1, b1);
 }
 
 // ---------------------------------------------------------------------------
@@ -346,10 +350,14 @@ __global__ __launch_bounds__(512) void bragg_kernel(const AngleDesc* __restrict_
   }
 }
 
-void launch_gemm(const GemmDesc* d_desc, int ndesc, int total_tiles, hipStream_t st) {
-  for (int t0 = 0; t0 < total_tiles; t0 += kMaxLaunchBlocks)
-    hipLaunchKernelGGL(zgemm_kernel, dim3(std::min(kMaxLaunchBlocks, total_tiles - t0)), dim3(256), 0, st, d_desc,
-                       ndesc, t0);
+void launch_gemm(const GemmDesc* d_desc, int ndesc, int total_tiles, hipStream_t st, int slab_k) {
+  for (int t0 = 0; t0 < total_tiles; t0 += kMaxLaunchBlocks) {
+    const dim3 grid(std::min(kMaxLaunchBlocks, total_tiles - t0));
+    if (slab_k == 16)
+      hipLaunchKernelGGL(zgemm_kernel<16>, grid, dim3(256), 0, st, d_desc, ndesc, t0);
+    else
+      hipLaunchKernelGGL(zgemm_kernel<8>, grid, dim3(256), 0, st, d_desc, ndesc, t0);
+  }
 }
 __global__ void stamp_kernel(unsigned long long* p) {
   if (threadIdx.x == 0) p[0] = (unsigned long long)wall_clock64();

@@ -363,7 +363,7 @@ struct mlh_stack_s {
   // device scratch of mlh_adjoint, kept between calls and grown on demand:
   // its buffers, their job tables, a shape-gradient pass, its contractions
   std::pair<char*, size_t> adj_buf[4] = {};
-  mlh_tuning tune{300, 3, 16, 1};  // launch choices (mlh_stack_set_tuning / mlh_stack_autotune)
+  mlh_tuning tune{300, 3, 16, 1, 8};  // launch choices (mlh_stack_set_tuning / mlh_stack_autotune)
   double flux_tol = 0.0;           // > 0: a solve whose flux error exceeds it reports MLH_E_ACCURACY
   int I = 0, P = 0, Mw = 0, Mud = 0, K = 0, nK = 0;
   double d = 0, yU = 0, yD = 0, R = 0, mu = 1e-14;
@@ -1940,7 +1940,7 @@ static mlh_status solve_systems(Runner& RN, mlh_ctx ctx, const mlh_tuning& tune,
       }
       if (stop_phase == 0 || stop_phase >= 3) {
         tb(prof ? &prof->schur_ms : nullptr);
-        launch_gemm(reinterpret_cast<GemmDesc*>(dbase + o_gs), (int)gs.size(), gtiles, ls);
+        launch_gemm(reinterpret_cast<GemmDesc*>(dbase + o_gs), (int)gs.size(), gtiles, ls, tune.gemm_slab_k);
         te();
         if (prof) {
           prof->n_schur_gemm++;
@@ -2048,7 +2048,8 @@ static mlh_status solve_systems(Runner& RN, mlh_ctx ctx, const mlh_tuning& tune,
           }
           if (!lv.upd.empty()) {
             tb(prof ? &prof->sweep_gemm_ms : nullptr);
-            launch_gemm(reinterpret_cast<GemmDesc*>(dbase + o_upd[l]), (int)lv.upd.size(), lv.upd_tiles, ls);
+            launch_gemm(reinterpret_cast<GemmDesc*>(dbase + o_upd[l]), (int)lv.upd.size(), lv.upd_tiles, ls,
+                        tune.gemm_slab_k);
             te();
             if (prof) {
               prof->n_sweep_gemm++;
@@ -2085,7 +2086,7 @@ static mlh_status solve_systems(Runner& RN, mlh_ctx ctx, const mlh_tuning& tune,
                                   asm_blk.tiles, gtiles, maxc, maxcols, maxncol, (int64_t)hq.size(),
                                   (int64_t)gs.size(), hq_small.n, hq_small.maxc, hq_small.maxncol, hq_large.maxc,
                                   hq_large.maxncol, tune.rhs_in_step_pct, tune.ls_row_blocks, tune.gje_rhs_cols,
-                                  tune.asm_in_panels, n_edst, max_seg, max_segn, (int64_t)o_eseg, (int64_t)o_edst,
+                                  tune.asm_in_panels, tune.gemm_slab_k, n_edst, max_seg, max_segn, (int64_t)o_eseg, (int64_t)o_edst,
                                   (int64_t)(intptr_t)opt.tstamp, bi == 0 ? 1 : 0};
       for (int b = 0; b <= nb; ++b) sig.push_back((int64_t)sys_off[b]);
       for (const Level& lv : levels) {
@@ -3189,7 +3190,7 @@ static mlh_status adjoint_shape(mlh_stack s, int32_t n_angles, const double* the
 struct mlh_batch_s {
   mlh_ctx ctx = nullptr;
   std::vector<mlh_stack_s*> st;
-  mlh_tuning tune{300, 3, 16, 1};
+  mlh_tuning tune{300, 3, 16, 1, 8};
   Runner run;
   std::vector<int64_t> out_off;  // first Bragg order of each stack in the concatenated outputs
   int64_t n_orders = 0;
@@ -3337,7 +3338,8 @@ extern "C" mlh_status mlh_stack_set_flux_tolerance(mlh_stack s, double tol) {
 // ---------------------------------------------------------------------------
 static bool tuning_valid(const mlh_tuning& t) {
   return t.rhs_in_step_pct >= 0 && t.rhs_in_step_pct <= 1000 && (t.ls_row_blocks == 3 || t.ls_row_blocks == 4) &&
-         (t.gje_rhs_cols == 16 || t.gje_rhs_cols == 8) && (t.asm_in_panels == 0 || t.asm_in_panels == 1);
+         (t.gje_rhs_cols == 16 || t.gje_rhs_cols == 8) && (t.asm_in_panels == 0 || t.asm_in_panels == 1) &&
+         (t.gemm_slab_k == 8 || t.gemm_slab_k == 16);
 }
 
 extern "C" mlh_status mlh_stack_get_tuning(mlh_stack s, mlh_tuning* out) {
@@ -3412,11 +3414,13 @@ static void tune_cache_load_locked() {
   if (!path || !*path) return;
   FILE* f = std::fopen(path, "r");
   if (!f) return;
-  char key[256];
+  char line[512], key[256];
   mlh_tuning t;
-  while (std::fscanf(f, "%255s %d %d %d %d", key, &t.rhs_in_step_pct, &t.ls_row_blocks, &t.gje_rhs_cols,
-                     &t.asm_in_panels) == 5)
-    if (tuning_valid(t)) g_tune_cache[key] = t;  // later lines win
+  while (std::fgets(line, sizeof line, f))  // one record a line; a line that does not parse is skipped
+    if (std::sscanf(line, "%255s %d %d %d %d %d", key, &t.rhs_in_step_pct, &t.ls_row_blocks, &t.gje_rhs_cols,
+                    &t.asm_in_panels, &t.gemm_slab_k) == 6 &&
+        tuning_valid(t))
+      g_tune_cache[key] = t;  // later lines win
   std::fclose(f);
 }
 
@@ -3436,8 +3440,8 @@ static void tune_cache_store(const std::string& key, const mlh_tuning& t) {
   const char* path = std::getenv("MLH_TUNING_CACHE");
   if (!path || !*path) return;
   if (FILE* f = std::fopen(path, "a")) {
-    std::fprintf(f, "%s %d %d %d %d\n", key.c_str(), t.rhs_in_step_pct, t.ls_row_blocks, t.gje_rhs_cols,
-                 t.asm_in_panels);
+    std::fprintf(f, "%s %d %d %d %d %d\n", key.c_str(), t.rhs_in_step_pct, t.ls_row_blocks, t.gje_rhs_cols,
+                 t.asm_in_panels, t.gemm_slab_k);
     std::fclose(f);
   }
 }
@@ -3479,6 +3483,7 @@ static mlh_status autotune_loop(mlh_tuning& tune, const std::function<mlh_status
   const int rows[] = {3, 4};
   const int cols[] = {16, 8};
   const int asmp[] = {1, 0};
+  const int slabs[] = {8, 16};
   auto sweep = [&](int32_t mlh_tuning::*field, const int* vals, int nv) {
     for (int i = 0; i < nv && r == MLH_OK; ++i) {
       mlh_tuning t = best_t;
@@ -3496,6 +3501,7 @@ static mlh_status autotune_loop(mlh_tuning& tune, const std::function<mlh_status
   sweep(&mlh_tuning::ls_row_blocks, rows, 2);
   sweep(&mlh_tuning::gje_rhs_cols, cols, 2);
   sweep(&mlh_tuning::asm_in_panels, asmp, 2);
+  sweep(&mlh_tuning::gemm_slab_k, slabs, 2);
   if (r != MLH_OK) {
     tune = start;
     return r;

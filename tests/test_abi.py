@@ -73,6 +73,6 @@ def test_binding_structs_follow_the_header(struct):
     assert [f for f, _ in getattr(_lib, struct)._fields_] == _header_struct_fields(struct)
 
 
-def test_tuning_struct_is_four_int32():
+def test_tuning_struct_is_five_int32():
     from paper_1410_5003_amd import _lib
-    assert ctypes.sizeof(_lib.mlh_tuning) == 16
+    assert ctypes.sizeof(_lib.mlh_tuning) == 20

@@ -128,7 +128,7 @@ def test_resolved_batch_stacks_against_stored_oracle_results():
 def test_batch_autotune_keeps_results(batch):
     descs, sts, b, th = batch
     t = b.autotune(th, reps=1)
-    assert set(t) == {"rhs_in_step_pct", "ls_row_blocks", "gje_rhs_cols", "asm_in_panels"}
+    assert set(t) == {"rhs_in_step_pct", "ls_row_blocks", "gje_rhs_cols", "asm_in_panels", "gemm_slab_k"}
     _check_against_single(descs, sts, b.solve(th), th, "tuned")
     b.set_tuning(rhs_in_step_pct=300, ls_row_blocks=3, gje_rhs_cols=16, asm_in_panels=1)
 

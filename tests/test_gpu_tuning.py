@@ -34,7 +34,8 @@ VARIANTS = [
     {"rhs_in_step_pct": 1000},
     {"ls_row_blocks": 4},
     {"asm_in_panels": 0},
-    {"rhs_in_step_pct": 0, "ls_row_blocks": 4, "gje_rhs_cols": 8, "asm_in_panels": 0},
+    {"gemm_slab_k": 16},
+    {"rhs_in_step_pct": 0, "ls_row_blocks": 4, "gje_rhs_cols": 8, "asm_in_panels": 0, "gemm_slab_k": 16},
 ]
 
 
@@ -43,7 +44,8 @@ def test_every_choice_matches_oracle(ctx, case, choice):
     import paper_1410_5003_amd as mlh
     desc, th, o = case
     st = mlh.Stack(ctx, desc)
-    assert st.get_tuning() == {"rhs_in_step_pct": 300, "ls_row_blocks": 3, "gje_rhs_cols": 16, "asm_in_panels": 1}
+    assert st.get_tuning() == {"rhs_in_step_pct": 300, "ls_row_blocks": 3, "gje_rhs_cols": 16, "asm_in_panels": 1,
+                               "gemm_slab_k": 8}
     st.set_tuning(**choice)
     for k, v in choice.items():
         assert st.get_tuning()[k] == v
@@ -61,7 +63,8 @@ def test_out_of_range_choices_are_rejected(ctx, case):
     desc, _, _ = case
     st = mlh.Stack(ctx, desc)
     before = st.get_tuning()
-    for bad in ({"ls_row_blocks": 5}, {"gje_rhs_cols": 12}, {"asm_in_panels": 2}, {"rhs_in_step_pct": -1},
+    for bad in ({"ls_row_blocks": 5}, {"gje_rhs_cols": 12}, {"asm_in_panels": 2}, {"gemm_slab_k": 12},
+                {"rhs_in_step_pct": -1},
                 {"rhs_in_step_pct": 1001}):
         with pytest.raises(mlh.MlhError):
             st.set_tuning(**bad)
